@@ -1,0 +1,184 @@
+"""Pins of the oracle's keys/sort/ranges (library sort, loops) and of its
+sampler (reference RNG values, invariants, exact inclusion probabilities by
+enumeration, frequency tests)."""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import binning, project, rng, sampler
+from oracle.params import SampleParams, pixels_per_tile, split_counts
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- binning
+def _scene(n=300, seed=2, size=96):
+    p = synth.gaussians(n, seed, logscale_mean=-3.0)
+    cam = synth.look_at((2.0, -1.5, 1.2), fx=size * 1.1, fy=size * 1.1, width=size, height=size - 20)
+    return p, cam, project.project(p, cam)
+
+
+def test_emit_loop_equals_vectorised():
+    _, cam, pr = _scene()
+    TX, TY = pr["TX"], pr["TY"]
+    valid = np.array([0, 3, 5, 6, 7, 11, TX * TY - 1])
+    for vt in (None, valid):
+        k1, v1 = binning.emit_pairs(pr["rect"], pr["depth32"], TX, TY, vt)
+        k2, v2 = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY, vt)
+        assert np.array_equal(k1, k2) and np.array_equal(v1, v2)
+
+
+def test_sort_and_ranges_against_python():
+    _, cam, pr = _scene()
+    TX, TY = pr["TX"], pr["TY"]
+    keys, vals = binning.emit_pairs(pr["rect"], pr["depth32"], TX, TY)
+    sk, sv = binning.sort_pairs(keys, vals)
+    ref = sorted(zip(keys.tolist(), vals.tolist()))
+    assert [int(k) for k in sk] == [r[0] for r in ref]
+    assert [int(v) for v in sv] == [r[1] for r in ref]
+    ranges = binning.tile_ranges(sk, TX * TY)
+    for t in range(TX * TY):
+        members = [i for i, k in enumerate(sk.tolist()) if (k >> 32) == t]
+        if members:
+            assert (ranges[t, 0], ranges[t, 1]) == (members[0], members[-1] + 1)
+        else:
+            assert (ranges[t] == 0).all()
+        # within a tile the order is by depth (the FP32 bits order like the depth)
+        d = pr["depth"][sv[ranges[t, 0]:ranges[t, 1]]]
+        assert (np.diff(d) >= 0).all()
+
+
+# ---------------------------------------------------------------- rng
+def test_splitmix64_reference_values():
+    vals = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert [rng.mix64(k * rng.GAMMA) for k in (1, 2, 3)] == vals
+
+
+def test_below_is_floor_of_scaled_draw():
+    for u in (0, 1, (1 << 63), (1 << 64) - 1):
+        for n in (1, 7, 256, (1 << 48) + 3):
+            assert rng.below(u, n) == (u * n) // (1 << 64)
+            assert 0 <= rng.below(u, n) < n
+
+
+# ---------------------------------------------------------------- counts
+def test_pixel_budget_formulas():
+    assert [pixels_per_tile(r) for r in (1000, 500, 250, 200, 150, 100, 1)] == [256, 128, 64, 51, 38, 25, 1]
+    assert split_counts(64, 400, 300) == (26, 19, 19)
+    assert split_counts(51, 400, 300) == (20, 15, 16)
+    assert split_counts(25, 400, 300) == (10, 8, 7)
+    assert split_counts(128, 400, 300) == (51, 38, 39)
+    assert split_counts(256, 400, 300) == (102, 77, 77)
+    for n in range(1, 257):
+        h, s, m = split_counts(n, 400, 300)
+        assert h + s + m == n and min(h, s, m) >= 0
+
+
+def test_half_weights_exact():
+    vals = np.array([0.0, 2.0 ** -24, 1.0, 65504.0, -1.0, np.inf, np.nan, 0.4], dtype=np.float16)
+    w = sampler.half_weights(vals.view(np.uint16))
+    assert w.tolist() == [0, 1, 1 << 24, 65504 << 24, 0, 0, 0, int(float(np.float16(0.4)) * (1 << 24))]
+
+
+# ---------------------------------------------------------------- sampler invariants
+@pytest.mark.parametrize("W,H,n_pix,n_sel", [(80, 56, 64, -1), (64, 64, 25, 5), (70, 40, 256, -1),
+                                              (48, 48, 51, 3)])
+def test_sampler_invariants(W, H, n_pix, n_sel):
+    E = synth.error_map(H, W, 11, zero_frac=0.3)
+    A = synth.age_map(H, W, 12)
+    sp = SampleParams(n_pix=n_pix, n_tiles_sel=n_sel)
+    s1 = sampler.sample_view(E, A, sp, seed=3, step=7, view=1)
+    s2 = sampler.sample_view(E, A, sp, seed=3, step=7, view=1)
+    assert all(np.array_equal(s1[k], s2[k]) for k in ("valid_tiles", "tile_off", "pix"))
+    TX, TY = s1["TX"], s1["TY"]
+    vt = s1["valid_tiles"]
+    assert (np.diff(vt) > 0).all()
+    assert vt.size == (TX * TY if n_sel < 0 else n_sel)
+    w = sampler.half_weights(E)
+    for i, t in enumerate(vt):
+        loc, x, y = sampler.tile_pixels(int(t), TX, W, H)
+        got = s1["pix"][s1["tile_off"][i]:s1["tile_off"][i + 1]].astype(int)
+        assert (np.diff(got) > 0).all()
+        assert set(got) <= set(loc.tolist())
+        assert got.size == min(n_pix, loc.size)
+        h, st, m = s1["sets"][i]
+        assert len(set(h) | set(st) | set(m)) == len(h) + len(st) + len(m) == got.size
+        wl = dict(zip(loc.tolist(), w[y, x].tolist()))
+        assert all(wl[int(k)] > 0 for k in h)               # zero-weight pixels are never hard
+        n_h, n_s, _ = split_counts(got.size, 400, 300)
+        assert len(st) == n_s and len(h) <= n_h
+        # stable = TopK age among the pixels not drawn as hard (library sort)
+        al = dict(zip(loc.tolist(), A[y, x].tolist()))
+        rest = sorted((k for k in loc.tolist() if k not in set(h.tolist())), key=lambda k: (-al[k], k))
+        assert list(st) == sorted(rest[:n_s])
+    # a different seed changes the draw
+    s3 = sampler.sample_view(E, A, sp, seed=4, step=7, view=1)
+    assert not np.array_equal(s1["pix"], s3["pix"]) or n_pix == 256
+
+
+def test_exhausted_weights_move_hard_slots_to_mixed():
+    W = H = 16
+    E = np.zeros((H, W), dtype=np.float16)
+    E[0, :3] = 1.0                                    # only three pixels carry error
+    A = np.zeros((H, W), dtype=np.uint16)
+    s = sampler.sample_view(E.view(np.uint16), A, SampleParams(n_pix=64), 1, 1, 0)
+    h, st, m = s["sets"][0]
+    assert sorted(h.tolist()) == [0, 1, 2]
+    assert len(st) == 19 and len(m) == 64 - 3 - 19
+
+
+def _inclusion_exact(weights, k):
+    """P(pixel in the first k sequential draws without replacement, prob. proportional
+    to the weights) by enumerating every ordered draw sequence."""
+    n = len(weights)
+    inc = np.zeros(n)
+    for seq in itertools.permutations(range(n), k):
+        p, rem = 1.0, float(sum(weights))
+        for i in seq:
+            p *= weights[i] / rem
+            rem -= weights[i]
+        for i in seq:
+            inc[i] += p
+    return inc
+
+
+def test_hard_draw_inclusion_probabilities_match_enumeration():
+    """On a 5-pixel tile (a 5x1 image) with n_pix=5 -> N_hard = 2, the hard set's
+    inclusion frequencies over many seeds match the exact sequential
+    without-replacement probabilities (chi-square)."""
+    E = np.array([[0.5, 1.0, 2.0, 0.25, 4.0]], dtype=np.float16)
+    A = np.zeros((1, 5), dtype=np.uint16)
+    sp = SampleParams(n_pix=5)
+    wts = [float(v) for v in E[0]]
+    exact = _inclusion_exact(wts, 2)
+    n_seeds = 20000
+    counts = np.zeros(5)
+    first = np.zeros(5)
+    for seed in range(n_seeds):
+        h, _, _ = sampler.sample_tile(sampler.half_weights(E.view(np.uint16)), A, 0, 1, 5, 1, sp, seed, 0, 0)
+        counts[h] += 1
+        u = rng.draw(seed, 0, 0, 0, 0)
+        first[np.searchsorted(np.cumsum(wts), rng.below(u, int(sum(wts) * 2 ** 24)) / 2 ** 24, side="right")] += 1
+    expected = exact * n_seeds
+    chi2 = (((counts - expected) ** 2) / expected).sum()
+    assert chi2 < 20.5            # 5 cells; p ~ 0.001 threshold for 4 dof is 18.5, margin for dependence
+    pf = np.array(wts) / sum(wts)
+    chi2_first = (((first - pf * n_seeds) ** 2) / (pf * n_seeds)).sum()
+    assert chi2_first < 18.5
+
+
+def test_tile_pass_prefers_high_error_tiles():
+    W = H = 64                                           # 16 tiles
+    E = np.full((H, W), 0.01, dtype=np.float16)
+    E[:16, :16] = 5.0                                    # tile 0 dominates
+    A = np.zeros((H, W), dtype=np.uint16)
+    hits = 0
+    for seed in range(200):
+        s = sampler.sample_view(E.view(np.uint16), A, SampleParams(n_pix=8, n_tiles_sel=2), seed, 0, 0)
+        hits += 0 in s["valid_tiles"].tolist()
+    assert hits > 190

@@ -1,0 +1,167 @@
+"""Pins of the oracle's sparse NCC loss, error/age maps and hybrid optimizer
+against identities, finite differences, numpy/torch library routines and
+closed forms (no GPU)."""
+import numpy as np
+import pytest
+
+from oracle import loss, maps, optim
+from oracle.params import LossParams, OptimParams
+
+
+# ---------------------------------------------------------------- loss
+def test_ncc_of_affine_copy_is_plus_minus_one():
+    rng = np.random.default_rng(0)
+    x = rng.uniform(size=(40, 3))
+    lp = LossParams(eps_ncc=0.0)
+    assert np.allclose(loss.tile_loss(x, 2.5 * x + 0.1, lp)["ncc"], 1.0)
+    assert np.allclose(loss.tile_loss(x, -0.7 * x + 0.9, lp)["ncc"], -1.0)
+
+
+def test_ncc_gradient_is_n_times_derivative_of_one_minus_ncc():
+    rng = np.random.default_rng(1)
+    x = rng.uniform(size=(25, 3))
+    y = rng.uniform(size=(25, 3))
+    lp = LossParams()
+    tl = loss.tile_loss(x, y, lp)
+    h = 1e-7
+    for i in (0, 7, 24):
+        for ch in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, ch] += h
+            xm[i, ch] -= h
+            fp = 1 - loss.tile_loss(xp, y, lp)["ncc"][ch]
+            fm = 1 - loss.tile_loss(xm, y, lp)["ncc"][ch]
+            assert np.isclose(25 * (fp - fm) / (2 * h), tl["gn"][i, ch], rtol=1e-6, atol=1e-8)
+
+
+def test_ncc_gradient_reduces_to_appendix_formula_without_eps():
+    rng = np.random.default_rng(2)
+    x = rng.uniform(size=(30, 3))
+    y = rng.uniform(size=(30, 3))
+    tl = loss.tile_loss(x, y, LossParams(eps_ncc=0.0))
+    mx, my = x.mean(0), y.mean(0)
+    vx, vy = x.var(0), y.var(0)
+    appendix = -((y - my) / np.sqrt(vx * vy) - tl["ncc"] * (x - mx) / vx)
+    assert np.allclose(tl["gn"], appendix, rtol=1e-10)
+
+
+def test_charbonnier_gradient_and_lambda_range():
+    rng = np.random.default_rng(3)
+    x = rng.uniform(size=(16, 3))
+    y = rng.uniform(size=(16, 3))
+    lp = LossParams(eps_charb=1e-3)
+    tl = loss.tile_loss(x, y, lp)
+    d = x - y
+    assert np.allclose(tl["g1"], d / np.sqrt(d * d + 1e-6))
+    assert 0.0 <= tl["lam"] <= 1.0
+    assert np.allclose(tl["err"], np.abs(d).sum(1))
+
+
+def test_full_sparse_loss_gradient_matches_finite_differences():
+    """dL/dI of Eq. (full_loss) with the per-tile weights held fixed."""
+    rng = np.random.default_rng(4)
+    off = np.array([0, 12, 30, 31, 50])               # includes a single-pixel tile
+    P = off[-1]
+    x = rng.uniform(size=(P, 3))
+    y = rng.uniform(size=(P, 3))
+    P_step, tiles_step = P + 17, 7                     # other views of the step add to the means
+    lp = LossParams()
+    out = loss.sparse_loss(x, y, off, P_step, tiles_step, lp)
+    f0 = loss.loss_value(x, y, off, P_step, tiles_step, out["lam"], lp)
+    assert np.isclose(f0, out["loss_l1"] + out["loss_ncc"], rtol=1e-12)
+    h = 1e-7
+    for i in (0, 11, 12, 30, 49):
+        for ch in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, ch] += h
+            xm[i, ch] -= h
+            fd = (loss.loss_value(xp, y, off, P_step, tiles_step, out["lam"], lp)
+                  - loss.loss_value(xm, y, off, P_step, tiles_step, out["lam"], lp)) / (2 * h)
+            assert np.isclose(fd, out["dL"][i, ch], rtol=1e-5, atol=1e-10)
+
+
+# ---------------------------------------------------------------- maps
+def test_ema_and_age_update_closed_form():
+    H, W = 8, 12
+    rng = np.random.default_rng(5)
+    E = rng.uniform(0, 2, size=(H, W)).astype(np.float16)
+    A = rng.integers(0, 65536, size=(H, W)).astype(np.uint16)
+    A[0, 0] = 65535
+    xs = np.array([1, 5, 11])
+    ys = np.array([0, 3, 7])
+    e = np.array([0.3, 1.7, 0.0], dtype=np.float32)
+    En, An = maps.ema_age_update(E.view(np.uint16), A, xs, ys, e, 0.4)
+    En = En.view(np.float16)
+    expect = (np.float32(0.6) * E[ys, xs].astype(np.float32) + np.float32(0.4) * e).astype(np.float16)
+    assert np.array_equal(En[ys, xs], expect)
+    mask = np.ones((H, W), bool)
+    mask[ys, xs] = False
+    assert np.array_equal(En[mask].view(np.uint16), E[mask].view(np.uint16))
+    assert (An[ys, xs] == 0).all()
+    assert An[0, 0] == 65535
+    assert np.array_equal(An[mask & (A < 65535)], A[mask & (A < 65535)] + 1)
+
+
+def test_dense_error_init_is_half_of_l1():
+    rng = np.random.default_rng(6)
+    x = rng.uniform(size=(5, 7, 3)).astype(np.float32)
+    y = rng.uniform(size=(3, 5, 7)).astype(np.float32)
+    e = maps.dense_error_init(x, y).view(np.float16)
+    ref = np.abs(x - np.moveaxis(y, 0, -1)).sum(-1)
+    assert np.allclose(e.astype(np.float64), ref, rtol=1e-3)
+
+
+# ---------------------------------------------------------------- optimizer
+def _state(N=64, seed=7):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(size=(59, N))
+    g = rng.normal(scale=1e-2, size=(59, N))
+    m = rng.normal(scale=1e-2, size=(59, N))
+    v = rng.uniform(1e-6, 1e-4, size=(59, N))
+    return p, g, m, v
+
+
+def test_lm_rank_one_matches_sherman_morrison():
+    p, g, m, v = _state()
+    op = OptimParams(lm_mode=0)
+    newp, newm, newv = optim.optimizer_step(p, g, m, v, None, op, step=3)
+    lr = op.row_lr()
+    for rows in (optim.GEOM_ROWS, optim.APP_ROWS):
+        gb = g[rows]
+        mb = op.beta1 * m[rows] + (1 - op.beta1) * gb
+        vb = op.beta2 * v[rows] + (1 - op.beta2) * gb * gb
+        Dinv = 1.0 / (np.sqrt(vb) + op.eps_lm)
+        # (D + g g^T)^-1 m = D^-1 m - D^-1 g (g^T D^-1 m) / (1 + g^T D^-1 g)
+        a = Dinv * mb
+        b = Dinv * gb
+        delta = -(a - b * (gb * a).sum(0) / (1 + (gb * b).sum(0)))
+        assert np.allclose(newp[rows] - p[rows], lr[rows][:, None] * delta, rtol=1e-9, atol=1e-15)
+
+
+def test_lm_diag_mode_closed_form():
+    p, g, m, v = _state(seed=8)
+    op = OptimParams(lm_mode=1)
+    newp, newm, newv = optim.optimizer_step(p, g, m, v, None, op, step=2)
+    rows = optim.GEOM_ROWS + optim.APP_ROWS
+    mb, vb = newm[rows], newv[rows]
+    delta = -mb / (g[rows] ** 2 + np.sqrt(vb) + op.eps_lm)
+    assert np.allclose(newp[rows] - p[rows], op.row_lr()[rows][:, None] * delta, rtol=1e-12)
+
+
+def test_adam_rows_match_torch_adam_and_sparse_mask():
+    torch = pytest.importorskip("torch")
+    p, g, m, v = _state(N=16, seed=9)
+    op = OptimParams(lm_mode=2, eps_adam=1e-8)
+    touched = np.zeros(16, bool)
+    touched[::3] = True
+    newp, newm, newv = optim.optimizer_step(p, g, np.zeros_like(m), np.zeros_like(v), touched, op, step=1)
+    # torch.optim.Adam, one step from zero moments, per row learning rate
+    lr = op.row_lr()
+    for row in (0, 4, 7, 10, 12, 20, 58):
+        t = torch.tensor(p[row, touched], dtype=torch.float64, requires_grad=True)
+        opt = torch.optim.Adam([t], lr=float(lr[row]), betas=(op.beta1, op.beta2), eps=op.eps_adam)
+        t.grad = torch.tensor(g[row, touched], dtype=torch.float64)
+        opt.step()
+        assert np.allclose(newp[row, touched], t.detach().numpy(), rtol=1e-12, atol=1e-15)
+    assert np.array_equal(newp[:, ~touched], p[:, ~touched])
+    assert (newm[:, ~touched] == 0).all() and (newv[:, ~touched] == 0).all()
