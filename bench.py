@@ -1,0 +1,221 @@
+"""Benchmark of the sparse-pixel training step on one MI355X.
+
+Workload (rasterizer scaling): 300k Gaussians (means U[-1,1]^3, log-scales
+N(-4, 0.5), random unit quaternions, opacity logits N(0,1), SH degree 3
+N(0, 0.2)), one 1296x840 view, error-guided sampling of every tile at 25 %
+(64 of 256 pixels per tile), Charbonnier + sparse NCC loss, adjoint backward
+and the hybrid LM/Adam update.  A step runs every stage of the path: sample,
+project, bin/sort, forward, loss, error/age update, backward, projection
+backward, optimizer.  The dense GPU step (every pixel, same arithmetic) and
+the 100/50/25/10 % sweep are reported beside it; the oracle is timed on the
+host for a bounded sample of the same step.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+N_GAUSS = 300_000
+WIDTH, HEIGHT = 1296, 840
+HEADLINE_RATE = 250          # per-mille of each tile's pixels
+SWEEP_RATES = (1000, 500, 250, 100)
+VALU_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed); see DESIGN
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic FP32 operations per (Gaussian, pixel) pair of the forward
+# compositing: an evaluation (offset, quadratic form, exp, alpha) and a
+# blend (transmittance update and colour accumulation).
+FWD_FLOP_EVAL = 14
+FWD_FLOP_BLEND = 9
+# Backward replay: the same evaluation, then per composited pair the
+# transmittance/colour replay and the nine screen-space gradient terms.
+BWD_FLOP_EVAL = 14
+BWD_FLOP_BLEND = 48
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(dev):
+    import torch
+
+    import synth
+    p = synth.gaussians(N_GAUSS, synth.SEED_SCENE)
+    cam = synth.config_camera("scaling")
+    gt = synth.image(HEIGHT, WIDTH, synth.SEED_NOISE)
+    return p, cam, gt
+
+
+def make_trainer(p, cam, gt, rate, dev):
+    import torch
+
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    cfg = StepConfig(rate_permille=rate)
+    E = torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev)
+    A = torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev)
+    tr = Trainer(torch.from_numpy(p).to(dev), [cam], [torch.from_numpy(gt).to(dev)], cfg, E=[E], A=[A])
+    if rate is not None:
+        tr.init_error_maps([0])
+    return tr
+
+
+def run(tr, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        tr.step([0])
+    torch.cuda.synchronize()
+    tr.events = {}
+    tr.counters.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step([0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage = tr.stage_ms()
+    cnt = tr.counters.cpu().tolist()
+    tr.events = None
+    return dict(seconds=t1 - t0, ms_per_step=(t1 - t0) * 1000.0 / steps, evals=cnt[0], blends=cnt[1],
+                stage_ms={k: v / steps for k, v in stage.items()},
+                n_pairs=int(tr._bufs[0].n_pairs))
+
+
+def cpu_baseline(p, cam, gt, n_tiles=48):
+    """The oracle's sparse step on ``n_tiles`` of the view's tiles at the
+    headline rate: sample, project, bin/sort, forward, loss, backward and
+    projection backward (every Gaussian), optimizer.  Returns blends/s."""
+    from oracle import binning, loss, project, project_bwd, render, sampler, optim
+    from oracle.params import OptimParams, RasterParams, SampleParams
+    import synth
+    rp = RasterParams()
+    E = synth.error_map(HEIGHT, WIDTH, 31)
+    A = np.zeros((HEIGHT, WIDTH), dtype=np.uint16)
+    TX, TY = (WIDTH + 15) // 16, (HEIGHT + 15) // 16
+    tiles = np.sort(np.random.default_rng(0).choice(TX * TY, n_tiles, replace=False))
+    t0 = time.perf_counter()
+    s = sampler.sample_view(E, A, SampleParams(n_pix=64), 3, 1, 0, tiles_subset=tiles)
+    pr = project.project(p, cam, rp)
+    _, sv, ranges = binning.bin_and_sort(pr, s["valid_tiles"])
+    xs, ys, _ = sampler.sample_coords(s, WIDTH, HEIGHT)
+    out = render.render_pixels(pr, sv, ranges, xs, ys, rp)
+    ls = loss.sparse_loss(out["rgb"], gt[:, ys, xs].T, s["tile_off"], xs.size, s["valid_tiles"].size)
+    g2d = render.render_pixels_bwd(pr, sv, ranges, xs, ys, ls["dL"], rp)
+    grad = project_bwd.project_bwd(p, cam, pr, g2d, rp)
+    touched = np.zeros(p.shape[1], dtype=bool)
+    touched[np.unique(sv)] = True
+    optim.optimizer_step(p, grad, np.zeros_like(grad), np.zeros_like(grad), touched, OptimParams(), 1)
+    dt = time.perf_counter() - t0
+    blends = int(out["n_blend"].sum())
+    return dict(value=blends / dt, unit="blends/s", cores=1, kind="oracle",
+                sample=f"{n_tiles} of {TX * TY} tiles at 25% ({xs.size} pixels, {blends} blends), "
+                       f"full projection/backward of {p.shape[1]} Gaussians; {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the pixel-rate sweep and dense run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU split by "
+              f"views is described but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    log("building workload")
+    p, cam, gt = make_workload(dev)
+
+    log(f"sparse {HEADLINE_RATE / 10:.0f}% run: {args.warmup} warmup + {args.steps} timed steps")
+    tr = make_trainer(p, cam, gt, HEADLINE_RATE, dev)
+    head = run(tr, args.steps, args.warmup)
+    log(f"  {head['ms_per_step']:.3f} ms/step, stages {head['stage_ms']}")
+    del tr
+
+    sweep = {}
+    dense = None
+    if not args.no_sweep:
+        for r in SWEEP_RATES:
+            if r == HEADLINE_RATE:
+                sweep[f"{r / 10:g}%"] = dict(ms_per_step=head["ms_per_step"],
+                                             blends_per_s=head["blends"] / head["seconds"])
+                continue
+            log(f"sweep {r / 10:g}%")
+            tr = make_trainer(p, cam, gt, r, dev)
+            res = run(tr, max(5, args.steps // 2), 2)
+            sweep[f"{r / 10:g}%"] = dict(ms_per_step=res["ms_per_step"], blends_per_s=res["blends"] / res["seconds"])
+            del tr
+        log("dense run")
+        tr = make_trainer(p, cam, gt, None, dev)
+        dres = run(tr, max(5, args.steps // 2), 2)
+        dense = dict(ms_per_step=dres["ms_per_step"], blends_per_s=dres["blends"] / dres["seconds"],
+                     stage_ms=dres["stage_ms"])
+        del tr
+
+    # roofline of the dominant kernel of the headline step
+    st = head["stage_ms"]
+    dom = max(("render_fwd", "render_bwd"), key=lambda k: st.get(k, 0.0))
+    per_launch_evals = head["evals"] / args.steps
+    per_launch_blends = head["blends"] / args.steps
+    if dom == "render_fwd":
+        flops = FWD_FLOP_EVAL * per_launch_evals + FWD_FLOP_BLEND * per_launch_blends
+    else:
+        flops = BWD_FLOP_EVAL * per_launch_evals + BWD_FLOP_BLEND * per_launch_blends
+    achieved = flops / (st[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "launch_ms": round(st[dom], 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("oracle CPU baseline")
+        cpu = cpu_baseline(p, cam, gt)
+
+    value = head["blends"] / head["seconds"]
+    line = {
+        "metric": "ms/train-step & Gaussian-pixel blends/s, sparse vs dense GPU at matched PSNR",
+        "value": value,
+        "unit": "blends/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rasterizer scaling: 300k Gaussians, one 1296x840 view, "
+                               "25% error-guided pixels per tile, full training step",
+                   "gaussians": N_GAUSS, "width": WIDTH, "height": HEIGHT, "rate": 0.25,
+                   "pairs": head["n_pairs"], "parallelism": "single GPU"},
+        "stage_ms": {k: round(v, 4) for k, v in st.items()},
+        "dense": dense,
+        "sparse_vs_dense_speedup": (dense["ms_per_step"] / head["ms_per_step"]) if dense else None,
+        "sweep": sweep or None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

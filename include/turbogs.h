@@ -1,0 +1,245 @@
+/*
+ * turbogs.h - C ABI of the MI355X (gfx950) sparse-pixel Gaussian rasterizer.
+ *
+ * The library implements the per-iteration hot path of error-guided sparse
+ * pixel training of 3D Gaussian Splatting (TurboGS, arXiv 2606.15924):
+ * projection with SH colour, tile x depth binning and sort, tile-wise
+ * error/age pixel sampling (Sec. 3.5), compositing of only the sampled
+ * pixels (Sec. 3.6), the sparse Charbonnier + tile NCC loss (Sec. 3.7),
+ * the error/age map update (Sec. 3.3), the adjoint backward, and the hybrid
+ * moment-damped LM / Adam update (Sec. 3.9).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a device pointer owned by the caller unless
+ *     stated otherwise.  The library never allocates device
+ *     memory; scratch space comes from a caller workspace sized by the
+ *     matching *_workspace_size function.  Struct arguments (camera and
+ *     parameter records) are host pointers read during the call.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *     null stream).  Only tgs_bin_sort synchronises (it reads the pair count).
+ *   - Return value: TGS_OK, or a negative error (TGS_ERR_INVALID for a null
+ *     pointer or a bad size, TGS_ERR_HIP for a failed launch/runtime call) or
+ *     TGS_ERR_CAPACITY (an output is too small; the required count is written
+ *     to the named host out-parameter).  tgs_last_error() returns a message
+ *     describing the last failure of the calling thread.
+ *   - Gaussian parameters live in one float array params[59][n] (row r of
+ *     Gaussian i at params[r * n + i]):
+ *       rows 0-2 mean xyz; 3-5 log-scale; 6-9 quaternion (w, x, y, z),
+ *       unnormalised; 10 opacity logit; 11 + 3k + c SH coefficient k
+ *       (k = 0..15, order l then m = -l..l) of colour channel c.
+ *     Gradients, and the Adam moments m, v, use the same layout.
+ *   - Images are tiled in 16 x 16 tiles; tiles_x = ceil(W/16),
+ *     tiles_y = ceil(H/16); tile id = ty * tiles_x + tx; a pixel's local
+ *     index inside its tile is ly * 16 + lx.
+ *   - A sample set (one view) is valid_tiles[n_st] (ascending tile ids),
+ *     tile_off[n_st + 1] (prefix offsets) and pix[P] (uint8 local indices,
+ *     ascending within a tile).  Per-sample outputs are indexed by sample.
+ *     Passing valid_tiles = NULL selects the dense mode: every tile, every
+ *     in-image pixel, outputs indexed row-major by y * W + x.
+ */
+#ifndef TURBOGS_H
+#define TURBOGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TGS_ABI_VERSION 1u
+#define TGS_TILE 16
+#define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
+#define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
+#define TGS_PARAM_ROWS 59
+
+enum {
+  TGS_OK = 0,
+  TGS_ERR_CAPACITY = 1,
+  TGS_ERR_INVALID = -1,
+  TGS_ERR_HIP = -2
+};
+
+/* OpenCV pinhole camera: x right, y down, z forward.  R (row-major) and t
+ * map a world point X to camera space R X + t. */
+typedef struct tgs_camera {
+  double R[9];
+  double t[3];
+  double fx, fy, cx, cy;
+  int32_t width, height;
+} tgs_camera;
+
+/* Rasterizer constants the paper leaves to the 3DGS conventions. */
+typedef struct tgs_raster_params {
+  int32_t sh_degree;  /* 0..3 */
+  float z_near;       /* cull t_z <= z_near */
+  float dilation;     /* added to the 2D covariance diagonal, px^2 */
+  float alpha_min;    /* skip alpha < alpha_min */
+  float alpha_max;    /* alpha = min(alpha_max, o * G) */
+  float T_min;        /* stop before T would fall below T_min */
+  float bg[3];        /* background colour */
+} tgs_raster_params;
+
+/* Pixel sampling of one view (Sec. 3.5). */
+typedef struct tgs_sample_params {
+  int32_t n_pix;            /* N_pix per full tile, 1..256 */
+  int32_t hard_permille;    /* r_hard in 1/1000 */
+  int32_t stable_permille;  /* r_stable in 1/1000 */
+  int32_t n_tiles_sel;      /* tiles drawn in proportion to error; < 0: all */
+  uint64_t seed;
+  uint64_t step;
+  int32_t view;
+  int32_t reserved;
+} tgs_sample_params;
+
+typedef struct tgs_loss_params {
+  float eps_charb;   /* Charbonnier epsilon */
+  float eps_ncc;     /* added to V_x V_y under the NCC square root */
+  float eps_lambda;  /* denominator guard of the balance weight */
+} tgs_loss_params;
+
+typedef struct tgs_optim_params {
+  double lr_mean, lr_scale, lr_quat, lr_opacity, lr_sh_dc, lr_sh_rest;
+  double beta1, beta2, eps_adam, eps_lm;
+  int32_t lm_mode;  /* 0: J^T J = g g^T, 1: diag(g^2), 2: Adam for every row */
+  int32_t reserved;
+} tgs_optim_params;
+
+uint32_t tgs_version(void);
+const char* tgs_last_error(void);
+
+/* N_pix = max(1, floor(r * 256)) with r = rate_permille / 1000 (Sec. 3.5). */
+int32_t tgs_pixels_per_tile(int32_t rate_permille);
+
+/* Number of sampled tiles tgs_sample produces for this view and parameters
+ * (host-side; sizes the per-tile outputs). */
+int32_t tgs_sample_tile_count(int32_t height, int32_t width, const tgs_sample_params* sp);
+
+/* EWA projection and SH colour (Sec. 3.1: each Gaussian is projected to a 2D
+ * splat whose footprint and opacity give alpha; colour from SH coefficients).
+ *   params   [59][n] float, read
+ *   splat    [n][12] float, written: floor(px), floor(py), px - floor(px),
+ *            py - floor(py), conic a, b, c (Q = [[a, b], [b, c]]), opacity,
+ *            r, g, b, depth.  The centre is in pixel-index space (pixel
+ *            (i, j) sits at offset (i, j) - centre).
+ *   depth    [n] float (camera-space z, FP32)
+ *   radius   [n] int32 (0 = culled)
+ *   rect     [n][4] int32 tile rectangle xmin, ymin, xmax, ymax (exclusive)
+ *   clamp    [n] uint8, bit c set when colour channel c was clamped at 0
+ * The projection is computed in FP64; depth bits, centre and rectangle
+ * follow a fixed operation order. */
+int32_t tgs_project(const float* params, int64_t n, const tgs_camera* cam,
+                    const tgs_raster_params* rp, float* splat, float* depth,
+                    int32_t* radius, int32_t* rect, uint8_t* clamp, void* stream);
+
+/* Tile-wise error/age pixel sampling (Sec. 3.5, Eq. pix_prob_err and
+ * Eq. pix_topk_age, plus the mixed remainder of the hyper-parameter table).
+ *   E, A        [H][W] uint16: half-precision error bits, age (read)
+ *   valid_tiles [n_st] int32, tile_off [n_st + 1] int32 (written)
+ *   pix         [n_st * n_pix] uint8 capacity (written up to tile_off[n_st])
+ *   tile_slot   [tiles_x * tiles_y] int32: slot of each tile or -1 (written)
+ *   totals      [2] int64 device counters: += P and += n_st of this view
+ *               (the caller zeroes them once per training step)
+ *   ws          workspace of tgs_sample_workspace_size(H, W) bytes
+ * Deterministic: counter-based SplitMix64 draws keyed by (seed, step, view,
+ * tile, slot). */
+size_t tgs_sample_workspace_size(int32_t height, int32_t width);
+int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
+                   const tgs_sample_params* sp, int32_t* valid_tiles, int32_t* tile_off,
+                   uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* Tile x depth binning, radix sort and per-tile ranges (the depth-ordered
+ * per-tile Gaussian lists of Eq. alpha_comp, in the tile order of Sec. 3.6).
+ *   rect, depth  projection outputs of n Gaussians
+ *   tile_slot    nullable: only tiles with tile_slot >= 0 receive pairs
+ *   keys, vals   [capacity] uint64 / uint32 outputs, sorted by
+ *                key = (tile << 32) | bits(depth), ties by Gaussian id
+ *   ranges       [tiles_x * tiles_y][2] uint32 [start, end), [0, 0) if empty
+ *   touched      nullable [n] uint8: set to 1 for Gaussians with a pair
+ *   n_pairs      host out: number of pairs
+ * Returns TGS_ERR_CAPACITY (and *n_pairs) when capacity is too small; the
+ * outputs are then unspecified.  Synchronises the stream once. */
+size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32_t n_tiles);
+int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t n,
+                     const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y,
+                     uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges,
+                     uint8_t* touched, int64_t* n_pairs, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* Front-to-back compositing of the sampled pixels of the sampled tiles
+ * (Eq. alpha_comp; Sec. 3.6 tile-parallel forward with prefix-sum pixel
+ * offsets).  valid_tiles = NULL: dense mode (n_st ignored).
+ *   max_per_tile  largest per-tile sample count (sizes the workgroup)
+ *   out       [P][4] float: r, g, b (including T_final * bg), T_final
+ *   ncontrib  [P] uint32: range position of the last composited Gaussian + 1
+ *   counters  nullable [2] uint64 += (evaluations, blends) */
+int32_t tgs_render_fwd(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                       int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                       const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                       int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
+                       float* out, uint32_t* ncontrib, uint64_t* counters, void* stream);
+
+/* Exact adjoint of tgs_render_fwd for the same samples (Sec. 3.6 backward
+ * over sampled pixels only).  Per-pixel state is recomputed front to back
+ * from the tile ranges and the forward outputs; nothing per Gaussian is
+ * saved.
+ *   dL_dout  [P][4] float (channel 3 ignored)
+ *   g2d      [n][9] float, accumulated (+=): dL/d(centre x, y; conic a, b, c;
+ *            opacity; r, g, b) */
+int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                       int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                       const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                       int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
+                       const float* out, const uint32_t* ncontrib, const float* dL_dout,
+                       float* g2d, void* stream);
+
+/* Sparse supervision of one view (Sec. 3.7: Charbonnier L1 per pixel plus
+ * tile NCC with the gradient-balanced weight of Eq. ncc_weight_auto, summed
+ * as Eq. full_loss).
+ *   out        [P][4] rendered colours; gt [3][H][W] float target image
+ *   totals     [2] int64 device: sampled pixels and sampled tiles of the step
+ *   dL_dout    [P][4] written (channel 3 = 0); err [P] = |I_hat - I|_1
+ *   lambda     [n_st] balance weights; tile_loss [n_st][2] = (L1 part, NCC
+ *              part) of this tile's contribution to L */
+int32_t tgs_loss(const float* out, const float* gt, int32_t height, int32_t width,
+                 const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                 int32_t n_st, const int64_t* totals, const tgs_loss_params* lp,
+                 float* dL_dout, float* err, float* lambda, float* tile_loss, void* stream);
+
+/* Error-map EMA at sampled pixels (Eq. ema_err) and age update (Eq.
+ * age_update) of one selected view.  E is half bits, blended in FP32 as
+ * fl(fl(fl(1 - beta) E) + fl(beta e)) and rounded to nearest even; A is
+ * reset to 0 at samples and incremented (saturating) elsewhere. */
+int32_t tgs_ema_age_update(uint16_t* E, uint16_t* A, int32_t height, int32_t width,
+                           const int32_t* tile_slot, const int32_t* tile_off,
+                           const uint8_t* pix, const float* err, float beta, void* stream);
+
+/* Dense error-map initialisation (Sec. 3.3: E_v from the dense L1 error of
+ * the initial Gaussians): E = half(|dr| + |dg| + |db|) from a dense
+ * tgs_render_fwd output. */
+int32_t tgs_error_init(const float* out_dense, const float* gt, int32_t height, int32_t width,
+                       uint16_t* E, void* stream);
+
+/* Chain rule from g2d to the Gaussian parameters (backward of tgs_project),
+ * accumulated into grad[59][n] (+=).  Culled Gaussians (radius 0) are left
+ * untouched.  clamp: the tgs_project output. */
+int32_t tgs_project_bwd(const float* params, int64_t n, const tgs_camera* cam,
+                        const tgs_raster_params* rp, const int32_t* radius,
+                        const uint8_t* clamp, const float* g2d, float* grad, void* stream);
+
+/* Hybrid moment-damped LM / Adam update (Sec. 3.9, Eq. moment_damped_lm, and
+ * the appendix optimizer details): per touched Gaussian, Adam moments for all
+ * rows; geometry (rows 0-9) and base appearance (SH DC, opacity) solve
+ * (J^T J + diag(sqrt(v) + eps)) Delta = -m by Cholesky and move by lr * Delta;
+ * the other SH rows take a bias-corrected Adam step.  touched nullable (all).
+ * step >= 1.  Internally FP64. */
+int32_t tgs_optimizer_step(float* params, const float* grad, float* m, float* v, int64_t n,
+                           const uint8_t* touched, const tgs_optim_params* op, int64_t step,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TURBOGS_H */

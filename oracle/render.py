@@ -112,7 +112,8 @@ def render_pixels(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs: n
 
 
 def render_pixels_bwd(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs, ys,
-                      dL_drgb: np.ndarray, rp: RasterParams = RasterParams()) -> np.ndarray:
+                      dL_drgb: np.ndarray, rp: RasterParams = RasterParams(),
+                      with_abs: bool = False):
     """Exact adjoint of ``render_pixels``: given dL/dI at the pixels, return
     dL/d(screen-space splat parameters) per Gaussian, g2d [9, N] =
     (mean2d x, y; conic a, b, c; opacity; rgb r, g, b).
@@ -120,11 +121,19 @@ def render_pixels_bwd(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, x
     With B_k = I(p) - sum_{j<=k} T_j alpha_j c_j (what lies behind k, including
     the background term):  dI/dc_k = T_k alpha_k,
     dI/dalpha_k = T_k c_k - B_k / (1 - alpha_k).  alpha = o G is differentiated
-    only where it was not clamped at alpha_max; G = exp(power)."""
+    only where it was not clamped at alpha_max; G = exp(power).
+
+    With ``with_abs`` it also returns, per Gaussian and field, the sum over
+    pixels of an error scale for an FP32 evaluation: the absolute value of
+    each term, where dL/dalpha is replaced by the magnitude of its two parts,
+    sum_ch |g| (T |c| + (|I| + |C_{<=k}|) / (1 - alpha)).  A front-to-back
+    evaluation obtains B_k as I - C_{<=k}, a difference of two O(|I|)
+    numbers, so its rounding error scales with |I|, not with |B_k|."""
     rp = rp.f64()
     TX = proj["TX"]
     N = proj["opacity"].size
     g2d = np.zeros((9, N))
+    g2d_abs = np.zeros((9, N))
     xs = np.asarray(xs, dtype=np.int64)
     ys = np.asarray(ys, dtype=np.int64)
     g = np.asarray(dL_drgb, dtype=np.float64)
@@ -149,24 +158,30 @@ def render_pixels_bwd(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, x
         gp = g[sel]                                                    # [P, 3]
         dI_dalpha = Tb[:, :, None] * col[None, :, :] - Bk / (1.0 - alpha)[:, :, None]
         dL_dalpha = np.where(con, np.einsum("pkc,pc->pk", dI_dalpha, gp), 0.0)
-        dL_dcol = np.einsum("pk,pc->kc", w, gp)                        # [K, 3]
         unclamped = con & (ev["araw"] < rp.alpha_max)
         G = ev["G"]
         o = ev["o"][None, :]
-        dL_do = np.where(unclamped, G * dL_dalpha, 0.0).sum(axis=0)
         dL_dpow = np.where(unclamped, o * G * dL_dalpha, 0.0)          # dL/dG * dG/dpower
         dx, dy = ev["dx"], ev["dy"]
         a, b, c = ev["a"][None, :], ev["b"][None, :], ev["c"][None, :]
         # power = -1/2 (a dx^2 + c dy^2) - b dx dy, d = pixel - centre
-        dL_da = (-0.5 * dx * dx * dL_dpow).sum(axis=0)
-        dL_db = (-dx * dy * dL_dpow).sum(axis=0)
-        dL_dc = (-0.5 * dy * dy * dL_dpow).sum(axis=0)
-        dL_dpx = ((a * dx + b * dy) * dL_dpow).sum(axis=0)
-        dL_dpy = ((b * dx + c * dy) * dL_dpow).sum(axis=0)
-        for row, val in enumerate([dL_dpx, dL_dpy, dL_da, dL_db, dL_dc, dL_do,
-                                   dL_dcol[:, 0], dL_dcol[:, 1], dL_dcol[:, 2]]):
-            np.add.at(g2d[row], gids, val)
-    return g2d
+        terms = [(a * dx + b * dy) * dL_dpow, (b * dx + c * dy) * dL_dpow,
+                 -0.5 * dx * dx * dL_dpow, -dx * dy * dL_dpow, -0.5 * dy * dy * dL_dpow,
+                 np.where(unclamped, G * dL_dalpha, 0.0),
+                 w * gp[:, 0:1], w * gp[:, 1:2], w * gp[:, 2:3]]
+        for row, tm in enumerate(terms):
+            np.add.at(g2d[row], gids, tm.sum(axis=0))
+        if with_abs:
+            mag = np.einsum("pkc,pc->pk", Tb[:, :, None] * np.abs(col)[None, :, :]
+                            + (np.abs(Cp)[:, None, :] + np.abs(acc)) / (1.0 - alpha)[:, :, None],
+                            np.abs(gp))
+            mag_pow = np.where(unclamped, o * G * mag, 0.0)
+            scale = [np.abs(a * dx + b * dy) * mag_pow, np.abs(b * dx + c * dy) * mag_pow,
+                     0.5 * dx * dx * mag_pow, np.abs(dx * dy) * mag_pow, 0.5 * dy * dy * mag_pow,
+                     np.where(unclamped, G * mag, 0.0)] + [np.abs(tm) for tm in terms[6:]]
+            for row, sc in enumerate(scale):
+                np.add.at(g2d_abs[row], gids, sc.sum(axis=0))
+    return (g2d, g2d_abs) if with_abs else g2d
 
 
 def dense_pixels(W: int, H: int):

@@ -1,0 +1,68 @@
+"""``torch.autograd.Function`` around the sparse rasterizer.
+
+Forward: project, bin/sort and composite the given samples of one view
+(``tgs_project`` -> ``tgs_bin_sort`` -> ``tgs_render_fwd``).  Backward: the
+hand-written adjoint (``tgs_render_bwd`` -> ``tgs_project_bwd``).  The context
+keeps only the projected splats, the sorted ids with the tile ranges, and the
+per-sample outputs (final colour, transmittance, contributor count): the
+backward recomputes every per-pixel quantity from them instead of storing
+per-(pixel, Gaussian) state (Sec. 3.6: splat-parallel backward without a
+dense replay).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+from .pipeline import ViewBuffers
+
+
+class Samples:
+    """A view's sample set as device tensors (``None`` valid_tiles = dense)."""
+
+    def __init__(self, valid_tiles, tile_off, pix, n_st: int, max_per_tile: int, tile_slot=None):
+        self.valid_tiles, self.tile_off, self.pix = valid_tiles, tile_off, pix
+        self.n_st, self.max_per_tile, self.tile_slot = n_st, max_per_tile, tile_slot
+
+
+class SparseRasterize(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, cam, samples: Samples, rp=None):
+        rp = rp if rp is not None else B.raster_params()
+        n = params.shape[1]
+        params = params.contiguous()
+        vb = ViewBuffers(n, cam.width, cam.height, None, -1, params.device)
+        if samples.valid_tiles is not None:
+            vb.dense = False
+            vb.valid_tiles, vb.tile_off, vb.pix = samples.valid_tiles, samples.tile_off, samples.pix
+            vb.tile_slot = samples.tile_slot
+            vb.n_st, vb.n_pix = samples.n_st, samples.max_per_tile
+            P = int(samples.tile_off[-1].item()) if samples.n_st > 0 else 0
+            vb.out = torch.empty((max(P, 1), 4), dtype=torch.float32, device=params.device)
+            vb.ncontrib = torch.empty(max(P, 1), dtype=torch.int32, device=params.device)
+            vb.P = P
+        else:
+            vb.P = cam.width * cam.height
+        c = B.camera(cam)
+        vb.project(params, c, rp)
+        vb.bin_sort()
+        vb.render_fwd(rp)
+        ctx.vb, ctx.cam, ctx.rp = vb, c, rp
+        ctx.save_for_backward(params)
+        return vb.out[: vb.P, :3].clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (params,) = ctx.saved_tensors
+        vb = ctx.vb
+        dL = torch.zeros((max(vb.P, 1), 4), dtype=torch.float32, device=params.device)
+        dL[: vb.P, :3] = grad_out
+        vb.dL = dL
+        vb.render_bwd(ctx.rp)
+        grad = torch.zeros_like(params)
+        vb.project_bwd(params, ctx.cam, ctx.rp, grad)
+        return grad, None, None, None
+
+
+def rasterize(params, cam, samples: Samples, rp=None):
+    return SparseRasterize.apply(params, cam, samples, rp)

@@ -1,0 +1,268 @@
+"""ctypes binding of ``libturbogs.so`` with the C entry points' names.
+
+Argument marshalling only: tensors are passed as device pointers
+(``data_ptr()``), records as ctypes structures, and every call runs on
+torch's current HIP stream.  All work happens in the HIP kernels; a missing
+library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libturbogs.so")
+
+TGS_OK = 0
+TGS_ERR_CAPACITY = 1
+TGS_ERR_INVALID = -1
+TGS_ERR_HIP = -2
+SPLAT_FLOATS = 12
+G2D_FLOATS = 9
+PARAM_ROWS = 59
+TILE = 16
+
+
+class tgs_camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3), ("fx", ctypes.c_double),
+                ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class tgs_raster_params(ctypes.Structure):
+    _fields_ = [("sh_degree", ctypes.c_int32), ("z_near", ctypes.c_float), ("dilation", ctypes.c_float),
+                ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
+                ("bg", ctypes.c_float * 3)]
+
+
+class tgs_sample_params(ctypes.Structure):
+    _fields_ = [("n_pix", ctypes.c_int32), ("hard_permille", ctypes.c_int32),
+                ("stable_permille", ctypes.c_int32), ("n_tiles_sel", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("step", ctypes.c_uint64), ("view", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class tgs_loss_params(ctypes.Structure):
+    _fields_ = [("eps_charb", ctypes.c_float), ("eps_ncc", ctypes.c_float), ("eps_lambda", ctypes.c_float)]
+
+
+class tgs_optim_params(ctypes.Structure):
+    _fields_ = [("lr_mean", ctypes.c_double), ("lr_scale", ctypes.c_double), ("lr_quat", ctypes.c_double),
+                ("lr_opacity", ctypes.c_double), ("lr_sh_dc", ctypes.c_double),
+                ("lr_sh_rest", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps_adam", ctypes.c_double), ("eps_lm", ctypes.c_double), ("lm_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class CapacityError(RuntimeError):
+    def __init__(self, msg: str, required: int):
+        super().__init__(msg)
+        self.required = required
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+
+PROTOTYPES = {
+    "tgs_version": (ctypes.c_uint32, []),
+    "tgs_last_error": (ctypes.c_char_p, []),
+    "tgs_pixels_per_tile": (_I32, [_I32]),
+    "tgs_sample_tile_count": (_I32, [_I32, _I32, ctypes.POINTER(tgs_sample_params)]),
+    "tgs_project": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
+                           _P, _P, _P, _P, _P, _P]),
+    "tgs_sample_workspace_size": (_SZ, [_I32, _I32]),
+    "tgs_sample": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(tgs_sample_params), _P, _P, _P, _P, _P,
+                          _P, _SZ, _P]),
+    "tgs_bin_sort_workspace_size": (_SZ, [_I64, _I64, _I32]),
+    "tgs_bin_sort": (_I32, [_P, _P, _I64, _P, _I32, _I32, _P, _P, _I64, _P, _P,
+                            ctypes.POINTER(_I64), _P, _SZ, _P]),
+    "tgs_render_fwd": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                              ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P]),
+    "tgs_render_bwd": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                              ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P]),
+    "tgs_loss": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _I32, _P, ctypes.POINTER(tgs_loss_params),
+                        _P, _P, _P, _P, _P]),
+    "tgs_ema_age_update": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _P, ctypes.c_float, _P]),
+    "tgs_error_init": (_I32, [_P, _P, _I32, _I32, _P, _P]),
+    "tgs_project_bwd": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
+                               _P, _P, _P, _P, _P]),
+    "tgs_optimizer_step": (_I32, [_P, _P, _P, _P, _I64, _P, ctypes.POINTER(tgs_optim_params), _I64, _P]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_15924_amd.build`")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in PROTOTYPES.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def _check(status: int, name: str, required: int | None = None):
+    if status == TGS_OK:
+        return
+    msg = lib().tgs_last_error().decode()
+    if status == TGS_ERR_CAPACITY:
+        raise CapacityError(f"{name}: {msg}", int(required or 0))
+    raise RuntimeError(f"{name} failed ({status}): {msg}")
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ records
+def camera(cam) -> tgs_camera:
+    """A ``tgs_camera`` from any object with R, t, fx, fy, cx, cy, width, height."""
+    c = tgs_camera()
+    R = [float(v) for row in cam.R for v in row]
+    for i in range(9):
+        c.R[i] = R[i]
+    for i in range(3):
+        c.t[i] = float(cam.t[i])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def raster_params(sh_degree=3, z_near=0.2, dilation=0.3, alpha_min=1.0 / 255.0, alpha_max=0.99,
+                  T_min=1e-4, bg=(0.0, 0.0, 0.0)) -> tgs_raster_params:
+    r = tgs_raster_params()
+    r.sh_degree, r.z_near, r.dilation = sh_degree, z_near, dilation
+    r.alpha_min, r.alpha_max, r.T_min = alpha_min, alpha_max, T_min
+    for i in range(3):
+        r.bg[i] = bg[i]
+    return r
+
+
+def sample_params(n_pix, hard_permille=400, stable_permille=300, n_tiles_sel=-1, seed=0, step=0,
+                  view=0) -> tgs_sample_params:
+    s = tgs_sample_params()
+    s.n_pix, s.hard_permille, s.stable_permille, s.n_tiles_sel = n_pix, hard_permille, stable_permille, n_tiles_sel
+    s.seed, s.step, s.view = seed, step, view
+    return s
+
+
+def loss_params(eps_charb=1e-3, eps_ncc=1e-6, eps_lambda=1e-8) -> tgs_loss_params:
+    p = tgs_loss_params()
+    p.eps_charb, p.eps_ncc, p.eps_lambda = eps_charb, eps_ncc, eps_lambda
+    return p
+
+
+def optim_params(lr_mean=1.6e-4, lr_scale=5e-3, lr_quat=1e-3, lr_opacity=2.5e-2, lr_sh_dc=2.5e-3,
+                 lr_sh_rest=2.5e-3 / 20.0, beta1=0.9, beta2=0.999, eps_adam=1e-15, eps_lm=1e-8,
+                 lm_mode=0) -> tgs_optim_params:
+    o = tgs_optim_params()
+    o.lr_mean, o.lr_scale, o.lr_quat, o.lr_opacity = lr_mean, lr_scale, lr_quat, lr_opacity
+    o.lr_sh_dc, o.lr_sh_rest, o.beta1, o.beta2 = lr_sh_dc, lr_sh_rest, beta1, beta2
+    o.eps_adam, o.eps_lm, o.lm_mode = eps_adam, eps_lm, lm_mode
+    return o
+
+
+# ------------------------------------------------------------------ entry points
+def tgs_version() -> int:
+    return int(lib().tgs_version())
+
+
+def tgs_pixels_per_tile(rate_permille: int) -> int:
+    return int(lib().tgs_pixels_per_tile(rate_permille))
+
+
+def tgs_sample_tile_count(height: int, width: int, sp: tgs_sample_params) -> int:
+    return int(lib().tgs_sample_tile_count(height, width, ctypes.byref(sp)))
+
+
+def tgs_project(params, n, cam: tgs_camera, rp: tgs_raster_params, splat, depth, radius, rect, clamp):
+    _check(lib().tgs_project(_ptr(params), n, ctypes.byref(cam), ctypes.byref(rp), _ptr(splat), _ptr(depth),
+                             _ptr(radius), _ptr(rect), _ptr(clamp), _stream()), "tgs_project")
+
+
+def tgs_sample_workspace_size(height: int, width: int) -> int:
+    return int(lib().tgs_sample_workspace_size(height, width))
+
+
+def tgs_sample(E, A, height, width, sp: tgs_sample_params, valid_tiles, tile_off, pix, tile_slot,
+               totals, ws):
+    _check(lib().tgs_sample(_ptr(E), _ptr(A), height, width, ctypes.byref(sp), _ptr(valid_tiles),
+                            _ptr(tile_off), _ptr(pix), _ptr(tile_slot), _ptr(totals), _ptr(ws),
+                            ws.numel() * ws.element_size(), _stream()), "tgs_sample")
+
+
+def tgs_bin_sort_workspace_size(n: int, capacity: int, n_tiles: int) -> int:
+    return int(lib().tgs_bin_sort_workspace_size(n, capacity, n_tiles))
+
+
+def tgs_bin_sort(rect, depth, n, tile_slot, tiles_x, tiles_y, keys, vals, capacity, ranges, touched,
+                 ws) -> int:
+    """Returns the pair count; raises CapacityError(required) when it exceeds capacity."""
+    n_pairs = _I64(0)
+    st = lib().tgs_bin_sort(_ptr(rect), _ptr(depth), n, _ptr(tile_slot), tiles_x, tiles_y, _ptr(keys),
+                            _ptr(vals), capacity, _ptr(ranges), _ptr(touched), ctypes.byref(n_pairs),
+                            _ptr(ws), ws.numel() * ws.element_size(), _stream())
+    _check(st, "tgs_bin_sort", n_pairs.value)
+    return int(n_pairs.value)
+
+
+def tgs_render_fwd(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
+                   n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, counters=None):
+    _check(lib().tgs_render_fwd(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
+                                _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
+                                ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(counters), _stream()),
+           "tgs_render_fwd")
+
+
+def tgs_render_bwd(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
+                   n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL_dout, g2d):
+    _check(lib().tgs_render_bwd(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
+                                _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
+                                ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(dL_dout), _ptr(g2d),
+                                _stream()), "tgs_render_bwd")
+
+
+def tgs_loss(out, gt, height, width, valid_tiles, tile_off, pix, n_st, totals, lp: tgs_loss_params,
+             dL_dout, err, lam, tile_loss):
+    _check(lib().tgs_loss(_ptr(out), _ptr(gt), height, width, _ptr(valid_tiles), _ptr(tile_off), _ptr(pix),
+                          n_st, _ptr(totals), ctypes.byref(lp), _ptr(dL_dout), _ptr(err), _ptr(lam),
+                          _ptr(tile_loss), _stream()), "tgs_loss")
+
+
+def tgs_ema_age_update(E, A, height, width, tile_slot, tile_off, pix, err, beta):
+    _check(lib().tgs_ema_age_update(_ptr(E), _ptr(A), height, width, _ptr(tile_slot), _ptr(tile_off),
+                                    _ptr(pix), _ptr(err), beta, _stream()), "tgs_ema_age_update")
+
+
+def tgs_error_init(out_dense, gt, height, width, E):
+    _check(lib().tgs_error_init(_ptr(out_dense), _ptr(gt), height, width, _ptr(E), _stream()),
+           "tgs_error_init")
+
+
+def tgs_project_bwd(params, n, cam: tgs_camera, rp: tgs_raster_params, radius, clamp, g2d, grad):
+    _check(lib().tgs_project_bwd(_ptr(params), n, ctypes.byref(cam), ctypes.byref(rp), _ptr(radius),
+                                 _ptr(clamp), _ptr(g2d), _ptr(grad), _stream()), "tgs_project_bwd")
+
+
+def tgs_optimizer_step(params, grad, m, v, n, touched, op: tgs_optim_params, step):
+    _check(lib().tgs_optimizer_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, _ptr(touched),
+                                    ctypes.byref(op), step, _stream()), "tgs_optimizer_step")

@@ -1,0 +1,392 @@
+// EWA projection with SH colour (forward) and its chain rule (backward).
+//
+// One thread per Gaussian, FP64 arithmetic.  Both kernels are HBM-bound
+// (59 floats in, 12-17 out per Gaussian), so FP64 costs nothing measurable
+// on gfx950 (78.6 TFLOP/s FP64) and keeps the integer decisions (depth key
+// bits, tile rectangle, radius) identical to an FP64 reference written in
+// the same operation order.  Parameters are read row by row from the
+// [59][n] store, so every load is coalesced across the wave.
+#include "common.h"
+
+// The depth, centre and rectangle must follow a fixed sequence of rounded
+// operations; no multiply-add contraction in this file.
+#pragma clang fp contract(off)
+
+namespace tgs {
+
+struct CamArgs {
+  double R[9];
+  double t[3];
+  double center[3];
+  double fx, fy, cx, cy;
+  int width, height, tiles_x, tiles_y;
+};
+
+static CamArgs make_cam(const tgs_camera* c) {
+  CamArgs a;
+  for (int i = 0; i < 9; ++i) a.R[i] = c->R[i];
+  for (int i = 0; i < 3; ++i) a.t[i] = c->t[i];
+  // camera centre = -R^T t
+  for (int j = 0; j < 3; ++j)
+    a.center[j] = -(c->R[0 * 3 + j] * c->t[0] + c->R[1 * 3 + j] * c->t[1] + c->R[2 * 3 + j] * c->t[2]);
+  a.fx = c->fx;
+  a.fy = c->fy;
+  a.cx = c->cx;
+  a.cy = c->cy;
+  a.width = c->width;
+  a.height = c->height;
+  a.tiles_x = (int)ceil_div(c->width, kTile);
+  a.tiles_y = (int)ceil_div(c->height, kTile);
+  return a;
+}
+
+// Real SH basis up to degree 3 as Cartesian polynomials of the unit
+// direction (Condon-Shortley phase, order l then m = -l..l).  Constants are
+// the normalisations sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) (x sqrt(2) for
+// m != 0) folded with the polynomial factors:
+constexpr double kC0 = 0.28209479177387814;    // 1/(2 sqrt(pi))
+constexpr double kC1 = 0.4886025119029199;     // sqrt(3/(4 pi))
+constexpr double kC2a = 1.0925484305920792;    // sqrt(15/(4 pi))
+constexpr double kC2b = 0.31539156525252005;   // sqrt(5/(16 pi))
+constexpr double kC2c = 0.5462742152960396;    // sqrt(15/(16 pi))
+constexpr double kC3a = 0.5900435899266435;    // sqrt(35/(32 pi))
+constexpr double kC3b = 2.890611442640554;     // sqrt(105/(4 pi))
+constexpr double kC3c = 0.4570457994644658;    // sqrt(21/(32 pi))
+constexpr double kC3d = 0.3731763325901154;    // sqrt(7/(16 pi))
+constexpr double kC3e = 1.445305721320277;     // sqrt(105/(16 pi))
+
+__device__ __forceinline__ void sh_eval(double x, double y, double z, double Y[16]) {
+  const double xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = kC0;
+  Y[1] = -kC1 * y;
+  Y[2] = kC1 * z;
+  Y[3] = -kC1 * x;
+  Y[4] = kC2a * x * y;
+  Y[5] = -kC2a * y * z;
+  Y[6] = kC2b * (2.0 * zz - xx - yy);
+  Y[7] = -kC2a * x * z;
+  Y[8] = kC2c * (xx - yy);
+  Y[9] = -kC3a * y * (3.0 * xx - yy);
+  Y[10] = kC3b * x * y * z;
+  Y[11] = -kC3c * y * (4.0 * zz - xx - yy);
+  Y[12] = kC3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+  Y[13] = -kC3c * x * (4.0 * zz - xx - yy);
+  Y[14] = kC3e * z * (xx - yy);
+  Y[15] = -kC3a * x * (xx - 3.0 * yy);
+}
+
+// Gradient of each polynomial above with respect to (x, y, z).
+__device__ __forceinline__ void sh_grad(double x, double y, double z, double dY[16][3]) {
+  const double xx = x * x, yy = y * y, zz = z * z;
+  dY[0][0] = 0; dY[0][1] = 0; dY[0][2] = 0;
+  dY[1][0] = 0; dY[1][1] = -kC1; dY[1][2] = 0;
+  dY[2][0] = 0; dY[2][1] = 0; dY[2][2] = kC1;
+  dY[3][0] = -kC1; dY[3][1] = 0; dY[3][2] = 0;
+  dY[4][0] = kC2a * y; dY[4][1] = kC2a * x; dY[4][2] = 0;
+  dY[5][0] = 0; dY[5][1] = -kC2a * z; dY[5][2] = -kC2a * y;
+  dY[6][0] = -2.0 * kC2b * x; dY[6][1] = -2.0 * kC2b * y; dY[6][2] = 4.0 * kC2b * z;
+  dY[7][0] = -kC2a * z; dY[7][1] = 0; dY[7][2] = -kC2a * x;
+  dY[8][0] = 2.0 * kC2c * x; dY[8][1] = -2.0 * kC2c * y; dY[8][2] = 0;
+  dY[9][0] = -kC3a * 6.0 * x * y; dY[9][1] = -kC3a * (3.0 * xx - 3.0 * yy); dY[9][2] = 0;
+  dY[10][0] = kC3b * y * z; dY[10][1] = kC3b * x * z; dY[10][2] = kC3b * x * y;
+  dY[11][0] = -kC3c * (-2.0 * x * y);
+  dY[11][1] = -kC3c * (4.0 * zz - xx - 3.0 * yy);
+  dY[11][2] = -kC3c * (8.0 * y * z);
+  dY[12][0] = kC3d * (-6.0 * x * z);
+  dY[12][1] = kC3d * (-6.0 * y * z);
+  dY[12][2] = kC3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+  dY[13][0] = -kC3c * (4.0 * zz - 3.0 * xx - yy);
+  dY[13][1] = -kC3c * (-2.0 * x * y);
+  dY[13][2] = -kC3c * (8.0 * x * z);
+  dY[14][0] = kC3e * 2.0 * x * z; dY[14][1] = -kC3e * 2.0 * y * z; dY[14][2] = kC3e * (xx - yy);
+  dY[15][0] = -kC3a * (3.0 * xx - 3.0 * yy); dY[15][1] = -kC3a * (-6.0 * x * y); dY[15][2] = 0;
+}
+
+__device__ __forceinline__ int n_sh(int degree) { return (degree + 1) * (degree + 1); }
+
+// Forward geometry shared by both kernels (recomputed in the backward).
+struct Geom {
+  double mu[3], t[3];
+  double s[3], qn[4], qnorm;
+  double Rq[3][3], M[3][3], Sigma[3][3];
+  double J00, J02, J11, J12;
+  double T[2][3];
+  double a, b, c, det;
+  double px, py, radius;
+  bool visible;
+  int rect[4];
+};
+
+__device__ __forceinline__ void geometry(const float* __restrict__ params, int64_t n, int64_t i,
+                                         const CamArgs& cam, double z_near, double dil, Geom& g) {
+  for (int k = 0; k < 3; ++k) g.mu[k] = (double)params[(int64_t)k * n + i];
+  for (int r = 0; r < 3; ++r)
+    g.t[r] = ((cam.R[r * 3 + 0] * g.mu[0] + cam.R[r * 3 + 1] * g.mu[1]) + cam.R[r * 3 + 2] * g.mu[2]) +
+             cam.t[r];
+  const double tx = g.t[0], ty = g.t[1], tz = g.t[2];
+  const bool in_front = tz > z_near;
+  const double tzs = in_front ? tz : 1.0;
+
+  for (int k = 0; k < 3; ++k) g.s[k] = exp((double)params[(int64_t)(3 + k) * n + i]);
+  const double qw = params[6 * n + i], qx = params[7 * n + i], qy = params[8 * n + i],
+               qz = params[9 * n + i];
+  g.qnorm = sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+  const double w = qw / g.qnorm, x = qx / g.qnorm, y = qy / g.qnorm, z = qz / g.qnorm;
+  g.qn[0] = w; g.qn[1] = x; g.qn[2] = y; g.qn[3] = z;
+  g.Rq[0][0] = 1.0 - 2.0 * (y * y + z * z);
+  g.Rq[0][1] = 2.0 * (x * y - w * z);
+  g.Rq[0][2] = 2.0 * (x * z + w * y);
+  g.Rq[1][0] = 2.0 * (x * y + w * z);
+  g.Rq[1][1] = 1.0 - 2.0 * (x * x + z * z);
+  g.Rq[1][2] = 2.0 * (y * z - w * x);
+  g.Rq[2][0] = 2.0 * (x * z - w * y);
+  g.Rq[2][1] = 2.0 * (y * z + w * x);
+  g.Rq[2][2] = 1.0 - 2.0 * (x * x + y * y);
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) g.M[r][k] = g.Rq[r][k] * g.s[k];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k)
+      g.Sigma[r][k] = (g.M[r][0] * g.M[k][0] + g.M[r][1] * g.M[k][1]) + g.M[r][2] * g.M[k][2];
+
+  g.J00 = cam.fx / tzs;
+  g.J02 = -(cam.fx * tx) / (tzs * tzs);
+  g.J11 = cam.fy / tzs;
+  g.J12 = -(cam.fy * ty) / (tzs * tzs);
+  for (int j = 0; j < 3; ++j) {
+    g.T[0][j] = g.J00 * cam.R[0 * 3 + j] + g.J02 * cam.R[2 * 3 + j];
+    g.T[1][j] = g.J11 * cam.R[1 * 3 + j] + g.J12 * cam.R[2 * 3 + j];
+  }
+  double TS[2][3];
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 3; ++k)
+      TS[r][k] = (g.T[r][0] * g.Sigma[0][k] + g.T[r][1] * g.Sigma[1][k]) + g.T[r][2] * g.Sigma[2][k];
+  const double s00 = (TS[0][0] * g.T[0][0] + TS[0][1] * g.T[0][1]) + TS[0][2] * g.T[0][2];
+  const double s01 = (TS[0][0] * g.T[1][0] + TS[0][1] * g.T[1][1]) + TS[0][2] * g.T[1][2];
+  const double s11 = (TS[1][0] * g.T[1][0] + TS[1][1] * g.T[1][1]) + TS[1][2] * g.T[1][2];
+  g.a = s00 + dil;
+  g.b = s01;
+  g.c = s11 + dil;
+  g.det = g.a * g.c - g.b * g.b;
+  const bool ok_det = g.det > 0.0;
+
+  const double mid = 0.5 * (g.a + g.c);
+  const double lam1 = mid + sqrt(fmax(0.1, mid * mid - g.det));
+  g.radius = ceil(3.0 * sqrt(lam1));
+  g.px = ((cam.fx * tx) / tzs + cam.cx) - 0.5;
+  g.py = ((cam.fy * ty) / tzs + cam.cy) - 0.5;
+
+  auto tclamp = [](double v, int hi) -> int {
+    double tv = trunc(v);
+    if (!(tv > 0.0)) return 0;  // also maps NaN to 0
+    if (tv > (double)hi) return hi;
+    return (int)tv;
+  };
+  const double r = g.radius;
+  g.rect[0] = tclamp((g.px - r) / 16.0, cam.tiles_x);
+  g.rect[1] = tclamp((g.py - r) / 16.0, cam.tiles_y);
+  g.rect[2] = tclamp(((g.px + r) + 15.0) / 16.0, cam.tiles_x);
+  g.rect[3] = tclamp(((g.py + r) + 15.0) / 16.0, cam.tiles_y);
+  const int area = (g.rect[2] - g.rect[0]) * (g.rect[3] - g.rect[1]);
+  g.visible = in_front && ok_det && area > 0;
+}
+
+__global__ void __launch_bounds__(256) project_fwd_kernel(
+    const float* __restrict__ params, int64_t n, CamArgs cam, int sh_degree, double z_near,
+    double dil, float4* __restrict__ splat, float* __restrict__ depth, int* __restrict__ radius,
+    int4* __restrict__ rect, uint8_t* __restrict__ clampm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Geom g;
+  geometry(params, n, i, cam, z_near, dil, g);
+  depth[i] = (float)g.t[2];
+  if (!g.visible) {
+    radius[i] = 0;
+    rect[i] = make_int4(0, 0, 0, 0);
+    clampm[i] = 0;
+    splat[3 * i + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    splat[3 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    splat[3 * i + 2] = make_float4(0.f, 0.f, 0.f, (float)g.t[2]);
+    return;
+  }
+  // view-dependent colour
+  const double dx = g.mu[0] - cam.center[0], dy = g.mu[1] - cam.center[1],
+               dz = g.mu[2] - cam.center[2];
+  const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+  double Y[16];
+  sh_eval(dx / dn, dy / dn, dz / dn, Y);
+  const int nk = n_sh(sh_degree);
+  double rgb[3] = {0.5, 0.5, 0.5};
+  for (int k = 0; k < nk; ++k)
+    for (int ch = 0; ch < 3; ++ch) rgb[ch] += Y[k] * (double)params[(int64_t)(11 + 3 * k + ch) * n + i];
+  uint8_t cm = 0;
+  for (int ch = 0; ch < 3; ++ch)
+    if (rgb[ch] < 0.0) {
+      rgb[ch] = 0.0;
+      cm |= (uint8_t)(1u << ch);
+    }
+  const double opac = 1.0 / (1.0 + exp(-(double)params[10 * n + i]));
+  const double fxp = floor(g.px), fyp = floor(g.py);
+  splat[3 * i + 0] = make_float4((float)fxp, (float)fyp, (float)(g.px - fxp), (float)(g.py - fyp));
+  splat[3 * i + 1] = make_float4((float)(g.c / g.det), (float)(-g.b / g.det), (float)(g.a / g.det),
+                                 (float)opac);
+  splat[3 * i + 2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], (float)g.t[2]);
+  radius[i] = (int)g.radius;
+  rect[i] = make_int4(g.rect[0], g.rect[1], g.rect[2], g.rect[3]);
+  clampm[i] = cm;
+}
+
+__global__ void __launch_bounds__(256) project_bwd_kernel(
+    const float* __restrict__ params, int64_t n, CamArgs cam, int sh_degree, double z_near,
+    double dil, const int* __restrict__ radius, const uint8_t* __restrict__ clampm,
+    const float* __restrict__ g2d, float* __restrict__ grad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || radius[i] == 0) return;
+  Geom g;
+  geometry(params, n, i, cam, z_near, dil, g);
+  double gg[9];
+  for (int k = 0; k < 9; ++k) gg[k] = (double)g2d[i * 9 + k];
+  const double tx = g.t[0], ty = g.t[1], tz = g.t[2];
+
+  // ---- colour -> SH coefficients and the view direction
+  const uint8_t cm = clampm[i];
+  double drgb[3];
+  for (int ch = 0; ch < 3; ++ch) drgb[ch] = (cm >> ch) & 1u ? 0.0 : gg[6 + ch];
+  const double vx = g.mu[0] - cam.center[0], vy = g.mu[1] - cam.center[1], vz = g.mu[2] - cam.center[2];
+  const double dn = sqrt(vx * vx + vy * vy + vz * vz);
+  const double ux = vx / dn, uy = vy / dn, uz = vz / dn;
+  double Y[16], dY[16][3];
+  sh_eval(ux, uy, uz, Y);
+  sh_grad(ux, uy, uz, dY);
+  const int nk = n_sh(sh_degree);
+  double dL_du[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < nk; ++k) {
+    double gk = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+      const int64_t row = (int64_t)(11 + 3 * k + ch) * n + i;
+      grad[row] += (float)(Y[k] * drgb[ch]);
+      gk += (double)params[row] * drgb[ch];
+    }
+    for (int a = 0; a < 3; ++a) dL_du[a] += dY[k][a] * gk;
+  }
+  // d Y(v/|v|) / dv = (I - u u^T) grad Y(u) / |v|
+  const double udot = ux * dL_du[0] + uy * dL_du[1] + uz * dL_du[2];
+  double dmu[3] = {(dL_du[0] - ux * udot) / dn, (dL_du[1] - uy * udot) / dn,
+                   (dL_du[2] - uz * udot) / dn};
+
+  // ---- opacity
+  const double o = 1.0 / (1.0 + exp(-(double)params[10 * n + i]));
+  grad[10 * n + i] += (float)(gg[5] * o * (1.0 - o));
+
+  // ---- centre
+  const double tz2 = tz * tz, tz3 = tz2 * tz;
+  double dt[3];
+  dt[0] = gg[0] * cam.fx / tz;
+  dt[1] = gg[1] * cam.fy / tz;
+  dt[2] = gg[0] * (-cam.fx * tx / tz2) + gg[1] * (-cam.fy * ty / tz2);
+
+  // ---- conic (ca, cb, cc) = (c, -b, a) / det  ->  Sigma' entries
+  const double a = g.a, b = g.b, c = g.c, det = g.det, d2 = det * det;
+  const double gca = gg[2], gcb = gg[3], gcc = gg[4];
+  const double dLa = gca * (-c * c / d2) + gcb * (b * c / d2) + gcc * (1.0 / det - a * c / d2);
+  const double dLb = gca * (2.0 * b * c / d2) + gcb * (-1.0 / det - 2.0 * b * b / d2) + gcc * (2.0 * a * b / d2);
+  const double dLc = gca * (1.0 / det - a * c / d2) + gcb * (a * b / d2) + gcc * (-a * a / d2);
+  const double G[2][2] = {{dLa, 0.5 * dLb}, {0.5 * dLb, dLc}};
+
+  // dSigma = T^T G T ; dT = 2 G T Sigma
+  double GT[2][3];
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 3; ++k) GT[r][k] = G[r][0] * g.T[0][k] + G[r][1] * g.T[1][k];
+  double dSigma[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) dSigma[r][k] = g.T[0][r] * GT[0][k] + g.T[1][r] * GT[1][k];
+  double dT[2][3];
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 3; ++k)
+      dT[r][k] = 2.0 * (GT[r][0] * g.Sigma[0][k] + GT[r][1] * g.Sigma[1][k] + GT[r][2] * g.Sigma[2][k]);
+  // T = J W  ->  dJ = dT W^T (only the four non-zero entries of J matter)
+  auto dJ = [&](int r, int k) {
+    return dT[r][0] * cam.R[k * 3 + 0] + dT[r][1] * cam.R[k * 3 + 1] + dT[r][2] * cam.R[k * 3 + 2];
+  };
+  const double dJ00 = dJ(0, 0), dJ02 = dJ(0, 2), dJ11 = dJ(1, 1), dJ12 = dJ(1, 2);
+  dt[0] += dJ02 * (-cam.fx / tz2);
+  dt[1] += dJ12 * (-cam.fy / tz2);
+  dt[2] += dJ00 * (-cam.fx / tz2) + dJ02 * (2.0 * cam.fx * tx / tz3) + dJ11 * (-cam.fy / tz2) +
+           dJ12 * (2.0 * cam.fy * ty / tz3);
+  // t = W mu + t_cam
+  for (int k = 0; k < 3; ++k)
+    dmu[k] += cam.R[0 * 3 + k] * dt[0] + cam.R[1 * 3 + k] * dt[1] + cam.R[2 * 3 + k] * dt[2];
+
+  // ---- Sigma = M M^T, M = R(q) diag(s)
+  double dM[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k)
+      dM[r][k] = 2.0 * (dSigma[r][0] * g.M[0][k] + dSigma[r][1] * g.M[1][k] + dSigma[r][2] * g.M[2][k]);
+  double dR[3][3];
+  for (int k = 0; k < 3; ++k) {
+    const double ds = g.Rq[0][k] * dM[0][k] + g.Rq[1][k] * dM[1][k] + g.Rq[2][k] * dM[2][k];
+    grad[(int64_t)(3 + k) * n + i] += (float)(ds * g.s[k]);
+    for (int r = 0; r < 3; ++r) dR[r][k] = dM[r][k] * g.s[k];
+  }
+  const double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+  // dL/dq_n from the derivative of each rotation entry
+  double dq[4];
+  dq[0] = 2.0 * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
+  dq[1] = 2.0 * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.0 * x * dR[1][1] - w * dR[1][2] +
+                 z * dR[2][0] + w * dR[2][1] - 2.0 * x * dR[2][2]);
+  dq[2] = 2.0 * (-2.0 * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] -
+                 w * dR[2][0] + z * dR[2][1] - 2.0 * y * dR[2][2]);
+  dq[3] = 2.0 * (-2.0 * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.0 * z * dR[1][1] +
+                 y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+  const double qdot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+  grad[6 * n + i] += (float)((dq[0] - w * qdot) / g.qnorm);
+  grad[7 * n + i] += (float)((dq[1] - x * qdot) / g.qnorm);
+  grad[8 * n + i] += (float)((dq[2] - y * qdot) / g.qnorm);
+  grad[9 * n + i] += (float)((dq[3] - z * qdot) / g.qnorm);
+  for (int k = 0; k < 3; ++k) grad[(int64_t)k * n + i] += (float)dmu[k];
+}
+
+}  // namespace tgs
+
+using namespace tgs;
+
+static int32_t check_raster_params(const tgs_raster_params* rp) {
+  TGS_REQUIRE(rp != nullptr, "raster params: null");
+  TGS_REQUIRE(rp->sh_degree >= 0 && rp->sh_degree <= 3, "raster params: sh_degree %d not in 0..3",
+              rp->sh_degree);
+  return TGS_OK;
+}
+
+extern "C" int32_t tgs_project(const float* params, int64_t n, const tgs_camera* cam,
+                               const tgs_raster_params* rp, float* splat, float* depth,
+                               int32_t* radius, int32_t* rect, uint8_t* clamp, void* stream) {
+  TGS_REQUIRE(n >= 0, "tgs_project: n < 0");
+  TGS_REQUIRE(cam != nullptr && cam->width > 0 && cam->height > 0, "tgs_project: bad camera");
+  if (int32_t e = check_raster_params(rp)) return e;
+  if (n == 0) return TGS_OK;
+  TGS_REQUIRE(params && splat && depth && radius && rect && clamp, "tgs_project: null pointer");
+  TGS_REQUIRE(((uintptr_t)splat & 15) == 0 && ((uintptr_t)rect & 15) == 0,
+              "tgs_project: splat and rect must be 16-byte aligned");
+  const CamArgs ca = make_cam(cam);
+  const int block = 256;
+  hipLaunchKernelGGL(project_fwd_kernel, dim3((unsigned)ceil_div(n, block)), dim3(block), 0,
+                     as_stream(stream), params, n, ca, rp->sh_degree, (double)rp->z_near,
+                     (double)rp->dilation, (float4*)splat, depth, radius, (int4*)rect, clamp);
+  return hip_status("tgs_project");
+}
+
+extern "C" int32_t tgs_project_bwd(const float* params, int64_t n, const tgs_camera* cam,
+                                   const tgs_raster_params* rp, const int32_t* radius,
+                                   const uint8_t* clamp, const float* g2d, float* grad,
+                                   void* stream) {
+  TGS_REQUIRE(n >= 0, "tgs_project_bwd: n < 0");
+  TGS_REQUIRE(cam != nullptr && cam->width > 0 && cam->height > 0, "tgs_project_bwd: bad camera");
+  if (int32_t e = check_raster_params(rp)) return e;
+  if (n == 0) return TGS_OK;
+  TGS_REQUIRE(params && radius && clamp && g2d && grad, "tgs_project_bwd: null pointer");
+  const CamArgs ca = make_cam(cam);
+  const int block = 256;
+  hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)ceil_div(n, block)), dim3(block), 0,
+                     as_stream(stream), params, n, ca, rp->sh_degree, (double)rp->z_near,
+                     (double)rp->dilation, radius, clamp, g2d, grad);
+  return hip_status("tgs_project_bwd");
+}

@@ -1,0 +1,320 @@
+// Tile-wise error/age pixel sampling (Sec. 3.5).
+//
+// Three kernels per view:
+//   tile_weights  one wave per tile: integer tile weight (sum of E * 2^24), only
+//                 when tiles are drawn in proportion to error;
+//   tile_select   one workgroup: the tile draws (or every tile), the per-tile
+//                 sample counts, their prefix offsets and the tile -> slot map;
+//   tile_pixels   one wave per selected tile: N_hard sequential error-weighted
+//                 draws without replacement, TopK age, uniform mixed draws.
+// All decisions are integer: weights are exact integers (every finite
+// non-negative half times 2^24 is one), a draw r = floor(u * W / 2^64) uses
+// the high half of a 64 x 64-bit product, and the pick is the first pixel
+// (ascending local index) whose running weight exceeds r.  Each lane owns four
+// consecutive local indices, so lane order is index order and a wave prefix
+// sum locates a draw.
+#include "common.h"
+
+namespace tgs {
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+// SplitMix64 finaliser (Steele, Lea & Flood 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t absorb(uint64_t h, uint64_t field) {
+  return mix64(h + kGamma * (field + 1ull));
+}
+
+// Key of the (seed, step, view, tile) stream; a draw is absorb(key, slot).
+__device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t step, uint64_t view,
+                                               uint64_t tile) {
+  return absorb(absorb(absorb(seed, step), view), tile);
+}
+
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+// E * 2^24 for a half bit pattern; negative, infinite and NaN values weigh 0.
+__device__ __forceinline__ uint64_t half_weight(uint16_t h) {
+  const uint32_t sign = h >> 15, ex = (h >> 10) & 0x1f, man = h & 0x3ff;
+  if (sign || ex == 0x1f) return 0;
+  if (ex == 0) return man;
+  return (uint64_t)(1024u + man) << (ex - 1);
+}
+
+__device__ __forceinline__ int tile_valid_w(int tx, int W) { return min(kTile, W - tx * kTile); }
+__device__ __forceinline__ int tile_valid_h(int ty, int H) { return min(kTile, H - ty * kTile); }
+
+// ------------------------------------------------------------------ tile weights
+__global__ void __launch_bounds__(64) tile_weights_kernel(const uint16_t* __restrict__ E, int H,
+                                                          int W, int tiles_x, int n_t,
+                                                          uint64_t* __restrict__ tw) {
+  const int t = blockIdx.x;
+  if (t >= n_t) return;
+  const int tx = t % tiles_x, ty = t / tiles_x;
+  const int lane = threadIdx.x;
+  uint64_t s = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int loc = lane * 4 + k;
+    const int x = tx * kTile + (loc & 15), y = ty * kTile + (loc >> 4);
+    if (x < W && y < H) s += half_weight(E[(int64_t)y * W + x]);
+  }
+  // wave sum of u64 as two 32-bit halves is not exact; use the inclusive scan
+  s = wave_inclusive_scan_u64(s);
+  if (lane == 63) tw[t] = s;
+}
+
+// ------------------------------------------------------------------ tile select
+// One wave of 64 lanes; lane l owns tiles [l * chunk, (l + 1) * chunk).
+constexpr int kSelectThreads = 64;
+
+__global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
+    uint64_t* __restrict__ tw, int H, int W, int tiles_x, int n_t, int n_sel, int n_pix,
+    uint64_t seed, uint64_t step, uint64_t view, int32_t* __restrict__ valid_tiles,
+    int32_t* __restrict__ tile_off, int32_t* __restrict__ tile_slot, int64_t* __restrict__ totals,
+    uint8_t* __restrict__ chosen) {
+  const int lane = threadIdx.x;
+  const int chunk = (n_t + kSelectThreads - 1) / kSelectThreads;
+  const int c0 = min(n_t, lane * chunk), c1 = min(n_t, c0 + chunk);
+  const bool all_tiles = n_sel < 0 || n_sel >= n_t;
+  for (int t = c0; t < c1; ++t) chosen[t] = all_tiles ? 1 : 0;
+  if (!all_tiles) {
+    uint64_t lsum = 0;
+    for (int t = c0; t < c1; ++t) lsum += tw[t];
+    int lrem = c1 - c0;
+    const uint64_t key = stream_key(seed, step, view, (uint64_t)n_t);
+    for (int j = 0; j < n_sel; ++j) {
+      const uint64_t u = absorb(key, (uint64_t)j);
+      const uint64_t incl = wave_inclusive_scan_u64(lsum);
+      const uint64_t total = __shfl(incl, 63, kWave);
+      if (total > 0) {
+        const uint64_t r = mulhi64(u, total);
+        const uint64_t excl = incl - lsum;
+        if (lsum > 0 && excl <= r && r < incl) {
+          uint64_t run = excl;
+          for (int t = c0; t < c1; ++t) {
+            run += tw[t];
+            if (run > r) {
+              lsum -= tw[t];
+              tw[t] = 0;
+              chosen[t] = 1;
+              --lrem;
+              break;
+            }
+          }
+        }
+      } else {
+        const int ic = wave_inclusive_scan_i(lrem);
+        const int nrem = __shfl(ic, 63, kWave);
+        const int r = (int)mulhi64(u, (uint64_t)nrem);
+        const int ex = ic - lrem;
+        if (lrem > 0 && ex <= r && r < ic) {
+          int k = ex;
+          for (int t = c0; t < c1; ++t) {
+            if (!chosen[t]) {
+              if (k == r) {
+                chosen[t] = 1;
+                --lrem;
+                break;
+              }
+              ++k;
+            }
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+  }
+  __syncthreads();
+  // compact chosen tiles in ascending order with their sample counts
+  int lcount = 0, lpix = 0;
+  for (int t = c0; t < c1; ++t)
+    if (chosen[t]) {
+      ++lcount;
+      const int tx = t % tiles_x, ty = t / tiles_x;
+      lpix += min(n_pix, tile_valid_w(tx, W) * tile_valid_h(ty, H));
+    }
+  const int ic = wave_inclusive_scan_i(lcount);
+  const int ip = wave_inclusive_scan_i(lpix);
+  int slot = ic - lcount, off = ip - lpix;
+  for (int t = c0; t < c1; ++t) {
+    if (chosen[t]) {
+      const int tx = t % tiles_x, ty = t / tiles_x;
+      valid_tiles[slot] = t;
+      tile_off[slot] = off;
+      tile_slot[t] = slot;
+      off += min(n_pix, tile_valid_w(tx, W) * tile_valid_h(ty, H));
+      ++slot;
+    } else {
+      tile_slot[t] = -1;
+    }
+  }
+  if (lane == 63) {
+    tile_off[ic] = ip;
+    atomicAdd((unsigned long long*)&totals[0], (unsigned long long)ip);
+    atomicAdd((unsigned long long*)&totals[1], (unsigned long long)ic);
+  }
+}
+
+// ------------------------------------------------------------------ tile pixels
+__device__ __forceinline__ int split_round(int permille, int n) { return (permille * n + 500) / 1000; }
+
+__global__ void __launch_bounds__(64) tile_pixels_kernel(
+    const uint16_t* __restrict__ E, const uint16_t* __restrict__ A, int H, int W, int tiles_x,
+    int n_st, int n_pix, int hard_pm, int stable_pm, uint64_t seed, uint64_t step, uint64_t view,
+    const int32_t* __restrict__ valid_tiles, const int32_t* __restrict__ tile_off,
+    uint8_t* __restrict__ pix) {
+  const int slot = blockIdx.x;
+  if (slot >= n_st) return;
+  const int lane = threadIdx.x;
+  const int t = valid_tiles[slot];
+  const int tx = t % tiles_x, ty = t / tiles_x;
+  const int n_valid = tile_valid_w(tx, W) * tile_valid_h(ty, H);
+  const int n = min(n_pix, n_valid);
+  int n_hard = split_round(hard_pm, n);
+  int n_stable = split_round(stable_pm, n);
+  if (n_hard + n_stable > n) n_stable = n - n_hard;
+  int n_mixed = n - n_hard - n_stable;
+
+  uint64_t w[4];
+  uint32_t age[4];
+  bool valid[4];
+  for (int k = 0; k < 4; ++k) {
+    const int loc = lane * 4 + k;
+    const int x = tx * kTile + (loc & 15), y = ty * kTile + (loc >> 4);
+    valid[k] = x < W && y < H;
+    const int64_t idx = (int64_t)y * W + x;
+    w[k] = valid[k] ? half_weight(E[idx]) : 0;
+    age[k] = valid[k] ? A[idx] : 0;
+  }
+  uint32_t picked = 0;  // bit k: local index lane*4+k chosen
+  const uint64_t key = stream_key(seed, step, view, (uint64_t)t);
+
+  // --- hard: sequential error-weighted draws without replacement
+  int n_hard_done = 0;
+  for (int j = 0; j < n_hard; ++j) {
+    uint64_t ls = 0;
+    for (int k = 0; k < 4; ++k) ls += ((picked >> k) & 1u) ? 0 : w[k];
+    const uint64_t incl = wave_inclusive_scan_u64(ls);
+    const uint64_t total = __shfl(incl, 63, kWave);
+    if (total == 0) break;
+    const uint64_t r = mulhi64(absorb(key, (uint64_t)j), total);
+    const uint64_t excl = incl - ls;
+    if (ls > 0 && excl <= r && r < incl) {
+      uint64_t run = excl;
+      for (int k = 0; k < 4; ++k) {
+        if ((picked >> k) & 1u) continue;
+        run += w[k];
+        if (run > r) {
+          picked |= 1u << k;
+          break;
+        }
+      }
+    }
+    ++n_hard_done;
+  }
+  n_mixed += n_hard - n_hard_done;
+
+  // --- stable: TopK age among the rest; key (age << 8) | (255 - loc) is
+  // unique and orders by age, then by lower index.  The K-th largest key is
+  // found by bisection on counts.
+  if (n_stable > 0) {
+    uint32_t kk[4];
+    bool elig[4];
+    for (int k = 0; k < 4; ++k) {
+      elig[k] = valid[k] && !((picked >> k) & 1u);
+      kk[k] = (age[k] << 8) | (uint32_t)(255 - (lane * 4 + k));
+    }
+    uint32_t lo = 0, hi = 1u << 24;  // count(key >= lo) >= n_stable > count(key >= hi)
+    while (hi - lo > 1) {
+      const uint32_t mid = lo + (hi - lo) / 2;
+      int c = 0;
+      for (int k = 0; k < 4; ++k) c += (elig[k] && kk[k] >= mid) ? 1 : 0;
+      c = wave_sum_i(c);
+      if (c >= n_stable) lo = mid; else hi = mid;
+    }
+    for (int k = 0; k < 4; ++k)
+      if (elig[k] && kk[k] >= lo) picked |= 1u << k;
+  }
+
+  // --- mixed: uniform without replacement over the rest, ascending order
+  for (int j = 0; j < n_mixed; ++j) {
+    int lc = 0;
+    for (int k = 0; k < 4; ++k) lc += (valid[k] && !((picked >> k) & 1u)) ? 1 : 0;
+    const int ic = wave_inclusive_scan_i(lc);
+    const int nrem = __shfl(ic, 63, kWave);
+    const int r = (int)mulhi64(absorb(key, (uint64_t)(256 + j)), (uint64_t)nrem);
+    const int ex = ic - lc;
+    if (lc > 0 && ex <= r && r < ic) {
+      int c = ex;
+      for (int k = 0; k < 4; ++k) {
+        if (!valid[k] || ((picked >> k) & 1u)) continue;
+        if (c == r) {
+          picked |= 1u << k;
+          break;
+        }
+        ++c;
+      }
+    }
+  }
+
+  // --- write the sorted local indices
+  const int lc = __builtin_popcount(picked);
+  const int ic = wave_inclusive_scan_i(lc);
+  int pos = tile_off[slot] + ic - lc;
+  for (int k = 0; k < 4; ++k)
+    if ((picked >> k) & 1u) pix[pos++] = (uint8_t)(lane * 4 + k);
+}
+
+}  // namespace tgs
+
+using namespace tgs;
+
+extern "C" size_t tgs_sample_workspace_size(int32_t height, int32_t width) {
+  if (height <= 0 || width <= 0) return 0;
+  const size_t n_t = (size_t)(ceil_div(width, kTile) * ceil_div(height, kTile));
+  return align_up(n_t * sizeof(uint64_t), 256) + align_up(n_t, 256);
+}
+
+extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
+                              const tgs_sample_params* sp, int32_t* valid_tiles, int32_t* tile_off,
+                              uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
+                              size_t ws_bytes, void* stream) {
+  TGS_REQUIRE(height > 0 && width > 0, "tgs_sample: bad image size %d x %d", width, height);
+  TGS_REQUIRE(sp != nullptr, "tgs_sample: null params");
+  TGS_REQUIRE(sp->n_pix >= 1 && sp->n_pix <= kTilePixels, "tgs_sample: n_pix %d not in 1..256",
+              sp->n_pix);
+  TGS_REQUIRE(sp->hard_permille >= 0 && sp->stable_permille >= 0 &&
+                  sp->hard_permille + sp->stable_permille <= 1000,
+              "tgs_sample: bad hard/stable ratios");
+  TGS_REQUIRE(sp->view >= 0, "tgs_sample: negative view index");
+  TGS_REQUIRE(E && A && valid_tiles && tile_off && pix && tile_slot && totals && ws,
+              "tgs_sample: null pointer");
+  TGS_REQUIRE(ws_bytes >= tgs_sample_workspace_size(height, width),
+              "tgs_sample: workspace %zu bytes < %zu", ws_bytes,
+              tgs_sample_workspace_size(height, width));
+  const int tiles_x = (int)ceil_div(width, kTile), tiles_y = (int)ceil_div(height, kTile);
+  const int n_t = tiles_x * tiles_y;
+  const int n_st = tgs_sample_tile_count(height, width, sp);
+  uint64_t* tw = (uint64_t*)ws;
+  uint8_t* chosen = (uint8_t*)ws + align_up((size_t)n_t * sizeof(uint64_t), 256);
+  hipStream_t s = as_stream(stream);
+  const bool all_tiles = sp->n_tiles_sel < 0 || sp->n_tiles_sel >= n_t;
+  if (!all_tiles)
+    hipLaunchKernelGGL(tile_weights_kernel, dim3(n_t), dim3(64), 0, s, E, height, width, tiles_x,
+                       n_t, tw);
+  hipLaunchKernelGGL(tile_select_kernel, dim3(1), dim3(kSelectThreads), 0, s, tw, height, width,
+                     tiles_x, n_t, sp->n_tiles_sel, sp->n_pix, sp->seed, sp->step,
+                     (uint64_t)sp->view, valid_tiles, tile_off, tile_slot, totals, chosen);
+  if (n_st > 0)
+    hipLaunchKernelGGL(tile_pixels_kernel, dim3(n_st), dim3(64), 0, s, E, A, height, width, tiles_x,
+                       n_st, sp->n_pix, sp->hard_permille, sp->stable_permille, sp->seed, sp->step,
+                       (uint64_t)sp->view, valid_tiles, tile_off, pix);
+  return hip_status("tgs_sample");
+}

@@ -1,0 +1,230 @@
+"""Host-side orchestration of one training step on the GPU (Alg. 1, steps 3-10
+for the selected views): buffers are allocated once per shape and every step
+of the path runs in the HIP library through the C ABI.
+
+A view's work, in order, on torch's current stream:
+  tgs_sample -> tgs_project -> tgs_bin_sort -> tgs_render_fwd -> tgs_loss
+  -> tgs_ema_age_update -> tgs_render_bwd -> tgs_project_bwd
+and once per step tgs_optimizer_step.  The sampler of every view runs first
+because the loss normalises by the step's total sample and tile counts.
+"""
+from __future__ import annotations
+
+import contextlib
+from dataclasses import dataclass, field
+
+import torch
+
+from . import binding as B
+
+TILE = B.TILE
+
+
+@dataclass
+class StepConfig:
+    """What one step samples and how it renders (dense when ``rate_permille`` is None)."""
+    rate_permille: int | None = 250
+    n_tiles_sel: int = -1
+    hard_permille: int = 400
+    stable_permille: int = 300
+    beta: float = 0.4
+    seed: int = 3
+    raster: dict = field(default_factory=dict)
+    loss: dict = field(default_factory=dict)
+    optim: dict = field(default_factory=dict)
+
+
+class ViewBuffers:
+    """Per-view device buffers for one image size and sampling rate."""
+
+    def __init__(self, n: int, width: int, height: int, n_pix: int | None, n_tiles_sel: int,
+                 device, capacity: int | None = None):
+        self.n, self.width, self.height = n, width, height
+        self.tiles_x, self.tiles_y = (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
+        self.n_t = self.tiles_x * self.tiles_y
+        self.dense = n_pix is None
+        self.n_pix = 256 if n_pix is None else n_pix
+        dev = device
+        self.splat = torch.empty((n, B.SPLAT_FLOATS), dtype=torch.float32, device=dev)
+        self.depth = torch.empty(n, dtype=torch.float32, device=dev)
+        self.radius = torch.empty(n, dtype=torch.int32, device=dev)
+        self.rect = torch.empty((n, 4), dtype=torch.int32, device=dev)
+        self.clamp = torch.empty(n, dtype=torch.uint8, device=dev)
+        if self.dense:
+            self.n_st = self.n_t
+            self.P_cap = width * height
+            self.valid_tiles = self.tile_off = self.pix = self.tile_slot = None
+        else:
+            sp = B.sample_params(self.n_pix, n_tiles_sel=n_tiles_sel)
+            self.n_st = B.tgs_sample_tile_count(height, width, sp)
+            self.P_cap = self.n_st * self.n_pix
+            self.valid_tiles = torch.empty(max(self.n_st, 1), dtype=torch.int32, device=dev)
+            self.tile_off = torch.empty(self.n_st + 1, dtype=torch.int32, device=dev)
+            self.pix = torch.empty(max(self.P_cap, 1), dtype=torch.uint8, device=dev)
+            self.tile_slot = torch.empty(self.n_t, dtype=torch.int32, device=dev)
+            self.sample_ws = torch.empty(B.tgs_sample_workspace_size(height, width), dtype=torch.uint8,
+                                         device=dev)
+        self.ranges = torch.empty((self.n_t, 2), dtype=torch.int32, device=dev)
+        self.out = torch.empty((max(self.P_cap, 1), 4), dtype=torch.float32, device=dev)
+        self.ncontrib = torch.empty(max(self.P_cap, 1), dtype=torch.int32, device=dev)
+        self.dL = torch.zeros((max(self.P_cap, 1), 4), dtype=torch.float32, device=dev)
+        self.err = torch.empty(max(self.P_cap, 1), dtype=torch.float32, device=dev)
+        self.lam = torch.empty(max(self.n_st, 1), dtype=torch.float32, device=dev)
+        self.tile_loss = torch.zeros((max(self.n_st, 1), 2), dtype=torch.float32, device=dev)
+        self.g2d = torch.empty((n, B.G2D_FLOATS), dtype=torch.float32, device=dev)
+        self.counters = torch.zeros(2, dtype=torch.int64, device=dev)
+        self._alloc_pairs(capacity if capacity is not None else max(1 << 16, 8 * n))
+
+    def _alloc_pairs(self, capacity: int):
+        dev = self.splat.device
+        self.capacity = int(capacity)
+        self.keys = torch.empty(self.capacity, dtype=torch.int64, device=dev)
+        self.vals = torch.empty(self.capacity, dtype=torch.int32, device=dev)
+        self.sort_ws = torch.empty(B.tgs_bin_sort_workspace_size(self.n, self.capacity, self.n_t),
+                                   dtype=torch.uint8, device=dev)
+
+    # ---- the steps of one view
+    def sample(self, E, A, cfg: StepConfig, step: int, view: int, totals):
+        sp = B.sample_params(self.n_pix, cfg.hard_permille, cfg.stable_permille, cfg.n_tiles_sel,
+                             cfg.seed, step, view)
+        B.tgs_sample(E, A, self.height, self.width, sp, self.valid_tiles, self.tile_off, self.pix,
+                     self.tile_slot, totals, self.sample_ws)
+
+    def project(self, params, cam: B.tgs_camera, rp):
+        B.tgs_project(params, self.n, cam, rp, self.splat, self.depth, self.radius, self.rect, self.clamp)
+
+    def bin_sort(self, touched=None) -> int:
+        while True:
+            try:
+                self.n_pairs = B.tgs_bin_sort(self.rect, self.depth, self.n, self.tile_slot, self.tiles_x,
+                                              self.tiles_y, self.keys, self.vals, self.capacity,
+                                              self.ranges, touched, self.sort_ws)
+                return self.n_pairs
+            except B.CapacityError as e:
+                self._alloc_pairs(int(e.required * 1.25) + 1024)
+
+    def render_fwd(self, rp, counters=None):
+        B.tgs_render_fwd(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
+                         self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
+                         rp, self.out, self.ncontrib, counters)
+
+    def loss(self, gt, totals, lp):
+        B.tgs_loss(self.out, gt, self.height, self.width, self.valid_tiles, self.tile_off, self.pix,
+                   self.n_st, totals, lp, self.dL, self.err, self.lam, self.tile_loss)
+
+    def ema_age(self, E, A, beta):
+        B.tgs_ema_age_update(E, A, self.height, self.width, self.tile_slot, self.tile_off, self.pix,
+                             self.err, beta)
+
+    def render_bwd(self, rp):
+        self.g2d.zero_()
+        B.tgs_render_bwd(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
+                         self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
+                         rp, self.out, self.ncontrib, self.dL, self.g2d)
+
+    def project_bwd(self, params, cam: B.tgs_camera, rp, grad):
+        B.tgs_project_bwd(params, self.n, cam, rp, self.radius, self.clamp, self.g2d, grad)
+
+
+class Trainer:
+    """Gaussians, optimizer state and per-view buffers for sparse (or dense)
+    training steps over a fixed set of cameras."""
+
+    def __init__(self, params: torch.Tensor, cams, gts, cfg: StepConfig, E=None, A=None):
+        self.dev = params.device
+        self.params = params.contiguous()
+        self.n = params.shape[1]
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.touched = torch.zeros(self.n, dtype=torch.uint8, device=self.dev)
+        self.cams = [B.camera(c) for c in cams]
+        self.gts = gts
+        self.cfg = cfg
+        self.rp = B.raster_params(**cfg.raster)
+        self.lp = B.loss_params(**cfg.loss)
+        self.op = B.optim_params(**cfg.optim)
+        self.E, self.A = E, A
+        self.totals = torch.zeros(2, dtype=torch.int64, device=self.dev)
+        self.step_count = 0
+        self._bufs: dict = {}
+        self.counters = torch.zeros(2, dtype=torch.int64, device=self.dev)
+        self.events: dict | None = None   # stage name -> [(start, end)] when timing
+
+    @contextlib.contextmanager
+    def _stage(self, name):
+        """Brackets a stage with HIP events on the current stream when timing."""
+        if self.events is None:
+            yield
+            return
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        yield
+        b.record()
+        self.events.setdefault(name, []).append((a, b))
+
+    def stage_ms(self) -> dict:
+        """Total milliseconds per stage over the recorded events (synchronises)."""
+        torch.cuda.synchronize()
+        return {k: sum(a.elapsed_time(b) for a, b in v) for k, v in (self.events or {}).items()}
+
+    def buffers(self, key, cam) -> ViewBuffers:
+        if key not in self._bufs:
+            n_pix = None if self.cfg.rate_permille is None else B.tgs_pixels_per_tile(self.cfg.rate_permille)
+            self._bufs[key] = ViewBuffers(self.n, cam.width, cam.height, n_pix, self.cfg.n_tiles_sel, self.dev)
+        return self._bufs[key]
+
+    def init_error_maps(self, views):
+        """Dense L1 error of the current model per view (Sec. 3.3 initialisation)."""
+        for v in views:
+            cam = self.cams[v]
+            vb = ViewBuffers(self.n, cam.width, cam.height, None, -1, self.dev)
+            vb.project(self.params, cam, self.rp)
+            vb.bin_sort()
+            vb.render_fwd(self.rp)
+            B.tgs_error_init(vb.out, self.gts[v], cam.height, cam.width, self.E[v])
+
+    def step(self, views) -> list:
+        """One training step over ``views``; returns the per-view buffers."""
+        self.step_count += 1
+        t = self.step_count
+        views = list(views)
+        self.totals.zero_()
+        self.grad.zero_()
+        self.touched.zero_()
+        used = []
+        st = self._stage
+        for slot, v in enumerate(views):
+            cam = self.cams[v]
+            vb = self.buffers(slot, cam)
+            if vb.dense:
+                self.totals[0] += cam.width * cam.height
+                self.totals[1] += vb.n_t
+            else:
+                with st("sample"):
+                    vb.sample(self.E[v], self.A[v], self.cfg, t, v, self.totals)
+            used.append(vb)
+        for vb, v in zip(used, views):
+            cam = self.cams[v]
+            with st("project"):
+                vb.project(self.params, cam, self.rp)
+            with st("bin_sort"):
+                vb.bin_sort(self.touched)
+            with st("render_fwd"):
+                vb.render_fwd(self.rp, self.counters)
+            with st("loss"):
+                vb.loss(self.gts[v], self.totals, self.lp)
+            if not vb.dense:
+                with st("ema_age"):
+                    vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
+            with st("render_bwd"):
+                vb.render_bwd(self.rp)
+            with st("project_bwd"):
+                vb.project_bwd(self.params, cam, self.rp, self.grad)
+        with st("optimizer"):
+            B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
+        return used
+
+    def loss_value(self, used) -> float:
+        return float(sum(vb.tile_loss[: vb.n_st].sum() for vb in used))

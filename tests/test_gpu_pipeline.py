@@ -1,0 +1,229 @@
+"""GPU parity of whole steps: the training step of the tiny workload against
+the oracle's step, the autograd wrapper against the oracle gradient and FP64
+finite differences, and the rasterizer-scaling workload at full size in the
+benchmark's launch configuration (checked on sampled tiles/Gaussians)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import binning, maps, optim, pipeline, project, project_bwd, render, sampler
+from oracle.params import LossParams, OptimParams, RasterParams, SampleParams
+
+from support import assert_close, scene_c1, scene_scaling, small_scene, splat_as_oracle, splat_record
+
+pytestmark = pytest.mark.gpu
+
+RP = RasterParams()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_15924_amd import binding
+    binding.lib()
+    return binding
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_norm(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ------------------------------------------------------------------ tiny workload, one step
+@pytest.fixture(scope="module")
+def c1_inputs():
+    p, cams = scene_c1()
+    target = synth.perturb(p)
+    gts, E = [], []
+    for i, cam in enumerate(cams):
+        pr = project.project(target, cam, RP)
+        _, sv, rg = binning.bin_and_sort(pr)
+        xs, ys = render.dense_pixels(cam.width, cam.height)
+        img = render.render_pixels(pr, sv, rg, xs, ys, RP)["rgb"].reshape(cam.height, cam.width, 3)
+        gt = (np.moveaxis(img, -1, 0) + synth.pixel_noise((3, cam.height, cam.width), 2 + i)).astype(np.float32)
+        gts.append(gt)
+        pr0 = project.project(p, cam, RP)
+        _, sv0, rg0 = binning.bin_and_sort(pr0)
+        img0 = render.render_pixels(pr0, sv0, rg0, xs, ys, RP)["rgb"].reshape(cam.height, cam.width, 3)
+        E.append(maps.dense_error_init(img0.astype(np.float32), gt))
+    A = [np.zeros((c.height, c.width), dtype=np.uint16) for c in cams]
+    return p, cams, gts, E, A
+
+
+def test_c1_training_step_matches_oracle(B, c1_inputs):
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    p, cams, gts, E, A = c1_inputs
+    sp = SampleParams(n_pix=64, n_tiles_sel=64)
+    ref = pipeline.train_step(p, np.zeros_like(p, np.float64), np.zeros_like(p, np.float64), cams, gts, E, A,
+                              1, sp, RP, LossParams(), OptimParams(), seed=3)
+    cfg = StepConfig(rate_permille=250, n_tiles_sel=64, seed=3)
+    Eg = [dev(e.view(np.int16)) for e in E]
+    Ag = [dev(a.view(np.int16)) for a in A]
+    tr = Trainer(dev(p), cams, [dev(g) for g in gts], cfg, E=Eg, A=Ag)
+    used = tr.step([0, 1, 2, 3])
+    torch.cuda.synchronize()
+    for v, vb in enumerate(used):
+        rv = ref["views"][v]
+        s = rv["samples"]
+        P = int(s["tile_off"][-1])
+        assert np.array_equal(host(vb.valid_tiles), s["valid_tiles"])
+        assert np.array_equal(host(vb.pix)[:P], s["pix"])
+        o = host(vb.out)[:P]
+        flag = rv["fwd"]["out"]["flag"]
+        ok = ~flag
+        assert ok.mean() > 0.995
+        assert_close(o[ok, :3], rv["fwd"]["out"]["rgb"][ok], 1e-5, 1e-6, f"view {v} rgb")
+        assert np.array_equal(host(vb.ncontrib)[:P][ok], rv["fwd"]["out"]["n_contrib"][ok])
+        assert np.array_equal(host(Ag[v]).view(np.uint16), ref["A"][v])
+        # E: the blend input e differs in the last bits (FP32 render), so a
+        # half may round to a neighbour
+        e_gpu = host(Eg[v]).view(np.float16).astype(np.float64)
+        e_ref = ref["E"][v].view(np.float16).astype(np.float64)
+        assert np.all(np.abs(e_gpu - e_ref) <= np.abs(np.spacing(e_ref.astype(np.float16))).astype(np.float64))
+    loss_gpu = tr.loss_value(used)
+    assert abs(loss_gpu - ref["loss"]) <= 1e-4 * abs(ref["loss"])
+    assert np.array_equal(host(tr.touched).astype(bool), ref["touched"])
+    g = host(tr.grad)
+    for name, sl in {"mean": slice(0, 3), "scale": slice(3, 6), "quat": slice(6, 10),
+                     "opacity": slice(10, 11), "sh": slice(11, 59)}.items():
+        assert rel_norm(g[sl], ref["grad"][sl]) < 2e-3, name
+    dp_gpu = host(tr.params).astype(np.float64) - p
+    dp_ref = ref["params"] - p
+    assert rel_norm(dp_gpu, dp_ref) < 2e-3
+
+
+# ------------------------------------------------------------------ autograd
+def test_autograd_matches_oracle_gradient_and_finite_differences(B):
+    from paper_2606_15924_amd.autograd import Samples, rasterize
+    p, cam = small_scene(n=300, seed=33, W=64, H=48)
+    p[10] = np.clip(p[10], -3.0, 1.5)           # keep alpha well below the 0.99 clamp
+    E = synth.error_map(cam.height, cam.width, 71)
+    A = synth.age_map(cam.height, cam.width, 72)
+    s = sampler.sample_view(E, A, SampleParams(n_pix=128), 3, 1, 0)
+    xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
+    w = np.random.default_rng(8).normal(size=(xs.size, 3))
+    samples = Samples(dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"]), s["valid_tiles"].size, 128)
+    P = dev(p).requires_grad_(True)
+    rgb = rasterize(P, cam, samples)
+    (rgb * dev(w.astype(np.float32))).sum().backward()
+    g_gpu = host(P.grad).astype(np.float64)
+    # oracle gradient of the same functional
+    pr = project.project(p, cam, RP)
+    _, sv, rg = binning.bin_and_sort(pr, s["valid_tiles"])
+    out = render.render_pixels(pr, sv, rg, xs, ys, RP)
+    assert_close(host(rgb.detach())[~out["flag"]], out["rgb"][~out["flag"]], 1e-5, 1e-6, "rgb")
+    g2d = render.render_pixels_bwd(pr, sv, rg, xs, ys, w, RP)
+    g_ref = project_bwd.project_bwd(p, cam, pr, g2d, RP)
+    groups = {"mean": slice(0, 3), "scale": slice(3, 6), "quat": slice(6, 10), "opacity": slice(10, 11),
+              "sh": slice(11, 59)}
+    for name, sl in groups.items():
+        assert rel_norm(g_gpu[sl], g_ref[sl]) < 1e-4, name
+    # FP64 central differences of the oracle forward along random directions
+    rng = np.random.default_rng(9)
+    p64 = p.astype(np.float64)
+    for name, sl in groups.items():
+        u = np.zeros_like(p64)
+        u[sl] = rng.normal(size=u[sl].shape)
+        h = 1e-6
+        vals = []
+        for sgn in (1, -1):
+            q = p64 + sgn * h * u
+            prq = project.project(q, cam, RP)
+            _, svq, rgq = binning.bin_and_sort(prq, s["valid_tiles"])
+            vals.append((w * render.render_pixels(prq, svq, rgq, xs, ys, RP)["rgb"]).sum())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = float((g_gpu * u).sum())
+        assert abs(fd - an) <= 1e-3 * max(abs(fd), 1e-3), (name, fd, an)
+
+
+# ------------------------------------------------------------------ full-size workload
+@pytest.fixture(scope="module")
+def scaling(B):
+    from paper_2606_15924_amd.pipeline import ViewBuffers
+    p, cam = scene_scaling()
+    n = p.shape[1]
+    E = synth.error_map(cam.height, cam.width, 81)
+    A = synth.age_map(cam.height, cam.width, 82)
+    vb = ViewBuffers(n, cam.width, cam.height, 64, -1, torch.device("cuda"))
+    totals = torch.zeros(2, dtype=torch.int64, device="cuda")
+    from paper_2606_15924_amd.pipeline import StepConfig
+    vb.sample(dev(E.view(np.int16)), dev(A.view(np.int16)), StepConfig(rate_permille=250), 1, 0, totals)
+    c = B.camera(cam)
+    vb.project(dev(p), c, B.raster_params())
+    vb.bin_sort()
+    vb.render_fwd(B.raster_params())
+    torch.cuda.synchronize()
+    pr = project.project(p, cam, RP)
+    return dict(p=p, cam=cam, E=E, A=A, vb=vb, pr=pr)
+
+
+def test_scaling_projection_and_sort_bit_exact(B, scaling):
+    vb, pr = scaling["vb"], scaling["pr"]
+    vis = pr["visible"]
+    assert np.array_equal(host(vb.depth).view(np.uint32), pr["depth32"].view(np.uint32))
+    safe = vis & (pr["radius_margin"] > 1e-9)
+    assert np.array_equal(host(vb.rect)[safe], pr["rect"].T[safe])
+    # the GPU sort of every pair against the library sort of the oracle's pairs
+    sk, sv, rg = binning.bin_and_sort(pr)
+    assert vb.n_pairs == sk.size
+    assert np.array_equal(host(vb.keys)[: sk.size].view(np.uint64), sk)
+    assert np.array_equal(host(vb.vals)[: sk.size].view(np.uint32), sv)
+    assert np.array_equal(host(vb.ranges).astype(np.int64), rg)
+
+
+def test_scaling_forward_and_backward_on_sampled_tiles(B, scaling):
+    vb, pr, cam = scaling["vb"], scaling["pr"], scaling["cam"]
+    q = splat_as_oracle(pr, splat_record(pr))    # the oracle's own splats, rounded as stored
+    TX = pr["TX"]
+    rng = np.random.default_rng(5)
+    tiles = np.sort(rng.choice(TX * pr["TY"], 24, replace=False))
+    s = sampler.sample_view(scaling["E"], scaling["A"], SampleParams(n_pix=64), 3, 1, 0, tiles_subset=tiles)
+    xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
+    sk, sv, rg = binning.bin_and_sort(pr)
+    ref = render.render_pixels(q, sv, rg, xs, ys, RP)
+    off = host(vb.tile_off)
+    idx = np.concatenate([np.arange(off[t], off[t + 1]) for t in tiles])   # slot == tile id here
+    assert np.array_equal(host(vb.pix)[idx], s["pix"])
+    o = host(vb.out)[idx]
+    ok = ~ref["flag"]
+    assert_close(o[ok, :3], ref["rgb"][ok], 1e-5, 1e-7, "rgb")
+    assert np.array_equal(host(vb.ncontrib)[idx][ok], ref["n_contrib"][ok])
+    # backward: dL/dI non-zero only on the sampled tiles
+    g = rng.normal(size=(xs.size, 3)) * 1e-3
+    g[ref["flag"]] = 0.0
+    dl = torch.zeros_like(vb.dL)
+    dl_h = np.zeros((idx.size, 4), dtype=np.float32)
+    dl_h[:, :3] = g
+    dl[torch.from_numpy(idx).cuda()] = dev(dl_h)
+    vb.dL = dl
+    vb.render_bwd(B.raster_params())
+    got = host(vb.g2d).T
+    g2d, g2d_abs = render.render_pixels_bwd(q, sv, rg, xs, ys, g, RP, with_abs=True)
+    for f in range(9):
+        assert_close(got[f], g2d[f], 1e-4, 2e-6 * g2d_abs[f] + 1e-12, f"g2d field {f}")
+
+
+def test_scaling_optimizer_on_sampled_gaussians(B, scaling):
+    p = scaling["p"]
+    n = p.shape[1]
+    rng = np.random.default_rng(6)
+    g = (rng.normal(size=p.shape) * 1e-3).astype(np.float32)
+    touched = (rng.uniform(size=n) < 0.5).astype(np.uint8)
+    P, M, V = dev(p.copy()), torch.zeros((59, n), device="cuda"), torch.zeros((59, n), device="cuda")
+    B.tgs_optimizer_step(P, dev(g), M, V, n, dev(touched), B.optim_params(), 1)
+    pick = rng.choice(n, 2000, replace=False)
+    rp_, rm, rv = optim.optimizer_step(p[:, pick], g[:, pick], np.zeros((59, 2000)), np.zeros((59, 2000)),
+                                       touched[pick], OptimParams(), 1)
+    gp = host(P)[:, pick]
+    b32 = rp_.astype(np.float32)
+    assert (np.abs(gp.astype(np.float64) - b32) <= np.abs(np.spacing(b32))).all()

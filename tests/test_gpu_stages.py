@@ -1,0 +1,453 @@
+"""GPU parity of each stage against the oracle, stage by stage, on identical
+seeded inputs (each GPU stage gets its inputs from synth or the oracle).
+
+Bars: bit-exact for keys, values, ranges, sample indices, tile maps, age
+maps and half error maps; FP32 values against the FP64 oracle within the
+stated relative tolerances (images 1e-5, gradients 1e-4, plus an FP32
+summation bound where terms cancel); pixels whose discrete decisions lie in
+the oracle's guard band are excluded and counted."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import binning, loss, maps, optim, project, project_bwd, render, sampler
+from oracle.params import LossParams, OptimParams, RasterParams, SampleParams
+
+from support import (assert_close, scene_c1, small_scene, splat_as_oracle, splat_record)
+
+pytestmark = pytest.mark.gpu
+
+RP = RasterParams()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_15924_amd import binding
+    binding.lib()
+    return binding
+
+
+def dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ------------------------------------------------------------------ projection
+@pytest.mark.parametrize("case", ["c1", "ragged", "deg0"])
+def test_project_parity(B, case):
+    if case == "c1":
+        p, cams = scene_c1()
+        cam = cams[2]
+        rp = RP
+    else:
+        p, cam = small_scene(n=3000, seed=5)
+        rp = RasterParams(sh_degree=0) if case == "deg0" else RP
+    pr = project.project(p, cam, rp)
+    n = p.shape[1]
+    P = dev(p)
+    splat = torch.empty((n, 12), dtype=torch.float32, device="cuda")
+    depth = torch.empty(n, dtype=torch.float32, device="cuda")
+    radius = torch.empty(n, dtype=torch.int32, device="cuda")
+    rect = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    clamp = torch.empty(n, dtype=torch.uint8, device="cuda")
+    brp = B.raster_params(sh_degree=rp.sh_degree)
+    B.tgs_project(P, n, B.camera(cam), brp, splat, depth, radius, rect, clamp)
+    s, d, r, rc, cm = host(splat), host(depth), host(radius), host(rect), host(clamp)
+    # depth key bits: exact for every Gaussian
+    assert np.array_equal(d.view(np.uint32), pr["depth32"].view(np.uint32))
+    vis = pr["visible"]
+    safe = vis & (pr["radius_margin"] > 1e-9)
+    assert safe.sum() >= vis.sum() - 2
+    assert np.array_equal(r[safe], pr["radius"][safe])
+    assert np.array_equal(rc[safe], pr["rect"].T[safe])
+    assert np.array_equal(r[~vis], np.zeros((~vis).sum()))
+    rec = splat_record(pr)
+    assert np.array_equal(s[vis][:, :2], rec[vis][:, :2])               # integer parts of the centre
+    px = s[:, 0].astype(np.float64) + s[:, 2]
+    py = s[:, 1].astype(np.float64) + s[:, 3]
+    assert_close(px[vis], pr["mean2d"][0][vis], 0, 2e-7 * 2 ** 0, "centre x")
+    assert_close(py[vis], pr["mean2d"][1][vis], 0, 2e-7, "centre y")
+    assert_close(s[vis][:, 4:7], pr["conic"].T[vis], 2e-7, 0, "conic")
+    assert_close(s[vis][:, 7], pr["opacity"][vis], 2e-7, 0, "opacity")
+    assert_close(s[vis][:, 8:11], pr["rgb"].T[vis], 2e-7, 1e-12, "rgb")
+    clamp_bits = (pr["clamp"][0] * 1 + pr["clamp"][1] * 2 + pr["clamp"][2] * 4).astype(np.uint8)
+    assert np.array_equal(cm[vis], clamp_bits[vis])
+
+
+# ------------------------------------------------------------------ binning + sort
+@pytest.mark.parametrize("case", ["c1_all", "c1_sampled", "ragged"])
+def test_bin_sort_bit_exact(B, case):
+    if case.startswith("c1"):
+        p, cams = scene_c1()
+        cam = cams[0]
+    else:
+        p, cam = small_scene(n=3000, seed=6)
+    pr = project.project(p, cam, RP)
+    TX, TY = pr["TX"], pr["TY"]
+    n = p.shape[1]
+    valid = None
+    tile_slot = None
+    if case == "c1_sampled":
+        valid = np.sort(np.random.default_rng(1).choice(TX * TY, 64, replace=False))
+        ts = -np.ones(TX * TY, dtype=np.int32)
+        ts[valid] = np.arange(valid.size)
+        tile_slot = dev(ts)
+    keys, vals = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY, valid)
+    sk, sv = binning.sort_pairs(keys, vals)
+    ranges = binning.tile_ranges(sk, TX * TY)
+    rect = dev(pr["rect"].T.astype(np.int32))
+    depth = dev(pr["depth32"])
+    cap = int(sk.size) + 17
+    K = torch.empty(cap, dtype=torch.int64, device="cuda")
+    V = torch.empty(cap, dtype=torch.int32, device="cuda")
+    R = torch.empty((TX * TY, 2), dtype=torch.int32, device="cuda")
+    touched = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(B.tgs_bin_sort_workspace_size(n, cap, TX * TY), dtype=torch.uint8, device="cuda")
+    npairs = B.tgs_bin_sort(rect, depth, n, tile_slot, TX, TY, K, V, cap, R, touched, ws)
+    assert npairs == sk.size
+    assert np.array_equal(host(K)[:npairs].view(np.uint64), sk)
+    assert np.array_equal(host(V)[:npairs].view(np.uint32), sv)
+    assert np.array_equal(host(R).astype(np.int64), ranges)
+    t_ref = np.zeros(n, dtype=np.uint8)
+    t_ref[np.unique(sv)] = 1
+    assert np.array_equal(host(touched), t_ref)
+    # too-small capacity reports the required count
+    with pytest.raises(B.CapacityError) as ei:
+        B.tgs_bin_sort(rect, depth, n, tile_slot, TX, TY, K, V, 10, R, None, ws)
+    assert ei.value.required == sk.size
+
+
+# ------------------------------------------------------------------ sampler
+@pytest.mark.parametrize("W,H,n_pix,n_sel,zero", [(256, 256, 64, 64, 0.1), (150, 107, 25, -1, 0.3),
+                                                   (150, 107, 256, -1, 0.0), (96, 80, 51, 7, 1.0),
+                                                   (1296, 840, 64, -1, 0.1)])
+def test_sampler_bit_exact(B, W, H, n_pix, n_sel, zero):
+    E = synth.error_map(H, W, 31, zero_frac=zero)
+    A = synth.age_map(H, W, 32)
+    seed, step, view = 3, 5, 2
+    sp = SampleParams(n_pix=n_pix, n_tiles_sel=n_sel)
+    bsp = B.sample_params(n_pix, n_tiles_sel=n_sel, seed=seed, step=step, view=view)
+    n_st = B.tgs_sample_tile_count(H, W, bsp)
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    vt = torch.empty(n_st, dtype=torch.int32, device="cuda")
+    off = torch.empty(n_st + 1, dtype=torch.int32, device="cuda")
+    pix = torch.empty(n_st * n_pix, dtype=torch.uint8, device="cuda")
+    slot = torch.empty(TX * TY, dtype=torch.int32, device="cuda")
+    totals = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ws = torch.empty(B.tgs_sample_workspace_size(H, W), dtype=torch.uint8, device="cuda")
+    B.tgs_sample(dev(E), dev(A), H, W, bsp, vt, off, pix, slot, totals, ws)
+    g_vt, g_off, g_pix, g_slot, g_tot = host(vt), host(off), host(pix), host(slot), host(totals)
+    subset = None
+    if W * H > 200000:   # full-size view: the oracle checks a subset of tiles
+        rng = np.random.default_rng(0)
+        subset = np.unique(np.concatenate([rng.choice(TX * TY, 120, replace=False),
+                                           np.arange(TX * TY - TX, TX * TY), np.arange(TX - 1, TX * TY, TX)]))
+    ref = sampler.sample_view(E, A, sp, seed, step, view, tiles_subset=subset)
+    if subset is None:
+        assert np.array_equal(g_vt, ref["valid_tiles"])
+        assert np.array_equal(g_off, ref["tile_off"])
+        assert np.array_equal(g_pix[: g_off[-1]], ref["pix"])
+        ts = -np.ones(TX * TY, dtype=np.int32)
+        ts[ref["valid_tiles"]] = np.arange(ref["valid_tiles"].size)
+        assert np.array_equal(g_slot, ts)
+        assert g_tot.tolist() == [int(ref["tile_off"][-1]), n_st]
+    else:
+        assert np.array_equal(g_vt, np.arange(TX * TY))
+        for i, t in enumerate(ref["valid_tiles"]):
+            got = g_pix[g_off[t]:g_off[t + 1]]
+            want = ref["pix"][ref["tile_off"][i]:ref["tile_off"][i + 1]]
+            assert np.array_equal(got, want), t
+
+
+# ------------------------------------------------------------------ forward render
+def _render_case(case):
+    if case == "c1_sparse":
+        p, cams = scene_c1()
+        cam = cams[1]
+        E = synth.error_map(cam.height, cam.width, 41)
+        A = synth.age_map(cam.height, cam.width, 42)
+        s = sampler.sample_view(E, A, SampleParams(n_pix=64, n_tiles_sel=64), 3, 1, 1)
+    elif case == "ragged_sparse25":
+        p, cam = small_scene(n=2500, seed=7)
+        E = synth.error_map(cam.height, cam.width, 43)
+        A = synth.age_map(cam.height, cam.width, 44)
+        s = sampler.sample_view(E, A, SampleParams(n_pix=25), 3, 1, 0)
+    elif case == "ragged_sparse128":
+        p, cam = small_scene(n=2500, seed=8)
+        E = synth.error_map(cam.height, cam.width, 45)
+        A = synth.age_map(cam.height, cam.width, 46)
+        s = sampler.sample_view(E, A, SampleParams(n_pix=128), 3, 1, 0)
+    else:
+        p, cam = small_scene(n=2500, seed=9)
+        s = None
+    return p, cam, s
+
+
+def _gpu_render(B, rec, sv, ranges, cam, s, rp, n_pix):
+    TX, TY = (cam.width + 15) // 16, (cam.height + 15) // 16
+    splat = dev(rec)
+    V = dev(sv.view(np.int32))
+    R = dev(ranges.astype(np.int32))
+    if s is None:
+        P = cam.width * cam.height
+        vt = off = pix = None
+        n_st, mpt = TX * TY, 256
+    else:
+        P = int(s["tile_off"][-1])
+        vt, off, pix = dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"])
+        n_st, mpt = s["valid_tiles"].size, n_pix
+    out = torch.empty((max(P, 1), 4), dtype=torch.float32, device="cuda")
+    nc = torch.empty(max(P, 1), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    B.tgs_render_fwd(splat, V, R, TX, TY, cam.width, cam.height, vt, off, pix, n_st, mpt, rp, out, nc, cnt)
+    return out, nc, cnt, (splat, V, R, vt, off, pix, n_st, mpt, TX, TY)
+
+
+@pytest.mark.parametrize("case,bg", [("c1_sparse", (0, 0, 0)), ("ragged_sparse25", (0, 0, 0)),
+                                     ("ragged_sparse128", (0.3, 0.6, 0.9)), ("dense", (0, 0, 0))])
+def test_render_fwd_parity(B, case, bg):
+    p, cam, s = _render_case(case)
+    rp = RasterParams(bg=bg)
+    pr = project.project(p, cam, rp)
+    rec = splat_record(pr)
+    q = splat_as_oracle(pr, rec)
+    valid = None if s is None else s["valid_tiles"]
+    _, sv, ranges = binning.bin_and_sort(pr, valid)
+    if s is None:
+        xs, ys = render.dense_pixels(cam.width, cam.height)
+    else:
+        xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
+    ref = render.render_pixels(q, sv, ranges, xs, ys, rp)
+    n_pix = 256 if s is None else max(int(np.diff(s["tile_off"]).max()), 1)
+    out, nc, cnt, _ = _gpu_render(B, rec, sv, ranges, cam, s, B.raster_params(bg=bg), n_pix)
+    o, c, k = host(out)[: xs.size], host(nc)[: xs.size], host(cnt)
+    ok = ~ref["flag"]
+    assert ok.mean() > 0.995, ok.mean()
+    assert_close(o[ok, :3], ref["rgb"][ok], 1e-5, 1e-7, "rgb")
+    assert_close(o[ok, 3], ref["T"][ok], 1e-5, 1e-7, "T_final")
+    assert np.array_equal(c[ok], ref["n_contrib"][ok])
+    # counters: exact when no pixel sits in the guard band
+    if ok.all():
+        assert k.tolist() == [int(ref["n_eval"].sum()), int(ref["n_blend"].sum())]
+    else:
+        assert abs(int(k[1]) - int(ref["n_blend"].sum())) <= 64 * (~ok).sum()
+
+
+def test_sparse_full_rate_equals_dense_bitwise(B):
+    p, cam = small_scene(n=2500, seed=10)
+    pr = project.project(p, cam, RP)
+    rec = splat_record(pr)
+    _, sv, ranges = binning.bin_and_sort(pr)
+    TX, TY = pr["TX"], pr["TY"]
+    E = synth.error_map(cam.height, cam.width, 47)
+    A = synth.age_map(cam.height, cam.width, 48)
+    s = sampler.sample_view(E, A, SampleParams(n_pix=256), 3, 1, 0)
+    out_s, nc_s, _, _ = _gpu_render(B, rec, sv, ranges, cam, s, B.raster_params(), 256)
+    out_d, nc_d, _, _ = _gpu_render(B, rec, sv, ranges, cam, None, B.raster_params(), 256)
+    xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
+    od = host(out_d)[ys * cam.width + xs]
+    assert np.array_equal(host(out_s)[: xs.size].view(np.uint32), od.view(np.uint32))
+    assert np.array_equal(host(nc_s)[: xs.size], host(nc_d)[ys * cam.width + xs])
+
+
+# ------------------------------------------------------------------ backward render
+@pytest.mark.parametrize("case", ["c1_sparse", "ragged_sparse25", "ragged_sparse128", "dense"])
+def test_render_bwd_parity(B, case):
+    p, cam, s = _render_case(case)
+    rp = RasterParams(bg=(0.2, 0.1, 0.4))
+    pr = project.project(p, cam, rp)
+    rec = splat_record(pr)
+    q = splat_as_oracle(pr, rec)
+    valid = None if s is None else s["valid_tiles"]
+    _, sv, ranges = binning.bin_and_sort(pr, valid)
+    if s is None:
+        xs, ys = render.dense_pixels(cam.width, cam.height)
+    else:
+        xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
+    ref = render.render_pixels(q, sv, ranges, xs, ys, rp)
+    g = np.random.default_rng(3).normal(size=(xs.size, 3)) * 1e-3
+    g[ref["flag"]] = 0.0                     # guard-band pixels carry no gradient
+    g2d, g2d_abs = render.render_pixels_bwd(q, sv, ranges, xs, ys, g, rp, with_abs=True)
+    n_pix = 256 if s is None else max(int(np.diff(s["tile_off"]).max()), 1)
+    brp = B.raster_params(bg=rp.bg)
+    # forward outputs from the oracle (FP32), ncontrib exact
+    out = np.zeros((xs.size, 4), dtype=np.float32)
+    out[:, :3] = ref["rgb"]
+    out[:, 3] = ref["T"]
+    dl = np.zeros((xs.size, 4), dtype=np.float32)
+    dl[:, :3] = g
+    if s is None:
+        o_full = np.zeros((cam.width * cam.height, 4), dtype=np.float32)
+        d_full = np.zeros_like(o_full)
+        nc_full = np.zeros(cam.width * cam.height, dtype=np.int32)
+        idx = ys * cam.width + xs
+        o_full[idx], d_full[idx], nc_full[idx] = out, dl, ref["n_contrib"]
+        out, dl, ncv = o_full, d_full, nc_full
+    else:
+        ncv = ref["n_contrib"].astype(np.int32)
+    TX, TY = pr["TX"], pr["TY"]
+    G = torch.zeros((p.shape[1], 9), dtype=torch.float32, device="cuda")
+    vt = off = pix = None
+    n_st = TX * TY
+    if s is not None:
+        vt, off, pix = dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"])
+        n_st = s["valid_tiles"].size
+    B.tgs_render_bwd(dev(rec), dev(sv.view(np.int32)), dev(ranges.astype(np.int32)), TX, TY, cam.width,
+                     cam.height, vt, off, pix, n_st, n_pix, brp, dev(out), dev(ncv), dev(dl), G)
+    got = host(G).T
+    names = ["dx", "dy", "ca", "cb", "cc", "opacity", "r", "g", "b"]
+    for f in range(9):
+        # 1e-4 relative, plus 16 FP32 ulps of the error scale of each sum (see
+        # render_pixels_bwd: B_k = I - C_{<=k} cancels in a front-to-back replay)
+        assert_close(got[f], g2d[f], 1e-4, 2e-6 * g2d_abs[f] + 1e-12, names[f])
+
+
+# ------------------------------------------------------------------ loss, maps
+@pytest.mark.parametrize("case", ["c1", "ragged25", "dense"])
+def test_loss_parity(B, case):
+    rng = np.random.default_rng(4)
+    if case == "dense":
+        W, H = 70, 45
+        TX, TY = 5, 3
+        x = rng.uniform(size=(W * H, 3)).astype(np.float32)
+        gt = synth.image(H, W, 50)
+        xs, ys = render.dense_pixels(W, H)
+        tiles = (ys // 16) * TX + xs // 16
+        order = np.argsort(tiles, kind="stable")
+        off = np.concatenate([[0], np.cumsum(np.bincount(tiles, minlength=TX * TY))])
+        P_step, T_step = W * H + 100, TX * TY + 3
+        ref = loss.sparse_loss(x[order], gt[:, ys[order], xs[order]].T, off, P_step, T_step)
+        dL_ref = np.zeros((W * H, 3))
+        dL_ref[order] = ref["dL"]
+        err_ref = np.zeros(W * H)
+        err_ref[order] = ref["err"]
+        out = np.zeros((W * H, 4), dtype=np.float32)
+        out[:, :3] = x
+        vt = offt = pix = None
+        n_st = TX * TY
+        lam_ref = ref["lam"]
+    else:
+        W, H, n_pix, n_sel = (256, 256, 64, 64) if case == "c1" else (150, 107, 25, -1)
+        E = synth.error_map(H, W, 51)
+        A = synth.age_map(H, W, 52)
+        s = sampler.sample_view(E, A, SampleParams(n_pix=n_pix, n_tiles_sel=n_sel), 3, 1, 0)
+        xs, ys, _ = sampler.sample_coords(s, W, H)
+        gt = synth.image(H, W, 53)
+        x = np.clip(gt[:, ys, xs].T + rng.normal(0, 0.05, size=(xs.size, 3)), 0, 1).astype(np.float32)
+        P_step, T_step = xs.size * 3, s["valid_tiles"].size * 3
+        ref = loss.sparse_loss(x, gt[:, ys, xs].T, s["tile_off"], P_step, T_step)
+        dL_ref, err_ref, lam_ref = ref["dL"], ref["err"], ref["lam"]
+        out = np.zeros((xs.size, 4), dtype=np.float32)
+        out[:, :3] = x
+        vt, offt, pix = dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"])
+        n_st = s["valid_tiles"].size
+    Pn = out.shape[0]
+    dL = torch.empty((Pn, 4), dtype=torch.float32, device="cuda")
+    err = torch.empty(Pn, dtype=torch.float32, device="cuda")
+    lam = torch.empty(n_st, dtype=torch.float32, device="cuda")
+    tl = torch.empty((n_st, 2), dtype=torch.float32, device="cuda")
+    totals = dev(np.array([P_step, T_step], dtype=np.int64))
+    B.tgs_loss(dev(out), dev(gt), H, W, vt, offt, pix, n_st, totals, B.loss_params(), dL, err, lam, tl)
+    gd, ge, gl, gt_l = host(dL), host(err), host(lam), host(tl)
+    assert_close(ge, err_ref, 1e-6, 1e-7, "err")
+    assert_close(gl, lam_ref, 1e-4, 1e-6, "lambda")
+    scale = np.abs(dL_ref).max()
+    assert_close(gd[:, :3], dL_ref, 1e-4, 1e-5 * scale, "dL/dI")
+    assert (gd[:, 3] == 0).all()
+    assert_close(gt_l.sum(), ref["loss_l1"] + ref["loss_ncc"], 1e-5, 0, "loss")
+
+
+def test_ema_age_and_error_init_bit_exact(B):
+    W, H = 150, 107
+    E = synth.error_map(H, W, 61)
+    A = synth.age_map(H, W, 62, max_age=65535)
+    A[0, :5] = 65535
+    s = sampler.sample_view(E, A, SampleParams(n_pix=51, n_tiles_sel=9), 3, 1, 0)
+    xs, ys, _ = sampler.sample_coords(s, W, H)
+    err = np.random.default_rng(5).uniform(0, 2, size=xs.size).astype(np.float32)
+    E_ref, A_ref = maps.ema_age_update(E, A, xs, ys, err, 0.4)
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    ts = -np.ones(TX * TY, dtype=np.int32)
+    ts[s["valid_tiles"]] = np.arange(s["valid_tiles"].size)
+    Eg, Ag = dev(E.view(np.int16)), dev(A.view(np.int16))
+    B.tgs_ema_age_update(Eg, Ag, H, W, dev(ts), dev(s["tile_off"]), dev(s["pix"]), dev(err), 0.4)
+    assert np.array_equal(host(Eg).view(np.uint16), E_ref)
+    assert np.array_equal(host(Ag).view(np.uint16), A_ref)
+    # dense error initialisation
+    x = np.random.default_rng(6).uniform(size=(H, W, 3)).astype(np.float32)
+    gt = synth.image(H, W, 63)
+    out = np.zeros((H * W, 4), dtype=np.float32)
+    out[:, :3] = x.reshape(-1, 3)
+    Eo = torch.empty(H * W, dtype=torch.int16, device="cuda")
+    B.tgs_error_init(dev(out), dev(gt), H, W, Eo)
+    assert np.array_equal(host(Eo).view(np.uint16), maps.dense_error_init(x, gt).ravel())
+
+
+# ------------------------------------------------------------------ projection backward
+@pytest.mark.parametrize("case", ["c1", "deg1_bg"])
+def test_project_bwd_parity(B, case):
+    if case == "c1":
+        p, cams = scene_c1(4000)
+        cam, rp = cams[3], RP
+    else:
+        p, cam = small_scene(n=3000, seed=12)
+        rp = RasterParams(sh_degree=1)
+    pr = project.project(p, cam, rp)
+    n = p.shape[1]
+    g2d = np.random.default_rng(7).normal(size=(9, n))
+    g2d[2:5] *= 1e2                                      # conic gradients are large per unit
+    ref = project_bwd.project_bwd(p, cam, pr, g2d, rp)
+    P = dev(p)
+    brp = B.raster_params(sh_degree=rp.sh_degree)
+    splat = torch.empty((n, 12), dtype=torch.float32, device="cuda")
+    depth = torch.empty(n, dtype=torch.float32, device="cuda")
+    radius = torch.empty(n, dtype=torch.int32, device="cuda")
+    rect = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    clamp = torch.empty(n, dtype=torch.uint8, device="cuda")
+    c = B.camera(cam)
+    B.tgs_project(P, n, c, brp, splat, depth, radius, rect, clamp)
+    grad0 = np.random.default_rng(8).normal(size=(59, n)).astype(np.float32)   # accumulation target
+    G = dev(grad0)
+    B.tgs_project_bwd(P, n, c, brp, radius, clamp, dev(g2d.T.astype(np.float32)), G)
+    got = host(G).astype(np.float64) - grad0
+    g32 = g2d.astype(np.float32).astype(np.float64)
+    ref = project_bwd.project_bwd(p, cam, pr, g32, rp)
+    groups = {"mean": slice(0, 3), "logscale": slice(3, 6), "quat": slice(6, 10), "opacity": slice(10, 11),
+              "sh": slice(11, 59)}
+    for name, sl in groups.items():
+        scale = np.abs(ref[sl]).max()
+        assert_close(got[sl], ref[sl], 1e-5, 1e-6 * scale + 4e-7 * np.abs(grad0[sl]), name)
+
+
+# ------------------------------------------------------------------ optimizer
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_optimizer_parity(B, mode):
+    rng = np.random.default_rng(9 + mode)
+    N = 5000
+    p = rng.normal(size=(59, N)).astype(np.float32)
+    g = (rng.normal(size=(59, N)) * 10.0 ** rng.uniform(-5, 0, size=(59, N))).astype(np.float32)
+    m = (rng.normal(size=(59, N)) * 1e-3).astype(np.float32)
+    v = (rng.uniform(0, 1e-4, size=(59, N))).astype(np.float32)
+    touched = (rng.uniform(size=N) < 0.7).astype(np.uint8)
+    op = OptimParams(lm_mode=mode)
+    step = 7
+    rp_, rm, rv = optim.optimizer_step(p, g, m, v, touched, op, step)
+    P, M, V = dev(p), dev(m), dev(v)
+    B.tgs_optimizer_step(P, dev(g), M, V, N, dev(touched), B.optim_params(lm_mode=mode), step)
+    gp, gm, gv = host(P), host(M), host(V)
+    # FP64 inside: results equal the FP32 rounding of the FP64 oracle to 1 ulp
+    for name, a, b in (("params", gp, rp_), ("m", gm, rm), ("v", gv, rv)):
+        b32 = b.astype(np.float32)
+        ulp = np.abs(np.spacing(b32))
+        assert (np.abs(a.astype(np.float64) - b32) <= ulp).all(), name
+    assert np.array_equal(gp[:, touched == 0], p[:, touched == 0])
