@@ -87,9 +87,11 @@ def run(tr, steps, warmup):
     stage = tr.stage_ms()
     cnt = tr.counters.cpu().tolist()
     tr.events = None
+    vb = tr._bufs[0]
+    pixels = (vb.width * vb.height) if vb.dense else int(vb.tile_off[-1].item())
     return dict(seconds=t1 - t0, ms_per_step=(t1 - t0) * 1000.0 / steps, evals=cnt[0], blends=cnt[1],
                 stage_ms={k: v / steps for k, v in stage.items()},
-                n_pairs=int(tr._bufs[0].n_pairs))
+                n_pairs=int(vb.n_pairs), pixels=pixels)
 
 
 def cpu_baseline(p, cam, gt, n_tiles=48):
@@ -130,6 +132,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the pixel-rate sweep and dense run")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU split by "
@@ -141,6 +145,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.calib_copy_mb > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("building workload")
     p, cam, gt = make_workload(dev)
 
@@ -208,6 +221,8 @@ def main():
                    "gaussians": N_GAUSS, "width": WIDTH, "height": HEIGHT, "rate": 0.25,
                    "pairs": head["n_pairs"], "parallelism": "single GPU"},
         "stage_ms": {k: round(v, 4) for k, v in st.items()},
+        "per_step": {"evaluations": per_launch_evals, "blends": per_launch_blends,
+                     "sampled_pixels": head["pixels"]},
         "dense": dense,
         "sparse_vs_dense_speedup": (dense["ms_per_step"] / head["ms_per_step"]) if dense else None,
         "sweep": sweep or None,

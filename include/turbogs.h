@@ -149,17 +149,22 @@ int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t
                    uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
                    size_t ws_bytes, void* stream);
 
-/* Tile x depth binning, radix sort and per-tile ranges (the depth-ordered
+/* Tile x depth binning, sort and per-tile ranges (the depth-ordered
  * per-tile Gaussian lists of Eq. alpha_comp, in the tile order of Sec. 3.6).
  *   rect, depth  projection outputs of n Gaussians
  *   tile_slot    nullable: only tiles with tile_slot >= 0 receive pairs
- *   keys, vals   [capacity] uint64 / uint32 outputs, sorted by
- *                key = (tile << 32) | bits(depth), ties by Gaussian id
+ *   keys         nullable [capacity] uint64: (tile << 32) | bits(depth) of
+ *                each sorted pair
+ *   vals         [capacity] uint32: Gaussian ids ordered by (tile, depth
+ *                bits, id)
  *   ranges       [tiles_x * tiles_y][2] uint32 [start, end), [0, 0) if empty
  *   touched      nullable [n] uint8: set to 1 for Gaussians with a pair
- *   n_pairs      host out: number of pairs
- * Returns TGS_ERR_CAPACITY (and *n_pairs) when capacity is too small; the
- * outputs are then unspecified.  Synchronises the stream once. */
+ *   n_pairs      host out: number of pairs in valid tiles
+ * capacity must hold one entry per tile of the rectangle of every Gaussian
+ * that has a pair (valid tile or not); when it does not, the call returns
+ * TGS_ERR_CAPACITY with that count in *n_pairs and the outputs are
+ * unspecified.  Synchronises the
+ * stream once (to size the sort). */
 size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32_t n_tiles);
 int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t n,
                      const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y,

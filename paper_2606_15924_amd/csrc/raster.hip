@@ -12,8 +12,12 @@
 // accumulated colour from the forward outputs (final colour and the number
 // of contributors), so nothing per Gaussian or per (pixel, Gaussian) is
 // stored.  Per Gaussian, each lane's contribution to the nine screen-space
-// gradients is summed across the wave with DPP, and nine lanes of the wave
-// issue one float atomic each.
+// gradients is summed across the wave (lane-half swaps, then DPP within rows
+// of 16), and nine lanes of the wave issue one float atomic each.
+//
+// Both walks keep the next batch's loads in flight while the current batch
+// is evaluated: at 64 samples per tile a tile is one wave, so there are few
+// waves per SIMD to hide memory latency otherwise.
 #include "common.h"
 
 namespace tgs {
@@ -31,13 +35,25 @@ struct RasterArgs {
 };
 
 // The alpha decisions must come out bit-identical in the forward and the
-// replay, so they are written with explicit fused operations and no
-// contraction left to the compiler.
-__device__ __forceinline__ float splat_power(float dx, float dy, float ca, float cb, float cc) {
+// replay, so both evaluate alpha through these functions, written with
+// explicit fused operations and no contraction left to the compiler.
+//
+// Staged conic: (A, B, C) = (-a/2, -b, -c/2) * log2(e), so that
+// p2 = A dx^2 + B dx dy + C dy^2 = log2(e) * power and G = exp(power) = 2^p2.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr int kUnroll = 4;   // forward: alphas evaluated per group
+constexpr int kUnrollB = 2;  // backward
+
+__device__ __forceinline__ float splat_exponent(float dx, float dy, float A, float Bq, float C) {
 #pragma clang fp contract(off)
   const float xx = dx * dx, yy = dy * dy, xy = dx * dy;
-  const float q = __builtin_fmaf(ca, xx, cc * yy);
-  return __builtin_fmaf(-0.5f, q, -(cb * xy));
+  return __builtin_fmaf(A, xx, __builtin_fmaf(C, yy, Bq * xy));
+}
+
+// alpha = min(alpha_max, o G); ok = exponent <= 0 and alpha >= alpha_min.
+__device__ __forceinline__ float splat_alpha(float p2, float opacity, float amax, float& G) {
+  G = __builtin_amdgcn_exp2f(p2);
+  return __builtin_amdgcn_fmed3f(opacity * G, 0.f, amax);  // o G >= 0
 }
 
 __device__ __forceinline__ float one_minus_times(float T, float alpha) {
@@ -69,12 +85,36 @@ __device__ __forceinline__ PixelSlot pixel_of(const RasterArgs& a, int slot, int
   return p;
 }
 
+// Staging of one batch: every thread holds one Gaussian of the batch in
+// registers; the next batch's loads are issued before the current batch is
+// evaluated, so their latency overlaps the compute.
+struct Staged {
+  float4 geo;  // tile-local centre x, y; staged conic A, B
+  float4 app;  // staged conic C, opacity, r, g
+  float4 con;  // conic a, b, c in natural units, blue (backward only)
+  float blue;
+  uint32_t gid;
+};
+
+__device__ __forceinline__ Staged stage_load(const RasterArgs& a, uint32_t gid, float x0, float y0) {
+  const float4 p0 = a.splat[3 * gid], p1 = a.splat[3 * gid + 1], p2 = a.splat[3 * gid + 2];
+  Staged st;
+  // exact integer difference first, then the fraction: the tile-local centre
+  // keeps full FP32 precision relative to the pixel offsets
+  st.geo = make_float4((p0.x - x0) + p0.z, (p0.y - y0) + p0.w, p1.x * (-0.5f * kLog2e), p1.y * -kLog2e);
+  st.app = make_float4(p1.z * (-0.5f * kLog2e), p1.w, p2.x, p2.y);
+  st.con = make_float4(p1.x, p1.y, p1.z, p2.z);
+  st.blue = p2.z;
+  st.gid = gid;
+  return st;
+}
+
 template <int kBlock, bool kDense>
 __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4* __restrict__ out,
                                                             uint32_t* __restrict__ ncontrib,
                                                             unsigned long long* __restrict__ counters) {
-  __shared__ float4 s_geo[kBlock];  // tile-local centre x, y; conic a, b
-  __shared__ float4 s_app[kBlock];  // conic c, opacity, r, g
+  __shared__ float4 s_geo[kBlock];
+  __shared__ float4 s_app[kBlock];
   __shared__ float s_blue[kBlock];
   const int slot = blockIdx.x, tid = threadIdx.x;
   const int tile = kDense ? slot : a.valid_tiles[slot];
@@ -83,43 +123,63 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
   const float lx = (float)(px.loc & 15), ly = (float)(px.loc >> 4);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const uint2 range = a.ranges[tile];
+  const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.T_min;
 
   float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-  uint32_t last = 0, n_eval = 0, n_blend = 0;
+  uint32_t last = 0;
+  uint32_t n_eval = 0, n_blend = 0;  // wave totals (ballot counts)
   bool done = !px.inside;
+
+  // prologue: records of batch 0 and ids of batch 1 in flight
+  Staged nxt = {};
+  uint32_t g_after = 0;
+  if (range.x + tid < range.y) nxt = stage_load(a, a.vals[range.x + tid], x0, y0);
+  if (range.x + kBlock + tid < range.y) g_after = a.vals[range.x + kBlock + tid];
+
   for (uint32_t start = range.x; start < range.y; start += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
-    const uint32_t idx = start + tid;
-    if (idx < range.y) {
-      const uint32_t g = a.vals[idx];
-      const float4 p0 = a.splat[3 * g], p1 = a.splat[3 * g + 1], p2 = a.splat[3 * g + 2];
-      s_geo[tid] = make_float4((p0.x - x0) + p0.z, (p0.y - y0) + p0.w, p1.x, p1.y);
-      s_app[tid] = make_float4(p1.z, p1.w, p2.x, p2.y);
-      s_blue[tid] = p2.z;
-    }
+    const bool live = start + tid < range.y;  // past the range: a zero-opacity record
+    s_geo[tid] = live ? nxt.geo : make_float4(0.f, 0.f, 0.f, 0.f);
+    s_app[tid] = live ? nxt.app : make_float4(0.f, 0.f, 0.f, 0.f);
+    s_blue[tid] = live ? nxt.blue : 0.f;
     __syncthreads();
+    const uint32_t i1 = start + kBlock + tid, i2 = start + 2 * kBlock + tid;
+    if (i1 < range.y) nxt = stage_load(a, g_after, x0, y0);
+    if (i2 < range.y) g_after = a.vals[i2];
     const int cnt = (int)min((uint32_t)kBlock, range.y - start);
-    if (!done) {
-      for (int j = 0; j < cnt; ++j) {
-        const float4 ge = s_geo[j];
-        const float4 ap = s_app[j];
-        const float power = splat_power(lx - ge.x, ly - ge.y, ge.z, ge.w, ap.x);
-        ++n_eval;
-        if (power > 0.f) continue;
-        const float alpha = fminf(a.alpha_max, ap.y * __expf(power));
-        if (alpha < a.alpha_min) continue;
-        const float t_next = one_minus_times(T, alpha);
-        if (t_next < a.T_min) {
-          done = true;
-          break;
-        }
-        const float w = alpha * T;
-        c0 += w * ap.z;
-        c1 += w * ap.w;
-        c2 += w * s_blue[j];
-        T = t_next;
-        last = start - range.x + (uint32_t)j + 1u;
-        ++n_blend;
+    const uint32_t pos0 = start - range.x;
+    // groups of kUnroll Gaussians: their alphas are independent and are
+    // evaluated first, then composited in order (entries past cnt hold a
+    // zero-opacity record and never composite)
+    for (int j = 0; j < cnt; j += kUnroll) {
+      if (__ballot(!done) == 0ull) break;  // the whole wave has terminated
+      float al[kUnroll], pw[kUnroll], cr[kUnroll], cg[kUnroll], cb[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const float4 ge = s_geo[j + u];
+        const float4 ap = s_app[j + u];
+        pw[u] = splat_exponent(lx - ge.x, ly - ge.y, ge.z, ge.w, ap.x);
+        float G;
+        al[u] = splat_alpha(pw[u], ap.y, amax, G);
+        cr[u] = ap.z;
+        cg[u] = ap.w;
+        cb[u] = s_blue[j + u];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const float t_next = one_minus_times(T, al[u]);
+        bool ok = !done && pw[u] <= 0.f && al[u] >= amin;
+        if (j + u < cnt) n_eval += (uint32_t)__popcll(__ballot(!done));
+        const bool stop = ok && t_next < tmin;
+        done = done || stop;
+        ok = ok && !stop;
+        const float w = ok ? al[u] * T : 0.f;
+        c0 = __builtin_fmaf(w, cr[u], c0);
+        c1 = __builtin_fmaf(w, cg[u], c1);
+        c2 = __builtin_fmaf(w, cb[u], c2);
+        T = ok ? t_next : T;
+        last = ok ? pos0 + (uint32_t)(j + u) + 1u : last;
+        n_blend += (uint32_t)__popcll(__ballot(ok));
       }
     }
   }
@@ -127,12 +187,52 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
     out[px.out] = make_float4(c0 + T * a.bg0, c1 + T * a.bg1, c2 + T * a.bg2, T);
     ncontrib[px.out] = last;
   }
-  if (counters != nullptr) {
-    const int se = wave_sum_i((int)n_eval), sb = wave_sum_i((int)n_blend);
-    if (lane_id() == 0) {
-      atomicAdd(&counters[0], (unsigned long long)se);
-      atomicAdd(&counters[1], (unsigned long long)sb);
-    }
+  if (counters != nullptr && lane_id() == 0) {  // n_eval, n_blend are wave totals
+    atomicAdd(&counters[0], (unsigned long long)n_eval);
+    atomicAdd(&counters[1], (unsigned long long)n_blend);
+  }
+}
+
+__device__ __forceinline__ float swap_sum32(float x, float y) {
+  // after the swap x = [x_lo | y_lo], y = [x_hi | y_hi]: the sum folds both
+  // values to 32 lanes, x in lanes 0-31 and y in lanes 32-63
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap_sum16(float x, float y) {
+  // rows of 16 lanes: x = [x0 y0 x2 y2], y = [x1 y1 x3 y3] after the swap
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dpp_f<kDppQuadPerm1032>(0.f, v);
+  v += dpp_f<kDppQuadPerm2301>(0.f, v);
+  v += dpp_f<kDppRowHalfMirror>(0.f, v);
+  v += dpp_f<kDppRowMirror>(0.f, v);
+  return v;  // every lane of a row holds the row's sum
+}
+
+// Sums each of v[0..8] over the wave and adds the nine sums to dst[0..8]
+// with one atomic instruction.  Halves of the wave are folded pairwise with
+// the lane swaps (64 -> 32 -> 16 lanes per value), then each row of 16 is
+// reduced with DPP; row r of register R_k then holds the sum of one field.
+__device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float* __restrict__ dst) {
+  const float p01 = swap_sum32(v[0], v[1]);
+  const float p23 = swap_sum32(v[2], v[3]);
+  const float p45 = swap_sum32(v[4], v[5]);
+  const float p67 = swap_sum32(v[6], v[7]);
+  const float p8 = swap_sum32(v[8], 0.f);
+  // rows of r0: fields 0, 2, 1, 3; rows of r1: 4, 6, 5, 7; row 0 of r2: 8
+  const float r0 = row_sum16(swap_sum16(p01, p23));
+  const float r1 = row_sum16(swap_sum16(p45, p67));
+  const float r2 = row_sum16(swap_sum16(p8, 0.f));
+  const int lane = lane_id(), k = lane & 15, row = lane >> 4;
+  if (k < 2 || (k == 2 && row == 0)) {
+    const float val = k == 0 ? r0 : (k == 1 ? r1 : r2);
+    const int field = k == 2 ? 8 : (k * 4 + ((row & 1) << 1) + (row >> 1));
+    if (val != 0.f) unsafeAtomicAdd(&dst[field], val);
   }
 }
 
@@ -144,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
                                                             float* __restrict__ g2d) {
   __shared__ float4 s_geo[kBlock];
   __shared__ float4 s_app[kBlock];
-  __shared__ float s_blue[kBlock];
+  __shared__ float4 s_con[kBlock];  // conic a, b, c (natural units), blue
   __shared__ uint32_t s_gid[kBlock];
   const int slot = blockIdx.x, tid = threadIdx.x;
   const int tile = kDense ? slot : a.valid_tiles[slot];
@@ -153,6 +253,7 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
   const float lx = (float)(px.loc & 15), ly = (float)(px.loc >> 4);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const uint2 range = a.ranges[tile];
+  const float amin = a.alpha_min, amax = a.alpha_max;
 
   float Cout0 = 0.f, Cout1 = 0.f, Cout2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
   uint32_t last = 0;
@@ -165,70 +266,67 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
   }
   bool done = last == 0;
   float T = 1.f, acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-  const int lane = lane_id();
+
+  Staged nxt = {};
+  uint32_t g_after = 0;
+  if (range.x + tid < range.y) nxt = stage_load(a, a.vals[range.x + tid], x0, y0);
+  if (range.x + kBlock + tid < range.y) g_after = a.vals[range.x + kBlock + tid];
+
   for (uint32_t start = range.x; start < range.y; start += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
-    const uint32_t idx = start + tid;
-    if (idx < range.y) {
-      const uint32_t g = a.vals[idx];
-      const float4 p0 = a.splat[3 * g], p1 = a.splat[3 * g + 1], p2 = a.splat[3 * g + 2];
-      s_geo[tid] = make_float4((p0.x - x0) + p0.z, (p0.y - y0) + p0.w, p1.x, p1.y);
-      s_app[tid] = make_float4(p1.z, p1.w, p2.x, p2.y);
-      s_blue[tid] = p2.z;
-      s_gid[tid] = g;
-    }
+    const bool live = start + tid < range.y;
+    s_geo[tid] = live ? nxt.geo : make_float4(0.f, 0.f, 0.f, 0.f);
+    s_app[tid] = live ? nxt.app : make_float4(0.f, 0.f, 0.f, 0.f);
+    s_con[tid] = live ? nxt.con : make_float4(0.f, 0.f, 0.f, 0.f);
+    s_gid[tid] = nxt.gid;
     __syncthreads();
+    const uint32_t i1 = start + kBlock + tid, i2 = start + 2 * kBlock + tid;
+    if (i1 < range.y) nxt = stage_load(a, g_after, x0, y0);
+    if (i2 < range.y) g_after = a.vals[i2];
     const int cnt = (int)min((uint32_t)kBlock, range.y - start);
-    for (int j = 0; j < cnt; ++j) {
+    const uint32_t pos0 = start - range.x;
+    for (int j = 0; j < cnt; j += kUnrollB) {
       if (__ballot(!done) == 0ull) break;  // the whole wave has finished
-      const uint32_t pos = start - range.x + (uint32_t)j;
-      const float4 ge = s_geo[j];
-      const float4 ap = s_app[j];
-      float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      bool contrib = false;
-      if (!done) {
-        const float dx = lx - ge.x, dy = ly - ge.y;
-        const float power = splat_power(dx, dy, ge.z, ge.w, ap.x);
-        if (power <= 0.f) {
-          const float G = __expf(power);
-          const float araw = ap.y * G;
-          const float alpha = fminf(a.alpha_max, araw);
-          if (alpha >= a.alpha_min) {
-            contrib = true;
-            const float blue = s_blue[j];
-            const float w = alpha * T;
-            acc0 += w * ap.z;
-            acc1 += w * ap.w;
-            acc2 += w * blue;
-            const float inv = 1.f / (1.f - alpha);
-            const float dalpha = g0 * (T * ap.z - (Cout0 - acc0) * inv) +
-                                 g1 * (T * ap.w - (Cout1 - acc1) * inv) +
-                                 g2 * (T * blue - (Cout2 - acc2) * inv);
-            v[6] = w * g0;
-            v[7] = w * g1;
-            v[8] = w * g2;
-            if (araw < a.alpha_max) {
-              v[5] = G * dalpha;
-              const float dpow = ap.y * G * dalpha;
-              v[0] = (ge.z * dx + ge.w * dy) * dpow;
-              v[1] = (ge.w * dx + ap.x * dy) * dpow;
-              v[2] = -0.5f * dx * dx * dpow;
-              v[3] = -dx * dy * dpow;
-              v[4] = -0.5f * dy * dy * dpow;
-            }
-            T = one_minus_times(T, alpha);
-          }
-        }
-        if (pos + 1u >= last) done = true;
-      }
-      if (__ballot(contrib) != 0ull) {
-        float mine = 0.f;
+      float al[kUnrollB], Gv[kUnrollB], pw[kUnrollB], dxv[kUnrollB], dyv[kUnrollB];
 #pragma unroll
-        for (int f = 0; f < 9; ++f) {
-          const float s = wave_sum(v[f]);
-          if (lane == f) mine = s;
-        }
-        if (lane < 9 && mine != 0.f) unsafeAtomicAdd(&g2d[(int64_t)s_gid[j] * 9 + lane], mine);
+      for (int u = 0; u < kUnrollB; ++u) {
+        const float4 ge = s_geo[j + u];
+        const float4 ap = s_app[j + u];
+        dxv[u] = lx - ge.x;
+        dyv[u] = ly - ge.y;
+        pw[u] = splat_exponent(dxv[u], dyv[u], ge.z, ge.w, ap.x);
+        al[u] = splat_alpha(pw[u], ap.y, amax, Gv[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnrollB; ++u) {
+        if (j + u >= cnt) break;  // uniform
+        const float4 ap = s_app[j + u];
+        const float4 cn = s_con[j + u];
+        const float alpha = al[u], G = Gv[u], dx = dxv[u], dy = dyv[u];
+        const bool ok = !done && pw[u] <= 0.f && alpha >= amin;
+        const float w = ok ? alpha * T : 0.f;
+        acc0 = __builtin_fmaf(w, ap.z, acc0);
+        acc1 = __builtin_fmaf(w, ap.w, acc1);
+        acc2 = __builtin_fmaf(w, cn.w, acc2);
+        const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+        const float dalpha = g0 * (T * ap.z - (Cout0 - acc0) * inv) + g1 * (T * ap.w - (Cout1 - acc1) * inv) +
+                             g2 * (T * cn.w - (Cout2 - acc2) * inv);
+        const bool unclamped = ok && ap.y * G < amax;
+        const float dop = unclamped ? G * dalpha : 0.f;
+        const float dpow = ap.y * dop;
+        float v[9];
+        v[0] = (cn.x * dx + cn.y * dy) * dpow;
+        v[1] = (cn.y * dx + cn.z * dy) * dpow;
+        v[2] = -0.5f * dx * dx * dpow;
+        v[3] = -dx * dy * dpow;
+        v[4] = -0.5f * dy * dy * dpow;
+        v[5] = dop;
+        v[6] = w * g0;
+        v[7] = w * g1;
+        v[8] = w * g2;
+        T = ok ? one_minus_times(T, alpha) : T;
+        done = done || (pos0 + (uint32_t)(j + u) + 1u >= last);
+        if (__ballot(ok) != 0ull) wave_sum9_atomic(v, &g2d[(int64_t)s_gid[j + u] * 9]);
       }
     }
   }

@@ -13,7 +13,7 @@
 // (ascending local index) whose running weight exceeds r.  Each lane owns four
 // consecutive local indices, so lane order is index order and a wave prefix
 // sum locates a draw.
-#include "common.h"
+#include "scan.h"
 
 namespace tgs {
 
@@ -69,20 +69,24 @@ __global__ void __launch_bounds__(64) tile_weights_kernel(const uint16_t* __rest
 }
 
 // ------------------------------------------------------------------ tile select
-// One wave of 64 lanes; lane l owns tiles [l * chunk, (l + 1) * chunk).
-constexpr int kSelectThreads = 64;
+// One workgroup.  The sequential tile draws (only when a subset of tiles is
+// drawn) run on the first wave, whose lane l owns tiles [l * chunk,
+// (l + 1) * chunk); then the whole workgroup lists the chosen tiles in
+// ascending order with their sample counts and prefix offsets.
+constexpr int kSelectThreads = 1024;
 
 __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
     uint64_t* __restrict__ tw, int H, int W, int tiles_x, int n_t, int n_sel, int n_pix,
     uint64_t seed, uint64_t step, uint64_t view, int32_t* __restrict__ valid_tiles,
     int32_t* __restrict__ tile_off, int32_t* __restrict__ tile_slot, int64_t* __restrict__ totals,
     uint8_t* __restrict__ chosen) {
-  const int lane = threadIdx.x;
-  const int chunk = (n_t + kSelectThreads - 1) / kSelectThreads;
-  const int c0 = min(n_t, lane * chunk), c1 = min(n_t, c0 + chunk);
+  const int tid = threadIdx.x;
   const bool all_tiles = n_sel < 0 || n_sel >= n_t;
-  for (int t = c0; t < c1; ++t) chosen[t] = all_tiles ? 1 : 0;
-  if (!all_tiles) {
+  if (!all_tiles && tid < kWave) {
+    const int lane = tid;
+    const int chunk = (n_t + kWave - 1) / kWave;
+    const int c0 = min(n_t, lane * chunk), c1 = min(n_t, c0 + chunk);
+    for (int t = c0; t < c1; ++t) chosen[t] = 0;
     uint64_t lsum = 0;
     for (int t = c0; t < c1; ++t) lsum += tw[t];
     int lrem = c1 - c0;
@@ -126,39 +130,37 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
           }
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
   }
   __syncthreads();
-  // compact chosen tiles in ascending order with their sample counts
-  int lcount = 0, lpix = 0;
+  // ascending list of the chosen tiles with their sample counts
+  __shared__ uint32_t lds[kSelectThreads / kWave];
+  const int chunk = (n_t + kSelectThreads - 1) / kSelectThreads;
+  const int c0 = min(n_t, tid * chunk), c1 = min(n_t, c0 + chunk);
+  uint32_t lcount = 0, lpix = 0;
   for (int t = c0; t < c1; ++t)
-    if (chosen[t]) {
+    if (all_tiles || chosen[t]) {
       ++lcount;
-      const int tx = t % tiles_x, ty = t / tiles_x;
-      lpix += min(n_pix, tile_valid_w(tx, W) * tile_valid_h(ty, H));
+      lpix += (uint32_t)min(n_pix, tile_valid_w(t % tiles_x, W) * tile_valid_h(t / tiles_x, H));
     }
-  const int ic = wave_inclusive_scan_i(lcount);
-  const int ip = wave_inclusive_scan_i(lpix);
-  int slot = ic - lcount, off = ip - lpix;
+  uint32_t n_chosen, P;
+  int slot = (int)block_exclusive_scan<kSelectThreads, uint32_t>(lcount, lds, &n_chosen);
+  int off = (int)block_exclusive_scan<kSelectThreads, uint32_t>(lpix, lds, &P);
   for (int t = c0; t < c1; ++t) {
-    if (chosen[t]) {
-      const int tx = t % tiles_x, ty = t / tiles_x;
+    if (all_tiles || chosen[t]) {
       valid_tiles[slot] = t;
       tile_off[slot] = off;
       tile_slot[t] = slot;
-      off += min(n_pix, tile_valid_w(tx, W) * tile_valid_h(ty, H));
+      off += min(n_pix, tile_valid_w(t % tiles_x, W) * tile_valid_h(t / tiles_x, H));
       ++slot;
     } else {
       tile_slot[t] = -1;
     }
   }
-  if (lane == 63) {
-    tile_off[ic] = ip;
-    atomicAdd((unsigned long long*)&totals[0], (unsigned long long)ip);
-    atomicAdd((unsigned long long*)&totals[1], (unsigned long long)ic);
+  if (tid == 0) {
+    tile_off[n_chosen] = (int32_t)P;
+    atomicAdd((unsigned long long*)&totals[0], (unsigned long long)P);
+    atomicAdd((unsigned long long*)&totals[1], (unsigned long long)n_chosen);
   }
 }
 

@@ -1,6 +1,6 @@
-// Device-wide exclusive prefix sum of uint32 values (three launches:
-// per-block reduce, scan of the block sums in one workgroup, per-block scan
-// with the block's offset).  out[n] receives the total.
+// Device-wide exclusive prefix sums (three launches: per-block reduce, scan
+// of the block sums in one workgroup, per-block scan with the block's
+// offset).  out[n] receives the total.
 #pragma once
 
 #include "common.h"
@@ -13,19 +13,29 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 
 inline int64_t scan_partials(int64_t n) { return ceil_div(n, kScanTile); }
 
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan_t(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T t = __shfl_up(v, o, kWave);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
 // Workgroup-wide exclusive scan of one value per thread; returns the
 // exclusive prefix and writes the workgroup total to *total.
-template <int kThreads>
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_waves,
-                                                         uint32_t* total) {
+template <int kThreads, typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* lds_waves, T* total) {
   constexpr int kWaves = kThreads / kWave;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const uint32_t incl = wave_inclusive_scan_u32(v);
+  const T incl = wave_inclusive_scan_t<T>(v);
   if (lane == kWave - 1) lds_waves[wave] = incl;
   __syncthreads();
-  uint32_t wave_off = 0, sum = 0;
+  T wave_off = 0, sum = 0;
   for (int w = 0; w < kWaves; ++w) {
-    const uint32_t c = lds_waves[w];
+    const T c = lds_waves[w];
     if (w < wave) wave_off += c;
     sum += c;
   }

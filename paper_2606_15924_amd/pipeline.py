@@ -38,8 +38,9 @@ class ViewBuffers:
     """Per-view device buffers for one image size and sampling rate."""
 
     def __init__(self, n: int, width: int, height: int, n_pix: int | None, n_tiles_sel: int,
-                 device, capacity: int | None = None):
+                 device, capacity: int | None = None, keep_keys: bool = False):
         self.n, self.width, self.height = n, width, height
+        self.keep_keys = keep_keys
         self.tiles_x, self.tiles_y = (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
         self.n_t = self.tiles_x * self.tiles_y
         self.dense = n_pix is None
@@ -78,7 +79,7 @@ class ViewBuffers:
     def _alloc_pairs(self, capacity: int):
         dev = self.splat.device
         self.capacity = int(capacity)
-        self.keys = torch.empty(self.capacity, dtype=torch.int64, device=dev)
+        self.keys = torch.empty(self.capacity, dtype=torch.int64, device=dev) if self.keep_keys else None
         self.vals = torch.empty(self.capacity, dtype=torch.int32, device=dev)
         self.sort_ws = torch.empty(B.tgs_bin_sort_workspace_size(self.n, self.capacity, self.n_t),
                                    dtype=torch.uint8, device=dev)
@@ -94,9 +95,11 @@ class ViewBuffers:
         B.tgs_project(params, self.n, cam, rp, self.splat, self.depth, self.radius, self.rect, self.clamp)
 
     def bin_sort(self, touched=None) -> int:
+        # every tile is valid when the sampler keeps all of them: no tile map needed
+        tile_slot = self.tile_slot if (self.tile_slot is not None and self.n_st < self.n_t) else None
         while True:
             try:
-                self.n_pairs = B.tgs_bin_sort(self.rect, self.depth, self.n, self.tile_slot, self.tiles_x,
+                self.n_pairs = B.tgs_bin_sort(self.rect, self.depth, self.n, tile_slot, self.tiles_x,
                                               self.tiles_y, self.keys, self.vals, self.capacity,
                                               self.ranges, touched, self.sort_ws)
                 return self.n_pairs

@@ -154,7 +154,7 @@ def scaling(B):
     n = p.shape[1]
     E = synth.error_map(cam.height, cam.width, 81)
     A = synth.age_map(cam.height, cam.width, 82)
-    vb = ViewBuffers(n, cam.width, cam.height, 64, -1, torch.device("cuda"))
+    vb = ViewBuffers(n, cam.width, cam.height, 64, -1, torch.device("cuda"), keep_keys=True)
     totals = torch.zeros(2, dtype=torch.int64, device="cuda")
     from paper_2606_15924_amd.pipeline import StepConfig
     vb.sample(dev(E.view(np.int16)), dev(A.view(np.int16)), StepConfig(rate_permille=250), 1, 0, totals)

@@ -107,7 +107,10 @@ def test_bin_sort_bit_exact(B, case):
     ranges = binning.tile_ranges(sk, TX * TY)
     rect = dev(pr["rect"].T.astype(np.int32))
     depth = dev(pr["depth32"])
-    cap = int(sk.size) + 17
+    # one entry per tile of the rectangle of each Gaussian with a pair, valid tile or not
+    rect_area = (pr["rect"][2] - pr["rect"][0]) * (pr["rect"][3] - pr["rect"][1])
+    area = int(rect_area[np.unique(sv)].sum())
+    cap = area + 17
     K = torch.empty(cap, dtype=torch.int64, device="cuda")
     V = torch.empty(cap, dtype=torch.int32, device="cuda")
     R = torch.empty((TX * TY, 2), dtype=torch.int32, device="cuda")
@@ -124,7 +127,7 @@ def test_bin_sort_bit_exact(B, case):
     # too-small capacity reports the required count
     with pytest.raises(B.CapacityError) as ei:
         B.tgs_bin_sort(rect, depth, n, tile_slot, TX, TY, K, V, 10, R, None, ws)
-    assert ei.value.required == sk.size
+    assert ei.value.required == area
 
 
 # ------------------------------------------------------------------ sampler
