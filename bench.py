@@ -85,7 +85,7 @@ def run(tr, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stage = tr.stage_ms()
-    cnt = tr.counters.cpu().tolist()
+    cnt = tr.counters.sum(dim=1).cpu().tolist()
     tr.events = None
     vb = tr._bufs[0]
     pixels = (vb.width * vb.height) if vb.dense else int(vb.tile_off[-1].item())

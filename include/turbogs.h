@@ -52,6 +52,7 @@ extern "C" {
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
 #define TGS_PARAM_ROWS 59
+#define TGS_COUNTER_SLOTS 64 /* slots per counter of tgs_render_fwd */
 
 enum {
   TGS_OK = 0,
@@ -178,7 +179,10 @@ int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t n,
  *   max_per_tile  largest per-tile sample count (sizes the workgroup)
  *   out       [P][4] float: r, g, b (including T_final * bg), T_final
  *   ncontrib  [P] uint32: range position of the last composited Gaussian + 1
- *   counters  nullable [2] uint64 += (evaluations, blends) */
+ *   counters  nullable [2][TGS_COUNTER_SLOTS] uint64: evaluations are added
+ *             to row 0 and blends to row 1, spread over the slots (a
+ *             workgroup adds to slot blockIdx mod TGS_COUNTER_SLOTS, which
+ *             keeps same-address atomics rare); the totals are the row sums */
 int32_t tgs_render_fwd(const float* splat, const uint32_t* vals, const uint32_t* ranges,
                        int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
                        const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,

@@ -22,6 +22,7 @@ SPLAT_FLOATS = 12
 G2D_FLOATS = 9
 PARAM_ROWS = 59
 TILE = 16
+COUNTER_SLOTS = 64
 
 
 class tgs_camera(ctypes.Structure):

@@ -5,27 +5,34 @@
 // every (Gaussian, tile) pair, the Gaussians are put in (depth, id) order once
 // (a 32-bit sort of n keys) and the pairs are emitted in that order; a
 // stable sort on the tile bits alone then yields the full order.  The pair
-// key is (tile << pos_bits) | position-in-depth-order, usually 32 bits, and
-// the id is read back from the depth order after the sort:
+// key is (tile << id_bits) | Gaussian id, usually 32 bits: the id bits only
+// ride along, since a stable sort never compares them.
 //
 //   count     per Gaussian: rectangle area, visibility, touched flag and the
-//             depth key (culled Gaussians get a key above every depth)
+//             depth key (culled Gaussians get a key above every depth); the
+//             rectangle's four corners go into a 2-D difference grid, whose
+//             prefix sums are the per-tile pair counts
 //   sort      LSD radix sort of (depth key, id) over n: stable, so ties keep
 //             id order; visible Gaussians come first
-//   gather    areas in depth order, exclusive scan -> pair offsets, total
-//   emit      one thread per pair (load-balanced: each block finds its first
-//             Gaussian with a 256-way search of the offsets), coalesced key
-//             writes; tiles outside the valid set get the sentinel tile id
-//             n_tiles, which sorts after every real tile
-//   sort      LSD radix sort of the pair keys on the tile bits only
-//   finalize  ids from depth positions, tile boundaries -> ranges and
-//             (optionally) the 64-bit (tile << 32) | depth-bits keys
+//   gather    rectangles and pair counts in depth order, exclusive scan ->
+//             pair offsets and the total (read back once)
+//   ranges    2-D prefix of the difference grid, then a scan over the valid
+//             tiles in tile order: each tile's [start, end)
+//   emit      4096 pairs per workgroup: the Gaussians that start inside the
+//             block mark their first slot in LDS and a max-scan hands every
+//             slot its Gaussian (a load-balanced search); keys are written
+//             coalesced, tiles outside the valid set get the sentinel tile
+//             id n_tiles (after every real tile), and the block's histogram
+//             of the first radix digit is taken on the way
+//   sort      LSD radix sort of the pair keys on the tile bits only; the
+//             last pass writes the ids (and, if asked, the 64-bit keys)
 //
-// Each radix pass is a stable counting sort: per-block digit histograms
-// (peer groups found by a 64-lane ballot match add their counts once), one
-// scan of the digit-major histogram table, and a per-block scatter whose
-// in-block ranks come from the same ballot match and a digit prefix across
-// the workgroup's waves.
+// A radix pass is a stable counting sort over blocks of 256 x kItems keys:
+// per-block digit histograms (peer lanes found by a ballot match add their
+// count once), one scan of the digit-major histogram table, and a scatter
+// that ranks the block's keys (each wave owns a contiguous quarter of the
+// block), reorders them by digit in LDS and writes runs of equal digits to
+// consecutive addresses.
 #include <algorithm>
 #include <utility>
 
@@ -108,26 +115,56 @@ static void exclusive_scan(const T* in, T* out, int64_t n, T* partials, hipStrea
   hipLaunchKernelGGL(scan_down_kernel<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials, out);
 }
 
-void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials, hipStream_t s) {
-  exclusive_scan<uint32_t>(in, out, n, partials, s);
-}
 
 
 // ------------------------------------------------------------------ count
 // Depth key of a culled Gaussian: above every finite positive depth bit pattern.
 constexpr uint32_t kCulledKey = 0xffffffffu;
 
-__global__ void __launch_bounds__(256) count_kernel(const int4* __restrict__ rect,
-                                                    const float* __restrict__ depth, int64_t n,
-                                                    const int32_t* __restrict__ tile_slot, int tiles_x,
-                                                    uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals,
-                                                    uint8_t* __restrict__ touched,
-                                                    unsigned long long* __restrict__ valid_total) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t valid = 0;
-  if (i < n) {
-    const int4 r = rect[i];
+// Rectangles are clamped to the tile grid (projection already does so; the
+// clamp keeps every index of the binning in bounds for any input).
+__device__ __forceinline__ int4 clamp_rect(int4 r, int tiles_x, int tiles_y) {
+  r.x = min(max(r.x, 0), tiles_x);
+  r.z = min(max(r.z, r.x), tiles_x);
+  r.y = min(max(r.y, 0), tiles_y);
+  r.w = min(max(r.w, r.y), tiles_y);
+  return r;
+}
+
+// Difference grid of the pair counts: (tiles_y + 1) x (tiles_x + 1) cells; a
+// Gaussian with a pair adds +1 at (y0, x0) and (y1, x1), -1 at (y0, x1) and
+// (y1, x0), so the 2-D inclusive prefix sum at (ty, tx) counts the rectangles
+// that cover tile (tx, ty).  Each count workgroup accumulates its own grid in
+// LDS and writes it out whole (contended device-wide atomics are slow), and
+// the grids are summed per cell afterwards.  Grids above kLdsCells cells use
+// device atomics on a single grid instead.
+constexpr int kCountThreads = 1024;
+constexpr int kCountBlocks = 64;   // at most; partial grids to sum
+constexpr int kLdsCells = 12288;   // 48 KiB of LDS
+
+__global__ void __launch_bounds__(kCountThreads) count_kernel(const int4* __restrict__ rect,
+                                                              const float* __restrict__ depth, int64_t n,
+                                                              const int32_t* __restrict__ tile_slot, int tiles_x,
+                                                              int tiles_y, uint32_t* __restrict__ dkeys,
+                                                              uint32_t* __restrict__ dvals,
+                                                              uint8_t* __restrict__ touched,
+                                                              int32_t* __restrict__ partial, bool lds_grid,
+                                                              unsigned long long* __restrict__ valid_total) {
+  __shared__ int32_t s_diff[kLdsCells];
+  __shared__ uint32_t lds[kCountThreads / kWave];
+  const int gw = tiles_x + 1;
+  const int cells = gw * (tiles_y + 1);
+  if (lds_grid) {
+    for (int c = threadIdx.x; c < cells; c += kCountThreads) s_diff[c] = 0;
+    __syncthreads();
+  }
+  int32_t* gdiff = lds_grid ? s_diff : partial;
+  uint32_t valid_sum = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kCountThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kCountThreads) {
+    const int4 r = clamp_rect(rect[i], tiles_x, tiles_y);
     const uint32_t area = (uint32_t)((r.z - r.x) * (r.w - r.y));
+    uint32_t valid = 0;
     if (tile_slot == nullptr) {
       valid = area;
     } else {
@@ -136,14 +173,36 @@ __global__ void __launch_bounds__(256) count_kernel(const int4* __restrict__ rec
     }
     dkeys[i] = valid > 0 ? __float_as_uint(depth[i]) : kCulledKey;
     dvals[i] = (uint32_t)i;
-    if (touched != nullptr && valid > 0) touched[i] = 1;
+    if (valid > 0) {
+      atomicAdd(&gdiff[r.y * gw + r.x], 1);
+      atomicAdd(&gdiff[r.y * gw + r.z], -1);
+      atomicAdd(&gdiff[r.w * gw + r.x], -1);
+      atomicAdd(&gdiff[r.w * gw + r.z], 1);
+      if (touched != nullptr) touched[i] = 1;
+    }
+    valid_sum += valid;
   }
-  if (tile_slot != nullptr) {  // pairs in valid tiles: one atomic per workgroup
-    __shared__ uint32_t lds[256 / kWave];
+  if (tile_slot != nullptr) {  // pairs in valid tiles, spread over the slots
     uint32_t tot;
-    block_exclusive_scan<256, uint32_t>(valid, lds, &tot);
-    if (threadIdx.x == 0 && tot > 0) atomicAdd(valid_total, (unsigned long long)tot);
+    block_exclusive_scan<kCountThreads, uint32_t>(valid_sum, lds, &tot);
+    if (threadIdx.x == 0 && tot > 0)
+      atomicAdd(&valid_total[blockIdx.x & (TGS_COUNTER_SLOTS - 1)], (unsigned long long)tot);
   }
+  if (lds_grid) {
+    __syncthreads();
+    int32_t* out = partial + (int64_t)blockIdx.x * cells;
+    for (int c = threadIdx.x; c < cells; c += kCountThreads) out[c] = s_diff[c];
+  }
+}
+
+// diff[c] = sum over the partial grids of cell c.
+__global__ void __launch_bounds__(256) diff_sum_kernel(const int32_t* __restrict__ partial, int n_grids,
+                                                       int cells, int32_t* __restrict__ diff) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cells) return;
+  int32_t s = 0;
+  for (int b = 0; b < n_grids; ++b) s += partial[(int64_t)b * cells + c];
+  diff[c] = s;
 }
 
 // Rectangles and pair counts in depth order (a Gaussian without a valid tile
@@ -151,18 +210,80 @@ __global__ void __launch_bounds__(256) count_kernel(const int4* __restrict__ rec
 __global__ void __launch_bounds__(256) gather_kernel(const uint32_t* __restrict__ perm,
                                                      const uint32_t* __restrict__ dkeys_sorted,
                                                      const int4* __restrict__ rect, int64_t n,
+                                                     int tiles_x, int tiles_y,
                                                      int4* __restrict__ rect_sorted,
                                                      uint32_t* __restrict__ area_sorted) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const int4 r = rect[perm[j]];
+  const int4 r = clamp_rect(rect[perm[j]], tiles_x, tiles_y);
   rect_sorted[j] = r;
   area_sorted[j] = dkeys_sorted[j] == kCulledKey ? 0u : (uint32_t)((r.z - r.x) * (r.w - r.y));
+}
+
+// ------------------------------------------------------------------ ranges
+// One workgroup: 2-D inclusive prefix of the difference grid (rows, then
+// columns; in LDS when it fits), then an exclusive scan of the valid tiles'
+// counts in tile order.  Empty and invalid tiles get [0, 0).
+constexpr int kRangeThreads = 1024;
+
+__global__ void __launch_bounds__(kRangeThreads) ranges_kernel(int32_t* __restrict__ diff, int tiles_x,
+                                                               int tiles_y, const int32_t* __restrict__ tile_slot,
+                                                               uint2* __restrict__ ranges) {
+  __shared__ int32_t s_grid[kLdsCells];
+  __shared__ uint32_t lds[kRangeThreads / kWave];
+  const int gw = tiles_x + 1;
+  const int cells = gw * (tiles_y + 1);
+  const bool in_lds = cells <= kLdsCells;
+  int32_t* g = in_lds ? s_grid : diff;
+  if (in_lds) {
+    for (int c = threadIdx.x; c < cells; c += kRangeThreads) s_grid[c] = diff[c];
+    __syncthreads();
+  }
+  for (int y = threadIdx.x; y < tiles_y; y += kRangeThreads) {
+    int32_t* row = g + (int64_t)y * gw;
+    int32_t acc = 0;
+    for (int x = 0; x < tiles_x; ++x) {
+      acc += row[x];
+      row[x] = acc;
+    }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < tiles_x; x += kRangeThreads) {
+    int32_t acc = 0;
+    for (int y = 0; y < tiles_y; ++y) {
+      acc += g[(int64_t)y * gw + x];
+      g[(int64_t)y * gw + x] = acc;
+    }
+  }
+  __syncthreads();
+  const int n_t = tiles_x * tiles_y;
+  uint32_t carry = 0;
+  for (int t0 = 0; t0 < n_t; t0 += kRangeThreads) {
+    const int t = t0 + (int)threadIdx.x;
+    uint32_t c = 0;
+    if (t < n_t && (tile_slot == nullptr || tile_slot[t] >= 0))
+      c = (uint32_t)g[(int64_t)(t / tiles_x) * gw + (t % tiles_x)];
+    uint32_t tot;
+    const uint32_t start = carry + block_exclusive_scan<kRangeThreads, uint32_t>(c, lds, &tot);
+    if (t < n_t) ranges[t] = c > 0 ? make_uint2(start, start + c) : make_uint2(0u, 0u);
+    carry += tot;
+  }
 }
 
 // ------------------------------------------------------------------ radix sort
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kPairItems = 16;  // keys per thread of the pair sort (and of emit)
+
+// Keys per thread: 16 for large sorts, 4 for small ones (more workgroups).
+static int sort_items(int64_t n) { return n >= (1ll << 20) ? 16 : 4; }
+
+static int64_t sort_blocks(int64_t n, int items) { return ceil_div(n, (int64_t)kSortThreads * items); }
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
 
 // Lanes of the wave holding the same kBits-bit digit (inactive lanes excluded).
 template <int kBits>
@@ -177,26 +298,30 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
   return peers;
 }
 
-template <typename K, int kBits>
+// Per-block histogram: block b covers keys [b * 256 * kItems, ...), wave w
+// the contiguous quarter w of it, 64 keys per round.
+template <typename K, int kBits, int kItems>
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K* __restrict__ keys, uint32_t n,
-                                                                 int shift, int rounds, int nblocks,
+                                                                 int shift, int nblocks,
                                                                  uint32_t* __restrict__ hist) {
   constexpr int kDigits = 1 << kBits;
   __shared__ uint32_t h[kDigits];
-  if (threadIdx.x < kDigits) h[threadIdx.x] = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t base = (int64_t)blockIdx.x * kSortThreads * rounds;
-  for (int k = 0; k < rounds; ++k) {
-    const int64_t i = base + (int64_t)k * kSortThreads + threadIdx.x;
-    const bool valid = i < n;
-    const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & (kDigits - 1u) : 0u;
-    const uint64_t peers = digit_peers<kBits>(d, valid);
-    if (valid && (peers & lt_mask) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+  for (int i = threadIdx.x; i < kDigits; i += kSortThreads) h[i] = 0;
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  const int64_t wbase = (int64_t)blockIdx.x * kSortThreads * kItems + (int64_t)wave * kWave * kItems;
+  K key[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = wbase + k * kWave + lane;
+    key[k] = i < n ? keys[i] : (K)0;
   }
   __syncthreads();
-  if (threadIdx.x < kDigits) hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k)
+    if (wbase + k * kWave + lane < n) atomicAdd(&h[(uint32_t)(key[k] >> shift) & (kDigits - 1u)], 1u);
+  __syncthreads();
+  for (int dg = threadIdx.x; dg < kDigits; dg += kSortThreads)
+    hist[(int64_t)dg * nblocks + blockIdx.x] = h[dg];
 }
 
 // One workgroup per digit: exclusive prefix of the digit's per-block counts
@@ -218,205 +343,294 @@ __global__ void __launch_bounds__(1024) digit_scan_kernel(const uint32_t* __rest
   if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
-template <typename K, bool kVals, int kBits>
+// Output of a scatter pass: keys (and values) for the next pass, or, in the
+// last pass of the pair sort, the Gaussian ids carried in the low key bits
+// and optionally the 64-bit (tile << 32) | depth-bits keys.
+struct ScatterOut {
+  void* keys;
+  uint32_t* vals;
+  int id_bits;           // final pass: key = (tile << id_bits) | id
+  const float* depth;    // final pass, for keys64
+  uint64_t* keys64;      // final pass, nullable
+};
+
+template <typename K, bool kVals, bool kFinal, int kBits, int kItems>
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
-    const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t n, int shift, int rounds,
-    int nblocks, const uint32_t* __restrict__ offs, const uint32_t* __restrict__ dtot,
-    K* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t n, int shift, int nblocks,
+    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ dtot, ScatterOut o) {
   constexpr int kDigits = 1 << kBits;
-  __shared__ uint32_t base[kDigits];                // running position of each digit
-  __shared__ uint32_t wcount[kSortWaves][kDigits];  // per-wave counts, then offsets, of this round
-  __shared__ uint32_t lds[kSortThreads / kWave];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  // start of each digit = totals of the smaller digits + this block's prefix within the digit
-  uint32_t dall;
-  const uint32_t dstart = block_exclusive_scan<kSortThreads, uint32_t>(tid < kDigits ? dtot[tid] : 0u, lds, &dall);
-  if (tid < kDigits) {
-    base[tid] = dstart + offs[(int64_t)tid * nblocks + blockIdx.x];
-    for (int w = 0; w < kSortWaves; ++w) wcount[w][tid] = 0;
+  constexpr int kBlockKeys = kSortThreads * kItems;
+  __shared__ uint32_t s_cnt[kSortWaves][kDigits];  // per-wave digit counts, then block-local offsets
+  __shared__ uint32_t s_gbase[kDigits];            // global position of block-local position 0 of the digit
+  __shared__ K s_keys[kBlockKeys];
+  __shared__ uint32_t s_vals[kVals ? kBlockKeys : 1];
+  __shared__ uint32_t s_red[kSortWaves];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  for (int i = tid; i < kSortWaves * kDigits; i += kSortThreads) (&s_cnt[0][0])[i] = 0;
+  const int64_t blk0 = (int64_t)blockIdx.x * kBlockKeys;
+  const int64_t wbase = blk0 + (int64_t)wave * kWave * kItems;
+  K key[kItems];
+  uint32_t val[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = wbase + k * kWave + lane;
+    key[k] = i < n ? keys_in[i] : (K)0;
+    if (kVals) val[k] = i < n ? vals_in[i] : 0u;
   }
   __syncthreads();
-  const int64_t blk = (int64_t)blockIdx.x * kSortThreads * rounds;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int k = 0; k < rounds; ++k) {
-    if (blk + (int64_t)k * kSortThreads >= n) break;  // uniform across the workgroup
-    const int64_t i = blk + (int64_t)k * kSortThreads + tid;
-    const bool valid = i < n;
-    K key = 0;
-    uint32_t val = 0;
-    if (valid) {
-      key = keys_in[i];
-      if (kVals) val = vals_in[i];
-    }
-    const uint32_t d = (uint32_t)(key >> shift) & (kDigits - 1u);
+  // rank of each key among the wave's keys of the same digit (stable: by
+  // round, then lane); the wave's running counts live in s_cnt[wave]
+  const uint64_t below = lanes_below();
+  uint32_t rank[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const bool valid = wbase + k * kWave + lane < n;
+    const uint32_t d = (uint32_t)(key[k] >> shift) & (kDigits - 1u);
     const uint64_t peers = digit_peers<kBits>(d, valid);
-    const int rank = __popcll(peers & lt_mask);
-    if (valid && rank == 0) wcount[wave][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (tid < kDigits) {
-      uint32_t run = base[tid];
-      for (int w = 0; w < kSortWaves; ++w) {
-        const uint32_t c = wcount[w][tid];
-        wcount[w][tid] = run;
-        run += c;
+    const uint32_t r = (uint32_t)__popcll(peers & below);
+    const uint32_t before = valid ? s_cnt[wave][d] : 0u;
+    rank[k] = before + r;
+    if (valid && r == 0) s_cnt[wave][d] = before + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // block-local start of each (digit, wave) and the digit's global base
+  uint32_t pre[kSortWaves];
+  uint32_t tot = 0;
+  if (tid < kDigits)
+    for (int w = 0; w < kSortWaves; ++w) {
+      pre[w] = tot;
+      tot += s_cnt[w][tid];
+    }
+  uint32_t all;
+  const uint32_t lstart = block_exclusive_scan<kSortThreads, uint32_t>(tid < kDigits ? tot : 0u, s_red, &all);
+  const uint32_t gstart =
+      block_exclusive_scan<kSortThreads, uint32_t>(tid < kDigits ? dtot[tid] : 0u, s_red, &all);
+  if (tid < kDigits) {
+    for (int w = 0; w < kSortWaves; ++w) s_cnt[w][tid] = lstart + pre[w];
+    s_gbase[tid] = gstart + offs[(int64_t)tid * nblocks + blockIdx.x] - lstart;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (wbase + k * kWave + lane < n) {
+      const uint32_t d = (uint32_t)(key[k] >> shift) & (kDigits - 1u);
+      const uint32_t lp = s_cnt[wave][d] + rank[k];
+      s_keys[lp] = key[k];
+      if (kVals) s_vals[lp] = val[k];
+    }
+  }
+  __syncthreads();
+  // runs of equal digits go to consecutive addresses
+  const int count = (int)min((int64_t)kBlockKeys, (int64_t)n - blk0);
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int lp = k * kSortThreads + tid;
+    if (lp < count) {
+      const K kk = s_keys[lp];
+      const uint32_t dst = s_gbase[(uint32_t)(kk >> shift) & (kDigits - 1u)] + (uint32_t)lp;
+      if (kFinal) {
+        const uint32_t g = (uint32_t)(kk & (((K)1 << o.id_bits) - 1));
+        o.vals[dst] = g;
+        if (o.keys64 != nullptr)
+          o.keys64[dst] = ((uint64_t)(kk >> o.id_bits) << 32) | (uint64_t)__float_as_uint(o.depth[g]);
+      } else {
+        ((K*)o.keys)[dst] = kk;
+        if (kVals) o.vals[dst] = s_vals[lp];
       }
-      base[tid] = run;
     }
-    __syncthreads();
-    if (valid) {
-      const uint32_t dst = wcount[wave][d] + (uint32_t)rank;
-      keys_out[dst] = key;
-      if (kVals) vals_out[dst] = val;
-    }
-    __syncthreads();
-    if (tid < kDigits)
-      for (int w = 0; w < kSortWaves; ++w) wcount[w][tid] = 0;
-    __syncthreads();
   }
 }
 
-// Keys per thread for n keys: enough workgroups to fill the GPU, at most 16.
-static int sort_rounds(uint32_t n) {
-  int r = (int)ceil_div(n, (int64_t)kSortThreads * 2048);
-  return std::min(16, std::max(1, r));
-}
-
-template <typename K, bool kVals, int kBits>
-static void radix_pass(K*& keys, uint32_t*& vals, K*& keys_alt, uint32_t*& vals_alt, uint32_t n, int shift,
-                       uint32_t* hist, uint32_t* hoffs, uint32_t* partials, hipStream_t s) {
-  const int rounds = sort_rounds(n);
-  const int nblocks = (int)ceil_div(n, (int64_t)kSortThreads * rounds);
-  hipLaunchKernelGGL((radix_hist_kernel<K, kBits>), dim3(nblocks), dim3(kSortThreads), 0, s, keys, n, shift,
-                     rounds, nblocks, hist);
-  uint32_t* dtot = partials;  // one total per digit
+// One radix pass over n keys on bits [shift, shift + kBits); the histogram
+// table is taken here unless the caller already wrote it (hist_ready).
+template <typename K, bool kVals, bool kFinal, int kBits, int kItems>
+static void radix_pass(const K* keys, const uint32_t* vals, uint32_t n, int shift, bool hist_ready,
+                       uint32_t* hist, uint32_t* hoffs, uint32_t* dtot, const ScatterOut& o, hipStream_t s) {
+  const int nblocks = (int)sort_blocks(n, kItems);
+  if (!hist_ready)
+    hipLaunchKernelGGL((radix_hist_kernel<K, kBits, kItems>), dim3(nblocks), dim3(kSortThreads), 0, s, keys, n,
+                       shift, nblocks, hist);
   hipLaunchKernelGGL(digit_scan_kernel, dim3(1 << kBits), dim3(1024), 0, s, hist, nblocks, hoffs, dtot);
-  hipLaunchKernelGGL((radix_scatter_kernel<K, kVals, kBits>), dim3(nblocks), dim3(kSortThreads), 0, s, keys,
-                     vals, n, shift, rounds, nblocks, hoffs, dtot, keys_alt, vals_alt);
-  std::swap(keys, keys_alt);
-  std::swap(vals, vals_alt);
+  hipLaunchKernelGGL((radix_scatter_kernel<K, kVals, kFinal, kBits, kItems>), dim3(nblocks), dim3(kSortThreads),
+                     0, s, keys, vals, n, shift, nblocks, hoffs, dtot, o);
 }
 
-// Sorts n keys (and values) on bits [lo, lo + bits); passes of at most 8
-// bits, split evenly.  The result lands in keys/vals (pointers are swapped).
-template <typename K, bool kVals>
-static void radix_sort(K*& keys, uint32_t*& vals, K*& keys_alt, uint32_t*& vals_alt, uint32_t n, int lo,
-                       int bits, uint32_t* hist, uint32_t* hoffs, uint32_t* partials, hipStream_t s) {
-  if (n <= 1 || bits <= 0) return;
-  const int passes = (bits + 7) / 8;
-  const int per = (bits + passes - 1) / passes;
-  int shift = lo;
-  for (int p = 0; p < passes; ++p) {
-    const int b = std::min(per, lo + bits - shift);
-    switch (b) {
-      case 1: radix_pass<K, kVals, 1>(keys, vals, keys_alt, vals_alt, n, shift, hist, hoffs, partials, s); break;
-      case 2: radix_pass<K, kVals, 2>(keys, vals, keys_alt, vals_alt, n, shift, hist, hoffs, partials, s); break;
-      case 3: radix_pass<K, kVals, 3>(keys, vals, keys_alt, vals_alt, n, shift, hist, hoffs, partials, s); break;
-      case 4: radix_pass<K, kVals, 4>(keys, vals, keys_alt, vals_alt, n, shift, hist, hoffs, partials, s); break;
-      case 5: radix_pass<K, kVals, 5>(keys, vals, keys_alt, vals_alt, n, shift, hist, hoffs, partials, s); break;
-      case 6: radix_pass<K, kVals, 6>(keys, vals, keys_alt, vals_alt, n, shift, hist, hoffs, partials, s); break;
-      case 7: radix_pass<K, kVals, 7>(keys, vals, keys_alt, vals_alt, n, shift, hist, hoffs, partials, s); break;
-      default: radix_pass<K, kVals, 8>(keys, vals, keys_alt, vals_alt, n, shift, hist, hoffs, partials, s); break;
-    }
-    shift += b;
+template <typename K, bool kVals, bool kFinal, int kItems>
+static void radix_pass_bits(int bits, const K* keys, const uint32_t* vals, uint32_t n, int shift,
+                            bool hist_ready, uint32_t* hist, uint32_t* hoffs, uint32_t* dtot,
+                            const ScatterOut& o, hipStream_t s) {
+  switch (bits) {
+#define TGS_PASS(B) \
+  case B: radix_pass<K, kVals, kFinal, B, kItems>(keys, vals, n, shift, hist_ready, hist, hoffs, dtot, o, s); break;
+    TGS_PASS(1) TGS_PASS(2) TGS_PASS(3) TGS_PASS(4) TGS_PASS(5) TGS_PASS(6) TGS_PASS(7)
+    default: radix_pass<K, kVals, kFinal, 8, kItems>(keys, vals, n, shift, hist_ready, hist, hoffs, dtot, o, s);
+#undef TGS_PASS
   }
+}
+
+// Passes of at most 8 bits over [lo, lo + bits), split evenly.
+static int pass_count(int bits) { return (bits + 7) / 8; }
+static int pass_bits(int bits, int p) {
+  const int per = (bits + pass_count(bits) - 1) / pass_count(bits);
+  return std::min(per, bits - p * per);
 }
 
 // ------------------------------------------------------------------ emit
-constexpr int kEmitThreads = 256;
-constexpr int kEmitItems = 8;
-constexpr int kEmitTile = kEmitThreads * kEmitItems;
-constexpr int kEmitWindow = 2048;
+constexpr int kEmitThreads = kSortThreads;
+constexpr int kEmitTile = kSortThreads * kPairItems;  // = a pair-sort block
+constexpr int kEmitWin = 512;                          // Gaussians staged in LDS per block
 
-// Largest j in [0, n) with off[j] <= target, by a 256-way search per round
-// (off[0] = 0 <= target; offsets are non-decreasing).
-__device__ __forceinline__ int64_t block_last_le(const uint32_t* __restrict__ off, int64_t n, uint32_t target) {
-  int64_t lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int64_t step = ceil_div(hi - lo, kEmitThreads);
-    const int64_t j = lo + (int64_t)threadIdx.x * step;
-    const bool pred = j < hi && off[j] <= target;
-    const int cnt = __syncthreads_count(pred);
-    lo = lo + (int64_t)(cnt - 1) * step;
-    hi = min(hi, lo + step);
-  }
-  return lo;
+// block_j0[b]: the Gaussian (depth position) holding pair b * kEmitTile.
+__global__ void __launch_bounds__(256) block_start_kernel(const uint32_t* __restrict__ off, int64_t n,
+                                                          int32_t* __restrict__ block_j0) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t a = off[j], e = off[j + 1];
+  for (uint32_t b = (uint32_t)ceil_div(a, kEmitTile); (uint64_t)b * kEmitTile < e; ++b) block_j0[b] = (int32_t)j;
 }
 
-template <typename K>
+// q = a / b and r = a % b for b > 0: below 2^22 a float estimate of the
+// quotient is off by at most one and is corrected; larger a divide exactly.
+__device__ __forceinline__ void divmod_small(uint32_t a, uint32_t b, uint32_t& q, uint32_t& r) {
+  if (a >= (1u << 22)) {
+    q = a / b;
+    r = a - q * b;
+    return;
+  }
+  int qi = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+  int ri = (int)a - qi * (int)b;
+  if (ri < 0) { --qi; ri += (int)b; }
+  if (ri >= (int)b) { ++qi; ri -= (int)b; }
+  q = (uint32_t)qi;
+  r = (uint32_t)ri;
+}
+
+// Pairs [p0, p0 + kEmitTile) of the depth-ordered pair list.  The Gaussians
+// that start inside the block (and j0, which holds p0) mark their first slot
+// with their index relative to j0 and stage rectangle, offset and id in LDS;
+// an inclusive max-scan then gives every slot its Gaussian.  Every
+// Gaussian before the culled tail has at least one pair, so the marked
+// slots are distinct.
+template <typename K, int kBits0>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
-    const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ off, int64_t n, uint32_t total,
-    const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t, int pbits, K* __restrict__ keys) {
-  __shared__ uint32_t s_off[kEmitWindow];
+    const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ ids_sorted,
+    const uint32_t* __restrict__ off, const int32_t* __restrict__ block_j0, int64_t n, uint32_t total,
+    const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t, int id_bits, K* __restrict__ keys,
+    int nblocks, uint32_t* __restrict__ hist) {
+  constexpr int kDigits = 1 << kBits0;
+  __shared__ int32_t s_j[kEmitTile];
+  __shared__ int4 s_rect[kEmitWin];
+  __shared__ uint32_t s_off[kEmitWin];
+  __shared__ uint32_t s_id[kEmitWin];
+  __shared__ uint32_t s_h[kDigits];
+  __shared__ int32_t s_red[kEmitThreads / kWave];
+  const int tid = threadIdx.x;
   const uint32_t p0 = blockIdx.x * (uint32_t)kEmitTile;
-  const uint32_t p_last = min(total, p0 + (uint32_t)kEmitTile) - 1u;
-  const int64_t j0 = block_last_le(off, n, p0);
-  const int64_t j1 = block_last_le(off, n, p_last);
-  const int64_t cnt = j1 - j0 + 1;
-  const bool windowed = cnt <= kEmitWindow;
-  if (windowed)
-    for (int64_t k = threadIdx.x; k < cnt; k += kEmitThreads) s_off[k] = off[j0 + k];
+  const uint32_t p_end = min(total, p0 + (uint32_t)kEmitTile);
+  for (int i = tid; i < kEmitTile; i += kEmitThreads) s_j[i] = -1;
+  for (int i = tid; i < kDigits; i += kEmitThreads) s_h[i] = 0;
+  const int64_t j0 = block_j0[blockIdx.x];
   __syncthreads();
-  for (int it = 0; it < kEmitItems; ++it) {
-    const uint32_t p = p0 + (uint32_t)(it * kEmitThreads) + threadIdx.x;
-    if (p >= total) break;
-    int64_t lo = 0, hi = cnt;  // last entry of the window with offset <= p
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      const uint32_t o = windowed ? s_off[mid] : off[j0 + mid];
-      if (o <= p) lo = mid; else hi = mid;
+  for (int jb = 0;; jb += kEmitThreads) {
+    const int jl = jb + tid;
+    const int64_t j = j0 + jl;
+    bool in = false;
+    if (j < n) {
+      const uint32_t o = off[j];
+      in = jl == 0 || o < p_end;
+      if (in) {
+        s_j[jl == 0 ? 0 : (int)(o - p0)] = jl;
+        if (jl < kEmitWin) {
+          s_rect[jl] = rect_sorted[j];
+          s_off[jl] = o;
+          s_id[jl] = ids_sorted[j];
+        }
+      }
     }
-    const int64_t j = j0 + lo;
-    const uint32_t l = p - (windowed ? s_off[lo] : off[j]);
-    const int4 r = rect_sorted[j];
-    const uint32_t w = (uint32_t)(r.z - r.x);
-    const uint32_t ty = (uint32_t)r.y + l / w, tx = (uint32_t)r.x + l % w;
-    uint32_t tile = ty * (uint32_t)tiles_x + tx;
-    if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
-    keys[p] = ((K)tile << pbits) | (K)j;
+    if (__syncthreads_count(in) == 0) break;
   }
-}
-
-// ------------------------------------------------------------------ finalize
-template <typename K>
-__global__ void __launch_bounds__(256) finalize_kernel(const K* __restrict__ keys, uint32_t total, int pbits,
-                                                       uint32_t n_t, const uint32_t* __restrict__ perm,
-                                                       const float* __restrict__ depth,
-                                                       uint32_t* __restrict__ vals, uint64_t* __restrict__ keys64,
-                                                       uint2* __restrict__ ranges) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const K key = keys[i];
-  const uint32_t t = (uint32_t)(key >> pbits);
-  if (t >= n_t) return;  // sentinel pairs (tiles outside the valid set) sit at the end
-  const uint32_t g = perm[(uint32_t)(key & (((K)1 << pbits) - 1))];
-  vals[i] = g;
-  if (keys64 != nullptr) keys64[i] = ((uint64_t)t << 32) | (uint64_t)__float_as_uint(depth[g]);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> pbits) != t) ranges[t].x = i;
-  if (i == total - 1 || (uint32_t)(keys[i + 1] >> pbits) != t) ranges[t].y = i + 1;
+  // inclusive max-scan: thread t owns slots [t * kPairItems, (t + 1) * kPairItems)
+  int32_t run = -1;
+#pragma unroll
+  for (int k = 0; k < kPairItems; ++k) run = max(run, s_j[tid * kPairItems + k]);
+  {
+    const int lane = lane_id(), wave = tid / kWave;
+    int32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int32_t t = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl = max(incl, t);
+    }
+    if (lane == kWave - 1) s_red[wave] = incl;
+    __syncthreads();
+    int32_t prev = __shfl_up(incl, 1, kWave);
+    if (lane == 0) prev = -1;
+    for (int w = 0; w < wave; ++w) prev = max(prev, s_red[w]);
+    run = prev;
+  }
+#pragma unroll
+  for (int k = 0; k < kPairItems; ++k) {
+    run = max(run, s_j[tid * kPairItems + k]);
+    s_j[tid * kPairItems + k] = run;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int k = 0; k < kPairItems; ++k) {
+    const int lp = k * kEmitThreads + tid;
+    const uint32_t p = p0 + (uint32_t)lp;
+    if (p < p_end) {
+      const int32_t jl = s_j[lp];
+      int4 r;
+      uint32_t o, g;
+      if (jl < kEmitWin) {
+        r = s_rect[jl];
+        o = s_off[jl];
+        g = s_id[jl];
+      } else {
+        const int64_t j = j0 + jl;
+        r = rect_sorted[j];
+        o = off[j];
+        g = ids_sorted[j];
+      }
+      uint32_t dy, dx;
+      divmod_small(p - o, (uint32_t)(r.z - r.x), dy, dx);
+      uint32_t tile = ((uint32_t)r.y + dy) * (uint32_t)tiles_x + (uint32_t)r.x + dx;
+      if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
+      keys[p] = ((K)tile << id_bits) | (K)g;
+      atomicAdd(&s_h[tile & (kDigits - 1u)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int dg = tid; dg < kDigits; dg += kEmitThreads) hist[(int64_t)dg * nblocks + blockIdx.x] = s_h[dg];
 }
 
 // ------------------------------------------------------------------ workspace
 struct SortWs {
-  unsigned long long* scalars;  // [0] valid pair total
+  unsigned long long* scalars;  // [TGS_COUNTER_SLOTS] partial valid-pair totals
+  int32_t* diff;                // [cells] difference grid, cells = (tiles_y + 1) * (tiles_x + 1)
+  int32_t* partial;             // [kCountBlocks][cells] per-workgroup grids
+  int32_t* block_j0;            // [max_blocks] first Gaussian of each emit block
   int4* rect_sorted;            // [n] rectangles in depth order
   uint32_t* area_sorted;        // [n] pair counts in depth order
   uint32_t* off;                // [n + 1] pair offsets in depth order
   uint32_t* dkeys[2];           // [n] depth keys (ping-pong)
   uint32_t* dvals[2];           // [n] ids
-  uint32_t* partials;           // scan block sums
+  uint32_t* partials;           // scan block sums, digit totals
   uint32_t* hist;               // [256 * max_blocks]
-  uint32_t* hoffs;              // [256 * max_blocks + 1]
+  uint32_t* hoffs;              // [256 * max_blocks]
   void* pkeys[2];               // [capacity] pair keys (u32 or u64), ping-pong
   size_t bytes;
 };
 
-static SortWs layout(void* ws, int64_t n, int64_t capacity) {
+static SortWs layout(void* ws, int64_t n, int64_t capacity, int64_t n_tiles) {
   const int64_t cap = std::max<int64_t>(capacity, 1), nn = std::max<int64_t>(n, 1);
   const int64_t m = std::max(cap, nn);
-  // sort_rounds keeps the grid at <= 2048 workgroups up to 16 x 2048 x 256 keys
-  const int64_t max_blocks = std::max<int64_t>(2048, ceil_div(m, (int64_t)kSortThreads * 16)) + 1;
-  const int64_t hist_n = 256 * (max_blocks + 1);
+  // blocks of any sort of up to m keys: 1024-key blocks below 2^20 keys, 4096-key blocks above
+  const int64_t max_blocks = std::max<int64_t>(1024, sort_blocks(m, kPairItems)) + 1;
+  const int64_t hist_n = 256 * max_blocks;
   const int64_t part_n = std::max<int64_t>(256, scan_partials(nn + 1)) + 1;
+  // (tiles_x + 1)(tiles_y + 1) <= 2 n_tiles + 2 for any grid of n_tiles tiles
+  const int64_t diff_n = 2 * std::max<int64_t>(n_tiles, 1) + 2;
   size_t o = 0;
   char* b = (char*)ws;
   auto take = [&](size_t bytes) {
@@ -425,7 +639,10 @@ static SortWs layout(void* ws, int64_t n, int64_t capacity) {
     return (void*)p;
   };
   SortWs w;
-  w.scalars = (unsigned long long*)take(64);
+  w.scalars = (unsigned long long*)take(sizeof(unsigned long long) * TGS_COUNTER_SLOTS);
+  w.diff = (int32_t*)take(sizeof(int32_t) * diff_n);
+  w.partial = (int32_t*)take(sizeof(int32_t) * diff_n * kCountBlocks);
+  w.block_j0 = (int32_t*)take(sizeof(int32_t) * max_blocks);
   w.rect_sorted = (int4*)take(sizeof(int4) * nn);
   w.area_sorted = (uint32_t*)take(sizeof(uint32_t) * nn);
   w.off = (uint32_t*)take(sizeof(uint32_t) * (nn + 1));
@@ -435,7 +652,7 @@ static SortWs layout(void* ws, int64_t n, int64_t capacity) {
   }
   w.partials = (uint32_t*)take(sizeof(uint32_t) * part_n);
   w.hist = (uint32_t*)take(sizeof(uint32_t) * hist_n);
-  w.hoffs = (uint32_t*)take(sizeof(uint32_t) * (hist_n + 1));
+  w.hoffs = (uint32_t*)take(sizeof(uint32_t) * hist_n);
   for (int k = 0; k < 2; ++k) w.pkeys[k] = take(sizeof(uint64_t) * cap);
   w.bytes = o;
   return w;
@@ -447,19 +664,57 @@ static int bits_for(uint64_t max_value) {  // bits needed to represent 0..max_va
   return b;
 }
 
+// Stable LSD sort of the n depth keys with their ids; returns the buffers
+// holding the sorted keys and ids.
+template <int kItems>
+static void sort_depth(const SortWs& w, uint32_t n, uint32_t** keys_out, uint32_t** ids_out, hipStream_t s) {
+  uint32_t* k[2] = {w.dkeys[0], w.dkeys[1]};
+  uint32_t* v[2] = {w.dvals[0], w.dvals[1]};
+  int cur = 0;
+  for (int p = 0; p < 4; ++p) {
+    const ScatterOut o = {k[cur ^ 1], v[cur ^ 1], 0, nullptr, nullptr};
+    radix_pass<uint32_t, true, false, 8, kItems>(k[cur], v[cur], n, 8 * p, false, w.hist, w.hoffs, w.partials, o, s);
+    cur ^= 1;
+  }
+  *keys_out = k[cur];
+  *ids_out = v[cur];
+}
+
 template <typename K>
-static void sort_pairs(const SortWs& w, const uint32_t* perm, int64_t n, uint32_t total,
-                       const int32_t* tile_slot, int tiles_x, uint32_t n_t, int pbits, int tbits,
-                       const float* depth, uint32_t* vals, uint64_t* keys64, uint32_t* ranges, hipStream_t s) {
-  K* ka = (K*)w.pkeys[0];
-  K* kb = (K*)w.pkeys[1];
-  uint32_t* va = nullptr;
-  uint32_t* vb = nullptr;
-  hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(total, kEmitTile)), dim3(kEmitThreads), 0, s,
-                     w.rect_sorted, w.off, n, total, tile_slot, tiles_x, n_t, pbits, ka);
-  radix_sort<K, false>(ka, va, kb, vb, total, pbits, tbits, w.hist, w.hoffs, w.partials, s);
-  hipLaunchKernelGGL((finalize_kernel<K>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, ka, total,
-                     pbits, n_t, perm, depth, vals, keys64, (uint2*)ranges);
+static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t total, const int32_t* tile_slot,
+                       int tiles_x, uint32_t n_t, int id_bits, int tbits, const float* depth, uint32_t* vals,
+                       uint64_t* keys64, hipStream_t s) {
+  K* kb[2] = {(K*)w.pkeys[0], (K*)w.pkeys[1]};
+  const int nblocks = (int)sort_blocks(total, kPairItems);
+  hipLaunchKernelGGL(block_start_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, w.off, n, w.block_j0);
+  const int passes = pass_count(tbits);
+  const int b0 = pass_bits(tbits, 0);
+  switch (b0) {
+#define TGS_EMIT(B)                                                                                          \
+  case B:                                                                                                    \
+    hipLaunchKernelGGL((emit_kernel<K, B>), dim3(nblocks), dim3(kEmitThreads), 0, s, w.rect_sorted, ids,     \
+                       w.off, w.block_j0, n, total, tile_slot, tiles_x, n_t, id_bits, kb[0], nblocks, w.hist); \
+    break;
+    TGS_EMIT(1) TGS_EMIT(2) TGS_EMIT(3) TGS_EMIT(4) TGS_EMIT(5) TGS_EMIT(6) TGS_EMIT(7)
+    default:
+      hipLaunchKernelGGL((emit_kernel<K, 8>), dim3(nblocks), dim3(kEmitThreads), 0, s, w.rect_sorted, ids, w.off,
+                         w.block_j0, n, total, tile_slot, tiles_x, n_t, id_bits, kb[0], nblocks, w.hist);
+#undef TGS_EMIT
+  }
+  int cur = 0, shift = id_bits;
+  for (int p = 0; p < passes; ++p) {
+    const int b = pass_bits(tbits, p);
+    const bool last = p == passes - 1;
+    const ScatterOut o = {kb[cur ^ 1], vals, id_bits, depth, keys64};
+    if (last)
+      radix_pass_bits<K, false, true, kPairItems>(b, kb[cur], nullptr, total, shift, p == 0, w.hist, w.hoffs,
+                                                  w.partials, o, s);
+    else
+      radix_pass_bits<K, false, false, kPairItems>(b, kb[cur], nullptr, total, shift, p == 0, w.hist, w.hoffs,
+                                                   w.partials, o, s);
+    cur ^= 1;
+    shift += b;
+  }
 }
 
 }  // namespace tgs
@@ -467,9 +722,8 @@ static void sort_pairs(const SortWs& w, const uint32_t* perm, int64_t n, uint32_
 using namespace tgs;
 
 extern "C" size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32_t n_tiles) {
-  (void)n_tiles;
-  if (n < 0 || capacity < 0) return 0;
-  return layout(nullptr, n, capacity).bytes;
+  if (n < 0 || capacity < 0 || n_tiles < 0) return 0;
+  return layout(nullptr, n, capacity, n_tiles).bytes;
 }
 
 extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t n,
@@ -484,36 +738,50 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t
   TGS_REQUIRE(vals && ranges && n_pairs && ws, "tgs_bin_sort: null pointer");  // keys may be null
   TGS_REQUIRE(n == 0 || (rect && depth), "tgs_bin_sort: null rect/depth");
   TGS_REQUIRE(((uintptr_t)rect & 15) == 0, "tgs_bin_sort: rect must be 16-byte aligned");
-  const SortWs w = layout(ws, n, capacity);
-  TGS_REQUIRE(ws_bytes >= w.bytes, "tgs_bin_sort: workspace %zu bytes < %zu", ws_bytes, w.bytes);
-  hipStream_t s = as_stream(stream);
   const uint32_t n_t = (uint32_t)tiles_x * (uint32_t)tiles_y;
-
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t, 256)), dim3(256), 0, s,
-                     ranges, 2 * (int64_t)n_t, 0u);
-  hipLaunchKernelGGL(set_kernel<unsigned long long>, dim3(1), dim3(64), 0, s, w.scalars, 0ull);
+  const SortWs w = layout(ws, n, capacity, n_t);
+  TGS_REQUIRE(ws_bytes >= w.bytes, "tgs_bin_sort: workspace %zu bytes < %zu (is n_tiles right?)", ws_bytes,
+              w.bytes);
+  hipStream_t s = as_stream(stream);
+  const int cells = (tiles_x + 1) * (tiles_y + 1);
+  const bool lds_grid = cells <= kLdsCells;
+  const int count_blocks = lds_grid ? (int)std::min<int64_t>(kCountBlocks, std::max<int64_t>(1, ceil_div(n, kCountThreads)))
+                                    : (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kCountThreads), 1024));
+  if (!lds_grid)  // one grid accumulated with device atomics
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, s,
+                       (uint32_t*)w.partial, (int64_t)cells, 0u);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s, (uint32_t*)w.scalars,
+                     (int64_t)(2 * TGS_COUNTER_SLOTS), 0u);
+  const int n_grids = n == 0 ? 0 : (lds_grid ? count_blocks : 1);
+  if (n > 0)
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)count_blocks), dim3(kCountThreads), 0, s, (const int4*)rect,
+                       depth, n, tile_slot, tiles_x, tiles_y, w.dkeys[0], w.dvals[0], touched, w.partial, lds_grid,
+                       w.scalars);
+  hipLaunchKernelGGL(diff_sum_kernel, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, s, w.partial, n_grids,
+                     cells, w.diff);
+  hipLaunchKernelGGL(ranges_kernel, dim3(1), dim3(kRangeThreads), 0, s, w.diff, tiles_x, tiles_y, tile_slot,
+                     (uint2*)ranges);
   if (n == 0) {
     *n_pairs = 0;
     return hip_status("tgs_bin_sort");
   }
-  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, (const int4*)rect, depth,
-                     n, tile_slot, tiles_x, w.dkeys[0], w.dvals[0], touched, w.scalars);
   // (depth, id) order; culled Gaussians last
-  uint32_t* dk = w.dkeys[0];
-  uint32_t* dv = w.dvals[0];
-  uint32_t* dk2 = w.dkeys[1];
-  uint32_t* dv2 = w.dvals[1];
-  radix_sort<uint32_t, true>(dk, dv, dk2, dv2, (uint32_t)n, 0, 32, w.hist, w.hoffs, w.partials, s);
-  const uint32_t* perm = dv;
+  uint32_t* dk = nullptr;
+  uint32_t* perm = nullptr;
+  if (sort_items(n) == 16) sort_depth<16>(w, (uint32_t)n, &dk, &perm, s);
+  else sort_depth<4>(w, (uint32_t)n, &dk, &perm, s);
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, perm, dk,
-                     (const int4*)rect, n, w.rect_sorted, w.area_sorted);
+                     (const int4*)rect, n, tiles_x, tiles_y, w.rect_sorted, w.area_sorted);
   exclusive_scan<uint32_t>(w.area_sorted, w.off, n, w.partials, s);
   uint32_t total = 0;
-  unsigned long long valid_total = 0;
+  unsigned long long slots[TGS_COUNTER_SLOTS] = {};
   if (hipMemcpyAsync(&total, w.off + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(&valid_total, w.scalars, sizeof(valid_total), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      (tile_slot != nullptr &&
+       hipMemcpyAsync(slots, w.scalars, sizeof(slots), hipMemcpyDeviceToHost, s) != hipSuccess) ||
       hipStreamSynchronize(s) != hipSuccess)
     return hip_status("tgs_bin_sort: count readback");
+  unsigned long long valid_total = 0;
+  for (int k = 0; k < TGS_COUNTER_SLOTS; ++k) valid_total += slots[k];
   if (tile_slot == nullptr) valid_total = total;
   if ((int64_t)total > capacity) {
     *n_pairs = (int64_t)total;
@@ -523,13 +791,11 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t
   *n_pairs = (int64_t)valid_total;
   if (total == 0) return hip_status("tgs_bin_sort");
 
-  const int pbits = std::max(1, bits_for((uint64_t)n - 1));
+  const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
   const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
-  if (pbits + tbits <= 32)
-    sort_pairs<uint32_t>(w, perm, n, total, tile_slot, tiles_x, n_t, pbits, tbits, depth, vals,
-                         keys, ranges, s);
+  if (id_bits + tbits <= 32)
+    sort_pairs<uint32_t>(w, perm, n, total, tile_slot, tiles_x, n_t, id_bits, tbits, depth, vals, keys, s);
   else
-    sort_pairs<uint64_t>(w, perm, n, total, tile_slot, tiles_x, n_t, pbits, tbits, depth, vals,
-                         keys, ranges, s);
+    sort_pairs<uint64_t>(w, perm, n, total, tile_slot, tiles_x, n_t, id_bits, tbits, depth, vals, keys, s);
   return hip_status("tgs_bin_sort");
 }

@@ -188,8 +188,9 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
     ncontrib[px.out] = last;
   }
   if (counters != nullptr && lane_id() == 0) {  // n_eval, n_blend are wave totals
-    atomicAdd(&counters[0], (unsigned long long)n_eval);
-    atomicAdd(&counters[1], (unsigned long long)n_blend);
+    const int cs = blockIdx.x & (TGS_COUNTER_SLOTS - 1);
+    atomicAdd(&counters[cs], (unsigned long long)n_eval);
+    atomicAdd(&counters[TGS_COUNTER_SLOTS + cs], (unsigned long long)n_blend);
   }
 }
 

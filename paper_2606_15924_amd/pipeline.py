@@ -73,7 +73,6 @@ class ViewBuffers:
         self.lam = torch.empty(max(self.n_st, 1), dtype=torch.float32, device=dev)
         self.tile_loss = torch.zeros((max(self.n_st, 1), 2), dtype=torch.float32, device=dev)
         self.g2d = torch.empty((n, B.G2D_FLOATS), dtype=torch.float32, device=dev)
-        self.counters = torch.zeros(2, dtype=torch.int64, device=dev)
         self._alloc_pairs(capacity if capacity is not None else max(1 << 16, 8 * n))
 
     def _alloc_pairs(self, capacity: int):
@@ -151,7 +150,7 @@ class Trainer:
         self.totals = torch.zeros(2, dtype=torch.int64, device=self.dev)
         self.step_count = 0
         self._bufs: dict = {}
-        self.counters = torch.zeros(2, dtype=torch.int64, device=self.dev)
+        self.counters = torch.zeros((2, B.COUNTER_SLOTS), dtype=torch.int64, device=self.dev)
         self.events: dict | None = None   # stage name -> [(start, end)] when timing
 
     @contextlib.contextmanager

@@ -211,7 +211,7 @@ def _gpu_render(B, rec, sv, ranges, cam, s, rp, n_pix):
         n_st, mpt = s["valid_tiles"].size, n_pix
     out = torch.empty((max(P, 1), 4), dtype=torch.float32, device="cuda")
     nc = torch.empty(max(P, 1), dtype=torch.int32, device="cuda")
-    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros((2, B.COUNTER_SLOTS), dtype=torch.int64, device="cuda")
     B.tgs_render_fwd(splat, V, R, TX, TY, cam.width, cam.height, vt, off, pix, n_st, mpt, rp, out, nc, cnt)
     return out, nc, cnt, (splat, V, R, vt, off, pix, n_st, mpt, TX, TY)
 
@@ -233,7 +233,7 @@ def test_render_fwd_parity(B, case, bg):
     ref = render.render_pixels(q, sv, ranges, xs, ys, rp)
     n_pix = 256 if s is None else max(int(np.diff(s["tile_off"]).max()), 1)
     out, nc, cnt, _ = _gpu_render(B, rec, sv, ranges, cam, s, B.raster_params(bg=bg), n_pix)
-    o, c, k = host(out)[: xs.size], host(nc)[: xs.size], host(cnt)
+    o, c, k = host(out)[: xs.size], host(nc)[: xs.size], host(cnt).sum(axis=1)
     ok = ~ref["flag"]
     assert ok.mean() > 0.995, ok.mean()
     assert_close(o[ok, :3], ref["rgb"][ok], 1e-5, 1e-7, "rgb")
