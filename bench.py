@@ -94,10 +94,15 @@ def run(tr, steps, warmup):
                 n_pairs=int(vb.n_pairs), pixels=pixels)
 
 
-def cpu_baseline(p, cam, gt, n_tiles=48):
-    """The oracle's sparse step on ``n_tiles`` of the view's tiles at the
-    headline rate: sample, project, bin/sort, forward, loss, backward and
-    projection backward (every Gaussian), optimizer.  Returns blends/s."""
+def cpu_baseline(p, cam, gt, n_tiles=384):
+    """The oracle's sparse step, timed on one host thread: the parts whose
+    cost scales with the sampled tiles (sampling, binning, forward, loss,
+    backward) on ``n_tiles`` random tiles at the headline rate, the parts
+    over every Gaussian (projection, projection backward, optimizer) whole.
+    The whole-view step time is extrapolated as fixed + per-tile x n_t /
+    n_tiles, and so are its blends; returns blends/s of that step."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import binning, loss, project, project_bwd, render, sampler, optim
     from oracle.params import OptimParams, RasterParams, SampleParams
     import synth
@@ -105,24 +110,35 @@ def cpu_baseline(p, cam, gt, n_tiles=48):
     E = synth.error_map(HEIGHT, WIDTH, 31)
     A = np.zeros((HEIGHT, WIDTH), dtype=np.uint16)
     TX, TY = (WIDTH + 15) // 16, (HEIGHT + 15) // 16
-    tiles = np.sort(np.random.default_rng(0).choice(TX * TY, n_tiles, replace=False))
-    t0 = time.perf_counter()
-    s = sampler.sample_view(E, A, SampleParams(n_pix=64), 3, 1, 0, tiles_subset=tiles)
-    pr = project.project(p, cam, rp)
-    _, sv, ranges = binning.bin_and_sort(pr, s["valid_tiles"])
-    xs, ys, _ = sampler.sample_coords(s, WIDTH, HEIGHT)
-    out = render.render_pixels(pr, sv, ranges, xs, ys, rp)
-    ls = loss.sparse_loss(out["rgb"], gt[:, ys, xs].T, s["tile_off"], xs.size, s["valid_tiles"].size)
-    g2d = render.render_pixels_bwd(pr, sv, ranges, xs, ys, ls["dL"], rp)
-    grad = project_bwd.project_bwd(p, cam, pr, g2d, rp)
-    touched = np.zeros(p.shape[1], dtype=bool)
-    touched[np.unique(sv)] = True
-    optim.optimizer_step(p, grad, np.zeros_like(grad), np.zeros_like(grad), touched, OptimParams(), 1)
-    dt = time.perf_counter() - t0
+    n_t = TX * TY
+    tiles = np.sort(np.random.default_rng(0).choice(n_t, n_tiles, replace=False))
+    with threadpool_limits(1):
+        c0 = time.perf_counter()
+        pr = project.project(p, cam, rp)
+        c1 = time.perf_counter()
+        s = sampler.sample_view(E, A, SampleParams(n_pix=64), 3, 1, 0, tiles_subset=tiles)
+        _, sv, ranges = binning.bin_and_sort(pr, s["valid_tiles"])
+        xs, ys, _ = sampler.sample_coords(s, WIDTH, HEIGHT)
+        out = render.render_pixels(pr, sv, ranges, xs, ys, rp)
+        ls = loss.sparse_loss(out["rgb"], gt[:, ys, xs].T, s["tile_off"], xs.size, s["valid_tiles"].size)
+        g2d = render.render_pixels_bwd(pr, sv, ranges, xs, ys, ls["dL"], rp)
+        c2 = time.perf_counter()
+        grad = project_bwd.project_bwd(p, cam, pr, g2d, rp)
+        touched = np.zeros(p.shape[1], dtype=bool)
+        touched[np.unique(sv)] = True
+        optim.optimizer_step(p, grad, np.zeros_like(grad), np.zeros_like(grad), touched, OptimParams(), 1)
+        c3 = time.perf_counter()
+    fixed = (c1 - c0) + (c3 - c2)
+    per_tile = (c2 - c1) / n_tiles
+    step_s = fixed + per_tile * n_t
     blends = int(out["n_blend"].sum())
-    return dict(value=blends / dt, unit="blends/s", cores=1, kind="oracle",
-                sample=f"{n_tiles} of {TX * TY} tiles at 25% ({xs.size} pixels, {blends} blends), "
-                       f"full projection/backward of {p.shape[1]} Gaussians; {dt:.1f} s")
+    blends_step = blends * n_t / n_tiles
+    return dict(value=blends_step / step_s, unit="blends/s", cores=1, kind="oracle",
+                step_s_extrapolated=round(step_s, 2),
+                sample=f"{n_tiles} of {n_t} random tiles at 25% ({xs.size} pixels, {blends} blends) plus "
+                       f"projection, projection backward and optimizer over all {p.shape[1]} Gaussians; "
+                       f"{c3 - c0:.1f} s measured ({fixed:.1f} s whole-model, {per_tile * 1e3:.1f} ms per tile), "
+                       f"whole-view step extrapolated to {step_s:.1f} s")
 
 
 def main():

@@ -230,12 +230,15 @@ int32_t tgs_ema_age_update(uint16_t* E, uint16_t* A, int32_t height, int32_t wid
 int32_t tgs_error_init(const float* out_dense, const float* gt, int32_t height, int32_t width,
                        uint16_t* E, void* stream);
 
-/* Chain rule from g2d to the Gaussian parameters (backward of tgs_project),
- * accumulated into grad[59][n] (+=).  Culled Gaussians (radius 0) are left
- * untouched.  clamp: the tgs_project output. */
+/* Chain rule from g2d to the Gaussian parameters (backward of tgs_project).
+ *   accumulate  1: grad[59][n] += gradient; culled Gaussians (radius 0) are
+ *               left untouched.  0: grad = gradient, every entry written
+ *               (zeros for culled Gaussians), so grad needs no clearing.
+ *   clamp       the tgs_project output. */
 int32_t tgs_project_bwd(const float* params, int64_t n, const tgs_camera* cam,
                         const tgs_raster_params* rp, const int32_t* radius,
-                        const uint8_t* clamp, const float* g2d, float* grad, void* stream);
+                        const uint8_t* clamp, const float* g2d, float* grad, int32_t accumulate,
+                        void* stream);
 
 /* Hybrid moment-damped LM / Adam update (Sec. 3.9, Eq. moment_damped_lm, and
  * the appendix optimizer details): per touched Gaussian, Adam moments for all

@@ -59,8 +59,8 @@ class SparseRasterize(torch.autograd.Function):
         dL[: vb.P, :3] = grad_out
         vb.dL = dL
         vb.render_bwd(ctx.rp)
-        grad = torch.zeros_like(params)
-        vb.project_bwd(params, ctx.cam, ctx.rp, grad)
+        grad = torch.empty_like(params)
+        vb.project_bwd(params, ctx.cam, ctx.rp, grad, accumulate=False)
         return grad, None, None, None
 
 

@@ -89,7 +89,7 @@ PROTOTYPES = {
     "tgs_ema_age_update": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _P, ctypes.c_float, _P]),
     "tgs_error_init": (_I32, [_P, _P, _I32, _I32, _P, _P]),
     "tgs_project_bwd": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
-                               _P, _P, _P, _P, _P]),
+                               _P, _P, _P, _P, _I32, _P]),
     "tgs_optimizer_step": (_I32, [_P, _P, _P, _P, _I64, _P, ctypes.POINTER(tgs_optim_params), _I64, _P]),
 }
 
@@ -259,9 +259,11 @@ def tgs_error_init(out_dense, gt, height, width, E):
            "tgs_error_init")
 
 
-def tgs_project_bwd(params, n, cam: tgs_camera, rp: tgs_raster_params, radius, clamp, g2d, grad):
+def tgs_project_bwd(params, n, cam: tgs_camera, rp: tgs_raster_params, radius, clamp, g2d, grad,
+                    accumulate: bool = True):
     _check(lib().tgs_project_bwd(_ptr(params), n, ctypes.byref(cam), ctypes.byref(rp), _ptr(radius),
-                                 _ptr(clamp), _ptr(g2d), _ptr(grad), _stream()), "tgs_project_bwd")
+                                 _ptr(clamp), _ptr(g2d), _ptr(grad), int(bool(accumulate)), _stream()),
+           "tgs_project_bwd")
 
 
 def tgs_optimizer_step(params, grad, m, v, n, touched, op: tgs_optim_params, step):

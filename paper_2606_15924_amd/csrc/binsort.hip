@@ -195,14 +195,27 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(const int4* __rest
   }
 }
 
-// diff[c] = sum over the partial grids of cell c.
-__global__ void __launch_bounds__(256) diff_sum_kernel(const int32_t* __restrict__ partial, int n_grids,
-                                                       int cells, int32_t* __restrict__ diff) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= cells) return;
-  int32_t s = 0;
-  for (int b = 0; b < n_grids; ++b) s += partial[(int64_t)b * cells + c];
-  diff[c] = s;
+// diff[c] = sum over the partial grids of cell c: 64 cells per workgroup
+// (a lane each), its 8 waves take every 8th grid, then LDS combines them.
+constexpr int kSumWaves = 8;
+
+__global__ void __launch_bounds__(kSumWaves * kWave) diff_sum_kernel(const int32_t* __restrict__ partial,
+                                                                     int n_grids, int cells,
+                                                                     int32_t* __restrict__ diff) {
+  __shared__ int32_t s_part[kSumWaves][kWave];
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  const int c = blockIdx.x * kWave + lane;
+  int32_t acc = 0;
+  if (c < cells)
+    for (int b = wave; b < n_grids; b += kSumWaves) acc += partial[(int64_t)b * cells + c];
+  s_part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && c < cells) {
+    int32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kSumWaves; ++w) t += s_part[w][lane];
+    diff[c] = t;
+  }
 }
 
 // Rectangles and pair counts in depth order (a Gaussian without a valid tile
@@ -239,17 +252,24 @@ __global__ void __launch_bounds__(kRangeThreads) ranges_kernel(int32_t* __restri
     for (int c = threadIdx.x; c < cells; c += kRangeThreads) s_grid[c] = diff[c];
     __syncthreads();
   }
-  for (int y = threadIdx.x; y < tiles_y; y += kRangeThreads) {
+  // rows: one wave per row, 64 columns per step with a wave scan
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  for (int y = wave; y < tiles_y; y += kRangeThreads / kWave) {
     int32_t* row = g + (int64_t)y * gw;
-    int32_t acc = 0;
-    for (int x = 0; x < tiles_x; ++x) {
-      acc += row[x];
-      row[x] = acc;
+    int32_t carry = 0;
+    for (int x0 = 0; x0 < tiles_x; x0 += kWave) {
+      const int x = x0 + lane;
+      const int32_t v = x < tiles_x ? row[x] : 0;
+      const int32_t incl = wave_inclusive_scan_i(v) + carry;
+      if (x < tiles_x) row[x] = incl;
+      carry = __shfl(incl, kWave - 1, kWave);
     }
   }
   __syncthreads();
+  // columns: a thread per column
   for (int x = threadIdx.x; x < tiles_x; x += kRangeThreads) {
     int32_t acc = 0;
+#pragma unroll 8
     for (int y = 0; y < tiles_y; ++y) {
       acc += g[(int64_t)y * gw + x];
       g[(int64_t)y * gw + x] = acc;
@@ -757,8 +777,8 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t
     hipLaunchKernelGGL(count_kernel, dim3((unsigned)count_blocks), dim3(kCountThreads), 0, s, (const int4*)rect,
                        depth, n, tile_slot, tiles_x, tiles_y, w.dkeys[0], w.dvals[0], touched, w.partial, lds_grid,
                        w.scalars);
-  hipLaunchKernelGGL(diff_sum_kernel, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, s, w.partial, n_grids,
-                     cells, w.diff);
+  hipLaunchKernelGGL(diff_sum_kernel, dim3((unsigned)ceil_div(cells, kWave)), dim3(kSumWaves * kWave), 0, s,
+                     w.partial, n_grids, cells, w.diff);
   hipLaunchKernelGGL(ranges_kernel, dim3(1), dim3(kRangeThreads), 0, s, w.diff, tiles_x, tiles_y, tile_slot,
                      (uint2*)ranges);
   if (n == 0) {

@@ -4,8 +4,7 @@
 // and writes params, m, v.  Two launches split the rows by their kind of
 // work so each runs at its own occupancy:
 //   lm_kernel     one thread per Gaussian, the two LM blocks (rows 0-13):
-//                 10x10 and 4x4 systems assembled and solved by Cholesky in
-//                 FP64 registers (register-heavy, few waves)
+//                 10x10 and 4x4 damped systems solved exactly in FP64
 //   adam_kernel   the plain Adam rows (14-58, or all rows in Adam mode): a
 //                 row per grid line, four consecutive Gaussians per thread
 //                 with 16-byte loads when the row length allows
@@ -30,59 +29,17 @@ __device__ __forceinline__ double row_lr(const OptArgs& o, int row) {
   return o.lr[5];
 }
 
-// Solve (g g^T + diag(d)) x = -m (mode 0) or (diag(g^2 + d)) x = -m (mode 1)
-// for one block of K rows; Cholesky factorisation in place (lower triangle).
-template <int K>
-__device__ __forceinline__ void lm_solve(const double* g, const double* m, const double* d, int mode,
-                                         double* x) {
-  if (mode == 1) {
-    for (int i = 0; i < K; ++i) x[i] = -m[i] / (g[i] * g[i] + d[i]);
-    return;
-  }
-  double L[K * (K + 1) / 2];
-#define LIDX(i, j) ((i) * ((i) + 1) / 2 + (j))
-#pragma unroll
-  for (int i = 0; i < K; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) L[LIDX(i, j)] = g[i] * g[j] + (i == j ? d[i] : 0.0);
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    double s = L[LIDX(j, j)];
-#pragma unroll
-    for (int k = 0; k < j; ++k) s -= L[LIDX(j, k)] * L[LIDX(j, k)];
-    const double ljj = sqrt(s);
-    L[LIDX(j, j)] = ljj;
-#pragma unroll
-    for (int i = j + 1; i < K; ++i) {
-      double t = L[LIDX(i, j)];
-#pragma unroll
-      for (int k = 0; k < j; ++k) t -= L[LIDX(i, k)] * L[LIDX(j, k)];
-      L[LIDX(i, j)] = t / ljj;
-    }
-  }
-  double y[K];
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    double t = -m[i];
-#pragma unroll
-    for (int k = 0; k < i; ++k) t -= L[LIDX(i, k)] * y[k];
-    y[i] = t / L[LIDX(i, i)];
-  }
-#pragma unroll
-  for (int i = K - 1; i >= 0; --i) {
-    double t = y[i];
-#pragma unroll
-    for (int k = i + 1; k < K; ++k) t -= L[LIDX(k, i)] * x[k];
-    x[i] = t / L[LIDX(i, i)];
-  }
-#undef LIDX
-}
-
+// Solve (g g^T + diag(d)) x = -m (mode 0) or diag(g^2 + d) x = -m (mode 1)
+// for one block of K rows.  The mode-0 matrix is diagonal plus rank one, so
+// its inverse follows the Sherman-Morrison identity:
+//   x = -(D^-1 m - D^-1 g (g^T D^-1 m) / (1 + g^T D^-1 g)),
+// an exact solve in K divisions and two dot products (no K x K factor in
+// registers).  d >= eps > 0 keeps D invertible and 1 + g^T D^-1 g >= 1.
 template <int K>
 __device__ __forceinline__ void lm_block(float* __restrict__ p, const float* __restrict__ grad,
                                          float* __restrict__ m, float* __restrict__ v, int64_t n,
                                          int64_t i, const int (&rows)[K], const OptArgs& o) {
-  double g[K], mm[K], d[K], x[K];
+  double g[K], mm[K], d[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int64_t idx = (int64_t)rows[k] * n + i;
@@ -93,7 +50,22 @@ __device__ __forceinline__ void lm_block(float* __restrict__ p, const float* __r
     m[idx] = (float)mm[k];
     v[idx] = (float)vv;
   }
-  lm_solve<K>(g, mm, d, o.lm_mode, x);
+  double x[K];
+  if (o.lm_mode == 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = -mm[k] / (g[k] * g[k] + d[k]);
+  } else {
+    double s = 0.0, t = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      d[k] = 1.0 / d[k];
+      s += g[k] * g[k] * d[k];
+      t += g[k] * mm[k] * d[k];
+    }
+    const double c = t / (1.0 + s);
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = (g[k] * c - mm[k]) * d[k];
+  }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int64_t idx = (int64_t)rows[k] * n + i;

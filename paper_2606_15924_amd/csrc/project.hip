@@ -55,51 +55,54 @@ constexpr double kC3c = 0.4570457994644658;    // sqrt(21/(32 pi))
 constexpr double kC3d = 0.3731763325901154;    // sqrt(7/(16 pi))
 constexpr double kC3e = 1.445305721320277;     // sqrt(105/(16 pi))
 
-__device__ __forceinline__ void sh_eval(double x, double y, double z, double Y[16]) {
+// Term k of the basis: Y_k and its gradient with respect to (x, y, z).
+// With k a constant (an unrolled loop) only that term is computed, so no
+// arrays of the basis are kept.
+__device__ __forceinline__ void sh_term(int k, double x, double y, double z, double& Y, double& gx,
+                                        double& gy, double& gz) {
   const double xx = x * x, yy = y * y, zz = z * z;
-  Y[0] = kC0;
-  Y[1] = -kC1 * y;
-  Y[2] = kC1 * z;
-  Y[3] = -kC1 * x;
-  Y[4] = kC2a * x * y;
-  Y[5] = -kC2a * y * z;
-  Y[6] = kC2b * (2.0 * zz - xx - yy);
-  Y[7] = -kC2a * x * z;
-  Y[8] = kC2c * (xx - yy);
-  Y[9] = -kC3a * y * (3.0 * xx - yy);
-  Y[10] = kC3b * x * y * z;
-  Y[11] = -kC3c * y * (4.0 * zz - xx - yy);
-  Y[12] = kC3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-  Y[13] = -kC3c * x * (4.0 * zz - xx - yy);
-  Y[14] = kC3e * z * (xx - yy);
-  Y[15] = -kC3a * x * (xx - 3.0 * yy);
-}
-
-// Gradient of each polynomial above with respect to (x, y, z).
-__device__ __forceinline__ void sh_grad(double x, double y, double z, double dY[16][3]) {
-  const double xx = x * x, yy = y * y, zz = z * z;
-  dY[0][0] = 0; dY[0][1] = 0; dY[0][2] = 0;
-  dY[1][0] = 0; dY[1][1] = -kC1; dY[1][2] = 0;
-  dY[2][0] = 0; dY[2][1] = 0; dY[2][2] = kC1;
-  dY[3][0] = -kC1; dY[3][1] = 0; dY[3][2] = 0;
-  dY[4][0] = kC2a * y; dY[4][1] = kC2a * x; dY[4][2] = 0;
-  dY[5][0] = 0; dY[5][1] = -kC2a * z; dY[5][2] = -kC2a * y;
-  dY[6][0] = -2.0 * kC2b * x; dY[6][1] = -2.0 * kC2b * y; dY[6][2] = 4.0 * kC2b * z;
-  dY[7][0] = -kC2a * z; dY[7][1] = 0; dY[7][2] = -kC2a * x;
-  dY[8][0] = 2.0 * kC2c * x; dY[8][1] = -2.0 * kC2c * y; dY[8][2] = 0;
-  dY[9][0] = -kC3a * 6.0 * x * y; dY[9][1] = -kC3a * (3.0 * xx - 3.0 * yy); dY[9][2] = 0;
-  dY[10][0] = kC3b * y * z; dY[10][1] = kC3b * x * z; dY[10][2] = kC3b * x * y;
-  dY[11][0] = -kC3c * (-2.0 * x * y);
-  dY[11][1] = -kC3c * (4.0 * zz - xx - 3.0 * yy);
-  dY[11][2] = -kC3c * (8.0 * y * z);
-  dY[12][0] = kC3d * (-6.0 * x * z);
-  dY[12][1] = kC3d * (-6.0 * y * z);
-  dY[12][2] = kC3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
-  dY[13][0] = -kC3c * (4.0 * zz - 3.0 * xx - yy);
-  dY[13][1] = -kC3c * (-2.0 * x * y);
-  dY[13][2] = -kC3c * (8.0 * x * z);
-  dY[14][0] = kC3e * 2.0 * x * z; dY[14][1] = -kC3e * 2.0 * y * z; dY[14][2] = kC3e * (xx - yy);
-  dY[15][0] = -kC3a * (3.0 * xx - 3.0 * yy); dY[15][1] = -kC3a * (-6.0 * x * y); dY[15][2] = 0;
+  switch (k) {
+    case 0: Y = kC0; gx = 0; gy = 0; gz = 0; break;
+    case 1: Y = -kC1 * y; gx = 0; gy = -kC1; gz = 0; break;
+    case 2: Y = kC1 * z; gx = 0; gy = 0; gz = kC1; break;
+    case 3: Y = -kC1 * x; gx = -kC1; gy = 0; gz = 0; break;
+    case 4: Y = kC2a * x * y; gx = kC2a * y; gy = kC2a * x; gz = 0; break;
+    case 5: Y = -kC2a * y * z; gx = 0; gy = -kC2a * z; gz = -kC2a * y; break;
+    case 6:
+      Y = kC2b * (2.0 * zz - xx - yy);
+      gx = -2.0 * kC2b * x; gy = -2.0 * kC2b * y; gz = 4.0 * kC2b * z;
+      break;
+    case 7: Y = -kC2a * x * z; gx = -kC2a * z; gy = 0; gz = -kC2a * x; break;
+    case 8: Y = kC2c * (xx - yy); gx = 2.0 * kC2c * x; gy = -2.0 * kC2c * y; gz = 0; break;
+    case 9:
+      Y = -kC3a * y * (3.0 * xx - yy);
+      gx = -kC3a * 6.0 * x * y; gy = -kC3a * (3.0 * xx - 3.0 * yy); gz = 0;
+      break;
+    case 10:
+      Y = kC3b * x * y * z;
+      gx = kC3b * y * z; gy = kC3b * x * z; gz = kC3b * x * y;
+      break;
+    case 11:
+      Y = -kC3c * y * (4.0 * zz - xx - yy);
+      gx = -kC3c * (-2.0 * x * y); gy = -kC3c * (4.0 * zz - xx - 3.0 * yy); gz = -kC3c * (8.0 * y * z);
+      break;
+    case 12:
+      Y = kC3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+      gx = kC3d * (-6.0 * x * z); gy = kC3d * (-6.0 * y * z); gz = kC3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+      break;
+    case 13:
+      Y = -kC3c * x * (4.0 * zz - xx - yy);
+      gx = -kC3c * (4.0 * zz - 3.0 * xx - yy); gy = -kC3c * (-2.0 * x * y); gz = -kC3c * (8.0 * x * z);
+      break;
+    case 14:
+      Y = kC3e * z * (xx - yy);
+      gx = kC3e * 2.0 * x * z; gy = -kC3e * 2.0 * y * z; gz = kC3e * (xx - yy);
+      break;
+    default:
+      Y = -kC3a * x * (xx - 3.0 * yy);
+      gx = -kC3a * (3.0 * xx - 3.0 * yy); gy = -kC3a * (-6.0 * x * y); gz = 0;
+      break;
+  }
 }
 
 __device__ __forceinline__ int n_sh(int degree) { return (degree + 1) * (degree + 1); }
@@ -212,12 +215,17 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
   const double dx = g.mu[0] - cam.center[0], dy = g.mu[1] - cam.center[1],
                dz = g.mu[2] - cam.center[2];
   const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-  double Y[16];
-  sh_eval(dx / dn, dy / dn, dz / dn, Y);
+  const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
   const int nk = n_sh(sh_degree);
   double rgb[3] = {0.5, 0.5, 0.5};
-  for (int k = 0; k < nk; ++k)
-    for (int ch = 0; ch < 3; ++ch) rgb[ch] += Y[k] * (double)params[(int64_t)(11 + 3 * k + ch) * n + i];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k < nk) {
+      double Yk, g0, g1, g2;
+      sh_term(k, ux, uy, uz, Yk, g0, g1, g2);
+      for (int ch = 0; ch < 3; ++ch) rgb[ch] += Yk * (double)params[(int64_t)(11 + 3 * k + ch) * n + i];
+    }
+  }
   uint8_t cm = 0;
   for (int ch = 0; ch < 3; ++ch)
     if (rgb[ch] < 0.0) {
@@ -235,12 +243,20 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
   clampm[i] = cm;
 }
 
+// accumulate: grad += gradient; otherwise grad = gradient, with zeros for
+// culled Gaussians (every row of every Gaussian is written once).
 __global__ void __launch_bounds__(256) project_bwd_kernel(
     const float* __restrict__ params, int64_t n, CamArgs cam, int sh_degree, double z_near,
     double dil, const int* __restrict__ radius, const uint8_t* __restrict__ clampm,
-    const float* __restrict__ g2d, float* __restrict__ grad) {
+    const float* __restrict__ g2d, float* __restrict__ grad, bool accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || radius[i] == 0) return;
+  if (i >= n) return;
+  if (radius[i] == 0) {
+    if (!accumulate)
+      for (int r = 0; r < TGS_PARAM_ROWS; ++r) grad[(int64_t)r * n + i] = 0.f;
+    return;
+  }
+  auto put = [&](int64_t idx, double v) { grad[idx] = accumulate ? grad[idx] + (float)v : (float)v; };
   Geom g;
   geometry(params, n, i, cam, z_near, dil, g);
   double gg[9];
@@ -254,19 +270,26 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
   const double vx = g.mu[0] - cam.center[0], vy = g.mu[1] - cam.center[1], vz = g.mu[2] - cam.center[2];
   const double dn = sqrt(vx * vx + vy * vy + vz * vz);
   const double ux = vx / dn, uy = vy / dn, uz = vz / dn;
-  double Y[16], dY[16][3];
-  sh_eval(ux, uy, uz, Y);
-  sh_grad(ux, uy, uz, dY);
   const int nk = n_sh(sh_degree);
   double dL_du[3] = {0.0, 0.0, 0.0};
-  for (int k = 0; k < nk; ++k) {
-    double gk = 0.0;
-    for (int ch = 0; ch < 3; ++ch) {
-      const int64_t row = (int64_t)(11 + 3 * k + ch) * n + i;
-      grad[row] += (float)(Y[k] * drgb[ch]);
-      gk += (double)params[row] * drgb[ch];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t row0 = (int64_t)(11 + 3 * k) * n + i;
+    if (k < nk) {
+      double Yk, d0, d1, d2;
+      sh_term(k, ux, uy, uz, Yk, d0, d1, d2);
+      double gk = 0.0;
+      for (int ch = 0; ch < 3; ++ch) {
+        const int64_t row = row0 + (int64_t)ch * n;
+        put(row, Yk * drgb[ch]);
+        gk += (double)params[row] * drgb[ch];
+      }
+      dL_du[0] += d0 * gk;
+      dL_du[1] += d1 * gk;
+      dL_du[2] += d2 * gk;
+    } else if (!accumulate) {
+      for (int ch = 0; ch < 3; ++ch) grad[row0 + (int64_t)ch * n] = 0.f;
     }
-    for (int a = 0; a < 3; ++a) dL_du[a] += dY[k][a] * gk;
   }
   // d Y(v/|v|) / dv = (I - u u^T) grad Y(u) / |v|
   const double udot = ux * dL_du[0] + uy * dL_du[1] + uz * dL_du[2];
@@ -275,7 +298,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
 
   // ---- opacity
   const double o = 1.0 / (1.0 + exp(-(double)params[10 * n + i]));
-  grad[10 * n + i] += (float)(gg[5] * o * (1.0 - o));
+  put(10 * n + i, gg[5] * o * (1.0 - o));
 
   // ---- centre
   const double tz2 = tz * tz, tz3 = tz2 * tz;
@@ -324,7 +347,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
   double dR[3][3];
   for (int k = 0; k < 3; ++k) {
     const double ds = g.Rq[0][k] * dM[0][k] + g.Rq[1][k] * dM[1][k] + g.Rq[2][k] * dM[2][k];
-    grad[(int64_t)(3 + k) * n + i] += (float)(ds * g.s[k]);
+    put((int64_t)(3 + k) * n + i, ds * g.s[k]);
     for (int r = 0; r < 3; ++r) dR[r][k] = dM[r][k] * g.s[k];
   }
   const double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
@@ -338,11 +361,11 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
   dq[3] = 2.0 * (-2.0 * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.0 * z * dR[1][1] +
                  y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
   const double qdot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-  grad[6 * n + i] += (float)((dq[0] - w * qdot) / g.qnorm);
-  grad[7 * n + i] += (float)((dq[1] - x * qdot) / g.qnorm);
-  grad[8 * n + i] += (float)((dq[2] - y * qdot) / g.qnorm);
-  grad[9 * n + i] += (float)((dq[3] - z * qdot) / g.qnorm);
-  for (int k = 0; k < 3; ++k) grad[(int64_t)k * n + i] += (float)dmu[k];
+  put(6 * n + i, (dq[0] - w * qdot) / g.qnorm);
+  put(7 * n + i, (dq[1] - x * qdot) / g.qnorm);
+  put(8 * n + i, (dq[2] - y * qdot) / g.qnorm);
+  put(9 * n + i, (dq[3] - z * qdot) / g.qnorm);
+  for (int k = 0; k < 3; ++k) put((int64_t)k * n + i, dmu[k]);
 }
 
 }  // namespace tgs
@@ -377,7 +400,7 @@ extern "C" int32_t tgs_project(const float* params, int64_t n, const tgs_camera*
 extern "C" int32_t tgs_project_bwd(const float* params, int64_t n, const tgs_camera* cam,
                                    const tgs_raster_params* rp, const int32_t* radius,
                                    const uint8_t* clamp, const float* g2d, float* grad,
-                                   void* stream) {
+                                   int32_t accumulate, void* stream) {
   TGS_REQUIRE(n >= 0, "tgs_project_bwd: n < 0");
   TGS_REQUIRE(cam != nullptr && cam->width > 0 && cam->height > 0, "tgs_project_bwd: bad camera");
   if (int32_t e = check_raster_params(rp)) return e;
@@ -387,6 +410,6 @@ extern "C" int32_t tgs_project_bwd(const float* params, int64_t n, const tgs_cam
   const int block = 256;
   hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)ceil_div(n, block)), dim3(block), 0,
                      as_stream(stream), params, n, ca, rp->sh_degree, (double)rp->z_near,
-                     (double)rp->dilation, radius, clamp, g2d, grad);
+                     (double)rp->dilation, radius, clamp, g2d, grad, accumulate != 0);
   return hip_status("tgs_project_bwd");
 }

@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
       for (int u = 0; u < kUnroll; ++u) {
         const float t_next = one_minus_times(T, al[u]);
         bool ok = !done && pw[u] <= 0.f && al[u] >= amin;
-        if (j + u < cnt) n_eval += (uint32_t)__popcll(__ballot(!done));
+        n_eval += j + u < cnt ? (uint32_t)__popcll(__ballot(!done)) : 0u;  // uniform select
         const bool stop = ok && t_next < tmin;
         done = done || stop;
         ok = ok && !stop;
@@ -303,31 +303,36 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
         if (j + u >= cnt) break;  // uniform
         const float4 ap = s_app[j + u];
         const float4 cn = s_con[j + u];
-        const float alpha = al[u], G = Gv[u], dx = dxv[u], dy = dyv[u];
+        const float alpha = al[u];
         const bool ok = !done && pw[u] <= 0.f && alpha >= amin;
         const float w = ok ? alpha * T : 0.f;
         acc0 = __builtin_fmaf(w, ap.z, acc0);
         acc1 = __builtin_fmaf(w, ap.w, acc1);
         acc2 = __builtin_fmaf(w, cn.w, acc2);
-        const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
-        const float dalpha = g0 * (T * ap.z - (Cout0 - acc0) * inv) + g1 * (T * ap.w - (Cout1 - acc1) * inv) +
-                             g2 * (T * cn.w - (Cout2 - acc2) * inv);
-        const bool unclamped = ok && ap.y * G < amax;
-        const float dop = unclamped ? G * dalpha : 0.f;
-        const float dpow = ap.y * dop;
-        float v[9];
-        v[0] = (cn.x * dx + cn.y * dy) * dpow;
-        v[1] = (cn.y * dx + cn.z * dy) * dpow;
-        v[2] = -0.5f * dx * dx * dpow;
-        v[3] = -dx * dy * dpow;
-        v[4] = -0.5f * dy * dy * dpow;
-        v[5] = dop;
-        v[6] = w * g0;
-        v[7] = w * g1;
-        v[8] = w * g2;
+        const float T_before = T;
         T = ok ? one_minus_times(T, alpha) : T;
         done = done || (pos0 + (uint32_t)(j + u) + 1u >= last);
-        if (__ballot(ok) != 0ull) wave_sum9_atomic(v, &g2d[(int64_t)s_gid[j + u] * 9]);
+        if (__ballot(ok) != 0ull) {  // the gradient terms only where some lane composited
+          const float G = Gv[u], dx = dxv[u], dy = dyv[u];
+          const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+          const float dalpha = g0 * (T_before * ap.z - (Cout0 - acc0) * inv) +
+                               g1 * (T_before * ap.w - (Cout1 - acc1) * inv) +
+                               g2 * (T_before * cn.w - (Cout2 - acc2) * inv);
+          const bool unclamped = ok && ap.y * G < amax;
+          const float dop = unclamped ? G * dalpha : 0.f;
+          const float dpow = ap.y * dop;
+          float v[9];
+          v[0] = (cn.x * dx + cn.y * dy) * dpow;
+          v[1] = (cn.y * dx + cn.z * dy) * dpow;
+          v[2] = -0.5f * dx * dx * dpow;
+          v[3] = -dx * dy * dpow;
+          v[4] = -0.5f * dy * dy * dpow;
+          v[5] = dop;
+          v[6] = w * g0;
+          v[7] = w * g1;
+          v[8] = w * g2;
+          wave_sum9_atomic(v, &g2d[(int64_t)s_gid[j + u] * 9]);
+        }
       }
     }
   }

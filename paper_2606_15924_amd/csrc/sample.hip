@@ -46,6 +46,13 @@ __device__ __forceinline__ uint64_t half_weight(uint16_t h) {
   return (uint64_t)(1024u + man) << (ex - 1);
 }
 
+// Lane l's value of a 64-bit register (l uniform).
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ int tile_valid_w(int tx, int W) { return min(kTile, W - tx * kTile); }
 __device__ __forceinline__ int tile_valid_h(int ty, int H) { return min(kTile, H - ty * kTile); }
 
@@ -198,28 +205,45 @@ __global__ void __launch_bounds__(64) tile_pixels_kernel(
   uint32_t picked = 0;  // bit k: local index lane*4+k chosen
   const uint64_t key = stream_key(seed, step, view, (uint64_t)t);
 
-  // --- hard: sequential error-weighted draws without replacement
+  // --- hard: sequential error-weighted draws without replacement.  The
+  // draws' random words are hashed up front, lane l holding draw l + 64 q
+  // in uh[q].  The wave prefix sum of the lanes' unpicked weight is taken
+  // once and kept up to date: a draw lands in the first lane whose
+  // inclusive sum exceeds r, and removing the picked weight lowers the sums
+  // of that lane and the lanes after it.
   int n_hard_done = 0;
-  for (int j = 0; j < n_hard; ++j) {
-    uint64_t ls = 0;
-    for (int k = 0; k < 4; ++k) ls += ((picked >> k) & 1u) ? 0 : w[k];
-    const uint64_t incl = wave_inclusive_scan_u64(ls);
-    const uint64_t total = __shfl(incl, 63, kWave);
-    if (total == 0) break;
-    const uint64_t r = mulhi64(absorb(key, (uint64_t)j), total);
-    const uint64_t excl = incl - ls;
-    if (ls > 0 && excl <= r && r < incl) {
-      uint64_t run = excl;
-      for (int k = 0; k < 4; ++k) {
-        if ((picked >> k) & 1u) continue;
-        run += w[k];
-        if (run > r) {
-          picked |= 1u << k;
-          break;
+  {
+    uint64_t uh[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) uh[q] = kWave * q < n_hard ? absorb(key, (uint64_t)(lane + kWave * q)) : 0;
+    uint64_t ls = w[0] + w[1] + w[2] + w[3];
+    uint64_t incl = wave_inclusive_scan_u64(ls);
+    uint64_t total = readlane_u64(incl, kWave - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      for (int jj = 0; jj < kWave && n_hard_done < n_hard && total != 0; ++jj) {
+        const uint64_t r = mulhi64(readlane_u64(uh[q], jj), total);
+        const int pl = (int)__builtin_ctzll(__ballot(incl > r));  // incl of lane 63 = total > r
+        uint64_t wp = 0;
+        if (lane == pl) {
+          uint64_t run = incl - ls;
+          for (int k = 0; k < 4; ++k) {
+            if ((picked >> k) & 1u) continue;
+            run += w[k];
+            if (run > r) {
+              picked |= 1u << k;
+              wp = w[k];
+              break;
+            }
+          }
+          ls -= wp;
         }
+        wp = readlane_u64(wp, pl);
+        if (lane >= pl) incl -= wp;
+        total -= wp;
+        ++n_hard_done;
       }
     }
-    ++n_hard_done;
   }
   n_mixed += n_hard - n_hard_done;
 
@@ -246,22 +270,39 @@ __global__ void __launch_bounds__(64) tile_pixels_kernel(
   }
 
   // --- mixed: uniform without replacement over the rest, ascending order
-  for (int j = 0; j < n_mixed; ++j) {
+  // (the r-th remaining pixel; words hashed up front and the count prefix
+  // kept up to date as above)
+  {
+    uint64_t um[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      um[q] = kWave * q < n_mixed ? absorb(key, (uint64_t)(256 + lane + kWave * q)) : 0;
     int lc = 0;
     for (int k = 0; k < 4; ++k) lc += (valid[k] && !((picked >> k) & 1u)) ? 1 : 0;
-    const int ic = wave_inclusive_scan_i(lc);
-    const int nrem = __shfl(ic, 63, kWave);
-    const int r = (int)mulhi64(absorb(key, (uint64_t)(256 + j)), (uint64_t)nrem);
-    const int ex = ic - lc;
-    if (lc > 0 && ex <= r && r < ic) {
-      int c = ex;
-      for (int k = 0; k < 4; ++k) {
-        if (!valid[k] || ((picked >> k) & 1u)) continue;
-        if (c == r) {
-          picked |= 1u << k;
-          break;
+    int ic = wave_inclusive_scan_i(lc);
+    int nrem = __builtin_amdgcn_readlane(ic, kWave - 1);
+    int done = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // nrem == 0: nothing left, every later draw picks nothing
+      for (int jj = 0; jj < kWave && done < n_mixed && nrem > 0; ++jj) {
+        const int r = (int)mulhi64(readlane_u64(um[q], jj), (uint64_t)nrem);
+        const int pl = (int)__builtin_ctzll(__ballot(ic > r));
+        if (lane == pl) {
+          int c = ic - lc;
+          for (int k = 0; k < 4; ++k) {
+            if (!valid[k] || ((picked >> k) & 1u)) continue;
+            if (c == r) {
+              picked |= 1u << k;
+              break;
+            }
+            ++c;
+          }
+          --lc;
         }
-        ++c;
+        if (lane >= pl) --ic;
+        --nrem;
+        ++done;
       }
     }
   }

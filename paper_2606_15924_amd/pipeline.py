@@ -124,8 +124,8 @@ class ViewBuffers:
                          self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
                          rp, self.out, self.ncontrib, self.dL, self.g2d)
 
-    def project_bwd(self, params, cam: B.tgs_camera, rp, grad):
-        B.tgs_project_bwd(params, self.n, cam, rp, self.radius, self.clamp, self.g2d, grad)
+    def project_bwd(self, params, cam: B.tgs_camera, rp, grad, accumulate=True):
+        B.tgs_project_bwd(params, self.n, cam, rp, self.radius, self.clamp, self.g2d, grad, accumulate)
 
 
 class Trainer:
@@ -193,8 +193,9 @@ class Trainer:
         t = self.step_count
         views = list(views)
         self.totals.zero_()
-        self.grad.zero_()
         self.touched.zero_()
+        if not views:
+            self.grad.zero_()
         used = []
         st = self._stage
         for slot, v in enumerate(views):
@@ -207,7 +208,7 @@ class Trainer:
                 with st("sample"):
                     vb.sample(self.E[v], self.A[v], self.cfg, t, v, self.totals)
             used.append(vb)
-        for vb, v in zip(used, views):
+        for k, (vb, v) in enumerate(zip(used, views)):
             cam = self.cams[v]
             with st("project"):
                 vb.project(self.params, cam, self.rp)
@@ -223,7 +224,8 @@ class Trainer:
             with st("render_bwd"):
                 vb.render_bwd(self.rp)
             with st("project_bwd"):
-                vb.project_bwd(self.params, cam, self.rp, self.grad)
+                # the first view overwrites the gradient, later views add to it
+                vb.project_bwd(self.params, cam, self.rp, self.grad, accumulate=k > 0)
         with st("optimizer"):
             B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
         return used

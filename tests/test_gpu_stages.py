@@ -430,6 +430,16 @@ def test_project_bwd_parity(B, case):
     for name, sl in groups.items():
         scale = np.abs(ref[sl]).max()
         assert_close(got[sl], ref[sl], 1e-5, 1e-6 * scale + 4e-7 * np.abs(grad0[sl]), name)
+    # overwrite mode: every entry written, culled Gaussians get zeros
+    G2 = torch.full((59, n), float("nan"), dtype=torch.float32, device="cuda")
+    B.tgs_project_bwd(P, n, c, brp, radius, clamp, dev(g2d.T.astype(np.float32)), G2, accumulate=False)
+    got2 = host(G2).astype(np.float64)
+    assert np.isfinite(got2).all()
+    culled = host(radius) == 0
+    assert (got2[:, culled] == 0).all()
+    for name, sl in groups.items():
+        scale = np.abs(ref[sl]).max()
+        assert_close(got2[sl], ref[sl], 1e-5, 1e-6 * scale, name)
 
 
 # ------------------------------------------------------------------ optimizer
