@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 1u
+#define TGS_ABI_VERSION 2u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
@@ -239,6 +239,23 @@ int32_t tgs_project_bwd(const float* params, int64_t n, const tgs_camera* cam,
                         const tgs_raster_params* rp, const int32_t* radius,
                         const uint8_t* clamp, const float* g2d, float* grad, int32_t accumulate,
                         void* stream);
+
+/* tgs_project_bwd followed by tgs_optimizer_step in one pass, for the last
+ * view of a training step (Sec. 3.9 update applied to the gradient of
+ * Sec. 3.6's backward): each parameter row's gradient stays in registers
+ * and the row is updated at once.  Results equal the two calls bit for bit.
+ *   grad_prev  nullable [59][n]: gradient accumulated from the step's
+ *              earlier views (read only); NULL when this is the only view
+ *   ws         workspace of tgs_project_bwd_optimizer_workspace_size(n)
+ *              bytes (8-byte aligned)
+ *   other arguments as in tgs_project_bwd and tgs_optimizer_step */
+size_t tgs_project_bwd_optimizer_workspace_size(int64_t n);
+int32_t tgs_project_bwd_optimizer_step(float* params, int64_t n, const tgs_camera* cam,
+                                       const tgs_raster_params* rp, const int32_t* radius,
+                                       const uint8_t* clamp, const float* g2d,
+                                       const float* grad_prev, float* m, float* v,
+                                       const uint8_t* touched, const tgs_optim_params* op,
+                                       int64_t step, void* ws, size_t ws_bytes, void* stream);
 
 /* Hybrid moment-damped LM / Adam update (Sec. 3.9, Eq. moment_damped_lm, and
  * the appendix optimizer details): per touched Gaussian, Adam moments for all

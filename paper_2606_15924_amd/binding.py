@@ -91,6 +91,10 @@ PROTOTYPES = {
     "tgs_project_bwd": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
                                _P, _P, _P, _P, _I32, _P]),
     "tgs_optimizer_step": (_I32, [_P, _P, _P, _P, _I64, _P, ctypes.POINTER(tgs_optim_params), _I64, _P]),
+    "tgs_project_bwd_optimizer_workspace_size": (_SZ, [_I64]),
+    "tgs_project_bwd_optimizer_step": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera),
+                                              ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P,
+                                              ctypes.POINTER(tgs_optim_params), _I64, _P, _SZ, _P]),
 }
 
 _lib = None
@@ -269,3 +273,16 @@ def tgs_project_bwd(params, n, cam: tgs_camera, rp: tgs_raster_params, radius, c
 def tgs_optimizer_step(params, grad, m, v, n, touched, op: tgs_optim_params, step):
     _check(lib().tgs_optimizer_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, _ptr(touched),
                                     ctypes.byref(op), step, _stream()), "tgs_optimizer_step")
+
+
+def tgs_project_bwd_optimizer_workspace_size(n: int) -> int:
+    return int(lib().tgs_project_bwd_optimizer_workspace_size(n))
+
+
+def tgs_project_bwd_optimizer_step(params, n, cam: tgs_camera, rp: tgs_raster_params, radius, clamp, g2d,
+                                   grad_prev, m, v, touched, op: tgs_optim_params, step, ws):
+    _check(lib().tgs_project_bwd_optimizer_step(_ptr(params), n, ctypes.byref(cam), ctypes.byref(rp),
+                                                _ptr(radius), _ptr(clamp), _ptr(g2d), _ptr(grad_prev),
+                                                _ptr(m), _ptr(v), _ptr(touched), ctypes.byref(op), step,
+                                                _ptr(ws), ws.numel() * ws.element_size(), _stream()),
+           "tgs_project_bwd_optimizer_step")

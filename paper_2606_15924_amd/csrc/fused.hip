@@ -1,0 +1,146 @@
+// Projection backward fused with the optimizer step, for the last view of
+// a training step: the chain rule produces each parameter row's gradient in
+// registers and the row is updated in the same pass, so the gradient never
+// goes through HBM.  Two launches split the rows by their work:
+//   sh_rest_kernel   the SH rows of degree >= 1 (rows 14-58, always Adam
+//                    rows): their gradient Y_k(u) * dL/drgb,
+//                    the Adam update, and the partial dL/du of these rows
+//                    (three doubles per Gaussian in the workspace);
+//                    light on registers, so many waves keep HBM busy
+//   geom_lm_kernel   the geometry chain rule and rows 0-13 (SH DC, opacity,
+//                    mean, scale, quaternion) with the LM (or Adam) update
+// The SH-rest kernel reads the coefficients before updating them, and the
+// geometry kernel only touches rows 0-13, so running them in this order
+// gives each the values the unfused path sees.  Results equal
+// tgs_project_bwd followed by tgs_optimizer_step bit for bit: gradients are
+// rounded to float as the unfused path stores them, the dL/du sum keeps
+// its order (the DC term contributes an exact zero), and both paths share
+// the update functions.
+#include <algorithm>
+
+#include "optimizer.h"
+#include "projection.h"
+
+namespace tgs {
+
+// Gradient of one row as the unfused path stores it (float), plus the
+// earlier views' gradient when there is one.
+__device__ __forceinline__ float stored_grad(const float* __restrict__ grad_prev, int64_t idx, double val) {
+  return grad_prev != nullptr ? grad_prev[idx] + (float)val : (float)val;
+}
+
+__global__ void __launch_bounds__(256) sh_rest_kernel(
+    float* params, int64_t n, CamArgs cam, int sh_degree, const int* __restrict__ radius,
+    const uint8_t* __restrict__ clampm, const float* __restrict__ g2d, const float* __restrict__ grad_prev,
+    float* __restrict__ m, float* __restrict__ v, const uint8_t* __restrict__ touched, OptArgs o,
+    double* __restrict__ dL_du_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (touched != nullptr && touched[i] == 0) return;  // untouched: parameters and moments stay
+  auto adam_row = [&](int row, double val) {
+    const int64_t idx = (int64_t)row * n + i;
+    float pp = params[idx], mm = m[idx], vv = v[idx];
+    adam_elem(pp, stored_grad(grad_prev, idx, val), mm, vv, row_lr(o, row), o);
+    params[idx] = pp;
+    m[idx] = mm;
+    v[idx] = vv;
+  };
+  if (radius[i] == 0) {
+    for (int row = 14; row < TGS_PARAM_ROWS; ++row) adam_row(row, 0.0);
+    return;
+  }
+  double mu[3], gg[9];
+  for (int k = 0; k < 3; ++k) mu[k] = (double)params[(int64_t)k * n + i];
+  for (int k = 0; k < 9; ++k) gg[k] = (double)g2d[i * 9 + k];
+  const ViewDir u = view_dir(mu, cam);
+  double drgb[3];
+  color_grad(gg, clampm[i], drgb);
+  double dL_du[3] = {0.0, 0.0, 0.0};
+  sh_backward(params, n, i, u, drgb, n_sh(sh_degree), 1, 16, dL_du, adam_row);
+  for (int k = 0; k < 3; ++k) dL_du_out[i * 3 + k] = dL_du[k];
+}
+
+__global__ void __launch_bounds__(256) geom_lm_kernel(
+    float* params, int64_t n, CamArgs cam, int sh_degree, double z_near, double dil,
+    const int* __restrict__ radius, const uint8_t* __restrict__ clampm, const float* __restrict__ g2d,
+    const float* __restrict__ grad_prev, float* __restrict__ m, float* __restrict__ v,
+    const uint8_t* __restrict__ touched, OptArgs o, const double* __restrict__ dL_du_in) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (touched != nullptr && touched[i] == 0) return;
+  const bool lm = o.lm_mode != 2;
+  float gl[14];  // gradients of rows 0-13 (LM blocks), applied after the chain rule
+  auto sink = [&](int row, double val) {
+    const int64_t idx = (int64_t)row * n + i;
+    const float gf = stored_grad(grad_prev, idx, val);
+    if (lm) {
+      gl[row] = gf;
+      return;
+    }
+    float pp = params[idx], mm = m[idx], vv = v[idx];
+    adam_elem(pp, gf, mm, vv, row_lr(o, row), o);
+    params[idx] = pp;
+    m[idx] = mm;
+    v[idx] = vv;
+  };
+  if (radius[i] != 0) {
+    Geom g;
+    geometry(params, n, i, cam, z_near, dil, g);
+    double gg[9];
+    for (int k = 0; k < 9; ++k) gg[k] = (double)g2d[i * 9 + k];
+    const ViewDir u = view_dir(g.mu, cam);
+    double drgb[3];
+    color_grad(gg, clampm[i], drgb);
+    double dc_du[3] = {0.0, 0.0, 0.0};  // the DC basis is constant: no dL/du
+    sh_backward(params, n, i, u, drgb, n_sh(sh_degree), 0, 1, dc_du, sink);
+    const double dL_du[3] = {dL_du_in[i * 3], dL_du_in[i * 3 + 1], dL_du_in[i * 3 + 2]};
+    geom_backward(params, n, i, cam, g, gg, u, dL_du, sink);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 14; ++r) sink(r, 0.0);
+  }
+  if (lm) {
+    float gg[10], ga[4];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) gg[k] = gl[kGeomRows[k]];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ga[k] = gl[kAppRows[k]];
+    lm_update<10>(params, m, v, n, i, kGeomRows, gg, o);
+    lm_update<4>(params, m, v, n, i, kAppRows, ga, o);
+  }
+}
+
+}  // namespace tgs
+
+using namespace tgs;
+
+extern "C" size_t tgs_project_bwd_optimizer_workspace_size(int64_t n) {
+  return n < 0 ? 0 : align_up((size_t)(3 * std::max<int64_t>(n, 1)) * sizeof(double), 256);
+}
+
+extern "C" int32_t tgs_project_bwd_optimizer_step(float* params, int64_t n, const tgs_camera* cam,
+                                                  const tgs_raster_params* rp, const int32_t* radius,
+                                                  const uint8_t* clamp, const float* g2d,
+                                                  const float* grad_prev, float* m, float* v,
+                                                  const uint8_t* touched, const tgs_optim_params* op,
+                                                  int64_t step, void* ws, size_t ws_bytes, void* stream) {
+  const char* who = "tgs_project_bwd_optimizer_step";
+  TGS_REQUIRE(n >= 0, "%s: n < 0", who);
+  TGS_REQUIRE(cam != nullptr && cam->width > 0 && cam->height > 0, "%s: bad camera", who);
+  if (int32_t e = check_raster_params(rp)) return e;
+  OptArgs o;
+  if (int32_t e = make_opt_args(op, step, who, o)) return e;
+  if (n == 0) return TGS_OK;
+  TGS_REQUIRE(params && radius && clamp && g2d && m && v && ws, "%s: null pointer", who);
+  TGS_REQUIRE(ws_bytes >= tgs_project_bwd_optimizer_workspace_size(n), "%s: workspace %zu bytes < %zu", who,
+              ws_bytes, tgs_project_bwd_optimizer_workspace_size(n));
+  TGS_REQUIRE(((uintptr_t)ws & 7) == 0, "%s: workspace must be 8-byte aligned", who);
+  const CamArgs ca = make_cam(cam);
+  hipStream_t s = as_stream(stream);
+  const dim3 grid((unsigned)ceil_div(n, 256));
+  hipLaunchKernelGGL(sh_rest_kernel, grid, dim3(256), 0, s, params, n, ca, rp->sh_degree, radius, clamp, g2d,
+                     grad_prev, m, v, touched, o, (double*)ws);
+  hipLaunchKernelGGL(geom_lm_kernel, grid, dim3(256), 0, s, params, n, ca, rp->sh_degree, (double)rp->z_near,
+                     (double)rp->dilation, radius, clamp, g2d, grad_prev, m, v, touched, o, (const double*)ws);
+  return hip_status(who);
+}

@@ -8,80 +8,9 @@
 //   adam_kernel   the plain Adam rows (14-58, or all rows in Adam mode): a
 //                 row per grid line, four consecutive Gaussians per thread
 //                 with 16-byte loads when the row length allows
-// Arithmetic is FP64 throughout; only the stored results are rounded.
-#include "common.h"
+#include "optimizer.h"
 
 namespace tgs {
-
-struct OptArgs {
-  double lr[6];  // mean, scale, quat, opacity, sh dc, sh rest
-  double beta1, beta2, eps_adam, eps_lm;
-  double bc1, bc2;  // 1 - beta^t
-  int lm_mode;
-};
-
-__device__ __forceinline__ double row_lr(const OptArgs& o, int row) {
-  if (row < 3) return o.lr[0];
-  if (row < 6) return o.lr[1];
-  if (row < 10) return o.lr[2];
-  if (row == 10) return o.lr[3];
-  if (row < 14) return o.lr[4];
-  return o.lr[5];
-}
-
-// Solve (g g^T + diag(d)) x = -m (mode 0) or diag(g^2 + d) x = -m (mode 1)
-// for one block of K rows.  The mode-0 matrix is diagonal plus rank one, so
-// its inverse follows the Sherman-Morrison identity:
-//   x = -(D^-1 m - D^-1 g (g^T D^-1 m) / (1 + g^T D^-1 g)),
-// an exact solve in K divisions and two dot products (no K x K factor in
-// registers).  d >= eps > 0 keeps D invertible and 1 + g^T D^-1 g >= 1.
-template <int K>
-__device__ __forceinline__ void lm_block(float* __restrict__ p, const float* __restrict__ grad,
-                                         float* __restrict__ m, float* __restrict__ v, int64_t n,
-                                         int64_t i, const int (&rows)[K], const OptArgs& o) {
-  double g[K], mm[K], d[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int64_t idx = (int64_t)rows[k] * n + i;
-    g[k] = grad[idx];
-    mm[k] = o.beta1 * (double)m[idx] + (1.0 - o.beta1) * g[k];
-    const double vv = o.beta2 * (double)v[idx] + (1.0 - o.beta2) * g[k] * g[k];
-    d[k] = sqrt(vv) + o.eps_lm;
-    m[idx] = (float)mm[k];
-    v[idx] = (float)vv;
-  }
-  double x[K];
-  if (o.lm_mode == 1) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) x[k] = -mm[k] / (g[k] * g[k] + d[k]);
-  } else {
-    double s = 0.0, t = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      d[k] = 1.0 / d[k];
-      s += g[k] * g[k] * d[k];
-      t += g[k] * mm[k] * d[k];
-    }
-    const double c = t / (1.0 + s);
-#pragma unroll
-    for (int k = 0; k < K; ++k) x[k] = (g[k] * c - mm[k]) * d[k];
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int64_t idx = (int64_t)rows[k] * n + i;
-    p[idx] = (float)((double)p[idx] + row_lr(o, rows[k]) * x[k]);
-  }
-}
-
-__device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v, double lr, const OptArgs& o) {
-  const double gd = g;
-  const double mm = o.beta1 * (double)m + (1.0 - o.beta1) * gd;
-  const double vv = o.beta2 * (double)v + (1.0 - o.beta2) * gd * gd;
-  m = (float)mm;
-  v = (float)vv;
-  const double mh = mm / o.bc1, vh = vv / o.bc2;
-  p = (float)((double)p - lr * mh / (sqrt(vh) + o.eps_adam));
-}
 
 __global__ void __launch_bounds__(256) lm_kernel(float* __restrict__ p, const float* __restrict__ grad,
                                                  float* __restrict__ m, float* __restrict__ v, int64_t n,
@@ -89,10 +18,13 @@ __global__ void __launch_bounds__(256) lm_kernel(float* __restrict__ p, const fl
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (touched != nullptr && touched[i] == 0) return;
-  const int geom[10] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9};
-  const int app[4] = {11, 12, 13, 10};
-  lm_block<10>(p, grad, m, v, n, i, geom, o);
-  lm_block<4>(p, grad, m, v, n, i, app, o);
+  float gg[10], ga[4];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) gg[k] = grad[(int64_t)kGeomRows[k] * n + i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) ga[k] = grad[(int64_t)kAppRows[k] * n + i];
+  lm_update<10>(p, m, v, n, i, kGeomRows, gg, o);
+  lm_update<4>(p, m, v, n, i, kAppRows, ga, o);
 }
 
 // Rows row0 + blockIdx.y; thread handles Gaussians [i0, i0 + 4).  kVec: the
@@ -146,27 +78,10 @@ extern "C" int32_t tgs_optimizer_step(float* params, const float* grad, float* m
                                       int64_t n, const uint8_t* touched,
                                       const tgs_optim_params* op, int64_t step, void* stream) {
   TGS_REQUIRE(n >= 0, "tgs_optimizer_step: n < 0");
-  TGS_REQUIRE(op != nullptr, "tgs_optimizer_step: null params");
-  TGS_REQUIRE(step >= 1, "tgs_optimizer_step: step must be >= 1");
-  TGS_REQUIRE(op->lm_mode >= 0 && op->lm_mode <= 2, "tgs_optimizer_step: bad lm_mode %d", op->lm_mode);
-  TGS_REQUIRE(op->beta1 >= 0.0 && op->beta1 < 1.0 && op->beta2 >= 0.0 && op->beta2 < 1.0,
-              "tgs_optimizer_step: betas must lie in [0, 1)");
+  OptArgs o;
+  if (int32_t e = make_opt_args(op, step, "tgs_optimizer_step", o)) return e;
   if (n == 0) return TGS_OK;
   TGS_REQUIRE(params && grad && m && v, "tgs_optimizer_step: null pointer");
-  OptArgs o;
-  o.lr[0] = op->lr_mean;
-  o.lr[1] = op->lr_scale;
-  o.lr[2] = op->lr_quat;
-  o.lr[3] = op->lr_opacity;
-  o.lr[4] = op->lr_sh_dc;
-  o.lr[5] = op->lr_sh_rest;
-  o.beta1 = op->beta1;
-  o.beta2 = op->beta2;
-  o.eps_adam = op->eps_adam;
-  o.eps_lm = op->eps_lm;
-  o.bc1 = 1.0 - pow(op->beta1, (double)step);
-  o.bc2 = 1.0 - pow(op->beta2, (double)step);
-  o.lm_mode = op->lm_mode;
   hipStream_t s = as_stream(stream);
   if (o.lm_mode != 2)
     hipLaunchKernelGGL(lm_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, params, grad, m, v, n,

@@ -1,0 +1,116 @@
+// Update rules of the hybrid moment-damped LM / Adam optimizer, shared by
+// the optimizer kernels and the fused backward + optimizer kernel.  Each
+// function fixes its own operation order (no multiply-add contraction), so
+// every kernel using them produces the same values bit for bit; arithmetic
+// is FP64 and only stored results are rounded.
+#pragma once
+
+#include <math.h>
+
+#include "common.h"
+
+namespace tgs {
+
+struct OptArgs {
+  double lr[6];  // mean, scale, quat, opacity, sh dc, sh rest
+  double beta1, beta2, eps_adam, eps_lm;
+  double bc1, bc2;  // 1 - beta^t
+  int lm_mode;
+};
+
+__host__ __device__ inline double row_lr(const OptArgs& o, int row) {
+  if (row < 3) return o.lr[0];
+  if (row < 6) return o.lr[1];
+  if (row < 10) return o.lr[2];
+  if (row == 10) return o.lr[3];
+  if (row < 14) return o.lr[4];
+  return o.lr[5];
+}
+
+// Rows of the two LM blocks: geometry (mean, log-scale, quaternion) and
+// base appearance (SH DC r, g, b, opacity).
+constexpr int kGeomRows[10] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9};
+constexpr int kAppRows[4] = {11, 12, 13, 10};
+
+// Adam step of one entry with gradient g (p, m, v updated in place).
+__device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v, double lr, const OptArgs& o) {
+#pragma clang fp contract(off)
+  const double gd = g;
+  const double mm = o.beta1 * (double)m + (1.0 - o.beta1) * gd;
+  const double vv = o.beta2 * (double)v + (1.0 - o.beta2) * gd * gd;
+  m = (float)mm;
+  v = (float)vv;
+  const double mh = mm / o.bc1, vh = vv / o.bc2;
+  p = (float)((double)p - lr * mh / (sqrt(vh) + o.eps_adam));
+}
+
+// LM step of one block of K rows of Gaussian i with block gradient gf.
+// Solves (g g^T + diag(d)) x = -m (mode 0) or diag(g^2 + d) x = -m (mode 1)
+// with the updated moments, d = sqrt(v) + eps.  The mode-0 matrix is
+// diagonal plus rank one, so its inverse follows the Sherman-Morrison
+// identity:
+//   x = -(D^-1 m - D^-1 g (g^T D^-1 m) / (1 + g^T D^-1 g)),
+// an exact solve in K divisions and two dot products (no K x K factor in
+// registers).  d >= eps > 0 keeps D invertible and 1 + g^T D^-1 g >= 1.
+template <int K>
+__device__ __forceinline__ void lm_update(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                          int64_t n, int64_t i, const int (&rows)[K], const float (&gf)[K],
+                                          const OptArgs& o) {
+#pragma clang fp contract(off)
+  double g[K], mm[K], d[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t idx = (int64_t)rows[k] * n + i;
+    g[k] = gf[k];
+    mm[k] = o.beta1 * (double)m[idx] + (1.0 - o.beta1) * g[k];
+    const double vv = o.beta2 * (double)v[idx] + (1.0 - o.beta2) * g[k] * g[k];
+    d[k] = sqrt(vv) + o.eps_lm;
+    m[idx] = (float)mm[k];
+    v[idx] = (float)vv;
+  }
+  double x[K];
+  if (o.lm_mode == 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = -mm[k] / (g[k] * g[k] + d[k]);
+  } else {
+    double s = 0.0, t = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      d[k] = 1.0 / d[k];
+      s += g[k] * g[k] * d[k];
+      t += g[k] * mm[k] * d[k];
+    }
+    const double c = t / (1.0 + s);
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = (g[k] * c - mm[k]) * d[k];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t idx = (int64_t)rows[k] * n + i;
+    p[idx] = (float)((double)p[idx] + row_lr(o, rows[k]) * x[k]);
+  }
+}
+
+inline int32_t make_opt_args(const tgs_optim_params* op, int64_t step, const char* who, OptArgs& o) {
+  TGS_REQUIRE(op != nullptr, "%s: null optimizer params", who);
+  TGS_REQUIRE(step >= 1, "%s: step must be >= 1", who);
+  TGS_REQUIRE(op->lm_mode >= 0 && op->lm_mode <= 2, "%s: bad lm_mode %d", who, op->lm_mode);
+  TGS_REQUIRE(op->beta1 >= 0.0 && op->beta1 < 1.0 && op->beta2 >= 0.0 && op->beta2 < 1.0,
+              "%s: betas must lie in [0, 1)", who);
+  o.lr[0] = op->lr_mean;
+  o.lr[1] = op->lr_scale;
+  o.lr[2] = op->lr_quat;
+  o.lr[3] = op->lr_opacity;
+  o.lr[4] = op->lr_sh_dc;
+  o.lr[5] = op->lr_sh_rest;
+  o.beta1 = op->beta1;
+  o.beta2 = op->beta2;
+  o.eps_adam = op->eps_adam;
+  o.eps_lm = op->eps_lm;
+  o.bc1 = 1.0 - pow(op->beta1, (double)step);
+  o.bc2 = 1.0 - pow(op->beta2, (double)step);
+  o.lm_mode = op->lm_mode;
+  return TGS_OK;
+}
+
+}  // namespace tgs

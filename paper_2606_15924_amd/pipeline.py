@@ -2,11 +2,18 @@
 for the selected views): buffers are allocated once per shape and every step
 of the path runs in the HIP library through the C ABI.
 
-A view's work, in order, on torch's current stream:
+A view's work, in order:
   tgs_sample -> tgs_project -> tgs_bin_sort -> tgs_render_fwd -> tgs_loss
   -> tgs_ema_age_update -> tgs_render_bwd -> tgs_project_bwd
-and once per step tgs_optimizer_step.  The sampler of every view runs first
+and once per step the optimizer update, fused with the last view's
+projection backward (tgs_project_bwd_optimizer_step).  The sampler of every view runs first
 because the loss normalises by the step's total sample and tile counts.
+
+Two streams (both at the default priority): the samplers run on a side
+stream while the main stream projects and bins (binning needs the sample
+only when it restricts the tiles), and each view's error/age update runs on
+the side stream beside the backward, which does not read the maps.  Events
+order the two; the step ends with the main stream waiting for the side one.
 """
 from __future__ import annotations
 
@@ -29,6 +36,7 @@ class StepConfig:
     stable_permille: int = 300
     beta: float = 0.4
     seed: int = 3
+    fuse_optimizer: bool = True   # last view's projection backward fused with the update
     raster: dict = field(default_factory=dict)
     loss: dict = field(default_factory=dict)
     optim: dict = field(default_factory=dict)
@@ -93,9 +101,13 @@ class ViewBuffers:
     def project(self, params, cam: B.tgs_camera, rp):
         B.tgs_project(params, self.n, cam, rp, self.splat, self.depth, self.radius, self.rect, self.clamp)
 
+    def bin_sort_needs_samples(self) -> bool:
+        """Binning reads the tile map only when the sampler keeps a subset of tiles."""
+        return self.tile_slot is not None and self.n_st < self.n_t
+
     def bin_sort(self, touched=None) -> int:
         # every tile is valid when the sampler keeps all of them: no tile map needed
-        tile_slot = self.tile_slot if (self.tile_slot is not None and self.n_st < self.n_t) else None
+        tile_slot = self.tile_slot if self.bin_sort_needs_samples() else None
         while True:
             try:
                 self.n_pairs = B.tgs_bin_sort(self.rect, self.depth, self.n, tile_slot, self.tiles_x,
@@ -151,6 +163,9 @@ class Trainer:
         self.step_count = 0
         self._bufs: dict = {}
         self.counters = torch.zeros((2, B.COUNTER_SLOTS), dtype=torch.int64, device=self.dev)
+        self.side = torch.cuda.Stream(device=self.dev)  # default priority
+        self.fused_ws = torch.empty(B.tgs_project_bwd_optimizer_workspace_size(self.n), dtype=torch.uint8,
+                                    device=self.dev)
         self.events: dict | None = None   # stage name -> [(start, end)] when timing
 
     @contextlib.contextmanager
@@ -192,42 +207,66 @@ class Trainer:
         self.step_count += 1
         t = self.step_count
         views = list(views)
+        main, side = torch.cuda.current_stream(), self.side
         self.totals.zero_()
         self.touched.zero_()
         if not views:
             self.grad.zero_()
-        used = []
         st = self._stage
-        for slot, v in enumerate(views):
-            cam = self.cams[v]
-            vb = self.buffers(slot, cam)
-            if vb.dense:
-                self.totals[0] += cam.width * cam.height
-                self.totals[1] += vb.n_t
-            else:
-                with st("sample"):
-                    vb.sample(self.E[v], self.A[v], self.cfg, t, v, self.totals)
-            used.append(vb)
+        used = [self.buffers(slot, self.cams[v]) for slot, v in enumerate(views)]
+        # samplers on the side stream (they see everything queued on main so far)
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            for vb, v in zip(used, views):
+                cam = self.cams[v]
+                if vb.dense:
+                    self.totals[0] += cam.width * cam.height
+                    self.totals[1] += vb.n_t
+                else:
+                    with st("sample"):
+                        vb.sample(self.E[v], self.A[v], self.cfg, t, v, self.totals)
+        sampled = torch.cuda.Event()
+        sampled.record(side)
+        waited = False
         for k, (vb, v) in enumerate(zip(used, views)):
             cam = self.cams[v]
             with st("project"):
                 vb.project(self.params, cam, self.rp)
+            if not waited and vb.bin_sort_needs_samples():
+                main.wait_event(sampled)
+                waited = True
             with st("bin_sort"):
                 vb.bin_sort(self.touched)
+            if not waited:
+                main.wait_event(sampled)
+                waited = True
             with st("render_fwd"):
                 vb.render_fwd(self.rp, self.counters)
             with st("loss"):
                 vb.loss(self.gts[v], self.totals, self.lp)
             if not vb.dense:
-                with st("ema_age"):
-                    vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
+                lossed = torch.cuda.Event()
+                lossed.record(main)
+                side.wait_event(lossed)
+                with torch.cuda.stream(side):
+                    with st("ema_age"):
+                        vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
             with st("render_bwd"):
                 vb.render_bwd(self.rp)
-            with st("project_bwd"):
-                # the first view overwrites the gradient, later views add to it
-                vb.project_bwd(self.params, cam, self.rp, self.grad, accumulate=k > 0)
-        with st("optimizer"):
-            B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
+            if k + 1 < len(used) or not self.cfg.fuse_optimizer:
+                with st("project_bwd"):
+                    # the first view overwrites the gradient, later views add to it
+                    vb.project_bwd(self.params, cam, self.rp, self.grad, accumulate=k > 0)
+            else:
+                # the last view's chain rule feeds the update directly
+                with st("project_bwd_optimizer"):
+                    B.tgs_project_bwd_optimizer_step(self.params, self.n, cam, self.rp, vb.radius, vb.clamp,
+                                                     vb.g2d, self.grad if k > 0 else None, self.m, self.v,
+                                                     self.touched, self.op, t, self.fused_ws)
+        if not used or not self.cfg.fuse_optimizer:
+            with st("optimizer"):
+                B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
+        main.wait_stream(side)
         return used
 
     def loss_value(self, used) -> float:

@@ -442,6 +442,49 @@ def test_project_bwd_parity(B, case):
         assert_close(got2[sl], ref[sl], 1e-5, 1e-6 * scale, name)
 
 
+# ------------------------------------------------------------------ fused backward + optimizer
+@pytest.mark.parametrize("mode,prev,deg", [(0, False, 3), (1, True, 3), (2, False, 3), (0, True, 1)])
+def test_project_bwd_optimizer_fused(B, mode, prev, deg):
+    """The fused entry point equals tgs_project_bwd then tgs_optimizer_step
+    bit for bit (culled, untouched and touched-but-culled Gaussians included)."""
+    p, cams = scene_c1(4000)
+    cam = cams[2]
+    n = p.shape[1]
+    rng = np.random.default_rng(31 + mode)
+    brp = B.raster_params(sh_degree=deg)
+    c = B.camera(cam)
+    P0 = dev(p)
+    splat = torch.empty((n, 12), dtype=torch.float32, device="cuda")
+    depth = torch.empty(n, dtype=torch.float32, device="cuda")
+    radius = torch.empty(n, dtype=torch.int32, device="cuda")
+    rect = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    clamp = torch.empty(n, dtype=torch.uint8, device="cuda")
+    B.tgs_project(P0, n, c, brp, splat, depth, radius, rect, clamp)
+    g2d = rng.normal(size=(n, 9)).astype(np.float32)
+    g2d[:, 2:5] *= 100.0
+    m0 = (rng.normal(size=(59, n)) * 1e-3).astype(np.float32)
+    v0 = rng.uniform(0, 1e-4, size=(59, n)).astype(np.float32)
+    touched = (rng.uniform(size=n) < 0.8).astype(np.uint8)
+    grad_prev = rng.normal(size=(59, n)).astype(np.float32) if prev else None
+    op = B.optim_params(lm_mode=mode)
+    step = 5
+    # unfused: gradient (accumulated onto the earlier views' one), then the update
+    Pa, Ma, Va = dev(p), dev(m0), dev(v0)
+    G = dev(grad_prev) if prev else torch.empty((59, n), dtype=torch.float32, device="cuda")
+    B.tgs_project_bwd(Pa, n, c, brp, radius, clamp, dev(g2d), G, accumulate=prev)
+    B.tgs_optimizer_step(Pa, G, Ma, Va, n, dev(touched), op, step)
+    # fused
+    Pb, Mb, Vb = dev(p), dev(m0), dev(v0)
+    B.tgs_project_bwd_optimizer_step(Pb, n, c, brp, radius, clamp, dev(g2d), dev(grad_prev) if prev else None,
+                                     Mb, Vb, dev(touched), op, step,
+                                     torch.empty(B.tgs_project_bwd_optimizer_workspace_size(n), dtype=torch.uint8,
+                                                 device="cuda"))
+    assert (host(radius) == 0).any() and (touched == 0).any()
+    for name, a, b in (("params", Pa, Pb), ("m", Ma, Mb), ("v", Va, Vb)):
+        assert torch.equal(a, b), name
+    assert np.array_equal(host(Pb)[:, touched == 0], p[:, touched == 0])
+
+
 # ------------------------------------------------------------------ optimizer
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_optimizer_parity(B, mode):
