@@ -26,10 +26,78 @@ def test_emit_loop_equals_vectorised():
     _, cam, pr = _scene()
     TX, TY = pr["TX"], pr["TY"]
     valid = np.array([0, 3, 5, 6, 7, 11, TX * TY - 1])
+    fields, tau = binning.splat_fields(pr), binning.cull_threshold(1.0 / 255.0)
     for vt in (None, valid):
-        k1, v1 = binning.emit_pairs(pr["rect"], pr["depth32"], TX, TY, vt)
-        k2, v2 = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY, vt)
-        assert np.array_equal(k1, k2) and np.array_equal(v1, v2)
+        for f, t in ((None, None), (fields, tau)):
+            k1, v1 = binning.emit_pairs(pr["rect"], pr["depth32"], TX, TY, vt, f, t)
+            k2, v2 = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY, vt, f, t)
+            assert np.array_equal(k1, k2) and np.array_equal(v1, v2)
+
+
+def test_cull_threshold():
+    # 2 ln(255) = 11.0825..., plus 0.1 %, rounded up to 1/64
+    assert binning.cull_threshold(1.0 / 255.0) == 710 / 64
+    for a in (1e-3, 1.0 / 255.0, 0.01, 0.1):
+        t = binning.cull_threshold(a)
+        assert 2 * math.log(1 / a) * 1.001 <= t < 2 * math.log(1 / a) * 1.001 + 1 / 64
+        assert (t * 64) == int(t * 64)
+
+
+def test_cull_never_drops_a_compositing_pixel():
+    """Brute force over every pixel centre of every culled rect tile: with
+    the largest opacity (1) the Gaussian's alpha stays below alpha_min."""
+    amin = 1.0 / 255.0
+    tau = binning.cull_threshold(amin)
+    culled_total = 0
+    for seed, lm in ((2, -3.0), (4, -2.5), (6, -3.5)):
+        p = synth.gaussians(400, seed, logscale_mean=lm)
+        cam = synth.look_at((2.0, -1.5, 1.2), fx=105.6, fy=105.6, width=96, height=76)
+        pr = project.project(p, cam)
+        f = binning.splat_fields(pr)
+        gid, tx, ty = binning.rect_tiles(pr["rect"])
+        g = {k: v[gid] for k, v in f.items()}
+        keep = binning.tile_touches(tx, ty, g["xi"], g["xf"], g["yi"], g["yf"], g["A"], g["B"], g["C"], tau)
+        lx, ly = np.meshgrid(np.arange(16.0), np.arange(16.0))
+        for j in np.nonzero(~keep)[0]:
+            dx = (16 * tx[j] + lx) - (g["xi"][j] + g["xf"][j])
+            dy = (16 * ty[j] + ly) - (g["yi"][j] + g["yf"][j])
+            q = g["A"][j] * dx * dx + 2 * g["B"][j] * dx * dy + g["C"][j] * dy * dy
+            assert (np.exp(-0.5 * q) < amin).all()
+        culled_total += int((~keep).sum())
+        assert (~keep).mean() > 0.15          # the test does remove pairs
+    assert culled_total > 100
+
+
+def test_cull_matches_dense_rectangle_minimum():
+    """Random SPD conics and rectangles: the decision agrees with the minimum
+    of q over a dense grid of the rectangle wherever that minimum is clearly
+    below or above tau (a dropped factor, sign or swapped axis fails)."""
+    rng = np.random.default_rng(11)
+    tau = 11.0
+    n_in = n_out = 0
+    for _ in range(400):
+        th = rng.uniform(0, np.pi)
+        s1, s2 = np.exp(rng.uniform(-1, 3, size=2))
+        R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        Sig = R @ np.diag([s1 * s1, s2 * s2]) @ R.T
+        Q = np.linalg.inv(Sig)
+        A, B, C = Q[0, 0], Q[0, 1], Q[1, 1]
+        cx, cy = rng.uniform(-60, 60, size=2)
+        xi, xf = np.floor(cx), cx - np.floor(cx)
+        yi, yf = np.floor(cy), cy - np.floor(cy)
+        tx, ty = rng.integers(-3, 3, size=2)
+        keep = bool(binning.tile_touches(tx, ty, xi, xf, yi, yf, A, B, C, tau))
+        gx = np.linspace(16 * tx, 16 * tx + 15, 301) - cx
+        gy = np.linspace(16 * ty, 16 * ty + 15, 301) - cy
+        X, Y = np.meshgrid(gx, gy)
+        qmin = (A * X * X + 2 * B * X * Y + C * Y * Y).min()
+        if qmin < 0.98 * tau:
+            assert keep
+            n_in += 1
+        elif qmin > 1.05 * tau + 0.5:
+            assert not keep
+            n_out += 1
+    assert n_in > 30 and n_out > 30
 
 
 def test_sort_and_ranges_against_python():
