@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 2u
+#define TGS_ABI_VERSION 3u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
@@ -152,8 +152,16 @@ int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t
 
 /* Tile x depth binning, sort and per-tile ranges (the depth-ordered
  * per-tile Gaussian lists of Eq. alpha_comp, in the tile order of Sec. 3.6).
- *   rect, depth  projection outputs of n Gaussians
+ * A (Gaussian, tile) pair is listed when the tile lies in the Gaussian's
+ * tile rectangle and its pixel-centre rectangle meets the ellipse
+ * q(d) <= tau of the splat's centre and conic (d measured from the centre,
+ * q = a dx^2 + 2 b dx dy + c dy^2, tau = 2 ln(1/alpha_min) x 1.001 rounded
+ * up to a multiple of 1/64): no dropped pair can reach alpha_min at any
+ * pixel of its tile, so the lists composite exactly like the rectangle
+ * lists.
+ *   rect, splat, depth  projection outputs of n Gaussians
  *   tile_slot    nullable: only tiles with tile_slot >= 0 receive pairs
+ *   alpha_min    the compositing threshold (as in tgs_raster_params)
  *   keys         nullable [capacity] uint64: (tile << 32) | bits(depth) of
  *                each sorted pair
  *   vals         [capacity] uint32: Gaussian ids ordered by (tile, depth
@@ -161,14 +169,13 @@ int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t
  *   ranges       [tiles_x * tiles_y][2] uint32 [start, end), [0, 0) if empty
  *   touched      nullable [n] uint8: set to 1 for Gaussians with a pair
  *   n_pairs      host out: number of pairs in valid tiles
- * capacity must hold one entry per tile of the rectangle of every Gaussian
- * that has a pair (valid tile or not); when it does not, the call returns
+ * capacity must hold every listed tile (valid or not) of every Gaussian
+ * that has a pair in a valid tile; when it does not, the call returns
  * TGS_ERR_CAPACITY with that count in *n_pairs and the outputs are
- * unspecified.  Synchronises the
- * stream once (to size the sort). */
+ * unspecified.  Synchronises the stream once (to size the sort). */
 size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32_t n_tiles);
-int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t n,
-                     const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y,
+int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const float* depth, int64_t n,
+                     const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
                      uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges,
                      uint8_t* touched, int64_t* n_pairs, void* ws, size_t ws_bytes,
                      void* stream);

@@ -13,10 +13,12 @@ set of Gaussians that can reach p's tile.  Readings:
   q <= 2 ln(1/alpha_min); tau adds a 0.1 % margin and is rounded up to a
   multiple of 1/64 (cull_threshold), so a culled pair never composites and
   the images and gradients are those of the plain rectangle lists;
-* the test takes the continuous minimum of q over the tile's pixel-centre
-  rectangle (a lower bound of the minimum over its pixel centres) in FP64,
-  with the operation order of tile_touches, so that any implementation of
-  the same order reproduces the decision bit for bit;
+* the test: q at the rectangle point nearest the centre is <= tau, or the
+  closed-form minimum of q along one of the rectangle's edges is; together
+  the continuous minimum of q over the tile's pixel-centre rectangle (a
+  lower bound of the minimum over its pixel centres), in FP64 with the
+  operation order of tile_touches, so that any implementation of the same
+  order reproduces the decision bit for bit;
 * one (key, value) pair per (visible Gaussian, kept tile that is valid for
   this view); emitted in Gaussian-id order, tiles row-major inside the rect;
 * key = (tile_id << 32) | bits(float32(t_z)), tile_id = ty * TX + tx; t_z is
@@ -67,7 +69,8 @@ def tile_touches(tx, ty, xi, xf, yi, yf, A, B, C, tau):
     X1 = (TILE * tx + (TILE - 1) - xi) - xf
     Y0 = (TILE * ty - yi) - yf
     Y1 = (TILE * ty + (TILE - 1) - yi) - yf
-    keep = (X0 <= 0) & (0 <= X1) & (Y0 <= 0) & (0 <= Y1)       # the centre lies in the tile
+    # the point of the rectangle nearest the centre (the centre itself when inside)
+    keep = _quad(A, B, C, np.minimum(np.maximum(0.0, X0), X1), np.minimum(np.maximum(0.0, Y0), Y1)) <= tau
     det = A * C - B * B
     for X in (X0, X1):                                          # vertical edges, y in [Y0, Y1]
         bx = B * X

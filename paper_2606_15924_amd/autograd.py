@@ -45,7 +45,7 @@ class SparseRasterize(torch.autograd.Function):
             vb.P = cam.width * cam.height
         c = B.camera(cam)
         vb.project(params, c, rp)
-        vb.bin_sort()
+        vb.bin_sort(alpha_min=rp.alpha_min)
         vb.render_fwd(rp)
         ctx.vb, ctx.cam, ctx.rp = vb, c, rp
         ctx.save_for_backward(params)

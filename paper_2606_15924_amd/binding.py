@@ -78,7 +78,7 @@ PROTOTYPES = {
     "tgs_sample": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(tgs_sample_params), _P, _P, _P, _P, _P,
                           _P, _SZ, _P]),
     "tgs_bin_sort_workspace_size": (_SZ, [_I64, _I64, _I32]),
-    "tgs_bin_sort": (_I32, [_P, _P, _I64, _P, _I32, _I32, _P, _P, _I64, _P, _P,
+    "tgs_bin_sort": (_I32, [_P, _P, _P, _I64, _P, _I32, _I32, ctypes.c_float, _P, _P, _I64, _P, _P,
                             ctypes.POINTER(_I64), _P, _SZ, _P]),
     "tgs_render_fwd": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
                               ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P]),
@@ -219,13 +219,13 @@ def tgs_bin_sort_workspace_size(n: int, capacity: int, n_tiles: int) -> int:
     return int(lib().tgs_bin_sort_workspace_size(n, capacity, n_tiles))
 
 
-def tgs_bin_sort(rect, depth, n, tile_slot, tiles_x, tiles_y, keys, vals, capacity, ranges, touched,
-                 ws) -> int:
+def tgs_bin_sort(rect, splat, depth, n, tile_slot, tiles_x, tiles_y, alpha_min, keys, vals, capacity, ranges,
+                 touched, ws) -> int:
     """Returns the pair count; raises CapacityError(required) when it exceeds capacity."""
     n_pairs = _I64(0)
-    st = lib().tgs_bin_sort(_ptr(rect), _ptr(depth), n, _ptr(tile_slot), tiles_x, tiles_y, _ptr(keys),
-                            _ptr(vals), capacity, _ptr(ranges), _ptr(touched), ctypes.byref(n_pairs),
-                            _ptr(ws), ws.numel() * ws.element_size(), _stream())
+    st = lib().tgs_bin_sort(_ptr(rect), _ptr(splat), _ptr(depth), n, _ptr(tile_slot), tiles_x, tiles_y,
+                            float(alpha_min), _ptr(keys), _ptr(vals), capacity, _ptr(ranges), _ptr(touched),
+                            ctypes.byref(n_pairs), _ptr(ws), ws.numel() * ws.element_size(), _stream())
     _check(st, "tgs_bin_sort", n_pairs.value)
     return int(n_pairs.value)
 

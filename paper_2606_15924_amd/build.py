@@ -28,6 +28,7 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
     "-Wall",
+    "-Wshadow",
     "-Wno-unused-function",
 ]
 

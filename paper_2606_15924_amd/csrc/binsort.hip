@@ -1,39 +1,43 @@
 // Tile x depth binning, sort and per-tile ranges.
 //
 // The per-tile Gaussian lists must follow (tile, FP32 depth bits, Gaussian
-// id).  Rather than radix-sorting a 64-bit (tile, depth) key with an id for
-// every (Gaussian, tile) pair, the Gaussians are put in (depth, id) order once
-// (a 32-bit sort of n keys) and the pairs are emitted in that order; a
-// stable sort on the tile bits alone then yields the full order.  The pair
-// key is (tile << id_bits) | Gaussian id, usually 32 bits: the id bits only
-// ride along, since a stable sort never compares them.
+// id) and hold only the (Gaussian, tile) pairs whose tile can composite: the
+// tile lies in the Gaussian's 3-sigma rectangle and its pixel-centre
+// rectangle meets the ellipse q(d) <= tau of the stored centre and conic
+// (tile_touches, an FP64 closed-form minimum with a fixed operation order).
+// Rather than radix-sorting a 64-bit (tile, depth) key with an id for every
+// pair, the Gaussians are put in (depth, id) order once (a 32-bit sort of n
+// keys) and the pairs are emitted in that order; a stable sort on the tile
+// bits alone then yields the full order.  The pair key is
+// (tile << id_bits) | Gaussian id, usually 32 bits: the id bits only ride
+// along, since a stable sort never compares them.
 //
-//   count     per Gaussian: rectangle area, visibility, touched flag and the
-//             depth key (culled Gaussians get a key above every depth); the
-//             rectangle's four corners go into a 2-D difference grid, whose
-//             prefix sums are the per-tile pair counts
+//   count     wave-cooperative over the rectangle tiles of 64 Gaussians: the
+//             kept tiles and the kept valid tiles per Gaussian, depth key
+//             (Gaussians without a kept valid tile get a key above every
+//             depth), touched flag
 //   sort      LSD radix sort of (depth key, id) over n: stable, so ties keep
-//             id order; visible Gaussians come first
+//             id order; Gaussians with pairs come first
 //   gather    rectangles and pair counts in depth order, exclusive scan ->
 //             pair offsets and the total (read back once)
-//   ranges    2-D prefix of the difference grid, then a scan over the valid
-//             tiles in tile order: each tile's [start, end)
-//   emit      4096 pairs per workgroup: the Gaussians that start inside the
-//             block mark their first slot in LDS and a max-scan hands every
-//             slot its Gaussian (a load-balanced search); keys are written
-//             coalesced, tiles outside the valid set get the sentinel tile
-//             id n_tiles (after every real tile), and the block's histogram
-//             of the first radix digit is taken on the way
+//   emit      wave-cooperative again over 64 depth-ordered Gaussians: the
+//             same test picks the kept tiles, whose keys are written
+//             contiguously from the wave's first offset; tiles outside the
+//             valid set get the sentinel tile id n_tiles (after every real
+//             tile)
 //   sort      LSD radix sort of the pair keys on the tile bits only; the
-//             last pass writes the ids (and, if asked, the 64-bit keys)
+//             last pass writes the ids, the sorted keys and (if asked) the
+//             64-bit keys
+//   ranges    tile boundaries of the sorted keys -> [start, end) per tile
 //
 // A radix pass is a stable counting sort over blocks of 256 x kItems keys:
-// per-block digit histograms (peer lanes found by a ballot match add their
-// count once), one scan of the digit-major histogram table, and a scatter
-// that ranks the block's keys (each wave owns a contiguous quarter of the
-// block), reorders them by digit in LDS and writes runs of equal digits to
+// per-block digit histograms, one scan of the digit-major histogram table,
+// and a scatter that ranks the block's keys (peer lanes of a digit found by
+// a ballot match; each wave owns a contiguous quarter of the block),
+// reorders them by digit in LDS and writes runs of equal digits to
 // consecutive addresses.
 #include <algorithm>
+#include <cmath>
 #include <utility>
 
 #include "scan.h"
@@ -117,8 +121,8 @@ static void exclusive_scan(const T* in, T* out, int64_t n, T* partials, hipStrea
 
 
 
-// ------------------------------------------------------------------ count
-// Depth key of a culled Gaussian: above every finite positive depth bit pattern.
+// ------------------------------------------------------------------ tile test
+// Depth key of a Gaussian without pairs: above every finite positive depth bit pattern.
 constexpr uint32_t kCulledKey = 0xffffffffu;
 
 // Rectangles are clamped to the tile grid (projection already does so; the
@@ -131,169 +135,271 @@ __device__ __forceinline__ int4 clamp_rect(int4 r, int tiles_x, int tiles_y) {
   return r;
 }
 
-// Difference grid of the pair counts: (tiles_y + 1) x (tiles_x + 1) cells; a
-// Gaussian with a pair adds +1 at (y0, x0) and (y1, x1), -1 at (y0, x1) and
-// (y1, x0), so the 2-D inclusive prefix sum at (ty, tx) counts the rectangles
-// that cover tile (tx, ty).  Each count workgroup accumulates its own grid in
-// LDS and writes it out whole (contended device-wide atomics are slow), and
-// the grids are summed per cell afterwards.  Grids above kLdsCells cells use
-// device atomics on a single grid instead.
-constexpr int kCountThreads = 1024;
-constexpr int kCountBlocks = 64;   // at most; partial grids to sum
-constexpr int kLdsCells = 12288;   // 48 KiB of LDS
+// What the tile test needs of one Gaussian: the stored centre (integer part
+// and fraction) and conic, widened to FP64 (exact).
+struct Ellipse {
+  double xi, xf, yi, yf, A, B, C;
+};
 
-__global__ void __launch_bounds__(kCountThreads) count_kernel(const int4* __restrict__ rect,
-                                                              const float* __restrict__ depth, int64_t n,
-                                                              const int32_t* __restrict__ tile_slot, int tiles_x,
-                                                              int tiles_y, uint32_t* __restrict__ dkeys,
-                                                              uint32_t* __restrict__ dvals,
-                                                              uint8_t* __restrict__ touched,
-                                                              int32_t* __restrict__ partial, bool lds_grid,
-                                                              unsigned long long* __restrict__ valid_total) {
-  __shared__ int32_t s_diff[kLdsCells];
-  __shared__ uint32_t lds[kCountThreads / kWave];
-  const int gw = tiles_x + 1;
-  const int cells = gw * (tiles_y + 1);
-  if (lds_grid) {
-    for (int c = threadIdx.x; c < cells; c += kCountThreads) s_diff[c] = 0;
-    __syncthreads();
+__device__ __forceinline__ Ellipse load_ellipse(const float4* __restrict__ splat, int64_t i) {
+  const float4 p0 = splat[3 * i], p1 = splat[3 * i + 1];
+  return Ellipse{p0.x, p0.z, p0.y, p0.w, p1.x, p1.y, p1.z};
+}
+
+__device__ __forceinline__ double ellipse_q(const Ellipse& e, double x, double y) {
+#pragma clang fp contract(off)
+  return ((e.A * x) * x + ((2.0 * e.B) * x) * y) + (e.C * y) * y;
+}
+
+// Whether the pixel-centre rectangle of tile (tx, ty) meets q <= tau: q at
+// the rectangle point nearest the centre at most tau (most kept tiles stop
+// here), or the closed-form minimum of q along one of the four edges.  A
+// lower bound of the minimum over the pixel centres.
+__device__ __forceinline__ bool tile_touches(const Ellipse& e, int tx, int ty, double tau) {
+#pragma clang fp contract(off)
+  const double X0 = ((double)(kTile * tx) - e.xi) - e.xf;
+  const double X1 = ((double)(kTile * tx + kTile - 1) - e.xi) - e.xf;
+  const double Y0 = ((double)(kTile * ty) - e.yi) - e.yf;
+  const double Y1 = ((double)(kTile * ty + kTile - 1) - e.yi) - e.yf;
+  // the rectangle point nearest the centre (the centre itself when inside)
+  if (ellipse_q(e, fmin(fmax(0.0, X0), X1), fmin(fmax(0.0, Y0), Y1)) <= tau) return true;
+  const double det = e.A * e.C - e.B * e.B;
+  bool keep = false;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {  // vertical edges, y in [Y0, Y1]
+    const double X = s == 0 ? X0 : X1;
+    const double bx = e.B * X;
+    const bool lo = -bx < e.C * Y0;
+    const bool hi = !lo && (-bx > e.C * Y1);
+    keep = keep || ((lo || hi) ? ellipse_q(e, X, lo ? Y0 : Y1) <= tau : (X * X) * det <= tau * e.C);
   }
-  int32_t* gdiff = lds_grid ? s_diff : partial;
-  uint32_t valid_sum = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kCountThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kCountThreads) {
-    const int4 r = clamp_rect(rect[i], tiles_x, tiles_y);
-    const uint32_t area = (uint32_t)((r.z - r.x) * (r.w - r.y));
-    uint32_t valid = 0;
-    if (tile_slot == nullptr) {
-      valid = area;
-    } else {
-      for (int ty = r.y; ty < r.w; ++ty)
-        for (int tx = r.x; tx < r.z; ++tx) valid += tile_slot[ty * tiles_x + tx] >= 0 ? 1u : 0u;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {  // horizontal edges, x in [X0, X1]
+    const double Y = s == 0 ? Y0 : Y1;
+    const double by = e.B * Y;
+    const bool lo = -by < e.A * X0;
+    const bool hi = !lo && (-by > e.A * X1);
+    keep = keep || ((lo || hi) ? ellipse_q(e, lo ? X0 : X1, Y) <= tau : (Y * Y) * det <= tau * e.A);
+  }
+  return keep;
+}
+
+// q = a / b and r = a % b for b > 0: below 2^22 a float estimate of the
+// quotient is off by at most one and is corrected; larger a divide exactly.
+__device__ __forceinline__ void divmod_small(uint32_t a, uint32_t b, uint32_t& q, uint32_t& r) {
+  if (a >= (1u << 22)) {
+    q = a / b;
+    r = a - q * b;
+    return;
+  }
+  int qi = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+  int ri = (int)a - qi * (int)b;
+  if (ri < 0) { --qi; ri += (int)b; }
+  if (ri >= (int)b) { ++qi; ri -= (int)b; }
+  q = (uint32_t)qi;
+  r = (uint32_t)ri;
+}
+
+// Inclusive max-scan over the wave (identity -1): DPP shifts inside rows of
+// 16, then the row broadcasts.
+__device__ __forceinline__ int wave_max_scan(int v) {
+  v = max(v, dpp_i<0x111>(-1, v));  // row_shr:1
+  v = max(v, dpp_i<0x112>(-1, v));  // row_shr:2
+  v = max(v, dpp_i<0x114>(-1, v));  // row_shr:4
+  v = max(v, dpp_i<0x118>(-1, v));  // row_shr:8
+  v = max(v, dpp_i<kDppRowBcast15, 0xa>(-1, v));
+  v = max(v, dpp_i<kDppRowBcast31, 0xc>(-1, v));
+  return v;
+}
+
+// Per-wave LDS slice of a batch of up to 64 Gaussians (one per lane).
+// Keep decisions of a Gaussian's first kBitTiles rectangle tiles (row-major)
+// are stored as bits by the count kernel and read back by emit; larger
+// rectangles are tested again.
+constexpr int kBitWords = 4;
+constexpr uint32_t kBitTiles = 64u * kBitWords;
+
+struct WaveBatch {
+  int4 rect[kWave];
+  uint32_t start[kWave];  // exclusive prefix of the rectangle areas in the batch
+  Ellipse ell[kWave];
+  uint32_t id[kWave];
+  int mark[kWave];
+  uint64_t bits[kWave][kBitWords];
+};
+
+// Wave-cooperative walk over the rectangle tiles of a batch: the tiles are
+// flattened Gaussian by Gaussian, row-major inside each rectangle, and each
+// round hands the next 64 to the lanes.  A Gaussian starting inside the
+// round marks its slot and an inclusive max-scan carries each owner to the
+// following slots, so a lane finds its owner without a search.
+// visit(in, owner lane, tile x, tile y, the tile's row-major index inside the
+// owner's rectangle) is called once per lane and round.
+// The workgroup is the one wave, so the barriers that order the lanes' LDS
+// exchanges are wave barriers; the trip count is uniform.
+template <typename Visit>
+__device__ __forceinline__ void walk_rect_tiles(WaveBatch& wb, uint32_t my_start, uint32_t my_area, uint32_t total,
+                                                Visit&& visit) {
+  const int lane = lane_id();
+  int carry = -1;
+  for (uint32_t f0 = 0; f0 < total; f0 += kWave) {
+    wb.mark[lane] = -1;
+    __syncthreads();
+    if (my_area > 0 && my_start >= f0 && my_start - f0 < (uint32_t)kWave) wb.mark[my_start - f0] = lane;
+    __syncthreads();
+    const int j = max(wave_max_scan(wb.mark[lane]), carry);
+    carry = __builtin_amdgcn_readlane(j, kWave - 1);
+    const uint32_t f = f0 + (uint32_t)lane;
+    const bool in = f < total && j >= 0;  // j >= 0 whenever f < total (the first area > 0 starts at 0)
+    int tx = 0, ty = 0;
+    uint32_t l = 0;
+    if (in) {
+      const int4 r = wb.rect[j];
+      l = f - wb.start[j];
+      uint32_t dy, dx;
+      divmod_small(l, (uint32_t)(r.z - r.x), dy, dx);
+      tx = r.x + (int)dx;
+      ty = r.y + (int)dy;
     }
+    visit(in, in ? j : 0, tx, ty, l);
+    __syncthreads();  // the round's reads and updates before the next round's writes
+  }
+}
+
+// Loads lane's Gaussian into the batch (area 0: no tiles) and returns the
+// batch's tile count; my_start receives the lane's first flat index.
+__device__ __forceinline__ uint32_t load_batch(WaveBatch& wb, int4 r, uint32_t area, const float4* __restrict__ splat,
+                                               uint32_t g, uint32_t& my_start) {
+  const int lane = lane_id();
+  const uint32_t incl = wave_inclusive_scan_u32(area);
+  my_start = incl - area;
+  __syncthreads();  // earlier readers of the batch slots are done
+  wb.rect[lane] = r;
+  wb.start[lane] = my_start;
+  wb.id[lane] = g;
+  if (area > 0) wb.ell[lane] = load_ellipse(splat, g);
+  __syncthreads();
+  return (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+}
+
+// ------------------------------------------------------------------ count
+constexpr int kBinThreads = kWave;  // one wave per workgroup: __syncthreads is a wave barrier
+constexpr int kBinWaves = 1;
+
+// Each workgroup (one wave) takes kCountBatch Gaussians in index order
+// (lanes beyond the batch hold none): fewer tiles per wave, more waves to
+// hide latency.  Per round, the lanes of one owner form a run; its first
+// lane adds the run's kept and kept-valid counts and ORs the run's keep bits
+// into the owner's bit words (one LDS update per owner and round).
+constexpr int kCountBatch = 32;
+
+__global__ void __launch_bounds__(kBinThreads) count_kernel(
+    const int4* __restrict__ rect, const float4* __restrict__ splat, const float* __restrict__ depth, int64_t n,
+    const int32_t* __restrict__ tile_slot, int tiles_x, int tiles_y, double tau, uint32_t* __restrict__ dkeys,
+    uint32_t* __restrict__ dvals, uint32_t* __restrict__ emit_cnt, uint64_t* __restrict__ tile_bits,
+    uint8_t* __restrict__ touched, unsigned long long* __restrict__ totals) {
+  __shared__ WaveBatch wb;
+  __shared__ uint32_t s_kept[kWave], s_valid[kWave];
+  __shared__ uint64_t s_red[1];
+  const int lane = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * kCountBatch + lane;
+  const bool mine = lane < kCountBatch && i < n;
+  int4 r = make_int4(0, 0, 0, 0);
+  if (mine) r = clamp_rect(rect[i], tiles_x, tiles_y);
+  const uint32_t area = (uint32_t)((r.z - r.x) * (r.w - r.y));
+  s_kept[lane] = 0;
+  s_valid[lane] = 0;
+  for (int q = 0; q < kBitWords; ++q) wb.bits[lane][q] = 0;
+  uint32_t my_start;
+  const uint32_t batch_tiles = load_batch(wb, r, area, splat, mine ? (uint32_t)i : 0u, my_start);
+  walk_rect_tiles(wb, my_start, area, batch_tiles, [&](bool in, int j, int tx, int ty, uint32_t l0) {
+    const bool keep = in && tile_touches(wb.ell[j], tx, ty, tau);
+    const bool valid = keep && (tile_slot == nullptr || tile_slot[ty * tiles_x + tx] >= 0);
+    const uint64_t kb = __ballot(keep), vb = __ballot(valid);
+    const int prev = dpp_i<kDppWaveShr1>(-2, j);
+    const bool head = in && prev != j;
+    const uint64_t heads = __ballot(head);
+    if (head) {
+      const uint64_t after = lane == kWave - 1 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+      const int nxt = after ? __builtin_ctzll(after) : kWave;
+      const uint64_t upto = nxt == kWave ? ~0ull : ((1ull << nxt) - 1ull);
+      const uint64_t run = upto & ~((1ull << lane) - 1ull);
+      s_kept[j] += (uint32_t)__popcll(kb & run);
+      s_valid[j] += (uint32_t)__popcll(vb & run);
+      // the run's keep bits, from the owner's local tile index l0 of this lane
+      const uint64_t rb = (kb & run) >> lane;
+      if (rb != 0 && l0 < kBitTiles) {
+        const uint32_t wq = l0 >> 6, sh = l0 & 63;
+        wb.bits[j][wq] |= rb << sh;
+        if (sh != 0 && wq + 1 < (uint32_t)kBitWords) wb.bits[j][wq + 1] |= rb >> (64 - sh);
+      }
+    }
+  });
+  const uint32_t kept = s_kept[lane], valid = s_valid[lane];
+  if (mine) {
     dkeys[i] = valid > 0 ? __float_as_uint(depth[i]) : kCulledKey;
     dvals[i] = (uint32_t)i;
-    if (valid > 0) {
-      atomicAdd(&gdiff[r.y * gw + r.x], 1);
-      atomicAdd(&gdiff[r.y * gw + r.z], -1);
-      atomicAdd(&gdiff[r.w * gw + r.x], -1);
-      atomicAdd(&gdiff[r.w * gw + r.z], 1);
-      if (touched != nullptr) touched[i] = 1;
-    }
-    valid_sum += valid;
+    emit_cnt[i] = valid > 0 ? kept : 0u;  // every kept tile, valid or not, once the Gaussian has a pair
+    if (touched != nullptr && valid > 0) touched[i] = 1;
+    if (valid > 0 && area <= kBitTiles)
+      for (int q = 0; q < kBitWords; ++q) tile_bits[i * kBitWords + q] = wb.bits[lane][q];
   }
-  if (tile_slot != nullptr) {  // pairs in valid tiles, spread over the slots
-    uint32_t tot;
-    block_exclusive_scan<kCountThreads, uint32_t>(valid_sum, lds, &tot);
-    if (threadIdx.x == 0 && tot > 0)
-      atomicAdd(&valid_total[blockIdx.x & (TGS_COUNTER_SLOTS - 1)], (unsigned long long)tot);
-  }
-  if (lds_grid) {
-    __syncthreads();
-    int32_t* out = partial + (int64_t)blockIdx.x * cells;
-    for (int c = threadIdx.x; c < cells; c += kCountThreads) out[c] = s_diff[c];
+  // 64-bit totals, spread over slots: [0] pairs in valid tiles, [1] all
+  // pairs, [2] rectangle tiles of the Gaussians with pairs
+  const uint64_t v3[3] = {valid, valid > 0 ? kept : 0u, valid > 0 ? area : 0u};
+  for (int k = 0; k < 3; ++k) {
+    uint64_t tot;
+    block_exclusive_scan<kBinThreads, uint64_t>(v3[k], s_red, &tot);
+    if (lane == 0 && tot > 0)
+      atomicAdd(&totals[k * TGS_COUNTER_SLOTS + (blockIdx.x & (TGS_COUNTER_SLOTS - 1))], (unsigned long long)tot);
   }
 }
 
-// diff[c] = sum over the partial grids of cell c: 64 cells per workgroup
-// (a lane each), its 8 waves take every 8th grid, then LDS combines them.
-constexpr int kSumWaves = 8;
-
-__global__ void __launch_bounds__(kSumWaves * kWave) diff_sum_kernel(const int32_t* __restrict__ partial,
-                                                                     int n_grids, int cells,
-                                                                     int32_t* __restrict__ diff) {
-  __shared__ int32_t s_part[kSumWaves][kWave];
-  const int lane = lane_id(), wave = threadIdx.x / kWave;
-  const int c = blockIdx.x * kWave + lane;
-  int32_t acc = 0;
-  if (c < cells)
-    for (int b = wave; b < n_grids; b += kSumWaves) acc += partial[(int64_t)b * cells + c];
-  s_part[wave][lane] = acc;
-  __syncthreads();
-  if (wave == 0 && c < cells) {
-    int32_t t = 0;
-#pragma unroll
-    for (int w = 0; w < kSumWaves; ++w) t += s_part[w][lane];
-    diff[c] = t;
-  }
-}
-
-// Rectangles and pair counts in depth order (a Gaussian without a valid tile
-// has the culled key and sits after the visible ones; its count is 0).
+// Rectangles, and the packed (rectangle area << 32) | pair count of each
+// Gaussian in depth order (both zero for Gaussians without pairs); one
+// 64-bit scan then gives the pair offsets and the rectangle-tile offsets.
 __global__ void __launch_bounds__(256) gather_kernel(const uint32_t* __restrict__ perm,
-                                                     const uint32_t* __restrict__ dkeys_sorted,
+                                                     const uint32_t* __restrict__ emit_cnt,
                                                      const int4* __restrict__ rect, int64_t n,
                                                      int tiles_x, int tiles_y,
                                                      int4* __restrict__ rect_sorted,
-                                                     uint32_t* __restrict__ area_sorted) {
+                                                     uint64_t* __restrict__ area_sorted) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const int4 r = clamp_rect(rect[perm[j]], tiles_x, tiles_y);
+  const uint32_t g = perm[j];
+  const int4 r = clamp_rect(rect[g], tiles_x, tiles_y);
+  const uint32_t c = emit_cnt[g];
   rect_sorted[j] = r;
-  area_sorted[j] = dkeys_sorted[j] == kCulledKey ? 0u : (uint32_t)((r.z - r.x) * (r.w - r.y));
+  const uint64_t a = c > 0 ? (uint64_t)((r.z - r.x) * (r.w - r.y)) : 0ull;
+  area_sorted[j] = (a << 32) | c;
 }
 
 // ------------------------------------------------------------------ ranges
-// One workgroup: 2-D inclusive prefix of the difference grid (rows, then
-// columns; in LDS when it fits), then an exclusive scan of the valid tiles'
-// counts in tile order.  Empty and invalid tiles get [0, 0).
-constexpr int kRangeThreads = 1024;
-
-__global__ void __launch_bounds__(kRangeThreads) ranges_kernel(int32_t* __restrict__ diff, int tiles_x,
-                                                               int tiles_y, const int32_t* __restrict__ tile_slot,
-                                                               uint2* __restrict__ ranges) {
-  __shared__ int32_t s_grid[kLdsCells];
-  __shared__ uint32_t lds[kRangeThreads / kWave];
-  const int gw = tiles_x + 1;
-  const int cells = gw * (tiles_y + 1);
-  const bool in_lds = cells <= kLdsCells;
-  int32_t* g = in_lds ? s_grid : diff;
-  if (in_lds) {
-    for (int c = threadIdx.x; c < cells; c += kRangeThreads) s_grid[c] = diff[c];
-    __syncthreads();
+// One thread per sorted pair: a tile boundary writes the start of the new
+// tile and the end of the previous one, the last pair the end of its tile.
+// Sentinel keys (tiles outside the valid set) sit after every real tile and
+// write nothing; empty tiles keep the [0, 0) of the fill.
+template <typename K>
+__global__ void __launch_bounds__(256) ranges_kernel(const K* __restrict__ keys, uint32_t total, int id_bits,
+                                                     uint32_t n_t, uint2* __restrict__ ranges) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const uint32_t t = (uint32_t)(keys[i] >> id_bits);
+  if (i == total - 1 && t < n_t) ranges[t].y = total;
+  if (i == 0) {
+    if (t < n_t) ranges[t].x = 0;
+    return;
   }
-  // rows: one wave per row, 64 columns per step with a wave scan
-  const int lane = lane_id(), wave = threadIdx.x / kWave;
-  for (int y = wave; y < tiles_y; y += kRangeThreads / kWave) {
-    int32_t* row = g + (int64_t)y * gw;
-    int32_t carry = 0;
-    for (int x0 = 0; x0 < tiles_x; x0 += kWave) {
-      const int x = x0 + lane;
-      const int32_t v = x < tiles_x ? row[x] : 0;
-      const int32_t incl = wave_inclusive_scan_i(v) + carry;
-      if (x < tiles_x) row[x] = incl;
-      carry = __shfl(incl, kWave - 1, kWave);
-    }
-  }
-  __syncthreads();
-  // columns: a thread per column
-  for (int x = threadIdx.x; x < tiles_x; x += kRangeThreads) {
-    int32_t acc = 0;
-#pragma unroll 8
-    for (int y = 0; y < tiles_y; ++y) {
-      acc += g[(int64_t)y * gw + x];
-      g[(int64_t)y * gw + x] = acc;
-    }
-  }
-  __syncthreads();
-  const int n_t = tiles_x * tiles_y;
-  uint32_t carry = 0;
-  for (int t0 = 0; t0 < n_t; t0 += kRangeThreads) {
-    const int t = t0 + (int)threadIdx.x;
-    uint32_t c = 0;
-    if (t < n_t && (tile_slot == nullptr || tile_slot[t] >= 0))
-      c = (uint32_t)g[(int64_t)(t / tiles_x) * gw + (t % tiles_x)];
-    uint32_t tot;
-    const uint32_t start = carry + block_exclusive_scan<kRangeThreads, uint32_t>(c, lds, &tot);
-    if (t < n_t) ranges[t] = c > 0 ? make_uint2(start, start + c) : make_uint2(0u, 0u);
-    carry += tot;
-  }
+  const uint32_t tp = (uint32_t)(keys[i - 1] >> id_bits);
+  if (t == tp) return;
+  if (t < n_t) ranges[t].x = i;
+  if (tp < n_t) ranges[tp].y = i;
 }
 
 // ------------------------------------------------------------------ radix sort
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
-constexpr int kPairItems = 16;  // keys per thread of the pair sort (and of emit)
+constexpr int kPairItems = 16;  // keys per thread of the pair sort
 
 // Keys per thread: 16 for large sorts, 4 for small ones (more workgroups).
 static int sort_items(int64_t n) { return n >= (1ll << 20) ? 16 : 4; }
@@ -363,9 +469,9 @@ __global__ void __launch_bounds__(1024) digit_scan_kernel(const uint32_t* __rest
   if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
-// Output of a scatter pass: keys (and values) for the next pass, or, in the
-// last pass of the pair sort, the Gaussian ids carried in the low key bits
-// and optionally the 64-bit (tile << 32) | depth-bits keys.
+// Output of a scatter pass: the keys (and values) for the next pass; in the
+// last pass of the pair sort also the Gaussian ids carried in the low key
+// bits and optionally the 64-bit (tile << 32) | depth-bits keys.
 struct ScatterOut {
   void* keys;
   uint32_t* vals;
@@ -448,14 +554,14 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     if (lp < count) {
       const K kk = s_keys[lp];
       const uint32_t dst = s_gbase[(uint32_t)(kk >> shift) & (kDigits - 1u)] + (uint32_t)lp;
+      ((K*)o.keys)[dst] = kk;
       if (kFinal) {
         const uint32_t g = (uint32_t)(kk & (((K)1 << o.id_bits) - 1));
         o.vals[dst] = g;
         if (o.keys64 != nullptr)
           o.keys64[dst] = ((uint64_t)(kk >> o.id_bits) << 32) | (uint64_t)__float_as_uint(o.depth[g]);
-      } else {
-        ((K*)o.keys)[dst] = kk;
-        if (kVals) o.vals[dst] = s_vals[lp];
+      } else if (kVals) {
+        o.vals[dst] = s_vals[lp];
       }
     }
   }
@@ -496,143 +602,91 @@ static int pass_bits(int bits, int p) {
 }
 
 // ------------------------------------------------------------------ emit
-constexpr int kEmitThreads = kSortThreads;
-constexpr int kEmitTile = kSortThreads * kPairItems;  // = a pair-sort block
-constexpr int kEmitWin = 512;                          // Gaussians staged in LDS per block
-
-// block_j0[b]: the Gaussian (depth position) holding pair b * kEmitTile.
-__global__ void __launch_bounds__(256) block_start_kernel(const uint32_t* __restrict__ off, int64_t n,
-                                                          int32_t* __restrict__ block_j0) {
+// The Gaussians with pairs (a prefix of the depth order) are split into
+// windows of about `win` rectangle tiles: window w owns the Gaussians whose
+// first rectangle tile falls in [w win, (w + 1) win), so every wave walks a
+// similar number of tiles whatever the size of its Gaussians.
+// win_first[w] = first Gaussian of window w; win_first[n_win] = the number
+// of Gaussians with pairs.
+__global__ void __launch_bounds__(256) window_kernel(const uint64_t* __restrict__ off, int64_t n, uint32_t win,
+                                                    uint32_t n_win, int32_t* __restrict__ win_first) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
-  const uint32_t a = off[j], e = off[j + 1];
-  for (uint32_t b = (uint32_t)ceil_div(a, kEmitTile); (uint64_t)b * kEmitTile < e; ++b) block_j0[b] = (int32_t)j;
+  const uint32_t rs = (uint32_t)(off[j] >> 32), re = (uint32_t)(off[j + 1] >> 32);
+  if (re == rs) return;  // no pairs (only at the end of the depth order)
+  const uint32_t prev = j == 0 ? 0u : (uint32_t)(off[j - 1] >> 32);
+  const uint32_t w0 = j == 0 ? 0u : prev / win + 1u;  // windows whose boundary lies in (prev, rs]
+  for (uint32_t w = w0; w <= rs / win && w <= n_win; ++w) win_first[w] = (int32_t)j;
+  const bool last = j + 1 == n || (uint32_t)(off[j + 2 > n ? n : j + 2] >> 32) == re;
+  if (last)
+    for (uint32_t w = rs / win + 1u; w <= n_win; ++w) win_first[w] = (int32_t)(j + 1);
 }
 
-// q = a / b and r = a % b for b > 0: below 2^22 a float estimate of the
-// quotient is off by at most one and is corrected; larger a divide exactly.
-__device__ __forceinline__ void divmod_small(uint32_t a, uint32_t b, uint32_t& q, uint32_t& r) {
-  if (a >= (1u << 22)) {
-    q = a / b;
-    r = a - q * b;
-    return;
-  }
-  int qi = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
-  int ri = (int)a - qi * (int)b;
-  if (ri < 0) { --qi; ri += (int)b; }
-  if (ri >= (int)b) { ++qi; ri -= (int)b; }
-  q = (uint32_t)qi;
-  r = (uint32_t)ri;
-}
-
-// Pairs [p0, p0 + kEmitTile) of the depth-ordered pair list.  The Gaussians
-// that start inside the block (and j0, which holds p0) mark their first slot
-// with their index relative to j0 and stage rectangle, offset and id in LDS;
-// an inclusive max-scan then gives every slot its Gaussian.  Every
-// Gaussian before the culled tail has at least one pair, so the marked
-// slots are distinct.
-template <typename K, int kBits0>
-__global__ void __launch_bounds__(kEmitThreads) emit_kernel(
-    const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ ids_sorted,
-    const uint32_t* __restrict__ off, const int32_t* __restrict__ block_j0, int64_t n, uint32_t total,
-    const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t, int id_bits, K* __restrict__ keys,
-    int nblocks, uint32_t* __restrict__ hist) {
-  constexpr int kDigits = 1 << kBits0;
-  __shared__ int32_t s_j[kEmitTile];
-  __shared__ int4 s_rect[kEmitWin];
-  __shared__ uint32_t s_off[kEmitWin];
-  __shared__ uint32_t s_id[kEmitWin];
-  __shared__ uint32_t s_h[kDigits];
-  __shared__ int32_t s_red[kEmitThreads / kWave];
-  const int tid = threadIdx.x;
-  const uint32_t p0 = blockIdx.x * (uint32_t)kEmitTile;
-  const uint32_t p_end = min(total, p0 + (uint32_t)kEmitTile);
-  for (int i = tid; i < kEmitTile; i += kEmitThreads) s_j[i] = -1;
-  for (int i = tid; i < kDigits; i += kEmitThreads) s_h[i] = 0;
-  const int64_t j0 = block_j0[blockIdx.x];
-  __syncthreads();
-  for (int jb = 0;; jb += kEmitThreads) {
-    const int jl = jb + tid;
-    const int64_t j = j0 + jl;
-    bool in = false;
-    if (j < n) {
-      const uint32_t o = off[j];
-      in = jl == 0 || o < p_end;
-      if (in) {
-        s_j[jl == 0 ? 0 : (int)(o - p0)] = jl;
-        if (jl < kEmitWin) {
-          s_rect[jl] = rect_sorted[j];
-          s_off[jl] = o;
-          s_id[jl] = ids_sorted[j];
-        }
-      }
+// A wave per window, 64 Gaussians per batch: their kept tiles (the count
+// kernel's decisions, stored as bits, or its test repeated for rectangles
+// above kBitTiles tiles) are keyed and written contiguously from the
+// batch's first pair offset in emission order (Gaussian, then row-major
+// tile), a ballot prefix placing each lane's key.
+template <typename K>
+__global__ void __launch_bounds__(kBinThreads) emit_kernel(
+    const int4* __restrict__ rect_sorted, const uint64_t* __restrict__ off, const int32_t* __restrict__ win_first,
+    uint32_t n_win, const uint32_t* __restrict__ ids_sorted, const float4* __restrict__ splat,
+    const uint64_t* __restrict__ tile_bits, const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t,
+    int id_bits, double tau, uint32_t total, K* __restrict__ keys) {
+  __shared__ WaveBatch wb;
+  const int lane = lane_id();
+  const uint32_t w = blockIdx.x;
+  if (w >= n_win) return;
+  const int64_t j_end = win_first[w + 1];
+  for (int64_t b0 = win_first[w]; b0 < j_end; b0 += kWave) {
+    const int64_t j = b0 + lane;
+    int4 r = make_int4(0, 0, 0, 0);
+    uint32_t g = 0;
+    if (j < j_end) {
+      r = rect_sorted[j];
+      g = ids_sorted[j];
     }
-    if (__syncthreads_count(in) == 0) break;
-  }
-  // inclusive max-scan: thread t owns slots [t * kPairItems, (t + 1) * kPairItems)
-  int32_t run = -1;
-#pragma unroll
-  for (int k = 0; k < kPairItems; ++k) run = max(run, s_j[tid * kPairItems + k]);
-  {
-    const int lane = lane_id(), wave = tid / kWave;
-    int32_t incl = run;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int32_t t = __shfl_up(incl, o, kWave);
-      if (lane >= o) incl = max(incl, t);
-    }
-    if (lane == kWave - 1) s_red[wave] = incl;
+    const uint32_t area = (uint32_t)((r.z - r.x) * (r.w - r.y));
+    uint64_t bits[kBitWords] = {0, 0, 0, 0};
+    if (area > 0 && area <= kBitTiles)
+      for (int q = 0; q < kBitWords; ++q) bits[q] = tile_bits[(int64_t)g * kBitWords + q];
+    uint32_t my_start;
+    const uint32_t batch_tiles = load_batch(wb, r, area, splat, g, my_start);  // barrier: old slots free
+    for (int q = 0; q < kBitWords; ++q) wb.bits[lane][q] = bits[q];
     __syncthreads();
-    int32_t prev = __shfl_up(incl, 1, kWave);
-    if (lane == 0) prev = -1;
-    for (int w = 0; w < wave; ++w) prev = max(prev, s_red[w]);
-    run = prev;
-  }
-#pragma unroll
-  for (int k = 0; k < kPairItems; ++k) {
-    run = max(run, s_j[tid * kPairItems + k]);
-    s_j[tid * kPairItems + k] = run;
-  }
-  __syncthreads();
-#pragma unroll 4
-  for (int k = 0; k < kPairItems; ++k) {
-    const int lp = k * kEmitThreads + tid;
-    const uint32_t p = p0 + (uint32_t)lp;
-    if (p < p_end) {
-      const int32_t jl = s_j[lp];
-      int4 r;
-      uint32_t o, g;
-      if (jl < kEmitWin) {
-        r = s_rect[jl];
-        o = s_off[jl];
-        g = s_id[jl];
-      } else {
-        const int64_t j = j0 + jl;
-        r = rect_sorted[j];
-        o = off[j];
-        g = ids_sorted[j];
+    const uint32_t base = (uint32_t)off[b0];  // pair offset of the batch's first Gaussian
+    uint32_t written = 0;                     // wave-uniform
+    walk_rect_tiles(wb, my_start, area, batch_tiles, [&](bool in, int jl, int tx, int ty, uint32_t l) {
+      bool keep = false;
+      if (in) {
+        const int4 rj = wb.rect[jl];
+        if ((uint32_t)((rj.z - rj.x) * (rj.w - rj.y)) <= kBitTiles)
+          keep = (wb.bits[jl][l >> 6] >> (l & 63)) & 1ull;  // the count kernel's decision
+        else
+          keep = tile_touches(wb.ell[jl], tx, ty, tau);
       }
-      uint32_t dy, dx;
-      divmod_small(p - o, (uint32_t)(r.z - r.x), dy, dx);
-      uint32_t tile = ((uint32_t)r.y + dy) * (uint32_t)tiles_x + (uint32_t)r.x + dx;
-      if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
-      keys[p] = ((K)tile << id_bits) | (K)g;
-      atomicAdd(&s_h[tile & (kDigits - 1u)], 1u);
-    }
+      const uint64_t kb = __ballot(keep);
+      const uint32_t pos = base + written + (uint32_t)mask_rank(kb);
+      if (keep && pos < total) {  // pos < total always (the count kernel's test); the bound is a safeguard
+        uint32_t tile = (uint32_t)(ty * tiles_x + tx);
+        if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
+        keys[pos] = ((K)tile << id_bits) | (K)wb.id[jl];
+      }
+      written += (uint32_t)__popcll(kb);
+    });
   }
-  __syncthreads();
-  for (int dg = tid; dg < kDigits; dg += kEmitThreads) hist[(int64_t)dg * nblocks + blockIdx.x] = s_h[dg];
 }
 
 // ------------------------------------------------------------------ workspace
 struct SortWs {
-  unsigned long long* scalars;  // [TGS_COUNTER_SLOTS] partial valid-pair totals
-  int32_t* diff;                // [cells] difference grid, cells = (tiles_y + 1) * (tiles_x + 1)
-  int32_t* partial;             // [kCountBlocks][cells] per-workgroup grids
-  int32_t* block_j0;            // [max_blocks] first Gaussian of each emit block
+  unsigned long long* scalars;  // [3][TGS_COUNTER_SLOTS] partial totals: valid pairs, pairs, rect tiles
+  uint32_t* emit_cnt;           // [n] pairs each Gaussian emits
+  uint64_t* tile_bits;          // [n][kBitWords] keep decisions of the first kBitTiles rectangle tiles
   int4* rect_sorted;            // [n] rectangles in depth order
-  uint32_t* area_sorted;        // [n] pair counts in depth order
-  uint32_t* off;                // [n + 1] pair offsets in depth order
+  uint64_t* area_sorted;        // [n] (rectangle area << 32) | pair count, depth order
+  uint64_t* off;                // [n + 1] its exclusive prefix: rectangle-tile and pair offsets
+  uint64_t* partials64;         // scan block sums of the offsets
+  int32_t* win_first;           // [max_windows + 1] first Gaussian of each emit window
   uint32_t* dkeys[2];           // [n] depth keys (ping-pong)
   uint32_t* dvals[2];           // [n] ids
   uint32_t* partials;           // scan block sums, digit totals
@@ -642,15 +696,16 @@ struct SortWs {
   size_t bytes;
 };
 
-static SortWs layout(void* ws, int64_t n, int64_t capacity, int64_t n_tiles) {
+// Emit windows: at most n / 16 + 1024, of at least 4096 rectangle tiles.
+static int64_t max_windows(int64_t n) { return n / 16 + 1024; }
+
+static SortWs layout(void* ws, int64_t n, int64_t capacity) {
   const int64_t cap = std::max<int64_t>(capacity, 1), nn = std::max<int64_t>(n, 1);
   const int64_t m = std::max(cap, nn);
   // blocks of any sort of up to m keys: 1024-key blocks below 2^20 keys, 4096-key blocks above
   const int64_t max_blocks = std::max<int64_t>(1024, sort_blocks(m, kPairItems)) + 1;
   const int64_t hist_n = 256 * max_blocks;
   const int64_t part_n = std::max<int64_t>(256, scan_partials(nn + 1)) + 1;
-  // (tiles_x + 1)(tiles_y + 1) <= 2 n_tiles + 2 for any grid of n_tiles tiles
-  const int64_t diff_n = 2 * std::max<int64_t>(n_tiles, 1) + 2;
   size_t o = 0;
   char* b = (char*)ws;
   auto take = [&](size_t bytes) {
@@ -659,13 +714,14 @@ static SortWs layout(void* ws, int64_t n, int64_t capacity, int64_t n_tiles) {
     return (void*)p;
   };
   SortWs w;
-  w.scalars = (unsigned long long*)take(sizeof(unsigned long long) * TGS_COUNTER_SLOTS);
-  w.diff = (int32_t*)take(sizeof(int32_t) * diff_n);
-  w.partial = (int32_t*)take(sizeof(int32_t) * diff_n * kCountBlocks);
-  w.block_j0 = (int32_t*)take(sizeof(int32_t) * max_blocks);
+  w.scalars = (unsigned long long*)take(sizeof(unsigned long long) * 3 * TGS_COUNTER_SLOTS);
+  w.emit_cnt = (uint32_t*)take(sizeof(uint32_t) * nn);
+  w.tile_bits = (uint64_t*)take(sizeof(uint64_t) * kBitWords * nn);
   w.rect_sorted = (int4*)take(sizeof(int4) * nn);
-  w.area_sorted = (uint32_t*)take(sizeof(uint32_t) * nn);
-  w.off = (uint32_t*)take(sizeof(uint32_t) * (nn + 1));
+  w.area_sorted = (uint64_t*)take(sizeof(uint64_t) * nn);
+  w.off = (uint64_t*)take(sizeof(uint64_t) * (nn + 1));
+  w.partials64 = (uint64_t*)take(sizeof(uint64_t) * part_n);
+  w.win_first = (int32_t*)take(sizeof(int32_t) * (max_windows(nn) + 1));
   for (int k = 0; k < 2; ++k) {
     w.dkeys[k] = (uint32_t*)take(sizeof(uint32_t) * nn);
     w.dvals[k] = (uint32_t*)take(sizeof(uint32_t) * nn);
@@ -701,40 +757,34 @@ static void sort_depth(const SortWs& w, uint32_t n, uint32_t** keys_out, uint32_
 }
 
 template <typename K>
-static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t total, const int32_t* tile_slot,
-                       int tiles_x, uint32_t n_t, int id_bits, int tbits, const float* depth, uint32_t* vals,
-                       uint64_t* keys64, hipStream_t s) {
+static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t total, uint32_t rect_total,
+                       const float4* splat, const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits,
+                       int tbits, double tau, const float* depth, uint32_t* vals, uint64_t* keys64,
+                       uint32_t* ranges, hipStream_t s) {
   K* kb[2] = {(K*)w.pkeys[0], (K*)w.pkeys[1]};
-  const int nblocks = (int)sort_blocks(total, kPairItems);
-  hipLaunchKernelGGL(block_start_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, w.off, n, w.block_j0);
+  const uint32_t win = (uint32_t)std::max<int64_t>(4096, ceil_div((int64_t)rect_total, max_windows(n)));
+  const uint32_t n_win = (uint32_t)ceil_div((int64_t)rect_total, (int64_t)win);
+  hipLaunchKernelGGL(window_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, w.off, n, win, n_win,
+                     w.win_first);
+  hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(n_win, kBinWaves)), dim3(kBinThreads), 0, s,
+                     w.rect_sorted, w.off, w.win_first, n_win, ids, splat, w.tile_bits, tile_slot, tiles_x, n_t,
+                     id_bits, tau, total, kb[0]);
   const int passes = pass_count(tbits);
-  const int b0 = pass_bits(tbits, 0);
-  switch (b0) {
-#define TGS_EMIT(B)                                                                                          \
-  case B:                                                                                                    \
-    hipLaunchKernelGGL((emit_kernel<K, B>), dim3(nblocks), dim3(kEmitThreads), 0, s, w.rect_sorted, ids,     \
-                       w.off, w.block_j0, n, total, tile_slot, tiles_x, n_t, id_bits, kb[0], nblocks, w.hist); \
-    break;
-    TGS_EMIT(1) TGS_EMIT(2) TGS_EMIT(3) TGS_EMIT(4) TGS_EMIT(5) TGS_EMIT(6) TGS_EMIT(7)
-    default:
-      hipLaunchKernelGGL((emit_kernel<K, 8>), dim3(nblocks), dim3(kEmitThreads), 0, s, w.rect_sorted, ids, w.off,
-                         w.block_j0, n, total, tile_slot, tiles_x, n_t, id_bits, kb[0], nblocks, w.hist);
-#undef TGS_EMIT
-  }
   int cur = 0, shift = id_bits;
   for (int p = 0; p < passes; ++p) {
     const int b = pass_bits(tbits, p);
-    const bool last = p == passes - 1;
     const ScatterOut o = {kb[cur ^ 1], vals, id_bits, depth, keys64};
-    if (last)
-      radix_pass_bits<K, false, true, kPairItems>(b, kb[cur], nullptr, total, shift, p == 0, w.hist, w.hoffs,
+    if (p == passes - 1)
+      radix_pass_bits<K, false, true, kPairItems>(b, kb[cur], nullptr, total, shift, false, w.hist, w.hoffs,
                                                   w.partials, o, s);
     else
-      radix_pass_bits<K, false, false, kPairItems>(b, kb[cur], nullptr, total, shift, p == 0, w.hist, w.hoffs,
+      radix_pass_bits<K, false, false, kPairItems>(b, kb[cur], nullptr, total, shift, false, w.hist, w.hoffs,
                                                    w.partials, o, s);
     cur ^= 1;
     shift += b;
   }
+  hipLaunchKernelGGL((ranges_kernel<K>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, kb[cur], total,
+                     id_bits, n_t, (uint2*)ranges);
 }
 
 }  // namespace tgs
@@ -742,12 +792,13 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
 using namespace tgs;
 
 extern "C" size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32_t n_tiles) {
-  if (n < 0 || capacity < 0 || n_tiles < 0) return 0;
-  return layout(nullptr, n, capacity, n_tiles).bytes;
+  (void)n_tiles;
+  if (n < 0 || capacity < 0) return 0;
+  return layout(nullptr, n, capacity).bytes;
 }
 
-extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t n,
-                                const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y,
+extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const float* depth, int64_t n,
+                                const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
                                 uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges,
                                 uint8_t* touched, int64_t* n_pairs, void* ws, size_t ws_bytes,
                                 void* stream) {
@@ -755,67 +806,63 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* depth, int64_t
   TGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && (int64_t)tiles_x * tiles_y < (1ll << 30),
               "tgs_bin_sort: bad tile grid");
   TGS_REQUIRE(capacity >= 0 && capacity < (1ll << 32), "tgs_bin_sort: capacity out of range");
+  TGS_REQUIRE(alpha_min > 0.f && alpha_min < 1.f, "tgs_bin_sort: alpha_min %g not in (0, 1)", (double)alpha_min);
   TGS_REQUIRE(vals && ranges && n_pairs && ws, "tgs_bin_sort: null pointer");  // keys may be null
-  TGS_REQUIRE(n == 0 || (rect && depth), "tgs_bin_sort: null rect/depth");
-  TGS_REQUIRE(((uintptr_t)rect & 15) == 0, "tgs_bin_sort: rect must be 16-byte aligned");
+  TGS_REQUIRE(n == 0 || (rect && splat && depth), "tgs_bin_sort: null rect/splat/depth");
+  TGS_REQUIRE(((uintptr_t)rect & 15) == 0 && ((uintptr_t)splat & 15) == 0,
+              "tgs_bin_sort: rect and splat must be 16-byte aligned");
   const uint32_t n_t = (uint32_t)tiles_x * (uint32_t)tiles_y;
-  const SortWs w = layout(ws, n, capacity, n_t);
-  TGS_REQUIRE(ws_bytes >= w.bytes, "tgs_bin_sort: workspace %zu bytes < %zu (is n_tiles right?)", ws_bytes,
-              w.bytes);
+  const SortWs w = layout(ws, n, capacity);
+  TGS_REQUIRE(ws_bytes >= w.bytes, "tgs_bin_sort: workspace %zu bytes < %zu", ws_bytes, w.bytes);
   hipStream_t s = as_stream(stream);
-  const int cells = (tiles_x + 1) * (tiles_y + 1);
-  const bool lds_grid = cells <= kLdsCells;
-  const int count_blocks = lds_grid ? (int)std::min<int64_t>(kCountBlocks, std::max<int64_t>(1, ceil_div(n, kCountThreads)))
-                                    : (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kCountThreads), 1024));
-  if (!lds_grid)  // one grid accumulated with device atomics
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(cells, 256)), dim3(256), 0, s,
-                       (uint32_t*)w.partial, (int64_t)cells, 0u);
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s, (uint32_t*)w.scalars,
-                     (int64_t)(2 * TGS_COUNTER_SLOTS), 0u);
-  const int n_grids = n == 0 ? 0 : (lds_grid ? count_blocks : 1);
-  if (n > 0)
-    hipLaunchKernelGGL(count_kernel, dim3((unsigned)count_blocks), dim3(kCountThreads), 0, s, (const int4*)rect,
-                       depth, n, tile_slot, tiles_x, tiles_y, w.dkeys[0], w.dvals[0], touched, w.partial, lds_grid,
-                       w.scalars);
-  hipLaunchKernelGGL(diff_sum_kernel, dim3((unsigned)ceil_div(cells, kWave)), dim3(kSumWaves * kWave), 0, s,
-                     w.partial, n_grids, cells, w.diff);
-  hipLaunchKernelGGL(ranges_kernel, dim3(1), dim3(kRangeThreads), 0, s, w.diff, tiles_x, tiles_y, tile_slot,
-                     (uint2*)ranges);
+  // 2 ln(1/alpha_min) with a 0.1 % margin, rounded up to a multiple of 1/64
+  const double tau = std::ceil(128.0 * std::log(1.0 / (double)alpha_min) * 1.001) / 64.0;
+
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t, 256)), dim3(256), 0, s, ranges,
+                     2 * (int64_t)n_t, 0u);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(6 * TGS_COUNTER_SLOTS, 256)), dim3(256), 0, s,
+                     (uint32_t*)w.scalars, (int64_t)(6 * TGS_COUNTER_SLOTS), 0u);
   if (n == 0) {
     *n_pairs = 0;
     return hip_status("tgs_bin_sort");
   }
-  // (depth, id) order; culled Gaussians last
+  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kBinThreads), 0, s,
+                     (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau,
+                     w.dkeys[0], w.dvals[0], w.emit_cnt, w.tile_bits, touched, w.scalars);
+  // (depth, id) order; Gaussians without pairs last
   uint32_t* dk = nullptr;
   uint32_t* perm = nullptr;
   if (sort_items(n) == 16) sort_depth<16>(w, (uint32_t)n, &dk, &perm, s);
   else sort_depth<4>(w, (uint32_t)n, &dk, &perm, s);
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, perm, dk,
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, perm, w.emit_cnt,
                      (const int4*)rect, n, tiles_x, tiles_y, w.rect_sorted, w.area_sorted);
-  exclusive_scan<uint32_t>(w.area_sorted, w.off, n, w.partials, s);
-  uint32_t total = 0;
-  unsigned long long slots[TGS_COUNTER_SLOTS] = {};
-  if (hipMemcpyAsync(&total, w.off + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      (tile_slot != nullptr &&
-       hipMemcpyAsync(slots, w.scalars, sizeof(slots), hipMemcpyDeviceToHost, s) != hipSuccess) ||
+  exclusive_scan<uint64_t>(w.area_sorted, w.off, n, w.partials64, s);
+  unsigned long long slots[3 * TGS_COUNTER_SLOTS] = {};
+  if (hipMemcpyAsync(slots, w.scalars, sizeof(slots), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return hip_status("tgs_bin_sort: count readback");
-  unsigned long long valid_total = 0;
-  for (int k = 0; k < TGS_COUNTER_SLOTS; ++k) valid_total += slots[k];
-  if (tile_slot == nullptr) valid_total = total;
-  if ((int64_t)total > capacity) {
-    *n_pairs = (int64_t)total;
-    set_error("tgs_bin_sort: %u pairs exceed capacity %lld", total, (long long)capacity);
+  unsigned long long sum[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k)
+    for (int q = 0; q < TGS_COUNTER_SLOTS; ++q) sum[k] += slots[k * TGS_COUNTER_SLOTS + q];
+  const unsigned long long valid_total = sum[0], total64 = sum[1], rect64 = sum[2];
+  if ((int64_t)total64 > capacity) {
+    *n_pairs = (int64_t)total64;
+    set_error("tgs_bin_sort: %llu pairs exceed capacity %lld", total64, (long long)capacity);
     return TGS_ERR_CAPACITY;
   }
+  // the packed 64-bit offsets hold both prefixes while each total fits 32 bits
+  TGS_REQUIRE(rect64 < (1ull << 32), "tgs_bin_sort: %llu rectangle tiles exceed 2^32", rect64);
+  const uint32_t total = (uint32_t)total64, rect_total = (uint32_t)rect64;
   *n_pairs = (int64_t)valid_total;
   if (total == 0) return hip_status("tgs_bin_sort");
 
   const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
   const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
   if (id_bits + tbits <= 32)
-    sort_pairs<uint32_t>(w, perm, n, total, tile_slot, tiles_x, n_t, id_bits, tbits, depth, vals, keys, s);
+    sort_pairs<uint32_t>(w, perm, n, total, rect_total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+                         tbits, tau, depth, vals, keys, ranges, s);
   else
-    sort_pairs<uint64_t>(w, perm, n, total, tile_slot, tiles_x, n_t, id_bits, tbits, depth, vals, keys, s);
+    sort_pairs<uint64_t>(w, perm, n, total, rect_total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+                         tbits, tau, depth, vals, keys, ranges, s);
   return hip_status("tgs_bin_sort");
 }

@@ -105,13 +105,13 @@ class ViewBuffers:
         """Binning reads the tile map only when the sampler keeps a subset of tiles."""
         return self.tile_slot is not None and self.n_st < self.n_t
 
-    def bin_sort(self, touched=None) -> int:
+    def bin_sort(self, touched=None, alpha_min: float = 1.0 / 255.0) -> int:
         # every tile is valid when the sampler keeps all of them: no tile map needed
         tile_slot = self.tile_slot if self.bin_sort_needs_samples() else None
         while True:
             try:
-                self.n_pairs = B.tgs_bin_sort(self.rect, self.depth, self.n, tile_slot, self.tiles_x,
-                                              self.tiles_y, self.keys, self.vals, self.capacity,
+                self.n_pairs = B.tgs_bin_sort(self.rect, self.splat, self.depth, self.n, tile_slot, self.tiles_x,
+                                              self.tiles_y, alpha_min, self.keys, self.vals, self.capacity,
                                               self.ranges, touched, self.sort_ws)
                 return self.n_pairs
             except B.CapacityError as e:
@@ -198,7 +198,7 @@ class Trainer:
             cam = self.cams[v]
             vb = ViewBuffers(self.n, cam.width, cam.height, None, -1, self.dev)
             vb.project(self.params, cam, self.rp)
-            vb.bin_sort()
+            vb.bin_sort(alpha_min=self.rp.alpha_min)
             vb.render_fwd(self.rp)
             B.tgs_error_init(vb.out, self.gts[v], cam.height, cam.width, self.E[v])
 
@@ -236,7 +236,7 @@ class Trainer:
                 main.wait_event(sampled)
                 waited = True
             with st("bin_sort"):
-                vb.bin_sort(self.touched)
+                vb.bin_sort(self.touched, self.rp.alpha_min)
             if not waited:
                 main.wait_event(sampled)
                 waited = True

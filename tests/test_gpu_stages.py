@@ -102,21 +102,26 @@ def test_bin_sort_bit_exact(B, case):
         ts = -np.ones(TX * TY, dtype=np.int32)
         ts[valid] = np.arange(valid.size)
         tile_slot = dev(ts)
-    keys, vals = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY, valid)
+    fields, tau = binning.splat_fields(pr), binning.cull_threshold(1.0 / 255.0)
+    keys, vals = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY, valid, fields, tau)
     sk, sv = binning.sort_pairs(keys, vals)
     ranges = binning.tile_ranges(sk, TX * TY)
     rect = dev(pr["rect"].T.astype(np.int32))
+    splat = dev(splat_record(pr))
     depth = dev(pr["depth32"])
-    # one entry per tile of the rectangle of each Gaussian with a pair, valid tile or not
-    rect_area = (pr["rect"][2] - pr["rect"][0]) * (pr["rect"][3] - pr["rect"][1])
-    area = int(rect_area[np.unique(sv)].sum())
+    # one entry per kept tile (valid or not) of each Gaussian with a pair
+    gid, _, _ = binning.kept_tiles(pr["rect"], fields, tau)
+    kept = np.bincount(gid, minlength=n)
+    area = int(kept[np.unique(sv)].sum())
     cap = area + 17
+    rect_area = (pr["rect"][2] - pr["rect"][0]) * (pr["rect"][3] - pr["rect"][1])
+    assert area < int(rect_area[np.unique(sv)].sum())      # the ellipse test drops pairs
     K = torch.empty(cap, dtype=torch.int64, device="cuda")
     V = torch.empty(cap, dtype=torch.int32, device="cuda")
     R = torch.empty((TX * TY, 2), dtype=torch.int32, device="cuda")
     touched = torch.zeros(n, dtype=torch.uint8, device="cuda")
     ws = torch.empty(B.tgs_bin_sort_workspace_size(n, cap, TX * TY), dtype=torch.uint8, device="cuda")
-    npairs = B.tgs_bin_sort(rect, depth, n, tile_slot, TX, TY, K, V, cap, R, touched, ws)
+    npairs = B.tgs_bin_sort(rect, splat, depth, n, tile_slot, TX, TY, 1.0 / 255.0, K, V, cap, R, touched, ws)
     assert npairs == sk.size
     assert np.array_equal(host(K)[:npairs].view(np.uint64), sk)
     assert np.array_equal(host(V)[:npairs].view(np.uint32), sv)
@@ -126,7 +131,7 @@ def test_bin_sort_bit_exact(B, case):
     assert np.array_equal(host(touched), t_ref)
     # too-small capacity reports the required count
     with pytest.raises(B.CapacityError) as ei:
-        B.tgs_bin_sort(rect, depth, n, tile_slot, TX, TY, K, V, 10, R, None, ws)
+        B.tgs_bin_sort(rect, splat, depth, n, tile_slot, TX, TY, 1.0 / 255.0, K, V, 10, R, None, ws)
     assert ei.value.required == area
 
 
