@@ -13,12 +13,12 @@ set of Gaussians that can reach p's tile.  Readings:
   q <= 2 ln(1/alpha_min); tau adds a 0.1 % margin and is rounded up to a
   multiple of 1/64 (cull_threshold), so a culled pair never composites and
   the images and gradients are those of the plain rectangle lists;
-* the test: q at the rectangle point nearest the centre is <= tau, or the
-  closed-form minimum of q along one of the rectangle's edges is; together
-  the continuous minimum of q over the tile's pixel-centre rectangle (a
-  lower bound of the minimum over its pixel centres), in FP64 with the
-  operation order of tile_touches, so that any implementation of the same
-  order reproduces the decision bit for bit;
+* the test: q at the rectangle point P nearest the centre is <= tau, or the
+  closed-form minimum of q along one of the (at most two) edges through P
+  that face the centre is; together the continuous minimum of q over the
+  tile's pixel-centre rectangle (a lower bound of the minimum over its pixel
+  centres), in FP64 with the operation order of tile_touches, so that any
+  implementation of the same order reproduces the decision bit for bit;
 * one (key, value) pair per (visible Gaussian, kept tile that is valid for
   this view); emitted in Gaussian-id order, tiles row-major inside the rect;
 * key = (tile_id << 32) | bits(float32(t_z)), tile_id = ty * TX + tx; t_z is
@@ -62,30 +62,35 @@ def tile_touches(tx, ty, xi, xf, yi, yf, A, B, C, tau):
     """Whether the pixel-centre rectangle of tile (tx, ty) meets q <= tau
     (element-wise over arrays; FP64, fixed operation order).  Pixel centres
     of the tile sit at x = 16 tx .. 16 tx + 15 relative to the image; d is
-    measured from the stored centre xi + xf."""
+    measured from the stored centre xi + xf.  With P the rectangle point
+    nearest the centre, the minimum of the convex q over the rectangle lies
+    on the edges through P that face the centre (x = P_x when the centre is
+    left or right of the rectangle, y = P_y when above or below): kept when
+    q(P) <= tau or the closed-form minimum along a facing edge is."""
     tx = np.asarray(tx, dtype=np.float64)
     ty = np.asarray(ty, dtype=np.float64)
     X0 = (TILE * tx - xi) - xf
     X1 = (TILE * tx + (TILE - 1) - xi) - xf
     Y0 = (TILE * ty - yi) - yf
     Y1 = (TILE * ty + (TILE - 1) - yi) - yf
-    # the point of the rectangle nearest the centre (the centre itself when inside)
-    keep = _quad(A, B, C, np.minimum(np.maximum(0.0, X0), X1), np.minimum(np.maximum(0.0, Y0), Y1)) <= tau
+    Px = np.minimum(np.maximum(0.0, X0), X1)
+    Py = np.minimum(np.maximum(0.0, Y0), Y1)
+    keep = _quad(A, B, C, Px, Py) <= tau
     det = A * C - B * B
-    for X in (X0, X1):                                          # vertical edges, y in [Y0, Y1]
-        bx = B * X
-        lo = -bx < C * Y0
-        hi = ~lo & (-bx > C * Y1)
-        y = np.where(lo, Y0, Y1)
-        edge = np.where(lo | hi, _quad(A, B, C, X, y) <= tau, (X * X) * det <= tau * C)
-        keep = keep | edge
-    for Y in (Y0, Y1):                                          # horizontal edges, x in [X0, X1]
-        by = B * Y
-        lo = -by < A * X0
-        hi = ~lo & (-by > A * X1)
-        x = np.where(lo, X0, X1)
-        edge = np.where(lo | hi, _quad(A, B, C, x, Y) <= tau, (Y * Y) * det <= tau * A)
-        keep = keep | edge
+    # vertical facing edge x = Px, y in [Y0, Y1]
+    bx = B * Px
+    lo = -bx < C * Y0
+    hi = ~lo & (-bx > C * Y1)
+    y = np.where(lo, Y0, Y1)
+    edge = np.where(lo | hi, _quad(A, B, C, Px, y) <= tau, (Px * Px) * det <= tau * C)
+    keep = keep | ((Px != 0.0) & edge)
+    # horizontal facing edge y = Py, x in [X0, X1]
+    by = B * Py
+    lo = -by < A * X0
+    hi = ~lo & (-by > A * X1)
+    x = np.where(lo, X0, X1)
+    edge = np.where(lo | hi, _quad(A, B, C, x, Py) <= tau, (Py * Py) * det <= tau * A)
+    keep = keep | ((Py != 0.0) & edge)
     return keep
 
 

@@ -151,35 +151,33 @@ __device__ __forceinline__ double ellipse_q(const Ellipse& e, double x, double y
   return ((e.A * x) * x + ((2.0 * e.B) * x) * y) + (e.C * y) * y;
 }
 
-// Whether the pixel-centre rectangle of tile (tx, ty) meets q <= tau: q at
-// the rectangle point nearest the centre at most tau (most kept tiles stop
-// here), or the closed-form minimum of q along one of the four edges.  A
-// lower bound of the minimum over the pixel centres.
+// Whether the pixel-centre rectangle of tile (tx, ty) meets q <= tau.  With
+// P the rectangle point nearest the centre, the minimum of the convex q
+// over the rectangle lies on the edges through P that face the centre:
+// kept when q(P) <= tau (most kept tiles stop here) or the closed-form
+// minimum along a facing edge is at most tau.  A lower bound of the
+// minimum over the tile's pixel centres.
 __device__ __forceinline__ bool tile_touches(const Ellipse& e, int tx, int ty, double tau) {
 #pragma clang fp contract(off)
   const double X0 = ((double)(kTile * tx) - e.xi) - e.xf;
   const double X1 = ((double)(kTile * tx + kTile - 1) - e.xi) - e.xf;
   const double Y0 = ((double)(kTile * ty) - e.yi) - e.yf;
   const double Y1 = ((double)(kTile * ty + kTile - 1) - e.yi) - e.yf;
-  // the rectangle point nearest the centre (the centre itself when inside)
-  if (ellipse_q(e, fmin(fmax(0.0, X0), X1), fmin(fmax(0.0, Y0), Y1)) <= tau) return true;
+  const double Px = fmin(fmax(0.0, X0), X1), Py = fmin(fmax(0.0, Y0), Y1);
+  if (ellipse_q(e, Px, Py) <= tau) return true;
   const double det = e.A * e.C - e.B * e.B;
   bool keep = false;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {  // vertical edges, y in [Y0, Y1]
-    const double X = s == 0 ? X0 : X1;
-    const double bx = e.B * X;
+  if (Px != 0.0) {  // vertical facing edge x = Px, y in [Y0, Y1]
+    const double bx = e.B * Px;
     const bool lo = -bx < e.C * Y0;
     const bool hi = !lo && (-bx > e.C * Y1);
-    keep = keep || ((lo || hi) ? ellipse_q(e, X, lo ? Y0 : Y1) <= tau : (X * X) * det <= tau * e.C);
+    keep = (lo || hi) ? ellipse_q(e, Px, lo ? Y0 : Y1) <= tau : (Px * Px) * det <= tau * e.C;
   }
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {  // horizontal edges, x in [X0, X1]
-    const double Y = s == 0 ? Y0 : Y1;
-    const double by = e.B * Y;
+  if (Py != 0.0) {  // horizontal facing edge y = Py, x in [X0, X1]
+    const double by = e.B * Py;
     const bool lo = -by < e.A * X0;
     const bool hi = !lo && (-by > e.A * X1);
-    keep = keep || ((lo || hi) ? ellipse_q(e, lo ? X0 : X1, Y) <= tau : (Y * Y) * det <= tau * e.A);
+    keep = keep || ((lo || hi) ? ellipse_q(e, lo ? X0 : X1, Py) <= tau : (Py * Py) * det <= tau * e.A);
   }
   return keep;
 }
