@@ -44,6 +44,30 @@ BWD_FLOP_EVAL = 14
 BWD_FLOP_BLEND = 48
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_scaling_300k_25pct.txt")
+RASTER_SOURCES = ("paper_2606_15924_amd/csrc/raster.hip", "paper_2606_15924_amd/csrc/common.h")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (already scaled by the plain-copy
+    calibration), or None when there is no record for it or the kernel's
+    source has changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = dict(line.split(": ", 1) for line in open(TRAFFIC_RECORD).read().splitlines()
+                   if line.startswith("traffic-"))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in RASTER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("traffic-kernel") != kernel or rec.get("traffic-source-sha256") != h.hexdigest():
+        return None
+    return int(rec["traffic-read-bytes"]) + int(rec["traffic-write-bytes"])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -94,13 +118,16 @@ def run(tr, steps, warmup):
                 n_pairs=int(vb.n_pairs), pixels=pixels)
 
 
-def cpu_baseline(p, cam, gt, n_tiles=384):
+def cpu_baseline(p, cam, gt, target_s=15.0):
     """The oracle's sparse step, timed on one host thread: the parts whose
-    cost scales with the sampled tiles (sampling, binning, forward, loss,
-    backward) on ``n_tiles`` random tiles at the headline rate, the parts
-    over every Gaussian (projection, projection backward, optimizer) whole.
-    The whole-view step time is extrapolated as fixed + per-tile x n_t /
-    n_tiles, and so are its blends; returns blends/s of that step."""
+    cost scales with the sampled tiles (sampling, forward, loss, backward)
+    on a random subset of tiles at the headline rate, the parts over every
+    Gaussian (projection, binning of the whole view, projection backward,
+    optimizer) whole.
+    The subset is sized from a 32-tile probe so the tile part takes about
+    ``target_s`` seconds.  The whole-view step time is extrapolated as
+    fixed + per-tile x n_t / n_tiles, and so are its blends; returns
+    blends/s of that step."""
     from threadpoolctl import threadpool_limits
 
     from oracle import binning, loss, project, project_bwd, render, sampler, optim
@@ -111,17 +138,28 @@ def cpu_baseline(p, cam, gt, n_tiles=384):
     A = np.zeros((HEIGHT, WIDTH), dtype=np.uint16)
     TX, TY = (WIDTH + 15) // 16, (HEIGHT + 15) // 16
     n_t = TX * TY
-    tiles = np.sort(np.random.default_rng(0).choice(n_t, n_tiles, replace=False))
-    with threadpool_limits(1):
-        c0 = time.perf_counter()
-        pr = project.project(p, cam, rp)
-        c1 = time.perf_counter()
+    order = np.random.default_rng(0).permutation(n_t)
+
+    def tile_part(pr, sv, ranges, tiles):
         s = sampler.sample_view(E, A, SampleParams(n_pix=64), 3, 1, 0, tiles_subset=tiles)
-        _, sv, ranges = binning.bin_and_sort(pr, s["valid_tiles"])
         xs, ys, _ = sampler.sample_coords(s, WIDTH, HEIGHT)
         out = render.render_pixels(pr, sv, ranges, xs, ys, rp)
         ls = loss.sparse_loss(out["rgb"], gt[:, ys, xs].T, s["tile_off"], xs.size, s["valid_tiles"].size)
         g2d = render.render_pixels_bwd(pr, sv, ranges, xs, ys, ls["dL"], rp)
+        return xs, out, g2d
+
+    with threadpool_limits(1):
+        c0 = time.perf_counter()
+        pr = project.project(p, cam, rp)
+        # every tile of the view is sampled at this rate: the lists cover the view
+        _, sv, ranges = binning.bin_and_sort(pr, np.arange(n_t))
+        c1 = time.perf_counter()
+        tile_part(pr, sv, ranges, np.sort(order[:32]))
+        probe = (time.perf_counter() - c1) / 32
+        n_tiles = int(min(n_t, max(32, target_s / probe)))
+        tiles = np.sort(order[:n_tiles])
+        c1b = time.perf_counter()
+        xs, out, g2d = tile_part(pr, sv, ranges, tiles)
         c2 = time.perf_counter()
         grad = project_bwd.project_bwd(p, cam, pr, g2d, rp)
         touched = np.zeros(p.shape[1], dtype=bool)
@@ -129,16 +167,17 @@ def cpu_baseline(p, cam, gt, n_tiles=384):
         optim.optimizer_step(p, grad, np.zeros_like(grad), np.zeros_like(grad), touched, OptimParams(), 1)
         c3 = time.perf_counter()
     fixed = (c1 - c0) + (c3 - c2)
-    per_tile = (c2 - c1) / n_tiles
+    per_tile = (c2 - c1b) / n_tiles
     step_s = fixed + per_tile * n_t
     blends = int(out["n_blend"].sum())
     blends_step = blends * n_t / n_tiles
     return dict(value=blends_step / step_s, unit="blends/s", cores=1, kind="oracle",
                 step_s_extrapolated=round(step_s, 2),
                 sample=f"{n_tiles} of {n_t} random tiles at 25% ({xs.size} pixels, {blends} blends) plus "
-                       f"projection, projection backward and optimizer over all {p.shape[1]} Gaussians; "
-                       f"{c3 - c0:.1f} s measured ({fixed:.1f} s whole-model, {per_tile * 1e3:.1f} ms per tile), "
-                       f"whole-view step extrapolated to {step_s:.1f} s")
+                       f"projection, whole-view binning, projection backward and optimizer over all "
+                       f"{p.shape[1]} Gaussians; "
+                       f"{fixed + (c2 - c1b):.1f} s measured ({fixed:.1f} s whole-model, "
+                       f"{per_tile * 1e3:.1f} ms per tile), whole-view step extrapolated to {step_s:.1f} s")
 
 
 def main():
@@ -210,7 +249,8 @@ def main():
         flops = BWD_FLOP_EVAL * per_launch_evals + BWD_FLOP_BLEND * per_launch_blends
     achieved = flops / (st[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(dom),
                 "launch_ms": round(st[dom], 4)}
 
     cpu = None

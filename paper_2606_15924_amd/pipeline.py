@@ -130,8 +130,9 @@ class ViewBuffers:
         B.tgs_ema_age_update(E, A, self.height, self.width, self.tile_slot, self.tile_off, self.pix,
                              self.err, beta)
 
-    def render_bwd(self, rp):
-        self.g2d.zero_()
+    def render_bwd(self, rp, zero=True):
+        if zero:
+            self.g2d.zero_()
         B.tgs_render_bwd(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                          self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
                          rp, self.out, self.ncontrib, self.dL, self.g2d)
@@ -251,8 +252,10 @@ class Trainer:
                 with torch.cuda.stream(side):
                     with st("ema_age"):
                         vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
+            with st("zero_g2d"):
+                vb.g2d.zero_()
             with st("render_bwd"):
-                vb.render_bwd(self.rp)
+                vb.render_bwd(self.rp, zero=False)
             if k + 1 < len(used) or not self.cfg.fuse_optimizer:
                 with st("project_bwd"):
                     # the first view overwrites the gradient, later views add to it
