@@ -158,7 +158,8 @@ int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t
  * q = a dx^2 + 2 b dx dy + c dy^2, tau = 2 ln(1/alpha_min) x 1.001 rounded
  * up to a multiple of 1/64): no dropped pair can reach alpha_min at any
  * pixel of its tile, so the lists composite exactly like the rectangle
- * lists.
+ * lists.  The kept tiles of a tile row are one interval of columns, found
+ * in FP64 from the ellipse's x-extent over the row's pixel-centre strip.
  *   rect, splat, depth  projection outputs of n Gaussians
  *   tile_slot    nullable: only tiles with tile_slot >= 0 receive pairs
  *   alpha_min    the compositing threshold (as in tgs_raster_params)

@@ -13,12 +13,20 @@ set of Gaussians that can reach p's tile.  Readings:
   q <= 2 ln(1/alpha_min); tau adds a 0.1 % margin and is rounded up to a
   multiple of 1/64 (cull_threshold), so a culled pair never composites and
   the images and gradients are those of the plain rectangle lists;
-* the test: q at the rectangle point P nearest the centre is <= tau, or the
-  closed-form minimum of q along one of the (at most two) edges through P
-  that face the centre is; together the continuous minimum of q over the
-  tile's pixel-centre rectangle (a lower bound of the minimum over its pixel
-  centres), in FP64 with the operation order of tile_touches, so that any
-  implementation of the same order reproduces the decision bit for bit;
+* the test, row by row: the ellipse cut by the pixel-centre strip of tile
+  row ty (dy in [Y0, Y1]) is convex, so the tiles of the row it meets are
+  those whose pixel-centre column range [X0, X1] meets its x-extent
+  [xmin, xmax].  q is convex, the right boundary x(y) of the ellipse is
+  concave and the left one convex, so xmax is x(y) at the ellipse's
+  rightmost point's dy clamped to the strip (and xmin likewise); with
+  det = AC - B^2 the ellipse spans |dy| <= sqrt(tau A / det) and its
+  rightmost point sits at dy = -B sqrt(tau / (C det)).  Exactly the tiles
+  whose pixel-centre rectangle meets the ellipse (a lower bound of the
+  minimum of q over the tile's pixel centres), computed in FP64 with the
+  operation order of row_span, so that any implementation of the same order
+  (IEEE +, -, *, /, sqrt, no fused multiply-add) reproduces the decision
+  bit for bit; a conic that is not positive definite keeps its whole
+  rectangle;
 * one (key, value) pair per (visible Gaussian, kept tile that is valid for
   this view); emitted in Gaussian-id order, tiles row-major inside the rect;
 * key = (tile_id << 32) | bits(float32(t_z)), tile_id = ty * TX + tx; t_z is
@@ -54,44 +62,47 @@ def splat_fields(proj: dict) -> dict:
     return dict(xi=f32(fx), xf=f32(px - fx), yi=f32(fy), yf=f32(py - fy), A=f32(A), B=f32(B), C=f32(C))
 
 
-def _quad(A, B, C, x, y):
-    return ((A * x) * x + ((2.0 * B) * x) * y) + (C * y) * y
+def row_span(ty, xi, xf, yi, yf, A, B, C, tau):
+    """Tile columns [lo, hi] (floats; lo > hi when none) of tile row ty
+    whose pixel-centre rectangles meet q <= tau, before clamping to the
+    Gaussian's rectangle (element-wise; FP64, fixed operation order).  Pixel
+    centres of the row sit at y = 16 ty .. 16 ty + 15 and of column tx at
+    x = 16 tx .. 16 tx + 15 relative to the image; d is measured from the
+    stored centre xi + xf, yi + yf."""
+    ty = np.asarray(ty, dtype=np.float64)
+    A, B, C = (np.asarray(v, dtype=np.float64) for v in (A, B, C))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        det = A * C - B * B
+        pd = (A > 0.0) & (det > 0.0)
+        ym = np.sqrt((tau * A) / det)                 # half-height of the ellipse
+        ys = B * np.sqrt(tau / (C * det))             # -dy of its rightmost point
+        Y0 = (TILE * ty - yi) - yf
+        Y1 = ((TILE * ty + (TILE - 1)) - yi) - yf
+        ylo = np.maximum(Y0, -ym)
+        yhi = np.minimum(Y1, ym)
+        yr = np.minimum(np.maximum(-ys, ylo), yhi)    # dy of the strip's rightmost point
+        yl = np.minimum(np.maximum(ys, ylo), yhi)     # dy of its leftmost point
+        tA = tau * A
+        sr = np.sqrt(np.maximum(0.0, tA - det * (yr * yr)))
+        sl = np.sqrt(np.maximum(0.0, tA - det * (yl * yl)))
+        xmax = (sr - B * yr) / A
+        xmin = (-sl - B * yl) / A
+        PL = (xmin + xf) + xi                         # in image pixel coordinates
+        PR = (xmax + xf) + xi
+        lo = np.ceil((PL - (TILE - 1)) * (1.0 / TILE))
+        hi = np.floor(PR * (1.0 / TILE))
+    empty = pd & ~(ylo <= yhi)
+    lo = np.where(pd, np.where(empty, np.inf, lo), -np.inf)
+    hi = np.where(pd, np.where(empty, -np.inf, hi), np.inf)
+    return lo, hi
 
 
 def tile_touches(tx, ty, xi, xf, yi, yf, A, B, C, tau):
     """Whether the pixel-centre rectangle of tile (tx, ty) meets q <= tau
-    (element-wise over arrays; FP64, fixed operation order).  Pixel centres
-    of the tile sit at x = 16 tx .. 16 tx + 15 relative to the image; d is
-    measured from the stored centre xi + xf.  With P the rectangle point
-    nearest the centre, the minimum of the convex q over the rectangle lies
-    on the edges through P that face the centre (x = P_x when the centre is
-    left or right of the rectangle, y = P_y when above or below): kept when
-    q(P) <= tau or the closed-form minimum along a facing edge is."""
+    (element-wise): tx inside the row's span."""
+    lo, hi = row_span(ty, xi, xf, yi, yf, A, B, C, tau)
     tx = np.asarray(tx, dtype=np.float64)
-    ty = np.asarray(ty, dtype=np.float64)
-    X0 = (TILE * tx - xi) - xf
-    X1 = (TILE * tx + (TILE - 1) - xi) - xf
-    Y0 = (TILE * ty - yi) - yf
-    Y1 = (TILE * ty + (TILE - 1) - yi) - yf
-    Px = np.minimum(np.maximum(0.0, X0), X1)
-    Py = np.minimum(np.maximum(0.0, Y0), Y1)
-    keep = _quad(A, B, C, Px, Py) <= tau
-    det = A * C - B * B
-    # vertical facing edge x = Px, y in [Y0, Y1]
-    bx = B * Px
-    lo = -bx < C * Y0
-    hi = ~lo & (-bx > C * Y1)
-    y = np.where(lo, Y0, Y1)
-    edge = np.where(lo | hi, _quad(A, B, C, Px, y) <= tau, (Px * Px) * det <= tau * C)
-    keep = keep | ((Px != 0.0) & edge)
-    # horizontal facing edge y = Py, x in [X0, X1]
-    by = B * Py
-    lo = -by < A * X0
-    hi = ~lo & (-by > A * X1)
-    x = np.where(lo, X0, X1)
-    edge = np.where(lo | hi, _quad(A, B, C, x, Py) <= tau, (Py * Py) * det <= tau * A)
-    keep = keep | ((Py != 0.0) & edge)
-    return keep
+    return (lo <= tx) & (tx <= hi)
 
 
 def emit_pairs(rect: np.ndarray, depth32: np.ndarray, TX: int, TY: int,
@@ -136,13 +147,22 @@ def rect_tiles(rect):
 
 
 def kept_tiles(rect, fields, tau):
-    """Rect tiles that pass the ellipse test: (Gaussian id, tx, ty)."""
-    gid, tx, ty = rect_tiles(rect)
-    if fields is not None:
-        f = {k: v[gid] for k, v in fields.items()}
-        keep = tile_touches(tx, ty, f["xi"], f["xf"], f["yi"], f["yf"], f["A"], f["B"], f["C"], tau)
-        gid, tx, ty = gid[keep], tx[keep], ty[keep]
-    return gid, tx, ty
+    """Rect tiles that pass the ellipse test: (Gaussian id, tx, ty), in
+    Gaussian-id order, row-major inside the rect (spans clamped to it)."""
+    if fields is None:
+        return rect_tiles(rect)
+    xmin, ymin, xmax, ymax = (np.asarray(r, dtype=np.int64) for r in rect)
+    h = np.maximum(ymax - ymin, 0) * (xmax > xmin)
+    gr = np.repeat(np.arange(xmin.size, dtype=np.int64), h)
+    ty = ymin[gr] + (np.arange(gr.size, dtype=np.int64) - np.repeat(np.cumsum(h) - h, h))
+    f = {k: v[gr] for k, v in fields.items()}
+    lo, hi = row_span(ty, f["xi"], f["xf"], f["yi"], f["yf"], f["A"], f["B"], f["C"], tau)
+    lo = np.clip(lo, xmin[gr], xmax[gr]).astype(np.int64)
+    hi = np.clip(hi, xmin[gr] - 1, xmax[gr] - 1).astype(np.int64)
+    c = np.maximum(hi - lo + 1, 0)
+    gid = np.repeat(gr, c)
+    tx = np.repeat(lo, c) + (np.arange(gid.size, dtype=np.int64) - np.repeat(np.cumsum(c) - c, c))
+    return gid, tx, np.repeat(ty, c)
 
 
 def emit_pairs_fast(rect, depth32, TX, TY, valid_tiles=None, fields=None, tau=None):

@@ -3,28 +3,26 @@
 // The per-tile Gaussian lists must follow (tile, FP32 depth bits, Gaussian
 // id) and hold only the (Gaussian, tile) pairs whose tile can composite: the
 // tile lies in the Gaussian's 3-sigma rectangle and its pixel-centre
-// rectangle meets the ellipse q(d) <= tau of the stored centre and conic
-// (tile_touches, an FP64 closed-form minimum with a fixed operation order).
-// Rather than radix-sorting a 64-bit (tile, depth) key with an id for every
-// pair, the Gaussians are put in (depth, id) order once (a 32-bit sort of n
-// keys) and the pairs are emitted in that order; a stable sort on the tile
-// bits alone then yields the full order.  The pair key is
-// (tile << id_bits) | Gaussian id, usually 32 bits: the id bits only ride
-// along, since a stable sort never compares them.
+// rectangle meets the ellipse q(d) <= tau of the stored centre and conic.
+// Row by row that is an interval of columns (row_span, FP64 with a fixed
+// operation order).  Rather than radix-sorting a 64-bit (tile, depth) key
+// with an id for every pair, the Gaussians are put in (depth, id) order once
+// (a 32-bit sort of n keys) and the pairs are emitted in that order; a
+// stable sort on the tile bits alone then yields the full order.  The pair
+// key is (tile << id_bits) | Gaussian id, usually 32 bits: the id bits only
+// ride along, since a stable sort never compares them.
 //
-//   count     wave-cooperative over the rectangle tiles of 64 Gaussians: the
-//             kept tiles and the kept valid tiles per Gaussian, depth key
-//             (Gaussians without a kept valid tile get a key above every
-//             depth), touched flag
+//   count     a thread per Gaussian over its rectangle rows: kept pairs and
+//             kept pairs in valid tiles, depth key (Gaussians without a kept
+//             valid tile get a key above every depth), touched flag
 //   sort      LSD radix sort of (depth key, id) over n: stable, so ties keep
 //             id order; Gaussians with pairs come first
 //   gather    rectangles and pair counts in depth order, exclusive scan ->
-//             pair offsets and the total (read back once)
-//   emit      wave-cooperative again over 64 depth-ordered Gaussians: the
-//             same test picks the kept tiles, whose keys are written
-//             contiguously from the wave's first offset; tiles outside the
-//             valid set get the sentinel tile id n_tiles (after every real
-//             tile)
+//             pair offsets; the totals are read back once
+//   emit      a wave per 64 depth-ordered Gaussians walks their rows; each
+//             row's span is keyed and written contiguously after the rows
+//             before it; tiles outside the valid set get the sentinel tile
+//             id n_tiles (after every real tile)
 //   sort      LSD radix sort of the pair keys on the tile bits only; the
 //             last pass writes the ids, the sorted keys and (if asked) the
 //             64-bit keys
@@ -121,7 +119,7 @@ static void exclusive_scan(const T* in, T* out, int64_t n, T* partials, hipStrea
 
 
 
-// ------------------------------------------------------------------ tile test
+// ------------------------------------------------------------------ row spans
 // Depth key of a Gaussian without pairs: above every finite positive depth bit pattern.
 constexpr uint32_t kCulledKey = 0xffffffffu;
 
@@ -135,67 +133,70 @@ __device__ __forceinline__ int4 clamp_rect(int4 r, int tiles_x, int tiles_y) {
   return r;
 }
 
-// What the tile test needs of one Gaussian: the stored centre (integer part
-// and fraction) and conic, widened to FP64 (exact).
-struct Ellipse {
-  double xi, xf, yi, yf, A, B, C;
+// What the row test needs of one Gaussian: the stored centre (integer part
+// and fraction) and conic widened to FP64 (exact), and per-Gaussian terms of
+// the ellipse q(d) = A dx^2 + 2 B dx dy + C dy^2 <= tau: det = AC - B^2,
+// its half-height ym = sqrt(tau A / det), ys = B sqrt(tau / (C det)) (the
+// rightmost point of the ellipse sits at dy = -ys, the leftmost at +ys) and
+// tA = tau A.  pd = 0 for a conic that is not positive definite.
+struct RowEllipse {
+  double xi, xf, yi, yf, A, B, det, ym, ys, tA;
+  int pd;
 };
 
-__device__ __forceinline__ Ellipse load_ellipse(const float4* __restrict__ splat, int64_t i) {
+__device__ __forceinline__ RowEllipse load_row_ellipse(const float4* __restrict__ splat, int64_t i, double tau) {
+#pragma clang fp contract(off)
   const float4 p0 = splat[3 * i], p1 = splat[3 * i + 1];
-  return Ellipse{p0.x, p0.z, p0.y, p0.w, p1.x, p1.y, p1.z};
+  RowEllipse e;
+  e.xi = p0.x;
+  e.yi = p0.y;
+  e.xf = p0.z;
+  e.yf = p0.w;
+  e.A = p1.x;
+  e.B = p1.y;
+  const double C = p1.z;
+  e.det = e.A * C - e.B * e.B;
+  e.pd = e.A > 0.0 && e.det > 0.0;
+  e.ym = e.pd ? sqrt((tau * e.A) / e.det) : 0.0;
+  e.ys = e.pd ? e.B * sqrt(tau / (C * e.det)) : 0.0;
+  e.tA = tau * e.A;
+  return e;
 }
 
-__device__ __forceinline__ double ellipse_q(const Ellipse& e, double x, double y) {
+// Kept columns [lo, hi] of tile row ty inside the rectangle columns
+// [rx0, rx1) (lo > hi when none): the tiles whose pixel-centre column range
+// meets the x-extent of the ellipse cut by the row's pixel-centre strip.
+// The right boundary of the ellipse, x(dy) = (sqrt(tA - det dy^2) - B dy)/A,
+// is concave, so the strip's rightmost point is at the ellipse's rightmost
+// dy clamped to the strip (the leftmost likewise).  FP64, IEEE operations
+// in a fixed order and no contraction: the decision is reproducible bit for
+// bit by any implementation of the same order.
+__device__ __forceinline__ void row_span(const RowEllipse& e, int ty, int rx0, int rx1, int& lo, int& hi) {
 #pragma clang fp contract(off)
-  return ((e.A * x) * x + ((2.0 * e.B) * x) * y) + (e.C * y) * y;
-}
-
-// Whether the pixel-centre rectangle of tile (tx, ty) meets q <= tau.  With
-// P the rectangle point nearest the centre, the minimum of the convex q
-// over the rectangle lies on the edges through P that face the centre:
-// kept when q(P) <= tau (most kept tiles stop here) or the closed-form
-// minimum along a facing edge is at most tau.  A lower bound of the
-// minimum over the tile's pixel centres.
-__device__ __forceinline__ bool tile_touches(const Ellipse& e, int tx, int ty, double tau) {
-#pragma clang fp contract(off)
-  const double X0 = ((double)(kTile * tx) - e.xi) - e.xf;
-  const double X1 = ((double)(kTile * tx + kTile - 1) - e.xi) - e.xf;
-  const double Y0 = ((double)(kTile * ty) - e.yi) - e.yf;
-  const double Y1 = ((double)(kTile * ty + kTile - 1) - e.yi) - e.yf;
-  const double Px = fmin(fmax(0.0, X0), X1), Py = fmin(fmax(0.0, Y0), Y1);
-  if (ellipse_q(e, Px, Py) <= tau) return true;
-  const double det = e.A * e.C - e.B * e.B;
-  bool keep = false;
-  if (Px != 0.0) {  // vertical facing edge x = Px, y in [Y0, Y1]
-    const double bx = e.B * Px;
-    const bool lo = -bx < e.C * Y0;
-    const bool hi = !lo && (-bx > e.C * Y1);
-    keep = (lo || hi) ? ellipse_q(e, Px, lo ? Y0 : Y1) <= tau : (Px * Px) * det <= tau * e.C;
-  }
-  if (Py != 0.0) {  // horizontal facing edge y = Py, x in [X0, X1]
-    const double by = e.B * Py;
-    const bool lo = -by < e.A * X0;
-    const bool hi = !lo && (-by > e.A * X1);
-    keep = keep || ((lo || hi) ? ellipse_q(e, lo ? X0 : X1, Py) <= tau : (Py * Py) * det <= tau * e.A);
-  }
-  return keep;
-}
-
-// q = a / b and r = a % b for b > 0: below 2^22 a float estimate of the
-// quotient is off by at most one and is corrected; larger a divide exactly.
-__device__ __forceinline__ void divmod_small(uint32_t a, uint32_t b, uint32_t& q, uint32_t& r) {
-  if (a >= (1u << 22)) {
-    q = a / b;
-    r = a - q * b;
+  if (!e.pd) {  // keeps the whole rectangle row
+    lo = rx0;
+    hi = rx1 - 1;
     return;
   }
-  int qi = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
-  int ri = (int)a - qi * (int)b;
-  if (ri < 0) { --qi; ri += (int)b; }
-  if (ri >= (int)b) { ++qi; ri -= (int)b; }
-  q = (uint32_t)qi;
-  r = (uint32_t)ri;
+  const double Y0 = ((double)(kTile * ty) - e.yi) - e.yf;
+  const double Y1 = ((double)(kTile * ty + kTile - 1) - e.yi) - e.yf;
+  const double ylo = fmax(Y0, -e.ym), yhi = fmin(Y1, e.ym);
+  if (!(ylo <= yhi)) {
+    lo = rx0;
+    hi = rx0 - 1;
+    return;
+  }
+  const double yr = fmin(fmax(-e.ys, ylo), yhi);
+  const double yl = fmin(fmax(e.ys, ylo), yhi);
+  const double sr = sqrt(fmax(0.0, e.tA - e.det * (yr * yr)));
+  const double sl = sqrt(fmax(0.0, e.tA - e.det * (yl * yl)));
+  const double xmax = (sr - e.B * yr) / e.A;
+  const double xmin = (-sl - e.B * yl) / e.A;
+  const double PL = (xmin + e.xf) + e.xi, PR = (xmax + e.xf) + e.xi;  // image pixel coordinates
+  const double l = ceil((PL - (double)(kTile - 1)) * (1.0 / kTile));
+  const double h = floor(PR * (1.0 / kTile));
+  lo = (int)fmin(fmax(l, (double)rx0), (double)rx1);
+  hi = (int)fmin(fmax(h, (double)(rx0 - 1)), (double)(rx1 - 1));
 }
 
 // Inclusive max-scan over the wave (identity -1): DPP shifts inside rows of
@@ -210,166 +211,66 @@ __device__ __forceinline__ int wave_max_scan(int v) {
   return v;
 }
 
-// Per-wave LDS slice of a batch of up to 64 Gaussians (one per lane).
-// Keep decisions of a Gaussian's first kBitTiles rectangle tiles (row-major)
-// are stored as bits by the count kernel and read back by emit; larger
-// rectangles are tested again.
-constexpr int kBitWords = 4;
-constexpr uint32_t kBitTiles = 64u * kBitWords;
-
-struct WaveBatch {
-  int4 rect[kWave];
-  uint32_t start[kWave];  // exclusive prefix of the rectangle areas in the batch
-  Ellipse ell[kWave];
-  uint32_t id[kWave];
-  int mark[kWave];
-  uint64_t bits[kWave][kBitWords];
-};
-
-// Wave-cooperative walk over the rectangle tiles of a batch: the tiles are
-// flattened Gaussian by Gaussian, row-major inside each rectangle, and each
-// round hands the next 64 to the lanes.  A Gaussian starting inside the
-// round marks its slot and an inclusive max-scan carries each owner to the
-// following slots, so a lane finds its owner without a search.
-// visit(in, owner lane, tile x, tile y, the tile's row-major index inside the
-// owner's rectangle) is called once per lane and round.
-// The workgroup is the one wave, so the barriers that order the lanes' LDS
-// exchanges are wave barriers; the trip count is uniform.
-template <typename Visit>
-__device__ __forceinline__ void walk_rect_tiles(WaveBatch& wb, uint32_t my_start, uint32_t my_area, uint32_t total,
-                                                Visit&& visit) {
-  const int lane = lane_id();
-  int carry = -1;
-  for (uint32_t f0 = 0; f0 < total; f0 += kWave) {
-    wb.mark[lane] = -1;
-    __syncthreads();
-    if (my_area > 0 && my_start >= f0 && my_start - f0 < (uint32_t)kWave) wb.mark[my_start - f0] = lane;
-    __syncthreads();
-    const int j = max(wave_max_scan(wb.mark[lane]), carry);
-    carry = __builtin_amdgcn_readlane(j, kWave - 1);
-    const uint32_t f = f0 + (uint32_t)lane;
-    const bool in = f < total && j >= 0;  // j >= 0 whenever f < total (the first area > 0 starts at 0)
-    int tx = 0, ty = 0;
-    uint32_t l = 0;
-    if (in) {
-      const int4 r = wb.rect[j];
-      l = f - wb.start[j];
-      uint32_t dy, dx;
-      divmod_small(l, (uint32_t)(r.z - r.x), dy, dx);
-      tx = r.x + (int)dx;
-      ty = r.y + (int)dy;
-    }
-    visit(in, in ? j : 0, tx, ty, l);
-    __syncthreads();  // the round's reads and updates before the next round's writes
-  }
-}
-
-// Loads lane's Gaussian into the batch (area 0: no tiles) and returns the
-// batch's tile count; my_start receives the lane's first flat index.
-__device__ __forceinline__ uint32_t load_batch(WaveBatch& wb, int4 r, uint32_t area, const float4* __restrict__ splat,
-                                               uint32_t g, uint32_t& my_start) {
-  const int lane = lane_id();
-  const uint32_t incl = wave_inclusive_scan_u32(area);
-  my_start = incl - area;
-  __syncthreads();  // earlier readers of the batch slots are done
-  wb.rect[lane] = r;
-  wb.start[lane] = my_start;
-  wb.id[lane] = g;
-  if (area > 0) wb.ell[lane] = load_ellipse(splat, g);
-  __syncthreads();
-  return (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
-}
-
 // ------------------------------------------------------------------ count
-constexpr int kBinThreads = kWave;  // one wave per workgroup: __syncthreads is a wave barrier
-constexpr int kBinWaves = 1;
+constexpr int kCountThreads = 256;
 
-// Each workgroup (one wave) takes kCountBatch Gaussians in index order
-// (lanes beyond the batch hold none): fewer tiles per wave, more waves to
-// hide latency.  Per round, the lanes of one owner form a run; its first
-// lane adds the run's kept and kept-valid counts and ORs the run's keep bits
-// into the owner's bit words (one LDS update per owner and round).
-constexpr int kCountBatch = 32;
-
-__global__ void __launch_bounds__(kBinThreads) count_kernel(
+// One thread per Gaussian walks the rows of its rectangle: kept pairs, and
+// kept pairs in valid tiles (every kept pair when there is no tile subset);
+// depth key (Gaussians without a kept valid tile get a key above every
+// depth), pair count and touched flag.
+__global__ void __launch_bounds__(kCountThreads) count_kernel(
     const int4* __restrict__ rect, const float4* __restrict__ splat, const float* __restrict__ depth, int64_t n,
     const int32_t* __restrict__ tile_slot, int tiles_x, int tiles_y, double tau, uint32_t* __restrict__ dkeys,
-    uint32_t* __restrict__ dvals, uint32_t* __restrict__ emit_cnt, uint64_t* __restrict__ tile_bits,
-    uint8_t* __restrict__ touched, unsigned long long* __restrict__ totals) {
-  __shared__ WaveBatch wb;
-  __shared__ uint32_t s_kept[kWave], s_valid[kWave];
-  __shared__ uint64_t s_red[1];
-  const int lane = lane_id();
-  const int64_t i = (int64_t)blockIdx.x * kCountBatch + lane;
-  const bool mine = lane < kCountBatch && i < n;
-  int4 r = make_int4(0, 0, 0, 0);
-  if (mine) r = clamp_rect(rect[i], tiles_x, tiles_y);
-  const uint32_t area = (uint32_t)((r.z - r.x) * (r.w - r.y));
-  s_kept[lane] = 0;
-  s_valid[lane] = 0;
-  for (int q = 0; q < kBitWords; ++q) wb.bits[lane][q] = 0;
-  uint32_t my_start;
-  const uint32_t batch_tiles = load_batch(wb, r, area, splat, mine ? (uint32_t)i : 0u, my_start);
-  walk_rect_tiles(wb, my_start, area, batch_tiles, [&](bool in, int j, int tx, int ty, uint32_t l0) {
-    const bool keep = in && tile_touches(wb.ell[j], tx, ty, tau);
-    const bool valid = keep && (tile_slot == nullptr || tile_slot[ty * tiles_x + tx] >= 0);
-    const uint64_t kb = __ballot(keep), vb = __ballot(valid);
-    const int prev = dpp_i<kDppWaveShr1>(-2, j);
-    const bool head = in && prev != j;
-    const uint64_t heads = __ballot(head);
-    if (head) {
-      const uint64_t after = lane == kWave - 1 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
-      const int nxt = after ? __builtin_ctzll(after) : kWave;
-      const uint64_t upto = nxt == kWave ? ~0ull : ((1ull << nxt) - 1ull);
-      const uint64_t run = upto & ~((1ull << lane) - 1ull);
-      s_kept[j] += (uint32_t)__popcll(kb & run);
-      s_valid[j] += (uint32_t)__popcll(vb & run);
-      // the run's keep bits, from the owner's local tile index l0 of this lane
-      const uint64_t rb = (kb & run) >> lane;
-      if (rb != 0 && l0 < kBitTiles) {
-        const uint32_t wq = l0 >> 6, sh = l0 & 63;
-        wb.bits[j][wq] |= rb << sh;
-        if (sh != 0 && wq + 1 < (uint32_t)kBitWords) wb.bits[j][wq + 1] |= rb >> (64 - sh);
+    uint32_t* __restrict__ dvals, uint32_t* __restrict__ emit_cnt, uint8_t* __restrict__ touched,
+    unsigned long long* __restrict__ totals) {
+  __shared__ uint64_t s_red[kCountThreads / kWave];
+  const int64_t i = (int64_t)blockIdx.x * kCountThreads + threadIdx.x;
+  uint32_t kept = 0, valid = 0;
+  if (i < n) {
+    const int4 r = clamp_rect(rect[i], tiles_x, tiles_y);
+    if (r.z > r.x && r.w > r.y) {
+      const RowEllipse e = load_row_ellipse(splat, i, tau);
+      for (int ty = r.y; ty < r.w; ++ty) {
+        int lo, hi;
+        row_span(e, ty, r.x, r.z, lo, hi);
+        const uint32_t c = (uint32_t)max(hi - lo + 1, 0);
+        kept += c;
+        if (tile_slot == nullptr) {
+          valid += c;
+        } else {
+          const int32_t* row = tile_slot + (int64_t)ty * tiles_x;
+          for (int tx = lo; tx <= hi; ++tx) valid += row[tx] >= 0 ? 1u : 0u;
+        }
       }
     }
-  });
-  const uint32_t kept = s_kept[lane], valid = s_valid[lane];
-  if (mine) {
     dkeys[i] = valid > 0 ? __float_as_uint(depth[i]) : kCulledKey;
     dvals[i] = (uint32_t)i;
     emit_cnt[i] = valid > 0 ? kept : 0u;  // every kept tile, valid or not, once the Gaussian has a pair
     if (touched != nullptr && valid > 0) touched[i] = 1;
-    if (valid > 0 && area <= kBitTiles)
-      for (int q = 0; q < kBitWords; ++q) tile_bits[i * kBitWords + q] = wb.bits[lane][q];
   }
-  // 64-bit totals, spread over slots: [0] pairs in valid tiles, [1] all
-  // pairs, [2] rectangle tiles of the Gaussians with pairs
-  const uint64_t v3[3] = {valid, valid > 0 ? kept : 0u, valid > 0 ? area : 0u};
-  for (int k = 0; k < 3; ++k) {
+  // 64-bit totals, spread over slots: [0] pairs in valid tiles, [1] all pairs
+  const uint64_t v2[2] = {valid, valid > 0 ? kept : 0u};
+  for (int k = 0; k < 2; ++k) {
     uint64_t tot;
-    block_exclusive_scan<kBinThreads, uint64_t>(v3[k], s_red, &tot);
-    if (lane == 0 && tot > 0)
+    block_exclusive_scan<kCountThreads, uint64_t>(v2[k], s_red, &tot);
+    if (threadIdx.x == 0 && tot > 0)
       atomicAdd(&totals[k * TGS_COUNTER_SLOTS + (blockIdx.x & (TGS_COUNTER_SLOTS - 1))], (unsigned long long)tot);
   }
 }
 
-// Rectangles, and the packed (rectangle area << 32) | pair count of each
-// Gaussian in depth order (both zero for Gaussians without pairs); one
-// 64-bit scan then gives the pair offsets and the rectangle-tile offsets.
+// Rectangles and pair counts in depth order (count zero for Gaussians
+// without pairs); an exclusive scan of the counts gives the pair offsets.
 __global__ void __launch_bounds__(256) gather_kernel(const uint32_t* __restrict__ perm,
                                                      const uint32_t* __restrict__ emit_cnt,
                                                      const int4* __restrict__ rect, int64_t n,
                                                      int tiles_x, int tiles_y,
                                                      int4* __restrict__ rect_sorted,
-                                                     uint64_t* __restrict__ area_sorted) {
+                                                     uint32_t* __restrict__ cnt_sorted) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const uint32_t g = perm[j];
-  const int4 r = clamp_rect(rect[g], tiles_x, tiles_y);
-  const uint32_t c = emit_cnt[g];
-  rect_sorted[j] = r;
-  const uint64_t a = c > 0 ? (uint64_t)((r.z - r.x) * (r.w - r.y)) : 0ull;
-  area_sorted[j] = (a << 32) | c;
+  rect_sorted[j] = clamp_rect(rect[g], tiles_x, tiles_y);
+  cnt_sorted[j] = emit_cnt[g];
 }
 
 // ------------------------------------------------------------------ ranges
@@ -600,91 +501,95 @@ static int pass_bits(int bits, int p) {
 }
 
 // ------------------------------------------------------------------ emit
-// The Gaussians with pairs (a prefix of the depth order) are split into
-// windows of about `win` rectangle tiles: window w owns the Gaussians whose
-// first rectangle tile falls in [w win, (w + 1) win), so every wave walks a
-// similar number of tiles whatever the size of its Gaussians.
-// win_first[w] = first Gaussian of window w; win_first[n_win] = the number
-// of Gaussians with pairs.
-__global__ void __launch_bounds__(256) window_kernel(const uint64_t* __restrict__ off, int64_t n, uint32_t win,
-                                                    uint32_t n_win, int32_t* __restrict__ win_first) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  const uint32_t rs = (uint32_t)(off[j] >> 32), re = (uint32_t)(off[j + 1] >> 32);
-  if (re == rs) return;  // no pairs (only at the end of the depth order)
-  const uint32_t prev = j == 0 ? 0u : (uint32_t)(off[j - 1] >> 32);
-  const uint32_t w0 = j == 0 ? 0u : prev / win + 1u;  // windows whose boundary lies in (prev, rs]
-  for (uint32_t w = w0; w <= rs / win && w <= n_win; ++w) win_first[w] = (int32_t)j;
-  const bool last = j + 1 == n || (uint32_t)(off[j + 2 > n ? n : j + 2] >> 32) == re;
-  if (last)
-    for (uint32_t w = rs / win + 1u; w <= n_win; ++w) win_first[w] = (int32_t)(j + 1);
-}
+// Per-wave LDS slice of a batch of up to 64 depth-ordered Gaussians.
+struct RowBatch {
+  int4 rect[kWave];
+  uint32_t row0[kWave];  // exclusive prefix of the row counts in the batch
+  RowEllipse ell[kWave];
+  uint32_t id[kWave];
+  int mark[kWave];
+};
 
-// A wave per window, 64 Gaussians per batch: their kept tiles (the count
-// kernel's decisions, stored as bits, or its test repeated for rectangles
-// above kBitTiles tiles) are keyed and written contiguously from the
-// batch's first pair offset in emission order (Gaussian, then row-major
-// tile), a ballot prefix placing each lane's key.
+constexpr int kEmitThreads = kWave;  // one wave per workgroup: __syncthreads is a wave barrier
+
+// A wave per 64 depth-ordered Gaussians.  Their rectangle rows are
+// flattened Gaussian by Gaussian and handed out 64 per round; a Gaussian
+// whose first row falls in the round marks its slot and an inclusive
+// max-scan carries each owner to the following slots, so a lane finds its
+// Gaussian without a search.  Each lane takes its row's span; a wave scan of
+// the span lengths places the row's keys after those of the rows before it,
+// starting from the batch's first pair offset (pairs are emitted Gaussian by
+// Gaussian, row by row, columns ascending).  Tiles outside the valid set get
+// the sentinel tile id n_t.
 template <typename K>
-__global__ void __launch_bounds__(kBinThreads) emit_kernel(
-    const int4* __restrict__ rect_sorted, const uint64_t* __restrict__ off, const int32_t* __restrict__ win_first,
-    uint32_t n_win, const uint32_t* __restrict__ ids_sorted, const float4* __restrict__ splat,
-    const uint64_t* __restrict__ tile_bits, const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t,
+__global__ void __launch_bounds__(kEmitThreads) emit_kernel(
+    const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ off, const uint32_t* __restrict__ ids_sorted,
+    int64_t n, const float4* __restrict__ splat, const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t,
     int id_bits, double tau, uint32_t total, K* __restrict__ keys) {
-  __shared__ WaveBatch wb;
+  __shared__ RowBatch rb;
   const int lane = lane_id();
-  const uint32_t w = blockIdx.x;
-  if (w >= n_win) return;
-  const int64_t j_end = win_first[w + 1];
-  for (int64_t b0 = win_first[w]; b0 < j_end; b0 += kWave) {
-    const int64_t j = b0 + lane;
-    int4 r = make_int4(0, 0, 0, 0);
-    uint32_t g = 0;
-    if (j < j_end) {
-      r = rect_sorted[j];
-      g = ids_sorted[j];
-    }
-    const uint32_t area = (uint32_t)((r.z - r.x) * (r.w - r.y));
-    uint64_t bits[kBitWords] = {0, 0, 0, 0};
-    if (area > 0 && area <= kBitTiles)
-      for (int q = 0; q < kBitWords; ++q) bits[q] = tile_bits[(int64_t)g * kBitWords + q];
-    uint32_t my_start;
-    const uint32_t batch_tiles = load_batch(wb, r, area, splat, g, my_start);  // barrier: old slots free
-    for (int q = 0; q < kBitWords; ++q) wb.bits[lane][q] = bits[q];
+  const int64_t b0 = (int64_t)blockIdx.x * kWave;
+  const int64_t j = b0 + lane;
+  int4 r = make_int4(0, 0, 0, 0);
+  uint32_t g = 0, rows = 0;
+  if (j < n && off[j + 1] > off[j]) {
+    r = rect_sorted[j];
+    g = ids_sorted[j];
+    rows = (uint32_t)(r.w - r.y);
+  }
+  const uint32_t incl = wave_inclusive_scan_u32(rows);
+  const uint32_t my_row0 = incl - rows;
+  const uint32_t n_rows = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+  if (n_rows == 0) return;  // wave-uniform: no Gaussian of the batch has pairs
+  rb.rect[lane] = r;
+  rb.row0[lane] = my_row0;
+  rb.id[lane] = g;
+  if (rows > 0) rb.ell[lane] = load_row_ellipse(splat, g, tau);
+  const uint32_t base = off[b0];  // pair offset of the batch's first Gaussian
+  uint32_t written = 0;           // wave-uniform
+  int carry = -1;
+  for (uint32_t f0 = 0; f0 < n_rows; f0 += kWave) {
+    rb.mark[lane] = -1;
     __syncthreads();
-    const uint32_t base = (uint32_t)off[b0];  // pair offset of the batch's first Gaussian
-    uint32_t written = 0;                     // wave-uniform
-    walk_rect_tiles(wb, my_start, area, batch_tiles, [&](bool in, int jl, int tx, int ty, uint32_t l) {
-      bool keep = false;
-      if (in) {
-        const int4 rj = wb.rect[jl];
-        if ((uint32_t)((rj.z - rj.x) * (rj.w - rj.y)) <= kBitTiles)
-          keep = (wb.bits[jl][l >> 6] >> (l & 63)) & 1ull;  // the count kernel's decision
-        else
-          keep = tile_touches(wb.ell[jl], tx, ty, tau);
-      }
-      const uint64_t kb = __ballot(keep);
-      const uint32_t pos = base + written + (uint32_t)mask_rank(kb);
-      if (keep && pos < total) {  // pos < total always (the count kernel's test); the bound is a safeguard
-        uint32_t tile = (uint32_t)(ty * tiles_x + tx);
+    if (rows > 0 && my_row0 >= f0 && my_row0 - f0 < (uint32_t)kWave) rb.mark[my_row0 - f0] = lane;
+    __syncthreads();
+    const int jl = max(wave_max_scan(rb.mark[lane]), carry);
+    carry = __builtin_amdgcn_readlane(jl, kWave - 1);
+    const uint32_t f = f0 + (uint32_t)lane;
+    // jl >= 0 whenever f < n_rows: the first Gaussian with rows starts at row 0
+    const bool in = f < n_rows && jl >= 0;
+    int lo = 0, hi = -1, ty = 0;
+    uint32_t gid = 0;
+    if (in) {
+      const int4 rj = rb.rect[jl];
+      ty = rj.y + (int)(f - rb.row0[jl]);
+      gid = rb.id[jl];
+      row_span(rb.ell[jl], ty, rj.x, rj.z, lo, hi);
+    }
+    const uint32_t c = (uint32_t)max(hi - lo + 1, 0);
+    const uint32_t ci = wave_inclusive_scan_u32(c);
+    const uint32_t pos0 = base + written + ci - c;
+    written += (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
+    const int64_t trow = (int64_t)ty * tiles_x;
+    for (uint32_t k = 0; k < c; ++k) {
+      const uint32_t pos = pos0 + k;
+      if (pos < total) {  // always (same spans as the count kernel); the bound is a safeguard
+        uint32_t tile = (uint32_t)(trow + lo + (int)k);
         if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
-        keys[pos] = ((K)tile << id_bits) | (K)wb.id[jl];
+        keys[pos] = ((K)tile << id_bits) | (K)gid;
       }
-      written += (uint32_t)__popcll(kb);
-    });
+    }
+    __syncthreads();  // the round's mark reads before the next round's writes
   }
 }
 
 // ------------------------------------------------------------------ workspace
 struct SortWs {
-  unsigned long long* scalars;  // [3][TGS_COUNTER_SLOTS] partial totals: valid pairs, pairs, rect tiles
+  unsigned long long* scalars;  // [2][TGS_COUNTER_SLOTS] partial totals: valid pairs, pairs
   uint32_t* emit_cnt;           // [n] pairs each Gaussian emits
-  uint64_t* tile_bits;          // [n][kBitWords] keep decisions of the first kBitTiles rectangle tiles
   int4* rect_sorted;            // [n] rectangles in depth order
-  uint64_t* area_sorted;        // [n] (rectangle area << 32) | pair count, depth order
-  uint64_t* off;                // [n + 1] its exclusive prefix: rectangle-tile and pair offsets
-  uint64_t* partials64;         // scan block sums of the offsets
-  int32_t* win_first;           // [max_windows + 1] first Gaussian of each emit window
+  uint32_t* cnt_sorted;         // [n] pair counts in depth order
+  uint32_t* off;                // [n + 1] their exclusive prefix: pair offsets
   uint32_t* dkeys[2];           // [n] depth keys (ping-pong)
   uint32_t* dvals[2];           // [n] ids
   uint32_t* partials;           // scan block sums, digit totals
@@ -693,9 +598,6 @@ struct SortWs {
   void* pkeys[2];               // [capacity] pair keys (u32 or u64), ping-pong
   size_t bytes;
 };
-
-// Emit windows: at most n / 16 + 1024, of at least 4096 rectangle tiles.
-static int64_t max_windows(int64_t n) { return n / 16 + 1024; }
 
 static SortWs layout(void* ws, int64_t n, int64_t capacity) {
   const int64_t cap = std::max<int64_t>(capacity, 1), nn = std::max<int64_t>(n, 1);
@@ -712,14 +614,11 @@ static SortWs layout(void* ws, int64_t n, int64_t capacity) {
     return (void*)p;
   };
   SortWs w;
-  w.scalars = (unsigned long long*)take(sizeof(unsigned long long) * 3 * TGS_COUNTER_SLOTS);
+  w.scalars = (unsigned long long*)take(sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS);
   w.emit_cnt = (uint32_t*)take(sizeof(uint32_t) * nn);
-  w.tile_bits = (uint64_t*)take(sizeof(uint64_t) * kBitWords * nn);
   w.rect_sorted = (int4*)take(sizeof(int4) * nn);
-  w.area_sorted = (uint64_t*)take(sizeof(uint64_t) * nn);
-  w.off = (uint64_t*)take(sizeof(uint64_t) * (nn + 1));
-  w.partials64 = (uint64_t*)take(sizeof(uint64_t) * part_n);
-  w.win_first = (int32_t*)take(sizeof(int32_t) * (max_windows(nn) + 1));
+  w.cnt_sorted = (uint32_t*)take(sizeof(uint32_t) * nn);
+  w.off = (uint32_t*)take(sizeof(uint32_t) * (nn + 1));
   for (int k = 0; k < 2; ++k) {
     w.dkeys[k] = (uint32_t*)take(sizeof(uint32_t) * nn);
     w.dvals[k] = (uint32_t*)take(sizeof(uint32_t) * nn);
@@ -755,18 +654,12 @@ static void sort_depth(const SortWs& w, uint32_t n, uint32_t** keys_out, uint32_
 }
 
 template <typename K>
-static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t total, uint32_t rect_total,
-                       const float4* splat, const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits,
-                       int tbits, double tau, const float* depth, uint32_t* vals, uint64_t* keys64,
-                       uint32_t* ranges, hipStream_t s) {
+static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t total, const float4* splat,
+                       const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits, int tbits, double tau,
+                       const float* depth, uint32_t* vals, uint64_t* keys64, uint32_t* ranges, hipStream_t s) {
   K* kb[2] = {(K*)w.pkeys[0], (K*)w.pkeys[1]};
-  const uint32_t win = (uint32_t)std::max<int64_t>(4096, ceil_div((int64_t)rect_total, max_windows(n)));
-  const uint32_t n_win = (uint32_t)ceil_div((int64_t)rect_total, (int64_t)win);
-  hipLaunchKernelGGL(window_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, w.off, n, win, n_win,
-                     w.win_first);
-  hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(n_win, kBinWaves)), dim3(kBinThreads), 0, s,
-                     w.rect_sorted, w.off, w.win_first, n_win, ids, splat, w.tile_bits, tile_slot, tiles_x, n_t,
-                     id_bits, tau, total, kb[0]);
+  hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(n, kWave)), dim3(kEmitThreads), 0, s,
+                     w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, id_bits, tau, total, kb[0]);
   const int passes = pass_count(tbits);
   int cur = 0, shift = id_bits;
   for (int p = 0; p < passes; ++p) {
@@ -818,49 +711,47 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
 
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t, 256)), dim3(256), 0, s, ranges,
                      2 * (int64_t)n_t, 0u);
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(6 * TGS_COUNTER_SLOTS, 256)), dim3(256), 0, s,
-                     (uint32_t*)w.scalars, (int64_t)(6 * TGS_COUNTER_SLOTS), 0u);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(4 * TGS_COUNTER_SLOTS, 256)), dim3(256), 0, s,
+                     (uint32_t*)w.scalars, (int64_t)(4 * TGS_COUNTER_SLOTS), 0u);
   if (n == 0) {
     *n_pairs = 0;
     return hip_status("tgs_bin_sort");
   }
-  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kBinThreads), 0, s,
+  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountThreads)), dim3(kCountThreads), 0, s,
                      (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau,
-                     w.dkeys[0], w.dvals[0], w.emit_cnt, w.tile_bits, touched, w.scalars);
+                     w.dkeys[0], w.dvals[0], w.emit_cnt, touched, w.scalars);
   // (depth, id) order; Gaussians without pairs last
   uint32_t* dk = nullptr;
   uint32_t* perm = nullptr;
   if (sort_items(n) == 16) sort_depth<16>(w, (uint32_t)n, &dk, &perm, s);
   else sort_depth<4>(w, (uint32_t)n, &dk, &perm, s);
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, perm, w.emit_cnt,
-                     (const int4*)rect, n, tiles_x, tiles_y, w.rect_sorted, w.area_sorted);
-  exclusive_scan<uint64_t>(w.area_sorted, w.off, n, w.partials64, s);
-  unsigned long long slots[3 * TGS_COUNTER_SLOTS] = {};
+                     (const int4*)rect, n, tiles_x, tiles_y, w.rect_sorted, w.cnt_sorted);
+  exclusive_scan<uint32_t>(w.cnt_sorted, w.off, n, w.partials, s);  // wraps only past capacity (checked below)
+  unsigned long long slots[2 * TGS_COUNTER_SLOTS] = {};
   if (hipMemcpyAsync(slots, w.scalars, sizeof(slots), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return hip_status("tgs_bin_sort: count readback");
-  unsigned long long sum[3] = {0, 0, 0};
-  for (int k = 0; k < 3; ++k)
+  unsigned long long sum[2] = {0, 0};
+  for (int k = 0; k < 2; ++k)
     for (int q = 0; q < TGS_COUNTER_SLOTS; ++q) sum[k] += slots[k * TGS_COUNTER_SLOTS + q];
-  const unsigned long long valid_total = sum[0], total64 = sum[1], rect64 = sum[2];
+  const unsigned long long valid_total = sum[0], total64 = sum[1];
   if ((int64_t)total64 > capacity) {
     *n_pairs = (int64_t)total64;
     set_error("tgs_bin_sort: %llu pairs exceed capacity %lld", total64, (long long)capacity);
     return TGS_ERR_CAPACITY;
   }
-  // the packed 64-bit offsets hold both prefixes while each total fits 32 bits
-  TGS_REQUIRE(rect64 < (1ull << 32), "tgs_bin_sort: %llu rectangle tiles exceed 2^32", rect64);
-  const uint32_t total = (uint32_t)total64, rect_total = (uint32_t)rect64;
+  const uint32_t total = (uint32_t)total64;  // capacity < 2^32
   *n_pairs = (int64_t)valid_total;
   if (total == 0) return hip_status("tgs_bin_sort");
 
   const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
   const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
   if (id_bits + tbits <= 32)
-    sort_pairs<uint32_t>(w, perm, n, total, rect_total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                         tbits, tau, depth, vals, keys, ranges, s);
+    sort_pairs<uint32_t>(w, perm, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits, tbits, tau,
+                         depth, vals, keys, ranges, s);
   else
-    sort_pairs<uint64_t>(w, perm, n, total, rect_total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                         tbits, tau, depth, vals, keys, ranges, s);
+    sort_pairs<uint64_t>(w, perm, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits, tbits, tau,
+                         depth, vals, keys, ranges, s);
   return hip_status("tgs_bin_sort");
 }
