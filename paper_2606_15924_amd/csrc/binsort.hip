@@ -682,6 +682,39 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
 
 using namespace tgs;
 
+// Pinned host buffer and event for the count totals, one per host thread
+// and device (kept until the process ends).  A call waits on its event
+// before it returns, so successive calls on a thread never share them in
+// flight.
+struct Readback {
+  int dev = -1;
+  unsigned long long* host = nullptr;
+  hipEvent_t ev = nullptr;
+};
+
+static Readback* readback() {
+  static thread_local Readback rb[8];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  Readback& r = rb[dev & 7];
+  if (r.dev != dev) {
+    if (r.ev != nullptr) (void)hipEventDestroy(r.ev);
+    r.ev = nullptr;
+    if (r.host == nullptr &&
+        hipHostMalloc((void**)&r.host, sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS, hipHostMallocPortable) !=
+            hipSuccess) {
+      r.host = nullptr;
+      return nullptr;
+    }
+    if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) {
+      r.ev = nullptr;
+      return nullptr;
+    }
+    r.dev = dev;
+  }
+  return &r;
+}
+
 extern "C" size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32_t n_tiles) {
   (void)n_tiles;
   if (n < 0 || capacity < 0) return 0;
@@ -720,6 +753,15 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
   hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountThreads)), dim3(kCountThreads), 0, s,
                      (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau,
                      w.dkeys[0], w.dvals[0], w.emit_cnt, touched, w.scalars);
+  // The totals go to pinned host memory right after the count; the host
+  // queues the depth sort, gather and scan before it waits for them, so the
+  // device keeps working while the host reads the totals and sizes the rest.
+  Readback* rb = readback();
+  if (rb == nullptr) return hip_status("tgs_bin_sort: pinned readback buffer");
+  if (hipMemcpyAsync(rb->host, w.scalars, sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS,
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipEventRecord(rb->ev, s) != hipSuccess)
+    return hip_status("tgs_bin_sort: count readback");
   // (depth, id) order; Gaussians without pairs last
   uint32_t* dk = nullptr;
   uint32_t* perm = nullptr;
@@ -728,10 +770,8 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, perm, w.emit_cnt,
                      (const int4*)rect, n, tiles_x, tiles_y, w.rect_sorted, w.cnt_sorted);
   exclusive_scan<uint32_t>(w.cnt_sorted, w.off, n, w.partials, s);  // wraps only past capacity (checked below)
-  unsigned long long slots[2 * TGS_COUNTER_SLOTS] = {};
-  if (hipMemcpyAsync(slots, w.scalars, sizeof(slots), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return hip_status("tgs_bin_sort: count readback");
+  if (hipEventSynchronize(rb->ev) != hipSuccess) return hip_status("tgs_bin_sort: count readback");
+  const unsigned long long* slots = rb->host;
   unsigned long long sum[2] = {0, 0};
   for (int k = 0; k < 2; ++k)
     for (int q = 0; q < TGS_COUNTER_SLOTS; ++q) sum[k] += slots[k * TGS_COUNTER_SLOTS + q];
