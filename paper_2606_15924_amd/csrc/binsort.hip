@@ -15,10 +15,12 @@
 //   count     a thread per Gaussian over its rectangle rows: kept pairs and
 //             kept pairs in valid tiles, depth key (Gaussians without a kept
 //             valid tile get a key above every depth), touched flag
-//   sort      LSD radix sort of (depth key, id) over n: stable, so ties keep
-//             id order; Gaussians with pairs come first
-//   gather    rectangles and pair counts in depth order, exclusive scan ->
-//             pair offsets; the totals are read back once
+//   sort      LSD radix sort of (depth key, id) over n, one kernel per pass:
+//             stable, so ties keep id order; Gaussians with pairs come
+//             first; the last pass gathers rectangles and pair counts into
+//             depth order
+//   scan      exclusive scan of the counts -> pair offsets; the totals are
+//             read back once
 //   emit      a wave per 64 depth-ordered Gaussians walks their rows; each
 //             row's span is keyed and written contiguously after the rows
 //             before it; tiles outside the valid set get the sentinel tile
@@ -63,24 +65,17 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const T* __re
   if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(1024) scan_partials_kernel(T* __restrict__ part, int64_t np) {
-  __shared__ T lds[1024 / kWave];
-  T carry = 0;
-  for (int64_t b = 0; b < np; b += 1024) {
-    const int64_t i = b + threadIdx.x;
-    const T v = i < np ? part[i] : 0;
-    T total;
-    const T ex = block_exclusive_scan<1024, T>(v, lds, &total);
-    if (i < np) part[i] = carry + ex;
-    carry += total;
-  }
-}
-
+// Down-sweep of a block: its prefix is the sum of the earlier blocks' sums
+// (each block adds them up itself, so the scan takes two launches).
 template <typename T>
 __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const T* __restrict__ in, int64_t n,
                                                                 const T* __restrict__ part,
                                                                 T* __restrict__ out) {
+  __shared__ T lds[kScanThreads / kWave];
+  T before = 0;
+  for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kScanThreads) before += part[b];
+  T block_pre;
+  (void)block_exclusive_scan<kScanThreads, T>(before, lds, &block_pre);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   T v[kScanItems];
   T s = 0;
@@ -89,9 +84,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const T* __rest
     v[k] = i < n ? in[i] : 0;
     s += v[k];
   }
-  __shared__ T lds[kScanThreads / kWave];
   T total;
-  T run = part[blockIdx.x] + block_exclusive_scan<kScanThreads, T>(s, lds, &total);
+  T run = block_pre + block_exclusive_scan<kScanThreads, T>(s, lds, &total);
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + k;
     if (i < n) out[i] = run;
@@ -105,6 +99,7 @@ __global__ void __launch_bounds__(64) set_kernel(T* __restrict__ p, T v) {
   if (threadIdx.x == 0) *p = v;
 }
 
+// out[0..n] = exclusive prefix of in[0..n) and the total.
 template <typename T>
 static void exclusive_scan(const T* in, T* out, int64_t n, T* partials, hipStream_t s) {
   const int64_t nb = scan_partials(n);
@@ -113,7 +108,6 @@ static void exclusive_scan(const T* in, T* out, int64_t n, T* partials, hipStrea
     return;
   }
   hipLaunchKernelGGL(scan_reduce_kernel<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials);
-  hipLaunchKernelGGL(scan_partials_kernel<T>, dim3(1), dim3(1024), 0, s, partials, nb);
   hipLaunchKernelGGL(scan_down_kernel<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials, out);
 }
 
@@ -213,6 +207,10 @@ __device__ __forceinline__ int wave_max_scan(int v) {
 
 // ------------------------------------------------------------------ count
 constexpr int kCountThreads = 256;
+// Depth sort blocks (see depth_pass_kernel): 256 threads x 8 keys, 256 digits.
+constexpr int kDepthItems = 8;
+constexpr int kDepthBlockKeys = 256 * kDepthItems;
+constexpr int kDepthDigits = 256;
 
 // One thread per Gaussian walks the rows of its rectangle: kept pairs, and
 // kept pairs in valid tiles (every kept pair when there is no tile subset);
@@ -258,21 +256,6 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(
   }
 }
 
-// Rectangles and pair counts in depth order (count zero for Gaussians
-// without pairs); an exclusive scan of the counts gives the pair offsets.
-__global__ void __launch_bounds__(256) gather_kernel(const uint32_t* __restrict__ perm,
-                                                     const uint32_t* __restrict__ emit_cnt,
-                                                     const int4* __restrict__ rect, int64_t n,
-                                                     int tiles_x, int tiles_y,
-                                                     int4* __restrict__ rect_sorted,
-                                                     uint32_t* __restrict__ cnt_sorted) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const uint32_t g = perm[j];
-  rect_sorted[j] = clamp_rect(rect[g], tiles_x, tiles_y);
-  cnt_sorted[j] = emit_cnt[g];
-}
-
 // ------------------------------------------------------------------ ranges
 // One thread per sorted pair: a tile boundary writes the start of the new
 // tile and the end of the previous one, the last pair the end of its tile.
@@ -299,9 +282,6 @@ __global__ void __launch_bounds__(256) ranges_kernel(const K* __restrict__ keys,
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kPairItems = 16;  // keys per thread of the pair sort
-
-// Keys per thread: 16 for large sorts, 4 for small ones (more workgroups).
-static int sort_items(int64_t n) { return n >= (1ll << 20) ? 16 : 4; }
 
 static int64_t sort_blocks(int64_t n, int items) { return ceil_div(n, (int64_t)kSortThreads * items); }
 
@@ -466,6 +446,128 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
   }
 }
 
+// ------------------------------------------------------------------ depth sort
+// The depth sort (four 8-bit passes over n keys with ids) takes two kernels
+// per pass: the per-block digit counts (the table hist[digit][block], row
+// stride hstride), then the scatter, in which each block derives its output
+// offsets from the table itself: for its digit d, a thread adds up the
+// counts of the earlier blocks and of all blocks (no separate scan of the
+// table).  The last pass writes the ids and gathers each Gaussian's
+// rectangle and pair count into depth order instead of writing keys.
+static_assert(kDepthBlockKeys == kSortThreads * kDepthItems && kDepthDigits == kSortThreads,
+              "a depth pass block: one thread per digit");
+
+static int64_t depth_blocks(int64_t n) { return ceil_div(n, (int64_t)kDepthBlockKeys); }
+static int64_t depth_hstride(int64_t n) { return ceil_div(std::max<int64_t>(depth_blocks(n), 1), 4) * 4; }
+
+struct DepthPassOut {
+  uint32_t* keys;             // not last: keys and ids
+  uint32_t* vals;
+  uint32_t* ids_sorted;       // last: ids, rectangles and pair counts in depth order
+  const int4* rect;
+  const uint32_t* emit_cnt;
+  int4* rect_sorted;
+  uint32_t* cnt_sorted;
+  int tiles_x, tiles_y;
+};
+
+template <bool kLast>
+__global__ void __launch_bounds__(kSortThreads) depth_pass_kernel(const uint32_t* __restrict__ keys_in,
+                                                                  const uint32_t* __restrict__ vals_in, uint32_t n,
+                                                                  int shift, int hstride,
+                                                                  const uint32_t* __restrict__ hist, DepthPassOut o) {
+  constexpr int kItems = kDepthItems, kBlockKeys = kDepthBlockKeys, kDigits = kDepthDigits;
+  __shared__ uint32_t s_cnt[kSortWaves][kDigits];  // per-wave digit counts, then block-local offsets
+  __shared__ uint32_t s_gbase[kDigits];            // global position of block-local position 0 of the digit
+  __shared__ uint32_t s_keys[kBlockKeys];
+  __shared__ uint32_t s_vals[kBlockKeys];
+  __shared__ uint32_t s_red[kSortWaves];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  for (int i = tid; i < kSortWaves * kDigits; i += kSortThreads) (&s_cnt[0][0])[i] = 0;
+  // counts of digit tid in the earlier blocks and in all blocks (rows padded to 4 with zeros)
+  uint32_t before = 0, all_d = 0;
+  {
+    const uint4* row = (const uint4*)(hist + (int64_t)tid * hstride);
+    const int b_me = (int)blockIdx.x, nq = hstride / 4;
+    auto add = [&](uint4 c, int b) {
+      all_d += c.x + c.y + c.z + c.w;
+      before += (b < b_me ? c.x : 0u) + (b + 1 < b_me ? c.y : 0u) + (b + 2 < b_me ? c.z : 0u) +
+                (b + 3 < b_me ? c.w : 0u);
+    };
+    int q = 0;
+    for (; q + 8 <= nq; q += 8) {  // eight independent loads in flight
+      uint4 c[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) c[j] = row[q + j];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) add(c[j], 4 * (q + j));
+    }
+    for (; q < nq; ++q) add(row[q], 4 * q);
+  }
+  const int64_t blk0 = (int64_t)blockIdx.x * kBlockKeys;
+  const int64_t wbase = blk0 + (int64_t)wave * kWave * kItems;
+  uint32_t key[kItems], val[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = wbase + k * kWave + lane;
+    key[k] = i < n ? keys_in[i] : 0u;
+    val[k] = i < n ? vals_in[i] : 0u;
+  }
+  __syncthreads();
+  const uint64_t below = lanes_below();
+  uint32_t rank[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const bool valid = wbase + k * kWave + lane < n;
+    const uint32_t d = (key[k] >> shift) & (kDigits - 1u);
+    const uint64_t peers = digit_peers<8>(d, valid);
+    const uint32_t r = (uint32_t)__popcll(peers & below);
+    const uint32_t prior = valid ? s_cnt[wave][d] : 0u;
+    rank[k] = prior + r;
+    if (valid && r == 0) s_cnt[wave][d] = prior + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  uint32_t pre[kSortWaves];
+  uint32_t tot = 0;
+  for (int w = 0; w < kSortWaves; ++w) {
+    pre[w] = tot;
+    tot += s_cnt[w][tid];
+  }
+  uint32_t all;
+  const uint32_t lstart = block_exclusive_scan<kSortThreads, uint32_t>(tot, s_red, &all);
+  const uint32_t dstart = block_exclusive_scan<kSortThreads, uint32_t>(all_d, s_red, &all);
+  for (int w = 0; w < kSortWaves; ++w) s_cnt[w][tid] = lstart + pre[w];
+  s_gbase[tid] = dstart + before - lstart;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (wbase + k * kWave + lane < n) {
+      const uint32_t d = (key[k] >> shift) & (kDigits - 1u);
+      const uint32_t lp = s_cnt[wave][d] + rank[k];
+      s_keys[lp] = key[k];
+      s_vals[lp] = val[k];
+    }
+  }
+  __syncthreads();
+  const int count = (int)min((int64_t)kBlockKeys, (int64_t)n - blk0);
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int lp = k * kSortThreads + tid;
+    if (lp < count) {
+      const uint32_t kk = s_keys[lp], g = s_vals[lp];
+      const uint32_t dst = s_gbase[(kk >> shift) & (kDigits - 1u)] + (uint32_t)lp;
+      if (kLast) {
+        o.ids_sorted[dst] = g;
+        o.rect_sorted[dst] = clamp_rect(o.rect[g], o.tiles_x, o.tiles_y);
+        o.cnt_sorted[dst] = o.emit_cnt[g];
+      } else {
+        o.keys[dst] = kk;
+        o.vals[dst] = g;
+      }
+    }
+  }
+}
+
 // One radix pass over n keys on bits [shift, shift + kBits); the histogram
 // table is taken here unless the caller already wrote it (hist_ready).
 template <typename K, bool kVals, bool kFinal, int kBits, int kItems>
@@ -586,10 +688,15 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
 // ------------------------------------------------------------------ workspace
 struct SortWs {
   unsigned long long* scalars;  // [2][TGS_COUNTER_SLOTS] partial totals: valid pairs, pairs
+  uint32_t* dhist[4];           // [256][hstride] per-block digit counts of each depth pass
+  uint32_t* zeroed;             // scalars and dhist: one region, cleared at the start
+  int64_t zeroed_words;         // its size in 32-bit words
+  int hstride;                  // row stride of the depth tables
   uint32_t* emit_cnt;           // [n] pairs each Gaussian emits
   int4* rect_sorted;            // [n] rectangles in depth order
   uint32_t* cnt_sorted;         // [n] pair counts in depth order
-  uint32_t* off;                // [n + 1] their exclusive prefix: pair offsets
+  uint32_t* ids_sorted;         // [n] Gaussian ids in depth order
+  uint32_t* off;                // [n + 1] exclusive prefix of the counts: pair offsets
   uint32_t* dkeys[2];           // [n] depth keys (ping-pong)
   uint32_t* dvals[2];           // [n] ids
   uint32_t* partials;           // scan block sums, digit totals
@@ -614,10 +721,17 @@ static SortWs layout(void* ws, int64_t n, int64_t capacity) {
     return (void*)p;
   };
   SortWs w;
-  w.scalars = (unsigned long long*)take(sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS);
+  w.hstride = (int)depth_hstride(nn);
+  const int64_t table_words = (int64_t)kDepthDigits * w.hstride;
+  const int64_t scalar_words = 2 * 2 * TGS_COUNTER_SLOTS;
+  w.zeroed_words = scalar_words + 4 * table_words;
+  w.zeroed = (uint32_t*)take(sizeof(uint32_t) * w.zeroed_words);
+  w.scalars = (unsigned long long*)w.zeroed;
+  for (int k = 0; k < 4; ++k) w.dhist[k] = w.zeroed ? w.zeroed + scalar_words + k * table_words : nullptr;
   w.emit_cnt = (uint32_t*)take(sizeof(uint32_t) * nn);
   w.rect_sorted = (int4*)take(sizeof(int4) * nn);
   w.cnt_sorted = (uint32_t*)take(sizeof(uint32_t) * nn);
+  w.ids_sorted = (uint32_t*)take(sizeof(uint32_t) * nn);
   w.off = (uint32_t*)take(sizeof(uint32_t) * (nn + 1));
   for (int k = 0; k < 2; ++k) {
     w.dkeys[k] = (uint32_t*)take(sizeof(uint32_t) * nn);
@@ -637,20 +751,35 @@ static int bits_for(uint64_t max_value) {  // bits needed to represent 0..max_va
   return b;
 }
 
-// Stable LSD sort of the n depth keys with their ids; returns the buffers
-// holding the sorted keys and ids.
-template <int kItems>
-static void sort_depth(const SortWs& w, uint32_t n, uint32_t** keys_out, uint32_t** ids_out, hipStream_t s) {
-  uint32_t* k[2] = {w.dkeys[0], w.dkeys[1]};
-  uint32_t* v[2] = {w.dvals[0], w.dvals[1]};
+// Stable LSD sort of the n depth keys with their ids (the count kernel has
+// filled the first pass's table); the last pass writes ids, rectangles and
+// pair counts in depth order.
+static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_x, int tiles_y, hipStream_t s) {
+  const unsigned nb = (unsigned)depth_blocks(n);
   int cur = 0;
   for (int p = 0; p < 4; ++p) {
-    const ScatterOut o = {k[cur ^ 1], v[cur ^ 1], 0, nullptr, nullptr};
-    radix_pass<uint32_t, true, false, 8, kItems>(k[cur], v[cur], n, 8 * p, false, w.hist, w.hoffs, w.partials, o, s);
+    // rows of hstride entries (the padding stays zero from the start-of-call fill)
+    hipLaunchKernelGGL((radix_hist_kernel<uint32_t, 8, kDepthItems>), dim3(nb), dim3(kSortThreads), 0, s,
+                       w.dkeys[cur], n, 8 * p, w.hstride, w.dhist[p]);
+    DepthPassOut o{};
+    if (p < 3) {
+      o.keys = w.dkeys[cur ^ 1];
+      o.vals = w.dvals[cur ^ 1];
+      hipLaunchKernelGGL(depth_pass_kernel<false>, dim3(nb), dim3(kSortThreads), 0, s, w.dkeys[cur], w.dvals[cur],
+                         n, 8 * p, w.hstride, w.dhist[p], o);
+    } else {
+      o.ids_sorted = w.ids_sorted;
+      o.rect = rect;
+      o.emit_cnt = w.emit_cnt;
+      o.rect_sorted = w.rect_sorted;
+      o.cnt_sorted = w.cnt_sorted;
+      o.tiles_x = tiles_x;
+      o.tiles_y = tiles_y;
+      hipLaunchKernelGGL(depth_pass_kernel<true>, dim3(nb), dim3(kSortThreads), 0, s, w.dkeys[cur], w.dvals[cur],
+                         n, 8 * p, w.hstride, w.dhist[p], o);
+    }
     cur ^= 1;
   }
-  *keys_out = k[cur];
-  *ids_out = v[cur];
 }
 
 template <typename K>
@@ -744,8 +873,8 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
 
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t, 256)), dim3(256), 0, s, ranges,
                      2 * (int64_t)n_t, 0u);
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(4 * TGS_COUNTER_SLOTS, 256)), dim3(256), 0, s,
-                     (uint32_t*)w.scalars, (int64_t)(4 * TGS_COUNTER_SLOTS), 0u);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(w.zeroed_words, 256)), dim3(256), 0, s, w.zeroed,
+                     w.zeroed_words, 0u);
   if (n == 0) {
     *n_pairs = 0;
     return hip_status("tgs_bin_sort");
@@ -763,12 +892,7 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
       hipEventRecord(rb->ev, s) != hipSuccess)
     return hip_status("tgs_bin_sort: count readback");
   // (depth, id) order; Gaussians without pairs last
-  uint32_t* dk = nullptr;
-  uint32_t* perm = nullptr;
-  if (sort_items(n) == 16) sort_depth<16>(w, (uint32_t)n, &dk, &perm, s);
-  else sort_depth<4>(w, (uint32_t)n, &dk, &perm, s);
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, perm, w.emit_cnt,
-                     (const int4*)rect, n, tiles_x, tiles_y, w.rect_sorted, w.cnt_sorted);
+  sort_depth(w, (uint32_t)n, (const int4*)rect, tiles_x, tiles_y, s);
   exclusive_scan<uint32_t>(w.cnt_sorted, w.off, n, w.partials, s);  // wraps only past capacity (checked below)
   if (hipEventSynchronize(rb->ev) != hipSuccess) return hip_status("tgs_bin_sort: count readback");
   const unsigned long long* slots = rb->host;
@@ -788,10 +912,10 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
   const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
   const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
   if (id_bits + tbits <= 32)
-    sort_pairs<uint32_t>(w, perm, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits, tbits, tau,
+    sort_pairs<uint32_t>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits, tbits, tau,
                          depth, vals, keys, ranges, s);
   else
-    sort_pairs<uint64_t>(w, perm, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits, tbits, tau,
+    sort_pairs<uint64_t>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits, tbits, tau,
                          depth, vals, keys, ranges, s);
   return hip_status("tgs_bin_sort");
 }

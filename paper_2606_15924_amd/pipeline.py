@@ -168,11 +168,12 @@ class Trainer:
         self.fused_ws = torch.empty(B.tgs_project_bwd_optimizer_workspace_size(self.n), dtype=torch.uint8,
                                     device=self.dev)
         self.events: dict | None = None   # stage name -> [(start, end)] when timing
+        self.timed_stages: set | None = None  # stages to time (all when None)
 
     @contextlib.contextmanager
     def _stage(self, name):
         """Brackets a stage with HIP events on the current stream when timing."""
-        if self.events is None:
+        if self.events is None or (self.timed_stages is not None and name not in self.timed_stages):
             yield
             return
         a = torch.cuda.Event(enable_timing=True)
