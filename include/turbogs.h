@@ -47,12 +47,14 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 3u
+#define TGS_ABI_VERSION 4u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
 #define TGS_PARAM_ROWS 59
 #define TGS_COUNTER_SLOTS 64 /* slots per counter of tgs_render_fwd */
+#define TGS_RENDER_CHUNKS 4     /* backward workgroups per tile when the forward keeps state */
+#define TGS_RENDER_CHUNK_LEN 64 /* list positions per backward chunk (the last takes the rest) */
 
 enum {
   TGS_OK = 0,
@@ -194,12 +196,21 @@ int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const float* depth
  *   counters  nullable [2][TGS_COUNTER_SLOTS] uint64: evaluations are added
  *             to row 0 and blends to row 1, spread over the slots (a
  *             workgroup adds to slot blockIdx mod TGS_COUNTER_SLOTS, which
- *             keeps same-address atomics rare); the totals are the row sums */
+ *             keeps same-address atomics rare); the totals are the row sums
+ *   state     nullable, tgs_render_state_size(n_slots, max_per_tile) bytes
+ *             (n_slots = n_st, or tiles_x * tiles_y in dense mode with
+ *             max_per_tile 256), 16-byte aligned: each pixel's transmittance
+ *             and accumulated colour (float4 T, r, g, b) at list positions
+ *             c * TGS_RENDER_CHUNK_LEN, c = 1 .. TGS_RENDER_CHUNKS - 1, where
+ *             the walk reaches them; lets tgs_render_bwd split each tile's
+ *             replay into chunks */
+size_t tgs_render_state_size(int32_t n_slots, int32_t max_per_tile);
 int32_t tgs_render_fwd(const float* splat, const uint32_t* vals, const uint32_t* ranges,
                        int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
                        const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
                        int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
-                       float* out, uint32_t* ncontrib, uint64_t* counters, void* stream);
+                       float* out, uint32_t* ncontrib, uint64_t* counters, float* state,
+                       void* stream);
 
 /* Exact adjoint of tgs_render_fwd for the same samples (Sec. 3.6 backward
  * over sampled pixels only).  Per-pixel state is recomputed front to back
@@ -207,13 +218,20 @@ int32_t tgs_render_fwd(const float* splat, const uint32_t* vals, const uint32_t*
  * saved.
  *   dL_dout  [P][4] float (channel 3 ignored)
  *   g2d      [n][9] float, accumulated (+=): dL/d(centre x, y; conic a, b, c;
- *            opacity; r, g, b) */
+ *            opacity; r, g, b)
+ *   state    nullable: the forward's state record for the same call
+ *            arguments.  Given, each tile's replay runs as TGS_RENDER_CHUNKS
+ *            workgroups, chunk c starting at list position
+ *            c * TGS_RENDER_CHUNK_LEN from the recorded state (the last chunk
+ *            takes the rest of the list); the per-pixel arithmetic is the
+ *            same as the single-workgroup replay, only the order of the
+ *            gradient atomics differs. */
 int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, const uint32_t* ranges,
                        int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
                        const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
                        int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
                        const float* out, const uint32_t* ncontrib, const float* dL_dout,
-                       float* g2d, void* stream);
+                       float* g2d, const float* state, void* stream);
 
 /* Sparse supervision of one view (Sec. 3.7: Charbonnier L1 per pixel plus
  * tile NCC with the gradient-balanced weight of Eq. ncc_weight_auto, summed

@@ -23,6 +23,8 @@ G2D_FLOATS = 9
 PARAM_ROWS = 59
 TILE = 16
 COUNTER_SLOTS = 64
+RENDER_CHUNKS = 4
+RENDER_CHUNK_LEN = 64
 
 
 class tgs_camera(ctypes.Structure):
@@ -80,10 +82,11 @@ PROTOTYPES = {
     "tgs_bin_sort_workspace_size": (_SZ, [_I64, _I64, _I32]),
     "tgs_bin_sort": (_I32, [_P, _P, _P, _I64, _P, _I32, _I32, ctypes.c_float, _P, _P, _I64, _P, _P,
                             ctypes.POINTER(_I64), _P, _SZ, _P]),
+    "tgs_render_state_size": (_SZ, [_I32, _I32]),
     "tgs_render_fwd": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
-                              ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P]),
-    "tgs_render_bwd": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
                               ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P]),
+    "tgs_render_bwd": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                              ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P]),
     "tgs_loss": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _I32, _P, ctypes.POINTER(tgs_loss_params),
                         _P, _P, _P, _P, _P]),
     "tgs_ema_age_update": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _P, ctypes.c_float, _P]),
@@ -230,20 +233,24 @@ def tgs_bin_sort(rect, splat, depth, n, tile_slot, tiles_x, tiles_y, alpha_min, 
     return int(n_pairs.value)
 
 
+def tgs_render_state_size(n_slots: int, max_per_tile: int) -> int:
+    return int(lib().tgs_render_state_size(n_slots, max_per_tile))
+
+
 def tgs_render_fwd(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
-                   n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, counters=None):
+                   n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, counters=None, state=None):
     _check(lib().tgs_render_fwd(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
                                 _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
-                                ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(counters), _stream()),
-           "tgs_render_fwd")
+                                ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(counters), _ptr(state),
+                                _stream()), "tgs_render_fwd")
 
 
 def tgs_render_bwd(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
-                   n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL_dout, g2d):
+                   n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL_dout, g2d, state=None):
     _check(lib().tgs_render_bwd(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
                                 _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
                                 ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(dL_dout), _ptr(g2d),
-                                _stream()), "tgs_render_bwd")
+                                _ptr(state), _stream()), "tgs_render_bwd")
 
 
 def tgs_loss(out, gt, height, width, valid_tiles, tile_off, pix, n_st, totals, lp: tgs_loss_params,

@@ -11,7 +11,13 @@
 // The backward replays the same walk front to back, recomputing T and the
 // accumulated colour from the forward outputs (final colour and the number
 // of contributors), so nothing per Gaussian or per (pixel, Gaussian) is
-// stored.  Per Gaussian, each lane's contribution to the nine screen-space
+// stored.  Optionally the forward records each pixel's (T, accumulated
+// colour) at list positions 64, 128 and 192; the backward then runs one
+// workgroup per (tile, chunk of 64 positions, the last chunk taking the
+// rest) that starts from the recorded state.  The replay performs the same
+// operations in the same order, so every per-lane value equals the
+// unchunked one; at 64 samples per tile this turns one wave per tile into
+// up to four, which the SIMDs need to hide latency.  Per Gaussian, each lane's contribution to the nine screen-space
 // gradients is summed across the wave (lane-half swaps, then DPP within rows
 // of 16), and nine lanes of the wave issue one float atomic each.
 //
@@ -112,7 +118,8 @@ __device__ __forceinline__ Staged stage_load(const RasterArgs& a, uint32_t gid, 
 template <int kBlock, bool kDense>
 __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4* __restrict__ out,
                                                             uint32_t* __restrict__ ncontrib,
-                                                            unsigned long long* __restrict__ counters) {
+                                                            unsigned long long* __restrict__ counters,
+                                                            float4* __restrict__ state) {
   __shared__ float4 s_geo[kBlock];
   __shared__ float4 s_app[kBlock];
   __shared__ float s_blue[kBlock];
@@ -153,6 +160,11 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
     // zero-opacity record and never composite)
     for (int j = 0; j < cnt; j += kUnroll) {
       if (__ballot(!done) == 0ull) break;  // the whole wave has terminated
+      const uint32_t pos = pos0 + (uint32_t)j;  // uniform; chunk starts are multiples of kUnroll
+      if (state != nullptr && pos % TGS_RENDER_CHUNK_LEN == 0 && pos > 0 &&
+          pos < (uint32_t)(TGS_RENDER_CHUNKS * TGS_RENDER_CHUNK_LEN))
+        state[((int64_t)slot * (TGS_RENDER_CHUNKS - 1) + pos / TGS_RENDER_CHUNK_LEN - 1) * kBlock + tid] =
+            make_float4(T, c0, c1, c2);
       float al[kUnroll], pw[kUnroll], cr[kUnroll], cg[kUnroll], cb[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -242,18 +254,24 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
                                                             const float4* __restrict__ out,
                                                             const uint32_t* __restrict__ ncontrib,
                                                             const float4* __restrict__ dL,
-                                                            float* __restrict__ g2d) {
+                                                            float* __restrict__ g2d,
+                                                            const float4* __restrict__ state) {
   __shared__ float4 s_geo[kBlock];
   __shared__ float4 s_app[kBlock];
   __shared__ float4 s_con[kBlock];  // conic a, b, c (natural units), blue
   __shared__ uint32_t s_gid[kBlock];
-  const int slot = blockIdx.x, tid = threadIdx.x;
+  const int slot = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
   const int tile = kDense ? slot : a.valid_tiles[slot];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const uint2 range = a.ranges[tile];
+  // list positions [begin, end) of this chunk (one chunk without a state record)
+  const uint32_t begin = range.x + (uint32_t)(chunk * TGS_RENDER_CHUNK_LEN);
+  if (begin >= range.y && chunk > 0) return;  // workgroup-uniform
+  const uint32_t end =
+      chunk + 1 == (int)gridDim.y ? range.y : min(range.y, begin + (uint32_t)TGS_RENDER_CHUNK_LEN);
   const PixelSlot px = pixel_of<kBlock, kDense>(a, slot, tile, tid);
   const float lx = (float)(px.loc & 15), ly = (float)(px.loc >> 4);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
-  const uint2 range = a.ranges[tile];
   const float amin = a.alpha_min, amax = a.alpha_max;
 
   float Cout0 = 0.f, Cout1 = 0.f, Cout2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
@@ -265,26 +283,33 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
     g0 = d.x; g1 = d.y; g2 = d.z;
     last = ncontrib[px.out];
   }
-  bool done = last == 0;
+  bool done = last <= begin - range.x;  // nothing composited from this chunk on
   float T = 1.f, acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+  if (chunk > 0 && !done) {
+    const float4 st = state[((int64_t)slot * (TGS_RENDER_CHUNKS - 1) + chunk - 1) * kBlock + tid];
+    T = st.x;
+    acc0 = st.y;
+    acc1 = st.z;
+    acc2 = st.w;
+  }
 
   Staged nxt = {};
   uint32_t g_after = 0;
-  if (range.x + tid < range.y) nxt = stage_load(a, a.vals[range.x + tid], x0, y0);
-  if (range.x + kBlock + tid < range.y) g_after = a.vals[range.x + kBlock + tid];
+  if (begin + tid < end) nxt = stage_load(a, a.vals[begin + tid], x0, y0);
+  if (begin + kBlock + tid < end) g_after = a.vals[begin + kBlock + tid];
 
-  for (uint32_t start = range.x; start < range.y; start += kBlock) {
+  for (uint32_t start = begin; start < end; start += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
-    const bool live = start + tid < range.y;
+    const bool live = start + tid < end;
     s_geo[tid] = live ? nxt.geo : make_float4(0.f, 0.f, 0.f, 0.f);
     s_app[tid] = live ? nxt.app : make_float4(0.f, 0.f, 0.f, 0.f);
     s_con[tid] = live ? nxt.con : make_float4(0.f, 0.f, 0.f, 0.f);
     s_gid[tid] = nxt.gid;
     __syncthreads();
     const uint32_t i1 = start + kBlock + tid, i2 = start + 2 * kBlock + tid;
-    if (i1 < range.y) nxt = stage_load(a, g_after, x0, y0);
-    if (i2 < range.y) g_after = a.vals[i2];
-    const int cnt = (int)min((uint32_t)kBlock, range.y - start);
+    if (i1 < end) nxt = stage_load(a, g_after, x0, y0);
+    if (i2 < end) g_after = a.vals[i2];
+    const int cnt = (int)min((uint32_t)kBlock, end - start);
     const uint32_t pos0 = start - range.x;
     for (int j = 0; j < cnt; j += kUnrollB) {
       if (__ballot(!done) == 0ull) break;  // the whole wave has finished
@@ -340,16 +365,23 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
 
 template <int kBlock, bool kDense>
 static void launch_fwd(const RasterArgs& a, int grid, float* out, uint32_t* ncontrib,
-                       uint64_t* counters, hipStream_t s) {
+                       uint64_t* counters, float* state, hipStream_t s) {
   hipLaunchKernelGGL((render_fwd_kernel<kBlock, kDense>), dim3(grid), dim3(kBlock), 0, s, a,
-                     (float4*)out, ncontrib, (unsigned long long*)counters);
+                     (float4*)out, ncontrib, (unsigned long long*)counters, (float4*)state);
 }
 
 template <int kBlock, bool kDense>
 static void launch_bwd(const RasterArgs& a, int grid, const float* out, const uint32_t* ncontrib,
-                       const float* dL, float* g2d, hipStream_t s) {
-  hipLaunchKernelGGL((render_bwd_kernel<kBlock, kDense>), dim3(grid), dim3(kBlock), 0, s, a,
-                     (const float4*)out, ncontrib, (const float4*)dL, g2d);
+                       const float* dL, float* g2d, const float* state, hipStream_t s) {
+  const unsigned chunks = state != nullptr ? TGS_RENDER_CHUNKS : 1;
+  hipLaunchKernelGGL((render_bwd_kernel<kBlock, kDense>), dim3(grid, chunks), dim3(kBlock), 0, s, a,
+                     (const float4*)out, ncontrib, (const float4*)dL, g2d, (const float4*)state);
+}
+
+// Workgroup size of the raster kernels for a launch.
+static int raster_block(bool dense, int32_t max_per_tile) {
+  if (dense || max_per_tile > 128) return 256;
+  return max_per_tile <= 64 ? 64 : 128;
 }
 
 static int32_t make_args(const float* splat, const uint32_t* vals, const uint32_t* ranges,
@@ -393,25 +425,31 @@ static int32_t make_args(const float* splat, const uint32_t* vals, const uint32_
 
 using namespace tgs;
 
+extern "C" size_t tgs_render_state_size(int32_t n_slots, int32_t max_per_tile) {
+  if (n_slots < 0 || max_per_tile < 0 || max_per_tile > kTilePixels) return 0;
+  return (size_t)n_slots * (TGS_RENDER_CHUNKS - 1) * (size_t)raster_block(false, max_per_tile) * sizeof(float4);
+}
+
 extern "C" int32_t tgs_render_fwd(const float* splat, const uint32_t* vals, const uint32_t* ranges,
                                   int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
                                   const int32_t* valid_tiles, const int32_t* tile_off,
                                   const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
                                   const tgs_raster_params* rp, float* out, uint32_t* ncontrib,
-                                  uint64_t* counters, void* stream) {
+                                  uint64_t* counters, float* state, void* stream) {
   RasterArgs a;
   if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
                             tile_off, pix, n_st, max_per_tile, rp, "tgs_render_fwd", a))
     return e;
   TGS_REQUIRE(out && ncontrib, "tgs_render_fwd: null output");
-  TGS_REQUIRE(((uintptr_t)out & 15) == 0, "tgs_render_fwd: out must be 16-byte aligned");
+  TGS_REQUIRE(((uintptr_t)out & 15) == 0 && ((uintptr_t)state & 15) == 0,
+              "tgs_render_fwd: out and state must be 16-byte aligned");
   hipStream_t s = as_stream(stream);
   if (valid_tiles == nullptr) {
-    launch_fwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, counters, s);
+    launch_fwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, counters, state, s);
   } else if (n_st > 0) {
-    if (max_per_tile <= 64) launch_fwd<64, false>(a, n_st, out, ncontrib, counters, s);
-    else if (max_per_tile <= 128) launch_fwd<128, false>(a, n_st, out, ncontrib, counters, s);
-    else launch_fwd<256, false>(a, n_st, out, ncontrib, counters, s);
+    if (max_per_tile <= 64) launch_fwd<64, false>(a, n_st, out, ncontrib, counters, state, s);
+    else if (max_per_tile <= 128) launch_fwd<128, false>(a, n_st, out, ncontrib, counters, state, s);
+    else launch_fwd<256, false>(a, n_st, out, ncontrib, counters, state, s);
   }
   return hip_status("tgs_render_fwd");
 }
@@ -422,21 +460,21 @@ extern "C" int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, cons
                                   const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
                                   const tgs_raster_params* rp, const float* out,
                                   const uint32_t* ncontrib, const float* dL_dout, float* g2d,
-                                  void* stream) {
+                                  const float* state, void* stream) {
   RasterArgs a;
   if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
                             tile_off, pix, n_st, max_per_tile, rp, "tgs_render_bwd", a))
     return e;
   TGS_REQUIRE(out && ncontrib && dL_dout && g2d, "tgs_render_bwd: null pointer");
-  TGS_REQUIRE(((uintptr_t)out & 15) == 0 && ((uintptr_t)dL_dout & 15) == 0,
-              "tgs_render_bwd: out and dL_dout must be 16-byte aligned");
+  TGS_REQUIRE(((uintptr_t)out & 15) == 0 && ((uintptr_t)dL_dout & 15) == 0 && ((uintptr_t)state & 15) == 0,
+              "tgs_render_bwd: out, dL_dout and state must be 16-byte aligned");
   hipStream_t s = as_stream(stream);
   if (valid_tiles == nullptr) {
-    launch_bwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, dL_dout, g2d, s);
+    launch_bwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, dL_dout, g2d, state, s);
   } else if (n_st > 0) {
-    if (max_per_tile <= 64) launch_bwd<64, false>(a, n_st, out, ncontrib, dL_dout, g2d, s);
-    else if (max_per_tile <= 128) launch_bwd<128, false>(a, n_st, out, ncontrib, dL_dout, g2d, s);
-    else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, s);
+    if (max_per_tile <= 64) launch_bwd<64, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s);
+    else if (max_per_tile <= 128) launch_bwd<128, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s);
+    else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s);
   }
   return hip_status("tgs_render_bwd");
 }

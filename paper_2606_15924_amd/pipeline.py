@@ -81,6 +81,9 @@ class ViewBuffers:
         self.lam = torch.empty(max(self.n_st, 1), dtype=torch.float32, device=dev)
         self.tile_loss = torch.zeros((max(self.n_st, 1), 2), dtype=torch.float32, device=dev)
         self.g2d = torch.empty((n, B.G2D_FLOATS), dtype=torch.float32, device=dev)
+        # per-pixel (T, colour) at the backward's chunk starts, kept by the forward
+        n_state = B.tgs_render_state_size(self.n_st, self.n_pix) // 4
+        self.state = torch.empty(max(n_state, 4), dtype=torch.float32, device=dev)
         self._alloc_pairs(capacity if capacity is not None else max(1 << 16, 8 * n))
 
     def _alloc_pairs(self, capacity: int):
@@ -120,7 +123,7 @@ class ViewBuffers:
     def render_fwd(self, rp, counters=None):
         B.tgs_render_fwd(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                          self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
-                         rp, self.out, self.ncontrib, counters)
+                         rp, self.out, self.ncontrib, counters, self.state)
 
     def loss(self, gt, totals, lp):
         B.tgs_loss(self.out, gt, self.height, self.width, self.valid_tiles, self.tile_off, self.pix,
@@ -135,7 +138,7 @@ class ViewBuffers:
             self.g2d.zero_()
         B.tgs_render_bwd(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                          self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
-                         rp, self.out, self.ncontrib, self.dL, self.g2d)
+                         rp, self.out, self.ncontrib, self.dL, self.g2d, self.state)
 
     def project_bwd(self, params, cam: B.tgs_camera, rp, grad, accumulate=True):
         B.tgs_project_bwd(params, self.n, cam, rp, self.radius, self.clamp, self.g2d, grad, accumulate)

@@ -36,7 +36,7 @@ def test_header_symbols_exported(B):
 
 
 def test_version_and_counts(B):
-    assert B.tgs_version() == 3
+    assert B.tgs_version() == 4
     for r in (1, 100, 150, 200, 250, 500, 1000):
         assert B.tgs_pixels_per_tile(r) == pixels_per_tile(r)
     sp = B.sample_params(64, n_tiles_sel=64)
@@ -79,7 +79,7 @@ def test_invalid_arguments_are_rejected_before_any_launch(B):
     # tile grid inconsistent with the image
     st = lib.tgs_render_fwd(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 3, 3, 64, 48,
                             None, None, None, 0, 0, ctypes.byref(rp), ctypes.c_void_p(16),
-                            ctypes.c_void_p(16), None, None)
+                            ctypes.c_void_p(16), None, None, None)
     assert st == B.TGS_ERR_INVALID and "tile grid" in lib.tgs_last_error().decode()
     # sampler: n_pix out of range, then too-small workspace
     sp = B.sample_params(300)
@@ -100,7 +100,7 @@ def test_invalid_arguments_are_rejected_before_any_launch(B):
     # misaligned splat record
     st = lib.tgs_render_fwd(ctypes.c_void_p(20), ctypes.c_void_p(16), ctypes.c_void_p(16), 4, 3, 64, 48,
                             None, None, None, 0, 0, ctypes.byref(rp), ctypes.c_void_p(16),
-                            ctypes.c_void_p(16), None, None)
+                            ctypes.c_void_p(16), None, None, None)
     assert st == B.TGS_ERR_INVALID and "aligned" in lib.tgs_last_error().decode()
 
 

@@ -320,6 +320,47 @@ def test_render_bwd_parity(B, case):
         assert_close(got[f], g2d[f], 1e-4, 2e-6 * g2d_abs[f] + 1e-12, names[f])
 
 
+@pytest.mark.parametrize("mode", ["sparse64", "sparse128", "dense"])
+def test_render_bwd_chunked_equals_single(B, mode):
+    """Deep lists (half the pixels composite more than 192 Gaussians): the
+    forward's state record does not change its outputs, and the backward
+    split into (tile, chunk) workgroups starting from that record gives the
+    gradients of the single-workgroup replay (same per-pixel arithmetic;
+    only the order of the float atomics differs)."""
+    p, cam = small_scene(n=4000, seed=12)
+    p = np.array(p)
+    p[10] = -3.5                              # opacity logit: ~3% per Gaussian
+    pr = project.project(p, cam, RP)
+    rec = splat_record(pr)
+    _, sv, ranges = binning.bin_and_sort(pr)
+    if mode == "dense":
+        s, n_pix = None, 256
+    else:
+        n_pix = 64 if mode == "sparse64" else 128
+        E = synth.error_map(cam.height, cam.width, 61)
+        A = synth.age_map(cam.height, cam.width, 62)
+        s = sampler.sample_view(E, A, SampleParams(n_pix=n_pix), 3, 1, 0)
+    out, nc, _, (splat, V, R, vt, off, pix, n_st, mpt, TX, TY) = _gpu_render(
+        B, rec, sv, ranges, cam, s, B.raster_params(), n_pix)
+    state = torch.zeros(B.tgs_render_state_size(n_st, mpt) // 4, dtype=torch.float32, device="cuda")
+    out2 = torch.empty_like(out)
+    nc2 = torch.empty_like(nc)
+    B.tgs_render_fwd(splat, V, R, TX, TY, cam.width, cam.height, vt, off, pix, n_st, mpt, B.raster_params(),
+                     out2, nc2, None, state)
+    assert np.array_equal(host(out).view(np.uint32), host(out2).view(np.uint32))
+    assert np.array_equal(host(nc), host(nc2))
+    assert (host(nc) > 3 * B.RENDER_CHUNK_LEN).mean() > 0.2   # the last chunk has work
+    dl = torch.from_numpy(np.random.default_rng(5).normal(size=out.shape).astype(np.float32) * 1e-3).cuda()
+    G1 = torch.zeros((p.shape[1], 9), dtype=torch.float32, device="cuda")
+    G2 = torch.zeros_like(G1)
+    args = (splat, V, R, TX, TY, cam.width, cam.height, vt, off, pix, n_st, mpt, B.raster_params(), out, nc, dl)
+    B.tgs_render_bwd(*args, G1)
+    B.tgs_render_bwd(*args, G2, state)
+    g1, g2 = host(G1), host(G2)
+    scale = np.abs(g1).max(axis=0) + 1e-12
+    assert_close(g2, g1, 1e-5, 1e-6 * scale, "chunked vs single")
+
+
 # ------------------------------------------------------------------ loss, maps
 @pytest.mark.parametrize("case", ["c1", "ragged25", "dense"])
 def test_loss_parity(B, case):
