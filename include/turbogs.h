@@ -53,8 +53,8 @@ extern "C" {
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
 #define TGS_PARAM_ROWS 59
 #define TGS_COUNTER_SLOTS 64 /* slots per counter of tgs_render_fwd */
-#define TGS_RENDER_CHUNKS 4     /* backward workgroups per tile when the forward keeps state */
-#define TGS_RENDER_CHUNK_LEN 64 /* list positions per backward chunk (the last takes the rest) */
+#define TGS_RENDER_CHUNKS 8     /* backward workgroups per tile when the forward keeps state */
+#define TGS_RENDER_CHUNK_LEN 32 /* list positions per backward chunk (the last takes the rest) */
 
 enum {
   TGS_OK = 0,

@@ -23,8 +23,8 @@ G2D_FLOATS = 9
 PARAM_ROWS = 59
 TILE = 16
 COUNTER_SLOTS = 64
-RENDER_CHUNKS = 4
-RENDER_CHUNK_LEN = 64
+RENDER_CHUNKS = 8
+RENDER_CHUNK_LEN = 32
 
 
 class tgs_camera(ctypes.Structure):

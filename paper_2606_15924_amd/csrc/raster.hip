@@ -12,12 +12,13 @@
 // accumulated colour from the forward outputs (final colour and the number
 // of contributors), so nothing per Gaussian or per (pixel, Gaussian) is
 // stored.  Optionally the forward records each pixel's (T, accumulated
-// colour) at list positions 64, 128 and 192; the backward then runs one
-// workgroup per (tile, chunk of 64 positions, the last chunk taking the
-// rest) that starts from the recorded state.  The replay performs the same
-// operations in the same order, so every per-lane value equals the
-// unchunked one; at 64 samples per tile this turns one wave per tile into
-// up to four, which the SIMDs need to hide latency.  Per Gaussian, each lane's contribution to the nine screen-space
+// colour) every TGS_RENDER_CHUNK_LEN list positions; the backward then runs
+// one workgroup per (tile, chunk of TGS_RENDER_CHUNK_LEN positions, the last
+// of TGS_RENDER_CHUNKS chunks taking the rest) that starts from the
+// recorded state.  The replay performs the same operations in the same
+// order, so every per-lane value equals the unchunked one; at 64 samples
+// per tile this turns one wave per tile into several, which the SIMDs need
+// to hide latency.  Per Gaussian, each lane's contribution to the nine screen-space
 // gradients is summed across the wave (lane-half swaps, then DPP within rows
 // of 16), and nine lanes of the wave issue one float atomic each.
 //

@@ -349,7 +349,7 @@ def test_render_bwd_chunked_equals_single(B, mode):
                      out2, nc2, None, state)
     assert np.array_equal(host(out).view(np.uint32), host(out2).view(np.uint32))
     assert np.array_equal(host(nc), host(nc2))
-    assert (host(nc) > 3 * B.RENDER_CHUNK_LEN).mean() > 0.2   # the last chunk has work
+    assert (host(nc) > (B.RENDER_CHUNKS - 1) * B.RENDER_CHUNK_LEN).mean() > 0.1   # the last chunk has work
     dl = torch.from_numpy(np.random.default_rng(5).normal(size=out.shape).astype(np.float32) * 1e-3).cuda()
     G1 = torch.zeros((p.shape[1], 9), dtype=torch.float32, device="cuda")
     G2 = torch.zeros_like(G1)
