@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) sh_rest_kernel(
   auto adam_row = [&](int row, double val) {
     const int64_t idx = (int64_t)row * n + i;
     float pp = params[idx], mm = m[idx], vv = v[idx];
-    adam_elem(pp, stored_grad(grad_prev, idx, val), mm, vv, row_lr(o, row), o);
+    adam_elem(pp, stored_grad(grad_prev, idx, val), mm, vv, row_lr_bc1(o, row), o);
     params[idx] = pp;
     m[idx] = mm;
     v[idx] = vv;
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(256) geom_lm_kernel(
       return;
     }
     float pp = params[idx], mm = m[idx], vv = v[idx];
-    adam_elem(pp, gf, mm, vv, row_lr(o, row), o);
+    adam_elem(pp, gf, mm, vv, row_lr_bc1(o, row), o);
     params[idx] = pp;
     m[idx] = mm;
     v[idx] = vv;

@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const 
   const int row = row0 + (int)blockIdx.y;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= n) return;
-  const double lr = row_lr(o, row);
+  const double lr = row_lr_bc1(o, row);
   const int64_t base = (int64_t)row * n + i0;
   if (kVec) {
     bool t[4] = {true, true, true, true};

@@ -15,6 +15,7 @@ struct OptArgs {
   double lr[6];  // mean, scale, quat, opacity, sh dc, sh rest
   double beta1, beta2, eps_adam, eps_lm;
   double bc1, bc2;  // 1 - beta^t
+  double inv_sqrt_bc2;  // 1 / sqrt(bc2)
   int lm_mode;
 };
 
@@ -33,16 +34,22 @@ constexpr int kGeomRows[10] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9};
 constexpr int kAppRows[4] = {11, 12, 13, 10};
 
 // Adam step of one entry with gradient g (p, m, v updated in place).
-__device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v, double lr, const OptArgs& o) {
+// Adam with bias correction, lr mh / (sqrt(vh) + eps), mh = m / bc1,
+// vh = v / bc2, evaluated as (lr / bc1) m / (sqrt(v) / sqrt(bc2) + eps):
+// the same value in exact arithmetic with one division and one square root
+// per element (lr_bc1 = lr / bc1 is per row group).
+__device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v, double lr_bc1, const OptArgs& o) {
 #pragma clang fp contract(off)
   const double gd = g;
   const double mm = o.beta1 * (double)m + (1.0 - o.beta1) * gd;
   const double vv = o.beta2 * (double)v + (1.0 - o.beta2) * gd * gd;
   m = (float)mm;
   v = (float)vv;
-  const double mh = mm / o.bc1, vh = vv / o.bc2;
-  p = (float)((double)p - lr * mh / (sqrt(vh) + o.eps_adam));
+  p = (float)((double)p - (lr_bc1 * mm) / (sqrt(vv) * o.inv_sqrt_bc2 + o.eps_adam));
 }
+
+// Learning rate of a row divided by the first-moment bias correction.
+__host__ __device__ inline double row_lr_bc1(const OptArgs& o, int row) { return row_lr(o, row) / o.bc1; }
 
 // LM step of one block of K rows of Gaussian i with block gradient gf.
 // Solves (g g^T + diag(d)) x = -m (mode 0) or diag(g^2 + d) x = -m (mode 1)
@@ -109,6 +116,7 @@ inline int32_t make_opt_args(const tgs_optim_params* op, int64_t step, const cha
   o.eps_lm = op->eps_lm;
   o.bc1 = 1.0 - pow(op->beta1, (double)step);
   o.bc2 = 1.0 - pow(op->beta2, (double)step);
+  o.inv_sqrt_bc2 = 1.0 / sqrt(o.bc2);
   o.lm_mode = op->lm_mode;
   return TGS_OK;
 }

@@ -48,7 +48,7 @@ struct RasterArgs {
 // Staged conic: (A, B, C) = (-a/2, -b, -c/2) * log2(e), so that
 // p2 = A dx^2 + B dx dy + C dy^2 = log2(e) * power and G = exp(power) = 2^p2.
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr int kUnroll = 4;   // forward: alphas evaluated per group
+constexpr int kUnroll = 8;   // forward: alphas evaluated per group
 constexpr int kUnrollB = 2;  // backward
 
 __device__ __forceinline__ float splat_exponent(float dx, float dy, float A, float Bq, float C) {
