@@ -290,15 +290,17 @@ __device__ __forceinline__ uint64_t lanes_below() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Lanes of the wave holding the same kBits-bit digit (inactive lanes excluded).
-template <int kBits>
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
-  uint64_t peers = __ballot(valid);
-#pragma unroll
-  for (int b = 0; b < kBits; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bal = __ballot(bit);
-    peers &= bit ? bal : ~bal;
+// Lanes of the wave holding the same digit (inactive lanes excluded), found
+// through LDS: each active lane clears its digit's mask word, ORs in its own
+// lane bit and reads the word back.  The three LDS operations of one wave
+// execute in order, so every read sees exactly the bits of the lanes that
+// share the digit.  s_mask holds one word per digit, private to the wave.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, uint64_t* s_mask) {
+  uint64_t peers = 0ull;
+  if (valid) {
+    s_mask[d] = 0ull;
+    __hip_atomic_fetch_or(&s_mask[d], 1ull << lane_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    peers = __hip_atomic_load(&s_mask[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   return peers;
 }
@@ -370,6 +372,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
   __shared__ K s_keys[kBlockKeys];
   __shared__ uint32_t s_vals[kVals ? kBlockKeys : 1];
   __shared__ uint32_t s_red[kSortWaves];
+  __shared__ uint64_t s_mask[kSortWaves][kDigits];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (int i = tid; i < kSortWaves * kDigits; i += kSortThreads) (&s_cnt[0][0])[i] = 0;
   const int64_t blk0 = (int64_t)blockIdx.x * kBlockKeys;
@@ -391,7 +394,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
   for (int k = 0; k < kItems; ++k) {
     const bool valid = wbase + k * kWave + lane < n;
     const uint32_t d = (uint32_t)(key[k] >> shift) & (kDigits - 1u);
-    const uint64_t peers = digit_peers<kBits>(d, valid);
+    const uint64_t peers = digit_peers(d, valid, s_mask[wave]);
     const uint32_t r = (uint32_t)__popcll(peers & below);
     const uint32_t before = valid ? s_cnt[wave][d] : 0u;
     rank[k] = before + r;
@@ -420,8 +423,10 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     if (wbase + k * kWave + lane < n) {
       const uint32_t d = (uint32_t)(key[k] >> shift) & (kDigits - 1u);
       const uint32_t lp = s_cnt[wave][d] + rank[k];
-      s_keys[lp] = key[k];
-      if (kVals) s_vals[lp] = val[k];
+      if (lp < (uint32_t)kBlockKeys) {  // always (ranks are a permutation); a safeguard
+        s_keys[lp] = key[k];
+        if (kVals) s_vals[lp] = val[k];
+      }
     }
   }
   __syncthreads();
@@ -433,6 +438,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     if (lp < count) {
       const K kk = s_keys[lp];
       const uint32_t dst = s_gbase[(uint32_t)(kk >> shift) & (kDigits - 1u)] + (uint32_t)lp;
+      if (dst >= n) continue;  // never taken for a consistent table; keeps every write in bounds
       ((K*)o.keys)[dst] = kk;
       if (kFinal) {
         const uint32_t g = (uint32_t)(kk & (((K)1 << o.id_bits) - 1));
@@ -482,6 +488,7 @@ __global__ void __launch_bounds__(kSortThreads) depth_pass_kernel(const uint32_t
   __shared__ uint32_t s_keys[kBlockKeys];
   __shared__ uint32_t s_vals[kBlockKeys];
   __shared__ uint32_t s_red[kSortWaves];
+  __shared__ uint64_t s_mask[kSortWaves][kDigits];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (int i = tid; i < kSortWaves * kDigits; i += kSortThreads) (&s_cnt[0][0])[i] = 0;
   // counts of digit tid in the earlier blocks and in all blocks (rows padded to 4 with zeros)
@@ -520,7 +527,7 @@ __global__ void __launch_bounds__(kSortThreads) depth_pass_kernel(const uint32_t
   for (int k = 0; k < kItems; ++k) {
     const bool valid = wbase + k * kWave + lane < n;
     const uint32_t d = (key[k] >> shift) & (kDigits - 1u);
-    const uint64_t peers = digit_peers<8>(d, valid);
+    const uint64_t peers = digit_peers(d, valid, s_mask[wave]);
     const uint32_t r = (uint32_t)__popcll(peers & below);
     const uint32_t prior = valid ? s_cnt[wave][d] : 0u;
     rank[k] = prior + r;
@@ -544,8 +551,10 @@ __global__ void __launch_bounds__(kSortThreads) depth_pass_kernel(const uint32_t
     if (wbase + k * kWave + lane < n) {
       const uint32_t d = (key[k] >> shift) & (kDigits - 1u);
       const uint32_t lp = s_cnt[wave][d] + rank[k];
-      s_keys[lp] = key[k];
-      s_vals[lp] = val[k];
+      if (lp < (uint32_t)kBlockKeys) {  // always (ranks are a permutation); a safeguard
+        s_keys[lp] = key[k];
+        s_vals[lp] = val[k];
+      }
     }
   }
   __syncthreads();
@@ -556,6 +565,7 @@ __global__ void __launch_bounds__(kSortThreads) depth_pass_kernel(const uint32_t
     if (lp < count) {
       const uint32_t kk = s_keys[lp], g = s_vals[lp];
       const uint32_t dst = s_gbase[(kk >> shift) & (kDigits - 1u)] + (uint32_t)lp;
+      if (dst >= n || g >= n) continue;  // never taken for a consistent table; keeps every access in bounds
       if (kLast) {
         o.ids_sorted[dst] = g;
         o.rect_sorted[dst] = clamp_rect(o.rect[g], o.tiles_x, o.tiles_y);
