@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 4u
+#define TGS_ABI_VERSION 5u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
@@ -129,11 +129,15 @@ int32_t tgs_sample_tile_count(int32_t height, int32_t width, const tgs_sample_pa
  *   radius   [n] int32 (0 = culled)
  *   rect     [n][4] int32 tile rectangle xmin, ymin, xmax, ymax (exclusive)
  *   clamp    [n] uint8, bit c set when colour channel c was clamped at 0
+ *   g2d_clear  nullable [n][9] float, set to zero (the screen-space gradient
+ *            accumulator that tgs_render_bwd adds to, cleared in the same
+ *            pass over the Gaussians)
  * The projection is computed in FP64; depth bits, centre and rectangle
  * follow a fixed operation order. */
 int32_t tgs_project(const float* params, int64_t n, const tgs_camera* cam,
                     const tgs_raster_params* rp, float* splat, float* depth,
-                    int32_t* radius, int32_t* rect, uint8_t* clamp, void* stream);
+                    int32_t* radius, int32_t* rect, uint8_t* clamp, float* g2d_clear,
+                    void* stream);
 
 /* Tile-wise error/age pixel sampling (Sec. 3.5, Eq. pix_prob_err and
  * Eq. pix_topk_age, plus the mixed remainder of the hyper-parameter table).

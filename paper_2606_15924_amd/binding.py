@@ -75,7 +75,7 @@ PROTOTYPES = {
     "tgs_pixels_per_tile": (_I32, [_I32]),
     "tgs_sample_tile_count": (_I32, [_I32, _I32, ctypes.POINTER(tgs_sample_params)]),
     "tgs_project": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
-                           _P, _P, _P, _P, _P, _P]),
+                           _P, _P, _P, _P, _P, _P, _P]),
     "tgs_sample_workspace_size": (_SZ, [_I32, _I32]),
     "tgs_sample": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(tgs_sample_params), _P, _P, _P, _P, _P,
                           _P, _SZ, _P]),
@@ -202,9 +202,10 @@ def tgs_sample_tile_count(height: int, width: int, sp: tgs_sample_params) -> int
     return int(lib().tgs_sample_tile_count(height, width, ctypes.byref(sp)))
 
 
-def tgs_project(params, n, cam: tgs_camera, rp: tgs_raster_params, splat, depth, radius, rect, clamp):
+def tgs_project(params, n, cam: tgs_camera, rp: tgs_raster_params, splat, depth, radius, rect, clamp,
+                g2d_clear=None):
     _check(lib().tgs_project(_ptr(params), n, ctypes.byref(cam), ctypes.byref(rp), _ptr(splat), _ptr(depth),
-                             _ptr(radius), _ptr(rect), _ptr(clamp), _stream()), "tgs_project")
+                             _ptr(radius), _ptr(rect), _ptr(clamp), _ptr(g2d_clear), _stream()), "tgs_project")
 
 
 def tgs_sample_workspace_size(height: int, width: int) -> int:

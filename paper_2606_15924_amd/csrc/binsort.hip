@@ -257,25 +257,41 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(
 }
 
 // ------------------------------------------------------------------ ranges
-// One thread per sorted pair: a tile boundary writes the start of the new
-// tile and the end of the previous one, the last pair the end of its tile.
-// Sentinel keys (tiles outside the valid set) sit after every real tile and
-// write nothing; empty tiles keep the [0, 0) of the fill.
+// A workgroup takes 256 x kRangeItems consecutive sorted pairs: their tile
+// ids are loaded coalesced into LDS (with the one before the block), then
+// each position is compared with its predecessor.  A tile boundary writes
+// the start of the new tile and the end of the previous one, the last pair
+// the end of its tile.  Sentinel keys (tiles outside the valid set) sit
+// after every real tile and write nothing; empty tiles keep the [0, 0) of
+// the fill.
+constexpr int kRangeItems = 8;
+constexpr int kRangeBlock = 256 * kRangeItems;
+
 template <typename K>
 __global__ void __launch_bounds__(256) ranges_kernel(const K* __restrict__ keys, uint32_t total, int id_bits,
                                                      uint32_t n_t, uint2* __restrict__ ranges) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const uint32_t t = (uint32_t)(keys[i] >> id_bits);
-  if (i == total - 1 && t < n_t) ranges[t].y = total;
-  if (i == 0) {
-    if (t < n_t) ranges[t].x = 0;
-    return;
+  __shared__ uint32_t s_t[kRangeBlock + 1];  // s_t[0]: the pair before the block
+  const uint32_t b0 = blockIdx.x * (uint32_t)kRangeBlock;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kRangeItems; ++k) {
+    const uint32_t i = b0 + (uint32_t)(k * 256 + tid);
+    s_t[1 + k * 256 + tid] = i < total ? (uint32_t)(keys[i] >> id_bits) : 0xffffffffu;
   }
-  const uint32_t tp = (uint32_t)(keys[i - 1] >> id_bits);
-  if (t == tp) return;
-  if (t < n_t) ranges[t].x = i;
-  if (tp < n_t) ranges[tp].y = i;
+  if (tid == 0) s_t[0] = b0 > 0 ? (uint32_t)(keys[b0 - 1] >> id_bits) : 0xffffffffu;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRangeItems; ++k) {
+    const int l = k * 256 + tid;
+    const uint32_t i = b0 + (uint32_t)l;
+    if (i >= total) break;
+    const uint32_t t = s_t[1 + l], tp = s_t[l];
+    if (i == 0 || t != tp) {
+      if (t < n_t) ranges[t].x = i;
+      if (i > 0 && tp < n_t) ranges[tp].y = i;
+    }
+    if (i == total - 1 && t < n_t) ranges[t].y = total;
+  }
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -813,8 +829,8 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
     cur ^= 1;
     shift += b;
   }
-  hipLaunchKernelGGL((ranges_kernel<K>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, kb[cur], total,
-                     id_bits, n_t, (uint2*)ranges);
+  hipLaunchKernelGGL((ranges_kernel<K>), dim3((unsigned)ceil_div(total, kRangeBlock)), dim3(256), 0, s,
+                     kb[cur], total, id_bits, n_t, (uint2*)ranges);
 }
 
 }  // namespace tgs

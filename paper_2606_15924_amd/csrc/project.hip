@@ -17,9 +17,11 @@ namespace tgs {
 __global__ void __launch_bounds__(256) project_fwd_kernel(
     const float* __restrict__ params, int64_t n, CamArgs cam, int sh_degree, double z_near,
     double dil, float4* __restrict__ splat, float* __restrict__ depth, int* __restrict__ radius,
-    int4* __restrict__ rect, uint8_t* __restrict__ clampm) {
+    int4* __restrict__ rect, uint8_t* __restrict__ clampm, float* __restrict__ g2d_clear) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (g2d_clear != nullptr)
+    for (int k = 0; k < 9; ++k) g2d_clear[i * 9 + k] = 0.f;
   Geom g;
   geometry(params, n, i, cam, z_near, dil, g);
   depth[i] = (float)g.t[2];
@@ -94,7 +96,8 @@ using namespace tgs;
 
 extern "C" int32_t tgs_project(const float* params, int64_t n, const tgs_camera* cam,
                                const tgs_raster_params* rp, float* splat, float* depth,
-                               int32_t* radius, int32_t* rect, uint8_t* clamp, void* stream) {
+                               int32_t* radius, int32_t* rect, uint8_t* clamp, float* g2d_clear,
+                               void* stream) {
   TGS_REQUIRE(n >= 0, "tgs_project: n < 0");
   TGS_REQUIRE(cam != nullptr && cam->width > 0 && cam->height > 0, "tgs_project: bad camera");
   if (int32_t e = check_raster_params(rp)) return e;
@@ -106,7 +109,7 @@ extern "C" int32_t tgs_project(const float* params, int64_t n, const tgs_camera*
   const int block = 256;
   hipLaunchKernelGGL(project_fwd_kernel, dim3((unsigned)ceil_div(n, block)), dim3(block), 0,
                      as_stream(stream), params, n, ca, rp->sh_degree, (double)rp->z_near,
-                     (double)rp->dilation, (float4*)splat, depth, radius, (int4*)rect, clamp);
+                     (double)rp->dilation, (float4*)splat, depth, radius, (int4*)rect, clamp, g2d_clear);
   return hip_status("tgs_project");
 }
 

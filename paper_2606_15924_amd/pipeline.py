@@ -102,7 +102,9 @@ class ViewBuffers:
                      self.tile_slot, totals, self.sample_ws)
 
     def project(self, params, cam: B.tgs_camera, rp):
-        B.tgs_project(params, self.n, cam, rp, self.splat, self.depth, self.radius, self.rect, self.clamp)
+        # also clears the screen-space gradient that the backward accumulates into
+        B.tgs_project(params, self.n, cam, rp, self.splat, self.depth, self.radius, self.rect, self.clamp,
+                      self.g2d)
 
     def bin_sort_needs_samples(self) -> bool:
         """Binning reads the tile map only when the sampler keeps a subset of tiles."""
@@ -256,10 +258,8 @@ class Trainer:
                 with torch.cuda.stream(side):
                     with st("ema_age"):
                         vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
-            with st("zero_g2d"):
-                vb.g2d.zero_()
             with st("render_bwd"):
-                vb.render_bwd(self.rp, zero=False)
+                vb.render_bwd(self.rp, zero=False)  # g2d was cleared by the projection
             if k + 1 < len(used) or not self.cfg.fuse_optimizer:
                 with st("project_bwd"):
                     # the first view overwrites the gradient, later views add to it

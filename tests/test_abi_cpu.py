@@ -36,7 +36,7 @@ def test_header_symbols_exported(B):
 
 
 def test_version_and_counts(B):
-    assert B.tgs_version() == 4
+    assert B.tgs_version() == 5
     for r in (1, 100, 150, 200, 250, 500, 1000):
         assert B.tgs_pixels_per_tile(r) == pixels_per_tile(r)
     sp = B.sample_params(64, n_tiles_sel=64)
@@ -67,13 +67,13 @@ def test_invalid_arguments_are_rejected_before_any_launch(B):
     rp = B.raster_params()
     # null output pointers
     st = lib.tgs_project(ctypes.c_void_p(16), 10, ctypes.byref(cam), ctypes.byref(rp), None, None, None,
-                         None, None, None)
+                         None, None, None, None)
     assert st == B.TGS_ERR_INVALID
     assert "null" in lib.tgs_last_error().decode()
     # bad SH degree
     rp.sh_degree = 4
     st = lib.tgs_project(ctypes.c_void_p(16), 10, ctypes.byref(cam), ctypes.byref(rp), None, None, None,
-                         None, None, None)
+                         None, None, None, None)
     assert st == B.TGS_ERR_INVALID and "sh_degree" in lib.tgs_last_error().decode()
     rp.sh_degree = 3
     # tile grid inconsistent with the image
@@ -110,7 +110,7 @@ def test_empty_inputs_are_no_ops(B):
     cam.width, cam.height = 64, 48
     rp = B.raster_params()
     assert lib.tgs_project(None, 0, ctypes.byref(cam), ctypes.byref(rp), None, None, None, None, None,
-                           None) == B.TGS_OK
+                           None, None) == B.TGS_OK
     op = B.optim_params()
     assert lib.tgs_optimizer_step(None, None, None, None, 0, None, ctypes.byref(op), 1, None) == B.TGS_OK
 
