@@ -44,6 +44,15 @@ BWD_FLOP_EVAL = 14
 BWD_FLOP_BLEND = 48
 
 
+# Matched-PSNR recovery task on the same scene: 100 cameras on the upper
+# hemisphere (every fifth held out), targets rendered from the perturbed
+# scene plus N(0, 0.01) noise, the model starting from the unperturbed one.
+PSNR_CAMS = 100
+PSNR_DENSE_STEPS = 500
+PSNR_RATES = (500, 250, 200, 100)
+PSNR_EVAL_EVERY = 25
+PSNR_MAX_STEPS = 4000
+
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_scaling_300k_25pct.txt")
 RASTER_SOURCES = ("paper_2606_15924_amd/csrc/raster.hip", "paper_2606_15924_amd/csrc/common.h")
 
@@ -130,6 +139,92 @@ def run(tr, steps, warmup):
                 stage_ms=stage, dominant=dom, dominant_ms=dom_ms, n_pairs=int(vb.n_pairs), pixels=pixels)
 
 
+def matched_psnr(dev, dense_steps=PSNR_DENSE_STEPS, max_steps=PSNR_MAX_STEPS):
+    """Dense training for ``dense_steps`` steps, then each sparse rate until
+    its held-out PSNR reaches the dense run's final PSNR (or ``max_steps``).
+    One random training view per step (seeded order, the same for every
+    run); PSNR over the 20 held-out views every PSNR_EVAL_EVERY steps; only
+    the training steps are clocked."""
+    import torch
+
+    import synth
+    from paper_2606_15924_amd import binding as B
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer, ViewBuffers
+    p0 = synth.gaussians(N_GAUSS, synth.SEED_SCENE)
+    p_true = synth.perturb(p0, synth.SEED_PERTURB)
+    cams = synth.hemisphere_cameras(PSNR_CAMS, width=WIDTH, height=HEIGHT, focal=300.0 * WIDTH / 256)
+    held = [i for i in range(PSNR_CAMS) if i % 5 == 2]
+    train = [i for i in range(PSNR_CAMS) if i % 5 != 2]
+    rp = B.raster_params()
+    vb = ViewBuffers(N_GAUSS, WIDTH, HEIGHT, None, -1, dev)
+
+    def render(params, cam):
+        c = B.camera(cam)
+        vb.project(params, c, rp)
+        vb.bin_sort(alpha_min=rp.alpha_min)
+        vb.render_fwd(rp)
+        return vb.out[: WIDTH * HEIGHT, :3].T.reshape(3, HEIGHT, WIDTH)
+
+    P_true = torch.from_numpy(p_true).to(dev)
+    gts = []
+    for k, i in enumerate(range(PSNR_CAMS)):
+        noise = torch.from_numpy(synth.pixel_noise((3, HEIGHT, WIDTH), synth.SEED_NOISE + k)).to(dev)
+        gts.append((render(P_true, cams[i]) + noise).contiguous())
+    del P_true
+
+    def heldout_psnr(params):
+        mse = 0.0
+        for i in held:
+            d = render(params, cams[i]) - gts[i]
+            mse += float((d * d).mean())
+        return 10.0 * np.log10(len(held) / mse)
+
+    order = np.random.default_rng(synth.SEED_VIEWS).integers(0, len(train), size=max_steps)
+
+    def run(rate, target_psnr, n_max):
+        cfg = StepConfig(rate_permille=rate)
+        E = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in train]
+        A = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in train]
+        tr = Trainer(torch.from_numpy(p0).to(dev), [cams[i] for i in train], [gts[i] for i in train], cfg,
+                     E=E, A=A)
+        if rate is not None:
+            tr.init_error_maps(range(len(train)))
+        curve = [(0, 0.0, heldout_psnr(tr.params))]
+        t_train, step = 0.0, 0
+        while step < n_max:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(PSNR_EVAL_EVERY):
+                tr.step([int(order[step])])
+                step += 1
+            torch.cuda.synchronize()
+            t_train += time.perf_counter() - t0
+            curve.append((step, t_train, heldout_psnr(tr.params)))
+            if target_psnr is not None and curve[-1][2] >= target_psnr:
+                break
+        del tr
+        return curve
+
+    log(f"matched PSNR: dense {dense_steps} steps")
+    dense = run(None, None, dense_steps)
+    target = dense[-1][2]
+    res = {"task": f"recovery of a perturbed {N_GAUSS}-Gaussian scene, {len(train)} training and "
+                   f"{len(held)} held-out {WIDTH}x{HEIGHT} views, one view per step",
+           "psnr_init": round(dense[0][2], 3),
+           "dense": {"steps": dense[-1][0], "train_s": round(dense[-1][1], 4), "psnr": round(target, 3),
+                     "ms_per_step": round(1e3 * dense[-1][1] / dense[-1][0], 4)},
+           "sparse": {}}
+    for r in PSNR_RATES:
+        log(f"matched PSNR: sparse {r / 10:g}%")
+        cv = run(r, target, max_steps)
+        hit = cv[-1][2] >= target
+        res["sparse"][f"{r / 10:g}%"] = {
+            "steps_to_match": cv[-1][0] if hit else None, "train_s": round(cv[-1][1], 4),
+            "psnr": round(cv[-1][2], 3), "ms_per_step": round(1e3 * cv[-1][1] / cv[-1][0], 4),
+            "time_speedup_vs_dense": round(dense[-1][1] / cv[-1][1], 3) if hit else None}
+    return res
+
+
 def cpu_baseline(p, cam, gt, target_s=15.0):
     """The oracle's sparse step, timed on one host thread: the parts whose
     cost scales with the sampled tiles (sampling, forward, loss, backward)
@@ -199,6 +294,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the pixel-rate sweep and dense run")
+    ap.add_argument("--no-psnr", action="store_true", help="skip the matched-PSNR training comparison")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -263,6 +359,10 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(dom), "launch_ms": round(head["dominant_ms"], 4)}
 
+    psnr = None
+    if not args.no_psnr:
+        psnr = matched_psnr(dev)
+
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline")
@@ -293,6 +393,7 @@ def main():
         "sparse_vs_dense_speedup": (dense["ms_per_step"] / head["ms_per_step"]) if dense else None,
         "sweep": sweep or None,
         "roofline": roofline,
+        "matched_psnr": psnr,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
