@@ -228,11 +228,29 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;  // every lane of a row holds the row's sum
 }
 
+// Which of the nine sums a lane holds after the reduction below, and
+// whether it issues that sum's atomic: row r of register R_k (rows of 16
+// lanes) holds one field, lanes 0 and 1 of every row issue r0's and r1's
+// field, lane 2 of row 0 issues field 8.  Fixed per lane, so computed once.
+struct Sum9Lane {
+  int field;   // 0..8, or -1 when the lane issues no atomic
+  int which;   // 0: r0, 1: r1, 2: r2
+};
+
+__device__ __forceinline__ Sum9Lane sum9_lane() {
+  const int lane = lane_id(), k = lane & 15, row = lane >> 4;
+  Sum9Lane s;
+  s.which = k < 3 ? k : 0;
+  s.field = k < 2 ? k * 4 + ((row & 1) << 1) + (row >> 1) : (k == 2 && row == 0 ? 8 : -1);
+  return s;
+}
+
 // Sums each of v[0..8] over the wave and adds the nine sums to dst[0..8]
 // with one atomic instruction.  Halves of the wave are folded pairwise with
 // the lane swaps (64 -> 32 -> 16 lanes per value), then each row of 16 is
 // reduced with DPP; row r of register R_k then holds the sum of one field.
-__device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float* __restrict__ dst) {
+// dst is wave-uniform (a scalar address).
+__device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float* __restrict__ dst, const Sum9Lane& sl) {
   const float p01 = swap_sum32(v[0], v[1]);
   const float p23 = swap_sum32(v[2], v[3]);
   const float p45 = swap_sum32(v[4], v[5]);
@@ -242,11 +260,9 @@ __device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float* __r
   const float r0 = row_sum16(swap_sum16(p01, p23));
   const float r1 = row_sum16(swap_sum16(p45, p67));
   const float r2 = row_sum16(swap_sum16(p8, 0.f));
-  const int lane = lane_id(), k = lane & 15, row = lane >> 4;
-  if (k < 2 || (k == 2 && row == 0)) {
-    const float val = k == 0 ? r0 : (k == 1 ? r1 : r2);
-    const int field = k == 2 ? 8 : (k * 4 + ((row & 1) << 1) + (row >> 1));
-    if (val != 0.f) unsafeAtomicAdd(&dst[field], val);
+  if (sl.field >= 0) {
+    const float val = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : r2);
+    if (val != 0.f) unsafeAtomicAdd(&dst[sl.field], val);
   }
 }
 
@@ -274,6 +290,7 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
   const float lx = (float)(px.loc & 15), ly = (float)(px.loc >> 4);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const float amin = a.alpha_min, amax = a.alpha_max;
+  const Sum9Lane sl = sum9_lane();
 
   float Cout0 = 0.f, Cout1 = 0.f, Cout2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
   uint32_t last = 0;
@@ -357,7 +374,8 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
           v[6] = w * g0;
           v[7] = w * g1;
           v[8] = w * g2;
-          wave_sum9_atomic(v, &g2d[(int64_t)s_gid[j + u] * 9]);
+          const uint32_t gid = __builtin_amdgcn_readfirstlane(s_gid[j + u]);  // uniform
+          wave_sum9_atomic(v, g2d + (size_t)gid * 9, sl);
         }
       }
     }
