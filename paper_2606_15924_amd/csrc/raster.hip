@@ -57,6 +57,17 @@ __device__ __forceinline__ float splat_exponent(float dx, float dy, float A, flo
   return __builtin_fmaf(A, xx, __builtin_fmaf(C, yy, Bq * xy));
 }
 
+// The same exponent (same operations, bit-identical), also returning the
+// products dx^2, dx dy, dy^2 for the conic gradient.
+__device__ __forceinline__ float splat_exponent_p(float dx, float dy, float A, float Bq, float C, float& xx,
+                                                  float& xy, float& yy) {
+#pragma clang fp contract(off)
+  xx = dx * dx;
+  yy = dy * dy;
+  xy = dx * dy;
+  return __builtin_fmaf(A, xx, __builtin_fmaf(C, yy, Bq * xy));
+}
+
 // alpha = min(alpha_max, o G); ok = exponent <= 0 and alpha >= alpha_min.
 __device__ __forceinline__ float splat_alpha(float p2, float opacity, float amax, float& G) {
   G = __builtin_amdgcn_exp2f(p2);
@@ -302,6 +313,9 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
     last = ncontrib[px.out];
   }
   bool done = last <= begin - range.x;  // nothing composited from this chunk on
+  // T and S = sum_c g_c (C_c - acc_c): the loss-weighted colour behind the
+  // current Gaussian (final colour minus what is composited in front of
+  // and at it), updated as S -= w * sum_c g_c colour_c
   float T = 1.f, acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
   if (chunk > 0 && !done) {
     const float4 st = state[((int64_t)slot * (TGS_RENDER_CHUNKS - 1) + chunk - 1) * kBlock + tid];
@@ -310,6 +324,7 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
     acc1 = st.z;
     acc2 = st.w;
   }
+  float S = g0 * (Cout0 - acc0) + g1 * (Cout1 - acc1) + g2 * (Cout2 - acc2);
 
   Staged nxt = {};
   uint32_t g_after = 0;
@@ -332,13 +347,14 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
     for (int j = 0; j < cnt; j += kUnrollB) {
       if (__ballot(!done) == 0ull) break;  // the whole wave has finished
       float al[kUnrollB], Gv[kUnrollB], pw[kUnrollB], dxv[kUnrollB], dyv[kUnrollB];
+      float pxx[kUnrollB], pxy[kUnrollB], pyy[kUnrollB];
 #pragma unroll
       for (int u = 0; u < kUnrollB; ++u) {
         const float4 ge = s_geo[j + u];
         const float4 ap = s_app[j + u];
         dxv[u] = lx - ge.x;
         dyv[u] = ly - ge.y;
-        pw[u] = splat_exponent(dxv[u], dyv[u], ge.z, ge.w, ap.x);
+        pw[u] = splat_exponent_p(dxv[u], dyv[u], ge.z, ge.w, ap.x, pxx[u], pxy[u], pyy[u]);
         al[u] = splat_alpha(pw[u], ap.y, amax, Gv[u]);
       }
 #pragma unroll
@@ -349,27 +365,27 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
         const float alpha = al[u];
         const bool ok = !done && pw[u] <= 0.f && alpha >= amin;
         const float w = ok ? alpha * T : 0.f;
-        acc0 = __builtin_fmaf(w, ap.z, acc0);
-        acc1 = __builtin_fmaf(w, ap.w, acc1);
-        acc2 = __builtin_fmaf(w, cn.w, acc2);
+        // loss-weighted colour of this Gaussian: sum_c g_c colour_c
+        const float gc = __builtin_fmaf(g2, cn.w, __builtin_fmaf(g1, ap.w, g0 * ap.z));
         const float T_before = T;
         T = ok ? one_minus_times(T, alpha) : T;
+        S = __builtin_fmaf(-w, gc, S);
         done = done || (pos0 + (uint32_t)(j + u) + 1u >= last);
         if (__ballot(ok) != 0ull) {  // the gradient terms only where some lane composited
           const float G = Gv[u], dx = dxv[u], dy = dyv[u];
           const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
-          const float dalpha = g0 * (T_before * ap.z - (Cout0 - acc0) * inv) +
-                               g1 * (T_before * ap.w - (Cout1 - acc1) * inv) +
-                               g2 * (T_before * cn.w - (Cout2 - acc2) * inv);
+          // dL/dalpha = T_before sum_c g_c colour_c - S / (1 - alpha)
+          const float dalpha = __builtin_fmaf(T_before, gc, -S * inv);
           const bool unclamped = ok && ap.y * G < amax;
           const float dop = unclamped ? G * dalpha : 0.f;
           const float dpow = ap.y * dop;
+          const float hdp = -0.5f * dpow;
           float v[9];
           v[0] = (cn.x * dx + cn.y * dy) * dpow;
           v[1] = (cn.y * dx + cn.z * dy) * dpow;
-          v[2] = -0.5f * dx * dx * dpow;
-          v[3] = -dx * dy * dpow;
-          v[4] = -0.5f * dy * dy * dpow;
+          v[2] = pxx[u] * hdp;
+          v[3] = pxy[u] * (2.f * hdp);
+          v[4] = pyy[u] * hdp;
           v[5] = dop;
           v[6] = w * g0;
           v[7] = w * g1;
