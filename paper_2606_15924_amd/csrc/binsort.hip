@@ -206,41 +206,79 @@ __device__ __forceinline__ int wave_max_scan(int v) {
 }
 
 // ------------------------------------------------------------------ count
-constexpr int kCountThreads = 256;
 // Depth sort blocks (see depth_pass_kernel): 256 threads x 8 keys, 256 digits.
 constexpr int kDepthItems = 8;
 constexpr int kDepthBlockKeys = 256 * kDepthItems;
 constexpr int kDepthDigits = 256;
 
-// One thread per Gaussian walks the rows of its rectangle: kept pairs, and
-// kept pairs in valid tiles (every kept pair when there is no tile subset);
-// depth key (Gaussians without a kept valid tile get a key above every
-// depth), pair count and touched flag.
-__global__ void __launch_bounds__(kCountThreads) count_kernel(
+// One wave per 64 Gaussians (in index order).  Their rectangle rows are
+// flattened Gaussian by Gaussian and handed out 64 per round, so every lane
+// evaluates a row span whatever the rectangles' heights; a Gaussian whose
+// first row falls in the round marks its slot and an inclusive max-scan
+// carries each owner to the following slots.  Per Gaussian: kept pairs, and
+// kept pairs in valid tiles (every kept pair when there is no tile subset),
+// summed by LDS atomics; then the depth key (Gaussians without a kept valid
+// tile get a key above every depth), pair count and touched flag.
+constexpr int kCountBatch = kWave;
+
+struct CountBatch {
+  int4 rect[kWave];
+  uint32_t row0[kWave];  // exclusive prefix of the row counts in the batch
+  RowEllipse ell[kWave];
+  int mark[kWave];
+  uint32_t kept[kWave], valid[kWave];
+};
+
+__global__ void __launch_bounds__(kCountBatch) count_kernel(
     const int4* __restrict__ rect, const float4* __restrict__ splat, const float* __restrict__ depth, int64_t n,
     const int32_t* __restrict__ tile_slot, int tiles_x, int tiles_y, double tau, uint32_t* __restrict__ dkeys,
     uint32_t* __restrict__ dvals, uint32_t* __restrict__ emit_cnt, uint8_t* __restrict__ touched,
     unsigned long long* __restrict__ totals) {
-  __shared__ uint64_t s_red[kCountThreads / kWave];
-  const int64_t i = (int64_t)blockIdx.x * kCountThreads + threadIdx.x;
-  uint32_t kept = 0, valid = 0;
-  if (i < n) {
-    const int4 r = clamp_rect(rect[i], tiles_x, tiles_y);
-    if (r.z > r.x && r.w > r.y) {
-      const RowEllipse e = load_row_ellipse(splat, i, tau);
-      for (int ty = r.y; ty < r.w; ++ty) {
-        int lo, hi;
-        row_span(e, ty, r.x, r.z, lo, hi);
-        const uint32_t c = (uint32_t)max(hi - lo + 1, 0);
-        kept += c;
-        if (tile_slot == nullptr) {
-          valid += c;
-        } else {
-          const int32_t* row = tile_slot + (int64_t)ty * tiles_x;
-          for (int tx = lo; tx <= hi; ++tx) valid += row[tx] >= 0 ? 1u : 0u;
-        }
+  __shared__ CountBatch cb;
+  __shared__ uint64_t s_red[1];
+  const int lane = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * kCountBatch + lane;
+  int4 r = make_int4(0, 0, 0, 0);
+  if (i < n) r = clamp_rect(rect[i], tiles_x, tiles_y);
+  const uint32_t rows = r.z > r.x ? (uint32_t)(r.w - r.y) : 0u;
+  const uint32_t incl = wave_inclusive_scan_u32(rows);
+  const uint32_t my_row0 = incl - rows;
+  const uint32_t n_rows = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+  cb.rect[lane] = r;
+  cb.row0[lane] = my_row0;
+  cb.kept[lane] = 0u;
+  cb.valid[lane] = 0u;
+  if (rows > 0) cb.ell[lane] = load_row_ellipse(splat, i, tau);
+  int carry = -1;
+  for (uint32_t f0 = 0; f0 < n_rows; f0 += kWave) {
+    cb.mark[lane] = -1;
+    __syncthreads();
+    if (rows > 0 && my_row0 >= f0 && my_row0 - f0 < (uint32_t)kWave) cb.mark[my_row0 - f0] = lane;
+    __syncthreads();
+    const int jl = max(wave_max_scan(cb.mark[lane]), carry);
+    carry = __builtin_amdgcn_readlane(jl, kWave - 1);
+    const uint32_t f = f0 + (uint32_t)lane;
+    // jl >= 0 whenever f < n_rows: the first Gaussian with rows starts at row 0
+    if (f < n_rows && jl >= 0) {
+      const int4 rj = cb.rect[jl];
+      const int ty = rj.y + (int)(f - cb.row0[jl]);
+      int lo, hi;
+      row_span(cb.ell[jl], ty, rj.x, rj.z, lo, hi);
+      const uint32_t c = (uint32_t)max(hi - lo + 1, 0);
+      uint32_t cv = c;
+      if (tile_slot != nullptr) {
+        cv = 0u;
+        const int32_t* trow = tile_slot + (int64_t)ty * tiles_x;
+        for (int tx = lo; tx <= hi; ++tx) cv += trow[tx] >= 0 ? 1u : 0u;
       }
+      if (c > 0) atomicAdd(&cb.kept[jl], c);
+      if (cv > 0) atomicAdd(&cb.valid[jl], cv);
     }
+    __syncthreads();  // the round's reads and sums before the next round's writes
+  }
+  __syncthreads();
+  const uint32_t kept = cb.kept[lane], valid = cb.valid[lane];
+  if (i < n) {
     dkeys[i] = valid > 0 ? __float_as_uint(depth[i]) : kCulledKey;
     dvals[i] = (uint32_t)i;
     emit_cnt[i] = valid > 0 ? kept : 0u;  // every kept tile, valid or not, once the Gaussian has a pair
@@ -250,8 +288,8 @@ __global__ void __launch_bounds__(kCountThreads) count_kernel(
   const uint64_t v2[2] = {valid, valid > 0 ? kept : 0u};
   for (int k = 0; k < 2; ++k) {
     uint64_t tot;
-    block_exclusive_scan<kCountThreads, uint64_t>(v2[k], s_red, &tot);
-    if (threadIdx.x == 0 && tot > 0)
+    block_exclusive_scan<kCountBatch, uint64_t>(v2[k], s_red, &tot);
+    if (lane == 0 && tot > 0)
       atomicAdd(&totals[k * TGS_COUNTER_SLOTS + (blockIdx.x & (TGS_COUNTER_SLOTS - 1))], (unsigned long long)tot);
   }
 }
@@ -905,7 +943,7 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
     *n_pairs = 0;
     return hip_status("tgs_bin_sort");
   }
-  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountThreads)), dim3(kCountThreads), 0, s,
+  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kCountBatch), 0, s,
                      (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau,
                      w.dkeys[0], w.dvals[0], w.emit_cnt, touched, w.scalars);
   // The totals go to pinned host memory right after the count; the host
