@@ -219,7 +219,7 @@ constexpr int kDepthDigits = 256;
 // kept pairs in valid tiles (every kept pair when there is no tile subset),
 // summed by LDS atomics; then the depth key (Gaussians without a kept valid
 // tile get a key above every depth), pair count and touched flag.
-constexpr int kCountBatch = kWave;
+constexpr int kCountBatch = kWave;  // Gaussians per wave (32 measured slower)
 
 struct CountBatch {
   int4 rect[kWave];
@@ -229,7 +229,7 @@ struct CountBatch {
   uint32_t kept[kWave], valid[kWave];
 };
 
-__global__ void __launch_bounds__(kCountBatch) count_kernel(
+__global__ void __launch_bounds__(kWave) count_kernel(
     const int4* __restrict__ rect, const float4* __restrict__ splat, const float* __restrict__ depth, int64_t n,
     const int32_t* __restrict__ tile_slot, int tiles_x, int tiles_y, double tau, uint32_t* __restrict__ dkeys,
     uint32_t* __restrict__ dvals, uint32_t* __restrict__ emit_cnt, uint8_t* __restrict__ touched,
@@ -238,8 +238,9 @@ __global__ void __launch_bounds__(kCountBatch) count_kernel(
   __shared__ uint64_t s_red[1];
   const int lane = lane_id();
   const int64_t i = (int64_t)blockIdx.x * kCountBatch + lane;
+  const bool mine = lane < kCountBatch && i < n;
   int4 r = make_int4(0, 0, 0, 0);
-  if (i < n) r = clamp_rect(rect[i], tiles_x, tiles_y);
+  if (mine) r = clamp_rect(rect[i], tiles_x, tiles_y);
   const uint32_t rows = r.z > r.x ? (uint32_t)(r.w - r.y) : 0u;
   const uint32_t incl = wave_inclusive_scan_u32(rows);
   const uint32_t my_row0 = incl - rows;
@@ -278,7 +279,7 @@ __global__ void __launch_bounds__(kCountBatch) count_kernel(
   }
   __syncthreads();
   const uint32_t kept = cb.kept[lane], valid = cb.valid[lane];
-  if (i < n) {
+  if (mine) {
     dkeys[i] = valid > 0 ? __float_as_uint(depth[i]) : kCulledKey;
     dvals[i] = (uint32_t)i;
     emit_cnt[i] = valid > 0 ? kept : 0u;  // every kept tile, valid or not, once the Gaussian has a pair
@@ -288,7 +289,7 @@ __global__ void __launch_bounds__(kCountBatch) count_kernel(
   const uint64_t v2[2] = {valid, valid > 0 ? kept : 0u};
   for (int k = 0; k < 2; ++k) {
     uint64_t tot;
-    block_exclusive_scan<kCountBatch, uint64_t>(v2[k], s_red, &tot);
+    block_exclusive_scan<kWave, uint64_t>(v2[k], s_red, &tot);
     if (lane == 0 && tot > 0)
       atomicAdd(&totals[k * TGS_COUNTER_SLOTS + (blockIdx.x & (TGS_COUNTER_SLOTS - 1))], (unsigned long long)tot);
   }
@@ -677,8 +678,9 @@ struct RowBatch {
 };
 
 constexpr int kEmitThreads = kWave;  // one wave per workgroup: __syncthreads is a wave barrier
+constexpr int kEmitBatch = 32;       // Gaussians per wave: more waves, fewer rounds each (64 measured slower)
 
-// A wave per 64 depth-ordered Gaussians.  Their rectangle rows are
+// A wave per kEmitBatch depth-ordered Gaussians.  Their rectangle rows are
 // flattened Gaussian by Gaussian and handed out 64 per round; a Gaussian
 // whose first row falls in the round marks its slot and an inclusive
 // max-scan carries each owner to the following slots, so a lane finds its
@@ -694,11 +696,11 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     int id_bits, double tau, uint32_t total, K* __restrict__ keys) {
   __shared__ RowBatch rb;
   const int lane = lane_id();
-  const int64_t b0 = (int64_t)blockIdx.x * kWave;
+  const int64_t b0 = (int64_t)blockIdx.x * kEmitBatch;
   const int64_t j = b0 + lane;
   int4 r = make_int4(0, 0, 0, 0);
   uint32_t g = 0, rows = 0;
-  if (j < n && off[j + 1] > off[j]) {
+  if (lane < kEmitBatch && j < n && off[j + 1] > off[j]) {
     r = rect_sorted[j];
     g = ids_sorted[j];
     rows = (uint32_t)(r.w - r.y);
@@ -851,7 +853,7 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
                        const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits, int tbits, double tau,
                        const float* depth, uint32_t* vals, uint64_t* keys64, uint32_t* ranges, hipStream_t s) {
   K* kb[2] = {(K*)w.pkeys[0], (K*)w.pkeys[1]};
-  hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(n, kWave)), dim3(kEmitThreads), 0, s,
+  hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(n, kEmitBatch)), dim3(kEmitThreads), 0, s,
                      w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, id_bits, tau, total, kb[0]);
   const int passes = pass_count(tbits);
   int cur = 0, shift = id_bits;
@@ -943,7 +945,7 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
     *n_pairs = 0;
     return hip_status("tgs_bin_sort");
   }
-  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kCountBatch), 0, s,
+  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kWave), 0, s,
                      (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau,
                      w.dkeys[0], w.dvals[0], w.emit_cnt, touched, w.scalars);
   // The totals go to pinned host memory right after the count; the host
