@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
 
   float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
   uint32_t last = 0;
-  uint32_t n_eval = 0, n_blend = 0;  // wave totals (ballot counts)
+  uint32_t n_eval = 0, n_blend = 0;  // this lane's evaluations and blends (summed over the wave at the end)
   bool done = !px.inside;
 
   // prologue: records of batch 0 and ids of batch 1 in flight
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
       for (int u = 0; u < kUnroll; ++u) {
         const float t_next = one_minus_times(T, al[u]);
         bool ok = !done && pw[u] <= 0.f && al[u] >= amin;
-        n_eval += j + u < cnt ? (uint32_t)__popcll(__ballot(!done)) : 0u;  // uniform select
+        n_eval += (j + u < cnt && !done) ? 1u : 0u;
         const bool stop = ok && t_next < tmin;
         done = done || stop;
         ok = ok && !stop;
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
         c2 = __builtin_fmaf(w, cb[u], c2);
         T = ok ? t_next : T;
         last = ok ? pos0 + (uint32_t)(j + u) + 1u : last;
-        n_blend += (uint32_t)__popcll(__ballot(ok));
+        n_blend += ok ? 1u : 0u;
       }
     }
   }
@@ -211,7 +211,11 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
     out[px.out] = make_float4(c0 + T * a.bg0, c1 + T * a.bg1, c2 + T * a.bg2, T);
     ncontrib[px.out] = last;
   }
-  if (counters != nullptr && lane_id() == 0) {  // n_eval, n_blend are wave totals
+  if (counters != nullptr) {
+    n_eval = (uint32_t)wave_sum_i((int)n_eval);
+    n_blend = (uint32_t)wave_sum_i((int)n_blend);
+  }
+  if (counters != nullptr && lane_id() == 0) {  // wave totals
     const int cs = blockIdx.x & (TGS_COUNTER_SLOTS - 1);
     atomicAdd(&counters[cs], (unsigned long long)n_eval);
     atomicAdd(&counters[TGS_COUNTER_SLOTS + cs], (unsigned long long)n_blend);
