@@ -174,7 +174,9 @@ int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t
  *   vals         [capacity] uint32: Gaussian ids ordered by (tile, depth
  *                bits, id)
  *   ranges       [tiles_x * tiles_y][2] uint32 [start, end), [0, 0) if empty
- *   touched      nullable [n] uint8: set to 1 for Gaussians with a pair
+ *   touched      nullable [n] uint8: set to 1 for Gaussians with a pair;
+ *                other entries are left as they are, so one array
+ *                cleared once collects the Gaussians of several views
  *   n_pairs      host out: number of pairs in valid tiles
  * capacity must hold every listed tile (valid or not) of every Gaussian
  * that has a pair in a valid tile; when it does not, the call returns
