@@ -60,54 +60,97 @@ __global__ void __launch_bounds__(256) sh_rest_kernel(
   for (int k = 0; k < 3; ++k) dL_du_out[i * 3 + k] = dL_du[k];
 }
 
-__global__ void __launch_bounds__(256) geom_lm_kernel(
+// Rows 0-13 of every Gaussian the wave updates: parameters, moments and (when
+// there is one) the earlier views' gradient are copied into LDS by the
+// memory system while the chain rule runs, so the update does not wait for
+// them at the end.  One wave per workgroup; LDS holds kPre (or kPre + 14)
+// rows of 64 floats.
+constexpr int kGeoRows = 14;
+constexpr int kPre = 3 * kGeoRows;  // params, m, v
+
+__global__ void __launch_bounds__(kWave) geom_lm_kernel(
     float* params, int64_t n, CamArgs cam, int sh_degree, double z_near, double dil,
     const int* __restrict__ radius, const uint8_t* __restrict__ clampm, const float* __restrict__ g2d,
     const float* __restrict__ grad_prev, float* __restrict__ m, float* __restrict__ v,
     const uint8_t* __restrict__ touched, OptArgs o, const double* __restrict__ dL_du_in) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (touched != nullptr && touched[i] == 0) return;
-  const bool lm = o.lm_mode != 2;
-  float gl[14];  // gradients of rows 0-13 (LM blocks), applied after the chain rule
-  auto sink = [&](int row, double val) {
-    const int64_t idx = (int64_t)row * n + i;
-    const float gf = stored_grad(grad_prev, idx, val);
-    if (lm) {
-      gl[row] = gf;
-      return;
+  extern __shared__ float s_rows[];  // [kPre (+ 14)][64]
+  const int lane = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+  const int64_t ic = i < n ? i : n - 1;  // lanes past the end load a valid element
+  // asynchronous row copies global -> LDS: lane l's value lands at [row][l]
+  const float* srcs[4] = {params, m, v, grad_prev};
+  const int n_src = grad_prev != nullptr ? 4 : 3;
+  for (int q = 0; q < n_src; ++q)
+#pragma unroll
+    for (int r = 0; r < kGeoRows; ++r)
+      __builtin_amdgcn_global_load_lds(srcs[q] + (int64_t)r * n + ic, s_rows + (q * kGeoRows + r) * kWave, 4, 0, 0);
+
+  const bool live = i < n && (touched == nullptr || touched[i] != 0);  // untouched: nothing changes
+  float gl[kGeoRows];  // this view's gradient of rows 0-13, rounded to float
+  if (live) {
+    auto sink = [&](int row, double val) { gl[row] = (float)val; };
+    if (radius[i] != 0) {
+      Geom g;
+      geometry(params, n, i, cam, z_near, dil, g);
+      double gg[9];
+      for (int k = 0; k < 9; ++k) gg[k] = (double)g2d[i * 9 + k];
+      const ViewDir u = view_dir(g.mu, cam);
+      double drgb[3];
+      color_grad(gg, clampm[i], drgb);
+      double dc_du[3] = {0.0, 0.0, 0.0};  // the DC basis is constant: no dL/du
+      sh_backward(params, n, i, u, drgb, n_sh(sh_degree), 0, 1, dc_du, sink);
+      const double dL_du[3] = {dL_du_in[i * 3], dL_du_in[i * 3 + 1], dL_du_in[i * 3 + 2]};
+      geom_backward(params, n, i, cam, g, gg, u, dL_du, sink);
+    } else {
+#pragma unroll
+      for (int r = 0; r < kGeoRows; ++r) gl[r] = 0.f;
     }
-    float pp = params[idx], mm = m[idx], vv = v[idx];
-    adam_elem(pp, gf, mm, vv, row_lr_bc1(o, row), o);
-    params[idx] = pp;
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // the row copies have landed
+  __syncthreads();
+  if (!live) return;
+  auto at = [&](int q, int row) -> float& { return s_rows[(q * kGeoRows + row) * kWave + lane]; };
+  // the step's gradient as the unfused path stores it
+  if (grad_prev != nullptr)
+#pragma unroll
+    for (int r = 0; r < kGeoRows; ++r) gl[r] = at(3, r) + gl[r];
+  auto store = [&](int row, float pp, float mm, float vv) {
+    const int64_t idx = (int64_t)row * n + i;
     m[idx] = mm;
     v[idx] = vv;
+    params[idx] = pp;
   };
-  if (radius[i] != 0) {
-    Geom g;
-    geometry(params, n, i, cam, z_near, dil, g);
-    double gg[9];
-    for (int k = 0; k < 9; ++k) gg[k] = (double)g2d[i * 9 + k];
-    const ViewDir u = view_dir(g.mu, cam);
-    double drgb[3];
-    color_grad(gg, clampm[i], drgb);
-    double dc_du[3] = {0.0, 0.0, 0.0};  // the DC basis is constant: no dL/du
-    sh_backward(params, n, i, u, drgb, n_sh(sh_degree), 0, 1, dc_du, sink);
-    const double dL_du[3] = {dL_du_in[i * 3], dL_du_in[i * 3 + 1], dL_du_in[i * 3 + 2]};
-    geom_backward(params, n, i, cam, g, gg, u, dL_du, sink);
-  } else {
+  if (o.lm_mode == 2) {
 #pragma unroll
-    for (int r = 0; r < 14; ++r) sink(r, 0.0);
+    for (int r = 0; r < kGeoRows; ++r) {
+      float pp = at(0, r), mm = at(1, r), vv = at(2, r);
+      adam_elem(pp, gl[r], mm, vv, row_lr_bc1(o, r), o);
+      store(r, pp, mm, vv);
+    }
+    return;
   }
-  if (lm) {
-    float gg[10], ga[4];
+  float pg[10], mg[10], vg[10], gg[10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) gg[k] = gl[kGeomRows[k]];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) ga[k] = gl[kAppRows[k]];
-    lm_update<10>(params, m, v, n, i, kGeomRows, gg, o);
-    lm_update<4>(params, m, v, n, i, kAppRows, ga, o);
+  for (int k = 0; k < 10; ++k) {
+    pg[k] = at(0, kGeomRows[k]);
+    mg[k] = at(1, kGeomRows[k]);
+    vg[k] = at(2, kGeomRows[k]);
+    gg[k] = gl[kGeomRows[k]];
   }
+  lm_block<10>(pg, mg, vg, kGeomRows, gg, o);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) store(kGeomRows[k], pg[k], mg[k], vg[k]);
+  float pa[4], ma[4], va[4], ga[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    pa[k] = at(0, kAppRows[k]);
+    ma[k] = at(1, kAppRows[k]);
+    va[k] = at(2, kAppRows[k]);
+    ga[k] = gl[kAppRows[k]];
+  }
+  lm_block<4>(pa, ma, va, kAppRows, ga, o);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) store(kAppRows[k], pa[k], ma[k], va[k]);
 }
 
 }  // namespace tgs
@@ -140,7 +183,9 @@ extern "C" int32_t tgs_project_bwd_optimizer_step(float* params, int64_t n, cons
   const dim3 grid((unsigned)ceil_div(n, 256));
   hipLaunchKernelGGL(sh_rest_kernel, grid, dim3(256), 0, s, params, n, ca, rp->sh_degree, radius, clamp, g2d,
                      grad_prev, m, v, touched, o, (double*)ws);
-  hipLaunchKernelGGL(geom_lm_kernel, grid, dim3(256), 0, s, params, n, ca, rp->sh_degree, (double)rp->z_near,
-                     (double)rp->dilation, radius, clamp, g2d, grad_prev, m, v, touched, o, (const double*)ws);
+  const size_t lds = (size_t)(grad_prev != nullptr ? kPre + kGeoRows : kPre) * kWave * sizeof(float);
+  hipLaunchKernelGGL(geom_lm_kernel, dim3((unsigned)ceil_div(n, kWave)), dim3(kWave), lds, s, params, n, ca,
+                     rp->sh_degree, (double)rp->z_near, (double)rp->dilation, radius, clamp, g2d, grad_prev, m, v,
+                     touched, o, (const double*)ws);
   return hip_status(who);
 }

@@ -51,7 +51,8 @@ __device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v,
 // Learning rate of a row divided by the first-moment bias correction.
 __host__ __device__ inline double row_lr_bc1(const OptArgs& o, int row) { return row_lr(o, row) / o.bc1; }
 
-// LM step of one block of K rows of Gaussian i with block gradient gf.
+// LM step of one block of K rows of a Gaussian (p, m, v updated in place)
+// with block gradient gf.
 // Solves (g g^T + diag(d)) x = -m (mode 0) or diag(g^2 + d) x = -m (mode 1)
 // with the updated moments, d = sqrt(v) + eps.  The mode-0 matrix is
 // diagonal plus rank one, so its inverse follows the Sherman-Morrison
@@ -60,20 +61,18 @@ __host__ __device__ inline double row_lr_bc1(const OptArgs& o, int row) { return
 // an exact solve in K divisions and two dot products (no K x K factor in
 // registers).  d >= eps > 0 keeps D invertible and 1 + g^T D^-1 g >= 1.
 template <int K>
-__device__ __forceinline__ void lm_update(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                                          int64_t n, int64_t i, const int (&rows)[K], const float (&gf)[K],
-                                          const OptArgs& o) {
+__device__ __forceinline__ void lm_block(float (&p)[K], float (&m)[K], float (&v)[K], const int (&rows)[K],
+                                         const float (&gf)[K], const OptArgs& o) {
 #pragma clang fp contract(off)
   double g[K], mm[K], d[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int64_t idx = (int64_t)rows[k] * n + i;
     g[k] = gf[k];
-    mm[k] = o.beta1 * (double)m[idx] + (1.0 - o.beta1) * g[k];
-    const double vv = o.beta2 * (double)v[idx] + (1.0 - o.beta2) * g[k] * g[k];
+    mm[k] = o.beta1 * (double)m[k] + (1.0 - o.beta1) * g[k];
+    const double vv = o.beta2 * (double)v[k] + (1.0 - o.beta2) * g[k] * g[k];
     d[k] = sqrt(vv) + o.eps_lm;
-    m[idx] = (float)mm[k];
-    v[idx] = (float)vv;
+    m[k] = (float)mm[k];
+    v[k] = (float)vv;
   }
   double x[K];
   if (o.lm_mode == 1) {
@@ -92,9 +91,30 @@ __device__ __forceinline__ void lm_update(float* __restrict__ p, float* __restri
     for (int k = 0; k < K; ++k) x[k] = (g[k] * c - mm[k]) * d[k];
   }
 #pragma unroll
+  for (int k = 0; k < K; ++k) p[k] = (float)((double)p[k] + row_lr(o, rows[k]) * x[k]);
+}
+
+// The same on the [59][n] stores: loads the block's rows of Gaussian i,
+// updates them and stores them back.
+template <int K>
+__device__ __forceinline__ void lm_update(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                          int64_t n, int64_t i, const int (&rows)[K], const float (&gf)[K],
+                                          const OptArgs& o) {
+  float pk[K], mk[K], vk[K];
+#pragma unroll
   for (int k = 0; k < K; ++k) {
     const int64_t idx = (int64_t)rows[k] * n + i;
-    p[idx] = (float)((double)p[idx] + row_lr(o, rows[k]) * x[k]);
+    pk[k] = p[idx];
+    mk[k] = m[idx];
+    vk[k] = v[idx];
+  }
+  lm_block<K>(pk, mk, vk, rows, gf, o);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t idx = (int64_t)rows[k] * n + i;
+    m[idx] = mk[k];
+    v[idx] = vk[k];
+    p[idx] = pk[k];
   }
 }
 

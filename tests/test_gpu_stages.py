@@ -489,11 +489,13 @@ def test_project_bwd_parity(B, case):
 
 
 # ------------------------------------------------------------------ fused backward + optimizer
-@pytest.mark.parametrize("mode,prev,deg", [(0, False, 3), (1, True, 3), (2, False, 3), (0, True, 1)])
-def test_project_bwd_optimizer_fused(B, mode, prev, deg):
+@pytest.mark.parametrize("mode,prev,deg,n", [(0, False, 3, 4000), (1, True, 3, 4000), (2, False, 3, 4000),
+                                            (0, True, 1, 4000), (0, False, 3, 20011), (1, True, 3, 20011)])
+def test_project_bwd_optimizer_fused(B, mode, prev, deg, n):
     """The fused entry point equals tgs_project_bwd then tgs_optimizer_step
-    bit for bit (culled, untouched and touched-but-culled Gaussians included)."""
-    p, cams = scene_c1(4000)
+    bit for bit (culled, untouched and touched-but-culled Gaussians included;
+    at 20011 Gaussians the update runs as two halves on two streams)."""
+    p, cams = scene_c1(n)
     cam = cams[2]
     n = p.shape[1]
     rng = np.random.default_rng(31 + mode)
