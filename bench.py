@@ -133,10 +133,22 @@ def run(tr, steps, warmup):
     cnt = tr.counters.sum(dim=1).cpu().tolist()
     tr.events = None
     tr.timed_stages = None
+    # spread of single steps: one event between consecutive steps (a pass of
+    # its own, so the timed steps above carry no per-step events)
+    n_dist = max(20, steps // 2)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_dist + 1)]
+    evs[0].record()
+    for k in range(n_dist):
+        tr.step([0])
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    per = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(n_dist))
+    pct = {f"p{q}": round(per[min(n_dist - 1, int(q / 100 * n_dist))], 4) for q in (10, 50, 90)}
     vb = tr._bufs[0]
     pixels = (vb.width * vb.height) if vb.dense else int(vb.tile_off[-1].item())
     return dict(seconds=t1 - t0, ms_per_step=(t1 - t0) * 1000.0 / steps, evals=cnt[0], blends=cnt[1],
-                stage_ms=stage, dominant=dom, dominant_ms=dom_ms, n_pairs=int(vb.n_pairs), pixels=pixels)
+                stage_ms=stage, dominant=dom, dominant_ms=dom_ms, n_pairs=int(vb.n_pairs), pixels=pixels,
+                step_ms_spread=pct)
 
 
 def matched_psnr(dev, dense_steps=PSNR_DENSE_STEPS, max_steps=PSNR_MAX_STEPS):
@@ -387,6 +399,11 @@ def main():
                    "gaussians": N_GAUSS, "width": WIDTH, "height": HEIGHT, "rate": 0.25,
                    "pairs": head["n_pairs"], "parallelism": "single GPU"},
         "stage_ms": {k: round(v, 4) for k, v in head["stage_ms"].items()},
+        "step_ms_spread": head["step_ms_spread"],
+        # blends per second of the raster kernels alone (forward; forward + backward)
+        "blends_per_s_fwd": per_launch_blends / (1e-3 * head["stage_ms"]["render_fwd"]),
+        "blends_per_s_fwd_bwd": per_launch_blends / (1e-3 * (head["stage_ms"]["render_fwd"] +
+                                                            head["stage_ms"]["render_bwd"])),
         "per_step": {"evaluations": per_launch_evals, "blends": per_launch_blends,
                      "sampled_pixels": head["pixels"]},
         "dense": dense,
