@@ -23,41 +23,75 @@
 
 namespace tgs {
 
-// Gradient of one row as the unfused path stores it (float), plus the
-// earlier views' gradient when there is one.
-__device__ __forceinline__ float stored_grad(const float* __restrict__ grad_prev, int64_t idx, double val) {
-  return grad_prev != nullptr ? grad_prev[idx] + (float)val : (float)val;
-}
-
+template <int kDeg>
 __global__ void __launch_bounds__(256) sh_rest_kernel(
-    float* params, int64_t n, CamArgs cam, int sh_degree, const int* __restrict__ radius,
-    const uint8_t* __restrict__ clampm, const float* __restrict__ g2d, const float* __restrict__ grad_prev,
-    float* __restrict__ m, float* __restrict__ v, const uint8_t* __restrict__ touched, OptArgs o,
-    double* __restrict__ dL_du_out) {
+    float* params, int64_t n, CamArgs cam, const int* __restrict__ radius, const uint8_t* __restrict__ clampm,
+    const float* __restrict__ g2d, const float* __restrict__ grad_prev, float* __restrict__ m,
+    float* __restrict__ v, const uint8_t* __restrict__ touched, OptArgs o, double* __restrict__ dL_du_out) {
+#pragma clang fp contract(off)
+  constexpr int nk = (kDeg + 1) * (kDeg + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (touched != nullptr && touched[i] == 0) return;  // untouched: parameters and moments stay
-  auto adam_row = [&](int row, double val) {
-    const int64_t idx = (int64_t)row * n + i;
-    float pp = params[idx], mm = m[idx], vv = v[idx];
-    adam_elem(pp, stored_grad(grad_prev, idx, val), mm, vv, row_lr_bc1(o, row), o);
-    params[idx] = pp;
-    m[idx] = mm;
-    v[idx] = vv;
-  };
-  if (radius[i] == 0) {
-    for (int row = 14; row < TGS_PARAM_ROWS; ++row) adam_row(row, 0.0);
-    return;
+  const bool vis = radius[i] != 0;
+  double drgb[3] = {0.0, 0.0, 0.0}, dL_du[3] = {0.0, 0.0, 0.0};
+  ViewDir u{};
+  if (vis) {
+    double mu[3], gg[9];
+    for (int k = 0; k < 3; ++k) mu[k] = (double)params[(int64_t)k * n + i];
+    for (int k = 0; k < 9; ++k) gg[k] = (double)g2d[i * 9 + k];
+    u = view_dir(mu, cam);
+    color_grad(gg, clampm[i], drgb);
   }
-  double mu[3], gg[9];
-  for (int k = 0; k < 3; ++k) mu[k] = (double)params[(int64_t)k * n + i];
-  for (int k = 0; k < 9; ++k) gg[k] = (double)g2d[i * 9 + k];
-  const ViewDir u = view_dir(mu, cam);
-  double drgb[3];
-  color_grad(gg, clampm[i], drgb);
-  double dL_du[3] = {0.0, 0.0, 0.0};
-  sh_backward(params, n, i, u, drgb, n_sh(sh_degree), 1, 16, dL_du, adam_row);
-  for (int k = 0; k < 3; ++k) dL_du_out[i * 3 + k] = dL_du[k];
+  // SH terms k = 1..15 (rows 11 + 3k + ch), software-pipelined: the rows of
+  // term k + 1 are loaded before term k is updated and stored.  The
+  // arithmetic is that of the projection backward (SH part) followed by Adam.
+  struct Rows { float p[3], m[3], v[3], g[3]; };
+  auto load = [&](int k, Rows& r) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const int64_t idx = (int64_t)(11 + 3 * k + ch) * n + i;
+      r.p[ch] = params[idx];
+      r.m[ch] = m[idx];
+      r.v[ch] = v[idx];
+      r.g[ch] = grad_prev != nullptr ? grad_prev[idx] : 0.f;
+    }
+  };
+  Rows cur, nxt;
+  load(1, cur);
+#pragma unroll
+  for (int k = 1; k < 16; ++k) {
+    if (k + 1 < 16) load(k + 1, nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    double grad[3] = {0.0, 0.0, 0.0};
+    if (vis && k < nk) {
+      double Yk, d0, d1, d2;
+      sh_term(k, u.ux, u.uy, u.uz, Yk, d0, d1, d2);
+      double gk = 0.0;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        gk += (double)cur.p[ch] * drgb[ch];
+        grad[ch] = Yk * drgb[ch];
+      }
+      dL_du[0] += d0 * gk;
+      dL_du[1] += d1 * gk;
+      dL_du[2] += d2 * gk;
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const int row = 11 + 3 * k + ch;
+      const int64_t idx = (int64_t)row * n + i;
+      float pp = cur.p[ch], mm = cur.m[ch], vv = cur.v[ch];
+      const float gf = grad_prev != nullptr ? cur.g[ch] + (float)grad[ch] : (float)grad[ch];
+      adam_elem(pp, gf, mm, vv, row_lr_bc1(o, row), o);
+      params[idx] = pp;
+      m[idx] = mm;
+      v[idx] = vv;
+    }
+    if (k + 1 < 16) cur = nxt;
+  }
+  if (vis)
+    for (int k = 0; k < 3; ++k) dL_du_out[i * 3 + k] = dL_du[k];
 }
 
 // Rows 0-13 of every Gaussian the wave updates: parameters, moments and (when
@@ -181,8 +215,16 @@ extern "C" int32_t tgs_project_bwd_optimizer_step(float* params, int64_t n, cons
   const CamArgs ca = make_cam(cam);
   hipStream_t s = as_stream(stream);
   const dim3 grid((unsigned)ceil_div(n, 256));
-  hipLaunchKernelGGL(sh_rest_kernel, grid, dim3(256), 0, s, params, n, ca, rp->sh_degree, radius, clamp, g2d,
-                     grad_prev, m, v, touched, o, (double*)ws);
+#define TGS_SH_REST(D)                                                                                \
+  hipLaunchKernelGGL(sh_rest_kernel<D>, grid, dim3(256), 0, s, params, n, ca, radius, clamp, g2d, grad_prev, m, v, \
+                     touched, o, (double*)ws)
+  switch (rp->sh_degree) {
+    case 0: TGS_SH_REST(0); break;
+    case 1: TGS_SH_REST(1); break;
+    case 2: TGS_SH_REST(2); break;
+    default: TGS_SH_REST(3); break;
+  }
+#undef TGS_SH_REST
   const size_t lds = (size_t)(grad_prev != nullptr ? kPre + kGeoRows : kPre) * kWave * sizeof(float);
   hipLaunchKernelGGL(geom_lm_kernel, dim3((unsigned)ceil_div(n, kWave)), dim3(kWave), lds, s, params, n, ca,
                      rp->sh_degree, (double)rp->z_near, (double)rp->dilation, radius, clamp, g2d, grad_prev, m, v,

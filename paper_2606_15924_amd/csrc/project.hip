@@ -14,8 +14,9 @@
 
 namespace tgs {
 
+template <int kDeg>
 __global__ void __launch_bounds__(256) project_fwd_kernel(
-    const float* __restrict__ params, int64_t n, CamArgs cam, int sh_degree, double z_near,
+    const float* __restrict__ params, int64_t n, CamArgs cam, double z_near,
     double dil, float4* __restrict__ splat, float* __restrict__ depth, int* __restrict__ radius,
     int4* __restrict__ rect, uint8_t* __restrict__ clampm, float* __restrict__ g2d_clear) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -39,15 +40,19 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
                dz = g.mu[2] - cam.center[2];
   const double dn = sqrt(dx * dx + dy * dy + dz * dz);
   const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
-  const int nk = n_sh(sh_degree);
+  // the degree is a template argument, so all coefficient loads are
+  // independent and issued together
+  constexpr int nk = (kDeg + 1) * (kDeg + 1);
+  float cf[3 * nk];
+#pragma unroll
+  for (int q = 0; q < 3 * nk; ++q) cf[q] = params[(int64_t)(11 + q) * n + i];
+  __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the SH arithmetic
   double rgb[3] = {0.5, 0.5, 0.5};
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    if (k < nk) {
-      double Yk, g0, g1, g2;
-      sh_term(k, ux, uy, uz, Yk, g0, g1, g2);
-      for (int ch = 0; ch < 3; ++ch) rgb[ch] += Yk * (double)params[(int64_t)(11 + 3 * k + ch) * n + i];
-    }
+  for (int k = 0; k < nk; ++k) {
+    double Yk, g0, g1, g2;
+    sh_term(k, ux, uy, uz, Yk, g0, g1, g2);
+    for (int ch = 0; ch < 3; ++ch) rgb[ch] += Yk * (double)cf[3 * k + ch];
   }
   uint8_t cm = 0;
   for (int ch = 0; ch < 3; ++ch)
@@ -107,9 +112,18 @@ extern "C" int32_t tgs_project(const float* params, int64_t n, const tgs_camera*
               "tgs_project: splat and rect must be 16-byte aligned");
   const CamArgs ca = make_cam(cam);
   const int block = 256;
-  hipLaunchKernelGGL(project_fwd_kernel, dim3((unsigned)ceil_div(n, block)), dim3(block), 0,
-                     as_stream(stream), params, n, ca, rp->sh_degree, (double)rp->z_near,
-                     (double)rp->dilation, (float4*)splat, depth, radius, (int4*)rect, clamp, g2d_clear);
+  const dim3 grid((unsigned)ceil_div(n, block));
+  hipStream_t s = as_stream(stream);
+#define TGS_PROJECT(D)                                                                                           \
+  hipLaunchKernelGGL(project_fwd_kernel<D>, grid, dim3(block), 0, s, params, n, ca, (double)rp->z_near,          \
+                     (double)rp->dilation, (float4*)splat, depth, radius, (int4*)rect, clamp, g2d_clear)
+  switch (rp->sh_degree) {
+    case 0: TGS_PROJECT(0); break;
+    case 1: TGS_PROJECT(1); break;
+    case 2: TGS_PROJECT(2); break;
+    default: TGS_PROJECT(3); break;
+  }
+#undef TGS_PROJECT
   return hip_status("tgs_project");
 }
 
