@@ -5,10 +5,12 @@
 //   sh_rest_kernel   the SH rows of degree >= 1 (rows 14-58, always Adam
 //                    rows): their gradient Y_k(u) * dL/drgb,
 //                    the Adam update, and the partial dL/du of these rows
-//                    (three doubles per Gaussian in the workspace);
-//                    light on registers, so many waves keep HBM busy
+//                    (three doubles per Gaussian in the workspace); each
+//                    SH term's rows are loaded while the previous term is
+//                    updated, so the kernel streams at close to HBM rate
 //   geom_lm_kernel   the geometry chain rule and rows 0-13 (SH DC, opacity,
-//                    mean, scale, quaternion) with the LM (or Adam) update
+//                    mean, scale, quaternion) with the LM (or Adam) update;
+//                    its rows reach LDS while the chain rule runs
 // The SH-rest kernel reads the coefficients before updating them, and the
 // geometry kernel only touches rows 0-13, so running them in this order
 // gives each the values the unfused path sees.  Results equal
