@@ -235,10 +235,10 @@ def test_scaling_optimizer_on_sampled_gaussians(B, scaling):
 
 # ------------------------------------------------------------------ full training step size
 # 1.5M Gaussians, 1600x1060 views on the upper hemisphere (f = 1875), 20%
-# error-guided sampling (51 px per tile), K = 3 views per step, LM in its
-# diagonal mode.  Checked at full size: one view's projection, pair lists
-# and ranges bit-exact; forward and backward on sampled tiles against the
-# oracle; the three-view step by properties that hold at any size.
+# error-guided sampling (51 px per tile), K = 3 and K = 10 views per step,
+# LM in its diagonal mode.  Checked at full size: one view's projection, pair
+# lists and ranges bit-exact; forward and backward on sampled tiles against
+# the oracle; the multi-view steps by properties that hold at any size.
 FULL_N = 1_500_000
 
 
@@ -307,8 +307,9 @@ def test_full_size_forward_and_backward_on_sampled_tiles(B, fullstep):
         assert_close(got[f], g2d[f], 1e-4, 2e-6 * g2d_abs[f] + 1e-12, f"g2d field {f}")
 
 
-def test_full_size_three_view_step_properties(B, fullstep):
-    """Three views per step at 20%, fused and unfused final update.  The
+@pytest.mark.parametrize("views", [[0, 50, 100], list(range(0, 150, 15))], ids=["K3", "K10"])
+def test_full_size_multi_view_step_properties(B, fullstep, views):
+    """K = 3 and K = 10 views per step at 20%, fused and unfused final update.  The
     backward's float atomics sum in a different order on every run, so the
     two runs agree up to that rounding (the stage tests compare the fused
     and unfused update bit for bit on identical inputs).  Gaussians without
@@ -317,16 +318,15 @@ def test_full_size_three_view_step_properties(B, fullstep):
     pixel get a zero gradient and stay)."""
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
     p, cams = fullstep["p"], fullstep["cams"]
-    views = [0, 50, 100]
     vcams = [cams[v] for v in views]
-    gts = [dev(synth.image(c.height, c.width, 93 + k)) for k, c in enumerate(vcams)]
+    gts = [dev(synth.image(c.height, c.width, 100 + k)) for k, c in enumerate(vcams)]
     res = []
     for fused in (True, False):
-        E = [dev(synth.error_map(c.height, c.width, 94 + k).view(np.int16)) for k, c in enumerate(vcams)]
-        A = [dev(synth.age_map(c.height, c.width, 97 + k).view(np.int16)) for k, c in enumerate(vcams)]
+        E = [dev(synth.error_map(c.height, c.width, 200 + k).view(np.int16)) for k, c in enumerate(vcams)]
+        A = [dev(synth.age_map(c.height, c.width, 300 + k).view(np.int16)) for k, c in enumerate(vcams)]
         cfg = StepConfig(rate_permille=200, fuse_optimizer=fused, optim=dict(lm_mode=1))
         tr = Trainer(dev(p.copy()), vcams, gts, cfg, E=E, A=A)
-        used = tr.step([0, 1, 2])
+        used = tr.step(list(range(len(views))))
         torch.cuda.synchronize()
         assert np.isfinite(tr.loss_value(used))
         res.append((host(tr.params), host(tr.m), host(tr.v), host(tr.touched).astype(bool)))
@@ -340,7 +340,7 @@ def test_full_size_three_view_step_properties(B, fullstep):
         u = np.abs(a.astype(np.float64) - p) + np.abs(b.astype(np.float64) - p) if a is p1 else \
             np.abs(a.astype(np.float64)) + np.abs(b.astype(np.float64))
         assert (d > 1e-3 * u + 1e-12).mean() < 1e-3
-    assert 0.3 < t1.mean() < 1.0
+    assert 0.3 < t1.mean() <= 1.0 and (len(views) > 3 or t1.mean() < 1.0)
     assert np.array_equal(p1[:, ~t1], p[:, ~t1]) and not m1[:, ~t1].any() and not v1[:, ~t1].any()
     moved = (p1[:, t1] != p[:, t1]).any(axis=0)
     assert moved.mean() > 0.05
