@@ -138,7 +138,8 @@ def _ptr(t) -> int | None:
 
 
 def _stream():
-    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    # the raw handle of the current stream (no Stream object per call)
+    return ctypes.c_void_p(torch._C._cuda_getCurrentRawStream(torch.cuda.current_device()))
 
 
 # ------------------------------------------------------------------ records

@@ -44,9 +44,20 @@
 
 namespace tgs {
 
-__global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+// Zeroes two arrays in one launch: [0, n0) of p0, then [0, n1) of p1.
+__global__ void __launch_bounds__(256) zero2_u32_kernel(uint32_t* __restrict__ p0, int64_t n0,
+                                                        uint32_t* __restrict__ p1, int64_t n1) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  if (i < n0) p0[i] = 0u;
+  else if (i - n0 < n1) p1[i - n0] = 0u;
+}
+
+// Copies the count kernel's partial totals into pinned host memory (mapped
+// into the device's address space), in place of a runtime copy.
+__global__ void __launch_bounds__(256) totals_to_host_kernel(const unsigned long long* __restrict__ slots,
+                                                             unsigned long long* host) {
+  const int i = threadIdx.x;
+  if (i < 2 * TGS_COUNTER_SLOTS) host[i] = slots[i];
 }
 
 // ------------------------------------------------------------------ scans
@@ -884,6 +895,7 @@ using namespace tgs;
 struct Readback {
   int dev = -1;
   unsigned long long* host = nullptr;
+  unsigned long long* mapped = nullptr;  // the device's address of host (null: copy instead)
   hipEvent_t ev = nullptr;
 };
 
@@ -896,10 +908,15 @@ static Readback* readback() {
     if (r.ev != nullptr) (void)hipEventDestroy(r.ev);
     r.ev = nullptr;
     if (r.host == nullptr &&
-        hipHostMalloc((void**)&r.host, sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS, hipHostMallocPortable) !=
-            hipSuccess) {
+        hipHostMalloc((void**)&r.host, sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS,
+                      hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
       r.host = nullptr;
       return nullptr;
+    }
+    r.mapped = nullptr;
+    if (hipHostGetDevicePointer((void**)&r.mapped, r.host, 0) != hipSuccess) {
+      r.mapped = nullptr;            // fall back to a runtime copy
+      (void)hipGetLastError();       // and leave no error behind
     }
     if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) {
       r.ev = nullptr;
@@ -937,10 +954,9 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
   // 2 ln(1/alpha_min) with a 0.1 % margin, rounded up to a multiple of 1/64
   const double tau = std::ceil(128.0 * std::log(1.0 / (double)alpha_min) * 1.001) / 64.0;
 
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t, 256)), dim3(256), 0, s, ranges,
-                     2 * (int64_t)n_t, 0u);
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(w.zeroed_words, 256)), dim3(256), 0, s, w.zeroed,
-                     w.zeroed_words, 0u);
+  // empty ranges and the zeroed workspace region (counters, table padding)
+  hipLaunchKernelGGL(zero2_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t + w.zeroed_words, 256)), dim3(256),
+                     0, s, ranges, 2 * (int64_t)n_t, w.zeroed, w.zeroed_words);
   if (n == 0) {
     *n_pairs = 0;
     return hip_status("tgs_bin_sort");
@@ -953,10 +969,12 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
   // device keeps working while the host reads the totals and sizes the rest.
   Readback* rb = readback();
   if (rb == nullptr) return hip_status("tgs_bin_sort: pinned readback buffer");
-  if (hipMemcpyAsync(rb->host, w.scalars, sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS,
-                     hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipEventRecord(rb->ev, s) != hipSuccess)
+  if (rb->mapped != nullptr)
+    hipLaunchKernelGGL(totals_to_host_kernel, dim3(1), dim3(256), 0, s, w.scalars, rb->mapped);
+  else if (hipMemcpyAsync(rb->host, w.scalars, sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS,
+                          hipMemcpyDeviceToHost, s) != hipSuccess)
     return hip_status("tgs_bin_sort: count readback");
+  if (hipEventRecord(rb->ev, s) != hipSuccess) return hip_status("tgs_bin_sort: count readback");
   // (depth, id) order; Gaussians without pairs last
   sort_depth(w, (uint32_t)n, (const int4*)rect, tiles_x, tiles_y, s);
   exclusive_scan<uint32_t>(w.cnt_sorted, w.off, n, w.partials, s);  // wraps only past capacity (checked below)

@@ -27,6 +27,9 @@ from . import binding as B
 TILE = B.TILE
 
 
+_NO_STAGE = contextlib.nullcontext()  # the stage bracket when a stage is not timed
+
+
 @dataclass
 class StepConfig:
     """What one step samples and how it renders (dense when ``rate_permille`` is None)."""
@@ -174,13 +177,20 @@ class Trainer:
                                     device=self.dev)
         self.events: dict | None = None   # stage name -> [(start, end)] when timing
         self.timed_stages: set | None = None  # stages to time (all when None)
+        # cross-stream events, recorded anew each step (a wait binds to the
+        # record queued before it)
+        self._cleared = torch.cuda.Event()
+        self._sampled = torch.cuda.Event()
+        self._lossed = torch.cuda.Event()
 
-    @contextlib.contextmanager
     def _stage(self, name):
         """Brackets a stage with HIP events on the current stream when timing."""
         if self.events is None or (self.timed_stages is not None and name not in self.timed_stages):
-            yield
-            return
+            return _NO_STAGE
+        return self._timed_stage(name)
+
+    @contextlib.contextmanager
+    def _timed_stage(self, name):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
@@ -215,15 +225,19 @@ class Trainer:
         t = self.step_count
         views = list(views)
         main, side = torch.cuda.current_stream(), self.side
-        self.totals.zero_()
-        self.touched.zero_()
         if not views:
             self.grad.zero_()
         st = self._stage
         used = [self.buffers(slot, self.cams[v]) for slot, v in enumerate(views)]
-        # samplers on the side stream (they see everything queued on main so far)
+        # the step's counters are cleared and the samplers run on the side
+        # stream (which sees everything queued on main so far), beside the
+        # first projection
         side.wait_stream(main)
+        cleared, sampled, lossed = self._cleared, self._sampled, self._lossed
         with torch.cuda.stream(side):
+            self.totals.zero_()
+            self.touched.zero_()
+            cleared.record(side)
             for vb, v in zip(used, views):
                 cam = self.cams[v]
                 if vb.dense:
@@ -232,13 +246,14 @@ class Trainer:
                 else:
                     with st("sample"):
                         vb.sample(self.E[v], self.A[v], self.cfg, t, v, self.totals)
-        sampled = torch.cuda.Event()
         sampled.record(side)
         waited = False
         for k, (vb, v) in enumerate(zip(used, views)):
             cam = self.cams[v]
             with st("project"):
                 vb.project(self.params, cam, self.rp)
+            if k == 0:
+                main.wait_event(cleared)  # touched is cleared
             if not waited and vb.bin_sort_needs_samples():
                 main.wait_event(sampled)
                 waited = True
@@ -252,7 +267,6 @@ class Trainer:
             with st("loss"):
                 vb.loss(self.gts[v], self.totals, self.lp)
             if not vb.dense:
-                lossed = torch.cuda.Event()
                 lossed.record(main)
                 side.wait_event(lossed)
                 with torch.cuda.stream(side):
@@ -270,6 +284,8 @@ class Trainer:
                     B.tgs_project_bwd_optimizer_step(self.params, self.n, cam, self.rp, vb.radius, vb.clamp,
                                                      vb.g2d, self.grad if k > 0 else None, self.m, self.v,
                                                      self.touched, self.op, t, self.fused_ws)
+        if not used:
+            main.wait_event(cleared)
         if not used or not self.cfg.fuse_optimizer:
             with st("optimizer"):
                 B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
