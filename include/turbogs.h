@@ -181,11 +181,12 @@ int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t
  * capacity must hold every listed tile (valid or not) of every Gaussian
  * that has a pair in a valid tile; when it does not, the call returns
  * TGS_ERR_CAPACITY with that count in *n_pairs and the outputs are
- * unspecified.  The host waits once, for the count totals (an event recorded
- * after the first kernel; the depth sort is already queued behind it), to
- * size the pair sort; the call returns with the rest queued on the stream.
- * Uses a small pinned host buffer per host thread and device, kept until
- * the process ends. */
+ * unspecified.  The host waits once, for the count totals (a kernel writes
+ * them into mapped pinned host memory right after the count and an event
+ * follows; the depth sort is already queued behind it), to size the pair
+ * sort; the call returns with the rest queued on the stream.  Uses a small
+ * pinned host buffer per host thread and device, kept until the process
+ * ends. */
 size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32_t n_tiles);
 int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const float* depth, int64_t n,
                      const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
