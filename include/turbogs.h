@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 5u
+#define TGS_ABI_VERSION 6u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
@@ -303,6 +303,47 @@ int32_t tgs_project_bwd_optimizer_step(float* params, int64_t n, const tgs_camer
 int32_t tgs_optimizer_step(float* params, const float* grad, float* m, float* v, int64_t n,
                            const uint8_t* touched, const tgs_optim_params* op, int64_t step,
                            void* stream);
+
+/* ---- Learned tile priority.  Not in the paper: a small network that
+ * predicts the tile error the error-map sampler (Sec. 3.3) would measure,
+ * from cheap per-(view, tile) features, trained online on the tile errors
+ * the method measures; the error-map ranking stays the reference.
+ * Parameter vector (float32, TGS_TILE_MLP_PARAMS): W1[32][64] at 0, b1 at
+ * 2048, W2[64][64] at 2112, b2 at 6208, w3[64] at 6272, b3 at 6336;
+ * y = w3 . gelu(W2^T gelu(W1^T x + b1) + b2) + b3 (GELU in its erf form).
+ * The two 64-wide layers run as bfloat16 MFMA products (x, W1, the first
+ * activation and W2 rounded to nearest even) with float32 sums. */
+#define TGS_TILE_MLP_FEATURES 32
+#define TGS_TILE_MLP_PARAMS 6337
+
+/* Features of every tile of one view, X [tiles_x * tiles_y][32] float
+ * (16-byte aligned), row-major tile order: tile centre x / W, y / H; 16 pose
+ * features of the camera centre c = -R^T t (c / |c|, |c| / 3, then sin and
+ * cos of pi c_j / |c| and of 2 pi c_j / |c| for j = 0, 1, 2); log(1 + pairs
+ * in ranges); the mean of E and log(1 + the mean of A) over the tile's
+ * in-image pixels; zeros.  ranges: tgs_bin_sort output; E, A: [H][W] half
+ * error and uint16 age maps. */
+int32_t tgs_tile_features(const uint32_t* ranges, const uint16_t* E, const uint16_t* A,
+                          int32_t height, int32_t width, const tgs_camera* cam, float* X,
+                          void* stream);
+
+/* Predictions y [n] for feature rows X [n][32] (16-byte aligned).  act:
+ * nullable [n][128] float, 16-byte aligned: the pre-activations of the two
+ * hidden layers, which tgs_tile_mlp_train_step needs. */
+int32_t tgs_tile_mlp_fwd(const float* params, const float* X, int64_t n, float* y, float* act,
+                         void* stream);
+
+/* One online training step: the gradient of mean_i (y_i - target_i)^2 over
+ * the n rows of the last tgs_tile_mlp_fwd (X, act, y), with each bfloat16
+ * rounding taken as the identity, then a bias-corrected Adam step (0.9,
+ * 0.999, 1e-8, learning rate lr) on params with moments m, v [6337] float.
+ * grad: nullable [6337] float, receives the gradient.  ws: workspace of
+ * tgs_tile_mlp_workspace_size(n) bytes.  step >= 1. */
+size_t tgs_tile_mlp_workspace_size(int64_t n);
+int32_t tgs_tile_mlp_train_step(float* params, float* m, float* v, const float* X,
+                                const float* act, const float* y, const float* target, int64_t n,
+                                int64_t step, float lr, float* grad, void* ws, size_t ws_bytes,
+                                void* stream);
 
 #ifdef __cplusplus
 }

@@ -94,6 +94,10 @@ PROTOTYPES = {
     "tgs_project_bwd": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
                                _P, _P, _P, _P, _I32, _P]),
     "tgs_optimizer_step": (_I32, [_P, _P, _P, _P, _I64, _P, ctypes.POINTER(tgs_optim_params), _I64, _P]),
+    "tgs_tile_features": (_I32, [_P, _P, _P, _I32, _I32, ctypes.POINTER(tgs_camera), _P, _P]),
+    "tgs_tile_mlp_fwd": (_I32, [_P, _P, _I64, _P, _P, _P]),
+    "tgs_tile_mlp_workspace_size": (_SZ, [_I64]),
+    "tgs_tile_mlp_train_step": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I64, _I64, ctypes.c_float, _P, _P, _SZ, _P]),
     "tgs_project_bwd_optimizer_workspace_size": (_SZ, [_I64]),
     "tgs_project_bwd_optimizer_step": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera),
                                               ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P,
@@ -295,3 +299,27 @@ def tgs_project_bwd_optimizer_step(params, n, cam: tgs_camera, rp: tgs_raster_pa
                                                 _ptr(m), _ptr(v), _ptr(touched), ctypes.byref(op), step,
                                                 _ptr(ws), ws.numel() * ws.element_size(), _stream()),
            "tgs_project_bwd_optimizer_step")
+
+
+# ------------------------------------------------------------------ learned tile priority
+TILE_MLP_FEATURES = 32
+TILE_MLP_PARAMS = 6337
+
+
+def tgs_tile_features(ranges, E, A, height: int, width: int, cam: tgs_camera, X):
+    _check(lib().tgs_tile_features(_ptr(ranges), _ptr(E), _ptr(A), height, width, ctypes.byref(cam), _ptr(X),
+                                   _stream()), "tgs_tile_features")
+
+
+def tgs_tile_mlp_fwd(params, X, n: int, y, act=None):
+    _check(lib().tgs_tile_mlp_fwd(_ptr(params), _ptr(X), n, _ptr(y), _ptr(act), _stream()), "tgs_tile_mlp_fwd")
+
+
+def tgs_tile_mlp_workspace_size(n: int) -> int:
+    return int(lib().tgs_tile_mlp_workspace_size(n))
+
+
+def tgs_tile_mlp_train_step(params, m, v, X, act, y, target, n: int, step: int, lr: float, ws, grad=None):
+    _check(lib().tgs_tile_mlp_train_step(_ptr(params), _ptr(m), _ptr(v), _ptr(X), _ptr(act), _ptr(y), _ptr(target),
+                                         n, step, float(lr), _ptr(grad), _ptr(ws), ws.numel() * ws.element_size(),
+                                         _stream()), "tgs_tile_mlp_train_step")
