@@ -52,6 +52,11 @@ PSNR_DENSE_STEPS = 500
 PSNR_RATES = (500, 250, 200, 100)
 PSNR_EVAL_EVERY = 25
 PSNR_MAX_STEPS = 4000
+TP_VIEWS = 40        # learned tile priority: training views
+TP_STEPS = 600       # online steps
+TP_EVAL_FROM = 400   # predictions scored from this step on
+TP_LR = 3e-3
+TP_SEED = 23
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_scaling_300k_25pct.txt")
 RASTER_SOURCES = ("paper_2606_15924_amd/csrc/raster.hip", "paper_2606_15924_amd/csrc/common.h")
@@ -237,6 +242,116 @@ def matched_psnr(dev, dense_steps=PSNR_DENSE_STEPS, max_steps=PSNR_MAX_STEPS):
     return res
 
 
+def tile_priority(dev, n_views=TP_VIEWS, steps=TP_STEPS, eval_from=TP_EVAL_FROM):
+    """The learned tile-priority model trained online beside sparse training
+    (25%, one view per step, seeded order) on the 300k-Gaussian recovery
+    task.  Each step: the view's tile features are taken before the step
+    (error and age maps as they were, pair counts of the step's binning), the
+    model predicts each tile's error, the step runs, and the tile means of
+    the updated error map are the targets of one training step.  Predictions
+    made before training on a step are scored against that step's measured
+    tile errors (Kendall tau, recall of the top quarter), next to the plain
+    error-map predictor (the tile means before the step).  Kernel times from
+    HIP events; the forward's FLOP count is 2 x rows x (32x64 + 64x64 + 64)."""
+    import torch
+    from scipy.stats import kendalltau
+
+    import synth
+    from paper_2606_15924_amd import binding as B
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer, ViewBuffers
+    p0 = synth.gaussians(N_GAUSS, synth.SEED_SCENE)
+    p_true = synth.perturb(p0, synth.SEED_PERTURB)
+    cams = synth.hemisphere_cameras(n_views, width=WIDTH, height=HEIGHT, focal=300.0 * WIDTH / 256)
+    rp = B.raster_params()
+    vb = ViewBuffers(N_GAUSS, WIDTH, HEIGHT, None, -1, dev)
+    P_true = torch.from_numpy(p_true).to(dev)
+    gts = []
+    for k, cam in enumerate(cams):
+        vb.project(P_true, B.camera(cam), rp)
+        vb.bin_sort(alpha_min=rp.alpha_min)
+        vb.render_fwd(rp)
+        noise = torch.from_numpy(synth.pixel_noise((3, HEIGHT, WIDTH), synth.SEED_NOISE + k)).to(dev)
+        gts.append((vb.out[: WIDTH * HEIGHT, :3].T.reshape(3, HEIGHT, WIDTH) + noise).contiguous())
+    del P_true, vb
+    E = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in cams]
+    A = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in cams]
+    tr = Trainer(torch.from_numpy(p0).to(dev), cams, gts, StepConfig(rate_permille=250), E=E, A=A)
+    tr.init_error_maps(range(n_views))
+    bcams = [B.camera(c) for c in cams]
+    n_t = ((WIDTH + 15) // 16) * ((HEIGHT + 15) // 16)
+    params = torch.from_numpy(tile_init_params()).to(dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    X = torch.empty((n_t, 32), dtype=torch.float32, device=dev)
+    Xa = torch.empty_like(X)
+    y = torch.empty(n_t, dtype=torch.float32, device=dev)
+    act = torch.empty((n_t, 128), dtype=torch.float32, device=dev)
+    ws = torch.empty(B.tgs_tile_mlp_workspace_size(n_t), dtype=torch.uint8, device=dev)
+    order = np.random.default_rng(synth.SEED_VIEWS).integers(0, n_views, size=steps)
+    k = n_t // 4
+    scores = {"model": [], "error_map": []}
+    for step in range(steps):
+        vi = int(order[step])
+        E0, A0 = E[vi].clone(), A[vi].clone()
+        tr.step([vi])
+        ranges = tr._bufs[0].ranges
+        B.tgs_tile_features(ranges, E0, A0, HEIGHT, WIDTH, bcams[vi], X)
+        B.tgs_tile_features(ranges, E[vi], A[vi], HEIGHT, WIDTH, bcams[vi], Xa)
+        target = Xa[:, 19].contiguous()
+        B.tgs_tile_mlp_fwd(params, X, n_t, y, act)
+        if step >= eval_from:
+            t_h, y_h, e_h = target.cpu().numpy(), y.cpu().numpy(), X[:, 19].cpu().numpy()
+            top = set(np.argsort(-t_h, kind="stable")[:k].tolist())
+            for name, pred in (("model", y_h), ("error_map", e_h)):
+                rec = len(top & set(np.argsort(-pred, kind="stable")[:k].tolist())) / k
+                scores[name].append((kendalltau(pred, t_h).statistic, rec))
+        B.tgs_tile_mlp_train_step(params, m, v, X, act, y, target, n_t, step + 1, TP_LR, ws)
+    torch.cuda.synchronize()
+    del tr
+
+    def timed(fn, reps=50):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    flop_row = 2 * (32 * 64 + 64 * 64 + 64)
+    fwd_ms = timed(lambda: B.tgs_tile_mlp_fwd(params, X, n_t, y, act))
+    nb = 1 << 20
+    Xb = torch.randn((nb, 32), dtype=torch.float32, device=dev)
+    yb = torch.empty(nb, dtype=torch.float32, device=dev)
+    big_ms = timed(lambda: B.tgs_tile_mlp_fwd(params, Xb, nb, yb, None))
+    train_ms = timed(lambda: B.tgs_tile_mlp_train_step(params, m, v, X, act, y, target, n_t, steps + 1, 0.0, ws))
+    feat_ms = timed(lambda: B.tgs_tile_features(ranges, E[0], A[0], HEIGHT, WIDTH, bcams[0], X))
+    res = {"task": f"online beside sparse 25% training, {n_views} views, {steps} steps; "
+                   f"predictions scored before each training step from step {eval_from}",
+           "kendall_tau": {kk: round(float(np.mean([s[0] for s in vv])), 4) for kk, vv in scores.items()},
+           "top_quarter_recall": {kk: round(float(np.mean([s[1] for s in vv])), 4) for kk, vv in scores.items()},
+           "features_ms": round(feat_ms, 4), "train_step_ms": round(train_ms, 4),
+           "fwd_ms": round(fwd_ms, 4), "fwd_rows": n_t,
+           "fwd_roofline": {"bound": "mfma", "rows": nb, "ms": round(big_ms, 4),
+                            "achieved": round(flop_row * nb / (big_ms * 1e-3) / 1e12, 3), "peak": 2500.0,
+                            "unit": "TFLOP/s",
+                            "frac": round(flop_row * nb / (big_ms * 1e-3) / 1e12 / 2500.0, 5)}}
+    return res
+
+
+def tile_init_params():
+    """Seeded initial weights of the tile-priority model: N(0, 1/fan_in)
+    hidden weights, zero biases and output layer (it starts as the error-map
+    predictor)."""
+    import math
+    rng = np.random.default_rng(TP_SEED)
+    p = np.zeros(6337, dtype=np.float32)
+    p[0:2048] = rng.normal(0.0, 1.0 / math.sqrt(32), 2048)
+    p[2112:6208] = rng.normal(0.0, 1.0 / math.sqrt(64), 4096)
+    return p
+
+
 def cpu_baseline(p, cam, gt, target_s=15.0):
     """The oracle's sparse step, timed on one host thread: the parts whose
     cost scales with the sampled tiles (sampling, forward, loss, backward)
@@ -307,6 +422,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the pixel-rate sweep and dense run")
     ap.add_argument("--no-psnr", action="store_true", help="skip the matched-PSNR training comparison")
+    ap.add_argument("--no-tile", action="store_true", help="skip the learned tile-priority measurement")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -371,6 +487,10 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(dom), "launch_ms": round(head["dominant_ms"], 4)}
 
+    tile = None
+    if not args.no_tile:
+        log("learned tile priority")
+        tile = tile_priority(dev)
     psnr = None
     if not args.no_psnr:
         psnr = matched_psnr(dev)
@@ -411,6 +531,7 @@ def main():
         "sweep": sweep or None,
         "roofline": roofline,
         "matched_psnr": psnr,
+        "tile_priority": tile,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -310,7 +310,9 @@ int32_t tgs_optimizer_step(float* params, const float* grad, float* m, float* v,
  * the method measures; the error-map ranking stays the reference.
  * Parameter vector (float32, TGS_TILE_MLP_PARAMS): W1[32][64] at 0, b1 at
  * 2048, W2[64][64] at 2112, b2 at 6208, w3[64] at 6272, b3 at 6336;
- * y = w3 . gelu(W2^T gelu(W1^T x + b1) + b2) + b3 (GELU in its erf form).
+ * y = x_19 + w3 . gelu(W2^T gelu(W1^T x + b1) + b2) + b3 (GELU in its erf
+ * form; x_19, the tile's mean error when its map was written, makes the
+ * network predict the change since then).
  * The two 64-wide layers run as bfloat16 MFMA products (x, W1, the first
  * activation and W2 rounded to nearest even) with float32 sums. */
 #define TGS_TILE_MLP_FEATURES 32

@@ -18,8 +18,11 @@ Readings (none of this is fixed by the paper):
   - 19: mean of E over the tile's in-image pixels;
   - 20: log(1 + mean of A over the same pixels);
   - 21-31: zero.
-* model: y = w3 . g(W2^T g(W1^T x + b1) + b2) + b3, g(z) = z Phi(z) (GELU,
-  erf form), widths 32 -> 64 -> 64 -> 1.
+* model: y = x_19 + w3 . g(W2^T g(W1^T x + b1) + b2) + b3, g(z) = z Phi(z)
+  (GELU, erf form), widths 32 -> 64 -> 64 -> 1: the network predicts the
+  change of the tile's error since its error map was written, so with w3
+  and b3 at zero (the initial state) it is exactly the error-map predictor
+  and training refines it.
 * precision: the two 64-wide layers take bfloat16 operands (x, W1, the
   first activation h1, W2; round to nearest even) with sums in float32;
   biases, GELU and the last layer are float32.  The oracle applies the same
@@ -74,12 +77,12 @@ def unpack(p):
 
 
 def init_params(seed: int) -> np.ndarray:
-    """Seeded initial weights: N(0, 1/fan_in) entries, zero biases."""
+    """Seeded initial weights: N(0, 1/fan_in) hidden weights, zero biases
+    and a zero output layer (the model starts as the error-map predictor)."""
     rng = np.random.default_rng(seed)
     p = np.zeros(N_PARAMS, dtype=np.float32)
     p[OFF_W1:OFF_B1] = rng.normal(0.0, 1.0 / math.sqrt(N_FEAT), N_FEAT * HID)
     p[OFF_W2:OFF_B2] = rng.normal(0.0, 1.0 / math.sqrt(HID), HID * HID)
-    p[OFF_W3:OFF_B3] = rng.normal(0.0, 1.0 / math.sqrt(HID), HID)
     return p
 
 
@@ -131,7 +134,7 @@ def forward(p, X, rounding: bool = True) -> dict:
     h1b = rnd(h1)
     z2 = h1b @ W2b + q["b2"]
     h2 = gelu(z2)
-    y = h2 @ q["w3"] + q["b3"][0]
+    y = X[:, 19] + (h2 @ q["w3"] + q["b3"][0])
     return dict(y=y, z1=z1, h1b=h1b, z2=z2, h2=h2, xb=xb, W2b=W2b)
 
 

@@ -1,5 +1,7 @@
 // Learned tile priority: per-(view, tile) features, a 32 -> 64 -> 64 -> 1
-// GELU network evaluated with bfloat16 MFMA (float32 sums), and its online
+// GELU network (added to the tile's stale mean error, feature 19: it
+// predicts the change since the error map was written) evaluated with
+// bfloat16 MFMA (float32 sums), and its online
 // training step (exact gradient of the mean squared error against the
 // measured tile errors, Adam on float32 master weights).  The model is not
 // part of the paper; it ranks tiles by the error the sampler of Sec. 3.3
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(kMlpBlock) tile_mlp_fwd_kernel(const float* __
   // the four lanes of a row (l, l + 16, l + 32, l + 48) hold its 64 products
   part += __shfl_xor(part, 16, kWave);
   part += __shfl_xor(part, 32, kWave);
-  if (lane < 16 && live) y[row] = part + p[kOffB3];
+  if (lane < 16 && live) y[row] = X[row * kFeat + 19] + (part + p[kOffB3]);
 }
 
 // Gradient of mean (y - target)^2 over n rows, per chunk of rows: the

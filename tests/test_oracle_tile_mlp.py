@@ -37,6 +37,7 @@ def _problem(n=40, seed=3):
     p = T.init_params(seed).astype(np.float64)
     p[T.OFF_B1:T.OFF_W2] = rng.normal(0, 0.1, T.HID)
     p[T.OFF_B2:T.OFF_W3] = rng.normal(0, 0.1, T.HID)
+    p[T.OFF_W3:T.OFF_B3] = rng.normal(0, 0.125, T.HID)   # the initial output layer is zero
     p[T.OFF_B3] = 0.2
     t = rng.uniform(0, 1, n)
     return p, X, t
@@ -59,7 +60,8 @@ def test_gradient_equals_finite_differences_without_rounding():
 
 
 def test_forward_of_a_single_unit_closed_form():
-    """Only x0 -> unit 0 -> unit 0 -> output: y = w3 g(W2 g(W1 x + b1) + b2) + b3."""
+    """Only x0 -> unit 0 -> unit 0 -> output, plus the stale error x19:
+    y = x19 + w3 g(W2 g(W1 x + b1) + b2) + b3."""
     p = np.zeros(T.N_PARAMS)
     p[T.OFF_W1 + 0 * T.HID + 0] = 0.5
     p[T.OFF_B1] = 0.25
@@ -69,14 +71,17 @@ def test_forward_of_a_single_unit_closed_form():
     p[T.OFF_B3] = 0.125
     X = np.zeros((3, T.N_FEAT))
     X[:, 0] = [0.0, 1.0, -2.0]   # all exact in bfloat16
+    X[:, 19] = [0.5, -0.25, 0.0]
     Phi = lambda z: 0.5 * (1 + math.erf(z / math.sqrt(2)))
     for r in range(3):
         h1 = (0.5 * X[r, 0] + 0.25) * Phi(0.5 * X[r, 0] + 0.25)
         h1b = T.bf16(np.array([h1]))[0]
         z2 = 2.0 * h1b - 0.5
         # the other 63 units of each layer give g(0) = 0, and layer 2 sees their 0
-        y = 3.0 * z2 * Phi(z2) + 0.125
+        y = X[r, 19] + (3.0 * z2 * Phi(z2) + 0.125)
         assert abs(T.forward(p, X)["y"][r] - y) < 1e-15
+    # the initial parameters give the stale error itself
+    assert np.array_equal(T.forward(T.init_params(1), X)["y"], X[:, 19])
 
 
 def test_adam_equals_torch_adam():
