@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 6u
+#define TGS_ABI_VERSION 7u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
@@ -142,6 +142,10 @@ int32_t tgs_project(const float* params, int64_t n, const tgs_camera* cam,
 /* Tile-wise error/age pixel sampling (Sec. 3.5, Eq. pix_prob_err and
  * Eq. pix_topk_age, plus the mixed remainder of the hyper-parameter table).
  *   E, A        [H][W] uint16: half-precision error bits, age (read)
+ *   tile_pred   nullable [tiles_x * tiles_y] float: predicted mean tile
+ *               errors (tgs_tile_mlp_fwd); when given, the tile pass draws
+ *               in proportion to floor(clamp(p, 0, 65504) * in-image pixels
+ *               * 2^24) instead of the error-map sums (same units)
  *   valid_tiles [n_st] int32, tile_off [n_st + 1] int32 (written)
  *   pix         [n_st * n_pix] uint8 capacity (written up to tile_off[n_st])
  *   tile_slot   [tiles_x * tiles_y] int32: slot of each tile or -1 (written)
@@ -152,8 +156,8 @@ int32_t tgs_project(const float* params, int64_t n, const tgs_camera* cam,
  * tile, slot). */
 size_t tgs_sample_workspace_size(int32_t height, int32_t width);
 int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
-                   const tgs_sample_params* sp, int32_t* valid_tiles, int32_t* tile_off,
-                   uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
+                   const tgs_sample_params* sp, const float* tile_pred, int32_t* valid_tiles,
+                   int32_t* tile_off, uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
                    size_t ws_bytes, void* stream);
 
 /* Tile x depth binning, sort and per-tile ranges (the depth-ordered

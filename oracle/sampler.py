@@ -58,15 +58,38 @@ def _pick_weighted(weights, u):
     return int(np.searchsorted(csum, r, side="right"))
 
 
+PRED_MAX = 65504.0   # predictions are clamped to the largest finite half, like E
+
+
+def predicted_tile_weights(pred, TX: int, TY: int, W: int, H: int) -> np.ndarray:
+    """Integer tile weights from predicted mean tile errors (a reading for the
+    learned tile priority): floor(clamp(p, 0, 65504) * in-image pixels * 2^24)
+    with p the float32 prediction, the units of the error-map sums (mean E
+    times the pixel count).  Exact in FP64: a float32 times a count up to 256
+    times a power of two."""
+    tw = np.zeros(TX * TY, dtype=np.int64)
+    for t in range(TX * TY):
+        _, x, _ = tile_pixels(t, TX, W, H)
+        p = float(np.float32(pred[t]))
+        p = min(p, PRED_MAX) if p > 0.0 else 0.0      # NaN and negatives give 0
+        tw[t] = int(np.floor(p * x.size * float(1 << 24)))
+    return tw
+
+
 def select_tiles(w: np.ndarray, TX: int, TY: int, W: int, H: int, n_sel: int,
-                 seed: int, step: int, view: int) -> np.ndarray:
+                 seed: int, step: int, view: int, tile_pred=None) -> np.ndarray:
+    """Tiles drawn without replacement with probability proportional to their
+    error-map sums (or to the predicted errors when tile_pred is given)."""
     n_t = TX * TY
     if n_sel < 0 or n_sel >= n_t:
         return np.arange(n_t, dtype=np.int64)
-    tw = np.zeros(n_t, dtype=np.int64)
-    for t in range(n_t):
-        _, x, y = tile_pixels(t, TX, W, H)
-        tw[t] = int(w[y, x].sum())
+    if tile_pred is not None:
+        tw = predicted_tile_weights(tile_pred, TX, TY, W, H)
+    else:
+        tw = np.zeros(n_t, dtype=np.int64)
+        for t in range(n_t):
+            _, x, y = tile_pixels(t, TX, W, H)
+            tw[t] = int(w[y, x].sum())
     remaining = np.ones(n_t, dtype=bool)
     chosen = []
     for j in range(n_sel):
@@ -119,20 +142,21 @@ def sample_tile(w: np.ndarray, A: np.ndarray, tile: int, TX: int, W: int, H: int
 
 
 def sample_view(E_bits: np.ndarray, A: np.ndarray, sp: SampleParams, seed: int, step: int,
-                view: int, tiles_subset=None) -> dict:
+                view: int, tiles_subset=None, tile_pred=None) -> dict:
     """Sparse sample set of one view.
 
     Returns valid_tiles [n_st] (ascending tile ids), tile_off [n_st + 1],
     pix [P] (uint8 local indices, ascending within each tile) and the per-tile
     hard/stable/mixed sets.  ``tiles_subset`` restricts the per-tile pass to
     some of the selected tiles (for sampled checks at full size); offsets then
-    cover only those tiles.
+    cover only those tiles.  ``tile_pred`` (per tile, optional) replaces the
+    error-map sums in the tile pass by predicted tile errors.
     """
     H, W = E_bits.shape
     TX, TY = (W + TILE - 1) // TILE, (H + TILE - 1) // TILE
     w = half_weights(E_bits)
     A = np.asarray(A)
-    tiles = select_tiles(w, TX, TY, W, H, sp.n_tiles_sel, seed, step, view)
+    tiles = select_tiles(w, TX, TY, W, H, sp.n_tiles_sel, seed, step, view, tile_pred)
     if tiles_subset is not None:
         keep = set(int(s) for s in tiles_subset)
         tiles = np.array([t for t in tiles if int(t) in keep], dtype=np.int64)

@@ -77,7 +77,7 @@ PROTOTYPES = {
     "tgs_project": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
                            _P, _P, _P, _P, _P, _P, _P]),
     "tgs_sample_workspace_size": (_SZ, [_I32, _I32]),
-    "tgs_sample": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(tgs_sample_params), _P, _P, _P, _P, _P,
+    "tgs_sample": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(tgs_sample_params), _P, _P, _P, _P, _P, _P,
                           _P, _SZ, _P]),
     "tgs_bin_sort_workspace_size": (_SZ, [_I64, _I64, _I32]),
     "tgs_bin_sort": (_I32, [_P, _P, _P, _I64, _P, _I32, _I32, ctypes.c_float, _P, _P, _I64, _P, _P,
@@ -218,8 +218,8 @@ def tgs_sample_workspace_size(height: int, width: int) -> int:
 
 
 def tgs_sample(E, A, height, width, sp: tgs_sample_params, valid_tiles, tile_off, pix, tile_slot,
-               totals, ws):
-    _check(lib().tgs_sample(_ptr(E), _ptr(A), height, width, ctypes.byref(sp), _ptr(valid_tiles),
+               totals, ws, tile_pred=None):
+    _check(lib().tgs_sample(_ptr(E), _ptr(A), height, width, ctypes.byref(sp), _ptr(tile_pred), _ptr(valid_tiles),
                             _ptr(tile_off), _ptr(pix), _ptr(tile_slot), _ptr(totals), _ptr(ws),
                             ws.numel() * ws.element_size(), _stream()), "tgs_sample")
 

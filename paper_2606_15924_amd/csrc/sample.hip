@@ -75,6 +75,20 @@ __global__ void __launch_bounds__(64) tile_weights_kernel(const uint16_t* __rest
   if (lane == 63) tw[t] = s;
 }
 
+// Tile weights from predicted mean tile errors: floor(clamp(p, 0, 65504) *
+// in-image pixels * 2^24), the units of the error-map sums; exact in FP64 (a
+// float times a count up to 256 times a power of two).
+__global__ void __launch_bounds__(256) tile_pred_weights_kernel(const float* __restrict__ pred, int H, int W,
+                                                               int tiles_x, int n_t, uint64_t* __restrict__ tw) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_t) return;
+  const int tx = t % tiles_x, ty = t / tiles_x;
+  const int nx = min(kTile, W - tx * kTile), ny = min(kTile, H - ty * kTile);
+  const float p = pred[t];
+  const double q = p > 0.f ? (double)fminf(p, 65504.f) : 0.0;  // NaN and negatives give 0
+  tw[t] = (uint64_t)floor(q * (double)(nx * ny) * 16777216.0);
+}
+
 // ------------------------------------------------------------------ tile select
 // One workgroup.  The sequential tile draws (only when a subset of tiles is
 // drawn) run on the first wave, whose lane l owns tiles [l * chunk,
@@ -326,8 +340,8 @@ extern "C" size_t tgs_sample_workspace_size(int32_t height, int32_t width) {
 }
 
 extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
-                              const tgs_sample_params* sp, int32_t* valid_tiles, int32_t* tile_off,
-                              uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
+                              const tgs_sample_params* sp, const float* tile_pred, int32_t* valid_tiles,
+                              int32_t* tile_off, uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
                               size_t ws_bytes, void* stream) {
   TGS_REQUIRE(height > 0 && width > 0, "tgs_sample: bad image size %d x %d", width, height);
   TGS_REQUIRE(sp != nullptr, "tgs_sample: null params");
@@ -349,7 +363,10 @@ extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t heig
   uint8_t* chosen = (uint8_t*)ws + align_up((size_t)n_t * sizeof(uint64_t), 256);
   hipStream_t s = as_stream(stream);
   const bool all_tiles = sp->n_tiles_sel < 0 || sp->n_tiles_sel >= n_t;
-  if (!all_tiles)
+  if (!all_tiles && tile_pred != nullptr)
+    hipLaunchKernelGGL(tile_pred_weights_kernel, dim3((unsigned)ceil_div(n_t, 256)), dim3(256), 0, s, tile_pred,
+                       height, width, tiles_x, n_t, tw);
+  else if (!all_tiles)
     hipLaunchKernelGGL(tile_weights_kernel, dim3(n_t), dim3(64), 0, s, E, height, width, tiles_x,
                        n_t, tw);
   hipLaunchKernelGGL(tile_select_kernel, dim3(1), dim3(kSelectThreads), 0, s, tw, height, width,

@@ -40,6 +40,9 @@ class StepConfig:
     beta: float = 0.4
     seed: int = 3
     fuse_optimizer: bool = True   # last view's projection backward fused with the update
+    learned_tiles: bool = False   # tile pass by the learned tile priority (with n_tiles_sel > 0)
+    tile_lr: float = 3e-3         # its online Adam learning rate
+    tile_seed: int = 23           # its initial weights
     raster: dict = field(default_factory=dict)
     loss: dict = field(default_factory=dict)
     optim: dict = field(default_factory=dict)
@@ -98,11 +101,11 @@ class ViewBuffers:
                                    dtype=torch.uint8, device=dev)
 
     # ---- the steps of one view
-    def sample(self, E, A, cfg: StepConfig, step: int, view: int, totals):
+    def sample(self, E, A, cfg: StepConfig, step: int, view: int, totals, tile_pred=None):
         sp = B.sample_params(self.n_pix, cfg.hard_permille, cfg.stable_permille, cfg.n_tiles_sel,
                              cfg.seed, step, view)
         B.tgs_sample(E, A, self.height, self.width, sp, self.valid_tiles, self.tile_off, self.pix,
-                     self.tile_slot, totals, self.sample_ws)
+                     self.tile_slot, totals, self.sample_ws, tile_pred=tile_pred)
 
     def project(self, params, cam: B.tgs_camera, rp):
         # also clears the screen-space gradient that the backward accumulates into
@@ -149,6 +152,62 @@ class ViewBuffers:
         B.tgs_project_bwd(params, self.n, cam, rp, self.radius, self.clamp, self.g2d, grad, accumulate)
 
 
+def init_tile_params(seed: int) -> torch.Tensor:
+    """Initial weights of the learned tile priority: N(0, 1/fan_in) hidden
+    weights, zero biases and a zero output layer, so the model starts as the
+    error-map predictor (it adds to the tile's stale mean error)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    p = np.zeros(B.TILE_MLP_PARAMS, dtype=np.float32)
+    p[0:2048] = rng.normal(0.0, 1.0 / np.sqrt(32.0), 2048)
+    p[2112:6208] = rng.normal(0.0, 1.0 / np.sqrt(64.0), 4096)
+    return torch.from_numpy(p)
+
+
+class TilePriority:
+    """The learned tile priority of one training run: model, Adam state, the
+    pair ranges each view had at its last binning, and per-slot scratch."""
+
+    def __init__(self, n_views: int, n_t: int, cfg: StepConfig, dev):
+        self.params = init_tile_params(cfg.tile_seed).to(dev)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.lr = cfg.tile_lr
+        self.steps = 0
+        self.n_t = n_t
+        self.ranges = torch.zeros((n_views, n_t, 2), dtype=torch.int32, device=dev)
+        self.ws = torch.empty(B.tgs_tile_mlp_workspace_size(n_t), dtype=torch.uint8, device=dev)
+        self._slots: dict = {}
+
+    def slot(self, k: int) -> dict:
+        if k not in self._slots:
+            d = self.params.device
+            self._slots[k] = dict(X=torch.empty((self.n_t, 32), dtype=torch.float32, device=d),
+                                  Xa=torch.empty((self.n_t, 32), dtype=torch.float32, device=d),
+                                  y=torch.empty(self.n_t, dtype=torch.float32, device=d),
+                                  t=torch.empty(self.n_t, dtype=torch.float32, device=d),
+                                  act=torch.empty((self.n_t, 128), dtype=torch.float32, device=d))
+        return self._slots[k]
+
+    def predict(self, k, v, E, A, vb, cam):
+        """Features from the view's maps and its last pair ranges; predictions."""
+        s = self.slot(k)
+        B.tgs_tile_features(self.ranges[v], E, A, vb.height, vb.width, cam, s["X"])
+        B.tgs_tile_mlp_fwd(self.params, s["X"], self.n_t, s["y"], s["act"])
+        return s["y"]
+
+    def learn(self, k, v, E, A, vb, cam):
+        """One training step towards the tile means of the updated error map;
+        the view's pair ranges are kept for its next prediction."""
+        s = self.slot(k)
+        B.tgs_tile_features(vb.ranges, E, A, vb.height, vb.width, cam, s["Xa"])
+        s["t"].copy_(s["Xa"][:, 19])
+        self.steps += 1
+        B.tgs_tile_mlp_train_step(self.params, self.m, self.v, s["X"], s["act"], s["y"], s["t"], self.n_t,
+                                  self.steps, self.lr, self.ws)
+        self.ranges[v].copy_(vb.ranges)
+
+
 class Trainer:
     """Gaussians, optimizer state and per-view buffers for sparse (or dense)
     training steps over a fixed set of cameras."""
@@ -177,6 +236,12 @@ class Trainer:
                                     device=self.dev)
         self.events: dict | None = None   # stage name -> [(start, end)] when timing
         self.timed_stages: set | None = None  # stages to time (all when None)
+        self.tiles: TilePriority | None = None
+        if cfg.learned_tiles and cfg.rate_permille is not None and cfg.n_tiles_sel > 0:
+            c0 = self.cams[0]
+            n_t = ((c0.width + TILE - 1) // TILE) * ((c0.height + TILE - 1) // TILE)
+            assert all(c.width == c0.width and c.height == c0.height for c in self.cams), "one image size"
+            self.tiles = TilePriority(len(self.cams), n_t, cfg, self.dev)
         # cross-stream events, recorded anew each step (a wait binds to the
         # record queued before it)
         self._cleared = torch.cuda.Event()
@@ -229,6 +294,7 @@ class Trainer:
             self.grad.zero_()
         st = self._stage
         used = [self.buffers(slot, self.cams[v]) for slot, v in enumerate(views)]
+        slot_of = {id(vb): k for k, vb in enumerate(used)}
         # the step's counters are cleared and the samplers run on the side
         # stream (which sees everything queued on main so far), beside the
         # first projection
@@ -244,8 +310,11 @@ class Trainer:
                     self.totals[0] += cam.width * cam.height
                     self.totals[1] += vb.n_t
                 else:
+                    pred = None
+                    if self.tiles is not None:
+                        pred = self.tiles.predict(slot_of[id(vb)], v, self.E[v], self.A[v], vb, cam)
                     with st("sample"):
-                        vb.sample(self.E[v], self.A[v], self.cfg, t, v, self.totals)
+                        vb.sample(self.E[v], self.A[v], self.cfg, t, v, self.totals, tile_pred=pred)
         sampled.record(side)
         waited = False
         for k, (vb, v) in enumerate(zip(used, views)):
@@ -272,6 +341,8 @@ class Trainer:
                 with torch.cuda.stream(side):
                     with st("ema_age"):
                         vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
+                    if self.tiles is not None:
+                        self.tiles.learn(k, v, self.E[v], self.A[v], vb, cam)
             with st("render_bwd"):
                 vb.render_bwd(self.rp, zero=False)  # g2d was cleared by the projection
             if k + 1 < len(used) or not self.cfg.fuse_optimizer:

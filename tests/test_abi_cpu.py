@@ -36,7 +36,7 @@ def test_header_symbols_exported(B):
 
 
 def test_version_and_counts(B):
-    assert B.tgs_version() == 6
+    assert B.tgs_version() == 7
     for r in (1, 100, 150, 200, 250, 500, 1000):
         assert B.tgs_pixels_per_tile(r) == pixels_per_tile(r)
     sp = B.sample_params(64, n_tiles_sel=64)
@@ -83,11 +83,11 @@ def test_invalid_arguments_are_rejected_before_any_launch(B):
     assert st == B.TGS_ERR_INVALID and "tile grid" in lib.tgs_last_error().decode()
     # sampler: n_pix out of range, then too-small workspace
     sp = B.sample_params(300)
-    st = lib.tgs_sample(ctypes.c_void_p(16), ctypes.c_void_p(16), 48, 64, ctypes.byref(sp),
+    st = lib.tgs_sample(ctypes.c_void_p(16), ctypes.c_void_p(16), 48, 64, ctypes.byref(sp), None,
                         *([ctypes.c_void_p(16)] * 6), 1 << 20, None)
     assert st == B.TGS_ERR_INVALID and "n_pix" in lib.tgs_last_error().decode()
     sp = B.sample_params(64)
-    st = lib.tgs_sample(ctypes.c_void_p(16), ctypes.c_void_p(16), 48, 64, ctypes.byref(sp),
+    st = lib.tgs_sample(ctypes.c_void_p(16), ctypes.c_void_p(16), 48, 64, ctypes.byref(sp), None,
                         *([ctypes.c_void_p(16)] * 6), 8, None)
     assert st == B.TGS_ERR_INVALID and "workspace" in lib.tgs_last_error().decode()
     # optimizer: step 0 and bad mode

@@ -136,14 +136,22 @@ def test_bin_sort_bit_exact(B, case):
 
 
 # ------------------------------------------------------------------ sampler
-@pytest.mark.parametrize("W,H,n_pix,n_sel,zero", [(256, 256, 64, 64, 0.1), (150, 107, 25, -1, 0.3),
-                                                   (150, 107, 256, -1, 0.0), (96, 80, 51, 7, 1.0),
-                                                   (1296, 840, 64, -1, 0.1)])
-def test_sampler_bit_exact(B, W, H, n_pix, n_sel, zero):
+@pytest.mark.parametrize("W,H,n_pix,n_sel,zero,pred", [(256, 256, 64, 64, 0.1, False), (150, 107, 25, -1, 0.3, False),
+                                                        (150, 107, 256, -1, 0.0, False), (96, 80, 51, 7, 1.0, False),
+                                                        (1296, 840, 64, -1, 0.1, False), (256, 256, 64, 64, 0.1, True),
+                                                        (150, 107, 25, 20, 0.3, True)])
+def test_sampler_bit_exact(B, W, H, n_pix, n_sel, zero, pred):
+    """pred: the tile pass draws by predicted tile errors (negative, NaN and
+    out-of-range predictions included)."""
     E = synth.error_map(H, W, 31, zero_frac=zero)
     A = synth.age_map(H, W, 32)
     seed, step, view = 3, 5, 2
     sp = SampleParams(n_pix=n_pix, n_tiles_sel=n_sel)
+    tile_pred = None
+    if pred:
+        nt = ((W + 15) // 16) * ((H + 15) // 16)
+        tile_pred = np.random.default_rng(33).normal(0.2, 0.2, nt).astype(np.float32)
+        tile_pred[:3] = [np.nan, 1e30, -1.0]
     bsp = B.sample_params(n_pix, n_tiles_sel=n_sel, seed=seed, step=step, view=view)
     n_st = B.tgs_sample_tile_count(H, W, bsp)
     TX, TY = (W + 15) // 16, (H + 15) // 16
@@ -153,14 +161,15 @@ def test_sampler_bit_exact(B, W, H, n_pix, n_sel, zero):
     slot = torch.empty(TX * TY, dtype=torch.int32, device="cuda")
     totals = torch.zeros(2, dtype=torch.int64, device="cuda")
     ws = torch.empty(B.tgs_sample_workspace_size(H, W), dtype=torch.uint8, device="cuda")
-    B.tgs_sample(dev(E), dev(A), H, W, bsp, vt, off, pix, slot, totals, ws)
+    B.tgs_sample(dev(E), dev(A), H, W, bsp, vt, off, pix, slot, totals, ws,
+                 tile_pred=None if tile_pred is None else dev(tile_pred))
     g_vt, g_off, g_pix, g_slot, g_tot = host(vt), host(off), host(pix), host(slot), host(totals)
     subset = None
     if W * H > 200000:   # full-size view: the oracle checks a subset of tiles
         rng = np.random.default_rng(0)
         subset = np.unique(np.concatenate([rng.choice(TX * TY, 120, replace=False),
                                            np.arange(TX * TY - TX, TX * TY), np.arange(TX - 1, TX * TY, TX)]))
-    ref = sampler.sample_view(E, A, sp, seed, step, view, tiles_subset=subset)
+    ref = sampler.sample_view(E, A, sp, seed, step, view, tiles_subset=subset, tile_pred=tile_pred)
     if subset is None:
         assert np.array_equal(g_vt, ref["valid_tiles"])
         assert np.array_equal(g_off, ref["tile_off"])

@@ -147,3 +147,31 @@ def test_online_training_fits_a_tile_error_field(B):
             losses.append(float(((y - td) ** 2).mean()))
         B.tgs_tile_mlp_train_step(P, M, V, Xd, act, y, td, n, step, 3e-3, ws)
     assert np.isfinite(losses).all() and losses[1] < 0.2 * losses[0], losses
+
+
+def test_trainer_tile_pass_uses_the_learned_priority(B):
+    """A training step with the learned tile priority: the tiles drawn are
+    those the oracle sampler draws from the model's predictions; at the first
+    step the zero output layer makes them the tile means of the error map;
+    the step trains the model."""
+    from oracle import sampler
+    from oracle.params import SampleParams
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer, init_tile_params
+    from support import scene_c1
+    p, cams = scene_c1()
+    H, W = cams[0].height, cams[0].width
+    gts = [dev(synth.image(H, W, 70 + k)) for k in range(len(cams))]
+    E = [synth.error_map(H, W, 80 + k) for k in range(len(cams))]
+    A = [synth.age_map(H, W, 90 + k) for k in range(len(cams))]
+    Eg = [dev(e.view(np.int16)) for e in E]
+    Ag = [dev(a.view(np.int16)) for a in A]
+    cfg = StepConfig(rate_permille=250, n_tiles_sel=64, learned_tiles=True)
+    tr = Trainer(dev(p), cams, gts, cfg, E=Eg, A=Ag)
+    used = tr.step([2])
+    y = host(tr.tiles.slot(0)["y"])
+    ref = sampler.sample_view(E[2], A[2], SampleParams(n_pix=64, n_tiles_sel=64), cfg.seed, 1, 2, tile_pred=y)
+    assert np.array_equal(host(used[0].valid_tiles), ref["valid_tiles"])
+    X = T.tile_features(np.zeros((y.size, 2)), E[2], A[2], H, W, project.camera_center(cams[2]))
+    assert np.allclose(y, X[:, 19], rtol=1e-6, atol=1e-7)
+    assert not torch.equal(tr.tiles.params.cpu(), init_tile_params(cfg.tile_seed))
+    assert np.array_equal(host(tr.tiles.ranges[2]), host(used[0].ranges))

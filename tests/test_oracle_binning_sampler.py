@@ -250,3 +250,25 @@ def test_tile_pass_prefers_high_error_tiles():
         s = sampler.sample_view(E.view(np.uint16), A, SampleParams(n_pix=8, n_tiles_sel=2), seed, 0, 0)
         hits += 0 in s["valid_tiles"].tolist()
     assert hits > 190
+
+
+def test_predicted_tile_weights_and_selection():
+    """Predicted tile errors: weights floor(clamp(p, 0, 65504) * pixels * 2^24)
+    (partial edge tiles count their in-image pixels); when exactly k tiles
+    have a positive prediction, a pass drawing k tiles takes exactly them."""
+    W, H = 40, 37
+    TX, TY = 3, 3
+    pred = np.array([0.5, -1.0, np.nan, 1e30, 0.25, 0.0, 2.0 ** -20, 1.0, 0.125], dtype=np.float32)
+    tw = sampler.predicted_tile_weights(pred, TX, TY, W, H)
+    px = [16 * 16, 16 * 16, 16 * 8, 16 * 16, 16 * 16, 16 * 8, 5 * 16, 5 * 16, 5 * 8]
+    want = [int(0.5 * px[0] * 2 ** 24), 0, 0, int(65504 * px[3] * 2 ** 24), int(0.25 * px[4] * 2 ** 24), 0,
+            int(2.0 ** -20 * px[6] * 2 ** 24), int(1.0 * px[7] * 2 ** 24), int(0.125 * px[8] * 2 ** 24)]
+    assert tw.tolist() == want
+    E = synth.error_map(H, W, 5)
+    A = synth.age_map(H, W, 6)
+    hot = np.zeros(TX * TY, dtype=np.float32)
+    hot[[1, 4, 8]] = [0.3, 0.01, 2.0]
+    for seed in range(5):
+        s = sampler.sample_view(E, A, SampleParams(n_pix=16, n_tiles_sel=3), seed, 1, 0, tile_pred=hot)
+        assert s["valid_tiles"].tolist() == [1, 4, 8]
+
