@@ -198,8 +198,8 @@ def matched_psnr(dev, dense_steps=PSNR_DENSE_STEPS, max_steps=PSNR_MAX_STEPS):
 
     order = np.random.default_rng(synth.SEED_VIEWS).integers(0, len(train), size=max_steps)
 
-    def run(rate, target_psnr, n_max):
-        cfg = StepConfig(rate_permille=rate)
+    def run(rate, target_psnr, n_max, n_tiles_sel=-1, learned=False):
+        cfg = StepConfig(rate_permille=rate, n_tiles_sel=n_tiles_sel, learned_tiles=learned)
         E = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in train]
         A = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in train]
         tr = Trainer(torch.from_numpy(p0).to(dev), [cams[i] for i in train], [gts[i] for i in train], cfg,
@@ -236,6 +236,18 @@ def matched_psnr(dev, dense_steps=PSNR_DENSE_STEPS, max_steps=PSNR_MAX_STEPS):
         cv = run(r, target, max_steps)
         hit = cv[-1][2] >= target
         res["sparse"][f"{r / 10:g}%"] = {
+            "steps_to_match": cv[-1][0] if hit else None, "train_s": round(cv[-1][1], 4),
+            "psnr": round(cv[-1][2], 3), "ms_per_step": round(1e3 * cv[-1][1] / cv[-1][0], 4),
+            "time_speedup_vs_dense": round(dense[-1][1] / cv[-1][1], 3) if hit else None}
+    # a quarter of the tiles per step (64 samples each), drawn by the error-map
+    # tile sums or by the learned tile priority
+    n_t = ((WIDTH + 15) // 16) * ((HEIGHT + 15) // 16)
+    res["quarter_tiles"] = {}
+    for name, learned in (("error_map", False), ("learned", True)):
+        log(f"matched PSNR: 25% of tiles, {name} tile pass")
+        cv = run(250, target, max_steps, n_tiles_sel=n_t // 4, learned=learned)
+        hit = cv[-1][2] >= target
+        res["quarter_tiles"][name] = {
             "steps_to_match": cv[-1][0] if hit else None, "train_s": round(cv[-1][1], 4),
             "psnr": round(cv[-1][2], 3), "ms_per_step": round(1e3 * cv[-1][1] / cv[-1][0], 4),
             "time_speedup_vs_dense": round(dense[-1][1] / cv[-1][1], 3) if hit else None}

@@ -95,15 +95,97 @@ __global__ void __launch_bounds__(256) tile_pred_weights_kernel(const float* __r
 // (l + 1) * chunk); then the whole workgroup lists the chosen tiles in
 // ascending order with their sample counts and prefix offsets.
 constexpr int kSelectThreads = 1024;
+constexpr int kSelectLdsTiles = 7168;  // up to this many tiles the draws run on LDS copies (9 B per tile)
+
+// The draws with the weights and chosen flags in LDS (first wave only).  The
+// lanes' inclusive prefix of their chunk sums is kept up to date instead of
+// being rescanned: a draw r falls in the first lane whose inclusive sum
+// exceeds r; the whole wave then scans that lane's chunk (64 tiles per round)
+// for the first tile whose running sum exceeds r.  The tile found is the one
+// of the sequential definition (ascending tile order), so the draws equal the
+// plain loop's.
+__device__ void select_tiles_lds(uint64_t* s_w, uint8_t* s_c, const uint64_t* __restrict__ tw, int n_t,
+                                 int n_sel, uint64_t key, uint8_t* __restrict__ chosen) {
+  const int lane = lane_id();
+  const int chunk = (n_t + kWave - 1) / kWave;
+  const int c0 = min(n_t, lane * chunk), c1 = min(n_t, c0 + chunk);
+  uint64_t lsum = 0;
+  for (int t = c0; t < c1; ++t) {
+    const uint64_t x = tw[t];
+    s_w[t] = x;
+    s_c[t] = 0;
+    lsum += x;
+  }
+  int lrem = c1 - c0;
+  uint64_t incl = wave_inclusive_scan_u64(lsum);
+  int icnt = wave_inclusive_scan_i(lrem);
+  for (int j = 0; j < n_sel; ++j) {
+    const uint64_t u = absorb(key, (uint64_t)j);
+    const uint64_t total = __shfl(incl, 63, kWave);
+    int pick = -1;
+    if (total > 0) {
+      const uint64_t r = mulhi64(u, total);
+      const int o = __ffsll((unsigned long long)__ballot(incl > r)) - 1;  // owner lane (incl[63] > r)
+      const int oc0 = min(n_t, max(o, 0) * chunk), olen = o < 0 ? 0 : min(n_t, oc0 + chunk) - oc0;
+      uint64_t base = __shfl(incl, max(o, 0), kWave) - __shfl(lsum, max(o, 0), kWave);
+      for (int s0 = 0; s0 < olen; s0 += kWave) {
+        const int k = s0 + lane;
+        const uint64_t run = base + wave_inclusive_scan_u64(k < olen ? s_w[oc0 + k] : 0ull);
+        const uint64_t hit = __ballot(k < olen && run > r);
+        if (hit != 0ull) {
+          pick = oc0 + s0 + __ffsll((unsigned long long)hit) - 1;
+          break;
+        }
+        base = __shfl(run, 63, kWave);
+      }
+    } else {  // every remaining weight is zero: uniform over the remaining tiles
+      const int nrem = __shfl(icnt, 63, kWave);
+      const int r = (int)mulhi64(u, (uint64_t)nrem);
+      const int o = __ffsll((unsigned long long)__ballot(icnt > r)) - 1;  // icnt[63] = nrem > r
+      const int oc0 = min(n_t, max(o, 0) * chunk), olen = o < 0 ? 0 : min(n_t, oc0 + chunk) - oc0;
+      int base = __shfl(icnt, max(o, 0), kWave) - __shfl(lrem, max(o, 0), kWave);
+      for (int s0 = 0; s0 < olen; s0 += kWave) {
+        const int k = s0 + lane;
+        const int run = base + wave_inclusive_scan_i(k < olen && s_c[oc0 + k] == 0 ? 1 : 0);
+        const uint64_t hit = __ballot(k < olen && s_c[oc0 + k] == 0 && run > r);
+        if (hit != 0ull) {
+          pick = oc0 + s0 + __ffsll((unsigned long long)hit) - 1;
+          break;
+        }
+        base = __shfl(run, 63, kWave);
+      }
+    }
+    if (pick < 0 || pick >= n_t) continue;  // never taken (the sums are consistent); keeps accesses in bounds
+    const uint64_t wp = s_w[pick];          // wave-uniform; read before lane 0 clears it
+    const int owner = pick / chunk;
+    if (lane >= owner) {
+      incl -= wp;
+      icnt -= 1;
+    }
+    if (lane == owner) {
+      lsum -= wp;
+      lrem -= 1;
+    }
+    if (lane == 0) {
+      s_w[pick] = 0;
+      s_c[pick] = 1;
+    }
+  }
+  for (int t = c0; t < c1; ++t) chosen[t] = s_c[t];
+}
 
 __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
     uint64_t* __restrict__ tw, int H, int W, int tiles_x, int n_t, int n_sel, int n_pix,
     uint64_t seed, uint64_t step, uint64_t view, int32_t* __restrict__ valid_tiles,
     int32_t* __restrict__ tile_off, int32_t* __restrict__ tile_slot, int64_t* __restrict__ totals,
     uint8_t* __restrict__ chosen) {
+  extern __shared__ uint64_t s_sel[];  // [n_t] weights, then [n_t] flags, when n_t <= kSelectLdsTiles
   const int tid = threadIdx.x;
   const bool all_tiles = n_sel < 0 || n_sel >= n_t;
-  if (!all_tiles && tid < kWave) {
+  if (!all_tiles && tid < kWave && n_t <= kSelectLdsTiles) {
+    select_tiles_lds(s_sel, (uint8_t*)(s_sel + n_t), tw, n_t, n_sel, stream_key(seed, step, view, (uint64_t)n_t),
+                     chosen);
+  } else if (!all_tiles && tid < kWave) {
     const int lane = tid;
     const int chunk = (n_t + kWave - 1) / kWave;
     const int c0 = min(n_t, lane * chunk), c1 = min(n_t, c0 + chunk);
@@ -369,7 +451,8 @@ extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t heig
   else if (!all_tiles)
     hipLaunchKernelGGL(tile_weights_kernel, dim3(n_t), dim3(64), 0, s, E, height, width, tiles_x,
                        n_t, tw);
-  hipLaunchKernelGGL(tile_select_kernel, dim3(1), dim3(kSelectThreads), 0, s, tw, height, width,
+  const size_t sel_lds = !all_tiles && n_t <= kSelectLdsTiles ? (size_t)n_t * 9 : 0;
+  hipLaunchKernelGGL(tile_select_kernel, dim3(1), dim3(kSelectThreads), sel_lds, s, tw, height, width,
                      tiles_x, n_t, sp->n_tiles_sel, sp->n_pix, sp->seed, sp->step,
                      (uint64_t)sp->view, valid_tiles, tile_off, tile_slot, totals, chosen);
   if (n_st > 0)
