@@ -263,8 +263,17 @@ __global__ void __launch_bounds__(256) tile_mlp_adam_kernel(float* __restrict__ 
                                                             float* __restrict__ grad_out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= kParams) return;
+  // chunk order; eight loads in flight at a time
   float g = 0.f;
-  for (int c = 0; c < chunks; ++c) g += partials[(int64_t)c * kParams + i];
+  int c = 0;
+  for (; c + 8 <= chunks; c += 8) {
+    float q[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = partials[(int64_t)(c + k) * kParams + i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g += q[k];
+  }
+  for (; c < chunks; ++c) g += partials[(int64_t)c * kParams + i];
   if (grad_out != nullptr) grad_out[i] = g;
   const double b1 = 0.9, b2 = 0.999;
   const double mm = b1 * (double)m[i] + (1.0 - b1) * (double)g;
