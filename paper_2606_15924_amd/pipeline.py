@@ -244,7 +244,6 @@ class Trainer:
             self.tiles = TilePriority(len(self.cams), n_t, cfg, self.dev)
         # cross-stream events, recorded anew each step (a wait binds to the
         # record queued before it)
-        self._cleared = torch.cuda.Event()
         self._sampled = torch.cuda.Event()
         self._lossed = torch.cuda.Event()
 
@@ -295,15 +294,14 @@ class Trainer:
         st = self._stage
         used = [self.buffers(slot, self.cams[v]) for slot, v in enumerate(views)]
         slot_of = {id(vb): k for k, vb in enumerate(used)}
-        # the step's counters are cleared and the samplers run on the side
+        self.touched.zero_()
+        # the sample totals are cleared and the samplers run on the side
         # stream (which sees everything queued on main so far), beside the
         # first projection
         side.wait_stream(main)
-        cleared, sampled, lossed = self._cleared, self._sampled, self._lossed
+        sampled, lossed = self._sampled, self._lossed
         with torch.cuda.stream(side):
             self.totals.zero_()
-            self.touched.zero_()
-            cleared.record(side)
             for vb, v in zip(used, views):
                 cam = self.cams[v]
                 if vb.dense:
@@ -321,8 +319,6 @@ class Trainer:
             cam = self.cams[v]
             with st("project"):
                 vb.project(self.params, cam, self.rp)
-            if k == 0:
-                main.wait_event(cleared)  # touched is cleared
             if not waited and vb.bin_sort_needs_samples():
                 main.wait_event(sampled)
                 waited = True
@@ -355,8 +351,6 @@ class Trainer:
                     B.tgs_project_bwd_optimizer_step(self.params, self.n, cam, self.rp, vb.radius, vb.clamp,
                                                      vb.g2d, self.grad if k > 0 else None, self.m, self.v,
                                                      self.touched, self.op, t, self.fused_ws)
-        if not used:
-            main.wait_event(cleared)
         if not used or not self.cfg.fuse_optimizer:
             with st("optimizer"):
                 B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
