@@ -118,12 +118,15 @@ def run(tr, steps, warmup):
     import torch
     for _ in range(warmup):
         tr.step([0])
-    n_stage = max(5, steps // 5)
+    n_stage = max(20, steps // 2)
     tr.events = {}
     tr.timed_stages = None
     for _ in range(n_stage):
         tr.step([0])
-    stage = {k: v / n_stage for k, v in tr.stage_ms().items()}
+    samples = tr.stage_samples_ms()
+    stage = {k: sum(v) / n_stage for k, v in samples.items()}
+    stage_spread = {k: {f"p{q}": round(float(np.percentile(v, q)), 4) for q in (10, 50, 90)}
+                    for k, v in samples.items()}
     dom = max(("render_fwd", "render_bwd"), key=lambda k: stage.get(k, 0.0))
     tr.events = {}
     tr.timed_stages = {dom}
@@ -153,7 +156,7 @@ def run(tr, steps, warmup):
     pixels = (vb.width * vb.height) if vb.dense else int(vb.tile_off[-1].item())
     return dict(seconds=t1 - t0, ms_per_step=(t1 - t0) * 1000.0 / steps, evals=cnt[0], blends=cnt[1],
                 stage_ms=stage, dominant=dom, dominant_ms=dom_ms, n_pairs=int(vb.n_pairs), pixels=pixels,
-                step_ms_spread=pct)
+                step_ms_spread=pct, stage_ms_spread=stage_spread)
 
 
 def matched_psnr(dev, dense_steps=PSNR_DENSE_STEPS, max_steps=PSNR_MAX_STEPS):
@@ -532,6 +535,7 @@ def main():
                    "pairs": head["n_pairs"], "parallelism": "single GPU"},
         "stage_ms": {k: round(v, 4) for k, v in head["stage_ms"].items()},
         "step_ms_spread": head["step_ms_spread"],
+        "stage_ms_spread": head["stage_ms_spread"],
         # blends per second of the raster kernels alone (forward; forward + backward)
         "blends_per_s_fwd": per_launch_blends / (1e-3 * head["stage_ms"]["render_fwd"]),
         "blends_per_s_fwd_bwd": per_launch_blends / (1e-3 * (head["stage_ms"]["render_fwd"] +

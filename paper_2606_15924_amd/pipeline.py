@@ -267,6 +267,11 @@ class Trainer:
         torch.cuda.synchronize()
         return {k: sum(a.elapsed_time(b) for a, b in v) for k, v in (self.events or {}).items()}
 
+    def stage_samples_ms(self) -> dict:
+        """Every recorded duration per stage, in milliseconds (synchronises)."""
+        torch.cuda.synchronize()
+        return {k: [a.elapsed_time(b) for a, b in v] for k, v in (self.events or {}).items()}
+
     def buffers(self, key, cam) -> ViewBuffers:
         if key not in self._bufs:
             n_pix = None if self.cfg.rate_permille is None else B.tgs_pixels_per_tile(self.cfg.rate_permille)
