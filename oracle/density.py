@@ -1,0 +1,72 @@
+"""Per-Gaussian statistics of the error-driven density control (Sec. 3.8,
+Eq. gauss_err_accum and Eq. gauss_score).
+
+A Gaussian i that is composited at pixel p with weight w_i(p) = T_i(p) alpha_i(p)
+(the weight of Eq. alpha_comp) collects, summed over the views and pixels
+rendered,
+
+  E_i = sum e(p) w_i(p),   W_i = sum w_i(p),   D_i = sum D_i(p) w_i(p),
+
+and its difficulty score is s_i = e_i + lambda_eff d_i with e_i = E_i / (W_i + eps),
+d_i = D_i / (W_i + eps) and lambda_eff = lambda_base (1 - rho).
+
+Readings (the paper leaves these open):
+
+* e(p) is the per-pixel error of the loss stage, |I_hat(p) - I(p)|_1 over the
+  three channels (the value the error-map EMA blends in, Eq. ema_err);
+* D_i(p) is the Mahalanobis distance of the pixel from the splat centre under
+  the conic Q (the inverse 2D covariance, dilation included):
+  sqrt(d^T Q d) = sqrt(-2 power) with power as in the compositing weight, and
+  it is weighted by w_i(p) as e(p) is ("replacing e by D");
+* the pixels are the ones rendered (the sparse samples of the sampled tiles,
+  or every pixel in dense mode); the walk, its skips and its stop are those of
+  the forward render, so only composited Gaussians collect anything;
+* eps = 1e-8, lambda_base and rho are inputs.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .params import RasterParams
+from .render import TILE, _tile_eval
+
+EPS = 1e-8
+
+
+def accumulate(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs, ys, err,
+               rp: RasterParams = RasterParams()) -> np.ndarray:
+    """Eq. gauss_err_accum over the pixels (xs[i], ys[i]) with errors err[i]:
+    returns [3, N] = (E, W, D) in FP64."""
+    rp = rp.f64()
+    TX = proj["TX"]
+    N = proj["opacity"].size
+    out = np.zeros((3, N))
+    xs = np.asarray(xs, dtype=np.int64)
+    ys = np.asarray(ys, dtype=np.int64)
+    e = np.asarray(err, dtype=np.float64)
+    tiles = (ys // TILE) * TX + (xs // TILE)
+    for t in np.unique(tiles):
+        sel = np.nonzero(tiles == t)[0]
+        lo, hi = ranges[t]
+        gids = sorted_vals[lo:hi].astype(np.int64)
+        if gids.size == 0:
+            continue
+        ev = _tile_eval(proj, gids, xs[sel].astype(np.float64), ys[sel].astype(np.float64), rp)
+        w = np.where(ev["contrib"], ev["T_before"] * ev["alpha"], 0.0)      # [P, K]
+        dist = np.sqrt(np.maximum(-2.0 * ev["power"], 0.0))                # [P, K]
+        np.add.at(out[0], gids, (e[sel][:, None] * w).sum(axis=0))
+        np.add.at(out[1], gids, w.sum(axis=0))
+        np.add.at(out[2], gids, (dist * w).sum(axis=0))
+    return out
+
+
+def score(stats: np.ndarray, lambda_base: float, rho: float, eps: float = EPS) -> dict:
+    """Eq. gauss_score: visibility-normalised error e_i and distance d_i, and
+    s_i = e_i + lambda_base (1 - rho) d_i."""
+    E, W, D = (np.asarray(stats[k], dtype=np.float64) for k in range(3))
+    e = E / (W + eps)
+    d = D / (W + eps)
+    lam = lambda_base * (1.0 - rho)
+    return dict(e=e, d=d, s=e + lam * d, lambda_eff=lam)

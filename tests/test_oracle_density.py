@@ -1,0 +1,103 @@
+"""Pins of the density-control oracle (Sec. 3.8, Eq. gauss_err_accum and
+Eq. gauss_score) against closed forms and invariants of compositing (CPU only)."""
+import math
+
+import numpy as np
+
+import synth
+from oracle import binning, density, project, render, sampler
+from oracle.params import RasterParams, SampleParams
+
+from support import small_scene
+
+
+def _proj(centres, sigma, opacity, TX=1):
+    """A hand-built projection: isotropic splats with conic I / sigma^2."""
+    n = len(opacity)
+    c = np.asarray(centres, dtype=np.float64).T
+    return dict(mean2d=c, conic=np.stack([np.full(n, 1 / sigma ** 2), np.zeros(n), np.full(n, 1 / sigma ** 2)]),
+                opacity=np.asarray(opacity, dtype=np.float64), rgb=np.zeros((3, n)), TX=TX)
+
+
+def test_two_splats_at_one_pixel_closed_form():
+    # pixel (3, 4); splat 0 at (3, 2), splat 1 at (6, 8): |d| = 2 and 5
+    sigma = 2.5
+    pr = _proj([(3.0, 2.0), (6.0, 8.0)], sigma, [0.8, 0.6])
+    vals = np.array([0, 1], dtype=np.uint32)
+    ranges = np.array([[0, 2]])
+    st = density.accumulate(pr, vals, ranges, [3], [4], [0.7], RasterParams())
+    a0 = 0.8 * math.exp(-0.5 * 4 / sigma ** 2)
+    a1 = 0.6 * math.exp(-0.5 * 25 / sigma ** 2)
+    w = [a0, (1 - a0) * a1]
+    dist = [2 / sigma, 5 / sigma]
+    for i in range(2):
+        assert abs(st[1, i] - w[i]) < 1e-15
+        assert abs(st[0, i] - 0.7 * w[i]) < 1e-15
+        assert abs(st[2, i] - dist[i] * w[i]) < 1e-15
+
+
+def test_walk_stops_where_the_forward_stops():
+    # alpha = 0.9 at the centre: T after k splats is 0.1^k; the fifth would
+    # take T below T_min = 1e-4, so it and everything behind collect nothing
+    pr = _proj([(5.0, 5.0)] * 7, 1.0, [0.9] * 7)
+    vals = np.arange(7, dtype=np.uint32)
+    st = density.accumulate(pr, vals, np.array([[0, 7]]), [5], [5], [1.0], RasterParams())
+    want = [0.9 * 0.1 ** k for k in range(4)] + [0.0] * 3
+    assert np.allclose(st[1], want, rtol=1e-12, atol=0)
+    assert not st[2].any()          # every composited splat sits at the pixel itself: D = 0
+
+
+def _scene_case(seed):
+    p, cam = small_scene(n=2500, seed=seed)
+    rp = RasterParams()
+    pr = project.project(p, cam, rp)
+    E = synth.error_map(cam.height, cam.width, 50 + seed)
+    A = synth.age_map(cam.height, cam.width, 60 + seed)
+    s = sampler.sample_view(E, A, SampleParams(n_pix=64), 3, 1, 0)
+    _, sv, ranges = binning.bin_and_sort(pr, s["valid_tiles"])
+    xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
+    err = np.random.default_rng(seed).uniform(0.0, 2.0, xs.size)
+    return pr, sv, ranges, xs, ys, err, rp
+
+
+def test_weights_telescope_to_one_minus_final_transmittance():
+    """sum_k T_k alpha_k = 1 - T_final at every pixel, so summed over the
+    Gaussians W and E equal the pixel sums of (1 - T) and e (1 - T) taken
+    from the forward render."""
+    pr, sv, ranges, xs, ys, err, rp = _scene_case(3)
+    st = density.accumulate(pr, sv, ranges, xs, ys, err, rp)
+    T = render.render_pixels(pr, sv, ranges, xs, ys, rp)["T"]
+    assert abs(st[1].sum() - (1 - T).sum()) <= 1e-10 * (1 - T).sum()
+    assert abs(st[0].sum() - (err * (1 - T)).sum()) <= 1e-10 * (err * (1 - T)).sum()
+    assert (1 - T).sum() > 10.0     # the case composites a lot
+
+
+def test_constant_error_and_distance_bound():
+    pr, sv, ranges, xs, ys, _, rp = _scene_case(4)
+    st = density.accumulate(pr, sv, ranges, xs, ys, np.full(xs.size, 0.25), rp)
+    assert np.allclose(st[0], 0.25 * st[1], rtol=1e-13, atol=0)
+    seen = st[1] > 0
+    assert seen.sum() > 100
+    sc = density.score(st, 0.5, 0.2)
+    # composited means o exp(-D^2 / 2) >= alpha_min, so D <= sqrt(2 ln(1 / alpha_min))
+    dmax = math.sqrt(2 * math.log(255.0))
+    assert (sc["d"][seen] <= dmax * (1 + 1e-9)).all()
+    assert np.allclose(sc["e"][seen], 0.25 * st[1][seen] / (st[1][seen] + density.EPS), rtol=1e-14)
+    assert not sc["s"][~seen].any()
+
+
+def test_score_is_a_weighted_mean_and_linear_in_lambda():
+    pr, sv, ranges, xs, ys, err, rp = _scene_case(5)
+    st = density.accumulate(pr, sv, ranges, xs, ys, err, rp)
+    seen = st[1] > 1e-3
+    sc = density.score(st, 0.0, 0.0)
+    # e_i is a w-weighted mean of the pixel errors (up to eps)
+    assert (sc["e"][seen] >= err.min() * (1 - 1e-6)).all() and (sc["e"][seen] <= err.max()).all()
+    s1 = density.score(st, 2.0, 0.25)
+    assert s1["lambda_eff"] == 1.5
+    assert np.allclose(s1["s"], sc["e"] + 1.5 * sc["d"], rtol=1e-15, atol=0)
+    # the sums are additive over views: two calls on halves equal one call on all
+    h = xs.size // 2
+    st2 = (density.accumulate(pr, sv, ranges, xs[:h], ys[:h], err[:h], rp)
+           + density.accumulate(pr, sv, ranges, xs[h:], ys[h:], err[h:], rp))
+    assert np.allclose(st2, st, rtol=1e-12, atol=1e-15)
