@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 7u
+#define TGS_ABI_VERSION 8u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
@@ -270,6 +270,41 @@ int32_t tgs_ema_age_update(uint16_t* E, uint16_t* A, int32_t height, int32_t wid
  * tgs_render_fwd output. */
 int32_t tgs_error_init(const float* out_dense, const float* gt, int32_t height, int32_t width,
                        uint16_t* E, void* stream);
+
+/* Error-driven density control, back-projection (Sec. 3.8, Eq.
+ * gauss_err_accum): replays the tgs_render_fwd walk of the same samples
+ * (same alpha decisions, bounded by the forward's ncontrib) and adds, for
+ * every composited Gaussian i at a rendered pixel p with weight
+ * w = T alpha,
+ *   stats[0][i] += e(p) w      (E_i)
+ *   stats[1][i] += w           (W_i)
+ *   stats[2][i] += D_i(p) w    (D_i), D_i(p) = sqrt(d^T Q d), the
+ *                              Mahalanobis distance of p from the centre
+ *                              under the conic Q.
+ * Arguments up to rp are those of the tgs_render_fwd call that produced
+ * ncontrib.
+ *   ncontrib  [P] uint32 from that call (sparse: P samples; dense: H*W)
+ *   err       [P] float per-pixel error e(p), indexed like ncontrib (the
+ *             tgs_loss err output in sparse mode)
+ *   n         number of Gaussians (ids in vals must be below n)
+ *   stats     [3][n] float, accumulated (+=): the caller clears it, then
+ *             calls once per view and step over which the sums run.
+ * Float atomics: the summation order is unspecified. */
+int32_t tgs_density_accumulate(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                               int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                               const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                               int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
+                               const uint32_t* ncontrib, const float* err, int64_t n, float* stats,
+                               void* stream);
+
+/* Difficulty score (Sec. 3.8, Eq. gauss_score) from tgs_density_accumulate's
+ * sums, in FP32: e_i = E_i / (W_i + eps), d_i = D_i / (W_i + eps),
+ * s_i = e_i + lambda_eff d_i with lambda_eff = lambda_base (1 - rho), rho in
+ * [0, 1] the training progress.  A Gaussian never composited scores 0.
+ *   stats  [3][n] float; e_out, d_out nullable [n]; s_out [n]
+ * Errors: eps <= 0 or rho outside [0, 1]. */
+int32_t tgs_density_score(const float* stats, int64_t n, float lambda_base, float rho, float eps,
+                          float* e_out, float* d_out, float* s_out, void* stream);
 
 /* Chain rule from g2d to the Gaussian parameters (backward of tgs_project).
  *   accumulate  1: grad[59][n] += gradient; culled Gaussians (radius 0) are

@@ -91,6 +91,9 @@ PROTOTYPES = {
                         _P, _P, _P, _P, _P]),
     "tgs_ema_age_update": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _P, ctypes.c_float, _P]),
     "tgs_error_init": (_I32, [_P, _P, _I32, _I32, _P, _P]),
+    "tgs_density_accumulate": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                                      ctypes.POINTER(tgs_raster_params), _P, _P, _I64, _P, _P]),
+    "tgs_density_score": (_I32, [_P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P]),
     "tgs_project_bwd": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
                                _P, _P, _P, _P, _I32, _P]),
     "tgs_optimizer_step": (_I32, [_P, _P, _P, _P, _I64, _P, ctypes.POINTER(tgs_optim_params), _I64, _P]),
@@ -274,6 +277,19 @@ def tgs_ema_age_update(E, A, height, width, tile_slot, tile_off, pix, err, beta)
 def tgs_error_init(out_dense, gt, height, width, E):
     _check(lib().tgs_error_init(_ptr(out_dense), _ptr(gt), height, width, _ptr(E), _stream()),
            "tgs_error_init")
+
+
+def tgs_density_accumulate(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
+                           n_st, max_per_tile, rp: tgs_raster_params, ncontrib, err, n, stats):
+    _check(lib().tgs_density_accumulate(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
+                                        _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
+                                        ctypes.byref(rp), _ptr(ncontrib), _ptr(err), n, _ptr(stats), _stream()),
+           "tgs_density_accumulate")
+
+
+def tgs_density_score(stats, n, lambda_base, rho, eps, e_out, d_out, s_out):
+    _check(lib().tgs_density_score(_ptr(stats), n, lambda_base, rho, eps, _ptr(e_out), _ptr(d_out), _ptr(s_out),
+                                   _stream()), "tgs_density_score")
 
 
 def tgs_project_bwd(params, n, cam: tgs_camera, rp: tgs_raster_params, radius, clamp, g2d, grad,

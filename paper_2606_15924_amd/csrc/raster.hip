@@ -402,6 +402,84 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
   }
 }
 
+// Back-projection of per-pixel statistics onto the Gaussians (Sec. 3.8,
+// Eq. gauss_err_accum): the forward walk is replayed with the same alpha
+// decisions, bounded by the forward's contributor count, and every
+// composited Gaussian collects e(p) w, w and D(p) w with w = T alpha and
+// D(p) = sqrt(d^T Q d) = sqrt(-2 ln2 p2) (p2 is the staged exponent, log2(e)
+// times the power).  Per Gaussian the three values are summed across the
+// wave (lane-half swaps, then DPP within rows of 16) and three lanes issue
+// one float atomic each into stats[0 | 1 | 2][gid].
+template <int kBlock, bool kDense>
+__global__ void __launch_bounds__(kBlock) render_accum_kernel(RasterArgs a, const uint32_t* __restrict__ ncontrib,
+                                                              const float* __restrict__ err, int64_t n,
+                                                              float* __restrict__ stats) {
+  __shared__ float4 s_geo[kBlock];
+  __shared__ float s_opa[kBlock];
+  __shared__ float s_cc[kBlock];
+  __shared__ uint32_t s_gid[kBlock];
+  const int slot = blockIdx.x, tid = threadIdx.x;
+  const int tile = kDense ? slot : a.valid_tiles[slot];
+  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const uint2 range = a.ranges[tile];
+  const PixelSlot px = pixel_of<kBlock, kDense>(a, slot, tile, tid);
+  const float lx = (float)(px.loc & 15), ly = (float)(px.loc >> 4);
+  const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
+  const float amin = a.alpha_min, amax = a.alpha_max;
+  constexpr float kTwoLn2 = 1.3862943611198906f;
+  // lane 0 of row 0 sums field 0, lane 0 of row 2 field 1, lane 0 of row 1 field 2
+  const int lane = lane_id();
+  const int field = (lane & 15) != 0 ? -1 : (lane == 0 ? 0 : (lane == 32 ? 1 : (lane == 16 ? 2 : -1)));
+
+  float e = 0.f;
+  uint32_t last = 0;
+  if (px.inside) {
+    e = err[px.out];
+    last = ncontrib[px.out];
+  }
+  bool done = last == 0;
+  float T = 1.f;
+
+  Staged nxt = {};
+  uint32_t g_after = 0;
+  if (range.x + tid < range.y) nxt = stage_load(a, a.vals[range.x + tid], x0, y0);
+  if (range.x + kBlock + tid < range.y) g_after = a.vals[range.x + kBlock + tid];
+
+  for (uint32_t start = range.x; start < range.y; start += kBlock) {
+    if (__syncthreads_count(done) == kBlock) break;
+    const bool live = start + tid < range.y;
+    s_geo[tid] = live ? nxt.geo : make_float4(0.f, 0.f, 0.f, 0.f);
+    s_cc[tid] = live ? nxt.app.x : 0.f;
+    s_opa[tid] = live ? nxt.app.y : 0.f;
+    s_gid[tid] = nxt.gid;
+    __syncthreads();
+    const uint32_t i1 = start + kBlock + tid, i2 = start + 2 * kBlock + tid;
+    if (i1 < range.y) nxt = stage_load(a, g_after, x0, y0);
+    if (i2 < range.y) g_after = a.vals[i2];
+    const int cnt = (int)min((uint32_t)kBlock, range.y - start);
+    const uint32_t pos0 = start - range.x;
+    for (int j = 0; j < cnt; ++j) {
+      if (__ballot(!done) == 0ull) break;  // the whole wave has finished
+      const float4 ge = s_geo[j];
+      const float pw = splat_exponent(lx - ge.x, ly - ge.y, ge.z, ge.w, s_cc[j]);
+      float G;
+      const float alpha = splat_alpha(pw, s_opa[j], amax, G);
+      const bool ok = !done && pw <= 0.f && alpha >= amin;
+      const float w = ok ? alpha * T : 0.f;
+      T = ok ? one_minus_times(T, alpha) : T;
+      done = done || (pos0 + (uint32_t)j + 1u >= last);
+      if (__ballot(ok) != 0ull) {
+        const float dist = __builtin_sqrtf(fmaxf(-kTwoLn2 * pw, 0.f));
+        const float p01 = swap_sum32(e * w, w);
+        const float p2 = swap_sum32(dist * w, 0.f);
+        const float r = row_sum16(swap_sum16(p01, p2));
+        const uint32_t gid = __builtin_amdgcn_readfirstlane(s_gid[j]);  // uniform
+        if (field >= 0 && r != 0.f && gid < (uint32_t)n) unsafeAtomicAdd(&stats[(int64_t)field * n + gid], r);
+      }
+    }
+  }
+}
+
 template <int kBlock, bool kDense>
 static void launch_fwd(const RasterArgs& a, int grid, float* out, uint32_t* ncontrib,
                        uint64_t* counters, float* state, hipStream_t s) {
@@ -516,4 +594,32 @@ extern "C" int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, cons
     else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s);
   }
   return hip_status("tgs_render_bwd");
+}
+
+extern "C" int32_t tgs_density_accumulate(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                                          int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                                          const int32_t* valid_tiles, const int32_t* tile_off,
+                                          const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
+                                          const tgs_raster_params* rp, const uint32_t* ncontrib,
+                                          const float* err, int64_t n, float* stats, void* stream) {
+  RasterArgs a;
+  if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
+                            tile_off, pix, n_st, max_per_tile, rp, "tgs_density_accumulate", a))
+    return e;
+  TGS_REQUIRE(n >= 0 && n < (1ll << 31), "tgs_density_accumulate: n out of range");
+  TGS_REQUIRE(ncontrib && err && stats, "tgs_density_accumulate: null pointer");
+  hipStream_t s = as_stream(stream);
+  if (n == 0) return hip_status("tgs_density_accumulate");
+  if (valid_tiles == nullptr) {
+    hipLaunchKernelGGL((render_accum_kernel<256, true>), dim3(tiles_x * tiles_y), dim3(256), 0, s, a, ncontrib, err,
+                       n, stats);
+  } else if (n_st > 0) {
+    if (max_per_tile <= 64)
+      hipLaunchKernelGGL((render_accum_kernel<64, false>), dim3(n_st), dim3(64), 0, s, a, ncontrib, err, n, stats);
+    else if (max_per_tile <= 128)
+      hipLaunchKernelGGL((render_accum_kernel<128, false>), dim3(n_st), dim3(128), 0, s, a, ncontrib, err, n, stats);
+    else
+      hipLaunchKernelGGL((render_accum_kernel<256, false>), dim3(n_st), dim3(256), 0, s, a, ncontrib, err, n, stats);
+  }
+  return hip_status("tgs_density_accumulate");
 }

@@ -14,6 +14,9 @@ stream while the main stream projects and bins (binning needs the sample
 only when it restricts the tiles), and each view's error/age update runs on
 the side stream beside the backward, which does not read the maps.  Events
 order the two; the step ends with the main stream waiting for the side one.
+With ``density_stats`` the side stream also back-projects each sparse view's
+per-pixel errors onto the Gaussians (tgs_density_accumulate, Sec. 3.8) for
+the density-control score (tgs_density_score).
 """
 from __future__ import annotations
 
@@ -43,6 +46,7 @@ class StepConfig:
     learned_tiles: bool = False   # tile pass by the learned tile priority (with n_tiles_sel > 0)
     tile_lr: float = 3e-3         # its online Adam learning rate
     tile_seed: int = 23           # its initial weights
+    density_stats: bool = False   # back-project (e, w, D) onto the Gaussians each sparse view (Sec. 3.8)
     raster: dict = field(default_factory=dict)
     loss: dict = field(default_factory=dict)
     optim: dict = field(default_factory=dict)
@@ -141,6 +145,11 @@ class ViewBuffers:
         B.tgs_ema_age_update(E, A, self.height, self.width, self.tile_slot, self.tile_off, self.pix,
                              self.err, beta)
 
+    def density(self, rp, stats):
+        B.tgs_density_accumulate(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
+                                 self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
+                                 rp, self.ncontrib, self.err, self.n, stats)
+
     def render_bwd(self, rp, zero=True):
         if zero:
             self.g2d.zero_()
@@ -237,6 +246,8 @@ class Trainer:
         self.events: dict | None = None   # stage name -> [(start, end)] when timing
         self.timed_stages: set | None = None  # stages to time (all when None)
         self.tiles: TilePriority | None = None
+        # density-control sums E, W, D per Gaussian (cleared by reset_density)
+        self.dstats = torch.zeros((3, self.n), dtype=torch.float32, device=self.dev) if cfg.density_stats else None
         if cfg.learned_tiles and cfg.rate_permille is not None and cfg.n_tiles_sel > 0:
             c0 = self.cams[0]
             n_t = ((c0.width + TILE - 1) // TILE) * ((c0.height + TILE - 1) // TILE)
@@ -344,6 +355,9 @@ class Trainer:
                         vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
                     if self.tiles is not None:
                         self.tiles.learn(k, v, self.E[v], self.A[v], vb, cam)
+                    if self.dstats is not None:
+                        with st("density"):
+                            vb.density(self.rp, self.dstats)
             with st("render_bwd"):
                 vb.render_bwd(self.rp, zero=False)  # g2d was cleared by the projection
             if k + 1 < len(used) or not self.cfg.fuse_optimizer:
@@ -361,6 +375,18 @@ class Trainer:
                 B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
         main.wait_stream(side)
         return used
+
+    def reset_density(self):
+        """Clears the density-control sums (the start of an accumulation window)."""
+        self.dstats.zero_()
+
+    def density_scores(self, lambda_base: float, rho: float, eps: float = 1e-8):
+        """Eq. gauss_score over the sums accumulated since the last reset:
+        (e, d, s) per Gaussian."""
+        e, d, sc = (torch.empty(self.n, dtype=torch.float32, device=self.dev) for _ in range(3))
+        torch.cuda.current_stream().wait_stream(self.side)  # the sums are added on the side stream
+        B.tgs_density_score(self.dstats, self.n, lambda_base, rho, eps, e, d, sc)
+        return e, d, sc
 
     def loss_value(self, used) -> float:
         return float(sum(vb.tile_loss[: vb.n_st].sum() for vb in used))

@@ -1,0 +1,170 @@
+"""GPU parity of the density-control statistics (Sec. 3.8): the
+back-projection of per-pixel errors, weights and distances onto the
+Gaussians (Eq. gauss_err_accum) and the difficulty score (Eq. gauss_score),
+against the oracle, plus the telescoping property at the full training size.
+
+Tolerances: every summed term is non-negative, so a per-Gaussian sum carries
+the relative error of its terms; a term's weight T alpha is a product of up
+to a few hundred FP32 factors (1e-4 relative).  The distance sqrt(d^T Q d)
+near a splat centre is the square root of a small FP32 difference, so D
+also gets an absolute 1e-3 per unit of weight."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import binning, density, project, render, sampler
+from oracle.params import RasterParams, SampleParams
+
+from support import assert_close, scene_c1, small_scene, splat_as_oracle, splat_record
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_15924_amd import binding
+    binding.lib()
+    return binding
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _case(case):
+    if case == "c1_sparse64":
+        p, cams = scene_c1()
+        cam = cams[2]
+        E = synth.error_map(cam.height, cam.width, 141)
+        A = synth.age_map(cam.height, cam.width, 142)
+        s = sampler.sample_view(E, A, SampleParams(n_pix=64, n_tiles_sel=64), 3, 1, 2)
+    elif case in ("ragged_sparse25", "ragged_sparse128"):
+        n_pix = 25 if case.endswith("25") else 128
+        p, cam = small_scene(n=2500, seed=17)
+        E = synth.error_map(cam.height, cam.width, 143)
+        A = synth.age_map(cam.height, cam.width, 144)
+        s = sampler.sample_view(E, A, SampleParams(n_pix=n_pix), 3, 1, 0)
+    else:
+        p, cam = small_scene(n=2500, seed=18)
+        s = None
+    return p, cam, s
+
+
+@pytest.mark.parametrize("case", ["c1_sparse64", "ragged_sparse25", "ragged_sparse128", "dense"])
+def test_density_accumulate_parity(B, case):
+    p, cam, s = _case(case)
+    rp = RasterParams(bg=(0.1, 0.2, 0.3))
+    pr = project.project(p, cam, rp)
+    rec = splat_record(pr)
+    q = splat_as_oracle(pr, rec)
+    _, sv, ranges = binning.bin_and_sort(pr, None if s is None else s["valid_tiles"])
+    if s is None:
+        xs, ys = render.dense_pixels(cam.width, cam.height)
+    else:
+        xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
+    ref = render.render_pixels(q, sv, ranges, xs, ys, rp)
+    err = np.random.default_rng(5).uniform(0.0, 2.0, xs.size).astype(np.float32)
+    ok = ~ref["flag"]
+    assert ok.mean() > 0.99
+    # guard-band pixels: no contributors on the GPU side, left out of the oracle's sums
+    nc = np.where(ok, ref["n_contrib"], 0).astype(np.int32)
+    want = density.accumulate(q, sv, ranges, xs[ok], ys[ok], err[ok], rp)
+    n = p.shape[1]
+    TX, TY = pr["TX"], pr["TY"]
+    if s is None:
+        idx = ys * cam.width + xs
+        nc_full = np.zeros(cam.width * cam.height, np.int32)
+        e_full = np.zeros(cam.width * cam.height, np.float32)
+        nc_full[idx], e_full[idx] = nc, err
+        nc, err = nc_full, e_full
+        vt = off = pix = None
+        n_st, mpt = TX * TY, 256
+    else:
+        vt, off, pix = dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"])
+        n_st, mpt = s["valid_tiles"].size, max(int(np.diff(s["tile_off"]).max()), 1)
+    stats = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+    args = (dev(rec), dev(sv.view(np.int32)), dev(ranges.astype(np.int32)), TX, TY, cam.width, cam.height,
+            vt, off, pix, n_st, mpt, B.raster_params(bg=rp.bg), dev(nc), dev(err), n, stats)
+    B.tgs_density_accumulate(*args)
+    got = host(stats).astype(np.float64)
+    assert (want[1] > 0).sum() > 200
+    assert_close(got[0], want[0], 1e-4, 1e-9, "E")
+    assert_close(got[1], want[1], 1e-4, 1e-9, "W")
+    assert_close(got[2], want[2], 1e-4, 1e-3 * want[1] + 1e-9, "D")
+    # a second call adds the same sums again
+    B.tgs_density_accumulate(*args)
+    assert_close(host(stats).astype(np.float64), 2 * want, 1e-4, 2e-3 * want[1] + 2e-9, "twice")
+
+
+def test_density_score_parity_and_errors(B):
+    rng = np.random.default_rng(9)
+    n = 100003
+    W = rng.uniform(0, 3, n) * (rng.uniform(0, 1, n) < 0.8)      # a fifth never composited
+    st = np.stack([W * rng.uniform(0, 2, n), W, W * rng.uniform(0, 3.3, n)]).astype(np.float32)
+    want = density.score(st.astype(np.float64), 0.7, 0.35, eps=float(np.float32(1e-8)))
+    e, d, sc = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3))
+    B.tgs_density_score(dev(st), n, 0.7, 0.35, 1e-8, e, d, sc)
+    for name, g in (("e", e), ("d", d), ("s", sc)):
+        assert_close(host(g), want[name], 1e-6, 0.0, name)
+    assert not host(sc)[W == 0].any()
+    # without the optional outputs
+    s2 = torch.empty(n, dtype=torch.float32, device="cuda")
+    B.tgs_density_score(dev(st), n, 0.7, 0.35, 1e-8, None, None, s2)
+    assert torch.equal(s2, sc)
+    with pytest.raises(RuntimeError, match="rho"):
+        B.tgs_density_score(dev(st), n, 0.7, 1.5, 1e-8, None, None, s2)
+    with pytest.raises(RuntimeError, match="eps"):
+        B.tgs_density_score(dev(st), n, 0.7, 0.5, 0.0, None, None, s2)
+    B.tgs_density_score(dev(st), 0, 0.7, 0.5, 1e-8, None, None, s2)   # empty: nothing to do
+
+
+def test_density_accumulate_without_tiles_leaves_stats(B):
+    p, cam = small_scene(n=300, seed=4)
+    pr = project.project(p, cam, RasterParams())
+    rec = splat_record(pr)
+    _, sv, ranges = binning.bin_and_sort(pr)
+    stats = torch.full((3, 300), 0.5, dtype=torch.float32, device="cuda")
+    z = torch.zeros(1, dtype=torch.int32, device="cuda")
+    B.tgs_density_accumulate(dev(rec), dev(sv.view(np.int32)), dev(ranges.astype(np.int32)), pr["TX"], pr["TY"],
+                             cam.width, cam.height, z, z, z.to(torch.uint8), 0, 64, B.raster_params(),
+                             z, z.float(), 300, stats)
+    assert (host(stats) == 0.5).all()
+
+
+def test_trainer_density_sums_telescope_at_full_size(B):
+    """300k Gaussians, one 1296x840 view at 25%: summed over the Gaussians,
+    W equals the sum over the samples of 1 - T_final and E the sum of
+    e (1 - T_final), both read from the step's own forward outputs."""
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    from support import scene_scaling
+    p, cam = scene_scaling()
+    H, W = cam.height, cam.width
+    gt = dev(synth.image(H, W, 171))
+    E = [dev(synth.error_map(H, W, 172).view(np.int16))]
+    A = [dev(synth.age_map(H, W, 173).view(np.int16))]
+    tr = Trainer(dev(p), [cam], [gt], StepConfig(rate_permille=250, density_stats=True), E=E, A=A)
+    used = tr.step([0])
+    vb = used[0]
+    P = int(host(vb.tile_off)[-1])
+    T = host(vb.out)[:P, 3].astype(np.float64)
+    err = host(vb.err)[:P].astype(np.float64)
+    st = host(tr.dstats).astype(np.float64)
+    assert P > 200000
+    assert abs(st[1].sum() - (1 - T).sum()) <= 1e-4 * (1 - T).sum()
+    assert abs(st[0].sum() - (err * (1 - T)).sum()) <= 1e-4 * (err * (1 - T)).sum()
+    assert (st >= 0).all() and (st[2][st[1] == 0] == 0).all()
+    e, d, sc = tr.density_scores(0.5, 0.25)
+    seen = st[1] > 1e-3
+    dg = host(d).astype(np.float64)
+    assert (dg[seen] <= np.sqrt(2 * np.log(255.0)) * (1 + 1e-4)).all()
+    assert np.allclose(host(sc), host(e) + 0.375 * dg, rtol=1e-6, atol=0)
+    tr.reset_density()
+    assert not tr.dstats.any()
