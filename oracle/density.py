@@ -21,7 +21,13 @@ Readings (the paper leaves these open):
 * the pixels are the ones rendered (the sparse samples of the sampled tiles,
   or every pixel in dense mode); the walk, its skips and its stop are those of
   the forward render, so only composited Gaussians collect anything;
-* eps = 1e-8, lambda_base and rho are inputs.
+* eps = 1e-8, lambda_base and rho are inputs;
+* percentile thresholds (Sec. 3.8 with the fractions eta_topk and eta_final of
+  the hyper-parameter table): densify the Gaussians whose score reaches the
+  eta_topk percentile, i.e. s_i >= the k-th largest score with
+  k = max(1, ceil((1 - eta_topk) n)); the final pruning keeps s_i >= the
+  k-th largest with k = max(1, ceil(eta_final n)).  Ties at the threshold are
+  all selected.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 """
@@ -70,3 +76,23 @@ def score(stats: np.ndarray, lambda_base: float, rho: float, eps: float = EPS) -
     d = D / (W + eps)
     lam = lambda_base * (1.0 - rho)
     return dict(e=e, d=d, s=e + lam * d, lambda_eff=lam)
+
+
+def kth_largest(values: np.ndarray, k: int) -> float:
+    """The k-th largest entry (1 <= k <= n), by sorting."""
+    v = np.sort(np.asarray(values).ravel())
+    assert 1 <= k <= v.size
+    return v[v.size - k]
+
+
+def percentile_count(n: int, fraction: float) -> int:
+    """k = max(1, ceil(fraction * n)): how many Gaussians a fraction selects."""
+    return max(1, int(np.ceil(fraction * n - 1e-9)))
+
+
+def select_masks(s: np.ndarray, eta_topk: float, eta_final: float) -> dict:
+    """Densification and final-pruning selections by percentile thresholds."""
+    n = s.size
+    t_d = kth_largest(s, percentile_count(n, 1.0 - eta_topk))
+    t_k = kth_largest(s, percentile_count(n, eta_final))
+    return dict(densify=s >= t_d, keep=s >= t_k, thr_densify=t_d, thr_keep=t_k)

@@ -101,3 +101,29 @@ def test_score_is_a_weighted_mean_and_linear_in_lambda():
     st2 = (density.accumulate(pr, sv, ranges, xs[:h], ys[:h], err[:h], rp)
            + density.accumulate(pr, sv, ranges, xs[h:], ys[h:], err[h:], rp))
     assert np.allclose(st2, st, rtol=1e-12, atol=1e-15)
+
+
+def test_kth_largest_by_counting_and_library_extremes():
+    rng = np.random.default_rng(12)
+    v = np.concatenate([rng.exponential(1.0, 5000), np.full(300, 0.5), np.zeros(700)]).astype(np.float32)
+    rng.shuffle(v)
+    assert density.kth_largest(v, 1) == v.max()
+    assert density.kth_largest(v, v.size) == v.min()
+    for k in (1, 2, 17, 1000, 2500, 4700, 4999, 5000, 5001, 5299, 5300, 5301, 5999, 6000):
+        t = density.kth_largest(v, k)
+        assert (v > t).sum() < k <= (v >= t).sum(), k
+        assert t in v
+
+
+def test_select_masks_counts():
+    rng = np.random.default_rng(13)
+    s = rng.exponential(1.0, 1003)
+    s[:200] = 0.0                                   # never composited
+    m = density.select_masks(s, eta_topk=0.9, eta_final=0.75)
+    k_d, k_k = density.percentile_count(1003, 0.1), density.percentile_count(1003, 0.75)
+    assert (k_d, k_k) == (101, 753)
+    assert m["densify"].sum() == 101 and m["keep"].sum() == 753     # no ties among the positive scores
+    assert (s[m["densify"]].min() >= s[~m["densify"]].max())
+    # keeping more than the 803 positive scores reaches the zeros, which all tie
+    assert density.select_masks(s, 0.9, 0.85)["keep"].all()
+    assert density.percentile_count(10, 0.3) == 3 and density.percentile_count(7, 0.0) == 1
