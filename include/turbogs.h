@@ -306,6 +306,23 @@ int32_t tgs_density_accumulate(const float* splat, const uint32_t* vals, const u
 int32_t tgs_density_score(const float* stats, int64_t n, float lambda_base, float rho, float eps,
                           float* e_out, float* d_out, float* s_out, void* stream);
 
+/* Percentile threshold of the density control (Sec. 3.8: densification and
+ * pruning by percentile thresholds of the scores): the k-th largest
+ * (1 <= k <= n) of values[n] in the total order of the IEEE bit patterns
+ * (-0 below +0, NaN above +inf), written to out (one device float) by an
+ * exact MSB-first radix select that stays on the device (nine small
+ * launches, no host synchronisation).
+ *   ws  tgs_select_workspace_size() bytes, 16-byte aligned, device memory
+ *       (fully rewritten by every call; calls that share it must not overlap)
+ * Errors: n < 1, k outside [1, n], a short workspace. */
+size_t tgs_select_workspace_size(void);
+int32_t tgs_select_kth_largest(const float* values, int64_t n, int64_t k, float* out, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* mask[i] = 1 when values[i] >= *thr in the order above (thr is a device
+ * pointer, e.g. the tgs_select_kth_largest output), else 0. */
+int32_t tgs_threshold_mask(const float* values, int64_t n, const float* thr, uint8_t* mask, void* stream);
+
 /* Chain rule from g2d to the Gaussian parameters (backward of tgs_project).
  *   accumulate  1: grad[59][n] += gradient; culled Gaussians (radius 0) are
  *               left untouched.  0: grad = gradient, every entry written

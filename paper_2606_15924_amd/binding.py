@@ -94,6 +94,9 @@ PROTOTYPES = {
     "tgs_density_accumulate": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
                                       ctypes.POINTER(tgs_raster_params), _P, _P, _I64, _P, _P]),
     "tgs_density_score": (_I32, [_P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P]),
+    "tgs_select_workspace_size": (_SZ, []),
+    "tgs_select_kth_largest": (_I32, [_P, _I64, _I64, _P, _P, _SZ, _P]),
+    "tgs_threshold_mask": (_I32, [_P, _I64, _P, _P, _P]),
     "tgs_project_bwd": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
                                _P, _P, _P, _P, _I32, _P]),
     "tgs_optimizer_step": (_I32, [_P, _P, _P, _P, _I64, _P, ctypes.POINTER(tgs_optim_params), _I64, _P]),
@@ -290,6 +293,19 @@ def tgs_density_accumulate(splat, vals, ranges, tiles_x, tiles_y, width, height,
 def tgs_density_score(stats, n, lambda_base, rho, eps, e_out, d_out, s_out):
     _check(lib().tgs_density_score(_ptr(stats), n, lambda_base, rho, eps, _ptr(e_out), _ptr(d_out), _ptr(s_out),
                                    _stream()), "tgs_density_score")
+
+
+def tgs_select_workspace_size() -> int:
+    return int(lib().tgs_select_workspace_size())
+
+
+def tgs_select_kth_largest(values, n, k, out, ws):
+    _check(lib().tgs_select_kth_largest(_ptr(values), n, k, _ptr(out), _ptr(ws), ws.numel() * ws.element_size(), _stream()),
+           "tgs_select_kth_largest")
+
+
+def tgs_threshold_mask(values, n, thr, mask):
+    _check(lib().tgs_threshold_mask(_ptr(values), n, _ptr(thr), _ptr(mask), _stream()), "tgs_threshold_mask")
 
 
 def tgs_project_bwd(params, n, cam: tgs_camera, rp: tgs_raster_params, radius, clamp, g2d, grad,

@@ -21,6 +21,7 @@ the density-control score (tgs_density_score).
 from __future__ import annotations
 
 import contextlib
+import math
 from dataclasses import dataclass, field
 
 import torch
@@ -387,6 +388,25 @@ class Trainer:
         torch.cuda.current_stream().wait_stream(self.side)  # the sums are added on the side stream
         B.tgs_density_score(self.dstats, self.n, lambda_base, rho, eps, e, d, sc)
         return e, d, sc
+
+    def density_select(self, lambda_base: float, rho: float, eta_topk: float, eta_final: float,
+                       eps: float = 1e-8):
+        """The percentile selections of the density control over the current
+        sums: densify where s_i reaches the k-th largest score,
+        k = max(1, ceil((1 - eta_topk) n)); keep (final pruning) where it
+        reaches the k-th largest with k = max(1, ceil(eta_final n)); ties are
+        selected.  Returns (densify, keep) uint8 masks, the two thresholds and
+        the scores."""
+        e, d, sc = self.density_scores(lambda_base, rho, eps)
+        if getattr(self, "_select_ws", None) is None:
+            self._select_ws = torch.empty(B.tgs_select_workspace_size(), dtype=torch.uint8, device=self.dev)
+        thr = torch.empty(2, dtype=torch.float32, device=self.dev)
+        masks = torch.empty((2, self.n), dtype=torch.uint8, device=self.dev)
+        for j, frac in enumerate((1.0 - eta_topk, eta_final)):
+            k = max(1, math.ceil(frac * self.n - 1e-9))
+            B.tgs_select_kth_largest(sc, self.n, k, thr[j:j + 1], self._select_ws)
+            B.tgs_threshold_mask(sc, self.n, thr[j:j + 1], masks[j])
+        return masks[0], masks[1], thr, (e, d, sc)
 
     def loss_value(self, used) -> float:
         return float(sum(vb.tile_loss[: vb.n_st].sum() for vb in used))

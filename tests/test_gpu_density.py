@@ -1,7 +1,9 @@
 """GPU parity of the density-control statistics (Sec. 3.8): the
 back-projection of per-pixel errors, weights and distances onto the
 Gaussians (Eq. gauss_err_accum) and the difficulty score (Eq. gauss_score),
-against the oracle, plus the telescoping property at the full training size.
+and the percentile thresholds (an exact k-th largest, bit for bit) against
+the oracle, plus the telescoping property and the selection counts at the
+full training size.
 
 Tolerances: every summed term is non-negative, so a per-Gaussian sum carries
 the relative error of its terms; a term's weight T alpha is a product of up
@@ -168,3 +170,58 @@ def test_trainer_density_sums_telescope_at_full_size(B):
     assert np.allclose(host(sc), host(e) + 0.375 * dg, rtol=1e-6, atol=0)
     tr.reset_density()
     assert not tr.dstats.any()
+
+
+@pytest.mark.parametrize("n", [1, 1000, 300000, (1 << 20) + 7])
+def test_select_kth_largest_bit_exact(B, n):
+    rng = np.random.default_rng(n)
+    v = rng.exponential(1.0, n).astype(np.float32)
+    if n > 10:
+        v[rng.integers(0, n, n // 5)] = 0.0                       # ties at zero
+        v[rng.integers(0, n, n // 10)] = np.float32(0.75)        # ties inside
+        v[rng.integers(0, n, n // 20)] = -rng.exponential(1.0, n // 20).astype(np.float32)
+        v[:2] = [np.inf, -np.inf]
+    V = dev(v)
+    ws = torch.empty(B.tgs_select_workspace_size(), dtype=torch.uint8, device="cuda")
+    out = torch.empty(1, dtype=torch.float32, device="cuda")
+    mask = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ks = sorted(k for k in {1, 2, n // 3 + 1, n // 2, n - 1, n} if 1 <= k <= n)
+    for k in ks:
+        B.tgs_select_kth_largest(V, n, k, out, ws)
+        t = density.kth_largest(v, k)
+        got = host(out)[0]
+        assert np.float32(got).view(np.uint32) == np.float32(t).view(np.uint32), (k, got, t)
+        B.tgs_threshold_mask(V, n, out, mask)
+        assert np.array_equal(host(mask).astype(bool), v >= t), k
+    with pytest.raises(RuntimeError, match="k"):
+        B.tgs_select_kth_largest(V, n, n + 1, out, ws)
+    with pytest.raises(RuntimeError, match="k"):
+        B.tgs_select_kth_largest(V, n, 0, out, ws)
+
+
+def test_trainer_density_selection_at_full_size(B):
+    """Two steps of sparse training at 300k Gaussians, then the percentile
+    selections: each mask holds at least k Gaussians and everything above its
+    threshold, and fewer than k lie strictly above it."""
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    from support import scene_scaling
+    p, cam = scene_scaling()
+    H, W = cam.height, cam.width
+    gt = dev(synth.image(H, W, 181))
+    E = [dev(synth.error_map(H, W, 182).view(np.int16))]
+    A = [dev(synth.age_map(H, W, 183).view(np.int16))]
+    tr = Trainer(dev(p), [cam], [gt], StepConfig(rate_permille=250, density_stats=True), E=E, A=A)
+    tr.step([0])
+    tr.step([0])
+    dm, km, thr, (_, _, sc) = tr.density_select(0.5, 0.3, eta_topk=0.95, eta_final=0.85)
+    s = host(sc)
+    t = host(thr)
+    for mask, k, th in ((host(dm), 15000, t[0]), (host(km), 255000, t[1])):
+        m = mask.astype(bool)
+        assert np.array_equal(m, s >= th)
+        assert (s > th).sum() < k <= m.sum()
+    # about 24k Gaussians are composited in two steps of one view: the
+    # densification threshold lies among them, the keep threshold at the
+    # zero scores of the rest (all kept)
+    assert (s > 0).sum() > 15000 and t[0] > 0
+    assert t[1] == 0 and host(km).all()
