@@ -96,11 +96,11 @@ def make_workload(dev):
     return p, cam, gt
 
 
-def make_trainer(p, cam, gt, rate, dev):
+def make_trainer(p, cam, gt, rate, dev, density_stats=False):
     import torch
 
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
-    cfg = StepConfig(rate_permille=rate)
+    cfg = StepConfig(rate_permille=rate, density_stats=density_stats)
     E = torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev)
     A = torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev)
     tr = Trainer(torch.from_numpy(p).to(dev), [cam], [torch.from_numpy(gt).to(dev)], cfg, E=[E], A=[A])
@@ -429,6 +429,46 @@ def cpu_baseline(p, cam, gt, target_s=15.0):
                        f"{per_tile * 1e3:.1f} ms per tile), whole-view step extrapolated to {step_s:.1f} s")
 
 
+def density_control(p, cam, gt, dev, blends_per_step):
+    """The density-control statistics beside the headline step: the step
+    with the back-projection fused into the backward, that backward's time,
+    the standalone back-projection kernel on the same samples, and the score
+    plus both percentile selections over all Gaussians."""
+    import torch
+
+    from paper_2606_15924_amd import binding as B
+    tr = make_trainer(p, cam, gt, HEADLINE_RATE, dev, density_stats=True)
+    res = run(tr, 20, 3)
+    vb = tr._bufs[0]
+
+    def standalone():
+        vb.density(tr.rp, tr.dstats)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    standalone()
+    a.record()
+    for _ in range(20):
+        standalone()
+    b.record()
+    torch.cuda.synchronize()
+    acc_ms = a.elapsed_time(b) / 20
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tr.density_select(0.5, 0.3, 0.9, 0.85)
+    reps = 20
+    a.record()
+    for _ in range(reps):
+        tr.density_select(0.5, 0.3, 0.9, 0.85)
+    b.record()
+    torch.cuda.synchronize()
+    sel_ms = a.elapsed_time(b) / reps
+    del tr
+    return {"step_ms_with_accumulation": round(res["ms_per_step"], 4),
+            "render_bwd_with_accumulation_ms": round(res["stage_ms"]["render_bwd"], 4),
+            "standalone_accumulate_ms": round(acc_ms, 4),
+            "standalone_accumulate_blends_per_s": blends_per_step / (acc_ms * 1e-3),
+            "score_and_selections_ms": round(sel_ms, 4),
+            "selection": "densify top 10% (eta_topk 0.9), keep top 85% (eta_final 0.85) of 300k scores"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -502,6 +542,9 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(dom), "launch_ms": round(head["dominant_ms"], 4)}
 
+    log("density-control statistics")
+    dens = density_control(p, cam, gt, dev, per_launch_blends)
+
     tile = None
     if not args.no_tile:
         log("learned tile priority")
@@ -548,6 +591,7 @@ def main():
         "roofline": roofline,
         "matched_psnr": psnr,
         "tile_priority": tile,
+        "density_control": dens,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -276,9 +276,9 @@ int32_t tgs_error_init(const float* out_dense, const float* gt, int32_t height, 
  * (same alpha decisions, bounded by the forward's ncontrib) and adds, for
  * every composited Gaussian i at a rendered pixel p with weight
  * w = T alpha,
- *   stats[0][i] += e(p) w      (E_i)
- *   stats[1][i] += w           (W_i)
- *   stats[2][i] += D_i(p) w    (D_i), D_i(p) = sqrt(d^T Q d), the
+ *   stats[i][0] += e(p) w      (E_i)
+ *   stats[i][1] += w           (W_i)
+ *   stats[i][2] += D_i(p) w    (D_i), D_i(p) = sqrt(d^T Q d), the
  *                              Mahalanobis distance of p from the centre
  *                              under the conic Q.
  * Arguments up to rp are those of the tgs_render_fwd call that produced
@@ -286,22 +286,41 @@ int32_t tgs_error_init(const float* out_dense, const float* gt, int32_t height, 
  *   ncontrib  [P] uint32 from that call (sparse: P samples; dense: H*W)
  *   err       [P] float per-pixel error e(p), indexed like ncontrib (the
  *             tgs_loss err output in sparse mode)
+ *   state     nullable: that call's state record; given, each tile's walk
+ *             runs as TGS_RENDER_CHUNKS workgroups as in tgs_render_bwd
+ *             (same per-pixel arithmetic, another order of the atomics)
  *   n         number of Gaussians (ids in vals must be below n)
- *   stats     [3][n] float, accumulated (+=): the caller clears it, then
- *             calls once per view and step over which the sums run.
+ *   stats     [n][4] float, 16-byte aligned, accumulated (+=); entry 3 of
+ *             each slot is not touched (the three sums of a Gaussian share
+ *             a cache line).  The caller clears it, then calls once per
+ *             view and step over which the sums run.
  * Float atomics: the summation order is unspecified. */
 int32_t tgs_density_accumulate(const float* splat, const uint32_t* vals, const uint32_t* ranges,
                                int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
                                const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
                                int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
-                               const uint32_t* ncontrib, const float* err, int64_t n, float* stats,
+                               const uint32_t* ncontrib, const float* err, const float* state, int64_t n,
+                               float* stats, void* stream);
+
+/* tgs_render_bwd that also adds the density-control sums of
+ * tgs_density_accumulate (Sec. 3.8) for the same samples: the backward's
+ * replay already forms each composited Gaussian's weight w = T alpha, and
+ * the three sums join the gradient's wave reduction.  g2d gets what
+ * tgs_render_bwd gives (same arithmetic; float atomics in another order);
+ * err, n and stats are as in tgs_density_accumulate (n > 0). */
+int32_t tgs_render_bwd_density(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                               int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                               const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                               int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
+                               const float* out, const uint32_t* ncontrib, const float* dL_dout,
+                               float* g2d, const float* state, const float* err, int64_t n, float* stats,
                                void* stream);
 
 /* Difficulty score (Sec. 3.8, Eq. gauss_score) from tgs_density_accumulate's
  * sums, in FP32: e_i = E_i / (W_i + eps), d_i = D_i / (W_i + eps),
  * s_i = e_i + lambda_eff d_i with lambda_eff = lambda_base (1 - rho), rho in
  * [0, 1] the training progress.  A Gaussian never composited scores 0.
- *   stats  [3][n] float; e_out, d_out nullable [n]; s_out [n]
+ *   stats  [n][4] float (16-byte aligned); e_out, d_out nullable [n]; s_out [n]
  * Errors: eps <= 0 or rho outside [0, 1]. */
 int32_t tgs_density_score(const float* stats, int64_t n, float lambda_base, float rho, float eps,
                           float* e_out, float* d_out, float* s_out, void* stream);

@@ -92,7 +92,9 @@ PROTOTYPES = {
     "tgs_ema_age_update": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _P, ctypes.c_float, _P]),
     "tgs_error_init": (_I32, [_P, _P, _I32, _I32, _P, _P]),
     "tgs_density_accumulate": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
-                                      ctypes.POINTER(tgs_raster_params), _P, _P, _I64, _P, _P]),
+                                      ctypes.POINTER(tgs_raster_params), _P, _P, _P, _I64, _P, _P]),
+    "tgs_render_bwd_density": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                                      ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _I64, _P, _P]),
     "tgs_density_score": (_I32, [_P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P]),
     "tgs_select_workspace_size": (_SZ, []),
     "tgs_select_kth_largest": (_I32, [_P, _I64, _I64, _P, _P, _SZ, _P]),
@@ -283,11 +285,22 @@ def tgs_error_init(out_dense, gt, height, width, E):
 
 
 def tgs_density_accumulate(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
-                           n_st, max_per_tile, rp: tgs_raster_params, ncontrib, err, n, stats):
+                           n_st, max_per_tile, rp: tgs_raster_params, ncontrib, err, n, stats, state=None):
     _check(lib().tgs_density_accumulate(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
                                         _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
-                                        ctypes.byref(rp), _ptr(ncontrib), _ptr(err), n, _ptr(stats), _stream()),
+                                        ctypes.byref(rp), _ptr(ncontrib), _ptr(err), _ptr(state), n, _ptr(stats),
+                                        _stream()),
            "tgs_density_accumulate")
+
+
+def tgs_render_bwd_density(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
+                           n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL_dout, g2d, err, n, stats,
+                           state=None):
+    _check(lib().tgs_render_bwd_density(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
+                                        _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
+                                        ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(dL_dout), _ptr(g2d),
+                                        _ptr(state), _ptr(err), n, _ptr(stats), _stream()),
+           "tgs_render_bwd_density")
 
 
 def tgs_density_score(stats, n, lambda_base, rho, eps, e_out, d_out, s_out):

@@ -2,7 +2,8 @@
 // Eq. gauss_score) from the back-projected sums of tgs_density_accumulate:
 // e_i = E_i / (W_i + eps), d_i = D_i / (W_i + eps), s_i = e_i + lambda_eff d_i
 // with lambda_eff = lambda_base (1 - rho).  Elementwise and HBM-bound:
-// 12 bytes read and up to 12 written per Gaussian, one Gaussian per thread.
+// 16 bytes read (one [E, W, D, -] slot) and up to 12 written per Gaussian,
+// one Gaussian per thread.
 #include <algorithm>
 
 #include "common.h"
@@ -23,8 +24,9 @@ __global__ void __launch_bounds__(256) density_score_kernel(const float* __restr
                                                             float* __restrict__ d_out, float* __restrict__ s_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const float4 st = reinterpret_cast<const float4*>(stats)[i];
   float e, d, sc;
-  score_one(stats[i], stats[n + i], stats[2 * n + i], eps, lam, e, d, sc);
+  score_one(st.x, st.y, st.z, eps, lam, e, d, sc);
   if (e_out != nullptr) e_out[i] = e;
   if (d_out != nullptr) d_out[i] = d;
   s_out[i] = sc;
@@ -78,18 +80,25 @@ __global__ void __launch_bounds__(256) select_hist_kernel(const float* __restric
 }
 
 // One workgroup of 256: digit d's count of keys with a larger digit is a
-// suffix sum; the digit with above < k_rem <= above + hist[d] holds the target.
+// suffix sum (an inclusive Hillis-Steele scan from the top, eight rounds);
+// the digit with above < k_rem <= above + hist[d] holds the target.
 __global__ void __launch_bounds__(256) select_pick_kernel(int shift, SelectState* __restrict__ st,
                                                           float* __restrict__ out) {
-  __shared__ uint32_t h[256];
+  __shared__ uint32_t sfx[256];
   const int d = threadIdx.x;
-  h[d] = st->hist[d];
+  const uint32_t hd = st->hist[d];
+  sfx[d] = hd;
   __syncthreads();
-  uint32_t above = 0u;
-  for (int j = d + 1; j < 256; ++j) above += h[j];
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t add = d + off < 256 ? sfx[d + off] : 0u;
+    __syncthreads();
+    sfx[d] += add;
+    __syncthreads();
+  }
+  const uint32_t above = sfx[d] - hd;
   const uint32_t k = st->k_rem;
   __syncthreads();
-  const bool mine = above < k && k <= above + h[d];
+  const bool mine = above < k && k <= above + hd;
   st->hist[d] = 0u;  // cleared for the next round
   __syncthreads();
   if (mine) {
@@ -151,6 +160,7 @@ extern "C" int32_t tgs_density_score(const float* stats, int64_t n, float lambda
   TGS_REQUIRE(rho >= 0.f && rho <= 1.f, "tgs_density_score: rho %g not in [0, 1]", (double)rho);
   if (n == 0) return TGS_OK;
   TGS_REQUIRE(stats && s_out, "tgs_density_score: null pointer");
+  TGS_REQUIRE(((uintptr_t)stats & 15) == 0, "tgs_density_score: stats must be 16-byte aligned");
   hipStream_t s = as_stream(stream);
   const float lam = lambda_base * (1.0f - rho);
   hipLaunchKernelGGL(density_score_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0, s, stats, n,

@@ -252,11 +252,12 @@ struct Sum9Lane {
   int which;   // 0: r0, 1: r1, 2: r2
 };
 
-__device__ __forceinline__ Sum9Lane sum9_lane() {
+__device__ __forceinline__ Sum9Lane sum9_lane(bool twelve = false) {
   const int lane = lane_id(), k = lane & 15, row = lane >> 4;
   Sum9Lane s;
   s.which = k < 3 ? k : 0;
-  s.field = k < 2 ? k * 4 + ((row & 1) << 1) + (row >> 1) : (k == 2 && row == 0 ? 8 : -1);
+  const int f = k * 4 + ((row & 1) << 1) + (row >> 1);
+  s.field = k < 2 ? f : (k == 2 && (twelve || row == 0) ? f : -1);
   return s;
 }
 
@@ -281,13 +282,47 @@ __device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float* __r
   }
 }
 
-template <int kBlock, bool kDense>
+// The nine gradient sums plus the three density-control sums (e w, w, D w)
+// of the same Gaussian: the same folding with fields 9-11 in the rows of
+// r2 that the nine-value form leaves empty (row 2: field 9, row 1: 10,
+// row 3: 11); they go to stats[gid][field - 9], one 16-byte slot.
+__device__ __forceinline__ void wave_sum12_atomic(const float (&v)[12], float* __restrict__ dst,
+                                                  float* __restrict__ stats, uint32_t gid, int64_t n,
+                                                  const Sum9Lane& sl) {
+  const float p01 = swap_sum32(v[0], v[1]);
+  const float p23 = swap_sum32(v[2], v[3]);
+  const float p45 = swap_sum32(v[4], v[5]);
+  const float p67 = swap_sum32(v[6], v[7]);
+  const float p89 = swap_sum32(v[8], v[9]);
+  const float pab = swap_sum32(v[10], v[11]);
+  const float r0 = row_sum16(swap_sum16(p01, p23));
+  const float r1 = row_sum16(swap_sum16(p45, p67));
+  const float r2 = row_sum16(swap_sum16(p89, pab));
+  if (sl.field >= 0) {
+    const float val = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : r2);
+    if (val != 0.f) {
+      if (sl.field < 9) unsafeAtomicAdd(&dst[sl.field], val);
+      else if (gid < (uint32_t)n) unsafeAtomicAdd(&stats[(int64_t)gid * 4 + (sl.field - 9)], val);
+    }
+  }
+}
+
+// Optional density-control sums in the backward (Sec. 3.8): the replay
+// already has each composited Gaussian's weight w = T alpha.
+struct DensityArgs {
+  const float* err;  // [P] per-pixel error e(p), indexed like out
+  float* stats;      // [n][4] E, W, D, unused (+=)
+  int64_t n;
+};
+
+template <int kBlock, bool kDense, bool kDensity = false>
 __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
                                                             const float4* __restrict__ out,
                                                             const uint32_t* __restrict__ ncontrib,
                                                             const float4* __restrict__ dL,
                                                             float* __restrict__ g2d,
-                                                            const float4* __restrict__ state) {
+                                                            const float4* __restrict__ state,
+                                                            DensityArgs dens = {}) {
   __shared__ float4 s_geo[kBlock];
   __shared__ float4 s_app[kBlock];
   __shared__ float4 s_con[kBlock];  // conic a, b, c (natural units), blue
@@ -305,16 +340,18 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
   const float lx = (float)(px.loc & 15), ly = (float)(px.loc >> 4);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const float amin = a.alpha_min, amax = a.alpha_max;
-  const Sum9Lane sl = sum9_lane();
+  const Sum9Lane sl = sum9_lane(kDensity);
 
   float Cout0 = 0.f, Cout1 = 0.f, Cout2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
   uint32_t last = 0;
+  float e_pix = 0.f;
   if (px.inside) {
     const float4 o = out[px.out];
     const float4 d = dL[px.out];
     Cout0 = o.x; Cout1 = o.y; Cout2 = o.z;
     g0 = d.x; g1 = d.y; g2 = d.z;
     last = ncontrib[px.out];
+    if (kDensity) e_pix = dens.err[px.out];
   }
   bool done = last <= begin - range.x;  // nothing composited from this chunk on
   // T and S = sum_c g_c (C_c - acc_c): the loss-weighted colour behind the
@@ -395,7 +432,15 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
           v[7] = w * g1;
           v[8] = w * g2;
           const uint32_t gid = __builtin_amdgcn_readfirstlane(s_gid[j + u]);  // uniform
-          wave_sum9_atomic(v, g2d + (size_t)gid * 9, sl);
+          if constexpr (kDensity) {
+            constexpr float kTwoLn2 = 1.3862943611198906f;
+            const float dist = __builtin_sqrtf(fmaxf(-kTwoLn2 * pw[u], 0.f));
+            const float v12[12] = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8],
+                                   e_pix * w, w, dist * w};
+            wave_sum12_atomic(v12, g2d + (size_t)gid * 9, dens.stats, gid, dens.n, sl);
+          } else {
+            wave_sum9_atomic(v, g2d + (size_t)gid * 9, sl);
+          }
         }
       }
     }
@@ -409,19 +454,26 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
 // D(p) = sqrt(d^T Q d) = sqrt(-2 ln2 p2) (p2 is the staged exponent, log2(e)
 // times the power).  Per Gaussian the three values are summed across the
 // wave (lane-half swaps, then DPP within rows of 16) and three lanes issue
-// one float atomic each into stats[0 | 1 | 2][gid].
+// one float atomic each into stats[gid][0 | 1 | 2] (one 16-byte slot, so the
+// three atomics touch one cache line).  With the forward's
+// state record the walk is split into chunks exactly as the backward's.
 template <int kBlock, bool kDense>
 __global__ void __launch_bounds__(kBlock) render_accum_kernel(RasterArgs a, const uint32_t* __restrict__ ncontrib,
                                                               const float* __restrict__ err, int64_t n,
-                                                              float* __restrict__ stats) {
+                                                              float* __restrict__ stats,
+                                                              const float4* __restrict__ state) {
   __shared__ float4 s_geo[kBlock];
   __shared__ float s_opa[kBlock];
   __shared__ float s_cc[kBlock];
   __shared__ uint32_t s_gid[kBlock];
-  const int slot = blockIdx.x, tid = threadIdx.x;
+  const int slot = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
   const int tile = kDense ? slot : a.valid_tiles[slot];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const uint2 range = a.ranges[tile];
+  const uint32_t begin = range.x + (uint32_t)(chunk * TGS_RENDER_CHUNK_LEN);
+  if (begin >= range.y && chunk > 0) return;  // workgroup-uniform
+  const uint32_t end =
+      chunk + 1 == (int)gridDim.y ? range.y : min(range.y, begin + (uint32_t)TGS_RENDER_CHUNK_LEN);
   const PixelSlot px = pixel_of<kBlock, kDense>(a, slot, tile, tid);
   const float lx = (float)(px.loc & 15), ly = (float)(px.loc >> 4);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
@@ -437,44 +489,53 @@ __global__ void __launch_bounds__(kBlock) render_accum_kernel(RasterArgs a, cons
     e = err[px.out];
     last = ncontrib[px.out];
   }
-  bool done = last == 0;
+  bool done = last <= begin - range.x;  // nothing composited from this chunk on
   float T = 1.f;
+  if (chunk > 0 && !done) T = state[((int64_t)slot * (TGS_RENDER_CHUNKS - 1) + chunk - 1) * kBlock + tid].x;
 
   Staged nxt = {};
   uint32_t g_after = 0;
-  if (range.x + tid < range.y) nxt = stage_load(a, a.vals[range.x + tid], x0, y0);
-  if (range.x + kBlock + tid < range.y) g_after = a.vals[range.x + kBlock + tid];
+  if (begin + tid < end) nxt = stage_load(a, a.vals[begin + tid], x0, y0);
+  if (begin + kBlock + tid < end) g_after = a.vals[begin + kBlock + tid];
 
-  for (uint32_t start = range.x; start < range.y; start += kBlock) {
+  for (uint32_t start = begin; start < end; start += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
-    const bool live = start + tid < range.y;
+    const bool live = start + tid < end;
     s_geo[tid] = live ? nxt.geo : make_float4(0.f, 0.f, 0.f, 0.f);
     s_cc[tid] = live ? nxt.app.x : 0.f;
     s_opa[tid] = live ? nxt.app.y : 0.f;
     s_gid[tid] = nxt.gid;
     __syncthreads();
     const uint32_t i1 = start + kBlock + tid, i2 = start + 2 * kBlock + tid;
-    if (i1 < range.y) nxt = stage_load(a, g_after, x0, y0);
-    if (i2 < range.y) g_after = a.vals[i2];
-    const int cnt = (int)min((uint32_t)kBlock, range.y - start);
+    if (i1 < end) nxt = stage_load(a, g_after, x0, y0);
+    if (i2 < end) g_after = a.vals[i2];
+    const int cnt = (int)min((uint32_t)kBlock, end - start);
     const uint32_t pos0 = start - range.x;
-    for (int j = 0; j < cnt; ++j) {
+    for (int j = 0; j < cnt; j += kUnrollB) {
       if (__ballot(!done) == 0ull) break;  // the whole wave has finished
-      const float4 ge = s_geo[j];
-      const float pw = splat_exponent(lx - ge.x, ly - ge.y, ge.z, ge.w, s_cc[j]);
-      float G;
-      const float alpha = splat_alpha(pw, s_opa[j], amax, G);
-      const bool ok = !done && pw <= 0.f && alpha >= amin;
-      const float w = ok ? alpha * T : 0.f;
-      T = ok ? one_minus_times(T, alpha) : T;
-      done = done || (pos0 + (uint32_t)j + 1u >= last);
-      if (__ballot(ok) != 0ull) {
-        const float dist = __builtin_sqrtf(fmaxf(-kTwoLn2 * pw, 0.f));
-        const float p01 = swap_sum32(e * w, w);
-        const float p2 = swap_sum32(dist * w, 0.f);
-        const float r = row_sum16(swap_sum16(p01, p2));
-        const uint32_t gid = __builtin_amdgcn_readfirstlane(s_gid[j]);  // uniform
-        if (field >= 0 && r != 0.f && gid < (uint32_t)n) unsafeAtomicAdd(&stats[(int64_t)field * n + gid], r);
+      float al[kUnrollB], pw[kUnrollB];
+#pragma unroll
+      for (int u = 0; u < kUnrollB; ++u) {
+        const float4 ge = s_geo[j + u];
+        pw[u] = splat_exponent(lx - ge.x, ly - ge.y, ge.z, ge.w, s_cc[j + u]);
+        float G;
+        al[u] = splat_alpha(pw[u], s_opa[j + u], amax, G);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnrollB; ++u) {
+        if (j + u >= cnt) break;  // uniform
+        const bool ok = !done && pw[u] <= 0.f && al[u] >= amin;
+        const float w = ok ? al[u] * T : 0.f;
+        T = ok ? one_minus_times(T, al[u]) : T;
+        done = done || (pos0 + (uint32_t)(j + u) + 1u >= last);
+        if (__ballot(ok) != 0ull) {
+          const float dist = __builtin_sqrtf(fmaxf(-kTwoLn2 * pw[u], 0.f));
+          const float p01 = swap_sum32(e * w, w);
+          const float p2 = swap_sum32(dist * w, 0.f);
+          const float r = row_sum16(swap_sum16(p01, p2));
+          const uint32_t gid = __builtin_amdgcn_readfirstlane(s_gid[j + u]);  // uniform
+          if (field >= 0 && r != 0.f && gid < (uint32_t)n) unsafeAtomicAdd(&stats[(int64_t)gid * 4 + field], r);
+        }
       }
     }
   }
@@ -489,10 +550,15 @@ static void launch_fwd(const RasterArgs& a, int grid, float* out, uint32_t* ncon
 
 template <int kBlock, bool kDense>
 static void launch_bwd(const RasterArgs& a, int grid, const float* out, const uint32_t* ncontrib,
-                       const float* dL, float* g2d, const float* state, hipStream_t s) {
+                       const float* dL, float* g2d, const float* state, hipStream_t s,
+                       const DensityArgs* dens = nullptr) {
   const unsigned chunks = state != nullptr ? TGS_RENDER_CHUNKS : 1;
-  hipLaunchKernelGGL((render_bwd_kernel<kBlock, kDense>), dim3(grid, chunks), dim3(kBlock), 0, s, a,
-                     (const float4*)out, ncontrib, (const float4*)dL, g2d, (const float4*)state);
+  if (dens != nullptr)
+    hipLaunchKernelGGL((render_bwd_kernel<kBlock, kDense, true>), dim3(grid, chunks), dim3(kBlock), 0, s, a,
+                       (const float4*)out, ncontrib, (const float4*)dL, g2d, (const float4*)state, *dens);
+  else
+    hipLaunchKernelGGL((render_bwd_kernel<kBlock, kDense>), dim3(grid, chunks), dim3(kBlock), 0, s, a,
+                       (const float4*)out, ncontrib, (const float4*)dL, g2d, (const float4*)state, DensityArgs{});
 }
 
 // Workgroup size of the raster kernels for a launch.
@@ -596,30 +662,64 @@ extern "C" int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, cons
   return hip_status("tgs_render_bwd");
 }
 
+extern "C" int32_t tgs_render_bwd_density(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                                          int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                                          const int32_t* valid_tiles, const int32_t* tile_off,
+                                          const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
+                                          const tgs_raster_params* rp, const float* out,
+                                          const uint32_t* ncontrib, const float* dL_dout, float* g2d,
+                                          const float* state, const float* err, int64_t n, float* stats,
+                                          void* stream) {
+  RasterArgs a;
+  if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
+                            tile_off, pix, n_st, max_per_tile, rp, "tgs_render_bwd_density", a))
+    return e;
+  TGS_REQUIRE(out && ncontrib && dL_dout && g2d && err && stats, "tgs_render_bwd_density: null pointer");
+  TGS_REQUIRE(n > 0 && n < (1ll << 31), "tgs_render_bwd_density: n out of range");
+  TGS_REQUIRE(((uintptr_t)stats & 15) == 0, "tgs_render_bwd_density: stats must be 16-byte aligned");
+  TGS_REQUIRE(((uintptr_t)out & 15) == 0 && ((uintptr_t)dL_dout & 15) == 0 && ((uintptr_t)state & 15) == 0,
+              "tgs_render_bwd_density: out, dL_dout and state must be 16-byte aligned");
+  hipStream_t s = as_stream(stream);
+  const DensityArgs d{err, stats, n};
+  if (valid_tiles == nullptr) {
+    launch_bwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, dL_dout, g2d, state, s, &d);
+  } else if (n_st > 0) {
+    if (max_per_tile <= 64) launch_bwd<64, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s, &d);
+    else if (max_per_tile <= 128) launch_bwd<128, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s, &d);
+    else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s, &d);
+  }
+  return hip_status("tgs_render_bwd_density");
+}
+
 extern "C" int32_t tgs_density_accumulate(const float* splat, const uint32_t* vals, const uint32_t* ranges,
                                           int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
                                           const int32_t* valid_tiles, const int32_t* tile_off,
                                           const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
                                           const tgs_raster_params* rp, const uint32_t* ncontrib,
-                                          const float* err, int64_t n, float* stats, void* stream) {
+                                          const float* err, const float* state, int64_t n, float* stats,
+                                          void* stream) {
   RasterArgs a;
   if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
                             tile_off, pix, n_st, max_per_tile, rp, "tgs_density_accumulate", a))
     return e;
   TGS_REQUIRE(n >= 0 && n < (1ll << 31), "tgs_density_accumulate: n out of range");
   TGS_REQUIRE(ncontrib && err && stats, "tgs_density_accumulate: null pointer");
+  TGS_REQUIRE(((uintptr_t)stats & 15) == 0, "tgs_density_accumulate: stats must be 16-byte aligned");
+  TGS_REQUIRE(((uintptr_t)state & 15) == 0, "tgs_density_accumulate: state must be 16-byte aligned");
   hipStream_t s = as_stream(stream);
   if (n == 0) return hip_status("tgs_density_accumulate");
+  const unsigned chunks = state != nullptr ? TGS_RENDER_CHUNKS : 1;
+  const float4* st = (const float4*)state;
+#define TGS_ACCUM(BLK, DENSE, GRID) \
+  hipLaunchKernelGGL((render_accum_kernel<BLK, DENSE>), dim3(GRID, chunks), dim3(BLK), 0, s, a, ncontrib, err, n, \
+                     stats, st)
   if (valid_tiles == nullptr) {
-    hipLaunchKernelGGL((render_accum_kernel<256, true>), dim3(tiles_x * tiles_y), dim3(256), 0, s, a, ncontrib, err,
-                       n, stats);
+    TGS_ACCUM(256, true, tiles_x * tiles_y);
   } else if (n_st > 0) {
-    if (max_per_tile <= 64)
-      hipLaunchKernelGGL((render_accum_kernel<64, false>), dim3(n_st), dim3(64), 0, s, a, ncontrib, err, n, stats);
-    else if (max_per_tile <= 128)
-      hipLaunchKernelGGL((render_accum_kernel<128, false>), dim3(n_st), dim3(128), 0, s, a, ncontrib, err, n, stats);
-    else
-      hipLaunchKernelGGL((render_accum_kernel<256, false>), dim3(n_st), dim3(256), 0, s, a, ncontrib, err, n, stats);
+    if (max_per_tile <= 64) TGS_ACCUM(64, false, n_st);
+    else if (max_per_tile <= 128) TGS_ACCUM(128, false, n_st);
+    else TGS_ACCUM(256, false, n_st);
   }
+#undef TGS_ACCUM
   return hip_status("tgs_density_accumulate");
 }

@@ -14,9 +14,9 @@ stream while the main stream projects and bins (binning needs the sample
 only when it restricts the tiles), and each view's error/age update runs on
 the side stream beside the backward, which does not read the maps.  Events
 order the two; the step ends with the main stream waiting for the side one.
-With ``density_stats`` the side stream also back-projects each sparse view's
-per-pixel errors onto the Gaussians (tgs_density_accumulate, Sec. 3.8) for
-the density-control score (tgs_density_score).
+With ``density_stats`` each sparse view's backward also back-projects the
+per-pixel errors onto the Gaussians (tgs_render_bwd_density, Sec. 3.8) for
+the density-control score (tgs_density_score) and its percentile selections.
 """
 from __future__ import annotations
 
@@ -149,11 +149,18 @@ class ViewBuffers:
     def density(self, rp, stats):
         B.tgs_density_accumulate(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                                  self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
-                                 rp, self.ncontrib, self.err, self.n, stats)
+                                 rp, self.ncontrib, self.err, self.n, stats, self.state)
 
-    def render_bwd(self, rp, zero=True):
+    def render_bwd(self, rp, zero=True, stats=None):
+        """The backward; with ``stats`` it also adds the density-control sums."""
         if zero:
             self.g2d.zero_()
+        if stats is not None:
+            B.tgs_render_bwd_density(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
+                                     self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st,
+                                     self.n_pix, rp, self.out, self.ncontrib, self.dL, self.g2d, self.err, self.n,
+                                     stats, self.state)
+            return
         B.tgs_render_bwd(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                          self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
                          rp, self.out, self.ncontrib, self.dL, self.g2d, self.state)
@@ -247,8 +254,8 @@ class Trainer:
         self.events: dict | None = None   # stage name -> [(start, end)] when timing
         self.timed_stages: set | None = None  # stages to time (all when None)
         self.tiles: TilePriority | None = None
-        # density-control sums E, W, D per Gaussian (cleared by reset_density)
-        self.dstats = torch.zeros((3, self.n), dtype=torch.float32, device=self.dev) if cfg.density_stats else None
+        # density-control sums [E, W, D, -] per Gaussian (cleared by reset_density)
+        self.dstats = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev) if cfg.density_stats else None
         if cfg.learned_tiles and cfg.rate_permille is not None and cfg.n_tiles_sel > 0:
             c0 = self.cams[0]
             n_t = ((c0.width + TILE - 1) // TILE) * ((c0.height + TILE - 1) // TILE)
@@ -356,11 +363,10 @@ class Trainer:
                         vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
                     if self.tiles is not None:
                         self.tiles.learn(k, v, self.E[v], self.A[v], vb, cam)
-                    if self.dstats is not None:
-                        with st("density"):
-                            vb.density(self.rp, self.dstats)
             with st("render_bwd"):
-                vb.render_bwd(self.rp, zero=False)  # g2d was cleared by the projection
+                # g2d was cleared by the projection; the density sums of sparse
+                # views join the backward's reduction
+                vb.render_bwd(self.rp, zero=False, stats=None if vb.dense else self.dstats)
             if k + 1 < len(used) or not self.cfg.fuse_optimizer:
                 with st("project_bwd"):
                     # the first view overwrites the gradient, later views add to it
@@ -385,7 +391,6 @@ class Trainer:
         """Eq. gauss_score over the sums accumulated since the last reset:
         (e, d, s) per Gaussian."""
         e, d, sc = (torch.empty(self.n, dtype=torch.float32, device=self.dev) for _ in range(3))
-        torch.cuda.current_stream().wait_stream(self.side)  # the sums are added on the side stream
         B.tgs_density_score(self.dstats, self.n, lambda_base, rho, eps, e, d, sc)
         return e, d, sc
 

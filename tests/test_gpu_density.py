@@ -92,18 +92,18 @@ def test_density_accumulate_parity(B, case):
     else:
         vt, off, pix = dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"])
         n_st, mpt = s["valid_tiles"].size, max(int(np.diff(s["tile_off"]).max()), 1)
-    stats = torch.zeros((3, n), dtype=torch.float32, device="cuda")
+    stats = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
     args = (dev(rec), dev(sv.view(np.int32)), dev(ranges.astype(np.int32)), TX, TY, cam.width, cam.height,
             vt, off, pix, n_st, mpt, B.raster_params(bg=rp.bg), dev(nc), dev(err), n, stats)
     B.tgs_density_accumulate(*args)
-    got = host(stats).astype(np.float64)
+    got = host(stats)[:, :3].T.astype(np.float64)
     assert (want[1] > 0).sum() > 200
     assert_close(got[0], want[0], 1e-4, 1e-9, "E")
     assert_close(got[1], want[1], 1e-4, 1e-9, "W")
     assert_close(got[2], want[2], 1e-4, 1e-3 * want[1] + 1e-9, "D")
     # a second call adds the same sums again
     B.tgs_density_accumulate(*args)
-    assert_close(host(stats).astype(np.float64), 2 * want, 1e-4, 2e-3 * want[1] + 2e-9, "twice")
+    assert_close(host(stats)[:, :3].T.astype(np.float64), 2 * want, 1e-4, 2e-3 * want[1] + 2e-9, "twice")
 
 
 def test_density_score_parity_and_errors(B):
@@ -112,6 +112,7 @@ def test_density_score_parity_and_errors(B):
     W = rng.uniform(0, 3, n) * (rng.uniform(0, 1, n) < 0.8)      # a fifth never composited
     st = np.stack([W * rng.uniform(0, 2, n), W, W * rng.uniform(0, 3.3, n)]).astype(np.float32)
     want = density.score(st.astype(np.float64), 0.7, 0.35, eps=float(np.float32(1e-8)))
+    st = np.ascontiguousarray(np.concatenate([st.T, np.full((n, 1), np.nan, np.float32)], axis=1))  # [n][4]
     e, d, sc = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3))
     B.tgs_density_score(dev(st), n, 0.7, 0.35, 1e-8, e, d, sc)
     for name, g in (("e", e), ("d", d), ("s", sc)):
@@ -133,7 +134,7 @@ def test_density_accumulate_without_tiles_leaves_stats(B):
     pr = project.project(p, cam, RasterParams())
     rec = splat_record(pr)
     _, sv, ranges = binning.bin_and_sort(pr)
-    stats = torch.full((3, 300), 0.5, dtype=torch.float32, device="cuda")
+    stats = torch.full((300, 4), 0.5, dtype=torch.float32, device="cuda")
     z = torch.zeros(1, dtype=torch.int32, device="cuda")
     B.tgs_density_accumulate(dev(rec), dev(sv.view(np.int32)), dev(ranges.astype(np.int32)), pr["TX"], pr["TY"],
                              cam.width, cam.height, z, z, z.to(torch.uint8), 0, 64, B.raster_params(),
@@ -158,7 +159,7 @@ def test_trainer_density_sums_telescope_at_full_size(B):
     P = int(host(vb.tile_off)[-1])
     T = host(vb.out)[:P, 3].astype(np.float64)
     err = host(vb.err)[:P].astype(np.float64)
-    st = host(tr.dstats).astype(np.float64)
+    st = host(tr.dstats)[:, :3].T.astype(np.float64)
     assert P > 200000
     assert abs(st[1].sum() - (1 - T).sum()) <= 1e-4 * (1 - T).sum()
     assert abs(st[0].sum() - (err * (1 - T)).sum()) <= 1e-4 * (err * (1 - T)).sum()
@@ -225,3 +226,108 @@ def test_trainer_density_selection_at_full_size(B):
     # zero scores of the rest (all kept)
     assert (s > 0).sum() > 15000 and t[0] > 0
     assert t[1] == 0 and host(km).all()
+
+
+@pytest.mark.parametrize("mode", ["sparse64", "sparse128", "dense"])
+def test_density_accumulate_chunked_equals_single(B, mode):
+    """Deep lists (faint Gaussians, so most pixels reach the last chunk): the
+    walk split into (tile, chunk) workgroups from the forward's state record
+    gives the sums of the single-workgroup walk (same per-pixel arithmetic,
+    another order of the float atomics)."""
+    p, cam = small_scene(n=4000, seed=12)
+    p = np.array(p)
+    p[10] = -3.5                              # opacity logit: ~3% per Gaussian
+    rp = RasterParams()
+    pr = project.project(p, cam, rp)
+    rec = splat_record(pr)
+    _, sv, ranges = binning.bin_and_sort(pr)
+    TX, TY = pr["TX"], pr["TY"]
+    if mode == "dense":
+        vt = off = pix = None
+        n_st, mpt, P = TX * TY, 256, cam.width * cam.height
+    else:
+        mpt = 64 if mode == "sparse64" else 128
+        E = synth.error_map(cam.height, cam.width, 61)
+        A = synth.age_map(cam.height, cam.width, 62)
+        s = sampler.sample_view(E, A, SampleParams(n_pix=mpt), 3, 1, 0)
+        vt, off, pix = dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"])
+        n_st, P = s["valid_tiles"].size, int(s["tile_off"][-1])
+    splat, V, R = dev(rec), dev(sv.view(np.int32)), dev(ranges.astype(np.int32))
+    brp = B.raster_params()
+    out = torch.empty((P, 4), dtype=torch.float32, device="cuda")
+    nc = torch.empty(P, dtype=torch.int32, device="cuda")
+    state = torch.zeros(B.tgs_render_state_size(n_st, mpt) // 4, dtype=torch.float32, device="cuda")
+    B.tgs_render_fwd(splat, V, R, TX, TY, cam.width, cam.height, vt, off, pix, n_st, mpt, brp, out, nc, None, state)
+    assert (host(nc) > (B.RENDER_CHUNKS - 1) * B.RENDER_CHUNK_LEN).mean() > 0.1   # the last chunk has work
+    err = dev(np.random.default_rng(6).uniform(0, 2, P).astype(np.float32))
+    n = p.shape[1]
+    S1 = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    S2 = torch.zeros_like(S1)
+    args = (splat, V, R, TX, TY, cam.width, cam.height, vt, off, pix, n_st, mpt, brp, nc, err, n)
+    B.tgs_density_accumulate(*args, S1)
+    B.tgs_density_accumulate(*args, S2, state=state)
+    s1, s2 = host(S1)[:, :3].T.astype(np.float64), host(S2)[:, :3].T.astype(np.float64)
+    assert (s1[1] > 0).sum() > 1000
+    assert_close(s2, s1, 1e-5, 1e-6 * s1.max(axis=1, keepdims=True), "chunked vs single")
+    assert not host(S2)[:, 3].any()                  # the fourth entry of a slot is untouched
+
+
+@pytest.mark.parametrize("case,chunked", [("c1_sparse64", True), ("ragged_sparse25", False),
+                                          ("ragged_sparse128", True), ("dense", True)])
+def test_render_bwd_density_parity(B, case, chunked):
+    """The backward with the density sums fused in: its sums match the oracle
+    as the standalone kernel's do, and its gradient matches tgs_render_bwd."""
+    p, cam, s = _case(case)
+    rp = RasterParams(bg=(0.1, 0.2, 0.3))
+    pr = project.project(p, cam, rp)
+    rec = splat_record(pr)
+    q = splat_as_oracle(pr, rec)
+    _, sv, ranges = binning.bin_and_sort(pr, None if s is None else s["valid_tiles"])
+    if s is None:
+        xs, ys = render.dense_pixels(cam.width, cam.height)
+    else:
+        xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
+    ref = render.render_pixels(q, sv, ranges, xs, ys, rp)
+    ok = ~ref["flag"]
+    err = np.random.default_rng(7).uniform(0.0, 2.0, xs.size).astype(np.float32)
+    want = density.accumulate(q, sv, ranges, xs[ok], ys[ok], err[ok], rp)
+    n = p.shape[1]
+    TX, TY = pr["TX"], pr["TY"]
+    P = xs.size
+    brp = B.raster_params(bg=rp.bg)
+    splat, V, R = dev(rec), dev(sv.view(np.int32)), dev(ranges.astype(np.int32))
+    if s is None:
+        vt = off = pix = None
+        n_st, mpt, Pbuf = TX * TY, 256, cam.width * cam.height
+        idx = ys * cam.width + xs
+    else:
+        vt, off, pix = dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"])
+        n_st, mpt, Pbuf = s["valid_tiles"].size, max(int(np.diff(s["tile_off"]).max()), 1), P
+        idx = np.arange(P)
+    # forward outputs from the GPU forward (its state record for the chunked walk);
+    # guard-band pixels get no contributors and drop out of the oracle's sums
+    out = torch.empty((Pbuf, 4), dtype=torch.float32, device="cuda")
+    nc = torch.empty(Pbuf, dtype=torch.int32, device="cuda")
+    state = None
+    if chunked:
+        state = torch.zeros(B.tgs_render_state_size(n_st, mpt) // 4, dtype=torch.float32, device="cuda")
+    B.tgs_render_fwd(splat, V, R, TX, TY, cam.width, cam.height, vt, off, pix, n_st, mpt, brp, out, nc, None, state)
+    nch = host(nc)
+    assert np.array_equal(nch[idx][ok], ref["n_contrib"][ok])
+    nch[idx[~ok]] = 0
+    e_full = np.zeros(Pbuf, np.float32)
+    e_full[idx] = err
+    dl = torch.from_numpy(np.random.default_rng(8).normal(size=(Pbuf, 4)).astype(np.float32) * 1e-3).cuda()
+    G1 = torch.zeros((n, 9), dtype=torch.float32, device="cuda")
+    G2 = torch.zeros_like(G1)
+    S = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    args = (splat, V, R, TX, TY, cam.width, cam.height, vt, off, pix, n_st, mpt, brp, out, dev(nch), dl)
+    B.tgs_render_bwd(*args, G1, state)
+    B.tgs_render_bwd_density(*args, G2, dev(e_full), n, S, state=state)
+    got = host(S)[:, :3].T.astype(np.float64)
+    assert (want[1] > 0).sum() > 200
+    assert_close(got[0], want[0], 1e-4, 1e-9, "E")
+    assert_close(got[1], want[1], 1e-4, 1e-9, "W")
+    assert_close(got[2], want[2], 1e-4, 1e-3 * want[1] + 1e-9, "D")
+    g1, g2 = host(G1), host(G2)
+    assert_close(g2, g1, 1e-5, 1e-6 * (np.abs(g1).max(axis=0) + 1e-12), "g2d fused vs plain")
