@@ -96,3 +96,46 @@ def select_masks(s: np.ndarray, eta_topk: float, eta_final: float) -> dict:
     t_d = kth_largest(s, percentile_count(n, 1.0 - eta_topk))
     t_k = kth_largest(s, percentile_count(n, eta_final))
     return dict(densify=s >= t_d, keep=s >= t_k, thr_densify=t_d, thr_keep=t_k)
+
+
+SPLIT_FACTOR = 1.6   # scale divisor of a split (the 3D Gaussian splatting convention)
+
+
+def apply_topology(params: np.ndarray, m: np.ndarray, v: np.ndarray, keep, densify, z: np.ndarray,
+                   log_split: float) -> dict:
+    """Densify and prune (Alg. 1 step 11, second line) on the selections.
+
+    Readings (the paper names the step, not its mechanics; these follow the
+    3D Gaussian splatting convention it builds on):
+    * a Gaussian with keep = 0 is removed; the kept ones stay in order, then
+      one new Gaussian per kept Gaussian with densify = 1, in order;
+    * a densified Gaussian whose largest log-scale exceeds log_split is split:
+      with o = R(q / |q|) diag(exp(s)) z (z the caller's standard normal draw
+      for it) the kept slot moves to mean + o and the new one to mean - o,
+      both with log-scales s - ln 1.6; otherwise the new one is a clone;
+    * the moments of split and new Gaussians restart at zero; the others keep
+      theirs.
+    Parameter rows: 0-2 mean, 3-5 log-scale, 6-9 quaternion (w, x, y, z),
+    10 opacity logit, 11-58 SH."""
+    from .project import quat_to_rot
+    keep = np.asarray(keep).astype(bool)
+    dens = np.asarray(densify).astype(bool) & keep
+    P = np.asarray(params, dtype=np.float64)
+    s = P[3:6]
+    split = dens & (np.asarray(params[3:6]).max(axis=0) > np.float32(log_split))
+    q = P[6:10] / np.linalg.norm(P[6:10], axis=0, keepdims=True)
+    R = quat_to_rot(q)                                                 # [3, 3, N]
+    o = np.einsum("ijn,jn->in", R, np.exp(s) * np.asarray(z, dtype=np.float64).T)
+    kept = P.copy()
+    kept[0:3] = np.where(split, P[0:3] + o, P[0:3])
+    kept[3:6] = np.where(split, s - np.log(SPLIT_FACTOR), s)
+    new = P.copy()
+    new[0:3] = np.where(split, P[0:3] - o, P[0:3])
+    new[3:6] = kept[3:6]
+    mk = np.where(split, 0.0, np.asarray(m, dtype=np.float64))
+    vk = np.where(split, 0.0, np.asarray(v, dtype=np.float64))
+    out = np.concatenate([kept[:, keep], new[:, dens]], axis=1)
+    zeros = np.zeros((P.shape[0], int(dens.sum())))
+    return dict(params=out, m=np.concatenate([mk[:, keep], zeros], axis=1),
+                v=np.concatenate([vk[:, keep], zeros], axis=1),
+                n_keep=int(keep.sum()), n_new=int(dens.sum()), split=split)

@@ -127,3 +127,40 @@ def test_select_masks_counts():
     # keeping more than the 803 positive scores reaches the zeros, which all tie
     assert density.select_masks(s, 0.9, 0.85)["keep"].all()
     assert density.percentile_count(10, 0.3) == 3 and density.percentile_count(7, 0.0) == 1
+
+
+def test_topology_split_clone_prune_closed_forms():
+    n = 5
+    P = np.zeros((59, n))
+    P[0:3] = np.arange(15, dtype=np.float64).reshape(3, n)
+    P[3:6] = np.log(2.0)                                   # scale 2 on every axis
+    P[3:6, 1] = np.log(0.01)                               # Gaussian 1: small (clone)
+    P[6] = 1.0                                             # identity rotation
+    P[6:10, 3] = [np.cos(np.pi / 4), 0, 0, np.sin(np.pi / 4)]   # Gaussian 3: 90 degrees about z
+    P[10] = np.arange(n)
+    P[11:] = np.random.default_rng(1).normal(size=(48, n))
+    m = np.full((59, n), 0.5)
+    v = np.full((59, n), 0.25)
+    keep = np.array([1, 1, 0, 1, 1], np.uint8)
+    dens = np.array([1, 1, 1, 1, 0], np.uint8)             # Gaussian 2 is pruned, so not densified
+    z = np.array([[1.0, -2.0, 0.5]] * n)
+    r = density.apply_topology(P, m, v, keep, dens, z, log_split=np.log(0.1))
+    assert (r["n_keep"], r["n_new"]) == (4, 3) and r["params"].shape == (59, 7)
+    out = r["params"]
+    # order: kept 0, 1, 3, 4, then new copies of 0, 1, 3
+    assert np.array_equal(out[10], [0, 1, 3, 4, 0, 1, 3])
+    assert np.array_equal(out[11:], P[11:][:, [0, 1, 3, 4, 0, 1, 3]])
+    # Gaussian 0, identity rotation: o = S z = (2, -4, 1)
+    assert np.allclose(out[0:3, 0], P[0:3, 0] + [2, -4, 1], atol=1e-14)
+    assert np.allclose(out[0:3, 4], P[0:3, 0] - [2, -4, 1], atol=1e-14)
+    assert np.allclose(out[3:6, [0, 4]], np.log(2.0 / 1.6), atol=1e-15)
+    # Gaussian 3, 90 degrees about z maps x to y: o = (4, 2, 1)
+    assert np.allclose(out[0:3, 2], P[0:3, 3] + [4, 2, 1], atol=1e-12)
+    assert np.allclose((out[0:3, 2] + out[0:3, 6]) / 2, P[0:3, 3], atol=1e-12)   # centroid kept
+    # Gaussian 1 is small: an exact clone that keeps its scale
+    assert np.array_equal(out[:, 1], P[:, 1]) and np.array_equal(out[:, 5], P[:, 1])
+    # Gaussian 4: kept, untouched
+    assert np.array_equal(out[:, 3], P[:, 4])
+    # moments: split slots and new ones restart at zero
+    assert np.array_equal(r["m"][0], [0, 0.5, 0, 0.5, 0, 0, 0])
+    assert np.array_equal(r["v"][5], [0, 0.25, 0, 0.25, 0, 0, 0])
