@@ -342,6 +342,31 @@ int32_t tgs_select_kth_largest(const float* values, int64_t n, int64_t k, float*
  * pointer, e.g. the tgs_select_kth_largest output), else 0. */
 int32_t tgs_threshold_mask(const float* values, int64_t n, const float* thr, uint8_t* mask, void* stream);
 
+/* Densify and prune on the selections (Alg. 1 step 11, second line), in
+ * two calls.  tgs_density_topology_count scans the masks (keep[n],
+ * densify[n] uint8, nonzero = set) into ws and returns, after waiting for
+ * the stream, n_keep = #keep and n_new = #(keep and densify).
+ * tgs_density_topology_apply then writes the new arrays, n_out = n_keep +
+ * n_new Gaussians, from the same ws (same n; the masks are not read again):
+ *   - Gaussians with keep = 0 are dropped; the kept ones stay in order,
+ *     then one new Gaussian per kept and densified one, in order;
+ *   - a densified Gaussian whose largest log-scale (rows 3-5) exceeds
+ *     log_split is split: o = R(q/|q|) diag(exp(s)) z[i] (z: [n][3] standard
+ *     normal draws supplied by the caller), the kept slot at mean + o, the
+ *     new one at mean - o, both with log-scales lowered by ln 1.6;
+ *     otherwise the new Gaussian is a copy;
+ *   - m and v are copied, except for split and new Gaussians (zeros).
+ *   params, m, v        [59][n] float, read
+ *   params_out, m_out, v_out  [59][n_out] float, written
+ * Errors: n outside [1, 2^31), n_out outside [0, 2n], a short workspace. */
+size_t tgs_density_topology_workspace_size(int64_t n);
+int32_t tgs_density_topology_count(const uint8_t* keep, const uint8_t* densify, int64_t n, int64_t* n_keep,
+                                   int64_t* n_new, void* ws, size_t ws_bytes, void* stream);
+int32_t tgs_density_topology_apply(const float* params, const float* m, const float* v, int64_t n,
+                                   const float* z, float log_split, const void* ws, size_t ws_bytes,
+                                   float* params_out, float* m_out, float* v_out, int64_t n_out,
+                                   void* stream);
+
 /* Chain rule from g2d to the Gaussian parameters (backward of tgs_project).
  *   accumulate  1: grad[59][n] += gradient; culled Gaussians (radius 0) are
  *               left untouched.  0: grad = gradient, every entry written

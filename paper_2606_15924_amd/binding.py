@@ -96,6 +96,9 @@ PROTOTYPES = {
     "tgs_render_bwd_density": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
                                       ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _I64, _P, _P]),
     "tgs_density_score": (_I32, [_P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P]),
+    "tgs_density_topology_workspace_size": (_SZ, [_I64]),
+    "tgs_density_topology_count": (_I32, [_P, _P, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P, _SZ, _P]),
+    "tgs_density_topology_apply": (_I32, [_P, _P, _P, _I64, _P, ctypes.c_float, _P, _SZ, _P, _P, _P, _I64, _P]),
     "tgs_select_workspace_size": (_SZ, []),
     "tgs_select_kth_largest": (_I32, [_P, _I64, _I64, _P, _P, _SZ, _P]),
     "tgs_threshold_mask": (_I32, [_P, _I64, _P, _P, _P]),
@@ -306,6 +309,25 @@ def tgs_render_bwd_density(splat, vals, ranges, tiles_x, tiles_y, width, height,
 def tgs_density_score(stats, n, lambda_base, rho, eps, e_out, d_out, s_out):
     _check(lib().tgs_density_score(_ptr(stats), n, lambda_base, rho, eps, _ptr(e_out), _ptr(d_out), _ptr(s_out),
                                    _stream()), "tgs_density_score")
+
+
+def tgs_density_topology_workspace_size(n) -> int:
+    return int(lib().tgs_density_topology_workspace_size(n))
+
+
+def tgs_density_topology_count(keep, densify, n, ws):
+    """Returns (n_keep, n_new)."""
+    nk, nn = _I64(0), _I64(0)
+    _check(lib().tgs_density_topology_count(_ptr(keep), _ptr(densify), n, ctypes.byref(nk), ctypes.byref(nn),
+                                            _ptr(ws), ws.numel() * ws.element_size(), _stream()),
+           "tgs_density_topology_count")
+    return int(nk.value), int(nn.value)
+
+
+def tgs_density_topology_apply(params, m, v, n, z, log_split, ws, params_out, m_out, v_out, n_out):
+    _check(lib().tgs_density_topology_apply(_ptr(params), _ptr(m), _ptr(v), n, _ptr(z), log_split, _ptr(ws),
+                                            ws.numel() * ws.element_size(), _ptr(params_out), _ptr(m_out),
+                                            _ptr(v_out), n_out, _stream()), "tgs_density_topology_apply")
 
 
 def tgs_select_workspace_size() -> int:

@@ -122,6 +122,10 @@ static void exclusive_scan(const T* in, T* out, int64_t n, T* partials, hipStrea
   hipLaunchKernelGGL(scan_down_kernel<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials, out);
 }
 
+void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials, hipStream_t s) {
+  exclusive_scan<uint32_t>(in, out, n, partials, s);
+}
+
 
 
 // ------------------------------------------------------------------ row spans

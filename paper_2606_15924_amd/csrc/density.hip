@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "scan.h"
 
 namespace tgs {
 
@@ -117,9 +118,153 @@ __global__ void __launch_bounds__(256) threshold_mask_kernel(const float* __rest
   mask[i] = order_key(v[i]) >= order_key(*thr) ? 1u : 0u;
 }
 
+// ------------------------------------------------------------------ densify and prune
+// The step that acts on the selections (Alg. 1 step 11): Gaussians with
+// keep = 0 are dropped, the kept ones stay in order, then one new Gaussian
+// per kept Gaussian with densify = 1, in order.  A densified Gaussian whose
+// largest log-scale exceeds log_split is split: with o = R(q/|q|) diag(exp(s)) z
+// the kept slot moves to mean + o and the new one to mean - o, both with the
+// log-scales lowered by ln 1.6; otherwise the new one is a clone.  Split
+// and new Gaussians restart their moments at zero.  Output positions come
+// from exclusive scans of the two flag arrays (the count call), so a thread
+// per Gaussian writes its rows with no atomics.
+constexpr float kLnSplit = 0.47000362924573558f;  // ln 1.6
+
+struct TopoWs {
+  uint32_t* kflag;
+  uint32_t* dflag;
+  uint32_t* koff;  // [n + 1]
+  uint32_t* doff;  // [n + 1]
+  uint32_t* part;
+  size_t bytes;
+};
+
+static TopoWs topo_layout(void* base, int64_t n) {
+  TopoWs w{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    void* p = base ? (void*)((char*)base + o) : nullptr;
+    o += (b + 255) / 256 * 256;
+    return (uint32_t*)p;
+  };
+  w.kflag = take(sizeof(uint32_t) * n);
+  w.dflag = take(sizeof(uint32_t) * n);
+  w.koff = take(sizeof(uint32_t) * (n + 1));
+  w.doff = take(sizeof(uint32_t) * (n + 1));
+  w.part = take(sizeof(uint32_t) * scan_partials(n));
+  w.bytes = o;
+  return w;
+}
+
+__global__ void __launch_bounds__(256) topo_flags_kernel(const uint8_t* __restrict__ keep,
+                                                         const uint8_t* __restrict__ dens, int64_t n,
+                                                         uint32_t* __restrict__ kflag,
+                                                         uint32_t* __restrict__ dflag) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = keep[i] != 0 ? 1u : 0u;
+  kflag[i] = k;
+  dflag[i] = k & (dens[i] != 0 ? 1u : 0u);
+}
+
+__global__ void __launch_bounds__(256) topo_apply_kernel(const float* __restrict__ p, const float* __restrict__ m,
+                                                         const float* __restrict__ v, int64_t n,
+                                                         const uint32_t* __restrict__ kflag,
+                                                         const uint32_t* __restrict__ dflag,
+                                                         const uint32_t* __restrict__ koff,
+                                                         const uint32_t* __restrict__ doff,
+                                                         const float* __restrict__ z, float log_split,
+                                                         float* __restrict__ po, float* __restrict__ mo,
+                                                         float* __restrict__ vo, int64_t n_out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n || kflag[i] == 0u) return;
+  const bool dn = dflag[i] != 0u;
+  const int64_t dst = koff[i];
+  const int64_t dst2 = (int64_t)koff[n] + doff[i];
+  if (dst >= n_out || (dn && dst2 >= n_out)) return;  // an n_out not from the count call: stay in bounds
+  const float s0 = p[3 * n + i], s1 = p[4 * n + i], s2 = p[5 * n + i];
+  const bool split = dn && fmaxf(s0, fmaxf(s1, s2)) > log_split;
+  float o[3] = {0.f, 0.f, 0.f};
+  if (split) {
+    float qw = p[6 * n + i], qx = p[7 * n + i], qy = p[8 * n + i], qz = p[9 * n + i];
+    const float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+    const float e0 = expf(s0) * z[3 * i], e1 = expf(s1) * z[3 * i + 1], e2 = expf(s2) * z[3 * i + 2];
+    const float R00 = 1.f - 2.f * (qy * qy + qz * qz), R01 = 2.f * (qx * qy - qw * qz), R02 = 2.f * (qx * qz + qw * qy);
+    const float R10 = 2.f * (qx * qy + qw * qz), R11 = 1.f - 2.f * (qx * qx + qz * qz), R12 = 2.f * (qy * qz - qw * qx);
+    const float R20 = 2.f * (qx * qz - qw * qy), R21 = 2.f * (qy * qz + qw * qx), R22 = 1.f - 2.f * (qx * qx + qy * qy);
+    o[0] = R00 * e0 + R01 * e1 + R02 * e2;
+    o[1] = R10 * e0 + R11 * e1 + R12 * e2;
+    o[2] = R20 * e0 + R21 * e1 + R22 * e2;
+  }
+  for (int r = 0; r < TGS_PARAM_ROWS; ++r) {
+    const float val = p[(int64_t)r * n + i];
+    float kv = val, nv = val;
+    if (split && r < 3) {
+      kv = val + o[r];
+      nv = val - o[r];
+    } else if (split && r < 6) {
+      kv = nv = val - kLnSplit;
+    }
+    po[(int64_t)r * n_out + dst] = kv;
+    mo[(int64_t)r * n_out + dst] = split ? 0.f : m[(int64_t)r * n + i];
+    vo[(int64_t)r * n_out + dst] = split ? 0.f : v[(int64_t)r * n + i];
+    if (dn) {
+      po[(int64_t)r * n_out + dst2] = nv;
+      mo[(int64_t)r * n_out + dst2] = 0.f;
+      vo[(int64_t)r * n_out + dst2] = 0.f;
+    }
+  }
+}
+
 }  // namespace tgs
 
 using namespace tgs;
+
+extern "C" size_t tgs_density_topology_workspace_size(int64_t n) {
+  if (n < 0) return 0;
+  return topo_layout(nullptr, n).bytes;
+}
+
+extern "C" int32_t tgs_density_topology_count(const uint8_t* keep, const uint8_t* densify, int64_t n,
+                                              int64_t* n_keep, int64_t* n_new, void* ws, size_t ws_bytes,
+                                              void* stream) {
+  TGS_REQUIRE(n > 0 && n < (1ll << 31), "tgs_density_topology_count: n out of range");
+  TGS_REQUIRE(keep && densify && n_keep && n_new && ws, "tgs_density_topology_count: null pointer");
+  const TopoWs w = topo_layout(ws, n);
+  TGS_REQUIRE(ws_bytes >= w.bytes, "tgs_density_topology_count: workspace %zu bytes < %zu", ws_bytes, w.bytes);
+  hipStream_t s = as_stream(stream);
+  hipLaunchKernelGGL(topo_flags_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0, s, keep, densify,
+                     n, w.kflag, w.dflag);
+  exclusive_scan_u32(w.kflag, w.koff, n, w.part, s);
+  exclusive_scan_u32(w.dflag, w.doff, n, w.part, s);
+  uint32_t tot[2] = {0u, 0u};
+  if (hipMemcpyAsync(&tot[0], w.koff + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&tot[1], w.doff + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return hip_status("tgs_density_topology_count");
+  *n_keep = tot[0];
+  *n_new = tot[1];
+  return hip_status("tgs_density_topology_count");
+}
+
+extern "C" int32_t tgs_density_topology_apply(const float* params, const float* m, const float* v, int64_t n,
+                                              const float* z, float log_split, const void* ws, size_t ws_bytes,
+                                              float* params_out, float* m_out, float* v_out, int64_t n_out,
+                                              void* stream) {
+  TGS_REQUIRE(n > 0 && n < (1ll << 31), "tgs_density_topology_apply: n out of range");
+  TGS_REQUIRE(n_out >= 0 && n_out <= 2 * n, "tgs_density_topology_apply: n_out %lld out of range",
+              (long long)n_out);
+  TGS_REQUIRE(params && m && v && z && ws, "tgs_density_topology_apply: null pointer");
+  const TopoWs w = topo_layout((void*)ws, n);
+  TGS_REQUIRE(ws_bytes >= w.bytes, "tgs_density_topology_apply: workspace %zu bytes < %zu", ws_bytes, w.bytes);
+  if (n_out == 0) return TGS_OK;
+  TGS_REQUIRE(params_out && m_out && v_out, "tgs_density_topology_apply: null output");
+  hipStream_t s = as_stream(stream);
+  hipLaunchKernelGGL(topo_apply_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0, s, params, m, v,
+                     n, w.kflag, w.dflag, w.koff, w.doff, z, log_split, params_out, m_out, v_out, n_out);
+  return hip_status("tgs_density_topology_apply");
+}
 
 extern "C" size_t tgs_select_workspace_size(void) { return sizeof(SelectState); }
 

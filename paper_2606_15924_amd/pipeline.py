@@ -413,5 +413,27 @@ class Trainer:
             B.tgs_threshold_mask(sc, self.n, thr[j:j + 1], masks[j])
         return masks[0], masks[1], thr, (e, d, sc)
 
+    def densify_and_prune(self, densify, keep, z, log_split: float):
+        """Applies the selections (tgs_density_topology_*): the Gaussians,
+        their moments and every per-Gaussian buffer move to the new count;
+        the density sums restart.  z: [n, 3] standard normal draws for the
+        splits.  Returns the new count."""
+        ws = torch.empty(B.tgs_density_topology_workspace_size(self.n), dtype=torch.uint8, device=self.dev)
+        n_keep, n_new = B.tgs_density_topology_count(keep, densify, self.n, ws)
+        n_out = n_keep + n_new
+        p_out, m_out, v_out = (torch.empty((self.params.shape[0], n_out), dtype=torch.float32, device=self.dev)
+                               for _ in range(3))
+        B.tgs_density_topology_apply(self.params, self.m, self.v, self.n, z.contiguous(), log_split, ws,
+                                     p_out, m_out, v_out, n_out)
+        self.params, self.m, self.v, self.n = p_out, m_out, v_out, n_out
+        self.grad = torch.zeros_like(self.params)
+        self.touched = torch.zeros(self.n, dtype=torch.uint8, device=self.dev)
+        self.fused_ws = torch.empty(B.tgs_project_bwd_optimizer_workspace_size(self.n), dtype=torch.uint8,
+                                    device=self.dev)
+        if self.dstats is not None:
+            self.dstats = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev)
+        self._bufs = {}   # per-view buffers are sized by the Gaussian count
+        return n_out
+
     def loss_value(self, used) -> float:
         return float(sum(vb.tile_loss[: vb.n_st].sum() for vb in used))

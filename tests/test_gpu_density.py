@@ -331,3 +331,60 @@ def test_render_bwd_density_parity(B, case, chunked):
     assert_close(got[2], want[2], 1e-4, 1e-3 * want[1] + 1e-9, "D")
     g1, g2 = host(G1), host(G2)
     assert_close(g2, g1, 1e-5, 1e-6 * (np.abs(g1).max(axis=0) + 1e-12), "g2d fused vs plain")
+
+
+@pytest.mark.parametrize("n", [1, 777, 20011])
+def test_densify_and_prune_parity(B, n):
+    rng = np.random.default_rng(n + 3)
+    p = synth.gaussians(n, 31)
+    p[6:10] *= rng.uniform(0.5, 2.0, n).astype(np.float32)          # unnormalised quaternions
+    m = rng.normal(size=(59, n)).astype(np.float32)
+    v = rng.uniform(0, 1, (59, n)).astype(np.float32)
+    keep = (rng.uniform(0, 1, n) < 0.8).astype(np.uint8)
+    dens = (rng.uniform(0, 1, n) < 0.3).astype(np.uint8)
+    if n == 1:
+        keep[:], dens[:] = 1, 1
+    z = rng.normal(size=(n, 3)).astype(np.float32)
+    log_split = float(np.float32(np.median(p[3:6].max(axis=0))))
+    want = density.apply_topology(p, m, v, keep, dens, z, log_split)
+    ws = torch.empty(B.tgs_density_topology_workspace_size(n), dtype=torch.uint8, device="cuda")
+    nk, nn = B.tgs_density_topology_count(dev(keep), dev(dens), n, ws)
+    assert (nk, nn) == (want["n_keep"], want["n_new"])
+    n_out = nk + nn
+    po, mo, vo = (torch.full((59, n_out), np.nan, dtype=torch.float32, device="cuda") for _ in range(3))
+    B.tgs_density_topology_apply(dev(p), dev(m), dev(v), n, dev(z), log_split, ws, po, mo, vo, n_out)
+    got, gm, gv = host(po), host(mo), host(vo)
+    ref = want["params"]
+    # rows copied as they are, and the moments: bit for bit
+    assert np.array_equal(got[6:], ref[6:].astype(np.float32))
+    assert np.array_equal(gm, want["m"].astype(np.float32)) and np.array_equal(gv, want["v"].astype(np.float32))
+    # split means and log-scales: FP32 arithmetic against FP64
+    assert_close(got[3:6], ref[3:6], 0.0, 1e-6, "log-scales")
+    o_scale = np.abs(ref[0:3]) + np.exp(ref[3:6].max(axis=0)) * 1.6 * 4.0
+    assert_close(got[0:3], ref[0:3], 0.0, 1e-6 * o_scale, "means")
+    if n > 1:
+        assert want["split"].sum() > 10 and (dens & keep & ~want["split"]).sum() > 10
+
+
+def test_trainer_densify_and_prune_then_step(B):
+    """Select, densify and prune at 300k Gaussians, then train on: the count
+    follows the selections and the next step runs on the new Gaussians."""
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    from support import scene_scaling
+    p, cam = scene_scaling()
+    H, W = cam.height, cam.width
+    gt = dev(synth.image(H, W, 191))
+    E = [dev(synth.error_map(H, W, 192).view(np.int16))]
+    A = [dev(synth.age_map(H, W, 193).view(np.int16))]
+    tr = Trainer(dev(p), [cam], [gt], StepConfig(rate_permille=250, density_stats=True), E=E, A=A)
+    tr.step([0])
+    dm, km, thr, _ = tr.density_select(0.5, 0.3, eta_topk=0.95, eta_final=0.85)
+    # prune a random fifth of the Gaussians the score would keep
+    keep = km * (torch.rand(tr.n, device="cuda") > 0.2).to(torch.uint8)
+    n_keep, n_new = int(keep.sum()), int((keep * dm).sum())
+    z = torch.randn((tr.n, 3), device="cuda")
+    n_out = tr.densify_and_prune(dm, keep, z, float(np.log(0.02)))
+    assert n_out == n_keep + n_new == tr.n and tr.params.shape == (59, n_out)
+    used = tr.step([0])
+    assert torch.isfinite(tr.params).all()
+    assert used[0].n == n_out and tr.dstats.shape == (n_out, 4) and float(tr.dstats[:, 1].sum()) > 0
