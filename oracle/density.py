@@ -139,3 +139,25 @@ def apply_topology(params: np.ndarray, m: np.ndarray, v: np.ndarray, keep, densi
     return dict(params=out, m=np.concatenate([mk[:, keep], zeros], axis=1),
                 v=np.concatenate([vk[:, keep], zeros], axis=1),
                 n_keep=int(keep.sum()), n_new=int(dens.sum()), split=split)
+
+
+def grad_screen_accumulate(acc: np.ndarray, g2d: np.ndarray, radius: np.ndarray) -> np.ndarray:
+    """Screen-space statistics for densification (Alg. 1 step 8, second
+    line, and the gradient threshold tau_grad of the hyper-parameter table),
+    per view: acc[i] = (sum of |dL/d centre_i|, views in which i was
+    projected (radius > 0), largest radius, -).  Reading: the norm is taken
+    of the 2D centre gradient of that view's backward (pixel units), as in
+    the 3D Gaussian splatting densification statistic."""
+    acc = np.array(acc, dtype=np.float64, copy=True)
+    g = np.asarray(g2d, dtype=np.float64)
+    vis = np.asarray(radius) > 0
+    acc[:, 0] += np.where(vis, np.hypot(g[:, 0], g[:, 1]), 0.0)
+    acc[:, 1] += vis
+    acc[:, 2] = np.maximum(acc[:, 2], np.where(vis, np.asarray(radius, dtype=np.float64), 0.0))
+    return acc
+
+
+def grad_screen_mean(acc: np.ndarray) -> np.ndarray:
+    """Mean gradient norm per view in which the Gaussian was projected (0 if none)."""
+    acc = np.asarray(acc, dtype=np.float64)
+    return np.where(acc[:, 1] > 0, acc[:, 0] / np.maximum(acc[:, 1], 1.0), 0.0)

@@ -164,3 +164,15 @@ def test_topology_split_clone_prune_closed_forms():
     # moments: split slots and new ones restart at zero
     assert np.array_equal(r["m"][0], [0, 0.5, 0, 0.5, 0, 0, 0])
     assert np.array_equal(r["v"][5], [0, 0.25, 0, 0.25, 0, 0, 0])
+
+
+def test_grad_screen_statistics():
+    acc = np.zeros((4, 4))
+    g = np.zeros((4, 9))
+    g[:, 0:2] = [[3, 4], [-5, 12], [1, 1], [0, 0]]
+    g[:, 2:] = 7.0                                    # other gradient fields do not enter
+    acc = density.grad_screen_accumulate(acc, g, np.array([2, 9, 0, 4]))
+    acc = density.grad_screen_accumulate(acc, g * 2, np.array([5, 0, 0, 1]))
+    assert np.allclose(acc[:, 0], [5 + 10, 13, 0, 0])
+    assert np.array_equal(acc[:, 1], [2, 1, 0, 2]) and np.array_equal(acc[:, 2], [5, 9, 0, 4])
+    assert np.allclose(density.grad_screen_mean(acc), [7.5, 13, 0, 0])
