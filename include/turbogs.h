@@ -367,6 +367,20 @@ int32_t tgs_density_topology_apply(const float* params, const float* m, const fl
                                    float* params_out, float* m_out, float* v_out, int64_t n_out,
                                    void* stream);
 
+/* Screen-space statistics of densification (Alg. 1 step 8, second line;
+ * the gradient threshold tau_grad of the hyper-parameter table), per view
+ * after its backward: for every Gaussian projected in the view
+ * (radius > 0), acc[i][0] += |(g2d[i][0], g2d[i][1])| (the 2D centre
+ * gradient, pixel units), acc[i][1] += 1, acc[i][2] = max(acc[i][2],
+ * radius); acc[i][3] is not touched.
+ *   g2d [n][9] (tgs_render_bwd output), radius [n] (tgs_project output),
+ *   acc [n][4] float, 16-byte aligned; the caller clears it.
+ * tgs_grad_screen_mean: out[i] = acc[i][0] / acc[i][1], 0 where never
+ * projected. */
+int32_t tgs_grad_screen_accumulate(const float* g2d, const int32_t* radius, int64_t n, float* acc,
+                                   void* stream);
+int32_t tgs_grad_screen_mean(const float* acc, int64_t n, float* out, void* stream);
+
 /* Chain rule from g2d to the Gaussian parameters (backward of tgs_project).
  *   accumulate  1: grad[59][n] += gradient; culled Gaussians (radius 0) are
  *               left untouched.  0: grad = gradient, every entry written

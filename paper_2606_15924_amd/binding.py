@@ -99,6 +99,8 @@ PROTOTYPES = {
     "tgs_density_topology_workspace_size": (_SZ, [_I64]),
     "tgs_density_topology_count": (_I32, [_P, _P, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P, _SZ, _P]),
     "tgs_density_topology_apply": (_I32, [_P, _P, _P, _I64, _P, ctypes.c_float, _P, _SZ, _P, _P, _P, _I64, _P]),
+    "tgs_grad_screen_accumulate": (_I32, [_P, _P, _I64, _P, _P]),
+    "tgs_grad_screen_mean": (_I32, [_P, _I64, _P, _P]),
     "tgs_select_workspace_size": (_SZ, []),
     "tgs_select_kth_largest": (_I32, [_P, _I64, _I64, _P, _P, _SZ, _P]),
     "tgs_threshold_mask": (_I32, [_P, _I64, _P, _P, _P]),
@@ -328,6 +330,15 @@ def tgs_density_topology_apply(params, m, v, n, z, log_split, ws, params_out, m_
     _check(lib().tgs_density_topology_apply(_ptr(params), _ptr(m), _ptr(v), n, _ptr(z), log_split, _ptr(ws),
                                             ws.numel() * ws.element_size(), _ptr(params_out), _ptr(m_out),
                                             _ptr(v_out), n_out, _stream()), "tgs_density_topology_apply")
+
+
+def tgs_grad_screen_accumulate(g2d, radius, n, acc):
+    _check(lib().tgs_grad_screen_accumulate(_ptr(g2d), _ptr(radius), n, _ptr(acc), _stream()),
+           "tgs_grad_screen_accumulate")
+
+
+def tgs_grad_screen_mean(acc, n, out):
+    _check(lib().tgs_grad_screen_mean(_ptr(acc), n, _ptr(out), _stream()), "tgs_grad_screen_mean")
 
 
 def tgs_select_workspace_size() -> int:

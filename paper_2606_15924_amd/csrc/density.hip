@@ -217,9 +217,59 @@ __global__ void __launch_bounds__(256) topo_apply_kernel(const float* __restrict
   }
 }
 
+// ------------------------------------------------------------------ screen-space statistics
+// Per view, after its backward: the norm of each projected Gaussian's 2D
+// centre gradient (g2d fields 0-1) is added to acc[i][0], the view count
+// to acc[i][1], and acc[i][2] keeps the largest radius (the statistics the
+// gradient threshold of densification reads).  16 bytes read-modify-written
+// and 8 + 4 read per Gaussian.
+__global__ void __launch_bounds__(256) grad_screen_kernel(const float* __restrict__ g2d,
+                                                          const int32_t* __restrict__ radius, int64_t n,
+                                                          float4* __restrict__ acc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = radius[i];
+  if (r <= 0) return;
+  const float gx = g2d[9 * i], gy = g2d[9 * i + 1];
+  float4 a = acc[i];
+  a.x += sqrtf(gx * gx + gy * gy);
+  a.y += 1.f;
+  a.z = fmaxf(a.z, (float)r);
+  acc[i] = a;
+}
+
+__global__ void __launch_bounds__(256) grad_screen_mean_kernel(const float4* __restrict__ acc, int64_t n,
+                                                               float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float4 a = acc[i];
+  out[i] = a.y > 0.f ? a.x / a.y : 0.f;
+}
+
 }  // namespace tgs
 
 using namespace tgs;
+
+extern "C" int32_t tgs_grad_screen_accumulate(const float* g2d, const int32_t* radius, int64_t n, float* acc,
+                                              void* stream) {
+  TGS_REQUIRE(n >= 0 && n < (1ll << 31), "tgs_grad_screen_accumulate: n out of range");
+  if (n == 0) return TGS_OK;
+  TGS_REQUIRE(g2d && radius && acc, "tgs_grad_screen_accumulate: null pointer");
+  TGS_REQUIRE(((uintptr_t)acc & 15) == 0, "tgs_grad_screen_accumulate: acc must be 16-byte aligned");
+  hipLaunchKernelGGL(grad_screen_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0, as_stream(stream),
+                     g2d, radius, n, (float4*)acc);
+  return hip_status("tgs_grad_screen_accumulate");
+}
+
+extern "C" int32_t tgs_grad_screen_mean(const float* acc, int64_t n, float* out, void* stream) {
+  TGS_REQUIRE(n >= 0 && n < (1ll << 31), "tgs_grad_screen_mean: n out of range");
+  if (n == 0) return TGS_OK;
+  TGS_REQUIRE(acc && out, "tgs_grad_screen_mean: null pointer");
+  TGS_REQUIRE(((uintptr_t)acc & 15) == 0, "tgs_grad_screen_mean: acc must be 16-byte aligned");
+  hipLaunchKernelGGL(grad_screen_mean_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0,
+                     as_stream(stream), (const float4*)acc, n, out);
+  return hip_status("tgs_grad_screen_mean");
+}
 
 extern "C" size_t tgs_density_topology_workspace_size(int64_t n) {
   if (n < 0) return 0;

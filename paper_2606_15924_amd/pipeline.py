@@ -256,6 +256,8 @@ class Trainer:
         self.tiles: TilePriority | None = None
         # density-control sums [E, W, D, -] per Gaussian (cleared by reset_density)
         self.dstats = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev) if cfg.density_stats else None
+        # screen-space gradient statistics [sum |dL/d centre|, views, max radius, -]
+        self.gstats = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev) if cfg.density_stats else None
         if cfg.learned_tiles and cfg.rate_permille is not None and cfg.n_tiles_sel > 0:
             c0 = self.cams[0]
             n_t = ((c0.width + TILE - 1) // TILE) * ((c0.height + TILE - 1) // TILE)
@@ -367,6 +369,8 @@ class Trainer:
                 # g2d was cleared by the projection; the density sums of sparse
                 # views join the backward's reduction
                 vb.render_bwd(self.rp, zero=False, stats=None if vb.dense else self.dstats)
+            if self.gstats is not None:
+                B.tgs_grad_screen_accumulate(vb.g2d, vb.radius, self.n, self.gstats)
             if k + 1 < len(used) or not self.cfg.fuse_optimizer:
                 with st("project_bwd"):
                     # the first view overwrites the gradient, later views add to it
@@ -386,6 +390,13 @@ class Trainer:
     def reset_density(self):
         """Clears the density-control sums (the start of an accumulation window)."""
         self.dstats.zero_()
+        self.gstats.zero_()
+
+    def grad_screen_mean(self):
+        """Mean 2D centre gradient norm per view in which each Gaussian was projected."""
+        out = torch.empty(self.n, dtype=torch.float32, device=self.dev)
+        B.tgs_grad_screen_mean(self.gstats, self.n, out)
+        return out
 
     def density_scores(self, lambda_base: float, rho: float, eps: float = 1e-8):
         """Eq. gauss_score over the sums accumulated since the last reset:
@@ -432,6 +443,7 @@ class Trainer:
                                     device=self.dev)
         if self.dstats is not None:
             self.dstats = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev)
+            self.gstats = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev)
         self._bufs = {}   # per-view buffers are sized by the Gaussian count
         return n_out
 

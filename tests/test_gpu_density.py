@@ -388,3 +388,40 @@ def test_trainer_densify_and_prune_then_step(B):
     used = tr.step([0])
     assert torch.isfinite(tr.params).all()
     assert used[0].n == n_out and tr.dstats.shape == (n_out, 4) and float(tr.dstats[:, 1].sum()) > 0
+
+
+def test_grad_screen_statistics_parity(B):
+    rng = np.random.default_rng(21)
+    n = 50021
+    acc = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    want = np.zeros((n, 4))
+    for view in range(3):
+        g = (rng.normal(size=(n, 9)) * 10.0 ** rng.uniform(-6, 0, (n, 1))).astype(np.float32)
+        r = np.where(rng.uniform(0, 1, n) < 0.6, rng.integers(1, 200, n), 0).astype(np.int32)
+        B.tgs_grad_screen_accumulate(dev(g), dev(r), n, acc)
+        want = density.grad_screen_accumulate(want, g, r)
+    got = host(acc).astype(np.float64)
+    assert_close(got[:, 0], want[:, 0], 1e-6, 0.0, "norm sum")
+    assert np.array_equal(got[:, 1:3], want[:, 1:3]) and not got[:, 3].any()
+    mean = torch.empty(n, dtype=torch.float32, device="cuda")
+    B.tgs_grad_screen_mean(acc, n, mean)
+    assert_close(host(mean), density.grad_screen_mean(want), 2e-6, 0.0, "mean")
+
+
+def test_trainer_grad_screen_statistics(B):
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    p, cams = scene_c1()
+    H, W = cams[0].height, cams[0].width
+    gts = [dev(synth.image(H, W, 200 + k)) for k in range(len(cams))]
+    E = [dev(synth.error_map(H, W, 210 + k).view(np.int16)) for k in range(len(cams))]
+    A = [dev(synth.age_map(H, W, 220 + k).view(np.int16)) for k in range(len(cams))]
+    tr = Trainer(dev(p), cams, gts, StepConfig(rate_permille=250, density_stats=True), E=E, A=A)
+    used = tr.step([0, 1, 2])
+    vis = sum((host(vb.radius) > 0).astype(np.int64) for vb in used)
+    gs = host(tr.gstats)
+    assert np.array_equal(gs[:, 1], vis) and vis.max() == 3
+    assert (gs[:, 0] >= 0).all() and (gs[:, 0][vis == 0] == 0).all() and gs[:, 0].max() > 0
+    m = host(tr.grad_screen_mean())
+    assert np.isfinite(m).all() and (m[vis == 0] == 0).all()
+    tr.reset_density()
+    assert not tr.gstats.any()
