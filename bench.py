@@ -478,6 +478,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the pixel-rate sweep and dense run")
     ap.add_argument("--no-psnr", action="store_true", help="skip the matched-PSNR training comparison")
     ap.add_argument("--no-tile", action="store_true", help="skip the learned tile-priority measurement")
+    ap.add_argument("--no-density", action="store_true", help="skip the density-control measurement")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -542,8 +543,10 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(dom), "launch_ms": round(head["dominant_ms"], 4)}
 
-    log("density-control statistics")
-    dens = density_control(p, cam, gt, dev, per_launch_blends)
+    dens = None
+    if not args.no_density:
+        log("density-control statistics")
+        dens = density_control(p, cam, gt, dev, per_launch_blends)
 
     tile = None
     if not args.no_tile:
