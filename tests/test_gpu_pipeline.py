@@ -106,6 +106,32 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     assert rel_norm(dp_gpu, dp_ref) < 2e-3
 
 
+def test_c1_step_density_sums_match_oracle(B, c1_inputs):
+    """A four-view step with the density sums in the backward: per Gaussian,
+    E, W and D summed over the views equal the oracle's back-projection of
+    its own step (its samples, splats and per-pixel errors).  Whole-step
+    comparison: the FP32 render and errors and the few guard-band pixels
+    keep it to a norm bar, as for the gradient."""
+    from oracle import density
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    p, cams, gts, E, A = c1_inputs
+    sp = SampleParams(n_pix=64, n_tiles_sel=64)
+    ref = pipeline.train_step(p, np.zeros_like(p, np.float64), np.zeros_like(p, np.float64), cams, gts, E, A,
+                              1, sp, RP, LossParams(), OptimParams(), seed=3)
+    want = np.zeros((3, p.shape[1]))
+    for v in range(4):
+        fv, ls = ref["views"][v]["fwd"], ref["views"][v]["loss"]
+        want += density.accumulate(fv["proj"], fv["vals"], fv["ranges"], fv["xs"], fv["ys"], ls["err"], RP)
+    cfg = StepConfig(rate_permille=250, n_tiles_sel=64, seed=3, density_stats=True)
+    tr = Trainer(dev(p), cams, [dev(g) for g in gts], cfg, E=[dev(e.view(np.int16)) for e in E],
+                 A=[dev(a.view(np.int16)) for a in A])
+    tr.step([0, 1, 2, 3])
+    got = host(tr.dstats)[:, :3].T.astype(np.float64)
+    assert (want[1] > 0).sum() > 1000
+    for k, name in enumerate("EWD"):
+        assert rel_norm(got[k], want[k]) < 2e-3, name
+
+
 # ------------------------------------------------------------------ autograd
 def test_autograd_matches_oracle_gradient_and_finite_differences(B):
     from paper_2606_15924_amd.autograd import Samples, rasterize
