@@ -381,6 +381,14 @@ int32_t tgs_grad_screen_accumulate(const float* g2d, const int32_t* radius, int6
                                    void* stream);
 int32_t tgs_grad_screen_mean(const float* acc, int64_t n, float* out, void* stream);
 
+/* Per-view error sums for the anchor view (Sec. 3.4, Eq. anchor_view):
+ * sums[v] = the exact sum over the image of E_v(p) * 2^24 (every finite
+ * non-negative half is then an integer; negative, infinite and NaN values
+ * count 0, as in the sampler), so E_bar_v = sums[v] / (2^24 * pixels).
+ *   E     [n_views][pixels] half bits, contiguous
+ *   sums  [n_views] uint64, written (cleared first) */
+int32_t tgs_view_error_sums(const uint16_t* E, int32_t n_views, int64_t pixels, uint64_t* sums, void* stream);
+
 /* Chain rule from g2d to the Gaussian parameters (backward of tgs_project).
  *   accumulate  1: grad[59][n] += gradient; culled Gaussians (radius 0) are
  *               left untouched.  0: grad = gradient, every entry written

@@ -101,6 +101,7 @@ PROTOTYPES = {
     "tgs_density_topology_apply": (_I32, [_P, _P, _P, _I64, _P, ctypes.c_float, _P, _SZ, _P, _P, _P, _I64, _P]),
     "tgs_grad_screen_accumulate": (_I32, [_P, _P, _I64, _P, _P]),
     "tgs_grad_screen_mean": (_I32, [_P, _I64, _P, _P]),
+    "tgs_view_error_sums": (_I32, [_P, _I32, _I64, _P, _P]),
     "tgs_select_workspace_size": (_SZ, []),
     "tgs_select_kth_largest": (_I32, [_P, _I64, _I64, _P, _P, _SZ, _P]),
     "tgs_threshold_mask": (_I32, [_P, _I64, _P, _P, _P]),
@@ -339,6 +340,10 @@ def tgs_grad_screen_accumulate(g2d, radius, n, acc):
 
 def tgs_grad_screen_mean(acc, n, out):
     _check(lib().tgs_grad_screen_mean(_ptr(acc), n, _ptr(out), _stream()), "tgs_grad_screen_mean")
+
+
+def tgs_view_error_sums(E, n_views, pixels, sums):
+    _check(lib().tgs_view_error_sums(_ptr(E), n_views, pixels, _ptr(sums), _stream()), "tgs_view_error_sums")
 
 
 def tgs_select_workspace_size() -> int:

@@ -461,3 +461,49 @@ extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t heig
                        (uint64_t)sp->view, valid_tiles, tile_off, pix);
   return hip_status("tgs_sample");
 }
+
+// ------------------------------------------------------------------ per-view mean error
+// Eq. anchor_view needs each view's mean error E_bar_v over the image: the
+// exact integer sum of the half values times 2^24 (the weights above), one
+// 64-bit atomic per workgroup; the host divides by 2^24 |Omega|.
+namespace tgs {
+
+__global__ void __launch_bounds__(256) view_error_sum_kernel(const uint16_t* __restrict__ E, int64_t pixels,
+                                                             unsigned long long* __restrict__ sums) {
+  __shared__ unsigned long long red[256];
+  const int v = blockIdx.y;
+  const uint16_t* map = E + (int64_t)v * pixels;
+  unsigned long long acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < pixels; i += (int64_t)gridDim.x * 256)
+    acc += half_weight(map[i]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0ull) atomicAdd(&sums[v], red[0]);
+}
+
+__global__ void __launch_bounds__(256) clear_u64_kernel(unsigned long long* __restrict__ p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+}  // namespace tgs
+
+extern "C" int32_t tgs_view_error_sums(const uint16_t* E, int32_t n_views, int64_t pixels, uint64_t* sums,
+                                       void* stream) {
+  using namespace tgs;
+  TGS_REQUIRE(n_views >= 0 && n_views <= 65535, "tgs_view_error_sums: n_views %d out of range", n_views);
+  TGS_REQUIRE(pixels > 0 && pixels < (1ll << 31), "tgs_view_error_sums: pixels out of range");
+  if (n_views == 0) return TGS_OK;
+  TGS_REQUIRE(E && sums, "tgs_view_error_sums: null pointer");
+  hipStream_t s = as_stream(stream);
+  hipLaunchKernelGGL(clear_u64_kernel, dim3((unsigned)ceil_div(n_views, 256)), dim3(256), 0, s,
+                     (unsigned long long*)sums, n_views);
+  const unsigned bx = (unsigned)std::min<int64_t>(ceil_div(pixels, (int64_t)256 * 16), 256);
+  hipLaunchKernelGGL(view_error_sum_kernel, dim3(bx, (unsigned)n_views), dim3(256), 0, s, E, pixels,
+                     (unsigned long long*)sums);
+  return hip_status("tgs_view_error_sums");
+}

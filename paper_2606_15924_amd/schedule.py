@@ -1,0 +1,108 @@
+"""Training-loop scheduling on the host (Sec. 3.4, Eq. anchor_view and
+Eq. view_sampling; App. A, Eq. sin_rate and the schedule of the pixel rate
+r_tile and the view budget K_t).  The per-view mean errors come from the GPU
+(tgs_view_error_sums); the rest is a handful of scalars per step.
+
+Conventions (fixed so that runs are reproducible):
+* E_bar_v = (exact sum of E_v * 2^24) / (2^24 |Omega|) in FP64;
+* the view stack is the set of views not yet drawn, refilled with every
+  view when fewer than K remain;
+* the anchor is the stack's view of largest E_bar (lowest index on ties);
+* K - 1 companions are drawn without replacement from the rest of the stack
+  with weights exp(-lambda_d |c_u - c_a| - lambda_theta (1 - <d_u, d_a>))
+  (FP64): companion j takes the SplitMix64 counter value of
+  (seed, t, 0, V, j), r = (u >> 11) 2^-53 W_rem, and the first candidate in
+  ascending view index whose running weight exceeds r;
+* rho_t = 1 - clip(t / tau_until, 0, 1), r_t = clip(E_bar_t / (E_bar_init
+  + 1e-8), 0, 1), phi = sin(pi/2 sqrt(r_t)), a = 1 - rho_t phi;
+  r_tile = r_min + (r_max - r_min) a, K_t = floor(K_min + (K_max - K_min)
+  exp(-alpha a) + 1/2), r_min = lambda / K_max, r_max = lambda / K_min; the
+  pixel rate in permille is floor(1000 r_tile + 1/2) clipped to [1, 1000].
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import binding as B
+
+_M64 = (1 << 64) - 1
+_GOLDEN = 0x9E3779B97F4A7C15
+
+
+def _finalise(z: int) -> int:
+    """SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014)."""
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def counter_draw(seed: int, *fields: int) -> int:
+    """The 64-bit value of a counter tuple: each field absorbed as
+    h <- finalise(h + golden * (field + 1)), from h = seed."""
+    h = seed & _M64
+    for f in fields:
+        h = _finalise((h + _GOLDEN * (f + 1)) & _M64)
+    return h
+
+
+def view_errors(E_maps, pixels: int, dev) -> list:
+    """E_bar_v of each view's half error map (one GPU reduction per view)."""
+    sums = torch.empty(len(E_maps), dtype=torch.int64, device=dev)
+    for v, E in enumerate(E_maps):
+        B.tgs_view_error_sums(E, 1, pixels, sums[v:v + 1])
+    return [int(s) / (float(1 << 24) * pixels) for s in sums.cpu().tolist()]
+
+
+def _weight(cu, du, ca, da, lam_d, lam_t) -> float:
+    dx, dy, dz = cu[0] - ca[0], cu[1] - ca[1], cu[2] - ca[2]
+    dist = math.sqrt(dx * dx + dy * dy + dz * dz)
+    return math.exp(-lam_d * dist - lam_t * (1.0 - (du[0] * da[0] + du[1] * da[1] + du[2] * da[2])))
+
+
+def pick_views(stack, means, centres, dirs, K, lam_d, lam_t, seed, t):
+    """Anchor and companions of step t; returns (views, stack left)."""
+    V = len(means)
+    K = min(K, V)
+    pool = sorted(stack) if len(stack) >= K else list(range(V))
+    anchor = pool[0]
+    for u in pool[1:]:
+        if means[u] > means[anchor]:
+            anchor = u
+    views = [anchor]
+    cand = [u for u in pool if u != anchor]
+    ca, da = [float(x) for x in centres[anchor]], [float(x) for x in dirs[anchor]]
+    for j in range(K - 1):
+        w = [_weight([float(x) for x in centres[u]], [float(x) for x in dirs[u]], ca, da, lam_d, lam_t)
+             for u in cand]
+        r = (counter_draw(seed, t, 0, V, j) >> 11) * 2.0 ** -53 * sum(w)
+        run, k = 0.0, len(cand) - 1
+        for i, wi in enumerate(w):
+            run += wi
+            if run > r:
+                k = i
+                break
+        views.append(cand.pop(k))
+    return views, [u for u in pool if u not in views]
+
+
+@dataclass
+class Schedule:
+    tau_until: int = 3500
+    K_min: int = 3
+    K_max: int = 10
+    lam: float = 1.0        # tile sampling scale
+    alpha: float = 3.0
+
+    def at(self, t: int, E_t: float, E_init: float) -> tuple:
+        """(K_t, pixel rate in permille) of step t."""
+        r = min(max(E_t / (E_init + 1e-8), 0.0), 1.0)
+        phi = math.sin(math.pi / 2.0 * math.sqrt(r))
+        rho = 1.0 - min(max(t / self.tau_until, 0.0), 1.0)
+        a = 1.0 - rho * phi
+        r_min, r_max = self.lam / self.K_max, self.lam / self.K_min
+        r_tile = r_min + (r_max - r_min) * a
+        K = int(math.floor(self.K_min + (self.K_max - self.K_min) * math.exp(-self.alpha * a) + 0.5))
+        return K, min(max(int(math.floor(1000.0 * r_tile + 0.5)), 1), 1000)
