@@ -435,8 +435,6 @@ def density_control(p, cam, gt, dev, blends_per_step):
     the standalone back-projection kernel on the same samples, and the score
     plus both percentile selections over all Gaussians."""
     import torch
-
-    from paper_2606_15924_amd import binding as B
     tr = make_trainer(p, cam, gt, HEADLINE_RATE, dev, density_stats=True)
     res = run(tr, 20, 3)
     vb = tr._bufs[0]

@@ -258,6 +258,7 @@ class Trainer:
         self.dstats = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev) if cfg.density_stats else None
         # screen-space gradient statistics [sum |dL/d centre|, views, max radius, -]
         self.gstats = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev) if cfg.density_stats else None
+        self._select_ws = None   # percentile-selection workspace, made on first use
         if cfg.learned_tiles and cfg.rate_permille is not None and cfg.n_tiles_sel > 0:
             c0 = self.cams[0]
             n_t = ((c0.width + TILE - 1) // TILE) * ((c0.height + TILE - 1) // TILE)
@@ -414,7 +415,7 @@ class Trainer:
         selected.  Returns (densify, keep) uint8 masks, the two thresholds and
         the scores."""
         e, d, sc = self.density_scores(lambda_base, rho, eps)
-        if getattr(self, "_select_ws", None) is None:
+        if self._select_ws is None:
             self._select_ws = torch.empty(B.tgs_select_workspace_size(), dtype=torch.uint8, device=self.dev)
         thr = torch.empty(2, dtype=torch.float32, device=self.dev)
         masks = torch.empty((2, self.n), dtype=torch.uint8, device=self.dev)

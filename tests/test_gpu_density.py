@@ -1,9 +1,10 @@
 """GPU parity of the density-control statistics (Sec. 3.8): the
 back-projection of per-pixel errors, weights and distances onto the
 Gaussians (Eq. gauss_err_accum) and the difficulty score (Eq. gauss_score),
-and the percentile thresholds (an exact k-th largest, bit for bit) against
-the oracle, plus the telescoping property and the selection counts at the
-full training size.
+the percentile thresholds (an exact k-th largest, bit for bit), densify and
+prune, and the screen-space statistics against the oracle, plus the
+telescoping property, the selection counts and training on after a
+topology change at the full training size.
 
 Tolerances: every summed term is non-negative, so a per-Gaussian sum carries
 the relative error of its terms; a term's weight T alpha is a product of up
