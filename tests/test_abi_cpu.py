@@ -104,6 +104,38 @@ def test_invalid_arguments_are_rejected_before_any_launch(B):
     assert st == B.TGS_ERR_INVALID and "aligned" in lib.tgs_last_error().decode()
 
 
+def test_density_and_schedule_arguments_are_rejected_before_any_launch(B):
+    lib = B.lib()
+    P = ctypes.c_void_p(16)
+
+    def err(st, word):
+        assert st == B.TGS_ERR_INVALID and word in lib.tgs_last_error().decode(), lib.tgs_last_error()
+
+    rp = B.raster_params()
+    # stats slot array must be 16-byte aligned
+    err(lib.tgs_density_accumulate(P, P, P, 4, 3, 64, 48, None, None, None, 0, 0, ctypes.byref(rp), P, P, None,
+                                   10, ctypes.c_void_p(20), None), "aligned")
+    err(lib.tgs_density_score(P, 10, 0.5, 1.5, 1e-8, None, None, P, None), "rho")
+    err(lib.tgs_density_score(P, 10, 0.5, 0.5, 0.0, None, None, P, None), "eps")
+    ws = B.tgs_select_workspace_size()
+    assert ws >= 256 * 4
+    err(lib.tgs_select_kth_largest(P, 10, 0, P, P, ws, None), "k")
+    err(lib.tgs_select_kth_largest(P, 10, 11, P, P, ws, None), "k")
+    err(lib.tgs_select_kth_largest(P, 10, 3, P, P, 8, None), "workspace")
+    nk, nn = ctypes.c_int64(0), ctypes.c_int64(0)
+    tws = lib.tgs_density_topology_workspace_size(1000)
+    assert tws >= 4 * 4 * 1000
+    err(lib.tgs_density_topology_count(P, P, 1000, ctypes.byref(nk), ctypes.byref(nn), P, 16, None), "workspace")
+    err(lib.tgs_density_topology_apply(P, P, P, 1000, P, 0.0, P, tws, P, P, P, 2001, None), "n_out")
+    err(lib.tgs_grad_screen_accumulate(P, P, 10, ctypes.c_void_p(20), None), "aligned")
+    err(lib.tgs_view_error_sums(P, 3, 0, P, None), "pixels")
+    # empty inputs: nothing to do
+    assert lib.tgs_density_score(None, 0, 0.5, 0.5, 1e-8, None, None, None, None) == B.TGS_OK
+    assert lib.tgs_grad_screen_accumulate(None, None, 0, None, None) == B.TGS_OK
+    assert lib.tgs_view_error_sums(None, 0, 100, None, None) == B.TGS_OK
+    assert lib.tgs_density_topology_apply(P, P, P, 1000, P, 0.0, P, tws, None, None, None, 0, None) == B.TGS_OK
+
+
 def test_empty_inputs_are_no_ops(B):
     lib = B.lib()
     cam = B.tgs_camera()
