@@ -6,7 +6,7 @@ tile's reconstruction error from cheap per-(view, tile) features.  It is
 trained online on the errors the method itself measures (the tile means of
 the error map E of Sec. 3.3), so tile selection can favour tiles it expects
 to be poor in views not rendered recently.  The error-map sampler
-(Sec. 3.3) stays the reference and the judge of its ranking.
+(Sec. 3.3) stays the reference its ranking is scored against.
 
 Readings (none of this is fixed by the paper):
 * features, 32 per (view, tile):
