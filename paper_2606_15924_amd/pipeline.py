@@ -294,9 +294,17 @@ class Trainer:
         torch.cuda.synchronize()
         return {k: [a.elapsed_time(b) for a, b in v] for k, v in (self.events or {}).items()}
 
-    def buffers(self, key, cam) -> ViewBuffers:
+    def buffers(self, key, cam, rate_permille: int | None = None) -> ViewBuffers:
+        """Buffers of view slot ``key`` at the configured rate, or at
+        ``rate_permille`` (then kept per (slot, rate))."""
+        if rate_permille is not None:
+            slot, key = key, (key, rate_permille)
+            if key not in self._bufs:  # one rate per slot is kept: drop the slot's others
+                for k in [k for k in self._bufs if isinstance(k, tuple) and k[0] == slot]:
+                    del self._bufs[k]
         if key not in self._bufs:
-            n_pix = None if self.cfg.rate_permille is None else B.tgs_pixels_per_tile(self.cfg.rate_permille)
+            rate = self.cfg.rate_permille if rate_permille is None else rate_permille
+            n_pix = None if rate is None else B.tgs_pixels_per_tile(rate)
             self._bufs[key] = ViewBuffers(self.n, cam.width, cam.height, n_pix, self.cfg.n_tiles_sel, self.dev)
         return self._bufs[key]
 
@@ -310,8 +318,9 @@ class Trainer:
             vb.render_fwd(self.rp)
             B.tgs_error_init(vb.out, self.gts[v], cam.height, cam.width, self.E[v])
 
-    def step(self, views) -> list:
-        """One training step over ``views``; returns the per-view buffers."""
+    def step(self, views, rate_permille: int | None = None) -> list:
+        """One training step over ``views`` (at ``rate_permille`` if given,
+        else the configured rate); returns the per-view buffers."""
         self.step_count += 1
         t = self.step_count
         views = list(views)
@@ -319,7 +328,7 @@ class Trainer:
         if not views:
             self.grad.zero_()
         st = self._stage
-        used = [self.buffers(slot, self.cams[v]) for slot, v in enumerate(views)]
+        used = [self.buffers(slot, self.cams[v], rate_permille) for slot, v in enumerate(views)]
         slot_of = {id(vb): k for k, vb in enumerate(used)}
         self.touched.zero_()
         # the sample totals are cleared and the samplers run on the side

@@ -106,3 +106,38 @@ class Schedule:
         r_tile = r_min + (r_max - r_min) * a
         K = int(math.floor(self.K_min + (self.K_max - self.K_min) * math.exp(-self.alpha * a) + 0.5))
         return K, min(max(int(math.floor(1000.0 * r_tile + 0.5)), 1), 1000)
+
+
+def camera_pose(cam) -> tuple:
+    """Centre c = -R^T t and unit viewing direction (the camera's +z axis,
+    the third row of the world-to-camera R) of a tgs_camera."""
+    R = [[cam.R[3 * i + j] for j in range(3)] for i in range(3)]
+    t = [cam.t[i] for i in range(3)]
+    c = [-(R[0][k] * t[0] + R[1][k] * t[1] + R[2][k] * t[2]) for k in range(3)]
+    d = R[2]
+    n = math.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+    return c, [x / n for x in d]
+
+
+def run_schedule(tr, steps: int, sch: Schedule, lam_d: float, lam_t: float, seed: int, t0: int = 1):
+    """Sparse training driven by the schedule: each step reads the views'
+    mean errors (GPU), takes K_t and the pixel rate from the schedule,
+    picks the anchor and its companions and runs the step at that rate.
+    E_bar_init is the mean error when the run starts.  Returns the per-step
+    (views, K_t, rate in permille, the views' mean errors before the step)."""
+    cams = tr.cams
+    pixels = cams[0].width * cams[0].height
+    assert all(c.width * c.height == pixels for c in cams), "one image size"
+    poses = [camera_pose(c) for c in cams]
+    centres, dirs = [p[0] for p in poses], [p[1] for p in poses]
+    means = view_errors(tr.E, pixels, tr.dev)
+    e_init = sum(means) / len(means)
+    stack = list(range(len(cams)))
+    log = []
+    for t in range(t0, t0 + steps):
+        K, permille = sch.at(t, sum(means) / len(means), e_init)
+        views, stack = pick_views(stack, means, centres, dirs, K, lam_d, lam_t, seed, t)
+        tr.step(views, rate_permille=permille)
+        log.append((views, K, permille, means))
+        means = view_errors(tr.E, pixels, tr.dev)
+    return log

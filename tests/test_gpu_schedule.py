@@ -39,3 +39,38 @@ def test_host_view_errors_equal_the_oracle_means(B):
     maps = [synth.error_map(H, W, 310 + v) for v in range(4)]
     got = view_errors([torch.from_numpy(m.view(np.int16)).cuda() for m in maps], H * W, "cuda")
     assert got == [S.mean_view_error(m) for m in maps]
+
+
+def test_schedule_driven_training(B):
+    """Twelve steps of sparse training driven by the schedule on four views:
+    each step trains K_t distinct views at the scheduled rate, the first
+    anchor is the view of largest mean error, and the maps and parameters
+    move."""
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    from paper_2606_15924_amd.schedule import Schedule, run_schedule
+    from support import scene_c1
+    p, cams = scene_c1()
+    H, W = cams[0].height, cams[0].width
+    gts = [torch.from_numpy(synth.image(H, W, 320 + k)).cuda() for k in range(len(cams))]
+    E = [torch.zeros((H, W), dtype=torch.int16, device="cuda") for _ in cams]
+    A = [torch.zeros((H, W), dtype=torch.int16, device="cuda") for _ in cams]
+    tr = Trainer(torch.from_numpy(p).cuda(), cams, gts, StepConfig(rate_permille=250), E=E, A=A)
+    tr.init_error_maps(list(range(len(cams))))
+    p0 = tr.params.clone()
+    sch = Schedule(tau_until=10, K_min=1, K_max=3, lam=0.75, alpha=3.0)
+    log = run_schedule(tr, 12, sch, lam_d=0.5, lam_t=1.0, seed=7)
+    for t, (views, K, permille, means) in enumerate(log, start=1):
+        assert len(views) == K == len(set(views)) and 1 <= K <= 3
+        assert 250 <= permille <= 750                       # r_min = 0.25, r_max = 0.75
+        assert all(0 <= v < 4 for v in views)
+    e_init = float(np.mean(log[0][3]))
+    for t, (views, K, permille, means) in enumerate(log, start=1):
+        assert (K, permille) == sch.at(t, float(np.mean(means)), e_init), t
+    views, K, permille, means = log[0]
+    assert K == 2 and permille == 300                       # t = 1: rho = 0.9, phi = 1, a = 0.1
+    assert views[0] == int(np.argmax(means))
+    assert log[-1][1] == 1 and log[-1][2] == 750            # after tau_until: a = 1
+    assert torch.isfinite(tr.params).all() and not torch.equal(tr.params, p0)
+    # buffers: one rate per slot at most
+    slots = [k[0] for k in tr._bufs if isinstance(k, tuple)]
+    assert len(slots) == len(set(slots))
