@@ -35,3 +35,16 @@ def test_schedule_equals_the_oracle():
         for e in (1.2, 1.0, 0.6, 0.2, 0.01):
             ref = S.schedule(t, e, 1.0, 3500, 3, 10, 0.8, 3.0)
             assert sch.at(t, e, 1.0) == (ref["K"], ref["permille"])
+
+
+def test_camera_pose_matches_the_oracle_centre_and_looks_at_the_target():
+    import synth
+    from oracle import project
+    from paper_2606_15924_amd.binding import camera
+    for eye in [(2.4, -1.1, 1.3), (0.0, 0.0, 3.0), (-1.0, 2.0, 0.5)]:
+        cam = synth.look_at(eye, fx=300.0, fy=300.0, width=64, height=48)
+        c, d = H.camera_pose(camera(cam))
+        assert np.allclose(c, project.camera_center(cam), atol=1e-12)
+        # a look-at camera views the origin: the direction points from the centre to it
+        to_origin = -np.asarray(c) / np.linalg.norm(c)
+        assert np.allclose(d, to_origin, atol=1e-9), (eye, d, to_origin)
