@@ -119,12 +119,31 @@ def camera_pose(cam) -> tuple:
     return c, [x / n for x in d]
 
 
-def run_schedule(tr, steps: int, sch: Schedule, lam_d: float, lam_t: float, seed: int, t0: int = 1):
+@dataclass
+class DensityPlan:
+    """When and how density control runs inside the loop (the table's
+    tau_from, tau_until, Delta_dens, eta_topk, eta_final; lambda_base and the
+    split threshold are inputs).  The trainer needs density_stats on."""
+    t_from: int = 200
+    t_until: int = 3500
+    every: int = 100
+    eta_topk: float = 0.9
+    eta_final: float = 0.9
+    lambda_base: float = 0.5
+    log_split: float = math.log(0.01)
+    seed: int = 11
+
+
+def run_schedule(tr, steps: int, sch: Schedule, lam_d: float, lam_t: float, seed: int, t0: int = 1,
+                 density: DensityPlan | None = None):
     """Sparse training driven by the schedule: each step reads the views'
     mean errors (GPU), takes K_t and the pixel rate from the schedule,
     picks the anchor and its companions and runs the step at that rate.
-    E_bar_init is the mean error when the run starts.  Returns the per-step
-    (views, K_t, rate in permille, the views' mean errors before the step)."""
+    With ``density``, every ``every`` steps from ``t_from`` to ``t_until``
+    the accumulated statistics select, densify and prune (split draws from a
+    seeded generator), and the sums restart.  E_bar_init is the mean error
+    when the run starts.  Returns the per-step (views, K_t, rate in
+    permille, the views' mean errors before the step, Gaussians after it)."""
     cams = tr.cams
     pixels = cams[0].width * cams[0].height
     assert all(c.width * c.height == pixels for c in cams), "one image size"
@@ -138,6 +157,12 @@ def run_schedule(tr, steps: int, sch: Schedule, lam_d: float, lam_t: float, seed
         K, permille = sch.at(t, sum(means) / len(means), e_init)
         views, stack = pick_views(stack, means, centres, dirs, K, lam_d, lam_t, seed, t)
         tr.step(views, rate_permille=permille)
-        log.append((views, K, permille, means))
+        if density is not None and density.t_from <= t <= density.t_until and t % density.every == 0:
+            rho = 1.0 - min(max(t / sch.tau_until, 0.0), 1.0)
+            dm, km, _, _ = tr.density_select(density.lambda_base, rho, density.eta_topk, density.eta_final)
+            gen = torch.Generator(device=tr.dev).manual_seed(density.seed + t)
+            z = torch.randn((tr.n, 3), generator=gen, device=tr.dev)
+            tr.densify_and_prune(dm, km, z, density.log_split)
+        log.append((views, K, permille, means, tr.n))
         means = view_errors(tr.E, pixels, tr.dev)
     return log

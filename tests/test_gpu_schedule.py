@@ -59,14 +59,14 @@ def test_schedule_driven_training(B):
     p0 = tr.params.clone()
     sch = Schedule(tau_until=10, K_min=1, K_max=3, lam=0.75, alpha=3.0)
     log = run_schedule(tr, 12, sch, lam_d=0.5, lam_t=1.0, seed=7)
-    for t, (views, K, permille, means) in enumerate(log, start=1):
+    for t, (views, K, permille, means, _) in enumerate(log, start=1):
         assert len(views) == K == len(set(views)) and 1 <= K <= 3
         assert 250 <= permille <= 750                       # r_min = 0.25, r_max = 0.75
         assert all(0 <= v < 4 for v in views)
     e_init = float(np.mean(log[0][3]))
-    for t, (views, K, permille, means) in enumerate(log, start=1):
+    for t, (views, K, permille, means, _) in enumerate(log, start=1):
         assert (K, permille) == sch.at(t, float(np.mean(means)), e_init), t
-    views, K, permille, means = log[0]
+    views, K, permille, means, _ = log[0]
     assert K == 2 and permille == 300                       # t = 1: rho = 0.9, phi = 1, a = 0.1
     assert views[0] == int(np.argmax(means))
     assert log[-1][1] == 1 and log[-1][2] == 750            # after tau_until: a = 1
@@ -74,3 +74,29 @@ def test_schedule_driven_training(B):
     # buffers: one rate per slot at most
     slots = [k[0] for k in tr._bufs if isinstance(k, tuple)]
     assert len(slots) == len(set(slots))
+
+
+def test_schedule_driven_training_with_density_control(B):
+    """The loop with density control every four steps from step 4 to 10:
+    the Gaussian count changes only there, by what the selections give,
+    and training continues on the new counts."""
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    from paper_2606_15924_amd.schedule import DensityPlan, Schedule, run_schedule
+    from support import scene_c1
+    p, cams = scene_c1()
+    H, W = cams[0].height, cams[0].width
+    gts = [torch.from_numpy(synth.image(H, W, 330 + k)).cuda() for k in range(len(cams))]
+    E = [torch.zeros((H, W), dtype=torch.int16, device="cuda") for _ in cams]
+    A = [torch.zeros((H, W), dtype=torch.int16, device="cuda") for _ in cams]
+    tr = Trainer(torch.from_numpy(p).cuda(), cams, gts, StepConfig(rate_permille=250, density_stats=True),
+                 E=E, A=A)
+    tr.init_error_maps(list(range(len(cams))))
+    n0 = tr.n
+    plan = DensityPlan(t_from=4, t_until=10, every=4, eta_topk=0.9, eta_final=0.95, log_split=float(np.log(0.02)))
+    log = run_schedule(tr, 12, Schedule(tau_until=10, K_min=1, K_max=3, lam=0.75), 0.5, 1.0, seed=7,
+                       density=plan)
+    counts = [n0] + [entry[4] for entry in log]
+    changed = [t for t in range(1, 13) if counts[t] != counts[t - 1]]
+    assert changed == [4, 8]
+    assert tr.n == counts[-1] and tr.params.shape == (59, tr.n) and tr.dstats.shape == (tr.n, 4)
+    assert torch.isfinite(tr.params).all()
