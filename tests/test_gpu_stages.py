@@ -187,6 +187,32 @@ def test_sampler_bit_exact(B, W, H, n_pix, n_sel, zero, pred):
             assert np.array_equal(got, want), t
 
 
+@pytest.mark.parametrize("hard,stable", [(0, 0), (1000, 0), (0, 1000)])
+def test_sampler_split_extremes_bit_exact(B, hard, stable):
+    """The sampler with the whole budget in one class: all mixed (uniform
+    random pixels per tile, the random-pixel-sampling baseline), all error
+    draws, all largest-age."""
+    W, H, n_pix = 150, 107, 64
+    E = synth.error_map(H, W, 34, zero_frac=0.2)
+    A = synth.age_map(H, W, 35)
+    sp = SampleParams(n_pix=n_pix, hard_permille=hard, stable_permille=stable)
+    bsp = B.sample_params(n_pix, hard, stable, seed=3, step=6, view=1)
+    n_st = B.tgs_sample_tile_count(H, W, bsp)
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    vt = torch.empty(n_st, dtype=torch.int32, device="cuda")
+    off = torch.empty(n_st + 1, dtype=torch.int32, device="cuda")
+    pix = torch.empty(n_st * n_pix, dtype=torch.uint8, device="cuda")
+    slot = torch.empty(TX * TY, dtype=torch.int32, device="cuda")
+    totals = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ws = torch.empty(B.tgs_sample_workspace_size(H, W), dtype=torch.uint8, device="cuda")
+    B.tgs_sample(dev(E), dev(A), H, W, bsp, vt, off, pix, slot, totals, ws)
+    ref = sampler.sample_view(E, A, sp, 3, 6, 1)
+    g_off = host(off)
+    assert np.array_equal(host(vt), ref["valid_tiles"])
+    assert np.array_equal(g_off, ref["tile_off"])
+    assert np.array_equal(host(pix)[: g_off[-1]], ref["pix"])
+
+
 # ------------------------------------------------------------------ forward render
 def _render_case(case):
     if case == "c1_sparse":
