@@ -48,3 +48,14 @@ def test_camera_pose_matches_the_oracle_centre_and_looks_at_the_target():
         # a look-at camera views the origin: the direction points from the centre to it
         to_origin = -np.asarray(c) / np.linalg.norm(c)
         assert np.allclose(d, to_origin, atol=1e-9), (eye, d, to_origin)
+
+
+def test_view_sets_at_the_edges():
+    c = np.zeros((3, 3))
+    d = np.tile([0.0, 0.0, 1.0], (3, 1))
+    means = [0.2, 0.2, 0.1]
+    for K in (1, 3, 7):                                  # K above the view count is clamped
+        vo, so = S.select_views([], means, c, d, K, 1.0, 1.0, seed=2, t=1)
+        vh, sh = H.pick_views([], means, c, d, K, 1.0, 1.0, seed=2, t=1)
+        assert vo == vh and so == sh and vh[0] == 0 and len(vh) == min(K, 3)
+    assert H.pick_views([0], [0.5], [[0, 0, 0]], [[0, 0, 1]], 1, 1.0, 1.0, 0, 0) == ([0], [])
