@@ -181,6 +181,8 @@ int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t
  *   touched      nullable [n] uint8: set to 1 for Gaussians with a pair;
  *                other entries are left as they are, so one array
  *                cleared once collects the Gaussians of several views
+ *                (tgs_render_bwd marks the narrower set of Gaussians
+ *                composited at a sample)
  *   n_pairs      host out: number of pairs in valid tiles
  * capacity must hold every listed tile (valid or not) of every Gaussian
  * that has a pair in a valid tile; when it does not, the call returns
@@ -236,13 +238,18 @@ int32_t tgs_render_fwd(const float* splat, const uint32_t* vals, const uint32_t*
  *            c * TGS_RENDER_CHUNK_LEN from the recorded state (the last chunk
  *            takes the rest of the list); the per-pixel arithmetic is the
  *            same as the single-workgroup replay, only the order of the
- *            gradient atomics differs. */
+ *            gradient atomics differs.
+ *   touched  nullable [n] uint8: set to 1 for every Gaussian composited at
+ *            one of the samples (the Gaussians the step's gradient reaches:
+ *            the set the sparse update of Sec. 3.9 moves); other entries are
+ *            left as they are, so one array cleared once collects the
+ *            Gaussians of several views. */
 int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, const uint32_t* ranges,
                        int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
                        const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
                        int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
                        const float* out, const uint32_t* ncontrib, const float* dL_dout,
-                       float* g2d, const float* state, void* stream);
+                       float* g2d, const float* state, uint8_t* touched, void* stream);
 
 /* Sparse supervision of one view (Sec. 3.7: Charbonnier L1 per pixel plus
  * tile NCC with the gradient-balanced weight of Eq. ncc_weight_auto, summed
@@ -305,7 +312,11 @@ int32_t tgs_density_accumulate(const float* splat, const uint32_t* vals, const u
 /* tgs_render_bwd that also adds the density-control sums of
  * tgs_density_accumulate (Sec. 3.8) for the same samples: the backward's
  * replay already forms each composited Gaussian's weight w = T alpha, and
- * the three sums join the gradient's wave reduction.  g2d gets what
+ * the three sums join the gradient's wave reduction.  It also adds, in
+ * stats[i][3], the absolute-gradient statistic of densification (the
+ * threshold tau_grad^abs of the hyper-parameter table): the sum over the
+ * rendered pixels of the norm of each pixel's own centre gradient in NDC
+ * units, |(W/2 dL_p/dx, H/2 dL_p/dy)|.  g2d and touched get what
  * tgs_render_bwd gives (same arithmetic; float atomics in another order);
  * err, n and stats are as in tgs_density_accumulate (n > 0). */
 int32_t tgs_render_bwd_density(const float* splat, const uint32_t* vals, const uint32_t* ranges,
@@ -313,8 +324,8 @@ int32_t tgs_render_bwd_density(const float* splat, const uint32_t* vals, const u
                                const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
                                int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
                                const float* out, const uint32_t* ncontrib, const float* dL_dout,
-                               float* g2d, const float* state, const float* err, int64_t n, float* stats,
-                               void* stream);
+                               float* g2d, const float* state, uint8_t* touched, const float* err, int64_t n,
+                               float* stats, void* stream);
 
 /* Difficulty score (Sec. 3.8, Eq. gauss_score) from tgs_density_accumulate's
  * sums, in FP32: e_i = E_i / (W_i + eps), d_i = D_i / (W_i + eps),
@@ -370,15 +381,38 @@ int32_t tgs_density_topology_apply(const float* params, const float* m, const fl
 /* Screen-space statistics of densification (Alg. 1 step 8, second line;
  * the gradient threshold tau_grad of the hyper-parameter table), per view
  * after its backward: for every Gaussian projected in the view
- * (radius > 0), acc[i][0] += |(g2d[i][0], g2d[i][1])| (the 2D centre
- * gradient, pixel units), acc[i][1] += 1, acc[i][2] = max(acc[i][2],
- * radius); acc[i][3] is not touched.
+ * (radius > 0), acc[i][0] += |(W/2 g2d[i][0], H/2 g2d[i][1])| (the 2D centre
+ * gradient in NDC units, the units the table's thresholds are stated in),
+ * acc[i][1] += 1, acc[i][2] = max(acc[i][2], radius); acc[i][3] is not
+ * touched.
  *   g2d [n][9] (tgs_render_bwd output), radius [n] (tgs_project output),
+ *   width, height  the view's image size (W, H above),
  *   acc [n][4] float, 16-byte aligned; the caller clears it.
  * tgs_grad_screen_mean: out[i] = acc[i][0] / acc[i][1], 0 where never
  * projected. */
-int32_t tgs_grad_screen_accumulate(const float* g2d, const int32_t* radius, int64_t n, float* acc,
-                                   void* stream);
+int32_t tgs_grad_screen_accumulate(const float* g2d, const int32_t* radius, int64_t n, int32_t width,
+                                   int32_t height, float* acc, void* stream);
+
+/* Both selections of one density step (Sec. 3.8: percentile thresholds of
+ * the score; the gradient thresholds tau_grad and tau_grad^abs of the
+ * hyper-parameter table gate densification), in one pass:
+ *   keep[i]    = prune ? scores[i] >= thr[1] : 1
+ *   densify[i] = keep[i] and scores[i] >= thr[0] and
+ *                (gmean_i >= tau_grad or amean_i >= tau_grad_abs)
+ * with gmean_i = gstats[i][0] / gstats[i][1] (tgs_grad_screen_accumulate
+ * sums) and amean_i = dstats[i][3] / gstats[i][1] (the absolute statistic of
+ * tgs_render_bwd_density), both FP32; a Gaussian never projected
+ * (gstats[i][1] = 0) is not densified.  Scores compare in the total order of
+ * tgs_threshold_mask.
+ *   scores  [n]; thr  device [2] (densify threshold, keep threshold, e.g.
+ *           from tgs_select_kth_largest)
+ *   gstats, dstats  [n][4], 16-byte aligned; dstats nullable (then only
+ *           tau_grad gates)
+ *   prune   nonzero on a final-pruning step
+ *   densify, keep  [n] uint8, written. */
+int32_t tgs_density_masks(const float* scores, const float* gstats, const float* dstats, int64_t n,
+                          const float* thr, float tau_grad, float tau_grad_abs, int32_t prune,
+                          uint8_t* densify, uint8_t* keep, void* stream);
 int32_t tgs_grad_screen_mean(const float* acc, int64_t n, float* out, void* stream);
 
 /* Per-view error sums for the anchor view (Sec. 3.4, Eq. anchor_view):

@@ -90,12 +90,53 @@ def percentile_count(n: int, fraction: float) -> int:
     return max(1, int(np.ceil(fraction * n - 1e-9)))
 
 
-def select_masks(s: np.ndarray, eta_topk: float, eta_final: float) -> dict:
-    """Densification and final-pruning selections by percentile thresholds."""
+def select_masks(s: np.ndarray, eta_topk: float, eta_final: float, gate=None, prune: bool = True) -> dict:
+    """Densification and final-pruning selections by percentile thresholds.
+
+    ``gate`` (bool [n], optional) is the gradient condition a densified
+    Gaussian must also meet (``gradient_gate``); with ``prune`` False (a
+    density step that is not a final-pruning step) every Gaussian is kept.
+    A Gaussian is densified only if it is kept."""
     n = s.size
     t_d = kth_largest(s, percentile_count(n, 1.0 - eta_topk))
     t_k = kth_largest(s, percentile_count(n, eta_final))
-    return dict(densify=s >= t_d, keep=s >= t_k, thr_densify=t_d, thr_keep=t_k)
+    keep = (s >= t_k) if prune else np.ones(n, dtype=bool)
+    dens = (s >= t_d) & keep
+    if gate is not None:
+        dens &= np.asarray(gate, dtype=bool)
+    return dict(densify=dens, keep=keep, thr_densify=t_d, thr_keep=t_k)
+
+
+def gradient_gate(acc: np.ndarray, abs_sum: np.ndarray, tau_grad: float, tau_abs: float) -> np.ndarray:
+    """The gradient condition of densification (the thresholds tau_grad and
+    tau_grad^abs of the hyper-parameter table): the mean screen-space centre
+    gradient norm per view in which the Gaussian was projected reaches
+    tau_grad, or the mean per view of the absolute statistic (the sum over
+    pixels of each pixel's own centre-gradient norm) reaches tau_grad^abs.
+    Both in NDC units; a Gaussian never projected fails.  Compared in FP32,
+    as the GPU compares them."""
+    acc = np.asarray(acc, dtype=np.float32)
+    views = acc[:, 1]
+    seen = views > 0
+    safe = np.where(seen, views, np.float32(1))
+    g = np.where(seen, acc[:, 0] / safe, np.float32(0))
+    a = np.where(seen, np.asarray(abs_sum, dtype=np.float32) / safe, np.float32(0))
+    return seen & ((g >= np.float32(tau_grad)) | (a >= np.float32(tau_abs)))
+
+
+def scene_extent(centres) -> float:
+    """Scene size for the percent-dense split rule (the 3D Gaussian splatting
+    convention): 1.1 times the largest distance of a camera centre from the
+    mean camera centre."""
+    c = np.asarray(centres, dtype=np.float64)
+    return 1.1 * float(np.linalg.norm(c - c.mean(axis=0), axis=1).max())
+
+
+def split_log_threshold(percent_dense: float, extent: float) -> float:
+    """A densified Gaussian is split when its largest scale exceeds
+    rho_dense times the scene extent (percent dense of the hyper-parameter
+    table), i.e. its largest log-scale exceeds ln(rho_dense extent)."""
+    return float(np.log(percent_dense * extent))
 
 
 SPLIT_FACTOR = 1.6   # scale divisor of a split (the 3D Gaussian splatting convention)
@@ -141,17 +182,19 @@ def apply_topology(params: np.ndarray, m: np.ndarray, v: np.ndarray, keep, densi
                 n_keep=int(keep.sum()), n_new=int(dens.sum()), split=split)
 
 
-def grad_screen_accumulate(acc: np.ndarray, g2d: np.ndarray, radius: np.ndarray) -> np.ndarray:
+def grad_screen_accumulate(acc: np.ndarray, g2d: np.ndarray, radius: np.ndarray, width: int,
+                           height: int) -> np.ndarray:
     """Screen-space statistics for densification (Alg. 1 step 8, second
     line, and the gradient threshold tau_grad of the hyper-parameter table),
     per view: acc[i] = (sum of |dL/d centre_i|, views in which i was
     projected (radius > 0), largest radius, -).  Reading: the norm is taken
-    of the 2D centre gradient of that view's backward (pixel units), as in
-    the 3D Gaussian splatting densification statistic."""
+    of the 2D centre gradient of that view's backward in NDC units (the pixel
+    gradient times (W/2, H/2)), the units of the 3D Gaussian splatting
+    densification statistic that the table's thresholds are stated for."""
     acc = np.array(acc, dtype=np.float64, copy=True)
     g = np.asarray(g2d, dtype=np.float64)
     vis = np.asarray(radius) > 0
-    acc[:, 0] += np.where(vis, np.hypot(g[:, 0], g[:, 1]), 0.0)
+    acc[:, 0] += np.where(vis, np.hypot(0.5 * width * g[:, 0], 0.5 * height * g[:, 1]), 0.0)
     acc[:, 1] += vis
     acc[:, 2] = np.maximum(acc[:, 2], np.where(vis, np.asarray(radius, dtype=np.float64), 0.0))
     return acc

@@ -26,7 +26,9 @@ def forward_view(params, cam, samples, rp: RasterParams):
 def train_step(params, m, v, cams, gts, E, A, step: int, sp: SampleParams, rp: RasterParams,
                lp: LossParams, op: OptimParams, seed: int, beta: float = 0.4, views=None):
     """One step over the views ``views`` (indices into cams).  Returns the new
-    state and per-view diagnostics.  E, A are lists of per-view maps."""
+    state and per-view diagnostics.  E, A are lists of per-view maps.  The
+    sparse update touches the Gaussians composited at a sampled pixel of one
+    of the views (the support of the step's gradient)."""
     views = list(range(len(cams))) if views is None else list(views)
     samples = {vi: sampler.sample_view(E[vi], A[vi], sp, seed, step, vi) for vi in views}
     P_step = sum(int(s["tile_off"][-1]) for s in samples.values())
@@ -45,7 +47,7 @@ def train_step(params, m, v, cams, gts, E, A, step: int, sp: SampleParams, rp: R
         g2d = render.render_pixels_bwd(fv["proj"], fv["vals"], fv["ranges"], fv["xs"], fv["ys"],
                                        ls["dL"], rp)
         grad += project_bwd.project_bwd(params, cams[vi], fv["proj"], g2d, rp)
-        touched[np.unique(fv["vals"])] = True
+        touched |= fv["out"]["composited"]
         diag[vi] = dict(fwd=fv, loss=ls, g2d=g2d, samples=samples[vi])
     newp, newm, newv = optim.optimizer_step(params, grad, m, v, touched, op, step)
     return dict(params=newp, m=newm, v=newv, E=E, A=A, grad=grad, touched=touched,

@@ -67,7 +67,9 @@ def render_pixels(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs: n
                   guard_T: float = 2e-3) -> dict:
     """Render the pixels (xs[i], ys[i]) (any order; grouped by tile internally).
 
-    Returns rgb [P, 3], T [P], n_contrib [P], n_eval [P], n_blend [P], flag [P]."""
+    Returns rgb [P, 3], T [P], n_contrib [P], n_eval [P], n_blend [P], flag [P]
+    and composited [N] (the Gaussians composited at one of the pixels at
+    least: the support of the gradient, what the sparse update touches)."""
     rp = rp.f64()
     TX = proj["TX"]
     xs = np.asarray(xs, dtype=np.int64)
@@ -79,6 +81,7 @@ def render_pixels(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs: n
     neval = np.zeros(P, dtype=np.int64)
     nblend = np.zeros(P, dtype=np.int64)
     flag = np.zeros(P, dtype=bool)
+    composited = np.zeros(proj["opacity"].size, dtype=bool)
     bg = np.asarray(rp.bg, dtype=np.float64)
     tiles = (ys // TILE) * TX + (xs // TILE)
     for t in np.unique(tiles):
@@ -90,6 +93,7 @@ def render_pixels(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs: n
             out[sel] = bg
             continue
         ev = _tile_eval(proj, gids, xs[sel].astype(np.float64), ys[sel].astype(np.float64), rp)
+        composited[gids[ev["contrib"].any(axis=0)]] = True
         w = np.where(ev["contrib"], ev["T_before"] * ev["alpha"], 0.0)
         col = proj["rgb"][:, gids].T                                  # [K, 3]
         # running sums/products taken left to right, as the scalar loop does
@@ -108,12 +112,13 @@ def render_pixels(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs: n
         near_max = np.abs(ev["araw"] - rp.alpha_max) <= guard * rp.alpha_max
         near_T = ev["ok"] & (np.abs(ev["T_after"] - rp.T_min) <= guard_T * rp.T_min)
         flag[sel] = (evaluated & (near_min | near_max | near_T)).any(axis=1)
-    return dict(rgb=out, T=T_out, n_contrib=ncon, n_eval=neval, n_blend=nblend, flag=flag)
+    return dict(rgb=out, T=T_out, n_contrib=ncon, n_eval=neval, n_blend=nblend, flag=flag,
+                composited=composited)
 
 
 def render_pixels_bwd(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs, ys,
                       dL_drgb: np.ndarray, rp: RasterParams = RasterParams(),
-                      with_abs: bool = False):
+                      with_abs: bool = False, centre_abs_scale=None):
     """Exact adjoint of ``render_pixels``: given dL/dI at the pixels, return
     dL/d(screen-space splat parameters) per Gaussian, g2d [9, N] =
     (mean2d x, y; conic a, b, c; opacity; rgb r, g, b).
@@ -128,12 +133,20 @@ def render_pixels_bwd(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, x
     each term, where dL/dalpha is replaced by the magnitude of its two parts,
     sum_ch |g| (T |c| + (|I| + |C_{<=k}|) / (1 - alpha)).  A front-to-back
     evaluation obtains B_k as I - C_{<=k}, a difference of two O(|I|)
-    numbers, so its rounding error scales with |I|, not with |B_k|."""
+    numbers, so its rounding error scales with |I|, not with |B_k|.
+
+    With ``centre_abs_scale = (sx, sy)`` it also returns, per Gaussian, the
+    sum over pixels of the norm of that pixel's own centre gradient in scaled
+    units, |(sx dL_p/dx, sy dL_p/dy)| (the absolute-gradient statistic of
+    densification, Sec. 3.8; sx = W/2, sy = H/2 turn pixel units into NDC
+    units): the norm is taken per pixel before summing, so pixels pulling the
+    centre in opposite directions do not cancel."""
     rp = rp.f64()
     TX = proj["TX"]
     N = proj["opacity"].size
     g2d = np.zeros((9, N))
     g2d_abs = np.zeros((9, N))
+    cabs = np.zeros(N)
     xs = np.asarray(xs, dtype=np.int64)
     ys = np.asarray(ys, dtype=np.int64)
     g = np.asarray(dL_drgb, dtype=np.float64)
@@ -171,6 +184,9 @@ def render_pixels_bwd(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, x
                  w * gp[:, 0:1], w * gp[:, 1:2], w * gp[:, 2:3]]
         for row, tm in enumerate(terms):
             np.add.at(g2d[row], gids, tm.sum(axis=0))
+        if centre_abs_scale is not None:
+            sx, sy = centre_abs_scale
+            np.add.at(cabs, gids, np.hypot(sx * terms[0], sy * terms[1]).sum(axis=0))
         if with_abs:
             mag = np.einsum("pkc,pc->pk", Tb[:, :, None] * np.abs(col)[None, :, :]
                             + (np.abs(Cp)[:, None, :] + np.abs(acc)) / (1.0 - alpha)[:, :, None],
@@ -181,7 +197,10 @@ def render_pixels_bwd(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, x
                      np.where(unclamped, G * mag, 0.0)] + [np.abs(tm) for tm in terms[6:]]
             for row, sc in enumerate(scale):
                 np.add.at(g2d_abs[row], gids, sc.sum(axis=0))
-    return (g2d, g2d_abs) if with_abs else g2d
+    res = (g2d, g2d_abs) if with_abs else (g2d,)
+    if centre_abs_scale is not None:
+        res = res + (cabs,)
+    return res if len(res) > 1 else res[0]
 
 
 def dense_pixels(W: int, H: int):

@@ -86,7 +86,7 @@ PROTOTYPES = {
     "tgs_render_fwd": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
                               ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P]),
     "tgs_render_bwd": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
-                              ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P]),
+                              ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P]),
     "tgs_loss": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _I32, _P, ctypes.POINTER(tgs_loss_params),
                         _P, _P, _P, _P, _P]),
     "tgs_ema_age_update": (_I32, [_P, _P, _I32, _I32, _P, _P, _P, _P, ctypes.c_float, _P]),
@@ -94,12 +94,14 @@ PROTOTYPES = {
     "tgs_density_accumulate": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
                                       ctypes.POINTER(tgs_raster_params), _P, _P, _P, _I64, _P, _P]),
     "tgs_render_bwd_density": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
-                                      ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _I64, _P, _P]),
+                                      ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P, _I64, _P,
+                                      _P]),
     "tgs_density_score": (_I32, [_P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P]),
     "tgs_density_topology_workspace_size": (_SZ, [_I64]),
     "tgs_density_topology_count": (_I32, [_P, _P, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P, _SZ, _P]),
     "tgs_density_topology_apply": (_I32, [_P, _P, _P, _I64, _P, ctypes.c_float, _P, _SZ, _P, _P, _P, _I64, _P]),
-    "tgs_grad_screen_accumulate": (_I32, [_P, _P, _I64, _P, _P]),
+    "tgs_grad_screen_accumulate": (_I32, [_P, _P, _I64, _I32, _I32, _P, _P]),
+    "tgs_density_masks": (_I32, [_P, _P, _P, _I64, _P, ctypes.c_float, ctypes.c_float, _I32, _P, _P, _P]),
     "tgs_grad_screen_mean": (_I32, [_P, _I64, _P, _P]),
     "tgs_view_error_sums": (_I32, [_P, _I32, _I64, _P, _P]),
     "tgs_select_workspace_size": (_SZ, []),
@@ -266,11 +268,12 @@ def tgs_render_fwd(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_t
 
 
 def tgs_render_bwd(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
-                   n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL_dout, g2d, state=None):
+                   n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL_dout, g2d, state=None,
+                   touched=None):
     _check(lib().tgs_render_bwd(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
                                 _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
                                 ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(dL_dout), _ptr(g2d),
-                                _ptr(state), _stream()), "tgs_render_bwd")
+                                _ptr(state), _ptr(touched), _stream()), "tgs_render_bwd")
 
 
 def tgs_loss(out, gt, height, width, valid_tiles, tile_off, pix, n_st, totals, lp: tgs_loss_params,
@@ -301,11 +304,11 @@ def tgs_density_accumulate(splat, vals, ranges, tiles_x, tiles_y, width, height,
 
 def tgs_render_bwd_density(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
                            n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL_dout, g2d, err, n, stats,
-                           state=None):
+                           state=None, touched=None):
     _check(lib().tgs_render_bwd_density(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
                                         _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
                                         ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(dL_dout), _ptr(g2d),
-                                        _ptr(state), _ptr(err), n, _ptr(stats), _stream()),
+                                        _ptr(state), _ptr(touched), _ptr(err), n, _ptr(stats), _stream()),
            "tgs_render_bwd_density")
 
 
@@ -333,9 +336,15 @@ def tgs_density_topology_apply(params, m, v, n, z, log_split, ws, params_out, m_
                                             _ptr(v_out), n_out, _stream()), "tgs_density_topology_apply")
 
 
-def tgs_grad_screen_accumulate(g2d, radius, n, acc):
-    _check(lib().tgs_grad_screen_accumulate(_ptr(g2d), _ptr(radius), n, _ptr(acc), _stream()),
+def tgs_grad_screen_accumulate(g2d, radius, n, width, height, acc):
+    _check(lib().tgs_grad_screen_accumulate(_ptr(g2d), _ptr(radius), n, width, height, _ptr(acc), _stream()),
            "tgs_grad_screen_accumulate")
+
+
+def tgs_density_masks(scores, gstats, dstats, n, thr, tau_grad, tau_grad_abs, prune, densify, keep):
+    _check(lib().tgs_density_masks(_ptr(scores), _ptr(gstats), _ptr(dstats), n, _ptr(thr), float(tau_grad),
+                                   float(tau_grad_abs), int(prune), _ptr(densify), _ptr(keep), _stream()),
+           "tgs_density_masks")
 
 
 def tgs_grad_screen_mean(acc, n, out):

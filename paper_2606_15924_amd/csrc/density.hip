@@ -219,23 +219,53 @@ __global__ void __launch_bounds__(256) topo_apply_kernel(const float* __restrict
 
 // ------------------------------------------------------------------ screen-space statistics
 // Per view, after its backward: the norm of each projected Gaussian's 2D
-// centre gradient (g2d fields 0-1) is added to acc[i][0], the view count
-// to acc[i][1], and acc[i][2] keeps the largest radius (the statistics the
-// gradient threshold of densification reads).  16 bytes read-modify-written
-// and 8 + 4 read per Gaussian.
+// centre gradient (g2d fields 0-1) in NDC units (the pixel gradient times
+// W/2 and H/2) is added to acc[i][0], the view count to acc[i][1], and
+// acc[i][2] keeps the largest radius (the statistics the gradient threshold
+// of densification reads).  16 bytes read-modify-written and 8 + 4 read per
+// Gaussian.
 __global__ void __launch_bounds__(256) grad_screen_kernel(const float* __restrict__ g2d,
                                                           const int32_t* __restrict__ radius, int64_t n,
-                                                          float4* __restrict__ acc) {
+                                                          float sx, float sy, float4* __restrict__ acc) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const int32_t r = radius[i];
   if (r <= 0) return;
-  const float gx = g2d[9 * i], gy = g2d[9 * i + 1];
+  const float gx = sx * g2d[9 * i], gy = sy * g2d[9 * i + 1];
   float4 a = acc[i];
   a.x += sqrtf(gx * gx + gy * gy);
   a.y += 1.f;
   a.z = fmaxf(a.z, (float)r);
   acc[i] = a;
+}
+
+// Both selections of one density step in one pass (Sec. 3.8 percentile
+// thresholds, gated by the gradient thresholds tau_grad and tau_grad^abs of
+// the hyper-parameter table): keep = s >= thr[1] on a final-pruning step,
+// else 1; densify = keep and s >= thr[0] and (gmean >= tau_grad or
+// amean >= tau_abs), with gmean = gstats[i][0] / gstats[i][1] and
+// amean = dstats[i][3] / gstats[i][1] (means over the views in which the
+// Gaussian was projected; never projected: not densified).  The score
+// comparisons use the total order of tgs_threshold_mask.
+__global__ void __launch_bounds__(256) density_masks_kernel(const float* __restrict__ sc,
+                                                            const float4* __restrict__ gstats,
+                                                            const float4* __restrict__ dstats, int64_t n,
+                                                            const float* __restrict__ thr, float tau_grad,
+                                                            float tau_abs, int prune, uint8_t* __restrict__ dens,
+                                                            uint8_t* __restrict__ keep) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = order_key(sc[i]);
+  const bool kp = prune == 0 || k >= order_key(thr[1]);
+  const float4 g = gstats[i];
+  bool gate = false;
+  if (g.y > 0.f) {
+    const float gm = g.x / g.y;
+    const float am = dstats != nullptr ? dstats[i].w / g.y : 0.f;
+    gate = gm >= tau_grad || (dstats != nullptr && am >= tau_abs);
+  }
+  keep[i] = kp ? 1u : 0u;
+  dens[i] = (kp && gate && k >= order_key(thr[0])) ? 1u : 0u;
 }
 
 __global__ void __launch_bounds__(256) grad_screen_mean_kernel(const float4* __restrict__ acc, int64_t n,
@@ -250,15 +280,30 @@ __global__ void __launch_bounds__(256) grad_screen_mean_kernel(const float4* __r
 
 using namespace tgs;
 
-extern "C" int32_t tgs_grad_screen_accumulate(const float* g2d, const int32_t* radius, int64_t n, float* acc,
-                                              void* stream) {
+extern "C" int32_t tgs_grad_screen_accumulate(const float* g2d, const int32_t* radius, int64_t n, int32_t width,
+                                              int32_t height, float* acc, void* stream) {
   TGS_REQUIRE(n >= 0 && n < (1ll << 31), "tgs_grad_screen_accumulate: n out of range");
+  TGS_REQUIRE(width > 0 && height > 0, "tgs_grad_screen_accumulate: bad image size %d x %d", width, height);
   if (n == 0) return TGS_OK;
   TGS_REQUIRE(g2d && radius && acc, "tgs_grad_screen_accumulate: null pointer");
   TGS_REQUIRE(((uintptr_t)acc & 15) == 0, "tgs_grad_screen_accumulate: acc must be 16-byte aligned");
   hipLaunchKernelGGL(grad_screen_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0, as_stream(stream),
-                     g2d, radius, n, (float4*)acc);
+                     g2d, radius, n, 0.5f * (float)width, 0.5f * (float)height, (float4*)acc);
   return hip_status("tgs_grad_screen_accumulate");
+}
+
+extern "C" int32_t tgs_density_masks(const float* scores, const float* gstats, const float* dstats, int64_t n,
+                                     const float* thr, float tau_grad, float tau_grad_abs, int32_t prune,
+                                     uint8_t* densify, uint8_t* keep, void* stream) {
+  TGS_REQUIRE(n >= 0 && n < (1ll << 31), "tgs_density_masks: n out of range");
+  if (n == 0) return TGS_OK;
+  TGS_REQUIRE(scores && gstats && thr && densify && keep, "tgs_density_masks: null pointer");
+  TGS_REQUIRE(((uintptr_t)gstats & 15) == 0 && ((uintptr_t)dstats & 15) == 0,
+              "tgs_density_masks: gstats and dstats must be 16-byte aligned");
+  hipLaunchKernelGGL(density_masks_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0,
+                     as_stream(stream), scores, (const float4*)gstats, (const float4*)dstats, n, thr, tau_grad,
+                     tau_grad_abs, (int)prune, densify, keep);
+  return hip_status("tgs_density_masks");
 }
 
 extern "C" int32_t tgs_grad_screen_mean(const float* acc, int64_t n, float* out, void* stream) {

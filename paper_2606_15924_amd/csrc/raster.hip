@@ -246,18 +246,22 @@ __device__ __forceinline__ float row_sum16(float v) {
 // Which of the nine sums a lane holds after the reduction below, and
 // whether it issues that sum's atomic: row r of register R_k (rows of 16
 // lanes) holds one field, lanes 0 and 1 of every row issue r0's and r1's
-// field, lane 2 of row 0 issues field 8.  Fixed per lane, so computed once.
+// field, lane 2 of row 0 issues field 8.  With the density sums (thirteen
+// fields) lane 2 of every row issues one of fields 8-11 and lane 3 of row 0
+// field 12.  Fixed per lane, so computed once.
 struct Sum9Lane {
-  int field;   // 0..8, or -1 when the lane issues no atomic
-  int which;   // 0: r0, 1: r1, 2: r2
+  int field;   // 0..12, or -1 when the lane issues no atomic
+  int which;   // 0: r0, 1: r1, 2: r2, 3: r3
 };
 
-__device__ __forceinline__ Sum9Lane sum9_lane(bool twelve = false) {
+__device__ __forceinline__ Sum9Lane sum9_lane(bool thirteen = false) {
   const int lane = lane_id(), k = lane & 15, row = lane >> 4;
   Sum9Lane s;
-  s.which = k < 3 ? k : 0;
+  s.which = k < 4 ? k : 0;
   const int f = k * 4 + ((row & 1) << 1) + (row >> 1);
-  s.field = k < 2 ? f : (k == 2 && (twelve || row == 0) ? f : -1);
+  if (k < 2) s.field = f;
+  else if (k == 2) s.field = (thirteen || row == 0) ? f : -1;
+  else s.field = (thirteen && k == 3 && row == 0) ? f : -1;
   return s;
 }
 
@@ -282,11 +286,12 @@ __device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float* __r
   }
 }
 
-// The nine gradient sums plus the three density-control sums (e w, w, D w)
-// of the same Gaussian: the same folding with fields 9-11 in the rows of
-// r2 that the nine-value form leaves empty (row 2: field 9, row 1: 10,
-// row 3: 11); they go to stats[gid][field - 9], one 16-byte slot.
-__device__ __forceinline__ void wave_sum12_atomic(const float (&v)[12], float* __restrict__ dst,
+// The nine gradient sums plus the four density-control sums (e w, w, D w
+// and the per-pixel centre-gradient norm) of the same Gaussian: the same
+// folding with fields 9-11 in the rows of r2 that the nine-value form leaves
+// empty (row 2: field 9, row 1: 10, row 3: 11) and field 12 in row 0 of r3;
+// they go to stats[gid][field - 9], one 16-byte slot.
+__device__ __forceinline__ void wave_sum13_atomic(const float (&v)[13], float* __restrict__ dst,
                                                   float* __restrict__ stats, uint32_t gid, int64_t n,
                                                   const Sum9Lane& sl) {
   const float p01 = swap_sum32(v[0], v[1]);
@@ -295,11 +300,13 @@ __device__ __forceinline__ void wave_sum12_atomic(const float (&v)[12], float* _
   const float p67 = swap_sum32(v[6], v[7]);
   const float p89 = swap_sum32(v[8], v[9]);
   const float pab = swap_sum32(v[10], v[11]);
+  const float pc = swap_sum32(v[12], 0.f);
   const float r0 = row_sum16(swap_sum16(p01, p23));
   const float r1 = row_sum16(swap_sum16(p45, p67));
   const float r2 = row_sum16(swap_sum16(p89, pab));
+  const float r3 = row_sum16(swap_sum16(pc, 0.f));
   if (sl.field >= 0) {
-    const float val = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : r2);
+    const float val = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : (sl.which == 2 ? r2 : r3));
     if (val != 0.f) {
       if (sl.field < 9) unsafeAtomicAdd(&dst[sl.field], val);
       else if (gid < (uint32_t)n) unsafeAtomicAdd(&stats[(int64_t)gid * 4 + (sl.field - 9)], val);
@@ -308,10 +315,11 @@ __device__ __forceinline__ void wave_sum12_atomic(const float (&v)[12], float* _
 }
 
 // Optional density-control sums in the backward (Sec. 3.8): the replay
-// already has each composited Gaussian's weight w = T alpha.
+// already has each composited Gaussian's weight w = T alpha and each lane's
+// own centre gradient.
 struct DensityArgs {
   const float* err;  // [P] per-pixel error e(p), indexed like out
-  float* stats;      // [n][4] E, W, D, unused (+=)
+  float* stats;      // [n][4] E, W, D, sum of per-pixel NDC centre-gradient norms (+=)
   int64_t n;
 };
 
@@ -322,6 +330,7 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
                                                             const float4* __restrict__ dL,
                                                             float* __restrict__ g2d,
                                                             const float4* __restrict__ state,
+                                                            uint8_t* __restrict__ touched,
                                                             DensityArgs dens = {}) {
   __shared__ float4 s_geo[kBlock];
   __shared__ float4 s_app[kBlock];
@@ -341,6 +350,7 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
   const float amin = a.alpha_min, amax = a.alpha_max;
   const Sum9Lane sl = sum9_lane(kDensity);
+  const float hw = 0.5f * (float)a.width, hh = 0.5f * (float)a.height;  // pixel -> NDC units
 
   float Cout0 = 0.f, Cout1 = 0.f, Cout2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
   uint32_t last = 0;
@@ -432,12 +442,14 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
           v[7] = w * g1;
           v[8] = w * g2;
           const uint32_t gid = __builtin_amdgcn_readfirstlane(s_gid[j + u]);  // uniform
+          if (touched != nullptr && lane_id() == 0) touched[gid] = 1u;  // composited at a sample
           if constexpr (kDensity) {
             constexpr float kTwoLn2 = 1.3862943611198906f;
             const float dist = __builtin_sqrtf(fmaxf(-kTwoLn2 * pw[u], 0.f));
-            const float v12[12] = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8],
-                                   e_pix * w, w, dist * w};
-            wave_sum12_atomic(v12, g2d + (size_t)gid * 9, dens.stats, gid, dens.n, sl);
+            const float nx = hw * v[0], ny = hh * v[1];
+            const float v13[13] = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8],
+                                   e_pix * w, w, dist * w, __builtin_sqrtf(nx * nx + ny * ny)};
+            wave_sum13_atomic(v13, g2d + (size_t)gid * 9, dens.stats, gid, dens.n, sl);
           } else {
             wave_sum9_atomic(v, g2d + (size_t)gid * 9, sl);
           }
@@ -550,15 +562,16 @@ static void launch_fwd(const RasterArgs& a, int grid, float* out, uint32_t* ncon
 
 template <int kBlock, bool kDense>
 static void launch_bwd(const RasterArgs& a, int grid, const float* out, const uint32_t* ncontrib,
-                       const float* dL, float* g2d, const float* state, hipStream_t s,
+                       const float* dL, float* g2d, const float* state, uint8_t* touched, hipStream_t s,
                        const DensityArgs* dens = nullptr) {
   const unsigned chunks = state != nullptr ? TGS_RENDER_CHUNKS : 1;
   if (dens != nullptr)
     hipLaunchKernelGGL((render_bwd_kernel<kBlock, kDense, true>), dim3(grid, chunks), dim3(kBlock), 0, s, a,
-                       (const float4*)out, ncontrib, (const float4*)dL, g2d, (const float4*)state, *dens);
+                       (const float4*)out, ncontrib, (const float4*)dL, g2d, (const float4*)state, touched, *dens);
   else
     hipLaunchKernelGGL((render_bwd_kernel<kBlock, kDense>), dim3(grid, chunks), dim3(kBlock), 0, s, a,
-                       (const float4*)out, ncontrib, (const float4*)dL, g2d, (const float4*)state, DensityArgs{});
+                       (const float4*)out, ncontrib, (const float4*)dL, g2d, (const float4*)state, touched,
+                       DensityArgs{});
 }
 
 // Workgroup size of the raster kernels for a launch.
@@ -643,7 +656,7 @@ extern "C" int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, cons
                                   const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
                                   const tgs_raster_params* rp, const float* out,
                                   const uint32_t* ncontrib, const float* dL_dout, float* g2d,
-                                  const float* state, void* stream) {
+                                  const float* state, uint8_t* touched, void* stream) {
   RasterArgs a;
   if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
                             tile_off, pix, n_st, max_per_tile, rp, "tgs_render_bwd", a))
@@ -653,11 +666,11 @@ extern "C" int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, cons
               "tgs_render_bwd: out, dL_dout and state must be 16-byte aligned");
   hipStream_t s = as_stream(stream);
   if (valid_tiles == nullptr) {
-    launch_bwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, dL_dout, g2d, state, s);
+    launch_bwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, dL_dout, g2d, state, touched, s);
   } else if (n_st > 0) {
-    if (max_per_tile <= 64) launch_bwd<64, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s);
-    else if (max_per_tile <= 128) launch_bwd<128, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s);
-    else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s);
+    if (max_per_tile <= 64) launch_bwd<64, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s);
+    else if (max_per_tile <= 128) launch_bwd<128, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s);
+    else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s);
   }
   return hip_status("tgs_render_bwd");
 }
@@ -668,8 +681,8 @@ extern "C" int32_t tgs_render_bwd_density(const float* splat, const uint32_t* va
                                           const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
                                           const tgs_raster_params* rp, const float* out,
                                           const uint32_t* ncontrib, const float* dL_dout, float* g2d,
-                                          const float* state, const float* err, int64_t n, float* stats,
-                                          void* stream) {
+                                          const float* state, uint8_t* touched, const float* err, int64_t n,
+                                          float* stats, void* stream) {
   RasterArgs a;
   if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
                             tile_off, pix, n_st, max_per_tile, rp, "tgs_render_bwd_density", a))
@@ -682,11 +695,12 @@ extern "C" int32_t tgs_render_bwd_density(const float* splat, const uint32_t* va
   hipStream_t s = as_stream(stream);
   const DensityArgs d{err, stats, n};
   if (valid_tiles == nullptr) {
-    launch_bwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, dL_dout, g2d, state, s, &d);
+    launch_bwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, dL_dout, g2d, state, touched, s, &d);
   } else if (n_st > 0) {
-    if (max_per_tile <= 64) launch_bwd<64, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s, &d);
-    else if (max_per_tile <= 128) launch_bwd<128, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s, &d);
-    else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, s, &d);
+    if (max_per_tile <= 64) launch_bwd<64, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s, &d);
+    else if (max_per_tile <= 128)
+      launch_bwd<128, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s, &d);
+    else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s, &d);
   }
   return hip_status("tgs_render_bwd_density");
 }

@@ -151,19 +151,20 @@ class ViewBuffers:
                                  self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
                                  rp, self.ncontrib, self.err, self.n, stats, self.state)
 
-    def render_bwd(self, rp, zero=True, stats=None):
-        """The backward; with ``stats`` it also adds the density-control sums."""
+    def render_bwd(self, rp, zero=True, stats=None, touched=None):
+        """The backward; with ``stats`` it also adds the density-control
+        sums; ``touched`` collects the Gaussians composited at a sample."""
         if zero:
             self.g2d.zero_()
         if stats is not None:
             B.tgs_render_bwd_density(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                                      self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st,
                                      self.n_pix, rp, self.out, self.ncontrib, self.dL, self.g2d, self.err, self.n,
-                                     stats, self.state)
+                                     stats, self.state, touched)
             return
         B.tgs_render_bwd(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                          self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
-                         rp, self.out, self.ncontrib, self.dL, self.g2d, self.state)
+                         rp, self.out, self.ncontrib, self.dL, self.g2d, self.state, touched)
 
     def project_bwd(self, params, cam: B.tgs_camera, rp, grad, accumulate=True):
         B.tgs_project_bwd(params, self.n, cam, rp, self.radius, self.clamp, self.g2d, grad, accumulate)
@@ -296,16 +297,20 @@ class Trainer:
 
     def buffers(self, key, cam, rate_permille: int | None = None) -> ViewBuffers:
         """Buffers of view slot ``key`` at the configured rate, or at
-        ``rate_permille`` (then kept per (slot, rate))."""
-        if rate_permille is not None:
-            slot, key = key, (key, rate_permille)
-            if key not in self._bufs:  # one rate per slot is kept: drop the slot's others
-                for k in [k for k in self._bufs if isinstance(k, tuple) and k[0] == slot]:
-                    del self._bufs[k]
-        if key not in self._bufs:
-            rate = self.cfg.rate_permille if rate_permille is None else rate_permille
-            n_pix = None if rate is None else B.tgs_pixels_per_tile(rate)
-            self._bufs[key] = ViewBuffers(self.n, cam.width, cam.height, n_pix, self.cfg.n_tiles_sel, self.dev)
+        ``rate_permille``.  A slot keeps one buffer set, keyed by its pixels
+        per tile (rates that give the same count share it); a new count
+        replaces the set and starts the pair arrays at the old capacity."""
+        rate = self.cfg.rate_permille if rate_permille is None else rate_permille
+        n_pix = None if rate is None else B.tgs_pixels_per_tile(rate)
+        old = self._bufs.get(key)
+        if old is not None and old.n == self.n and old.width == cam.width and old.height == cam.height \
+                and (old.n_pix if not old.dense else None) == n_pix:
+            return old
+        cap = old.capacity if old is not None and old.n == self.n else None
+        if old is not None:
+            del self._bufs[key]
+        self._bufs[key] = ViewBuffers(self.n, cam.width, cam.height, n_pix, self.cfg.n_tiles_sel, self.dev,
+                                      capacity=cap)
         return self._bufs[key]
 
     def init_error_maps(self, views):
@@ -359,7 +364,7 @@ class Trainer:
                 main.wait_event(sampled)
                 waited = True
             with st("bin_sort"):
-                vb.bin_sort(self.touched, self.rp.alpha_min)
+                vb.bin_sort(None, self.rp.alpha_min)
             if not waited:
                 main.wait_event(sampled)
                 waited = True
@@ -378,9 +383,9 @@ class Trainer:
             with st("render_bwd"):
                 # g2d was cleared by the projection; the density sums of sparse
                 # views join the backward's reduction
-                vb.render_bwd(self.rp, zero=False, stats=None if vb.dense else self.dstats)
+                vb.render_bwd(self.rp, zero=False, stats=None if vb.dense else self.dstats, touched=self.touched)
             if self.gstats is not None:
-                B.tgs_grad_screen_accumulate(vb.g2d, vb.radius, self.n, self.gstats)
+                B.tgs_grad_screen_accumulate(vb.g2d, vb.radius, self.n, cam.width, cam.height, self.gstats)
             if k + 1 < len(used) or not self.cfg.fuse_optimizer:
                 with st("project_bwd"):
                     # the first view overwrites the gradient, later views add to it
@@ -416,13 +421,16 @@ class Trainer:
         return e, d, sc
 
     def density_select(self, lambda_base: float, rho: float, eta_topk: float, eta_final: float,
-                       eps: float = 1e-8):
-        """The percentile selections of the density control over the current
-        sums: densify where s_i reaches the k-th largest score,
-        k = max(1, ceil((1 - eta_topk) n)); keep (final pruning) where it
+                       eps: float = 1e-8, tau_grad: float | None = None, tau_grad_abs: float | None = None,
+                       prune: bool = True):
+        """The selections of one density step over the current sums: the
+        percentile thresholds of the score (densify where s_i reaches the
+        k-th largest, k = max(1, ceil((1 - eta_topk) n)); keep where it
         reaches the k-th largest with k = max(1, ceil(eta_final n)); ties are
-        selected.  Returns (densify, keep) uint8 masks, the two thresholds and
-        the scores."""
+        selected), densification gated by the gradient thresholds (skipped
+        when tau_grad is None), and keep = 1 everywhere when ``prune`` is
+        off.  rho is the training progress of Eq. gauss_score.  Returns
+        (densify, keep) uint8 masks, the two thresholds and the scores."""
         e, d, sc = self.density_scores(lambda_base, rho, eps)
         if self._select_ws is None:
             self._select_ws = torch.empty(B.tgs_select_workspace_size(), dtype=torch.uint8, device=self.dev)
@@ -431,7 +439,16 @@ class Trainer:
         for j, frac in enumerate((1.0 - eta_topk, eta_final)):
             k = max(1, math.ceil(frac * self.n - 1e-9))
             B.tgs_select_kth_largest(sc, self.n, k, thr[j:j + 1], self._select_ws)
-            B.tgs_threshold_mask(sc, self.n, thr[j:j + 1], masks[j])
+        if tau_grad is None:
+            # ungated: the two percentile masks alone
+            B.tgs_threshold_mask(sc, self.n, thr[0:1], masks[0])
+            if prune:
+                B.tgs_threshold_mask(sc, self.n, thr[1:2], masks[1])
+            else:
+                masks[1].fill_(1)
+        else:
+            B.tgs_density_masks(sc, self.gstats, self.dstats, self.n, thr, tau_grad,
+                                float("inf") if tau_grad_abs is None else tau_grad_abs, prune, masks[0], masks[1])
         return masks[0], masks[1], thr, (e, d, sc)
 
     def densify_and_prune(self, densify, keep, z, log_split: float):

@@ -17,7 +17,10 @@ Conventions (fixed so that runs are reproducible):
   + 1e-8), 0, 1), phi = sin(pi/2 sqrt(r_t)), a = 1 - rho_t phi;
   r_tile = r_min + (r_max - r_min) a, K_t = floor(K_min + (K_max - K_min)
   exp(-alpha a) + 1/2), r_min = lambda / K_max, r_max = lambda / K_min; the
-  pixel rate in permille is floor(1000 r_tile + 1/2) clipped to [1, 1000].
+  pixel rate in permille is floor(1000 r_tile + 1/2) clipped to [1, 1000];
+* that rho_t (the appendix's) lives inside the schedule only; the density
+  score of Eq. gauss_score takes the training progress of Alg. 1,
+  min(1, t / tau_until).
 """
 from __future__ import annotations
 
@@ -48,12 +51,19 @@ def counter_draw(seed: int, *fields: int) -> int:
     return h
 
 
-def view_errors(E_maps, pixels: int, dev) -> list:
-    """E_bar_v of each view's half error map (one GPU reduction per view)."""
-    sums = torch.empty(len(E_maps), dtype=torch.int64, device=dev)
-    for v, E in enumerate(E_maps):
-        B.tgs_view_error_sums(E, 1, pixels, sums[v:v + 1])
-    return [int(s) / (float(1 << 24) * pixels) for s in sums.cpu().tolist()]
+def view_errors(E_maps, pixels: int, dev, views=None, means=None) -> list:
+    """E_bar_v of the views' half error maps (one GPU reduction per map, one
+    device-to-host copy).  With ``views`` and ``means`` only those views'
+    entries of ``means`` are refreshed (the maps of the other views have not
+    changed since they were last reduced)."""
+    views = list(range(len(E_maps))) if views is None else list(views)
+    sums = torch.empty(max(len(views), 1), dtype=torch.int64, device=dev)
+    for j, v in enumerate(views):
+        B.tgs_view_error_sums(E_maps[v], 1, pixels, sums[j:j + 1])
+    out = list(means) if means is not None else [0.0] * len(E_maps)
+    for v, s in zip(views, sums.cpu().tolist()):
+        out[v] = int(s) / (float(1 << 24) * pixels)
+    return out
 
 
 def _weight(cu, du, ca, da, lam_d, lam_t) -> float:
@@ -121,29 +131,62 @@ def camera_pose(cam) -> tuple:
 
 @dataclass
 class DensityPlan:
-    """When and how density control runs inside the loop (the table's
-    tau_from, tau_until, Delta_dens, eta_topk, eta_final; lambda_base and the
-    split threshold are inputs).  The trainer needs density_stats on."""
+    """When and how density control runs inside the loop (the hyper-parameter
+    table: tau_from, tau_until, Delta_dens, Delta_prune, eta_topk, eta_final,
+    tau_grad, tau_grad^abs, rho_dense, lambda_base).  Every ``every`` steps in
+    [t_from, t_until] the accumulated statistics select and densify; on the
+    steps that are also multiples of ``prune_every`` the final pruning keeps
+    the top eta_final of the scores.  A densified Gaussian is split when its
+    largest scale exceeds percent_dense times the scene extent (1.1 times the
+    largest distance of a camera centre from their mean), else cloned.  The
+    trainer needs density_stats on."""
     t_from: int = 200
     t_until: int = 3500
     every: int = 100
+    prune_every: int = 500
     eta_topk: float = 0.9
     eta_final: float = 0.9
-    lambda_base: float = 0.5
-    log_split: float = math.log(0.01)
+    tau_grad: float = 2e-4
+    tau_grad_abs: float = 4e-4
+    percent_dense: float = 0.01
+    lambda_base: float = 0.8
     seed: int = 11
 
 
+def scene_extent(cams) -> float:
+    """1.1 times the largest distance of a camera centre from the mean centre."""
+    cs = [camera_pose(c)[0] for c in cams]
+    m = [sum(c[k] for c in cs) / len(cs) for k in range(3)]
+    return 1.1 * max(math.sqrt(sum((c[k] - m[k]) ** 2 for k in range(3))) for c in cs)
+
+
+def density_step(tr, t: int, tau_until: int, plan: DensityPlan, extent: float):
+    """One density-control step at iteration t: the score at the training
+    progress rho = min(1, t / tau_until) of Alg. 1, the gated selections, the
+    topology change (split draws from a seeded generator) and a restart of
+    the sums.  Returns (densify mask, keep mask, rho) as used."""
+    rho = min(1.0, t / tau_until)
+    prune = plan.prune_every > 0 and t % plan.prune_every == 0
+    dm, km, _, _ = tr.density_select(plan.lambda_base, rho, plan.eta_topk, plan.eta_final,
+                                     tau_grad=plan.tau_grad, tau_grad_abs=plan.tau_grad_abs, prune=prune)
+    gen = torch.Generator(device=tr.dev).manual_seed(plan.seed + t)
+    z = torch.randn((tr.n, 3), generator=gen, device=tr.dev)
+    tr.densify_and_prune(dm, km, z, math.log(plan.percent_dense * extent))
+    return dm, km, rho
+
+
 def run_schedule(tr, steps: int, sch: Schedule, lam_d: float, lam_t: float, seed: int, t0: int = 1,
-                 density: DensityPlan | None = None):
-    """Sparse training driven by the schedule: each step reads the views'
-    mean errors (GPU), takes K_t and the pixel rate from the schedule,
-    picks the anchor and its companions and runs the step at that rate.
-    With ``density``, every ``every`` steps from ``t_from`` to ``t_until``
-    the accumulated statistics select, densify and prune (split draws from a
-    seeded generator), and the sums restart.  E_bar_init is the mean error
-    when the run starts.  Returns the per-step (views, K_t, rate in
-    permille, the views' mean errors before the step, Gaussians after it)."""
+                 density: DensityPlan | None = None, on_density=None):
+    """Sparse training driven by the schedule: each step takes K_t and the
+    pixel rate from the schedule, picks the anchor and its companions from
+    the views' mean errors and runs the step at that rate; afterwards only
+    the stepped views' mean errors are reduced again (the other maps are
+    unchanged).  With ``density``, every ``every`` steps from ``t_from`` to
+    ``t_until`` a density step runs (``density_step``); ``on_density(t, tr)``
+    is called just before it (e.g. to read the statistics).  E_bar_init is
+    the mean error when the run starts.  Returns the per-step (views, K_t,
+    rate in permille, the views' mean errors before the step, Gaussians
+    after it)."""
     cams = tr.cams
     pixels = cams[0].width * cams[0].height
     assert all(c.width * c.height == pixels for c in cams), "one image size"
@@ -151,6 +194,7 @@ def run_schedule(tr, steps: int, sch: Schedule, lam_d: float, lam_t: float, seed
     centres, dirs = [p[0] for p in poses], [p[1] for p in poses]
     means = view_errors(tr.E, pixels, tr.dev)
     e_init = sum(means) / len(means)
+    extent = scene_extent(cams)
     stack = list(range(len(cams)))
     log = []
     for t in range(t0, t0 + steps):
@@ -158,11 +202,9 @@ def run_schedule(tr, steps: int, sch: Schedule, lam_d: float, lam_t: float, seed
         views, stack = pick_views(stack, means, centres, dirs, K, lam_d, lam_t, seed, t)
         tr.step(views, rate_permille=permille)
         if density is not None and density.t_from <= t <= density.t_until and t % density.every == 0:
-            rho = 1.0 - min(max(t / sch.tau_until, 0.0), 1.0)
-            dm, km, _, _ = tr.density_select(density.lambda_base, rho, density.eta_topk, density.eta_final)
-            gen = torch.Generator(device=tr.dev).manual_seed(density.seed + t)
-            z = torch.randn((tr.n, 3), generator=gen, device=tr.dev)
-            tr.densify_and_prune(dm, km, z, density.log_split)
+            if on_density is not None:
+                on_density(t, tr)
+            density_step(tr, t, sch.tau_until, density, extent)
         log.append((views, K, permille, means, tr.n))
-        means = view_errors(tr.E, pixels, tr.dev)
+        means = view_errors(tr.E, pixels, tr.dev, views, means)
     return log

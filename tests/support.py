@@ -79,3 +79,82 @@ def assert_close(a, b, rtol, atol=0.0, what=""):
         raise AssertionError(f"{what}: {bad.sum()} of {bad.size} outside tolerance; worst index {i}: "
                              f"got {np.asarray(a).ravel()[i]!r}, want {np.asarray(b).ravel()[i]!r}, "
                              f"max rel {np.max(err / np.maximum(np.abs(b), 1e-30)):.3g}")
+
+
+def check_pair_lists(vals, ranges, n_pairs, pr: dict, valid_tiles=None, keys=None, alpha_min=1.0 / 255.0,
+                     max_dropped_checked: int | None = None, seed: int = 0, tiles_subset=None) -> dict:
+    """Checks a GPU pair list (vals [n_pairs] ids, ranges [n_tiles][2], keys
+    optional) against the oracle's rectangle lists of the projection ``pr``:
+
+    * ranges partition [0, n_pairs) in ascending tile order (empty: [0, 0)),
+      and only valid tiles hold pairs;
+    * within the whole list, (tile, depth bits, id) strictly increases, and
+      every (tile, id) pair is a pair of the oracle's list, so each tile's
+      GPU list is an order-preserving subsequence of the oracle's;
+    * the keys, when given, are (tile << 32) | bits of the oracle's FP32 depth;
+    * every pair the GPU list drops can composite nowhere in its tile: the
+      oracle's o exp(power) stays below alpha_min (1 - 1e-3) at all 256 pixel
+      centres (evaluated for all dropped pairs, or a seeded sample of
+      ``max_dropped_checked``).
+
+    With ``tiles_subset`` the membership and dropped-pair checks cover those
+    tiles only (the order, key and range checks still cover the whole list).
+    Returns counts (GPU pairs, oracle pairs, dropped, dropped checked)."""
+    vals = np.asarray(vals, dtype=np.uint32)[:n_pairs].astype(np.int64)
+    ranges = np.asarray(ranges, dtype=np.int64).reshape(-1, 2)
+    n_t = pr["TX"] * pr["TY"]
+    assert ranges.shape[0] == n_t
+    listed = np.arange(n_t) if valid_tiles is None else np.asarray(valid_tiles, dtype=np.int64)
+    if tiles_subset is not None:
+        listed = np.intersect1d(listed, np.asarray(tiles_subset, dtype=np.int64))
+    sk, sv, _ = binning.bin_and_sort(pr, listed)
+    # ranges: contiguous, ascending, covering exactly n_pairs; tile of each position
+    cnt = ranges[:, 1] - ranges[:, 0]
+    assert (cnt >= 0).all()
+    ne = np.nonzero(cnt > 0)[0]
+    assert (ranges[cnt == 0] == 0).all()
+    starts = np.concatenate([[0], np.cumsum(cnt[ne])[:-1]]) if ne.size else np.zeros(0, np.int64)
+    assert np.array_equal(ranges[ne, 0], starts) and int(cnt.sum()) == n_pairs
+    if valid_tiles is not None:
+        valid = np.zeros(n_t, dtype=bool)
+        valid[np.asarray(valid_tiles, dtype=np.int64)] = True
+        assert valid[ne].all()
+    tile = np.repeat(ne, cnt[ne])
+    bits = np.asarray(pr["depth32"], dtype=np.float32).view(np.uint32).astype(np.int64)
+    if keys is not None:
+        k = np.asarray(keys).view(np.uint64)[:n_pairs]
+        assert np.array_equal(k, (tile.astype(np.uint64) << np.uint64(32)) | bits[vals].astype(np.uint64))
+    # strictly increasing (tile, depth bits, id)
+    if n_pairs > 1:
+        t0, t1 = tile[:-1], tile[1:]
+        d0, d1 = bits[vals[:-1]], bits[vals[1:]]
+        inc = (t0 < t1) | ((t0 == t1) & ((d0 < d1) | ((d0 == d1) & (vals[:-1] < vals[1:]))))
+        assert inc.all()
+    # membership in the oracle's (tile, id) pairs
+    code_o = ((sk >> np.uint64(32)).astype(np.int64) << 32) | sv.astype(np.int64)
+    code_o_sorted = np.sort(code_o)
+    code_g = (tile << 32) | vals
+    if tiles_subset is not None:
+        code_g = code_g[np.isin(tile, listed)]
+    pos = np.searchsorted(code_o_sorted, code_g)
+    assert (pos < code_o_sorted.size).all() and np.array_equal(code_o_sorted[np.minimum(pos, code_o_sorted.size - 1)],
+                                                               code_g)
+    dropped = np.setdiff1d(code_o_sorted, code_g, assume_unique=True)
+    chk = dropped
+    if max_dropped_checked is not None and dropped.size > max_dropped_checked:
+        chk = np.random.default_rng(seed).choice(dropped, max_dropped_checked, replace=False)
+    if chk.size:
+        amax = binning.max_alpha_in_tile(pr, chk & 0xFFFFFFFF, chk >> 32)
+        assert (amax < alpha_min * (1.0 - 1e-3)).all(), float(amax.max() / alpha_min)
+    return dict(gpu=int(code_g.size), oracle=int(sk.size), dropped=int(dropped.size), checked=int(chk.size))
+
+
+def last_ids(vals, ranges, tiles, ncontrib) -> np.ndarray:
+    """The id of the last composited Gaussian of each pixel (-1 when none):
+    the ncontrib-th entry of the pixel's tile list.  Unique for a pixel
+    whatever Gaussians that cannot composite its list holds."""
+    vals = np.asarray(vals).astype(np.int64)
+    ranges = np.asarray(ranges, dtype=np.int64).reshape(-1, 2)
+    nc = np.asarray(ncontrib).astype(np.int64)
+    idx = ranges[np.asarray(tiles, dtype=np.int64), 0] + nc - 1
+    return np.where(nc > 0, vals[np.clip(idx, 0, max(vals.size - 1, 0))], -1)

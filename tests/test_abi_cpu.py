@@ -127,11 +127,14 @@ def test_density_and_schedule_arguments_are_rejected_before_any_launch(B):
     assert tws >= 4 * 4 * 1000
     err(lib.tgs_density_topology_count(P, P, 1000, ctypes.byref(nk), ctypes.byref(nn), P, 16, None), "workspace")
     err(lib.tgs_density_topology_apply(P, P, P, 1000, P, 0.0, P, tws, P, P, P, 2001, None), "n_out")
-    err(lib.tgs_grad_screen_accumulate(P, P, 10, ctypes.c_void_p(20), None), "aligned")
+    err(lib.tgs_grad_screen_accumulate(P, P, 10, 64, 48, ctypes.c_void_p(20), None), "aligned")
+    err(lib.tgs_grad_screen_accumulate(P, P, 10, 0, 48, P, None), "image size")
+    err(lib.tgs_density_masks(P, ctypes.c_void_p(20), None, 10, P, 1e-4, 2e-4, 1, P, P, None), "aligned")
     err(lib.tgs_view_error_sums(P, 3, 0, P, None), "pixels")
     # empty inputs: nothing to do
     assert lib.tgs_density_score(None, 0, 0.5, 0.5, 1e-8, None, None, None, None) == B.TGS_OK
-    assert lib.tgs_grad_screen_accumulate(None, None, 0, None, None) == B.TGS_OK
+    assert lib.tgs_grad_screen_accumulate(None, None, 0, 64, 48, None, None) == B.TGS_OK
+    assert lib.tgs_density_masks(None, None, None, 0, None, 0.0, 0.0, 0, None, None, None) == B.TGS_OK
     assert lib.tgs_view_error_sums(None, 0, 100, None, None) == B.TGS_OK
     assert lib.tgs_density_topology_apply(P, P, P, 1000, P, 0.0, P, tws, None, None, None, 0, None) == B.TGS_OK
 

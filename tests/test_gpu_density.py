@@ -332,6 +332,15 @@ def test_render_bwd_density_parity(B, case, chunked):
     assert_close(got[2], want[2], 1e-4, 1e-3 * want[1] + 1e-9, "D")
     g1, g2 = host(G1), host(G2)
     assert_close(g2, g1, 1e-5, 1e-6 * (np.abs(g1).max(axis=0) + 1e-12), "g2d fused vs plain")
+    # the absolute statistic: per-pixel centre-gradient norms in NDC units;
+    # each term carries the error of its pixel's gradient (1e-4 relative plus
+    # 16 FP32 ulps of the oracle's error scale of the two centre fields)
+    sx, sy = cam.width / 2, cam.height / 2
+    _, gabs, cabs = render.render_pixels_bwd(q, sv, ranges, xs[ok], ys[ok], host(dl)[idx[ok], :3], rp,
+                                             with_abs=True, centre_abs_scale=(sx, sy))
+    scale = np.hypot(sx * gabs[0], sy * gabs[1])
+    assert (cabs > 0).sum() > 200
+    assert_close(host(S)[:, 3].astype(np.float64), cabs, 1e-4, 16 * 2.0 ** -23 * scale + 1e-12, "abs grad")
 
 
 @pytest.mark.parametrize("n", [1, 777, 20011])
@@ -399,8 +408,8 @@ def test_grad_screen_statistics_parity(B):
     for view in range(3):
         g = (rng.normal(size=(n, 9)) * 10.0 ** rng.uniform(-6, 0, (n, 1))).astype(np.float32)
         r = np.where(rng.uniform(0, 1, n) < 0.6, rng.integers(1, 200, n), 0).astype(np.int32)
-        B.tgs_grad_screen_accumulate(dev(g), dev(r), n, acc)
-        want = density.grad_screen_accumulate(want, g, r)
+        B.tgs_grad_screen_accumulate(dev(g), dev(r), n, 1296, 840, acc)
+        want = density.grad_screen_accumulate(want, g, r, 1296, 840)
     got = host(acc).astype(np.float64)
     assert_close(got[:, 0], want[:, 0], 1e-6, 0.0, "norm sum")
     assert np.array_equal(got[:, 1:3], want[:, 1:3]) and not got[:, 3].any()
@@ -426,3 +435,37 @@ def test_trainer_grad_screen_statistics(B):
     assert np.isfinite(m).all() and (m[vis == 0] == 0).all()
     tr.reset_density()
     assert not tr.gstats.any()
+
+
+@pytest.mark.parametrize("prune", [True, False])
+def test_density_masks_bit_exact(B, prune):
+    """The fused selection kernel against the oracle's gated percentile
+    selection, on the same FP32 statistics (scores with ties and zeros,
+    Gaussians never projected, means on both sides of the thresholds)."""
+    rng = np.random.default_rng(31 + prune)
+    n = 200003
+    sc = rng.exponential(1.0, n).astype(np.float32)
+    sc[rng.integers(0, n, n // 5)] = 0.0
+    sc[rng.integers(0, n, n // 10)] = np.float32(0.5)
+    views = rng.integers(0, 4, n).astype(np.float32)
+    gacc = np.zeros((n, 4), np.float32)
+    gacc[:, 1] = views
+    gacc[:, 0] = (views * rng.exponential(2e-4, n)).astype(np.float32)
+    dst = np.zeros((n, 4), np.float32)
+    dst[:, 3] = (views * rng.exponential(4e-4, n)).astype(np.float32)
+    eta_topk, eta_final = 0.9, 0.8
+    want_gate = density.gradient_gate(gacc, dst[:, 3], 2e-4, 4e-4)
+    assert 0.2 < want_gate.mean() < 0.8
+    want = density.select_masks(sc, eta_topk, eta_final, gate=want_gate, prune=prune)
+    thr = dev(np.array([want["thr_densify"], want["thr_keep"]], np.float32))
+    dm = torch.empty(n, dtype=torch.uint8, device="cuda")
+    km = torch.empty(n, dtype=torch.uint8, device="cuda")
+    B.tgs_density_masks(dev(sc), dev(gacc), dev(dst), n, thr, 2e-4, 4e-4, prune, dm, km)
+    assert np.array_equal(host(km).astype(bool), want["keep"])
+    assert np.array_equal(host(dm).astype(bool), want["densify"])
+    assert want["densify"].sum() > 1000
+    # without the absolute statistic only tau_grad gates
+    B.tgs_density_masks(dev(sc), dev(gacc), None, n, thr, 2e-4, 4e-4, prune, dm, km)
+    g2 = density.gradient_gate(gacc, np.zeros(n), 2e-4, np.inf)
+    want2 = density.select_masks(sc, eta_topk, eta_final, gate=g2, prune=prune)
+    assert np.array_equal(host(dm).astype(bool), want2["densify"])

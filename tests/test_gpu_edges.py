@@ -15,7 +15,7 @@ import synth
 from oracle import binning, project, render, sampler
 from oracle.params import RasterParams, SampleParams
 
-from support import assert_close, small_scene, splat_as_oracle, splat_record
+from support import assert_close, check_pair_lists, small_scene, splat_as_oracle, splat_record
 
 pytestmark = pytest.mark.gpu
 
@@ -177,16 +177,14 @@ def _full_chain_parity(B, p, cam, rp, sample=None):
     # per-stage tests do: a last-bit difference in a conic must not move a
     # culling decision
     sk, sv, ranges = binning.bin_and_sort(pr, valid)
+    q = splat_as_oracle(pr, rec)
     ob = dict(rect=dev(pr["rect"].T.astype(np.int32)), splat=dev(rec), depth=dev(pr["depth32"]))
     npairs, K, V, R, touched = _bin(B, ob, n, TX, TY, tile_slot)
-    assert npairs == sk.size
-    assert np.array_equal(host(K)[:npairs].view(np.uint64), sk)
-    assert np.array_equal(host(V)[:npairs].view(np.uint32), sv)
-    assert np.array_equal(host(R).astype(np.int64), ranges)
+    gv = host(V)[:npairs].view(np.uint32)
+    check_pair_lists(gv, host(R), npairs, q, valid, keys=host(K))
     t_ref = np.full(n, 2, dtype=np.uint8)
-    t_ref[np.unique(sv)] = 1
+    t_ref[np.unique(gv)] = 1
     assert np.array_equal(host(touched)[:n], t_ref)
-    q = splat_as_oracle(pr, rec)
     if sample is None:
         xs, ys = render.dense_pixels(cam.width, cam.height)
     else:

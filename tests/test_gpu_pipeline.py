@@ -10,7 +10,8 @@ import synth
 from oracle import binning, maps, optim, pipeline, project, project_bwd, render, sampler
 from oracle.params import LossParams, OptimParams, RasterParams, SampleParams
 
-from support import assert_close, scene_c1, scene_scaling, small_scene, splat_as_oracle, splat_record
+from support import (assert_close, check_pair_lists, last_ids, scene_c1, scene_scaling, small_scene,
+                     splat_as_oracle, splat_record)
 
 pytestmark = pytest.mark.gpu
 
@@ -60,12 +61,52 @@ def c1_inputs():
     return p, cams, gts, E, A
 
 
+ULP32 = 2.0 ** -23
+GROUPS = {"mean": slice(0, 3), "scale": slice(3, 6), "quat": slice(6, 10), "opacity": slice(10, 11),
+          "sh": slice(11, 59)}
+
+
+def _param_error_scale(p, cam, pr, g2d_abs):
+    """The screen-space error scale of a view pushed to the parameters: the
+    projection backward is linear in its input, so |J|^T g2d_abs with |J| the
+    magnitudes of each Gaussian's Jacobian rows (one oracle call per
+    screen-space field with a unit input)."""
+    n = p.shape[1]
+    out = np.zeros((59, n))
+    for k in range(9):
+        e = np.zeros((9, n))
+        e[k] = 1.0
+        out += np.abs(project_bwd.project_bwd(p, cam, pr, e, RP)) * g2d_abs[k][None, :]
+    return out
+
+
+def _excluded_gaussians(ref, views, n):
+    """Gaussians listed in a tile that holds a guard-band pixel in one of the
+    step's views: that pixel's FP32 and FP64 decisions may differ, and the
+    tile's NCC statistics couple it to every sample of the tile."""
+    ex = np.zeros(n, dtype=bool)
+    for v in views:
+        fv = ref["views"][v]["fwd"]
+        TX = fv["proj"]["TX"]
+        tiles = np.unique(((fv["ys"] // 16) * TX + fv["xs"] // 16)[fv["out"]["flag"]])
+        for t in tiles:
+            lo, hi = fv["ranges"][t]
+            ex[fv["vals"][lo:hi].astype(np.int64)] = True
+    return ex
+
+
 @pytest.mark.parametrize("fused", [False, True])
 def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
-    """One four-view step; unfused, the accumulated gradient is checked too
-    (fused, the last view's gradient never leaves registers)."""
+    """One four-view step against the oracle's step, element by element:
+    samples bit for bit; rgb to 1e-5; the last composited Gaussian of every
+    pixel; ages bit for bit; the accumulated gradient (unfused) and the
+    parameter update per element at 1e-4 relative plus 16 FP32 ulps of the
+    oracle's error scale (the screen-space scale pushed through the exact
+    Jacobian magnitudes), outside the tiles that hold a guard-band pixel;
+    the touched set (Gaussians composited at a sample) exactly outside them."""
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
     p, cams, gts, E, A = c1_inputs
+    n = p.shape[1]
     sp = SampleParams(n_pix=64, n_tiles_sel=64)
     ref = pipeline.train_step(p, np.zeros_like(p, np.float64), np.zeros_like(p, np.float64), cams, gts, E, A,
                               1, sp, RP, LossParams(), OptimParams(), seed=3)
@@ -75,43 +116,69 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     tr = Trainer(dev(p), cams, [dev(g) for g in gts], cfg, E=Eg, A=Ag)
     used = tr.step([0, 1, 2, 3])
     torch.cuda.synchronize()
+    scale = np.zeros((59, n))
     for v, vb in enumerate(used):
         rv = ref["views"][v]
         s = rv["samples"]
+        fv = rv["fwd"]
         P = int(s["tile_off"][-1])
         assert np.array_equal(host(vb.valid_tiles), s["valid_tiles"])
         assert np.array_equal(host(vb.pix)[:P], s["pix"])
         o = host(vb.out)[:P]
-        flag = rv["fwd"]["out"]["flag"]
+        flag = fv["out"]["flag"]
         ok = ~flag
         assert ok.mean() > 0.995
-        assert_close(o[ok, :3], rv["fwd"]["out"]["rgb"][ok], 1e-5, 1e-6, f"view {v} rgb")
-        assert np.array_equal(host(vb.ncontrib)[:P][ok], rv["fwd"]["out"]["n_contrib"][ok])
+        assert_close(o[ok, :3], fv["out"]["rgb"][ok], 1e-5, 1e-6, f"view {v} rgb")
+        tiles = (fv["ys"] // 16) * fv["proj"]["TX"] + fv["xs"] // 16
+        got_last = last_ids(host(vb.vals), host(vb.ranges), tiles, host(vb.ncontrib)[:P])
+        want_last = last_ids(fv["vals"], fv["ranges"], tiles, fv["out"]["n_contrib"])
+        assert np.array_equal(got_last[ok], want_last[ok])
         assert np.array_equal(host(Ag[v]).view(np.uint16), ref["A"][v])
         # E: the blend input e differs in the last bits (FP32 render), so a
         # half may round to a neighbour
         e_gpu = host(Eg[v]).view(np.float16).astype(np.float64)
         e_ref = ref["E"][v].view(np.float16).astype(np.float64)
         assert np.all(np.abs(e_gpu - e_ref) <= np.abs(np.spacing(e_ref.astype(np.float16))).astype(np.float64))
+        _, g2d_abs = render.render_pixels_bwd(fv["proj"], fv["vals"], fv["ranges"], fv["xs"], fv["ys"],
+                                              rv["loss"]["dL"], RP, with_abs=True)
+        scale += _param_error_scale(p, cams[v], fv["proj"], g2d_abs)
     loss_gpu = tr.loss_value(used)
     assert abs(loss_gpu - ref["loss"]) <= 1e-4 * abs(ref["loss"])
-    assert np.array_equal(host(tr.touched).astype(bool), ref["touched"])
+    ex = _excluded_gaussians(ref, range(4), n)
+    assert ex.mean() < 0.35
+    t_gpu = host(tr.touched).astype(bool)
+    assert np.array_equal(t_gpu[~ex], ref["touched"][~ex]) and ref["touched"].sum() > 2000
+    keep = ~ex
+    tol_g = 1e-4 * np.abs(ref["grad"]) + 16 * ULP32 * scale + 1e-30
     if not fused:
-        g = host(tr.grad)
-        for name, sl in {"mean": slice(0, 3), "scale": slice(3, 6), "quat": slice(6, 10),
-                         "opacity": slice(10, 11), "sh": slice(11, 59)}.items():
-            assert rel_norm(g[sl], ref["grad"][sl]) < 2e-3, name
+        g = host(tr.grad).astype(np.float64)
+        for name, sl in GROUPS.items():
+            assert_close(g[sl][:, keep], ref["grad"][sl][:, keep], 1e-4, (16 * ULP32 * scale[sl] + 1e-30)[:, keep],
+                         f"gradient {name}")
+    # the update, where the gradient is determined beyond its error bar (the
+    # step-1 update of Adam and LM is close to -lr sign(g), which a gradient
+    # inside its bar may flip); elsewhere at most one learning rate per
+    # element, as the update of an exactly zero gradient is zero
     dp_gpu = host(tr.params).astype(np.float64) - p
     dp_ref = ref["params"] - p
-    assert rel_norm(dp_gpu, dp_ref) < 2e-3
+    det = keep[None, :] & (np.abs(ref["grad"]) > 2 * tol_g)
+    assert det.sum() > 0.5 * (ref["grad"][:, keep] != 0).sum()
+    for name, sl in GROUPS.items():
+        d = det[sl]
+        p32 = np.abs(ref["params"][sl][d]).astype(np.float32)
+        assert_close(dp_gpu[sl][d], dp_ref[sl][d], 1e-4, 2 * np.spacing(p32).astype(np.float64) + 1e-12,
+                     f"update {name}")
+    lr = OptimParams().row_lr()[:, None] * np.ones((1, n))
+    assert (np.abs(dp_gpu[:, keep]) <= 4 * lr[:, keep] + 1e-6).all()
 
 
 def test_c1_step_density_sums_match_oracle(B, c1_inputs):
     """A four-view step with the density sums in the backward: per Gaussian,
     E, W and D summed over the views equal the oracle's back-projection of
-    its own step (its samples, splats and per-pixel errors).  Whole-step
-    comparison: the FP32 render and errors and the few guard-band pixels
-    keep it to a norm bar, as for the gradient."""
+    its own step (its samples, splats and per-pixel errors), element by
+    element at 1e-4 relative (sums of non-negative terms; D also 1e-3 per
+    unit of weight, as in the stage test), outside the tiles that hold a
+    guard-band pixel."""
     from oracle import density
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
     p, cams, gts, E, A = c1_inputs
@@ -127,9 +194,11 @@ def test_c1_step_density_sums_match_oracle(B, c1_inputs):
                  A=[dev(a.view(np.int16)) for a in A])
     tr.step([0, 1, 2, 3])
     got = host(tr.dstats)[:, :3].T.astype(np.float64)
-    assert (want[1] > 0).sum() > 1000
-    for k, name in enumerate("EWD"):
-        assert rel_norm(got[k], want[k]) < 2e-3, name
+    keep = ~_excluded_gaussians(ref, range(4), p.shape[1])
+    assert (want[1][keep] > 0).sum() > 1000
+    assert_close(got[0][keep], want[0][keep], 1e-4, 1e-9, "E")
+    assert_close(got[1][keep], want[1][keep], 1e-4, 1e-9, "W")
+    assert_close(got[2][keep], want[2][keep], 1e-4, 1e-3 * want[1][keep] + 1e-9, "D")
 
 
 # ------------------------------------------------------------------ autograd
@@ -198,17 +267,20 @@ def scaling(B):
 
 
 def test_scaling_projection_and_sort_bit_exact(B, scaling):
+    """Depth keys and rectangles bit for bit; the pair lists of 600 random
+    tiles against the oracle's rectangle lists (subsequence, keys, ranges,
+    every dropped pair shown unable to composite), the order and range
+    partition over the whole list."""
     vb, pr = scaling["vb"], scaling["pr"]
     vis = pr["visible"]
     assert np.array_equal(host(vb.depth).view(np.uint32), pr["depth32"].view(np.uint32))
     safe = vis & (pr["radius_margin"] > 1e-9)
     assert np.array_equal(host(vb.rect)[safe], pr["rect"].T[safe])
-    # the GPU sort of every pair against the library sort of the oracle's pairs
-    sk, sv, rg = binning.bin_and_sort(pr)
-    assert vb.n_pairs == sk.size
-    assert np.array_equal(host(vb.keys)[: sk.size].view(np.uint64), sk)
-    assert np.array_equal(host(vb.vals)[: sk.size].view(np.uint32), sv)
-    assert np.array_equal(host(vb.ranges).astype(np.int64), rg)
+    q = splat_as_oracle(pr, splat_record(pr))
+    sub = np.random.default_rng(4).choice(pr["TX"] * pr["TY"], 600, replace=False)
+    info = check_pair_lists(host(vb.vals)[: vb.n_pairs].view(np.uint32), host(vb.ranges), vb.n_pairs, q,
+                            keys=host(vb.keys), tiles_subset=sub, max_dropped_checked=100000)
+    assert info["gpu"] > 500000 and info["dropped"] > 0.2 * info["oracle"]
 
 
 def test_scaling_forward_and_backward_on_sampled_tiles(B, scaling):
@@ -219,7 +291,7 @@ def test_scaling_forward_and_backward_on_sampled_tiles(B, scaling):
     tiles = np.sort(rng.choice(TX * pr["TY"], 24, replace=False))
     s = sampler.sample_view(scaling["E"], scaling["A"], SampleParams(n_pix=64), 3, 1, 0, tiles_subset=tiles)
     xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
-    sk, sv, rg = binning.bin_and_sort(pr)
+    sk, sv, rg = binning.bin_and_sort(pr, tiles)      # the rectangle lists of those tiles
     ref = render.render_pixels(q, sv, rg, xs, ys, RP)
     off = host(vb.tile_off)
     idx = np.concatenate([np.arange(off[t], off[t + 1]) for t in tiles])   # slot == tile id here
@@ -227,7 +299,9 @@ def test_scaling_forward_and_backward_on_sampled_tiles(B, scaling):
     o = host(vb.out)[idx]
     ok = ~ref["flag"]
     assert_close(o[ok, :3], ref["rgb"][ok], 1e-5, 1e-7, "rgb")
-    assert np.array_equal(host(vb.ncontrib)[idx][ok], ref["n_contrib"][ok])
+    ptile = (ys // 16) * TX + xs // 16
+    got_last = last_ids(host(vb.vals), host(vb.ranges), ptile, host(vb.ncontrib)[idx])
+    assert np.array_equal(got_last[ok], last_ids(sv, rg, ptile, ref["n_contrib"])[ok])
     # backward: dL/dI non-zero only on the sampled tiles
     g = rng.normal(size=(xs.size, 3)) * 1e-3
     g[ref["flag"]] = 0.0
@@ -285,20 +359,20 @@ def fullstep(B):
     vb.render_fwd(B.raster_params())
     torch.cuda.synchronize()
     pr = project.project(p, cam, RP)
-    sk, sv, rg = binning.bin_and_sort(pr)
-    return dict(p=p, cams=cams, E=E, A=A, vb=vb, pr=pr, sk=sk, sv=sv, rg=rg, n_pix=n_pix)
+    return dict(p=p, cams=cams, E=E, A=A, vb=vb, pr=pr, n_pix=n_pix)
 
 
 def test_full_size_projection_and_sort_bit_exact(B, fullstep):
-    vb, pr, sk = fullstep["vb"], fullstep["pr"], fullstep["sk"]
+    vb, pr = fullstep["vb"], fullstep["pr"]
     assert fullstep["n_pix"] == 51
     assert np.array_equal(host(vb.depth).view(np.uint32), pr["depth32"].view(np.uint32))
     safe = pr["visible"] & (pr["radius_margin"] > 1e-9)
     assert np.array_equal(host(vb.rect)[safe], pr["rect"].T[safe])
-    assert vb.n_pairs == sk.size
-    assert np.array_equal(host(vb.keys)[: sk.size].view(np.uint64), sk)
-    assert np.array_equal(host(vb.vals)[: sk.size].view(np.uint32), fullstep["sv"])
-    assert np.array_equal(host(vb.ranges).astype(np.int64), fullstep["rg"])
+    q = splat_as_oracle(pr, splat_record(pr))
+    sub = np.random.default_rng(14).choice(pr["TX"] * pr["TY"], 300, replace=False)
+    info = check_pair_lists(host(vb.vals)[: vb.n_pairs].view(np.uint32), host(vb.ranges), vb.n_pairs, q,
+                            keys=host(vb.keys), tiles_subset=sub, max_dropped_checked=100000)
+    assert vb.n_pairs > 20_000_000 and info["gpu"] > 1_000_000
 
 
 def test_full_size_forward_and_backward_on_sampled_tiles(B, fullstep):
@@ -308,7 +382,8 @@ def test_full_size_forward_and_backward_on_sampled_tiles(B, fullstep):
     tiles = np.sort(rng.choice(pr["TX"] * pr["TY"], 12, replace=False))
     s = sampler.sample_view(fullstep["E"], fullstep["A"], SampleParams(n_pix=51), 3, 1, 0, tiles_subset=tiles)
     xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
-    ref = render.render_pixels(q, fullstep["sv"], fullstep["rg"], xs, ys, RP)
+    _, sv, rg = binning.bin_and_sort(pr, tiles)
+    ref = render.render_pixels(q, sv, rg, xs, ys, RP)
     off = host(vb.tile_off)
     idx = np.concatenate([np.arange(off[t], off[t + 1]) for t in tiles])   # slot == tile id here
     assert np.array_equal(host(vb.pix)[idx], s["pix"])
@@ -318,7 +393,9 @@ def test_full_size_forward_and_backward_on_sampled_tiles(B, fullstep):
     # decision inside the guard band than in the smaller workloads
     assert ok.mean() > 0.95
     assert_close(o[ok, :3], ref["rgb"][ok], 1e-5, 1e-7, "rgb")
-    assert np.array_equal(host(vb.ncontrib)[idx][ok], ref["n_contrib"][ok])
+    ptile = (ys // 16) * pr["TX"] + xs // 16
+    got_last = last_ids(host(vb.vals), host(vb.ranges), ptile, host(vb.ncontrib)[idx])
+    assert np.array_equal(got_last[ok], last_ids(sv, rg, ptile, ref["n_contrib"])[ok])
     g = rng.normal(size=(xs.size, 3)) * 1e-3
     g[ref["flag"]] = 0.0
     dl = torch.zeros_like(vb.dL)
@@ -328,13 +405,14 @@ def test_full_size_forward_and_backward_on_sampled_tiles(B, fullstep):
     vb.dL = dl
     vb.render_bwd(B.raster_params())
     got = host(vb.g2d).T
-    g2d, g2d_abs = render.render_pixels_bwd(q, fullstep["sv"], fullstep["rg"], xs, ys, g, RP, with_abs=True)
+    g2d, g2d_abs = render.render_pixels_bwd(q, sv, rg, xs, ys, g, RP, with_abs=True)
     for f in range(9):
         assert_close(got[f], g2d[f], 1e-4, 2e-6 * g2d_abs[f] + 1e-12, f"g2d field {f}")
 
 
+@pytest.mark.parametrize("lm_mode", [0, 1], ids=["lm_rank1", "lm_diag"])
 @pytest.mark.parametrize("views", [[0, 50, 100], list(range(0, 150, 15))], ids=["K3", "K10"])
-def test_full_size_multi_view_step_properties(B, fullstep, views):
+def test_full_size_multi_view_step_properties(B, fullstep, views, lm_mode):
     """K = 3 and K = 10 views per step at 20%, fused and unfused final update.  The
     backward's float atomics sum in a different order on every run, so the
     two runs agree up to that rounding (the stage tests compare the fused
@@ -350,7 +428,7 @@ def test_full_size_multi_view_step_properties(B, fullstep, views):
     for fused in (True, False):
         E = [dev(synth.error_map(c.height, c.width, 200 + k).view(np.int16)) for k, c in enumerate(vcams)]
         A = [dev(synth.age_map(c.height, c.width, 300 + k).view(np.int16)) for k, c in enumerate(vcams)]
-        cfg = StepConfig(rate_permille=200, fuse_optimizer=fused, optim=dict(lm_mode=1))
+        cfg = StepConfig(rate_permille=200, fuse_optimizer=fused, optim=dict(lm_mode=lm_mode))
         tr = Trainer(dev(p.copy()), vcams, gts, cfg, E=E, A=A)
         used = tr.step(list(range(len(views))))
         torch.cuda.synchronize()
@@ -366,7 +444,7 @@ def test_full_size_multi_view_step_properties(B, fullstep, views):
         u = np.abs(a.astype(np.float64) - p) + np.abs(b.astype(np.float64) - p) if a is p1 else \
             np.abs(a.astype(np.float64)) + np.abs(b.astype(np.float64))
         assert (d > 1e-3 * u + 1e-12).mean() < 1e-3
-    assert 0.3 < t1.mean() <= 1.0 and (len(views) > 3 or t1.mean() < 1.0)
+    assert 0.1 < t1.mean() < 1.0
     assert np.array_equal(p1[:, ~t1], p[:, ~t1]) and not m1[:, ~t1].any() and not v1[:, ~t1].any()
     moved = (p1[:, t1] != p[:, t1]).any(axis=0)
     assert moved.mean() > 0.05

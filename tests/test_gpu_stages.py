@@ -14,7 +14,8 @@ import synth
 from oracle import binning, loss, maps, optim, project, project_bwd, render, sampler
 from oracle.params import LossParams, OptimParams, RasterParams, SampleParams
 
-from support import (assert_close, scene_c1, small_scene, splat_as_oracle, splat_record)
+from support import (assert_close, check_pair_lists, last_ids, scene_c1, small_scene, splat_as_oracle,
+                     splat_record)
 
 pytestmark = pytest.mark.gpu
 
@@ -86,7 +87,13 @@ def test_project_parity(B, case):
 
 # ------------------------------------------------------------------ binning + sort
 @pytest.mark.parametrize("case", ["c1_all", "c1_sampled", "ragged"])
-def test_bin_sort_bit_exact(B, case):
+def test_bin_sort_lists_against_rectangle_lists(B, case):
+    """The GPU's per-tile lists against the oracle's rectangle lists: an
+    order-preserving subsequence with consistent keys and ranges, every
+    dropped pair unable to composite anywhere in its tile (checked at all
+    256 pixel centres), only valid tiles listed, touched = the Gaussians
+    listed; and the capacity contract (a short capacity reports a count that
+    then suffices)."""
     if case.startswith("c1"):
         p, cams = scene_c1()
         cam = cams[0]
@@ -102,37 +109,36 @@ def test_bin_sort_bit_exact(B, case):
         ts = -np.ones(TX * TY, dtype=np.int32)
         ts[valid] = np.arange(valid.size)
         tile_slot = dev(ts)
-    fields, tau = binning.splat_fields(pr), binning.cull_threshold(1.0 / 255.0)
-    keys, vals = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY, valid, fields, tau)
-    sk, sv = binning.sort_pairs(keys, vals)
-    ranges = binning.tile_ranges(sk, TX * TY)
+    rec = splat_record(pr)
+    q = splat_as_oracle(pr, rec)
     rect = dev(pr["rect"].T.astype(np.int32))
-    splat = dev(splat_record(pr))
+    splat = dev(rec)
     depth = dev(pr["depth32"])
-    # one entry per kept tile (valid or not) of each Gaussian with a pair
-    gid, _, _ = binning.kept_tiles(pr["rect"], fields, tau)
-    kept = np.bincount(gid, minlength=n)
-    area = int(kept[np.unique(sv)].sum())
-    cap = area + 17
     rect_area = (pr["rect"][2] - pr["rect"][0]) * (pr["rect"][3] - pr["rect"][1])
-    assert area < int(rect_area[np.unique(sv)].sum())      # the ellipse test drops pairs
+    cap = int(rect_area[pr["visible"]].sum()) + 17              # the rectangle lists bound any list
     K = torch.empty(cap, dtype=torch.int64, device="cuda")
     V = torch.empty(cap, dtype=torch.int32, device="cuda")
     R = torch.empty((TX * TY, 2), dtype=torch.int32, device="cuda")
     touched = torch.zeros(n, dtype=torch.uint8, device="cuda")
     ws = torch.empty(B.tgs_bin_sort_workspace_size(n, cap, TX * TY), dtype=torch.uint8, device="cuda")
     npairs = B.tgs_bin_sort(rect, splat, depth, n, tile_slot, TX, TY, 1.0 / 255.0, K, V, cap, R, touched, ws)
-    assert npairs == sk.size
-    assert np.array_equal(host(K)[:npairs].view(np.uint64), sk)
-    assert np.array_equal(host(V)[:npairs].view(np.uint32), sv)
-    assert np.array_equal(host(R).astype(np.int64), ranges)
+    vals = host(V)[:npairs].view(np.uint32)
+    info = check_pair_lists(vals, host(R), npairs, q, valid, keys=host(K))
+    assert info["dropped"] > 0.15 * info["oracle"] and info["checked"] == info["dropped"]
     t_ref = np.zeros(n, dtype=np.uint8)
-    t_ref[np.unique(sv)] = 1
+    t_ref[np.unique(vals)] = 1
     assert np.array_equal(host(touched), t_ref)
-    # too-small capacity reports the required count
+    # too-small capacity reports the required count, which then suffices
     with pytest.raises(B.CapacityError) as ei:
         B.tgs_bin_sort(rect, splat, depth, n, tile_slot, TX, TY, 1.0 / 255.0, K, V, 10, R, None, ws)
-    assert ei.value.required == area
+    req = ei.value.required
+    assert npairs <= req <= int(rect_area[np.unique(vals)].sum())
+    ws2 = torch.empty(B.tgs_bin_sort_workspace_size(n, req, TX * TY), dtype=torch.uint8, device="cuda")
+    K2 = torch.empty(req, dtype=torch.int64, device="cuda")
+    V2 = torch.empty(req, dtype=torch.int32, device="cuda")
+    R2 = torch.empty((TX * TY, 2), dtype=torch.int32, device="cuda")
+    assert B.tgs_bin_sort(rect, splat, depth, n, tile_slot, TX, TY, 1.0 / 255.0, K2, V2, req, R2, None, ws2) == npairs
+    assert torch.equal(K2[:npairs], K[:npairs]) and torch.equal(V2[:npairs], V[:npairs]) and torch.equal(R2, R)
 
 
 # ------------------------------------------------------------------ sampler
@@ -346,9 +352,20 @@ def test_render_bwd_parity(B, case):
     if s is not None:
         vt, off, pix = dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"])
         n_st = s["valid_tiles"].size
+    touched = torch.full((p.shape[1],), 2, dtype=torch.uint8, device="cuda")
     B.tgs_render_bwd(dev(rec), dev(sv.view(np.int32)), dev(ranges.astype(np.int32)), TX, TY, cam.width,
-                     cam.height, vt, off, pix, n_st, n_pix, brp, dev(out), dev(ncv), dev(dl), G)
+                     cam.height, vt, off, pix, n_st, n_pix, brp, dev(out), dev(ncv), dev(dl), G, touched=touched)
     got = host(G).T
+    # touched: the Gaussians composited at a sample (1), the rest untouched (2)
+    t_got = host(touched)
+    assert set(np.unique(t_got).tolist()) <= {1, 2}
+    on = t_got == 1
+    ok = ~ref["flag"]
+    sure = render.render_pixels(q, sv, ranges, xs[ok], ys[ok], rp)["composited"]
+    near = np.zeros_like(on)
+    for t in np.unique(((ys // 16) * pr["TX"] + xs // 16)[~ok]):
+        near[sv[ranges[t, 0]:ranges[t, 1]].astype(np.int64)] = True
+    assert not (sure & ~on).any() and not (on & ~(ref["composited"] | near)).any() and sure.sum() > 100
     names = ["dx", "dy", "ca", "cb", "cc", "opacity", "r", "g", "b"]
     for f in range(9):
         # 1e-4 relative, plus 16 FP32 ulps of the error scale of each sum (see

@@ -26,78 +26,81 @@ def test_emit_loop_equals_vectorised():
     _, cam, pr = _scene()
     TX, TY = pr["TX"], pr["TY"]
     valid = np.array([0, 3, 5, 6, 7, 11, TX * TY - 1])
-    fields, tau = binning.splat_fields(pr), binning.cull_threshold(1.0 / 255.0)
     for vt in (None, valid):
-        for f, t in ((None, None), (fields, tau)):
-            k1, v1 = binning.emit_pairs(pr["rect"], pr["depth32"], TX, TY, vt, f, t)
-            k2, v2 = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY, vt, f, t)
-            assert np.array_equal(k1, k2) and np.array_equal(v1, v2)
+        k1, v1 = binning.emit_pairs(pr["rect"], pr["depth32"], TX, TY, vt)
+        k2, v2 = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY, vt)
+        assert np.array_equal(k1, k2) and np.array_equal(v1, v2) and k1.size > 100
 
 
-def test_cull_threshold():
-    # 2 ln(255) = 11.0825..., plus 0.1 %, rounded up to 1/64
-    assert binning.cull_threshold(1.0 / 255.0) == 710 / 64
-    for a in (1e-3, 1.0 / 255.0, 0.01, 0.1):
-        t = binning.cull_threshold(a)
-        assert 2 * math.log(1 / a) * 1.001 <= t < 2 * math.log(1 / a) * 1.001 + 1 / 64
-        assert (t * 64) == int(t * 64)
+def _rect_brute(px, py, r, TX, TY):
+    """The tiles whose 16-pixel span meets the closed interval [p - r, p + r - 1]
+    on both axes, found by walking every tile of the grid."""
+    xs = [tx for tx in range(TX) if 16 * tx <= px + r - 1 and px - r < 16 * tx + 16]
+    ys = [ty for ty in range(TY) if 16 * ty <= py + r - 1 and py - r < 16 * ty + 16]
+    return (xs[0], ys[0], xs[-1] + 1, ys[-1] + 1) if xs and ys else None
 
 
-def test_cull_never_drops_a_compositing_pixel():
-    """Brute force over every pixel centre of every culled rect tile: with
-    the largest opacity (1) the Gaussian's alpha stays below alpha_min."""
-    amin = 1.0 / 255.0
-    tau = binning.cull_threshold(amin)
-    culled_total = 0
-    for seed, lm in ((2, -3.0), (4, -2.5), (6, -3.5)):
-        p = synth.gaussians(400, seed, logscale_mean=lm)
-        cam = synth.look_at((2.0, -1.5, 1.2), fx=105.6, fy=105.6, width=96, height=76)
-        pr = project.project(p, cam)
-        f = binning.splat_fields(pr)
-        gid, tx, ty = binning.rect_tiles(pr["rect"])
-        g = {k: v[gid] for k, v in f.items()}
-        keep = binning.tile_touches(tx, ty, g["xi"], g["xf"], g["yi"], g["yf"], g["A"], g["B"], g["C"], tau)
-        lx, ly = np.meshgrid(np.arange(16.0), np.arange(16.0))
-        for j in np.nonzero(~keep)[0]:
-            dx = (16 * tx[j] + lx) - (g["xi"][j] + g["xf"][j])
-            dy = (16 * ty[j] + ly) - (g["yi"][j] + g["yf"][j])
-            q = g["A"][j] * dx * dx + 2 * g["B"][j] * dx * dy + g["C"][j] * dy * dy
-            assert (np.exp(-0.5 * q) < amin).all()
-        culled_total += int((~keep).sum())
-        assert (~keep).mean() > 0.15          # the test does remove pairs
-    assert culled_total > 100
+def test_tile_rectangle_brute_force():
+    """The rectangle of the projection is exactly the set of tiles meeting
+    [p - r, p + r - 1] on each axis (grid walk), and it holds every pixel
+    index within that interval: pixel centres up to r - 1 from the centre on
+    the right and r on the left (the 3D Gaussian splatting +15 rounding of
+    the upper bound).  Checked on a projected scene and on hand-placed
+    centres on and near tile boundaries, inside and outside the image."""
+    TX, TY = 6, 5
+    cases = []
+    for px in (-20.0, -0.5, 0.0, 15.0, 15.5, 16.0, 31.999, 40.25, 95.0, 96.0, 120.0):
+        for py in (-3.0, 0.0, 16.0, 47.5, 79.0, 80.0):
+            for r in (1, 3, 8, 16, 17, 40):
+                cases.append((px, py, r))
+    _, cam, pr = _scene()
+    vis = np.nonzero(pr["visible"])[0]
+    assert vis.size > 200
+    for g in vis:
+        want = _rect_brute(pr["mean2d"][0][g], pr["mean2d"][1][g], int(pr["radius"][g]), pr["TX"], pr["TY"])
+        got = tuple(int(v) for v in pr["rect"][:, g])
+        assert want is not None and got == want, (g, got, want)
+    n_empty = 0
+    for px, py, r in cases:
+        got = project.rect_of((px, py), r, TX, TY)
+        want = _rect_brute(px, py, r, TX, TY)
+        if want is None:
+            assert got[0] >= got[2] or got[1] >= got[3], (px, py, r, got)
+            n_empty += 1
+            continue
+        assert got == want, (px, py, r, got, want)
+        for i in range(int(np.ceil(px - r)), int(np.floor(px + r - 1)) + 1):
+            for j in range(int(np.ceil(py - r)), int(np.floor(py + r - 1)) + 1):
+                if 0 <= i < 16 * TX and 0 <= j < 16 * TY:
+                    assert got[0] <= i // 16 < got[2] and got[1] <= j // 16 < got[3]
+    assert n_empty > 10 and len(cases) - n_empty > 300
 
 
-def test_cull_matches_dense_rectangle_minimum():
-    """Random SPD conics and rectangles: the decision agrees with the minimum
-    of q over a dense grid of the rectangle wherever that minimum is clearly
-    below or above tau (a dropped factor, sign or swapped axis fails)."""
-    rng = np.random.default_rng(11)
-    tau = 11.0
-    n_in = n_out = 0
-    for _ in range(400):
-        th = rng.uniform(0, np.pi)
-        s1, s2 = np.exp(rng.uniform(-1, 3, size=2))
-        R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
-        Sig = R @ np.diag([s1 * s1, s2 * s2]) @ R.T
-        Q = np.linalg.inv(Sig)
-        A, B, C = Q[0, 0], Q[0, 1], Q[1, 1]
-        cx, cy = rng.uniform(-60, 60, size=2)
-        xi, xf = np.floor(cx), cx - np.floor(cx)
-        yi, yf = np.floor(cy), cy - np.floor(cy)
-        tx, ty = rng.integers(-3, 3, size=2)
-        keep = bool(binning.tile_touches(tx, ty, xi, xf, yi, yf, A, B, C, tau))
-        gx = np.linspace(16 * tx, 16 * tx + 15, 301) - cx
-        gy = np.linspace(16 * ty, 16 * ty + 15, 301) - cy
-        X, Y = np.meshgrid(gx, gy)
-        qmin = (A * X * X + 2 * B * X * Y + C * Y * Y).min()
-        if qmin < 0.98 * tau:
-            assert keep
-            n_in += 1
-        elif qmin > 1.05 * tau + 0.5:
-            assert not keep
-            n_out += 1
-    assert n_in > 30 and n_out > 30
+def test_max_alpha_in_tile_brute_force():
+    """The per-tile maximum of o exp(power) against a pixel-by-pixel loop,
+    and two closed forms: a splat centred on a pixel centre of the tile
+    reaches o there; one centred 40 pixels left of the tile at sigma 4
+    reaches o exp(-(40 - 0)^2 / 32) at the tile's first column."""
+    _, cam, pr = _scene()
+    gid, tx, ty = binning.rect_tiles(pr["rect"])
+    tiles = ty * pr["TX"] + tx
+    pick = np.random.default_rng(3).choice(gid.size, 60, replace=False)
+    got = binning.max_alpha_in_tile(pr, gid[pick], tiles[pick], chunk=7)
+    for k, j in enumerate(pick):
+        g, t = gid[j], tiles[j]
+        best = 0.0
+        for ly in range(16):
+            for lx in range(16):
+                dx = 16 * (t % pr["TX"]) + lx - pr["mean2d"][0][g]
+                dy = 16 * (t // pr["TX"]) + ly - pr["mean2d"][1][g]
+                a, b, c = pr["conic"][:, g]
+                best = max(best, pr["opacity"][g] * math.exp(-0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy))
+        assert abs(got[k] - best) <= 1e-15 * max(best, 1e-300), (k, got[k], best)
+    iso = dict(mean2d=np.array([[21.0, 16.0 - 40.0], [9.0, 9.0]]), conic=np.array([[1 / 16, 1 / 16], [0, 0],
+                                                                                      [1 / 16, 1 / 16]]),
+               opacity=np.array([0.7, 0.9]), TX=3)
+    m = binning.max_alpha_in_tile(iso, [0, 1], [1, 1])
+    assert m[0] == 0.7 and abs(m[1] - 0.9 * math.exp(-0.5 * 40.0 ** 2 / 16)) < 1e-30
 
 
 def test_sort_and_ranges_against_python():

@@ -171,8 +171,71 @@ def test_grad_screen_statistics():
     g = np.zeros((4, 9))
     g[:, 0:2] = [[3, 4], [-5, 12], [1, 1], [0, 0]]
     g[:, 2:] = 7.0                                    # other gradient fields do not enter
-    acc = density.grad_screen_accumulate(acc, g, np.array([2, 9, 0, 4]))
-    acc = density.grad_screen_accumulate(acc, g * 2, np.array([5, 0, 0, 1]))
+    # W = H = 2: NDC units equal pixel units
+    acc = density.grad_screen_accumulate(acc, g, np.array([2, 9, 0, 4]), 2, 2)
+    acc = density.grad_screen_accumulate(acc, g * 2, np.array([5, 0, 0, 1]), 2, 2)
     assert np.allclose(acc[:, 0], [5 + 10, 13, 0, 0])
     assert np.array_equal(acc[:, 1], [2, 1, 0, 2]) and np.array_equal(acc[:, 2], [5, 9, 0, 4])
     assert np.allclose(density.grad_screen_mean(acc), [7.5, 13, 0, 0])
+    # NDC units: x scaled by W/2, y by H/2 (a 6 x 8 image: (3, 4) -> (9, 16))
+    one = density.grad_screen_accumulate(np.zeros((1, 4)), g[:1], np.array([1]), 6, 8)
+    assert one[0, 0] == math.hypot(9.0, 16.0)
+
+
+def test_gradient_gate_and_selection_with_gate_and_prune_cadence():
+    acc = np.array([[6.0, 2.0, 0, 0],      # mean 3
+                    [1.0, 1.0, 0, 0],      # mean 1
+                    [9.0, 0.0, 0, 0],      # never projected
+                    [0.5, 1.0, 0, 0]])     # mean 0.5
+    absum = np.array([0.0, 0.0, 100.0, 8.0])  # abs means 0, 0, -, 8
+    gate = density.gradient_gate(acc, absum, tau_grad=2.0, tau_abs=5.0)
+    assert gate.tolist() == [True, False, False, True]
+    assert density.gradient_gate(acc, absum, 3.0, 8.0).tolist() == [True, False, False, True]
+    assert density.gradient_gate(acc, absum, 3.001, 8.001).tolist() == [False] * 4
+    s = np.array([4.0, 3.0, 2.0, 1.0])
+    m = density.select_masks(s, eta_topk=0.5, eta_final=0.5, gate=gate)
+    # top half densified by score (0 and 1), gated: only 0; keep the top half
+    assert m["densify"].tolist() == [True, False, False, False]
+    assert m["keep"].tolist() == [True, True, False, False]
+    m2 = density.select_masks(s, eta_topk=0.5, eta_final=0.5, gate=gate, prune=False)
+    assert m2["keep"].all() and m2["densify"].tolist() == [True, False, False, False]
+    # a pruned Gaussian is never densified
+    m3 = density.select_masks(s, eta_topk=1.0, eta_final=0.25, gate=np.ones(4, bool))
+    assert m3["densify"].tolist() == [True, False, False, False]
+
+
+def test_scene_extent_and_split_threshold():
+    # cameras on a sphere of radius 3 around the origin, symmetric: extent 1.1 * 3
+    c = 3.0 * np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], dtype=float)
+    assert abs(density.scene_extent(c) - 3.3) < 1e-12
+    assert abs(density.scene_extent(c + 5.0) - 3.3) < 1e-12        # translation does not change it
+    assert abs(np.exp(density.split_log_threshold(0.01, 3.3)) - 0.033) < 1e-15
+
+
+def test_absolute_centre_gradient_statistic():
+    """The absolute statistic is the sum over pixels of each pixel's own
+    centre-gradient norm: for one pixel it equals the norm of the summed
+    gradient; for two pixels placed symmetrically about an isotropic splat the
+    centre gradients cancel in the sum but not in the absolute statistic;
+    in general it bounds the norm of the sum (triangle inequality)."""
+    pr = _proj([(5.0, 5.0)], 2.0, [0.5])
+    pr["rgb"] = np.array([[0.8], [0.3], [0.1]])
+    vals = np.array([0], dtype=np.uint32)
+    ranges = np.array([[0, 1]])
+    rp = RasterParams()
+    g1, a1 = render.render_pixels_bwd(pr, vals, ranges, [7], [5], np.array([[1.0, 0.5, -0.2]]), rp,
+                                      centre_abs_scale=(3.0, 2.0))
+    assert abs(a1[0] - math.hypot(3.0 * g1[0, 0], 2.0 * g1[1, 0])) < 1e-15 and a1[0] > 0
+    g2, a2 = render.render_pixels_bwd(pr, vals, ranges, [7, 3], [5, 5], np.array([[1.0, 0.5, -0.2]] * 2), rp,
+                                      centre_abs_scale=(3.0, 2.0))
+    assert abs(g2[0, 0]) < 1e-15 and abs(g2[1, 0]) < 1e-15       # the two pulls cancel
+    assert abs(a2[0] - 2.0 * a1[0]) < 1e-14                       # the absolute sums do not
+    p, cam = small_scene(n=600, seed=4)
+    prs = project.project(p, cam, rp)
+    _, sv, rg = binning.bin_and_sort(prs)
+    rng = np.random.default_rng(2)
+    xs, ys = rng.integers(0, cam.width, 300), rng.integers(0, cam.height, 300)
+    g, a = render.render_pixels_bwd(prs, sv, rg, xs, ys, rng.normal(size=(300, 3)), rp,
+                                    centre_abs_scale=(cam.width / 2, cam.height / 2))
+    norm = np.hypot(cam.width / 2 * g[0], cam.height / 2 * g[1])
+    assert (a >= norm * (1 - 1e-12)).all() and (a > 0).sum() > 50

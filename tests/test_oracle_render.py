@@ -19,16 +19,11 @@ def _scene(n=120, seed=7, W=72, H=56, logscale=-2.6):
 
 def _brute_pixel(pr, x, y, rp):
     """Eq. (alpha_comp) for one pixel by a plain loop: every visible Gaussian
-    whose tile rectangle holds the pixel's tile and whose ellipse test keeps
-    that tile, sorted by (FP32 depth, id)."""
-    tau = binning.cull_threshold(rp.alpha_min)
+    whose tile rectangle holds the pixel's tile, sorted by (FP32 depth, id)."""
     rp = rp.f64()
     tx, ty = x // 16, y // 16
-    f = binning.splat_fields(pr)
     members = [g for g in range(pr["opacity"].size) if pr["visible"][g]
-               and pr["rect"][0, g] <= tx < pr["rect"][2, g] and pr["rect"][1, g] <= ty < pr["rect"][3, g]
-               and bool(binning.tile_touches(tx, ty, *(f[k][g] for k in ("xi", "xf", "yi", "yf", "A", "B", "C")),
-                                             tau))]
+               and pr["rect"][0, g] <= tx < pr["rect"][2, g] and pr["rect"][1, g] <= ty < pr["rect"][3, g]]
     members.sort(key=lambda g: (float(pr["depth32"][g]), g))
     T, C, ncon, nblend = 1.0, np.zeros(3), 0, 0
     for pos, g in enumerate(members):
@@ -193,28 +188,32 @@ def test_full_chain_matches_finite_differences_smooth_mode():
         assert abs(fd - an) <= 2e-6 * max(1.0, abs(an)), (name, fd, an)
 
 
-def test_culled_lists_leave_images_and_gradients_unchanged():
-    """The ellipse test only drops pairs that never composite: colour,
-    transmittance, blend counts and the adjoint equal those of the plain
-    rectangle lists exactly (only list positions, n_contrib, shift)."""
+def test_dropping_non_compositing_pairs_leaves_images_and_gradients_unchanged():
+    """A list without the pairs that stay below alpha_min at every pixel
+    centre of their tile (max_alpha_in_tile) renders the same colour,
+    transmittance and blend counts, and has the same adjoint, as the
+    rectangle list: the argument that lets a GPU list be any order-preserving
+    subsequence that keeps every pair able to composite."""
     for seed, ls in ((21, -2.6), (22, -2.2)):
         p, cam = _scene(n=150, seed=seed, logscale=ls)
         rp = RasterParams()
         pr = project.project(p, cam, rp)
         TX, TY = pr["TX"], pr["TY"]
-        k0, v0 = binning.emit_pairs_fast(pr["rect"], pr["depth32"], TX, TY)
-        sk0, sv0 = binning.sort_pairs(k0, v0)
-        rg0 = binning.tile_ranges(sk0, TX * TY)
-        sk1, sv1, rg1 = binning.bin_and_sort(pr)
-        assert sv1.size < sv0.size
+        sk0, sv0, rg0 = binning.bin_and_sort(pr)
+        tiles = (sk0 >> np.uint64(32)).astype(np.int64)
+        keep = binning.max_alpha_in_tile(pr, sv0, tiles) >= rp.f64().alpha_min
+        assert 0.1 < 1 - keep.mean() < 0.9
+        sk1, sv1 = sk0[keep], sv0[keep]
+        rg1 = binning.tile_ranges(sk1, TX * TY)
         ys, xs = np.mgrid[0:cam.height, 0:cam.width]
         xs, ys = xs.ravel(), ys.ravel()
         a = render.render_pixels(pr, sv0, rg0, xs, ys, rp)
         b = render.render_pixels(pr, sv1, rg1, xs, ys, rp)
         assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["T"], b["T"])
-        assert np.array_equal(a["n_blend"], b["n_blend"])
+        assert np.array_equal(a["n_blend"], b["n_blend"]) and np.array_equal(a["composited"], b["composited"])
         assert (b["n_eval"] <= a["n_eval"]).all() and b["n_eval"].sum() < a["n_eval"].sum()
         dL = np.random.default_rng(seed).normal(size=(xs.size, 3))
         ga = render.render_pixels_bwd(pr, sv0, rg0, xs, ys, dL, rp)
         gb = render.render_pixels_bwd(pr, sv1, rg1, xs, ys, dL, rp)
-        assert np.array_equal(ga, gb)
+        # equal up to the summation order numpy picks for the longer lists
+        assert np.allclose(ga, gb, rtol=1e-12, atol=1e-14 * np.abs(ga).max())
