@@ -21,11 +21,22 @@ The arrays are laid out per tile as [pixels, Gaussians] so each formula reads
 as written; T is the running product taken left to right (cumprod), the same
 sequence of multiplications as the scalar loop.
 
-Guard band: a pixel is flagged when one of its discrete decisions lies within
-a relative ``guard`` of its threshold (alpha vs alpha_min or alpha_max,
-T (1 - alpha) vs T_min).  FP32 and FP64 evaluations can take such a decision
-differently; tests exclude flagged pixels from element-wise comparison and
-bound how many there are.
+Guard band: a pixel is flagged when one of its discrete decisions (alpha vs
+alpha_min or alpha_max, T (1 - alpha) vs T_min) lies within ``guard`` times
+an error bound of an FP32 evaluation of that same quantity.  The bound
+follows from the arithmetic, per (pixel, Gaussian): with u = 2^-24 and
+S = |a| dx^2 / 2 + |c| dy^2 / 2 + |b dx dy| the magnitude of the exponent's
+terms, an FP32 exponent (the conic rounded to FP32 and scaled, the centre
+offset, the products and the sums each rounded once) carries an absolute
+error of a small multiple of u S; 32 u S is taken, about twice the largest
+error an FP32 emulation of that evaluation shows on the tiny and the
+rasterizer-scaling workloads.  So alpha carries a relative error of at most
+eps_a = 32 u S + 8 u (exponential, opacity and product included).  The
+transmittance after position k carries a relative error of at most the sum
+over the positions composited up to k of 2 u + eps_a alpha / (1 - alpha).
+FP32 and FP64 evaluations can take a decision inside its band differently;
+tests exclude flagged pixels from element-wise comparison and bound how many
+there are.
 """
 from __future__ import annotations
 
@@ -34,6 +45,7 @@ import numpy as np
 from .params import RasterParams
 
 TILE = 16
+U32 = 2.0 ** -24        # unit roundoff of FP32
 
 
 def _tile_eval(proj, gids, xs, ys, rp):
@@ -47,6 +59,8 @@ def _tile_eval(proj, gids, xs, ys, rp):
     araw = o[None, :] * G
     alpha = np.minimum(rp.alpha_max, araw)
     ok = (power <= 0.0) & (alpha >= rp.alpha_min)
+    S = 0.5 * np.abs(a)[None, :] * dx * dx + 0.5 * np.abs(c)[None, :] * dy * dy + np.abs(b[None, :] * dx * dy)
+    eps_a = 32.0 * U32 * S + 8.0 * U32
     av = np.where(ok, alpha, 0.0)
     one_m = 1.0 - av
     K = gids.size
@@ -57,14 +71,17 @@ def _tile_eval(proj, gids, xs, ys, rp):
     s = np.where(has_stop, np.argmax(stop, axis=1), K)           # first stopping position
     kidx = np.arange(K)[None, :]
     contrib = ok & (kidx < s[:, None])
+    # error bound of the FP32 transmittance after each position: the sum over
+    # the composited positions before it and the position itself
+    step_eps = 2.0 * U32 + eps_a * av / np.maximum(1.0 - av, 1e-300)
+    eps_T = np.cumsum(np.where(contrib | stop, step_eps, 0.0), axis=1)
     return dict(dx=dx, dy=dy, power=power, G=G, araw=araw, alpha=alpha, ok=ok,
                 T_before=T_before, T_after=T_after, contrib=contrib, stop_at=s,
-                has_stop=has_stop, a=a, b=b, c=c, o=o)
+                has_stop=has_stop, a=a, b=b, c=c, o=o, eps_a=eps_a, eps_T=eps_T)
 
 
 def render_pixels(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs: np.ndarray,
-                  ys: np.ndarray, rp: RasterParams = RasterParams(), guard: float = 1e-4,
-                  guard_T: float = 2e-3) -> dict:
+                  ys: np.ndarray, rp: RasterParams = RasterParams(), guard: float = 2.0) -> dict:
     """Render the pixels (xs[i], ys[i]) (any order; grouped by tile internally).
 
     Returns rgb [P, 3], T [P], n_contrib [P], n_eval [P], n_blend [P], flag [P]
@@ -108,9 +125,10 @@ def render_pixels(proj: dict, sorted_vals: np.ndarray, ranges: np.ndarray, xs: n
         nblend[sel] = ev["contrib"].sum(axis=1)
         # guard band over the evaluated positions
         evaluated = np.arange(K)[None, :] < neval[sel][:, None]
-        near_min = np.abs(ev["araw"] - rp.alpha_min) <= guard * rp.alpha_min
-        near_max = np.abs(ev["araw"] - rp.alpha_max) <= guard * rp.alpha_max
-        near_T = ev["ok"] & (np.abs(ev["T_after"] - rp.T_min) <= guard_T * rp.T_min)
+        band_a = guard * ev["eps_a"] * ev["araw"]
+        near_min = np.abs(ev["araw"] - rp.alpha_min) <= band_a
+        near_max = np.abs(ev["araw"] - rp.alpha_max) <= band_a
+        near_T = ev["ok"] & (np.abs(ev["T_after"] - rp.T_min) <= guard * ev["eps_T"] * ev["T_after"])
         flag[sel] = (evaluated & (near_min | near_max | near_T)).any(axis=1)
     return dict(rgb=out, T=T_out, n_contrib=ncon, n_eval=neval, n_blend=nblend, flag=flag,
                 composited=composited)

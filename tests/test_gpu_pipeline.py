@@ -127,7 +127,7 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
         o = host(vb.out)[:P]
         flag = fv["out"]["flag"]
         ok = ~flag
-        assert ok.mean() > 0.995
+        assert ok.mean() > 0.999
         assert_close(o[ok, :3], fv["out"]["rgb"][ok], 1e-5, 1e-6, f"view {v} rgb")
         tiles = (fv["ys"] // 16) * fv["proj"]["TX"] + fv["xs"] // 16
         got_last = last_ids(host(vb.vals), host(vb.ranges), tiles, host(vb.ncontrib)[:P])
@@ -145,7 +145,7 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     loss_gpu = tr.loss_value(used)
     assert abs(loss_gpu - ref["loss"]) <= 1e-4 * abs(ref["loss"])
     ex = _excluded_gaussians(ref, range(4), n)
-    assert ex.mean() < 0.35
+    assert ex.mean() < 0.15, ex.mean()
     t_gpu = host(tr.touched).astype(bool)
     assert np.array_equal(t_gpu[~ex], ref["touched"][~ex]) and ref["touched"].sum() > 2000
     keep = ~ex
@@ -389,9 +389,9 @@ def test_full_size_forward_and_backward_on_sampled_tiles(B, fullstep):
     assert np.array_equal(host(vb.pix)[idx], s["pix"])
     o = host(vb.out)[idx]
     ok = ~ref["flag"]
-    # pixels here evaluate several hundred Gaussians, so more of them hold a
-    # decision inside the guard band than in the smaller workloads
-    assert ok.mean() > 0.95
+    # pixels here evaluate several hundred Gaussians; a few may hold a
+    # decision inside the guard band
+    assert ok.mean() > 0.99
     assert_close(o[ok, :3], ref["rgb"][ok], 1e-5, 1e-7, "rgb")
     ptile = (ys // 16) * pr["TX"] + xs // 16
     got_last = last_ids(host(vb.vals), host(vb.ranges), ptile, host(vb.ncontrib)[idx])

@@ -1,6 +1,8 @@
 """Pins of the oracle's sparse NCC loss, error/age maps and hybrid optimizer
 against identities, finite differences, numpy/torch library routines and
 closed forms (no GPU)."""
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -81,6 +83,84 @@ def test_full_sparse_loss_gradient_matches_finite_differences():
 
 
 # ---------------------------------------------------------------- maps
+def _rne(x: Fraction, mant: int, emin: int) -> Fraction:
+    """x rounded to nearest, ties to even, in a binary format with ``mant``
+    significand bits and smallest normal exponent ``emin`` (subnormals
+    included, no overflow handling), in exact rational arithmetic."""
+    if x == 0:
+        return Fraction(0)
+    sgn = 1 if x > 0 else -1
+    a = abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    while Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    q = Fraction(2) ** (max(e, emin) - (mant - 1))           # spacing at x
+    k = a / q
+    fl = k.numerator // k.denominator
+    rem = k - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return sgn * fl * q
+
+
+def _half_bits(v: Fraction) -> int:
+    """Bits of a non-negative value that is exactly a finite half."""
+    if v == 0:
+        return 0
+    e = 30
+    while e > 0 and Fraction(2) ** (e - 15) > v:
+        e -= 1
+    if e <= 0:                                                 # subnormal
+        return int(v / Fraction(2) ** -24)
+    return (e << 10) | int(v / Fraction(2) ** (e - 15) * 1024 - 1024)
+
+
+def _half_value(bits: int) -> Fraction:
+    e, m = (bits >> 10) & 31, bits & 1023
+    return Fraction(m, 1024) * Fraction(2) ** -14 if e == 0 else (1 + Fraction(m, 1024)) * Fraction(2) ** (e - 15)
+
+
+def _ema_bits(E_bits: int, e: float, beta: float) -> int:
+    """Eq. (ema_err) built up from exact rationals: the FP32 constants beta
+    and 1 - beta, both products and the sum each rounded to FP32 (24 bits),
+    then the result rounded to half (11 bits, subnormals below 2^-14)."""
+    b = _rne(Fraction(beta), 24, -126)
+    omb = _rne(1 - b, 24, -126)
+    t1 = _rne(omb * _half_value(E_bits), 24, -126)
+    t2 = _rne(b * Fraction(np.float32(e).item()), 24, -126)
+    return _half_bits(_rne(t1 + t2, 11, -14))
+
+
+def test_ema_rounding_matches_exact_rational_construction():
+    """The EMA blend's bits against a construction in exact rationals that
+    uses no floating-point conversion: random half maps (subnormals, large
+    values) and errors, and crafted ties at beta = 1/2 where E and e are
+    neighbouring halves h1 < h2, so the FP32 blend is exactly their midpoint
+    and round-to-nearest-even must pick the one with the even significand."""
+    rng = np.random.default_rng(11)
+    H, W = 6, 40
+    E = rng.integers(0, 0x7800, size=(H, W)).astype(np.uint16)           # finite, below 32768
+    E[0, :8] = rng.integers(1, 1024, size=8)                              # subnormals
+    A = np.zeros((H, W), dtype=np.uint16)
+    ys, xs = np.nonzero(np.ones((H, W), bool))
+    e = np.abs(rng.normal(0.0, 1.0, size=xs.size)).astype(np.float32)
+    e[:10] = rng.uniform(0, 1e-5, size=10).astype(np.float32)
+    for beta in (0.4, 0.25):
+        En, _ = maps.ema_age_update(E, A, xs, ys, e, beta)
+        want = [_ema_bits(int(E[y, x]), float(e[i]), beta) for i, (x, y) in enumerate(zip(xs, ys))]
+        assert np.array_equal(En[ys, xs], np.array(want, dtype=np.uint16))
+    # ties: E = h1, e = h2 (adjacent halves), beta = 1/2
+    h1 = rng.integers(0x0400, 0x7000, size=W).astype(np.uint16)
+    E2 = np.tile(h1, (1, 1))
+    e2 = (h1 + 1).view(np.float16).astype(np.float32)
+    En2, _ = maps.ema_age_update(E2, np.zeros_like(E2), np.arange(W), np.zeros(W, np.int64), e2, 0.5)
+    even = np.where(h1 % 2 == 0, h1, h1 + 1)
+    assert np.array_equal(En2[0], even)
+    assert np.array_equal(En2[0], [_ema_bits(int(h), float(x), 0.5) for h, x in zip(h1, e2)])
+
+
 def test_ema_and_age_update_closed_form():
     H, W = 8, 12
     rng = np.random.default_rng(5)
@@ -92,8 +172,8 @@ def test_ema_and_age_update_closed_form():
     e = np.array([0.3, 1.7, 0.0], dtype=np.float32)
     En, An = maps.ema_age_update(E.view(np.uint16), A, xs, ys, e, 0.4)
     En = En.view(np.float16)
-    expect = (np.float32(0.6) * E[ys, xs].astype(np.float32) + np.float32(0.4) * e).astype(np.float16)
-    assert np.array_equal(En[ys, xs], expect)
+    expect = [_ema_bits(int(E.view(np.uint16)[y, x]), float(e[i]), 0.4) for i, (x, y) in enumerate(zip(xs, ys))]
+    assert np.array_equal(En.view(np.uint16)[ys, xs], np.array(expect, dtype=np.uint16))
     mask = np.ones((H, W), bool)
     mask[ys, xs] = False
     assert np.array_equal(En[mask].view(np.uint16), E[mask].view(np.uint16))

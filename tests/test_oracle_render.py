@@ -217,3 +217,167 @@ def test_dropping_non_compositing_pairs_leaves_images_and_gradients_unchanged():
         gb = render.render_pixels_bwd(pr, sv1, rg1, xs, ys, dL, rp)
         # equal up to the summation order numpy picks for the longer lists
         assert np.allclose(ga, gb, rtol=1e-12, atol=1e-14 * np.abs(ga).max())
+
+
+# ---------------------------------------------------------------- threshold branches
+def _splats(centres, conics, opacities, colours, TX=1, TY=1):
+    """A projection record built by hand: splats at the given tile-space
+    centres, all listed in tile 0 in the given order."""
+    n = len(opacities)
+    pr = dict(mean2d=np.array(centres, dtype=np.float64).T.copy(),
+              conic=np.array(conics, dtype=np.float64).T.copy(),
+              opacity=np.array(opacities, dtype=np.float64),
+              rgb=np.array(colours, dtype=np.float64).T.copy(), TX=TX, TY=TY)
+    sv = np.arange(n, dtype=np.uint32)
+    ranges = np.zeros((TX * TY, 2), dtype=np.int64)
+    ranges[0] = (0, n)
+    return pr, sv, ranges
+
+
+def test_alpha_max_clamp_zeroes_opacity_and_geometry_gradient():
+    """One Gaussian whose o G exceeds alpha_max at a pixel composites exactly
+    alpha_max there: the colour is alpha_max c + (1 - alpha_max) bg, its
+    gradient wrt the colour is alpha_max dL, and the opacity, centre and
+    conic gradients of that pixel are exactly zero (the clamp is flat).  At
+    a pixel where o G is below alpha_max the same Gaussian gets the
+    unclamped derivatives, which finite differences confirm."""
+    rp = RasterParams(bg=(0.1, 0.2, 0.3))
+    amax = rp.f64().alpha_max
+    pr, sv, rg = _splats([(7.3, 8.1)], [(0.02, 0.004, 0.03)], [0.999], [(0.6, 0.3, 0.9)])
+    xs, ys = np.array([7, 15]), np.array([8, 1])
+    ev = render.render_pixels(pr, sv, rg, xs, ys, rp)
+    G = np.exp(-0.5 * (0.02 * 0.3 ** 2 + 0.03 * 0.1 ** 2) - 0.004 * (-0.3) * (-0.1))
+    assert 0.999 * G > amax                                      # the clamped pixel
+    bg = np.asarray(rp.f64().bg)
+    assert np.allclose(ev["rgb"][0], amax * pr["rgb"][:, 0] + (1 - amax) * bg, rtol=0, atol=1e-15)
+    dL = np.array([[0.7, -1.1, 0.4], [0.0, 0.0, 0.0]])
+    g = render.render_pixels_bwd(pr, sv, rg, xs, ys, dL, rp)
+    assert (g[0:6, 0] == 0).all()
+    assert np.allclose(g[6:9, 0], amax * dL[0], rtol=1e-15, atol=0)
+    # the unclamped pixel: non-zero derivatives that match finite differences
+    dL2 = np.array([[0.0, 0.0, 0.0], [0.7, -1.1, 0.4]])
+    g2 = render.render_pixels_bwd(pr, sv, rg, xs, ys, dL2, rp)
+    assert (g2[0:6, 0] != 0).all()
+    for name, comp, row in (("mean2d", 0, 0), ("conic", 1, 3), ("opacity", None, 5)):
+        h = 1e-7
+        vals = []
+        for sgn in (1, -1):
+            q = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in pr.items()}
+            if comp is None:
+                q[name] = q[name] + sgn * h
+            else:
+                q[name][comp] += sgn * h
+            vals.append((dL2 * render.render_pixels(q, sv, rg, xs, ys, rp)["rgb"]).sum())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g2[row, 0]) <= 1e-6 * abs(fd), (name, fd, g2[row, 0])
+
+
+def test_transmittance_stop_fixed_position_matches_finite_differences():
+    """Four broad Gaussians stacked on one pixel, each with alpha near 0.95:
+    T after them is 0.05, 2.5e-3, 1.25e-4, 6.25e-6, so the walk stops before
+    the fourth (T would fall below T_min = 1e-4) with a wide margin on both
+    sides.  The fourth Gaussian gets exactly zero gradient; the three in
+    front match finite differences of the rendered colour in every splat
+    field, and the colour is the closed form over the first three."""
+    rp = RasterParams(bg=(0.25, 0.5, 0.75))
+    c = 2.0e-3
+    cols = [(0.9, 0.1, 0.2), (0.3, 0.8, 0.4), (0.5, 0.5, 0.9), (0.1, 0.9, 0.6)]
+    pr, sv, rg = _splats([(6.2, 7.4), (5.1, 9.3), (8.8, 6.6), (7.0, 7.0)],
+                         [(c, 0.0002, c * 1.3), (c * 0.8, -0.0003, c), (c * 1.1, 0.0001, c * 0.9), (c, 0.0, c)],
+                         [0.955, 0.952, 0.957, 0.95], cols)
+    xs, ys = np.array([7]), np.array([7])
+    out = render.render_pixels(pr, sv, rg, xs, ys, rp)
+    assert out["n_contrib"][0] == 3 and out["n_blend"][0] == 3 and out["n_eval"][0] == 4
+    # closed form over the first three
+    d = np.array([7.0, 7.0])[:, None] - pr["mean2d"]
+    a_, b_, c_ = pr["conic"]
+    alpha = pr["opacity"] * np.exp(-0.5 * (a_ * d[0] ** 2 + c_ * d[1] ** 2) - b_ * d[0] * d[1])
+    T = np.concatenate([[1.0], np.cumprod(1 - alpha)])
+    assert T[3] > 1.2 * rp.T_min and T[4] < 0.2 * rp.T_min
+    want = (T[:3, None] * alpha[:3, None] * pr["rgb"][:, :3].T).sum(0) + T[3] * np.asarray(rp.f64().bg)
+    assert np.allclose(out["rgb"][0], want, rtol=1e-14, atol=0)
+    dL = np.array([[0.6, -0.9, 1.3]])
+    g = render.render_pixels_bwd(pr, sv, rg, xs, ys, dL, rp)
+    assert (g[:, 3] == 0).all() and (g[:, :3] != 0).all()
+    fields = [("mean2d", 0), ("mean2d", 1), ("conic", 0), ("conic", 1), ("conic", 2),
+              ("opacity", None), ("rgb", 0), ("rgb", 1), ("rgb", 2)]
+    for row, (name, comp) in enumerate(fields):
+        for k in range(3):
+            h = 1e-6
+            vals = []
+            for sgn in (1, -1):
+                q = {kk: (v.copy() if isinstance(v, np.ndarray) else v) for kk, v in pr.items()}
+                if comp is None:
+                    q[name][k] += sgn * h
+                else:
+                    q[name][comp, k] += sgn * h
+                r = render.render_pixels(q, sv, rg, xs, ys, rp)
+                assert r["n_contrib"][0] == 3
+                vals.append((dL * r["rgb"]).sum())
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - g[row, k]) <= 1e-6 * max(abs(fd), 1e-2), (name, comp, k, fd, g[row, k])
+
+
+def test_guard_band_bounds_an_fp32_evaluation():
+    """The guard band is wide enough: an FP32 evaluation of each alpha (the
+    splat record rounded to FP32, the tile-local centre as the exact integer
+    difference plus the fraction, the exponent from single-rounded products
+    and sums, a rounded exponential) and of the running transmittance stays
+    within the oracle's error bounds eps_a and eps_T (half the band at the
+    default guard of two) at every evaluated position of two tiny-workload
+    views' sampled tiles; and few pixels are flagged."""
+    from support import splat_record
+    f32 = np.float32
+    l2e = f32(1.4426950408889634)
+    rp = RasterParams()
+    r64 = rp.f64()
+    p = synth.gaussians(10000, synth.SEED_SCENE)
+    cams = synth.tetra_cameras()
+    worst_a = worst_T = 0.0
+    flagged = total = 0
+    for vi in (0, 3):
+        cam = cams[vi]
+        pr = project.project(p, cam, rp)
+        rec = splat_record(pr)
+        tiles = np.random.default_rng(vi).choice(256, 24, replace=False)
+        _, sv, rg = binning.bin_and_sort(pr, tiles)
+        rng = np.random.default_rng(10 + vi)
+        for t in tiles:
+            lo, hi = rg[t]
+            gids = sv[lo:hi].astype(np.int64)
+            if gids.size == 0:
+                continue
+            loc = rng.choice(256, 48, replace=False)
+            xs = (t % 16) * 16 + loc % 16
+            ys = (t // 16) * 16 + loc // 16
+            ev = render._tile_eval(pr, gids, xs.astype(float), ys.astype(float), r64)
+            r = rec[gids]
+            x0, y0 = f32((t % 16) * 16), f32((t // 16) * 16)
+            gx = (r[:, 0] - x0) + r[:, 2]
+            gy = (r[:, 1] - y0) + r[:, 3]
+            A = r[:, 4] * f32(-0.5 * l2e)
+            Bq = r[:, 5] * (-l2e)
+            C = r[:, 6] * f32(-0.5 * l2e)
+            dx = (loc % 16).astype(f32)[:, None] - gx[None]
+            dy = (loc // 16).astype(f32)[:, None] - gy[None]
+            inner = (C[None].astype(np.float64) * (dy * dy) + (Bq[None] * (dx * dy))).astype(f32)
+            p2 = (A[None].astype(np.float64) * (dx * dx) + inner).astype(f32)
+            a32 = r[None, :, 7] * np.exp2(p2.astype(np.float64)).astype(f32)
+            neval = np.where(ev["has_stop"], ev["stop_at"] + 1, gids.size)
+            m = (np.arange(gids.size)[None] < neval[:, None]) & (ev["araw"] > 1e-30)
+            rel = np.abs(a32 - ev["araw"]) / np.where(m, ev["araw"], 1.0)
+            worst_a = max(worst_a, float((rel / ev["eps_a"])[m].max()))
+            al = np.minimum(f32(r64.alpha_max), a32)
+            T = np.ones(xs.size, f32)
+            for k in range(gids.size):
+                Tn = T * (f32(1) - al[:, k])
+                mk = ev["contrib"][:, k] | (ev["ok"][:, k] & (ev["stop_at"] == k))
+                if mk.any():
+                    relT = np.abs(Tn - ev["T_after"][:, k])[mk] / ev["T_after"][mk, k]
+                    worst_T = max(worst_T, float((relT / ev["eps_T"][mk, k]).max()))
+                T = np.where(ev["contrib"][:, k], Tn, T)
+            out = render.render_pixels(pr, sv, rg, xs, ys, rp)
+            flagged += int(out["flag"].sum())
+            total += xs.size
+    assert 0.05 < worst_a < 0.8 and worst_T < 0.8, (worst_a, worst_T)
+    assert flagged <= 1e-3 * total, (flagged, total)
