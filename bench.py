@@ -1,14 +1,23 @@
 """Benchmark of the sparse-pixel training step on one MI355X.
 
-Workload (rasterizer scaling): 300k Gaussians (means U[-1,1]^3, log-scales
-N(-4, 0.5), random unit quaternions, opacity logits N(0,1), SH degree 3
-N(0, 0.2)), one 1296x840 view, error-guided sampling of every tile at 25 %
-(64 of 256 pixels per tile), Charbonnier + sparse NCC loss, adjoint backward
-and the hybrid LM/Adam update.  A step runs every stage of the path: sample,
-project, bin/sort, forward, loss, error/age update, backward, projection
-backward, optimizer.  The dense GPU step (every pixel, same arithmetic) and
-the 100/50/25/10 % sweep are reported beside it; the oracle is timed on the
-host for a bounded sample of the same step.
+Headline workload (full training step): 1.5M Gaussians (means U[-1,1]^3,
+log-scales N(-4, 0.5), random unit quaternions, opacity logits N(0,1), SH
+degree 3 N(0, 0.2)), 150 cameras of 1600x1060 (f = 1875) on the upper
+hemisphere of radius 3, targets rendered densely from a seed-perturbed copy
+of the scene plus N(0, 0.01) noise, error maps initialised from the dense L1
+error of the initial model.  Each step trains K views (K = 3 and K = 10, a
+seeded random choice of distinct views per step) with error-guided sampling
+of 20 % of every tile's pixels (51 of 256), Charbonnier + sparse NCC loss,
+adjoint backward and the hybrid LM/Adam update.  A step runs every stage of
+the path for each view: sample, project, bin/sort, forward, loss, error/age
+update, backward, projection backward; then the update.  The dense GPU step
+(every pixel, same arithmetic) at the same K is reported beside it.
+
+Beside the headline: the rasterizer-scaling workload (300k Gaussians, one
+1296x840 view) at 100/50/25/10 % and dense, the density-control and
+learned tile-priority measurements and the matched-PSNR comparison on it;
+the oracle timed on the host for a bounded sample of one view of the full
+step, on one thread and on every core the process may use.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
 """
@@ -26,6 +35,15 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
+# full training step
+FULL_N = 1_500_000
+FULL_VIEWS = 150
+FULL_W, FULL_H = 1600, 1060
+FULL_RATE = 200              # per-mille of each tile's pixels (51 of 256)
+FULL_K = (3, 10)             # views per step (the schedule's K_min and K_max)
+HEADLINE_K = 3
+
+# rasterizer scaling
 N_GAUSS = 300_000
 WIDTH, HEIGHT = 1296, 840
 HEADLINE_RATE = 250          # per-mille of each tile's pixels
@@ -58,7 +76,7 @@ TP_EVAL_FROM = 400   # predictions scored from this step on
 TP_LR = 3e-3
 TP_SEED = 23
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_scaling_300k_25pct.txt")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_full_step_1p5m_20pct.txt")
 RASTER_SOURCES = ("paper_2606_15924_amd/csrc/raster.hip", "paper_2606_15924_amd/csrc/common.h")
 
 
@@ -109,20 +127,27 @@ def make_trainer(p, cam, gt, rate, dev, density_stats=False):
     return tr
 
 
-def run(tr, steps, warmup):
+def run(tr, steps, warmup, views_of=None):
     """Warmup, then an untimed pass with HIP events around every stage (the
     per-stage breakdown), then the timed steps.  Events cost the device a
     few microseconds each, so the timed steps bracket only the dominant
     raster kernel (for the roofline) and the step time is not inflated by
-    the breakdown."""
+    the breakdown.  ``views_of(i)`` gives the views of the i-th step (one
+    view, 0, when None); every pass draws from the same sequence."""
     import torch
+    calls = [0]
+
+    def step():
+        v = [0] if views_of is None else views_of(calls[0])
+        calls[0] += 1
+        tr.step(v)
     for _ in range(warmup):
-        tr.step([0])
+        step()
     n_stage = max(20, steps // 2)
     tr.events = {}
     tr.timed_stages = None
     for _ in range(n_stage):
-        tr.step([0])
+        step()
     samples = tr.stage_samples_ms()
     stage = {k: sum(v) / n_stage for k, v in samples.items()}
     stage_spread = {k: {f"p{q}": round(float(np.percentile(v, q)), 4) for q in (10, 50, 90)}
@@ -134,10 +159,11 @@ def run(tr, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        tr.step([0])
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    dom_ms = tr.stage_ms()[dom] / steps
+    launches = len(tr.events.get(dom, []))
+    dom_ms = tr.stage_ms()[dom] / max(launches, 1)
     cnt = tr.counters.sum(dim=1).cpu().tolist()
     tr.events = None
     tr.timed_stages = None
@@ -147,16 +173,89 @@ def run(tr, steps, warmup):
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_dist + 1)]
     evs[0].record()
     for k in range(n_dist):
-        tr.step([0])
+        step()
         evs[k + 1].record()
     torch.cuda.synchronize()
     per = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(n_dist))
     pct = {f"p{q}": round(per[min(n_dist - 1, int(q / 100 * n_dist))], 4) for q in (10, 50, 90)}
-    vb = tr._bufs[0]
-    pixels = (vb.width * vb.height) if vb.dense else int(vb.tile_off[-1].item())
+    pixels = 0
+    n_pairs = 0
+    for vb in tr._bufs.values():
+        pixels += (vb.width * vb.height) if vb.dense else int(vb.tile_off[-1].item())
+        n_pairs += int(vb.n_pairs)
     return dict(seconds=t1 - t0, ms_per_step=(t1 - t0) * 1000.0 / steps, evals=cnt[0], blends=cnt[1],
-                stage_ms=stage, dominant=dom, dominant_ms=dom_ms, n_pairs=int(vb.n_pairs), pixels=pixels,
-                step_ms_spread=pct, stage_ms_spread=stage_spread)
+                stage_ms=stage, dominant=dom, dominant_ms=dom_ms, launches_per_step=launches / steps,
+                n_pairs=n_pairs, pixels=pixels, step_ms_spread=pct, stage_ms_spread=stage_spread)
+
+
+# ------------------------------------------------------------------ full training step
+def full_workload(dev):
+    """The full-step scene on the device: parameters, cameras, dense
+    targets of the perturbed scene plus seeded N(0, 0.01) noise."""
+    import torch
+
+    import synth
+    from paper_2606_15924_amd import binding as B
+    from paper_2606_15924_amd.pipeline import ViewBuffers
+    p = synth.gaussians(FULL_N, synth.SEED_SCENE)
+    cams = synth.hemisphere_cameras(FULL_VIEWS, width=FULL_W, height=FULL_H)
+    P_true = torch.from_numpy(synth.perturb(p, synth.SEED_PERTURB)).to(dev)
+    rp = B.raster_params()
+    vb = ViewBuffers(FULL_N, FULL_W, FULL_H, None, -1, dev)
+    gen = torch.Generator(device=dev)
+    gts = []
+    for k, cam in enumerate(cams):
+        vb.project(P_true, B.camera(cam), rp)
+        vb.bin_sort(alpha_min=rp.alpha_min)
+        vb.render_fwd(rp)
+        gen.manual_seed(synth.SEED_NOISE * 1000 + k)
+        img = vb.out[: FULL_W * FULL_H, :3].T.reshape(3, FULL_H, FULL_W)
+        gts.append((img + 0.01 * torch.randn(img.shape, generator=gen, device=dev)).contiguous())
+    del P_true, vb
+    torch.cuda.synchronize()
+    return p, cams, gts
+
+
+def full_trainer(p, cams, gts, rate, dev):
+    import torch
+
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    cfg = StepConfig(rate_permille=rate)
+    E = [torch.zeros((FULL_H, FULL_W), dtype=torch.int16, device=dev) for _ in cams]
+    A = [torch.zeros((FULL_H, FULL_W), dtype=torch.int16, device=dev) for _ in cams]
+    tr = Trainer(torch.from_numpy(p).to(dev), cams, gts, cfg, E=E, A=A)
+    if rate is not None:
+        tr.init_error_maps(range(len(cams)))
+    return tr
+
+
+def view_order(K, n_views=FULL_VIEWS):
+    """Seeded choice of K distinct views for each step (the same sequence
+    for every run, sparse or dense)."""
+    import synth
+    rng = np.random.default_rng(synth.SEED_VIEWS)
+    seq = [rng.choice(n_views, K, replace=False).tolist() for _ in range(1024)]
+    return lambda i: seq[i % len(seq)]
+
+
+def full_step(dev, steps, warmup, with_dense=True):
+    """Sparse (20 %) and dense steps at K = 3 and K = 10."""
+    import torch
+    log("full step: building the 1.5M-Gaussian scene and 150 targets")
+    p, cams, gts = full_workload(dev)
+    res = {}
+    for K in FULL_K:
+        for name, rate in (("sparse", FULL_RATE), ("dense", None)):
+            if name == "dense" and not with_dense:
+                continue
+            log(f"full step K={K} {name}: {warmup} warmup + {steps} timed steps")
+            tr = full_trainer(p, cams, gts, rate, dev)
+            r = run(tr, steps, warmup, view_order(K))
+            log(f"  {r['ms_per_step']:.3f} ms/step, stages {r['stage_ms']}")
+            res[(K, name)] = r
+            del tr
+            torch.cuda.empty_cache()
+    return p, cams, res
 
 
 def matched_psnr(dev, dense_steps=PSNR_DENSE_STEPS, max_steps=PSNR_MAX_STEPS):
@@ -367,66 +466,156 @@ def tile_init_params():
     return p
 
 
-def cpu_baseline(p, cam, gt, target_s=15.0):
-    """The oracle's sparse step, timed on one host thread: the parts whose
-    cost scales with the sampled tiles (sampling, forward, loss, backward)
-    on a random subset of tiles at the headline rate, the parts over every
-    Gaussian (projection, binning of the whole view, projection backward,
-    optimizer) whole.
-    The subset is sized from a 32-tile probe so the tile part takes about
-    ``target_s`` seconds.  The whole-view step time is extrapolated as
-    fixed + per-tile x n_t / n_tiles, and so are its blends; returns
-    blends/s of that step."""
+# ------------------------------------------------------------------ oracle on the host
+_CPU = {}   # the oracle baseline's shared inputs (inherited by forked workers)
+
+
+def _gauss_chunks(n, parts):
+    edges = np.linspace(0, n, parts + 1).astype(np.int64)
+    return [(int(edges[k]), int(edges[k + 1])) for k in range(parts)]
+
+
+def _slice_proj(pr, lo, hi, n):
+    return {k: (v[..., lo:hi] if isinstance(v, np.ndarray) and v.shape[-1] == n else v) for k, v in pr.items()}
+
+
+def _w_project(lohi):
     from threadpoolctl import threadpool_limits
 
-    from oracle import binning, loss, project, project_bwd, render, sampler, optim
-    from oracle.params import OptimParams, RasterParams, SampleParams
+    from oracle import project
+    lo, hi = lohi
+    with threadpool_limits(1):
+        return project.project(_CPU["p"][:, lo:hi], _CPU["cam"], _CPU["rp"])
+
+
+def _w_tiles(tiles):
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        xs, out, g2d = _cpu_tile_part(_CPU["pr"], _CPU["sv"], _CPU["ranges"], np.asarray(tiles))
+    nz = np.nonzero(np.any(g2d != 0, axis=0))[0]
+    return int(out["n_blend"].sum()), int(xs.size), nz, g2d[:, nz]
+
+
+def _w_backward(lohi):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import optim, project_bwd
+    from oracle.params import OptimParams
+    lo, hi = lohi
+    n = _CPU["p"].shape[1]
+    with threadpool_limits(1):
+        p = _CPU["p"][:, lo:hi]
+        grad = project_bwd.project_bwd(p, _CPU["cam"], _slice_proj(_CPU["pr"], lo, hi, n),
+                                       _CPU["g2d"][:, lo:hi], _CPU["rp"])
+        z = np.zeros_like(grad)
+        optim.optimizer_step(p, grad, z, z, _CPU["touched"][lo:hi], OptimParams(), 1)
+    return hi - lo
+
+
+def _cpu_tile_part(pr, sv, ranges, tiles):
+    from oracle import loss, render, sampler
+    from oracle.params import SampleParams
+    n_pix = (FULL_RATE * 256) // 1000
+    s = sampler.sample_view(_CPU["E"], _CPU["A"], SampleParams(n_pix=n_pix), 3, 1, 0, tiles_subset=tiles)
+    xs, ys, _ = sampler.sample_coords(s, FULL_W, FULL_H)
+    out = render.render_pixels(pr, sv, ranges, xs, ys, _CPU["rp"])
+    ls = loss.sparse_loss(out["rgb"], _CPU["gt"][:, ys, xs].T, s["tile_off"], xs.size, s["valid_tiles"].size)
+    g2d = render.render_pixels_bwd(pr, sv, ranges, xs, ys, ls["dL"], _CPU["rp"])
+    return xs, out, g2d
+
+
+def cpu_baseline(p, cam, target_s=15.0, cores=1):
+    """The oracle's sparse step for one view of the full training step, timed
+    on the host: projection, binning of the whole view (the rectangle lists
+    of every tile), sampling + forward + loss + backward on a random subset
+    of tiles sized from a 16-tile probe so that part takes about
+    ``target_s`` seconds of one thread's work, then projection backward and
+    the update over every Gaussian.  The view's step time is extrapolated
+    as whole-model parts + per-tile time x tiles, and so are its blends;
+    the K-view step as K views plus nothing else shared.  With ``cores`` > 1
+    the independent work (Gaussian ranges of the projection, backward and
+    update; tiles of the tile part) is split over that many forked worker
+    processes of one thread each; binning runs in one process."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
     import synth
+    from oracle import binning
+    from oracle.params import RasterParams
     rp = RasterParams()
-    E = synth.error_map(HEIGHT, WIDTH, 31)
-    A = np.zeros((HEIGHT, WIDTH), dtype=np.uint16)
-    TX, TY = (WIDTH + 15) // 16, (HEIGHT + 15) // 16
+    n = p.shape[1]
+    TX, TY = (FULL_W + 15) // 16, (FULL_H + 15) // 16
     n_t = TX * TY
     order = np.random.default_rng(0).permutation(n_t)
+    _CPU.update(p=p, cam=cam, rp=rp, E=synth.error_map(FULL_H, FULL_W, 31),
+                A=np.zeros((FULL_H, FULL_W), dtype=np.uint16), gt=synth.image(FULL_H, FULL_W, 32))
+    ctx = mp.get_context("fork")
 
-    def tile_part(pr, sv, ranges, tiles):
-        s = sampler.sample_view(E, A, SampleParams(n_pix=64), 3, 1, 0, tiles_subset=tiles)
-        xs, ys, _ = sampler.sample_coords(s, WIDTH, HEIGHT)
-        out = render.render_pixels(pr, sv, ranges, xs, ys, rp)
-        ls = loss.sparse_loss(out["rgb"], gt[:, ys, xs].T, s["tile_off"], xs.size, s["valid_tiles"].size)
-        g2d = render.render_pixels_bwd(pr, sv, ranges, xs, ys, ls["dL"], rp)
-        return xs, out, g2d
+    def pmap(fn, items):
+        # a fresh pool per phase: workers fork after that phase's inputs are in place
+        with ctx.Pool(cores) as pool:
+            return pool.map(fn, items)
+    try:
+        with threadpool_limits(1):
+            c0 = time.perf_counter()
+            if cores == 1:
+                pr = _w_project((0, n))
+            else:
+                parts = pmap(_w_project, _gauss_chunks(n, cores))
+                pr = {k: (np.concatenate([q[k] for q in parts], axis=-1)
+                          if isinstance(parts[0][k], np.ndarray) and parts[0][k].shape[-1] == parts[0]["opacity"].size
+                          else parts[0][k]) for k in parts[0]}
+            c1 = time.perf_counter()
+            _, sv, ranges = binning.bin_and_sort(pr, np.arange(n_t))
+            c2 = time.perf_counter()
+            _CPU.update(pr=pr, sv=sv, ranges=ranges)
+            _cpu_tile_part(pr, sv, ranges, np.sort(order[:16]))
+            probe = (time.perf_counter() - c2) / 16
+            n_tiles = int(min(n_t, max(16, target_s / probe)))
+            tiles = np.sort(order[:n_tiles])
+            c3 = time.perf_counter()
+            g2d = np.zeros((9, n))
+            if cores == 1:
+                res = [_w_tiles(tiles)]
+            else:
+                res = pmap(_w_tiles, np.array_split(tiles, cores * 4))
+            blends = sum(r[0] for r in res)
+            pixels = sum(r[1] for r in res)
+            for r in res:
+                g2d[:, r[2]] += r[3]
+            c4 = time.perf_counter()
+            touched = np.zeros(n, dtype=bool)
+            touched[np.unique(sv)] = True
+            _CPU.update(g2d=g2d, touched=touched)
+            if cores == 1:
+                _w_backward((0, n))
+            else:
+                pmap(_w_backward, _gauss_chunks(n, cores))
+            c5 = time.perf_counter()
+    finally:
+        _CPU.clear()
+    whole = (c1 - c0) + (c2 - c1) + (c5 - c4)
+    per_tile = (c4 - c3) / n_tiles
+    view_s = whole + per_tile * n_t
+    blends_view = blends * n_t / n_tiles
+    step_s = HEADLINE_K * view_s
+    return dict(value=blends_view * HEADLINE_K / step_s, unit="blends/s", cores=cores, kind="oracle",
+                step_s_extrapolated=round(step_s, 2), view_s_extrapolated=round(view_s, 2),
+                sample=f"one 1600x1060 view of the 1.5M-Gaussian full step: {n_tiles} of {n_t} random tiles at "
+                       f"20% ({pixels} pixels, {blends} blends), plus projection ({c1 - c0:.1f} s), "
+                       f"whole-view binning ({c2 - c1:.1f} s, one process), projection backward and update "
+                       f"({c5 - c4:.1f} s) over all {n} Gaussians; {c5 - c0:.1f} s measured, "
+                       f"{per_tile * 1e3:.1f} ms per tile; the K={HEADLINE_K} step extrapolated to "
+                       f"{step_s:.1f} s")
 
-    with threadpool_limits(1):
-        c0 = time.perf_counter()
-        pr = project.project(p, cam, rp)
-        # every tile of the view is sampled at this rate: the lists cover the view
-        _, sv, ranges = binning.bin_and_sort(pr, np.arange(n_t))
-        c1 = time.perf_counter()
-        tile_part(pr, sv, ranges, np.sort(order[:32]))
-        probe = (time.perf_counter() - c1) / 32
-        n_tiles = int(min(n_t, max(32, target_s / probe)))
-        tiles = np.sort(order[:n_tiles])
-        c1b = time.perf_counter()
-        xs, out, g2d = tile_part(pr, sv, ranges, tiles)
-        c2 = time.perf_counter()
-        grad = project_bwd.project_bwd(p, cam, pr, g2d, rp)
-        touched = np.zeros(p.shape[1], dtype=bool)
-        touched[np.unique(sv)] = True
-        optim.optimizer_step(p, grad, np.zeros_like(grad), np.zeros_like(grad), touched, OptimParams(), 1)
-        c3 = time.perf_counter()
-    fixed = (c1 - c0) + (c3 - c2)
-    per_tile = (c2 - c1b) / n_tiles
-    step_s = fixed + per_tile * n_t
-    blends = int(out["n_blend"].sum())
-    blends_step = blends * n_t / n_tiles
-    return dict(value=blends_step / step_s, unit="blends/s", cores=1, kind="oracle",
-                step_s_extrapolated=round(step_s, 2),
-                sample=f"{n_tiles} of {n_t} random tiles at 25% ({xs.size} pixels, {blends} blends) plus "
-                       f"projection, whole-view binning, projection backward and optimizer over all "
-                       f"{p.shape[1]} Gaussians; "
-                       f"{fixed + (c2 - c1b):.1f} s measured ({fixed:.1f} s whole-model, "
-                       f"{per_tile * 1e3:.1f} ms per tile), whole-view step extrapolated to {step_s:.1f} s")
+
+def host_cores() -> int:
+    """Cores this process may use, at most 16 (one GPU's share of the host)."""
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(16, os.cpu_count() or 1))
 
 
 def density_control(p, cam, gt, dev, blends_per_step):
@@ -467,16 +656,51 @@ def density_control(p, cam, gt, dev, blends_per_step):
             "selection": "densify top 10% (eta_topk 0.9), keep top 85% (eta_final 0.85) of 300k scores"}
 
 
+def summarize(r, steps):
+    """The per-run figures reported for a step configuration."""
+    out = dict(ms_per_step=round(r["ms_per_step"], 4), step_ms_spread=r["step_ms_spread"],
+               blends_per_s=r["blends"] / r["seconds"], blends_per_step=r["blends"] / steps,
+               evaluations_per_step=r["evals"] / steps, sampled_pixels_per_step=r["pixels"],
+               pairs_per_step=r["n_pairs"], stage_ms_per_step={k: round(v, 4) for k, v in r["stage_ms"].items()})
+    fwd = r["stage_ms"].get("render_fwd")
+    bwd = r["stage_ms"].get("render_bwd")
+    if fwd:
+        out["blends_per_s_fwd"] = (r["blends"] / steps) / (1e-3 * fwd)
+        if bwd:
+            out["blends_per_s_fwd_bwd"] = (r["blends"] / steps) / (1e-3 * (fwd + bwd))
+    return out
+
+
+def roofline_of(r, steps):
+    """Roofline of the dominant raster kernel of a run, from the kernel's
+    average launch time measured with HIP events on its stream over the
+    timed steps and the algorithmic FLOP of one launch."""
+    dom = r["dominant"]
+    launches = max(r["launches_per_step"] * steps, 1)
+    ev, bl = r["evals"] / launches, r["blends"] / launches
+    if dom == "render_fwd":
+        flops = FWD_FLOP_EVAL * ev + FWD_FLOP_BLEND * bl
+    else:
+        flops = BWD_FLOP_EVAL * ev + BWD_FLOP_BLEND * bl
+    achieved = flops / (r["dominant_ms"] * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
+            "traffic": measured_traffic(dom), "launch_ms": round(r["dominant_ms"], 4),
+            "flop_per_launch": round(flops), "evaluations_per_launch": round(ev), "blends_per_launch": round(bl)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-sweep", action="store_true", help="skip the pixel-rate sweep and dense run")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense full steps")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 300k pixel-rate sweep and dense run")
     ap.add_argument("--no-psnr", action="store_true", help="skip the matched-PSNR training comparison")
     ap.add_argument("--no-tile", action="store_true", help="skip the learned tile-priority measurement")
     ap.add_argument("--no-density", action="store_true", help="skip the density-control measurement")
+    ap.add_argument("--only-headline", action="store_true", help="the K=3 sparse full step alone (profiling)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -499,65 +723,63 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    log("building workload")
-    p, cam, gt = make_workload(dev)
 
-    log(f"sparse {HEADLINE_RATE / 10:.0f}% run: {args.warmup} warmup + {args.steps} timed steps")
-    tr = make_trainer(p, cam, gt, HEADLINE_RATE, dev)
-    head = run(tr, args.steps, args.warmup)
-    log(f"  {head['ms_per_step']:.3f} ms/step, stages {head['stage_ms']}")
-    del tr
+    if args.only_headline:
+        global FULL_K
+        FULL_K = (HEADLINE_K,)
+    p_full, cams, full = full_step(dev, args.steps, args.warmup,
+                                   with_dense=not (args.no_dense or args.only_headline))
+    head = full[(HEADLINE_K, "sparse")]
+    roofline = roofline_of(head, args.steps)
+    full_out = {}
+    for (K, name), r in full.items():
+        full_out.setdefault(f"K{K}", {})[name] = summarize(r, args.steps)
+    for K in FULL_K:
+        d = full_out[f"K{K}"]
+        if "dense" in d:
+            d["sparse_vs_dense_speedup"] = round(d["dense"]["ms_per_step"] / d["sparse"]["ms_per_step"], 3)
 
-    sweep = {}
-    dense = None
-    if not args.no_sweep:
-        for r in SWEEP_RATES:
-            if r == HEADLINE_RATE:
-                sweep[f"{r / 10:g}%"] = dict(ms_per_step=head["ms_per_step"],
-                                             blends_per_s=head["blends"] / head["seconds"])
-                continue
-            log(f"sweep {r / 10:g}%")
-            tr = make_trainer(p, cam, gt, r, dev)
-            res = run(tr, max(5, args.steps // 2), 2)
-            sweep[f"{r / 10:g}%"] = dict(ms_per_step=res["ms_per_step"], blends_per_s=res["blends"] / res["seconds"])
+    scaling = None
+    dens = tile = psnr = None
+    if not args.only_headline:
+        p, cam, gt = make_workload(dev)
+        if not args.no_sweep:
+            scaling = {}
+            for r in SWEEP_RATES:
+                log(f"300k sweep {r / 10:g}%")
+                tr = make_trainer(p, cam, gt, r, dev)
+                res = run(tr, max(10, args.steps), 2)
+                scaling[f"{r / 10:g}%"] = summarize(res, max(10, args.steps))
+                del tr
+            log("300k dense")
+            tr = make_trainer(p, cam, gt, None, dev)
+            dres = run(tr, max(10, args.steps), 2)
+            scaling["dense"] = summarize(dres, max(10, args.steps))
+            for k in list(scaling):
+                if k != "dense":
+                    scaling[k]["sparse_vs_dense_speedup"] = round(
+                        scaling["dense"]["ms_per_step"] / scaling[k]["ms_per_step"], 3)
             del tr
-        log("dense run")
-        tr = make_trainer(p, cam, gt, None, dev)
-        dres = run(tr, max(5, args.steps // 2), 2)
-        dense = dict(ms_per_step=dres["ms_per_step"], blends_per_s=dres["blends"] / dres["seconds"],
-                     stage_ms=dres["stage_ms"])
-        del tr
-
-    # roofline of the dominant kernel of the headline step, timed inside the timed steps
-    dom = head["dominant"]
-    per_launch_evals = head["evals"] / args.steps
-    per_launch_blends = head["blends"] / args.steps
-    if dom == "render_fwd":
-        flops = FWD_FLOP_EVAL * per_launch_evals + FWD_FLOP_BLEND * per_launch_blends
-    else:
-        flops = BWD_FLOP_EVAL * per_launch_evals + BWD_FLOP_BLEND * per_launch_blends
-    achieved = flops / (head["dominant_ms"] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(dom), "launch_ms": round(head["dominant_ms"], 4)}
-
-    dens = None
-    if not args.no_density:
-        log("density-control statistics")
-        dens = density_control(p, cam, gt, dev, per_launch_blends)
-
-    tile = None
-    if not args.no_tile:
-        log("learned tile priority")
-        tile = tile_priority(dev)
-    psnr = None
-    if not args.no_psnr:
-        psnr = matched_psnr(dev)
+        if not args.no_density:
+            log("density-control statistics")
+            tr = make_trainer(p, cam, gt, HEADLINE_RATE, dev)
+            res = run(tr, 10, 2)
+            del tr
+            dens = density_control(p, cam, gt, dev, res["blends"] / 10)
+        if not args.no_tile:
+            log("learned tile priority")
+            tile = tile_priority(dev)
+        if not args.no_psnr:
+            psnr = matched_psnr(dev)
 
     cpu = None
     if not args.no_cpu:
-        log("oracle CPU baseline")
-        cpu = cpu_baseline(p, cam, gt)
+        cores = host_cores()
+        log("oracle CPU baseline, one thread")
+        cpu = cpu_baseline(p_full, cams[0], target_s=5.0, cores=1)
+        if cores > 1:
+            log(f"oracle CPU baseline, {cores} processes")
+            cpu["all_cores"] = cpu_baseline(p_full, cams[0], target_s=5.0, cores=cores)
 
     value = head["blends"] / head["seconds"]
     line = {
@@ -573,23 +795,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "rasterizer scaling: 300k Gaussians, one 1296x840 view, "
-                               "25% error-guided pixels per tile, full training step",
-                   "gaussians": N_GAUSS, "width": WIDTH, "height": HEIGHT, "rate": 0.25,
-                   "pairs": head["n_pairs"], "parallelism": "single GPU"},
-        "stage_ms": {k: round(v, 4) for k, v in head["stage_ms"].items()},
+        "config": {"workload": f"full training step: 1.5M Gaussians, 150 hemisphere cameras 1600x1060, "
+                               f"K={HEADLINE_K} views per step, 20% error-guided pixels per tile, "
+                               f"sparse NCC + Charbonnier, hybrid LM/Adam update",
+                   "gaussians": FULL_N, "views": FULL_VIEWS, "width": FULL_W, "height": FULL_H,
+                   "views_per_step": HEADLINE_K, "rate": FULL_RATE / 1000, "parallelism": "single GPU"},
         "step_ms_spread": head["step_ms_spread"],
-        "stage_ms_spread": head["stage_ms_spread"],
-        # blends per second of the raster kernels alone (forward; forward + backward)
-        "blends_per_s_fwd": per_launch_blends / (1e-3 * head["stage_ms"]["render_fwd"]),
-        "blends_per_s_fwd_bwd": per_launch_blends / (1e-3 * (head["stage_ms"]["render_fwd"] +
-                                                            head["stage_ms"]["render_bwd"])),
-        "per_step": {"evaluations": per_launch_evals, "blends": per_launch_blends,
-                     "sampled_pixels": head["pixels"]},
-        "dense": dense,
-        "sparse_vs_dense_speedup": (dense["ms_per_step"] / head["ms_per_step"]) if dense else None,
-        "sweep": sweep or None,
+        "full_step": full_out,
         "roofline": roofline,
+        "scaling_300k": scaling,
         "matched_psnr": psnr,
         "tile_priority": tile,
         "density_control": dens,

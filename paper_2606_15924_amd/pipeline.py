@@ -315,9 +315,12 @@ class Trainer:
 
     def init_error_maps(self, views):
         """Dense L1 error of the current model per view (Sec. 3.3 initialisation)."""
+        bufs = {}   # one dense buffer set per image size
         for v in views:
             cam = self.cams[v]
-            vb = ViewBuffers(self.n, cam.width, cam.height, None, -1, self.dev)
+            vb = bufs.get((cam.width, cam.height))
+            if vb is None:
+                vb = bufs[(cam.width, cam.height)] = ViewBuffers(self.n, cam.width, cam.height, None, -1, self.dev)
             vb.project(self.params, cam, self.rp)
             vb.bin_sort(alpha_min=self.rp.alpha_min)
             vb.render_fwd(self.rp)
