@@ -111,6 +111,13 @@ typedef struct tgs_optim_params {
 uint32_t tgs_version(void);
 const char* tgs_last_error(void);
 
+/* Debug check of any float array the path reads or writes (parameters,
+ * gradients, rendered colours): *count (one device int64) is set to the
+ * number of entries of x[n] that are NaN or infinite.  Asynchronous, like
+ * every other call; x must be 16-byte aligned, count 8-byte aligned.
+ * The hot path itself never checks for non-finite values. */
+int32_t tgs_check_finite(const float* x, int64_t n, int64_t* count, void* stream);
+
 /* N_pix = max(1, floor(r * 256)) with r = rate_permille / 1000 (Sec. 3.5). */
 int32_t tgs_pixels_per_tile(int32_t rate_permille);
 
@@ -250,6 +257,32 @@ int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, const uint32_t*
                        int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
                        const float* out, const uint32_t* ncontrib, const float* dL_dout,
                        float* g2d, const float* state, uint8_t* touched, void* stream);
+
+/* tgs_render_bwd with bitwise-reproducible gradients: the same adjoint and
+ * the same per-Gaussian wave sums, but each wave stores its nine sums of
+ * a pair into a per-(pair, wave) record of the workspace instead of adding
+ * them to g2d with float atomics (whose order varies run to run); a second
+ * pass adds, per Gaussian, the records of its pairs in a fixed order (the
+ * tiles of its rectangle row by row, then the waves) and adds the total to
+ * g2d.  Same inputs give the same bits on every run.  touched as in
+ * tgs_render_bwd.
+ *   depth, rect  the tgs_project outputs the lists were built from
+ *   n            Gaussians; n_pairs the pair count tgs_bin_sort returned
+ *   ws           tgs_render_bwd_det_workspace_size(n_pairs, max_per_tile,
+ *                dense) bytes, 16-byte aligned (cleared by the call):
+ *                36 bytes per pair and wave of a tile's workgroup (one wave
+ *                up to 64 samples per tile, two up to 128, four above and
+ *                in dense mode)
+ * The density-control variant keeps its atomics (tgs_render_bwd_density). */
+size_t tgs_render_bwd_det_workspace_size(int64_t n_pairs, int32_t max_per_tile, int32_t dense);
+int32_t tgs_render_bwd_deterministic(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                                     int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                                     const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                                     int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
+                                     const float* out, const uint32_t* ncontrib, const float* dL_dout,
+                                     float* g2d, const float* state, uint8_t* touched, const float* depth,
+                                     const int32_t* rect, int64_t n, int64_t n_pairs, void* ws,
+                                     size_t ws_bytes, void* stream);
 
 /* Sparse supervision of one view (Sec. 3.7: Charbonnier L1 per pixel plus
  * tile NCC with the gradient-balanced weight of Eq. ncc_weight_auto, summed
@@ -433,6 +466,38 @@ int32_t tgs_project_bwd(const float* params, int64_t n, const tgs_camera* cam,
                         const uint8_t* clamp, const float* g2d, float* grad, int32_t accumulate,
                         void* stream);
 
+/* ---- FP64 instantiation, for gradient checks (torch.autograd.gradcheck of
+ * the rasterizer as a function of the Gaussian parameters).  The same
+ * definitions as the FP32 path (projection of Sec. 3.1 with SH colour,
+ * Eq. alpha_comp with its thresholds, its exact adjoint, the chain rule),
+ * evaluated in doubles; not tuned for speed.
+ * tgs_project_f64: params[59][n] double; rec64[n][12] double written
+ *   (centre x, y; conic a, b, c; opacity; r, g, b; depth; 0; 0); splat,
+ *   depth, radius, rect, clamp written as by tgs_project (rounded to FP32),
+ *   so tgs_bin_sort builds the lists from them.
+ * tgs_render_fwd_f64 / tgs_render_bwd_f64: as tgs_render_fwd and
+ *   tgs_render_bwd (same sample layout, NULL valid_tiles = dense) over
+ *   rec64; out [P][4] double (colour, T), ncontrib [P]; the backward reads
+ *   dL [P][4] double and adds to g2d[n][9] double (the caller clears it).
+ * tgs_project_bwd_f64: as tgs_project_bwd over doubles. */
+int32_t tgs_project_f64(const double* params, int64_t n, const tgs_camera* cam,
+                        const tgs_raster_params* rp, double* rec64, float* splat, float* depth,
+                        int32_t* radius, int32_t* rect, uint8_t* clamp, void* stream);
+int32_t tgs_render_fwd_f64(const double* rec64, const uint32_t* vals, const uint32_t* ranges,
+                           int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                           const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                           int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
+                           double* out, uint32_t* ncontrib, void* stream);
+int32_t tgs_render_bwd_f64(const double* rec64, const uint32_t* vals, const uint32_t* ranges,
+                           int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                           const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                           int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
+                           const double* out, const uint32_t* ncontrib, const double* dL,
+                           double* g2d, void* stream);
+int32_t tgs_project_bwd_f64(const double* params, int64_t n, const tgs_camera* cam,
+                            const tgs_raster_params* rp, const int32_t* radius, const uint8_t* clamp,
+                            const double* g2d, double* grad, int32_t accumulate, void* stream);
+
 /* tgs_project_bwd followed by tgs_optimizer_step in one pass, for the last
  * view of a training step (Sec. 3.9 update applied to the gradient of
  * Sec. 3.6's backward): each parameter row's gradient stays in registers
@@ -453,8 +518,12 @@ int32_t tgs_project_bwd_optimizer_step(float* params, int64_t n, const tgs_camer
 /* Hybrid moment-damped LM / Adam update (Sec. 3.9, Eq. moment_damped_lm, and
  * the appendix optimizer details): per touched Gaussian, Adam moments for all
  * rows; geometry (rows 0-9) and base appearance (SH DC, opacity) solve
- * (J^T J + diag(sqrt(v) + eps)) Delta = -m by Cholesky and move by lr * Delta;
- * the other SH rows take a bias-corrected Adam step.  touched nullable (all).
+ * (J^T J + diag(sqrt(v) + eps)) Delta = -m and move by lr * Delta; with
+ * J^T J = g g^T (lm_mode 0) the system is diagonal plus rank one and is
+ * solved in closed form by the Sherman-Morrison identity, with
+ * J^T J = diag(g^2) (lm_mode 1) elementwise (lm_mode 2: Adam for every
+ * row); the other SH rows take a bias-corrected Adam step.  touched
+ * nullable (all).
  * step >= 1.  Internally FP64. */
 int32_t tgs_optimizer_step(float* params, const float* grad, float* m, float* v, int64_t n,
                            const uint8_t* touched, const tgs_optim_params* op, int64_t step,

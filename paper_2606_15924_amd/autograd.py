@@ -8,6 +8,12 @@ per-sample outputs (final colour, transmittance, contributor count): the
 backward recomputes every per-pixel quantity from them instead of storing
 per-(pixel, Gaussian) state (Sec. 3.6: splat-parallel backward without a
 dense replay).
+
+Float64 parameters select the FP64 instantiation of the same kernels
+(``tgs_project_f64``, ``tgs_render_fwd_f64``, ``tgs_render_bwd_f64``,
+``tgs_project_bwd_f64``; the lists come from the same ``tgs_bin_sort``), so
+``torch.autograd.gradcheck`` can check the adjoint against finite
+differences at double precision.
 """
 from __future__ import annotations
 
@@ -44,17 +50,37 @@ class SparseRasterize(torch.autograd.Function):
         else:
             vb.P = cam.width * cam.height
         c = B.camera(cam)
+        ctx.vb, ctx.cam, ctx.rp = vb, c, rp
+        ctx.save_for_backward(params)
+        if params.dtype == torch.float64:
+            vb.rec64 = torch.empty((n, 12), dtype=torch.float64, device=params.device)
+            B.tgs_project_f64(params, n, c, rp, vb.rec64, vb.splat, vb.depth, vb.radius, vb.rect, vb.clamp)
+            vb.bin_sort(alpha_min=rp.alpha_min)
+            vb.out64 = torch.empty((max(vb.P, 1), 4), dtype=torch.float64, device=params.device)
+            B.tgs_render_fwd_f64(vb.rec64, vb.vals, vb.ranges, vb.tiles_x, vb.tiles_y, vb.width, vb.height,
+                                 vb.valid_tiles, vb.tile_off, vb.pix, vb.n_st, vb.n_pix, rp, vb.out64, vb.ncontrib)
+            return vb.out64[: vb.P, :3].clone()
+        if params.dtype != torch.float32:
+            raise TypeError("SparseRasterize: parameters must be float32 or float64")
         vb.project(params, c, rp)
         vb.bin_sort(alpha_min=rp.alpha_min)
         vb.render_fwd(rp)
-        ctx.vb, ctx.cam, ctx.rp = vb, c, rp
-        ctx.save_for_backward(params)
         return vb.out[: vb.P, :3].clone()
 
     @staticmethod
     def backward(ctx, grad_out):
         (params,) = ctx.saved_tensors
         vb = ctx.vb
+        if params.dtype == torch.float64:
+            dL = torch.zeros((max(vb.P, 1), 4), dtype=torch.float64, device=params.device)
+            dL[: vb.P, :3] = grad_out
+            g2d = torch.zeros((vb.n, 9), dtype=torch.float64, device=params.device)
+            B.tgs_render_bwd_f64(vb.rec64, vb.vals, vb.ranges, vb.tiles_x, vb.tiles_y, vb.width, vb.height,
+                                 vb.valid_tiles, vb.tile_off, vb.pix, vb.n_st, vb.n_pix, ctx.rp, vb.out64,
+                                 vb.ncontrib, dL, g2d)
+            grad = torch.empty_like(params)
+            B.tgs_project_bwd_f64(params, vb.n, ctx.cam, ctx.rp, vb.radius, vb.clamp, g2d, grad, accumulate=False)
+            return grad, None, None, None
         dL = torch.zeros((max(vb.P, 1), 4), dtype=torch.float32, device=params.device)
         dL[: vb.P, :3] = grad_out
         vb.dL = dL

@@ -73,6 +73,19 @@ PROTOTYPES = {
     "tgs_version": (ctypes.c_uint32, []),
     "tgs_last_error": (ctypes.c_char_p, []),
     "tgs_pixels_per_tile": (_I32, [_I32]),
+    "tgs_check_finite": (_I32, [_P, _I64, _P, _P]),
+    "tgs_render_bwd_det_workspace_size": (_SZ, [_I64, _I32, _I32]),
+    "tgs_render_bwd_deterministic": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                                            ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P, _P,
+                                            _I64, _I64, _P, _SZ, _P]),
+    "tgs_project_f64": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
+                               _P, _P, _P, _P, _P, _P, _P]),
+    "tgs_render_fwd_f64": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                                  ctypes.POINTER(tgs_raster_params), _P, _P, _P]),
+    "tgs_render_bwd_f64": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                                  ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P]),
+    "tgs_project_bwd_f64": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
+                                   _P, _P, _P, _P, _I32, _P]),
     "tgs_sample_tile_count": (_I32, [_I32, _I32, ctypes.POINTER(tgs_sample_params)]),
     "tgs_project": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera), ctypes.POINTER(tgs_raster_params),
                            _P, _P, _P, _P, _P, _P, _P]),
@@ -215,6 +228,20 @@ def tgs_version() -> int:
     return int(lib().tgs_version())
 
 
+def tgs_check_finite(x, count):
+    """count (one device int64) <- number of NaN / infinite entries of x (float32)."""
+    if x.dtype != torch.float32 or count.dtype != torch.int64:
+        raise TypeError("tgs_check_finite: x float32, count int64")
+    _check(lib().tgs_check_finite(_ptr(x), x.numel(), _ptr(count), _stream()), "tgs_check_finite")
+
+
+def check_finite(x) -> int:
+    """The number of non-finite entries of a float32 device tensor (synchronises)."""
+    count = torch.empty(1, dtype=torch.int64, device=x.device)
+    tgs_check_finite(x, count)
+    return int(count.item())
+
+
 def tgs_pixels_per_tile(rate_permille: int) -> int:
     return int(lib().tgs_pixels_per_tile(rate_permille))
 
@@ -227,6 +254,33 @@ def tgs_project(params, n, cam: tgs_camera, rp: tgs_raster_params, splat, depth,
                 g2d_clear=None):
     _check(lib().tgs_project(_ptr(params), n, ctypes.byref(cam), ctypes.byref(rp), _ptr(splat), _ptr(depth),
                              _ptr(radius), _ptr(rect), _ptr(clamp), _ptr(g2d_clear), _stream()), "tgs_project")
+
+
+def tgs_project_f64(params, n, cam: tgs_camera, rp: tgs_raster_params, rec64, splat, depth, radius, rect, clamp):
+    _check(lib().tgs_project_f64(_ptr(params), n, ctypes.byref(cam), ctypes.byref(rp), _ptr(rec64), _ptr(splat),
+                                 _ptr(depth), _ptr(radius), _ptr(rect), _ptr(clamp), _stream()), "tgs_project_f64")
+
+
+def tgs_render_fwd_f64(rec64, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
+                       n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib):
+    _check(lib().tgs_render_fwd_f64(_ptr(rec64), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
+                                    _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
+                                    ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _stream()), "tgs_render_fwd_f64")
+
+
+def tgs_render_bwd_f64(rec64, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
+                       n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL, g2d):
+    _check(lib().tgs_render_bwd_f64(_ptr(rec64), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
+                                    _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
+                                    ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(dL), _ptr(g2d), _stream()),
+           "tgs_render_bwd_f64")
+
+
+def tgs_project_bwd_f64(params, n, cam: tgs_camera, rp: tgs_raster_params, radius, clamp, g2d, grad,
+                        accumulate: bool = False):
+    _check(lib().tgs_project_bwd_f64(_ptr(params), n, ctypes.byref(cam), ctypes.byref(rp), _ptr(radius),
+                                     _ptr(clamp), _ptr(g2d), _ptr(grad), int(bool(accumulate)), _stream()),
+           "tgs_project_bwd_f64")
 
 
 def tgs_sample_workspace_size(height: int, width: int) -> int:
@@ -274,6 +328,20 @@ def tgs_render_bwd(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_t
                                 _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
                                 ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(dL_dout), _ptr(g2d),
                                 _ptr(state), _ptr(touched), _stream()), "tgs_render_bwd")
+
+
+def tgs_render_bwd_det_workspace_size(n_pairs: int, max_per_tile: int, dense: bool) -> int:
+    return int(lib().tgs_render_bwd_det_workspace_size(n_pairs, max_per_tile, int(bool(dense))))
+
+
+def tgs_render_bwd_deterministic(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
+                                 n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL, g2d, state, touched,
+                                 depth, rect, n, n_pairs, ws):
+    _check(lib().tgs_render_bwd_deterministic(
+        _ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height, _ptr(valid_tiles), _ptr(tile_off),
+        _ptr(pix), n_st, max_per_tile, ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(dL), _ptr(g2d),
+        _ptr(state), _ptr(touched), _ptr(depth), _ptr(rect), n, n_pairs, _ptr(ws), ws.numel() * ws.element_size(),
+        _stream()), "tgs_render_bwd_deterministic")
 
 
 def tgs_loss(out, gt, height, width, valid_tiles, tile_off, pix, n_st, totals, lp: tgs_loss_params,

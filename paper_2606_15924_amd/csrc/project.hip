@@ -14,11 +14,15 @@
 
 namespace tgs {
 
-template <int kDeg>
+// PT = float: the training path.  PT = double: the FP64 instantiation for
+// gradient checks, which also writes the splat record in doubles (rec64:
+// centre x, y; conic a, b, c; opacity; r, g, b; depth; two zeros).
+template <typename PT, int kDeg>
 __global__ void __launch_bounds__(256) project_fwd_kernel(
-    const float* __restrict__ params, int64_t n, CamArgs cam, double z_near,
+    const PT* __restrict__ params, int64_t n, CamArgs cam, double z_near,
     double dil, float4* __restrict__ splat, float* __restrict__ depth, int* __restrict__ radius,
-    int4* __restrict__ rect, uint8_t* __restrict__ clampm, float* __restrict__ g2d_clear) {
+    int4* __restrict__ rect, uint8_t* __restrict__ clampm, float* __restrict__ g2d_clear,
+    double* __restrict__ rec64) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (g2d_clear != nullptr)
@@ -33,6 +37,8 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
     splat[3 * i + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
     splat[3 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
     splat[3 * i + 2] = make_float4(0.f, 0.f, 0.f, (float)g.t[2]);
+    if (rec64 != nullptr)
+      for (int k = 0; k < 12; ++k) rec64[12 * i + k] = k == 9 ? g.t[2] : 0.0;
     return;
   }
   // view-dependent colour
@@ -43,7 +49,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
   // the degree is a template argument, so all coefficient loads are
   // independent and issued together
   constexpr int nk = (kDeg + 1) * (kDeg + 1);
-  float cf[3 * nk];
+  PT cf[3 * nk];
 #pragma unroll
   for (int q = 0; q < 3 * nk; ++q) cf[q] = params[(int64_t)(11 + q) * n + i];
   __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the SH arithmetic
@@ -69,19 +75,25 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
   radius[i] = (int)g.radius;
   rect[i] = make_int4(g.rect[0], g.rect[1], g.rect[2], g.rect[3]);
   clampm[i] = cm;
+  if (rec64 != nullptr) {
+    const double r64[12] = {g.px, g.py, g.c / g.det, -g.b / g.det, g.a / g.det, opac,
+                            rgb[0], rgb[1], rgb[2], g.t[2], 0.0, 0.0};
+    for (int k = 0; k < 12; ++k) rec64[12 * i + k] = r64[k];
+  }
 }
 
 // accumulate: grad += gradient; otherwise grad = gradient, with zeros for
 // culled Gaussians (every row of every Gaussian is written once).
+template <typename PT>
 __global__ void __launch_bounds__(256) project_bwd_kernel(
-    const float* __restrict__ params, int64_t n, CamArgs cam, int sh_degree, double z_near,
+    const PT* __restrict__ params, int64_t n, CamArgs cam, int sh_degree, double z_near,
     double dil, const int* __restrict__ radius, const uint8_t* __restrict__ clampm,
-    const float* __restrict__ g2d, float* __restrict__ grad, bool accumulate) {
+    const PT* __restrict__ g2d, PT* __restrict__ grad, bool accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (radius[i] == 0) {
     if (!accumulate)
-      for (int r = 0; r < TGS_PARAM_ROWS; ++r) grad[(int64_t)r * n + i] = 0.f;
+      for (int r = 0; r < TGS_PARAM_ROWS; ++r) grad[(int64_t)r * n + i] = (PT)0;
     return;
   }
   Geom g;
@@ -90,7 +102,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
   for (int k = 0; k < 9; ++k) gg[k] = (double)g2d[i * 9 + k];
   chain_rule(params, n, i, cam, sh_degree, g, gg, clampm[i], [&](int row, double v) {
     const int64_t idx = (int64_t)row * n + i;
-    grad[idx] = accumulate ? grad[idx] + (float)v : (float)v;
+    grad[idx] = accumulate ? grad[idx] + (PT)v : (PT)v;
   });
 }
 
@@ -115,8 +127,9 @@ extern "C" int32_t tgs_project(const float* params, int64_t n, const tgs_camera*
   const dim3 grid((unsigned)ceil_div(n, block));
   hipStream_t s = as_stream(stream);
 #define TGS_PROJECT(D)                                                                                           \
-  hipLaunchKernelGGL(project_fwd_kernel<D>, grid, dim3(block), 0, s, params, n, ca, (double)rp->z_near,          \
-                     (double)rp->dilation, (float4*)splat, depth, radius, (int4*)rect, clamp, g2d_clear)
+  hipLaunchKernelGGL((project_fwd_kernel<float, D>), grid, dim3(block), 0, s, params, n, ca, (double)rp->z_near, \
+                     (double)rp->dilation, (float4*)splat, depth, radius, (int4*)rect, clamp, g2d_clear,      \
+                     (double*)nullptr)
   switch (rp->sh_degree) {
     case 0: TGS_PROJECT(0); break;
     case 1: TGS_PROJECT(1); break;
@@ -138,8 +151,54 @@ extern "C" int32_t tgs_project_bwd(const float* params, int64_t n, const tgs_cam
   TGS_REQUIRE(params && radius && clamp && g2d && grad, "tgs_project_bwd: null pointer");
   const CamArgs ca = make_cam(cam);
   const int block = 256;
-  hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)ceil_div(n, block)), dim3(block), 0,
+  hipLaunchKernelGGL(project_bwd_kernel<float>, dim3((unsigned)ceil_div(n, block)), dim3(block), 0,
                      as_stream(stream), params, n, ca, rp->sh_degree, (double)rp->z_near,
                      (double)rp->dilation, radius, clamp, g2d, grad, accumulate != 0);
   return hip_status("tgs_project_bwd");
+}
+
+// ---- FP64 instantiation (gradient checks): the same kernels over double
+// parameters; the float outputs feed tgs_bin_sort as usual.
+extern "C" int32_t tgs_project_f64(const double* params, int64_t n, const tgs_camera* cam,
+                                   const tgs_raster_params* rp, double* rec64, float* splat, float* depth,
+                                   int32_t* radius, int32_t* rect, uint8_t* clamp, void* stream) {
+  TGS_REQUIRE(n >= 0, "tgs_project_f64: n < 0");
+  TGS_REQUIRE(cam != nullptr && cam->width > 0 && cam->height > 0, "tgs_project_f64: bad camera");
+  if (int32_t e = check_raster_params(rp)) return e;
+  if (n == 0) return TGS_OK;
+  TGS_REQUIRE(params && rec64 && splat && depth && radius && rect && clamp, "tgs_project_f64: null pointer");
+  TGS_REQUIRE(((uintptr_t)splat & 15) == 0 && ((uintptr_t)rect & 15) == 0,
+              "tgs_project_f64: splat and rect must be 16-byte aligned");
+  const CamArgs ca = make_cam(cam);
+  const int block = 256;
+  const dim3 grid((unsigned)ceil_div(n, block));
+  hipStream_t s = as_stream(stream);
+#define TGS_PROJECT64(D)                                                                                         \
+  hipLaunchKernelGGL((project_fwd_kernel<double, D>), grid, dim3(block), 0, s, params, n, ca,                    \
+                     (double)rp->z_near, (double)rp->dilation, (float4*)splat, depth, radius, (int4*)rect, clamp, \
+                     (float*)nullptr, rec64)
+  switch (rp->sh_degree) {
+    case 0: TGS_PROJECT64(0); break;
+    case 1: TGS_PROJECT64(1); break;
+    case 2: TGS_PROJECT64(2); break;
+    default: TGS_PROJECT64(3); break;
+  }
+#undef TGS_PROJECT64
+  return hip_status("tgs_project_f64");
+}
+
+extern "C" int32_t tgs_project_bwd_f64(const double* params, int64_t n, const tgs_camera* cam,
+                                       const tgs_raster_params* rp, const int32_t* radius, const uint8_t* clamp,
+                                       const double* g2d, double* grad, int32_t accumulate, void* stream) {
+  TGS_REQUIRE(n >= 0, "tgs_project_bwd_f64: n < 0");
+  TGS_REQUIRE(cam != nullptr && cam->width > 0 && cam->height > 0, "tgs_project_bwd_f64: bad camera");
+  if (int32_t e = check_raster_params(rp)) return e;
+  if (n == 0) return TGS_OK;
+  TGS_REQUIRE(params && radius && clamp && g2d && grad, "tgs_project_bwd_f64: null pointer");
+  const CamArgs ca = make_cam(cam);
+  const int block = 256;
+  hipLaunchKernelGGL(project_bwd_kernel<double>, dim3((unsigned)ceil_div(n, block)), dim3(block), 0,
+                     as_stream(stream), params, n, ca, rp->sh_degree, (double)rp->z_near, (double)rp->dilation,
+                     radius, clamp, g2d, grad, accumulate != 0);
+  return hip_status("tgs_project_bwd_f64");
 }

@@ -120,7 +120,8 @@ struct Geom {
   int rect[4];
 };
 
-__device__ __forceinline__ void geometry(const float* __restrict__ params, int64_t n, int64_t i,
+template <typename PT>
+__device__ __forceinline__ void geometry(const PT* __restrict__ params, int64_t n, int64_t i,
                                          const CamArgs& cam, double z_near, double dil, Geom& g) {
 #pragma clang fp contract(off)
   for (int k = 0; k < 3; ++k) g.mu[k] = (double)params[(int64_t)k * n + i];
@@ -227,8 +228,8 @@ __device__ __forceinline__ void color_grad(const double (&gg)[9], uint8_t cm, do
 // to the sink and dL/du accumulates grad Y_k * (coefficients . drgb) in k
 // order.  Every coefficient is read before the sink sees its row, and
 // params is not restrict-qualified, so a sink may update it in place.
-template <typename Sink>
-__device__ __forceinline__ void sh_backward(const float* params, int64_t n, int64_t i, const ViewDir& u,
+template <typename PT, typename Sink>
+__device__ __forceinline__ void sh_backward(const PT* params, int64_t n, int64_t i, const ViewDir& u,
                                             const double (&drgb)[3], int nk, int k0, int k1,
                                             double (&dL_du)[3], Sink&& sink) {
 #pragma clang fp contract(off)
@@ -257,8 +258,8 @@ __device__ __forceinline__ void sh_backward(const float* params, int64_t n, int6
 
 // Rows 0-10 (mean, log-scale, quaternion, opacity) from the screen-space
 // gradient, the geometry and the complete dL/du of the SH rows.
-template <typename Sink>
-__device__ __forceinline__ void geom_backward(const float* params, int64_t n, int64_t i, const CamArgs& cam,
+template <typename PT, typename Sink>
+__device__ __forceinline__ void geom_backward(const PT* params, int64_t n, int64_t i, const CamArgs& cam,
                                               const Geom& g, const double (&gg)[9], const ViewDir& u,
                                               const double (&dL_du)[3], Sink&& sink) {
 #pragma clang fp contract(off)
@@ -343,8 +344,8 @@ __device__ __forceinline__ void geom_backward(const float* params, int64_t n, in
   for (int k = 0; k < 3; ++k) sink(k, dmu[k]);
 }
 
-template <typename Sink>
-__device__ __forceinline__ void chain_rule(const float* params, int64_t n, int64_t i,
+template <typename PT, typename Sink>
+__device__ __forceinline__ void chain_rule(const PT* params, int64_t n, int64_t i,
                                            const CamArgs& cam, int sh_degree, const Geom& g,
                                            const double (&gg)[9], uint8_t cm, Sink&& sink) {
   const ViewDir u = view_dir(g.mu, cam);

@@ -25,6 +25,8 @@
 // Both walks keep the next batch's loads in flight while the current batch
 // is evaluated: at 64 samples per tile a tile is one wave, so there are few
 // waves per SIMD to hide memory latency otherwise.
+#include <algorithm>
+
 #include "common.h"
 
 namespace tgs {
@@ -286,6 +288,21 @@ __device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float* __r
   }
 }
 
+// The same nine wave sums, stored (not added) to dst[0..8]: the
+// deterministic backward's per-(pair, wave) partial record, which no other
+// wave writes.  Zero sums are stored too (the record is not cleared).
+__device__ __forceinline__ void wave_sum9_store(const float (&v)[9], float* __restrict__ dst, const Sum9Lane& sl) {
+  const float p01 = swap_sum32(v[0], v[1]);
+  const float p23 = swap_sum32(v[2], v[3]);
+  const float p45 = swap_sum32(v[4], v[5]);
+  const float p67 = swap_sum32(v[6], v[7]);
+  const float p8 = swap_sum32(v[8], 0.f);
+  const float r0 = row_sum16(swap_sum16(p01, p23));
+  const float r1 = row_sum16(swap_sum16(p45, p67));
+  const float r2 = row_sum16(swap_sum16(p8, 0.f));
+  if (sl.field >= 0) dst[sl.field] = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : r2);
+}
+
 // The nine gradient sums plus the four density-control sums (e w, w, D w
 // and the per-pixel centre-gradient norm) of the same Gaussian: the same
 // folding with fields 9-11 in the rows of r2 that the nine-value form leaves
@@ -323,7 +340,11 @@ struct DensityArgs {
   int64_t n;
 };
 
-template <int kBlock, bool kDense, bool kDensity = false>
+// kDet: the deterministic variant.  Instead of adding each wave's nine sums
+// to g2d[gid] with atomics, it stores them to g2d[(pos * kWaves + wave) * 9]
+// (g2d is then the partial buffer, pos the pair's index in the sorted list);
+// det_reduce_kernel adds them up per Gaussian in a fixed order.
+template <int kBlock, bool kDense, bool kDensity = false, bool kDet = false>
 __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
                                                             const float4* __restrict__ out,
                                                             const uint32_t* __restrict__ ncontrib,
@@ -443,7 +464,10 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
           v[8] = w * g2;
           const uint32_t gid = __builtin_amdgcn_readfirstlane(s_gid[j + u]);  // uniform
           if (touched != nullptr && lane_id() == 0) touched[gid] = 1u;  // composited at a sample
-          if constexpr (kDensity) {
+          if constexpr (kDet) {
+            const size_t rec = (size_t)(start + (uint32_t)(j + u)) * (kBlock / kWave) + (size_t)(tid / kWave);
+            wave_sum9_store(v, g2d + rec * 9, sl);
+          } else if constexpr (kDensity) {
             constexpr float kTwoLn2 = 1.3862943611198906f;
             const float dist = __builtin_sqrtf(fmaxf(-kTwoLn2 * pw[u], 0.f));
             const float nx = hw * v[0], ny = hh * v[1];
@@ -574,6 +598,62 @@ static void launch_bwd(const RasterArgs& a, int grid, const float* out, const ui
                        DensityArgs{});
 }
 
+template <int kBlock, bool kDense>
+static void launch_bwd_det(const RasterArgs& a, int grid, const float* out, const uint32_t* ncontrib,
+                           const float* dL, float* partial, const float* state, uint8_t* touched, hipStream_t s) {
+  const unsigned chunks = state != nullptr ? TGS_RENDER_CHUNKS : 1;
+  hipLaunchKernelGGL((render_bwd_kernel<kBlock, kDense, false, true>), dim3(grid, chunks), dim3(kBlock), 0, s, a,
+                     (const float4*)out, ncontrib, (const float4*)dL, partial, (const float4*)state, touched,
+                     DensityArgs{});
+}
+
+__global__ void __launch_bounds__(256) zero_f32_kernel(float* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+// Deterministic reduction of the partial records: a thread per Gaussian
+// visits the tiles of its rectangle in row-major order, finds its pair in
+// the tile's list by binary search on (depth bits, id) (the list's order),
+// and adds the pair's wave records in wave order; the total is added to
+// g2d once.  Any order would do; a fixed one gives the same bits on every
+// run.
+__global__ void __launch_bounds__(256) det_reduce_kernel(const int4* __restrict__ rect, const float* __restrict__ depth,
+                                                         const uint32_t* __restrict__ vals,
+                                                         const uint2* __restrict__ ranges, int64_t n, int tiles_x,
+                                                         int tiles_y, int waves, const float* __restrict__ partial,
+                                                         float* __restrict__ g2d) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int4 r = rect[i];
+  r.x = min(max(r.x, 0), tiles_x);
+  r.z = min(max(r.z, r.x), tiles_x);
+  r.y = min(max(r.y, 0), tiles_y);
+  r.w = min(max(r.w, r.y), tiles_y);
+  const uint32_t key = __float_as_uint(depth[i]), id = (uint32_t)i;
+  float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  bool any = false;
+  for (int ty = r.y; ty < r.w; ++ty)
+    for (int tx = r.x; tx < r.z; ++tx) {
+      const uint2 rg = ranges[ty * tiles_x + tx];
+      uint32_t lo = rg.x, hi = rg.y;
+      while (lo < hi) {  // first position not below (key, id)
+        const uint32_t mid = lo + (hi - lo) / 2;
+        const uint32_t gm = vals[mid], km = __float_as_uint(depth[gm]);
+        if (km < key || (km == key && gm < id)) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < rg.y && vals[lo] == id) {
+        const float* p = partial + (size_t)lo * waves * 9;
+        for (int w = 0; w < waves; ++w)
+          for (int f = 0; f < 9; ++f) acc[f] += p[w * 9 + f];
+        any = true;
+      }
+    }
+  if (any)
+    for (int f = 0; f < 9; ++f) g2d[i * 9 + f] += acc[f];
+}
+
 // Workgroup size of the raster kernels for a launch.
 static int raster_block(bool dense, int32_t max_per_tile) {
   if (dense || max_per_tile > 128) return 256;
@@ -673,6 +753,54 @@ extern "C" int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, cons
     else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s);
   }
   return hip_status("tgs_render_bwd");
+}
+
+extern "C" size_t tgs_render_bwd_det_workspace_size(int64_t n_pairs, int32_t max_per_tile, int32_t dense) {
+  if (n_pairs < 0 || max_per_tile < 0 || max_per_tile > kTilePixels) return 0;
+  const int waves = raster_block(dense != 0, max_per_tile) / kWave;
+  return (size_t)std::max<int64_t>(n_pairs, 1) * (size_t)waves * 9 * sizeof(float);
+}
+
+extern "C" int32_t tgs_render_bwd_deterministic(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                                                int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                                                const int32_t* valid_tiles, const int32_t* tile_off,
+                                                const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
+                                                const tgs_raster_params* rp, const float* out,
+                                                const uint32_t* ncontrib, const float* dL_dout, float* g2d,
+                                                const float* state, uint8_t* touched, const float* depth,
+                                                const int32_t* rect, int64_t n, int64_t n_pairs, void* ws,
+                                                size_t ws_bytes, void* stream) {
+  RasterArgs a;
+  if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
+                            tile_off, pix, n_st, max_per_tile, rp, "tgs_render_bwd_deterministic", a))
+    return e;
+  TGS_REQUIRE(out && ncontrib && dL_dout && g2d && depth && rect && ws, "tgs_render_bwd_deterministic: null pointer");
+  TGS_REQUIRE(n >= 0 && n < (1ll << 31) && n_pairs >= 0 && n_pairs < (1ll << 32),
+              "tgs_render_bwd_deterministic: n or n_pairs out of range");
+  TGS_REQUIRE(((uintptr_t)out & 15) == 0 && ((uintptr_t)dL_dout & 15) == 0 && ((uintptr_t)state & 15) == 0 &&
+                  ((uintptr_t)rect & 15) == 0 && ((uintptr_t)ws & 15) == 0,
+              "tgs_render_bwd_deterministic: out, dL_dout, state, rect and ws must be 16-byte aligned");
+  const bool dense = valid_tiles == nullptr;
+  const size_t need = tgs_render_bwd_det_workspace_size(n_pairs, max_per_tile, dense);
+  TGS_REQUIRE(ws_bytes >= need, "tgs_render_bwd_deterministic: workspace %zu bytes < %zu", ws_bytes, need);
+  hipStream_t s = as_stream(stream);
+  float* partial = (float*)ws;
+  const int waves = raster_block(dense, max_per_tile) / kWave;
+  const int64_t words = std::max<int64_t>(n_pairs, 1) * waves * 9;
+  hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(words, 256), 8192)), dim3(256), 0,
+                     s, partial, words);
+  if (dense) {
+    launch_bwd_det<256, true>(a, tiles_x * tiles_y, out, ncontrib, dL_dout, partial, state, touched, s);
+  } else if (n_st > 0) {
+    if (max_per_tile <= 64) launch_bwd_det<64, false>(a, n_st, out, ncontrib, dL_dout, partial, state, touched, s);
+    else if (max_per_tile <= 128)
+      launch_bwd_det<128, false>(a, n_st, out, ncontrib, dL_dout, partial, state, touched, s);
+    else launch_bwd_det<256, false>(a, n_st, out, ncontrib, dL_dout, partial, state, touched, s);
+  }
+  if (n > 0)
+    hipLaunchKernelGGL(det_reduce_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, (const int4*)rect,
+                       depth, vals, (const uint2*)ranges, n, tiles_x, tiles_y, waves, partial, g2d);
+  return hip_status("tgs_render_bwd_deterministic");
 }
 
 extern "C" int32_t tgs_render_bwd_density(const float* splat, const uint32_t* vals, const uint32_t* ranges,

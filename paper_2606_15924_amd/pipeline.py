@@ -48,6 +48,7 @@ class StepConfig:
     tile_lr: float = 3e-3         # its online Adam learning rate
     tile_seed: int = 23           # its initial weights
     density_stats: bool = False   # back-project (e, w, D) onto the Gaussians each sparse view (Sec. 3.8)
+    deterministic: bool = False   # bitwise-reproducible backward (tgs_render_bwd_deterministic)
     raster: dict = field(default_factory=dict)
     loss: dict = field(default_factory=dict)
     optim: dict = field(default_factory=dict)
@@ -151,11 +152,24 @@ class ViewBuffers:
                                  self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
                                  rp, self.ncontrib, self.err, self.n, stats, self.state)
 
-    def render_bwd(self, rp, zero=True, stats=None, touched=None):
+    def render_bwd(self, rp, zero=True, stats=None, touched=None, deterministic=False):
         """The backward; with ``stats`` it also adds the density-control
-        sums; ``touched`` collects the Gaussians composited at a sample."""
+        sums; ``touched`` collects the Gaussians composited at a sample;
+        ``deterministic`` selects the bitwise-reproducible reduction (not
+        with ``stats``)."""
         if zero:
             self.g2d.zero_()
+        if deterministic:
+            if stats is not None:
+                raise ValueError("the deterministic backward has no density-control variant")
+            need = B.tgs_render_bwd_det_workspace_size(self.n_pairs, self.n_pix, self.dense)
+            if getattr(self, "det_ws", None) is None or self.det_ws.numel() < need:
+                self.det_ws = torch.empty(need, dtype=torch.uint8, device=self.splat.device)
+            B.tgs_render_bwd_deterministic(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
+                                           self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st,
+                                           self.n_pix, rp, self.out, self.ncontrib, self.dL, self.g2d, self.state,
+                                           touched, self.depth, self.rect, self.n, self.n_pairs, self.det_ws)
+            return
         if stats is not None:
             B.tgs_render_bwd_density(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                                      self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st,
@@ -231,6 +245,8 @@ class Trainer:
     training steps over a fixed set of cameras."""
 
     def __init__(self, params: torch.Tensor, cams, gts, cfg: StepConfig, E=None, A=None):
+        if cfg.deterministic and cfg.density_stats:
+            raise ValueError("the deterministic backward has no density-control variant")
         self.dev = params.device
         self.params = params.contiguous()
         self.n = params.shape[1]
@@ -386,7 +402,8 @@ class Trainer:
             with st("render_bwd"):
                 # g2d was cleared by the projection; the density sums of sparse
                 # views join the backward's reduction
-                vb.render_bwd(self.rp, zero=False, stats=None if vb.dense else self.dstats, touched=self.touched)
+                vb.render_bwd(self.rp, zero=False, stats=None if vb.dense else self.dstats, touched=self.touched,
+                              deterministic=self.cfg.deterministic)
             if self.gstats is not None:
                 B.tgs_grad_screen_accumulate(vb.g2d, vb.radius, self.n, cam.width, cam.height, self.gstats)
             if k + 1 < len(used) or not self.cfg.fuse_optimizer:

@@ -257,3 +257,21 @@ def test_gaussian_covering_every_tile(B):
     pr, sv = _full_chain_parity(B, p, cam, rp)
     TX, TY = pr["TX"], pr["TY"]
     assert np.count_nonzero(sv == p.shape[1] - 1) == TX * TY
+
+
+@pytest.mark.parametrize("n", [0, 1, 5, 1023, 1_000_003])
+def test_check_finite_counts_nan_and_inf(B, n):
+    """tgs_check_finite against numpy's isfinite: NaNs of several payloads,
+    both infinities, the largest finite float and subnormals (finite), at
+    lengths that are not multiples of four."""
+    rng = np.random.default_rng(n)
+    x = rng.normal(size=n).astype(np.float32)
+    if n:
+        bad = rng.choice(n, max(1, n // 97), replace=False)
+        vals = np.array([np.nan, np.inf, -np.inf, np.float32(np.nan) * -1], dtype=np.float32)
+        x[bad] = vals[rng.integers(0, 4, bad.size)]
+        x.view(np.uint32)[bad[: bad.size // 2]] |= 0x7fc00123         # quiet NaNs with payloads
+        ok = np.setdiff1d(np.arange(n), bad)[:8]
+        x[ok[:4]] = np.float32(3.4e38)
+        x[ok[4:]] = np.float32(1e-42)
+    assert B.check_finite(dev(x)) == int((~np.isfinite(x)).sum())

@@ -16,6 +16,7 @@ from support import (assert_close, check_pair_lists, last_ids, scene_c1, scene_s
 pytestmark = pytest.mark.gpu
 
 RP = RasterParams()
+FULL_N = 1_500_000      # Gaussians of the full training step
 
 
 @pytest.fixture(scope="module")
@@ -172,6 +173,52 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     assert (np.abs(dp_gpu[:, keep]) <= 4 * lr[:, keep] + 1e-6).all()
 
 
+@pytest.mark.parametrize("dense", [False, True], ids=["sparse", "dense"])
+def test_deterministic_backward_repeats_bit_for_bit(B, c1_inputs, dense):
+    """The deterministic backward gives the same bits on repeated runs, and
+    agrees with the atomic backward up to the order of the float sums (1e-5
+    relative plus 1e-6 of the field's largest magnitude); a whole four-view
+    step in deterministic mode gives the same parameters, moments and
+    touched set on two runs."""
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer, ViewBuffers
+    p, cams, gts, E, A = c1_inputs
+    n = p.shape[1]
+    cam = cams[1]
+    vb = ViewBuffers(n, cam.width, cam.height, None if dense else 64, -1, torch.device("cuda"))
+    totals = torch.zeros(2, dtype=torch.int64, device="cuda")
+    if not dense:
+        vb.sample(dev(E[1].view(np.int16)), dev(A[1].view(np.int16)), StepConfig(rate_permille=250), 1, 1, totals)
+    rp = B.raster_params()
+    vb.project(dev(p), B.camera(cam), rp)
+    vb.bin_sort(alpha_min=rp.alpha_min)
+    vb.render_fwd(rp)
+    P = cam.width * cam.height if dense else int(host(vb.tile_off)[-1])
+    g = np.zeros((vb.dL.shape[0], 4), dtype=np.float32)
+    g[:P, :3] = np.random.default_rng(12).normal(size=(P, 3)) * 1e-3
+    vb.dL = dev(g)
+    runs = []
+    for det in (True, True, False):
+        vb.render_bwd(rp, zero=True, deterministic=det)
+        runs.append(host(vb.g2d).copy())
+    assert np.array_equal(runs[0].view(np.uint32), runs[1].view(np.uint32))
+    d, a = runs[0].astype(np.float64), runs[2].astype(np.float64)
+    assert np.abs(d).max() > 0
+    for f in range(9):
+        assert_close(d[:, f], a[:, f], 1e-5, 1e-6 * np.abs(a[:, f]).max() + 1e-30, f"g2d field {f}")
+    if dense:
+        return
+    res = []
+    for _ in range(2):
+        cfg = StepConfig(rate_permille=250, n_tiles_sel=64, seed=3, deterministic=True)
+        tr = Trainer(dev(p), cams, [dev(x) for x in gts], cfg, E=[dev(e.view(np.int16)) for e in E],
+                     A=[dev(x.view(np.int16)) for x in A])
+        tr.step([0, 1, 2, 3])
+        res.append([host(t).copy() for t in (tr.params, tr.m, tr.v, tr.touched)])
+        del tr
+    for x, y in zip(*res):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
 def test_c1_step_density_sums_match_oracle(B, c1_inputs):
     """A four-view step with the density sums in the backward: per Gaussian,
     E, W and D summed over the views equal the oracle's back-projection of
@@ -243,6 +290,61 @@ def test_autograd_matches_oracle_gradient_and_finite_differences(B):
         fd = (vals[0] - vals[1]) / (2 * h)
         an = float((g_gpu * u).sum())
         assert abs(fd - an) <= 1e-3 * max(abs(fd), 1e-3), (name, fd, an)
+
+
+def test_fp64_path_matches_oracle_element_by_element(B):
+    """The FP64 instantiation against the FP64 oracle, sparse and dense:
+    colours, transmittance and contributor counts of every sample, and the
+    parameter gradient of a random functional through the autograd wrapper,
+    element by element at 1e-9 relative (both sides compute in doubles; they
+    differ only in the order of the gradient sums and the exponential's last
+    bits)."""
+    from paper_2606_15924_amd.autograd import Samples, rasterize
+    p, cam = small_scene(n=300, seed=34, W=64, H=48)
+    E = synth.error_map(cam.height, cam.width, 73)
+    A = synth.age_map(cam.height, cam.width, 74)
+    pr = project.project(p, cam, RP)
+    for dense in (False, True):
+        if dense:
+            xs, ys = render.dense_pixels(cam.width, cam.height)
+            samples = Samples(None, None, None, 0, 256)
+            _, sv, rg = binning.bin_and_sort(pr)
+        else:
+            s = sampler.sample_view(E, A, SampleParams(n_pix=100), 3, 1, 0)
+            xs, ys, _ = sampler.sample_coords(s, cam.width, cam.height)
+            samples = Samples(dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"]), s["valid_tiles"].size, 100)
+            _, sv, rg = binning.bin_and_sort(pr, s["valid_tiles"])
+        out = render.render_pixels(pr, sv, rg, xs, ys, RP)
+        P = dev(p.astype(np.float64)).requires_grad_(True)
+        rgb = rasterize(P, cam, samples)
+        assert rgb.dtype == torch.float64
+        assert_close(host(rgb.detach()), out["rgb"], 1e-9, 1e-13, "rgb")
+        w = np.random.default_rng(10 + dense).normal(size=(xs.size, 3))
+        (rgb * dev(w)).sum().backward()
+        g = host(P.grad)
+        g_ref = project_bwd.project_bwd(p, cam, pr, render.render_pixels_bwd(pr, sv, rg, xs, ys, w, RP), RP)
+        for name, sl in GROUPS.items():
+            assert_close(g[sl], g_ref[sl], 1e-9, 1e-12 * np.abs(g_ref[sl]).max() + 1e-300, f"gradient {name}")
+
+
+def test_fp64_gradcheck_on_full_step_subset(B):
+    """torch.autograd.gradcheck of the FP64 rasterizer: the first 2000
+    Gaussians of the 1.5M-Gaussian scene, one hemisphere view at 128x128
+    (the focal length scaled with the width), 20 % error-guided samples of
+    every tile; central differences along random directions (fast mode)
+    against the hand-written adjoint, with the default thresholds."""
+    from paper_2606_15924_amd.autograd import Samples, rasterize
+    p = synth.gaussians(FULL_N, synth.SEED_SCENE)[:, :2000].copy()
+    cam = synth.hemisphere_cameras(150, width=128, height=128, focal=1875.0 * 128 / 1600)[0]
+    E = synth.error_map(128, 128, 75)
+    A = synth.age_map(128, 128, 76)
+    s = sampler.sample_view(E, A, SampleParams(n_pix=51), 3, 1, 0)
+    samples = Samples(dev(s["valid_tiles"]), dev(s["tile_off"]), dev(s["pix"]), s["valid_tiles"].size, 51)
+    P = dev(p.astype(np.float64)).requires_grad_(True)
+    out = rasterize(P, cam, samples)
+    assert out.shape == (int(s["tile_off"][-1]), 3) and float(out.detach().abs().max()) > 0.05
+    assert torch.autograd.gradcheck(lambda q: rasterize(q, cam, samples), (P,), eps=1e-6, atol=1e-7, rtol=1e-5,
+                                    fast_mode=True, nondet_tol=1e-12)
 
 
 # ------------------------------------------------------------------ full-size workload
@@ -339,9 +441,6 @@ def test_scaling_optimizer_on_sampled_gaussians(B, scaling):
 # LM in its diagonal mode.  Checked at full size: one view's projection, pair
 # lists and ranges bit-exact; forward and backward on sampled tiles against
 # the oracle; the multi-view steps by properties that hold at any size.
-FULL_N = 1_500_000
-
-
 @pytest.fixture(scope="module")
 def fullstep(B):
     from paper_2606_15924_amd.pipeline import StepConfig, ViewBuffers
