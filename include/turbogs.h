@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 8u
+#define TGS_ABI_VERSION 9u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
@@ -95,10 +95,16 @@ typedef struct tgs_sample_params {
   int32_t reserved;
 } tgs_sample_params;
 
+/* Tile structure term of the sparse loss: S-NCC (Sec. 3.7), or a sparse
+ * SSIM over the tile's samples (the S-SSIM ablation of Tab. ablation_main). */
+#define TGS_STRUCTURE_NCC 0
+#define TGS_STRUCTURE_SSIM 1
+
 typedef struct tgs_loss_params {
   float eps_charb;   /* Charbonnier epsilon */
   float eps_ncc;     /* added to V_x V_y under the NCC square root */
   float eps_lambda;  /* denominator guard of the balance weight */
+  int32_t structure; /* TGS_STRUCTURE_NCC or TGS_STRUCTURE_SSIM */
 } tgs_loss_params;
 
 typedef struct tgs_optim_params {
@@ -286,7 +292,12 @@ int32_t tgs_render_bwd_deterministic(const float* splat, const uint32_t* vals, c
 
 /* Sparse supervision of one view (Sec. 3.7: Charbonnier L1 per pixel plus
  * tile NCC with the gradient-balanced weight of Eq. ncc_weight_auto, summed
- * as Eq. full_loss).
+ * as Eq. full_loss).  With lp->structure = TGS_STRUCTURE_SSIM the tile term
+ * is 1 - SSIM instead, SSIM = (2 mu_x mu_y + C1)(2 C_xy + C2) /
+ * ((mu_x^2 + mu_y^2 + C1)(V_x + V_y + C2)) per channel over the tile's
+ * samples (1/n moments, C1 = 0.01^2, C2 = 0.03^2), with the same balance
+ * weight built from its gradient; tile_loss then holds 1 - mean SSIM in
+ * place of 1 - mean NCC.
  *   out        [P][4] rendered colours; gt [3][H][W] float target image
  *   totals     [2] int64 device: sampled pixels and sampled tiles of the step
  *   dL_dout    [P][4] written (channel 3 = 0); err [P] = |I_hat - I|_1

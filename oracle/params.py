@@ -46,6 +46,7 @@ class LossParams:
     eps_charb: float = 1e-3
     eps_ncc: float = 1e-6
     eps_lambda: float = 1e-8
+    structure: str = "ncc"       # tile structure term: "ncc" (S-NCC) or "ssim" (the S-SSIM ablation)
 
 
 @dataclass

@@ -47,7 +47,11 @@ class tgs_sample_params(ctypes.Structure):
 
 
 class tgs_loss_params(ctypes.Structure):
-    _fields_ = [("eps_charb", ctypes.c_float), ("eps_ncc", ctypes.c_float), ("eps_lambda", ctypes.c_float)]
+    _fields_ = [("eps_charb", ctypes.c_float), ("eps_ncc", ctypes.c_float), ("eps_lambda", ctypes.c_float),
+                ("structure", ctypes.c_int32)]
+
+
+STRUCTURE = {"ncc": 0, "ssim": 1}   # TGS_STRUCTURE_NCC, TGS_STRUCTURE_SSIM
 
 
 class tgs_optim_params(ctypes.Structure):
@@ -207,9 +211,11 @@ def sample_params(n_pix, hard_permille=400, stable_permille=300, n_tiles_sel=-1,
     return s
 
 
-def loss_params(eps_charb=1e-3, eps_ncc=1e-6, eps_lambda=1e-8) -> tgs_loss_params:
+def loss_params(eps_charb=1e-3, eps_ncc=1e-6, eps_lambda=1e-8, structure="ncc") -> tgs_loss_params:
+    """Loss constants; ``structure`` is the tile term, "ncc" (S-NCC) or "ssim" (S-SSIM)."""
     p = tgs_loss_params()
     p.eps_charb, p.eps_ncc, p.eps_lambda = eps_charb, eps_ncc, eps_lambda
+    p.structure = STRUCTURE[structure] if isinstance(structure, str) else int(structure)
     return p
 
 

@@ -1,5 +1,5 @@
-// Sparse supervision (Charbonnier L1 + tile NCC with gradient balance) and the
-// per-pixel error/age maps.
+// Sparse supervision (Charbonnier L1 + tile NCC with gradient balance, or the
+// tile S-SSIM of the ablation in its place) and the per-pixel error/age maps.
 //
 // loss: one wave per sampled tile; a lane holds up to four of the tile's
 // samples (strided, so loads coalesce).  The tile statistics (means, centred
@@ -13,7 +13,11 @@
 
 namespace tgs {
 
-template <bool kDense>
+// SSIM constants for values in [0, 1]: (0.01)^2 and (0.03)^2.
+constexpr float kSsimC1 = 1e-4f;
+constexpr float kSsimC2 = 9e-4f;
+
+template <bool kDense, bool kSsim = false>
 __global__ void __launch_bounds__(64) loss_kernel(
     const float4* __restrict__ out, const float* __restrict__ gt, int H, int W, int tiles_x,
     const int32_t* __restrict__ valid_tiles, const int32_t* __restrict__ tile_off,
@@ -77,14 +81,24 @@ __global__ void __launch_bounds__(64) loss_kernel(
       m2[6 + c] += xc * yc;
     }
   }
-  float Vy[3], D[3], rsD[3], ncc[3];
+  // structure term per channel: NCC, or SSIM (ncc[] then holds SSIM and the
+  // per-sample gradient below uses the SSIM factors A1, A2, B1, B2)
+  float Vy[3], D[3], rsD[3], ncc[3], A1[3], A2[3], B1[3], B2[3];
   for (int c = 0; c < 3; ++c) {
     const float Vx = wave_sum(m2[c]) * inv_n;
     Vy[c] = wave_sum(m2[3 + c]) * inv_n;
     const float Cxy = wave_sum(m2[6 + c]) * inv_n;
-    D[c] = Vx * Vy[c] + eps_n;
-    rsD[c] = 1.f / sqrtf(D[c]);
-    ncc[c] = Cxy * rsD[c];
+    if constexpr (kSsim) {
+      A1[c] = 2.f * mx[c] * my[c] + kSsimC1;
+      A2[c] = 2.f * Cxy + kSsimC2;
+      B1[c] = mx[c] * mx[c] + my[c] * my[c] + kSsimC1;
+      B2[c] = Vx + Vy[c] + kSsimC2;
+      ncc[c] = (A1[c] * A2[c]) / (B1[c] * B2[c]);
+    } else {
+      D[c] = Vx * Vy[c] + eps_n;
+      rsD[c] = 1.f / sqrtf(D[c]);
+      ncc[c] = Cxy * rsD[c];
+    }
   }
   // per-sample gradients and their mean L1 norms
   float g1[4][3], gn[4][3];
@@ -102,7 +116,10 @@ __global__ void __launch_bounds__(64) loss_kernel(
       rho_sum += rho;
       g1[r][c] = d / rho;
       const float xc = x[r][c] - mx[c], yc = y[r][c] - my[c];
-      gn[r][c] = -(yc * rsD[c] - ncc[c] * Vy[c] * xc / D[c]);
+      if constexpr (kSsim)
+        gn[r][c] = -2.f * ncc[c] * (my[c] / A1[c] + yc / A2[c] - mx[c] / B1[c] - xc / B2[c]);
+      else
+        gn[r][c] = -(yc * rsD[c] - ncc[c] * Vy[c] * xc / D[c]);
       n1 += fabsf(g1[r][c]);
       nn += fabsf(gn[r][c]);
     }
@@ -194,20 +211,26 @@ extern "C" int32_t tgs_loss(const float* out, const float* gt, int32_t height, i
               "tgs_loss: out and dL_dout must be 16-byte aligned");
   const int tiles_x = (int)ceil_div(width, kTile), tiles_y = (int)ceil_div(height, kTile);
   hipStream_t s = as_stream(stream);
+  TGS_REQUIRE(lp->structure == TGS_STRUCTURE_NCC || lp->structure == TGS_STRUCTURE_SSIM,
+              "tgs_loss: unknown structure term %d", lp->structure);
   const float eps_c2 = lp->eps_charb * lp->eps_charb;
+  const bool ssim = lp->structure == TGS_STRUCTURE_SSIM;
+#define TGS_LOSS(DENSE, SSIM, GRID)                                                                              \
+  hipLaunchKernelGGL((loss_kernel<DENSE, SSIM>), dim3(GRID), dim3(64), 0, s, (const float4*)out, gt, height,     \
+                     width, tiles_x, valid_tiles, tile_off, pix, totals, eps_c2, lp->eps_ncc, lp->eps_lambda,    \
+                     (float4*)dL_dout, err, lambda, (float2*)tile_loss)
   if (valid_tiles == nullptr) {
-    hipLaunchKernelGGL(loss_kernel<true>, dim3(tiles_x * tiles_y), dim3(64), 0, s, (const float4*)out,
-                       gt, height, width, tiles_x, valid_tiles, tile_off, pix, totals, eps_c2,
-                       lp->eps_ncc, lp->eps_lambda, (float4*)dL_dout, err, lambda,
-                       (float2*)tile_loss);
+    if (ssim) TGS_LOSS(true, true, tiles_x * tiles_y);
+    else TGS_LOSS(true, false, tiles_x * tiles_y);
   } else {
     TGS_REQUIRE(tile_off && pix, "tgs_loss: null tile_off/pix");
     TGS_REQUIRE(n_st >= 0 && n_st <= tiles_x * tiles_y, "tgs_loss: bad n_st %d", n_st);
-    if (n_st > 0)
-      hipLaunchKernelGGL(loss_kernel<false>, dim3(n_st), dim3(64), 0, s, (const float4*)out, gt, height,
-                         width, tiles_x, valid_tiles, tile_off, pix, totals, eps_c2, lp->eps_ncc,
-                         lp->eps_lambda, (float4*)dL_dout, err, lambda, (float2*)tile_loss);
+    if (n_st > 0) {
+      if (ssim) TGS_LOSS(false, true, n_st);
+      else TGS_LOSS(false, false, n_st);
+    }
   }
+#undef TGS_LOSS
   return hip_status("tgs_loss");
 }
 

@@ -96,15 +96,53 @@ def _excluded_gaussians(ref, views, n):
     return ex
 
 
+N_DRAWS = 4
+
+
+def _dL_perturbations(fv, gt, s, P_step, tiles_step, rng):
+    """Seeded perturbations of one view's loss gradient dL/dI of the size an
+    FP32 evaluation can take it off the FP64 one: its response to the
+    rendered colours moving by 1e-6 relative + 1e-7 with random signs (the
+    FP32 render agrees with the oracle to a few 1e-7), plus 64 FP32 ulps of
+    the magnitudes of its Charbonnier and NCC parts with random signs (each
+    part comes from a handful of rounded operations); N_DRAWS draws."""
+    from oracle import loss as oloss
+    y = pipeline.gt_at(gt, fv["xs"], fv["ys"])
+    x = fv["out"]["rgb"]
+    base = oloss.sparse_loss(x, y, s["tile_off"], P_step, tiles_step)["dL"]
+    parts = np.zeros_like(base)
+    off = s["tile_off"]
+    for t in range(off.size - 1):
+        lo, hi = off[t], off[t + 1]
+        if hi > lo:
+            tl = oloss.tile_loss(x[lo:hi], y[lo:hi])
+            parts[lo:hi] = np.abs(tl["g1"]) / (3.0 * P_step) + tl["lam"] * np.abs(tl["gn"]) / (3.0 * (hi - lo) * tiles_step)
+    out = []
+    for _ in range(N_DRAWS):
+        sg = rng.choice([-1.0, 1.0], size=x.shape)
+        xp = x * (1.0 + 1e-6 * sg) + 1e-7 * sg
+        d = oloss.sparse_loss(xp, y, s["tile_off"], P_step, tiles_step)["dL"] - base
+        out.append(d + 64 * ULP32 * parts * rng.choice([-1.0, 1.0], size=x.shape))
+    return out
+
+
 @pytest.mark.parametrize("fused", [False, True])
 def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     """One four-view step against the oracle's step, element by element:
     samples bit for bit; rgb to 1e-5; the last composited Gaussian of every
-    pixel; ages bit for bit; the accumulated gradient (unfused) and the
-    parameter update per element at 1e-4 relative plus 16 FP32 ulps of the
-    oracle's error scale (the screen-space scale pushed through the exact
-    Jacobian magnitudes), outside the tiles that hold a guard-band pixel;
-    the touched set (Gaussians composited at a sample) exactly outside them."""
+    pixel; ages bit for bit; E within a half ulp step; the touched set
+    (Gaussians composited at a sample) exactly; outside the tiles that hold
+    a guard-band pixel:
+    * the accumulated gradient (unfused) per element at 1e-4 relative plus
+      the oracle's FP32 error scale: 16 ulps of the screen-space scale of
+      the replay pushed through the exact Jacobian magnitudes, plus four
+      times the largest response of the exact adjoint (screen space, then
+      the chain rule) to perturbations of dL/dI of FP32 size
+      (_dL_perturbations);
+    * the updated parameters per element within the spread of the oracle's
+      update over gradients moved inside that error bar (all magnitudes up,
+      all down, four random sign patterns; times 1.5), plus 1e-4 relative
+      and two FP32 ulps of the parameter."""
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
     p, cams, gts, E, A = c1_inputs
     n = p.shape[1]
@@ -118,6 +156,10 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     used = tr.step([0, 1, 2, 3])
     torch.cuda.synchronize()
     scale = np.zeros((59, n))
+    P_step = sum(int(ref["views"][v]["samples"]["tile_off"][-1]) for v in range(4))
+    T_step = sum(int(ref["views"][v]["samples"]["valid_tiles"].size) for v in range(4))
+    rng = np.random.default_rng(17)
+    resp = np.zeros((N_DRAWS, 59, n))
     for v, vb in enumerate(used):
         rv = ref["views"][v]
         s = rv["samples"]
@@ -142,7 +184,11 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
         assert np.all(np.abs(e_gpu - e_ref) <= np.abs(np.spacing(e_ref.astype(np.float16))).astype(np.float64))
         _, g2d_abs = render.render_pixels_bwd(fv["proj"], fv["vals"], fv["ranges"], fv["xs"], fv["ys"],
                                               rv["loss"]["dL"], RP, with_abs=True)
-        scale += _param_error_scale(p, cams[v], fv["proj"], g2d_abs)
+        scale += 16 * ULP32 * _param_error_scale(p, cams[v], fv["proj"], g2d_abs)
+        for k, dd in enumerate(_dL_perturbations(fv, gts[v], s, P_step, T_step, rng)):
+            g2d_k = render.render_pixels_bwd(fv["proj"], fv["vals"], fv["ranges"], fv["xs"], fv["ys"], dd, RP)
+            resp[k] += project_bwd.project_bwd(p, cams[v], fv["proj"], g2d_k, RP)
+    scale += 4.0 * np.abs(resp).max(axis=0)
     loss_gpu = tr.loss_value(used)
     assert abs(loss_gpu - ref["loss"]) <= 1e-4 * abs(ref["loss"])
     ex = _excluded_gaussians(ref, range(4), n)
@@ -150,27 +196,28 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     t_gpu = host(tr.touched).astype(bool)
     assert np.array_equal(t_gpu[~ex], ref["touched"][~ex]) and ref["touched"].sum() > 2000
     keep = ~ex
-    tol_g = 1e-4 * np.abs(ref["grad"]) + 16 * ULP32 * scale + 1e-30
+    tol_g = 1e-4 * np.abs(ref["grad"]) + scale + 1e-30
     if not fused:
         g = host(tr.grad).astype(np.float64)
         for name, sl in GROUPS.items():
-            assert_close(g[sl][:, keep], ref["grad"][sl][:, keep], 1e-4, (16 * ULP32 * scale[sl] + 1e-30)[:, keep],
+            assert_close(g[sl][:, keep], ref["grad"][sl][:, keep], 1e-4, (scale[sl] + 1e-30)[:, keep],
                          f"gradient {name}")
-    # the update, where the gradient is determined beyond its error bar (the
-    # step-1 update of Adam and LM is close to -lr sign(g), which a gradient
-    # inside its bar may flip); elsewhere at most one learning rate per
-    # element, as the update of an exactly zero gradient is zero
+    # the update: the spread of the oracle's update over gradients inside
+    # their error bar
+    z = np.zeros_like(p, np.float64)
+    sgn = np.sign(ref["grad"])
+    spread = np.zeros_like(z)
+    pert = [sgn, -sgn] + [rng.choice([-1.0, 1.0], size=p.shape) for _ in range(4)]
+    for d in pert:
+        pk, _, _ = optim.optimizer_step(p, ref["grad"] + d * tol_g, z, z, ref["touched"], OptimParams(), 1)
+        spread = np.maximum(spread, np.abs(pk - ref["params"]))
     dp_gpu = host(tr.params).astype(np.float64) - p
     dp_ref = ref["params"] - p
-    det = keep[None, :] & (np.abs(ref["grad"]) > 2 * tol_g)
-    assert det.sum() > 0.5 * (ref["grad"][:, keep] != 0).sum()
+    assert (dp_ref[:, keep] != 0).sum() > 0.5 * (ref["grad"][:, keep] != 0).sum()
     for name, sl in GROUPS.items():
-        d = det[sl]
-        p32 = np.abs(ref["params"][sl][d]).astype(np.float32)
-        assert_close(dp_gpu[sl][d], dp_ref[sl][d], 1e-4, 2 * np.spacing(p32).astype(np.float64) + 1e-12,
-                     f"update {name}")
-    lr = OptimParams().row_lr()[:, None] * np.ones((1, n))
-    assert (np.abs(dp_gpu[:, keep]) <= 4 * lr[:, keep] + 1e-6).all()
+        p32 = np.abs(ref["params"][sl][:, keep]).astype(np.float32)
+        assert_close(dp_gpu[sl][:, keep], dp_ref[sl][:, keep], 1e-4,
+                     1.5 * spread[sl][:, keep] + 2 * np.spacing(p32).astype(np.float64) + 1e-12, f"update {name}")
 
 
 @pytest.mark.parametrize("dense", [False, True], ids=["sparse", "dense"])
@@ -543,7 +590,9 @@ def test_full_size_multi_view_step_properties(B, fullstep, views, lm_mode):
         u = np.abs(a.astype(np.float64) - p) + np.abs(b.astype(np.float64) - p) if a is p1 else \
             np.abs(a.astype(np.float64)) + np.abs(b.astype(np.float64))
         assert (d > 1e-3 * u + 1e-12).mean() < 1e-3
-    assert 0.1 < t1.mean() < 1.0
+    # the update touches the Gaussians composited at a sample: at 20% of
+    # every tile and three views a few percent of the 1.5M
+    assert 0.01 < t1.mean() < 1.0
     assert np.array_equal(p1[:, ~t1], p[:, ~t1]) and not m1[:, ~t1].any() and not v1[:, ~t1].any()
     moved = (p1[:, t1] != p[:, t1]).any(axis=0)
     assert moved.mean() > 0.05

@@ -128,9 +128,12 @@ def test_bin_sort_lists_against_rectangle_lists(B, case):
     t_ref = np.zeros(n, dtype=np.uint8)
     t_ref[np.unique(vals)] = 1
     assert np.array_equal(host(touched), t_ref)
-    # too-small capacity reports the required count, which then suffices
+    # too-small capacity reports the required count, which then suffices (the
+    # failed call clears its ranges, so it gets arrays of its own)
+    R_first = R.clone()
     with pytest.raises(B.CapacityError) as ei:
-        B.tgs_bin_sort(rect, splat, depth, n, tile_slot, TX, TY, 1.0 / 255.0, K, V, 10, R, None, ws)
+        B.tgs_bin_sort(rect, splat, depth, n, tile_slot, TX, TY, 1.0 / 255.0, K.clone(), V.clone(), 10,
+                       torch.empty_like(R), None, ws)
     req = ei.value.required
     assert npairs <= req <= int(rect_area[np.unique(vals)].sum())
     ws2 = torch.empty(B.tgs_bin_sort_workspace_size(n, req, TX * TY), dtype=torch.uint8, device="cuda")
@@ -138,7 +141,7 @@ def test_bin_sort_lists_against_rectangle_lists(B, case):
     V2 = torch.empty(req, dtype=torch.int32, device="cuda")
     R2 = torch.empty((TX * TY, 2), dtype=torch.int32, device="cuda")
     assert B.tgs_bin_sort(rect, splat, depth, n, tile_slot, TX, TY, 1.0 / 255.0, K2, V2, req, R2, None, ws2) == npairs
-    assert torch.equal(K2[:npairs], K[:npairs]) and torch.equal(V2[:npairs], V[:npairs]) and torch.equal(R2, R)
+    assert torch.equal(K2[:npairs], K[:npairs]) and torch.equal(V2[:npairs], V[:npairs]) and torch.equal(R2, R_first)
 
 
 # ------------------------------------------------------------------ sampler
@@ -415,8 +418,13 @@ def test_render_bwd_chunked_equals_single(B, mode):
 
 
 # ------------------------------------------------------------------ loss, maps
+@pytest.mark.parametrize("structure", ["ncc", "ssim"])
 @pytest.mark.parametrize("case", ["c1", "ragged25", "dense"])
-def test_loss_parity(B, case):
+def test_loss_parity(B, case, structure):
+    """The sparse loss (Charbonnier plus the tile S-NCC, or the S-SSIM of the
+    ablation) against the oracle: per-pixel error, balance weights, dL/dI
+    and the loss value."""
+    lp = LossParams(structure=structure)
     rng = np.random.default_rng(4)
     if case == "dense":
         W, H = 70, 45
@@ -428,7 +436,7 @@ def test_loss_parity(B, case):
         order = np.argsort(tiles, kind="stable")
         off = np.concatenate([[0], np.cumsum(np.bincount(tiles, minlength=TX * TY))])
         P_step, T_step = W * H + 100, TX * TY + 3
-        ref = loss.sparse_loss(x[order], gt[:, ys[order], xs[order]].T, off, P_step, T_step)
+        ref = loss.sparse_loss(x[order], gt[:, ys[order], xs[order]].T, off, P_step, T_step, lp)
         dL_ref = np.zeros((W * H, 3))
         dL_ref[order] = ref["dL"]
         err_ref = np.zeros(W * H)
@@ -447,7 +455,7 @@ def test_loss_parity(B, case):
         gt = synth.image(H, W, 53)
         x = np.clip(gt[:, ys, xs].T + rng.normal(0, 0.05, size=(xs.size, 3)), 0, 1).astype(np.float32)
         P_step, T_step = xs.size * 3, s["valid_tiles"].size * 3
-        ref = loss.sparse_loss(x, gt[:, ys, xs].T, s["tile_off"], P_step, T_step)
+        ref = loss.sparse_loss(x, gt[:, ys, xs].T, s["tile_off"], P_step, T_step, lp)
         dL_ref, err_ref, lam_ref = ref["dL"], ref["err"], ref["lam"]
         out = np.zeros((xs.size, 4), dtype=np.float32)
         out[:, :3] = x
@@ -459,7 +467,8 @@ def test_loss_parity(B, case):
     lam = torch.empty(n_st, dtype=torch.float32, device="cuda")
     tl = torch.empty((n_st, 2), dtype=torch.float32, device="cuda")
     totals = dev(np.array([P_step, T_step], dtype=np.int64))
-    B.tgs_loss(dev(out), dev(gt), H, W, vt, offt, pix, n_st, totals, B.loss_params(), dL, err, lam, tl)
+    B.tgs_loss(dev(out), dev(gt), H, W, vt, offt, pix, n_st, totals, B.loss_params(structure=structure), dL, err,
+               lam, tl)
     gd, ge, gl, gt_l = host(dL), host(err), host(lam), host(tl)
     assert_close(ge, err_ref, 1e-6, 1e-7, "err")
     assert_close(gl, lam_ref, 1e-4, 1e-6, "lambda")

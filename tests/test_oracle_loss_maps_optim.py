@@ -245,3 +245,73 @@ def test_adam_rows_match_torch_adam_and_sparse_mask():
         assert np.allclose(newp[row, touched], t.detach().numpy(), rtol=1e-12, atol=1e-15)
     assert np.array_equal(newp[:, ~touched], p[:, ~touched])
     assert (newm[:, ~touched] == 0).all() and (newv[:, ~touched] == 0).all()
+
+
+# ---------------------------------------------------------------- S-SSIM variant
+def _ssim_lp():
+    return LossParams(structure="ssim")
+
+
+def test_ssim_identities_and_closed_forms():
+    """Sparse SSIM of one tile: SSIM(x, x) = 1 with zero gradient; symmetric
+    in x and y; constant tiles reduce to the luminance term
+    (2 a b + C1) / (a^2 + b^2 + C1); y = s x + c (s > 0) makes the
+    contrast-structure term (2 s V + C2) / ((1 + s^2) V + C2) with V the
+    variance of x; and |SSIM| <= 1."""
+    rng = np.random.default_rng(21)
+    x = rng.uniform(0.1, 0.9, size=(37, 3))
+    s, g = loss.ssim_terms(x, x)
+    assert np.allclose(s, 1.0, rtol=0, atol=1e-15) and np.allclose(g, 0.0, atol=1e-13)
+    y = rng.uniform(0.0, 1.0, size=(37, 3))
+    assert np.allclose(loss.ssim_terms(x, y)[0], loss.ssim_terms(y, x)[0], rtol=1e-14, atol=0)
+    a, b = 0.3, 0.7
+    s_const = loss.ssim_terms(np.full((20, 3), a), np.full((20, 3), b))[0]
+    assert np.allclose(s_const, (2 * a * b + loss.SSIM_C1) / (a * a + b * b + loss.SSIM_C1), rtol=1e-14)
+    sc, c = 1.7, -0.2
+    y2 = sc * x + c
+    mx, my = x.mean(0), y2.mean(0)
+    V = x.var(0)
+    lum = (2 * mx * my + loss.SSIM_C1) / (mx * mx + my * my + loss.SSIM_C1)
+    cs = (2 * sc * V + loss.SSIM_C2) / ((1 + sc * sc) * V + loss.SSIM_C2)
+    assert np.allclose(loss.ssim_terms(x, y2)[0], lum * cs, rtol=1e-13)
+    for _ in range(20):
+        u, v = rng.uniform(-1, 2, size=(2, 15, 3))
+        assert (np.abs(loss.ssim_terms(u, v)[0]) <= 1 + 1e-12).all()
+
+
+def test_ssim_gradient_matches_finite_differences():
+    """g_s = n d(1 - SSIM)/dx by central differences, per sample and channel."""
+    rng = np.random.default_rng(22)
+    x = rng.uniform(0.0, 1.0, size=(23, 3))
+    y = rng.uniform(0.0, 1.0, size=(23, 3))
+    _, g = loss.ssim_terms(x, y)
+    n = x.shape[0]
+    h = 1e-6
+    for i in range(n):
+        for ch in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, ch] += h
+            xm[i, ch] -= h
+            fd = -(loss.ssim_terms(xp, y)[0][ch] - loss.ssim_terms(xm, y)[0][ch]) / (2 * h)
+            assert np.isclose(n * fd, g[i, ch], rtol=1e-6, atol=1e-9)
+
+
+def test_ssim_sparse_loss_gradient_matches_finite_differences():
+    """dL/dI of the S-SSIM loss (lambdas held fixed) by central differences
+    of loss_value, and the S-NCC loss differs from it."""
+    rng = np.random.default_rng(23)
+    tile_off = np.array([0, 9, 9, 30, 41])
+    x = rng.uniform(0.0, 1.0, size=(41, 3))
+    y = rng.uniform(0.0, 1.0, size=(41, 3))
+    lp = _ssim_lp()
+    out = loss.sparse_loss(x, y, tile_off, 60, 5, lp)
+    assert not np.allclose(out["dL"], loss.sparse_loss(x, y, tile_off, 60, 5)["dL"])
+    h = 1e-6
+    for i in rng.choice(41, 12, replace=False):
+        for ch in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, ch] += h
+            xm[i, ch] -= h
+            fd = (loss.loss_value(xp, y, tile_off, 60, 5, out["lam"], lp) -
+                  loss.loss_value(xm, y, tile_off, 60, 5, out["lam"], lp)) / (2 * h)
+            assert np.isclose(fd, out["dL"][i, ch], rtol=1e-5, atol=1e-10)
