@@ -22,7 +22,12 @@ Readings (the paper leaves these open):
 * E_bar_t is the mean of the views' E_bar, E_bar_init its value after the
   dense initialisation; eps = 1e-8; round() is floor(x + 1/2); the pixel
   rate in permille is floor(1000 r_tile + 1/2) clipped to [1, 1000];
-* rho_t = 1 - clip(t / tau_until, 0, 1) (the appendix's definition).
+* rho_t = 1 - clip(t / tau_until, 0, 1) (the appendix's definition);
+* random view sampling (the "Geo-VS -> RVS" ablation baseline of Tab.
+  ablation_main) draws the step's K views uniformly without replacement
+  from all views, with no anchor and no stack: draw j takes the 64-bit
+  counter value u = draw(seed, t, 1, V, j) and picks the
+  floor(u m / 2^64)-th of the m views not yet drawn, in ascending order.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 """
@@ -32,7 +37,7 @@ import math
 
 import numpy as np
 
-from .rng import draw
+from .rng import below, draw
 
 SCALE = 1 << 24
 
@@ -92,3 +97,13 @@ def schedule(t: int, E_t: float, E_init: float, tau_until: int, K_min: int, K_ma
     K = int(math.floor(K_min + (K_max - K_min) * math.exp(-alpha * a) + 0.5))
     permille = min(max(int(math.floor(1000.0 * r_tile + 0.5)), 1), 1000)
     return dict(r=r, phi=phi, rho=rho, r_tile=r_tile, K=K, permille=permille)
+
+
+def random_views(V: int, K: int, seed: int, t: int) -> list:
+    """Random view sampling: K distinct views uniformly at random (draw order)."""
+    K = min(K, V)
+    rest = list(range(V))
+    chosen = []
+    for j in range(K):
+        chosen.append(rest.pop(below(draw(seed, t, 1, V, j), len(rest))))
+    return chosen

@@ -20,7 +20,11 @@ Conventions (fixed so that runs are reproducible):
   pixel rate in permille is floor(1000 r_tile + 1/2) clipped to [1, 1000];
 * that rho_t (the appendix's) lives inside the schedule only; the density
   score of Eq. gauss_score takes the training progress of Alg. 1,
-  min(1, t / tau_until).
+  min(1, t / tau_until);
+* random view sampling (the ablation baseline that replaces the
+  geometry-aware sampling): K distinct views uniformly at random, draw j
+  picking the floor(u m / 2^64)-th of the m views left (ascending), u the
+  counter value of (seed, t, 1, V, j).
 """
 from __future__ import annotations
 
@@ -96,6 +100,16 @@ def pick_views(stack, means, centres, dirs, K, lam_d, lam_t, seed, t):
                 break
         views.append(cand.pop(k))
     return views, [u for u in pool if u not in views]
+
+
+def pick_views_random(V: int, K: int, seed: int, t: int) -> list:
+    """Random view sampling: K distinct views, uniformly, in draw order."""
+    K = min(K, V)
+    rest = list(range(V))
+    views = []
+    for j in range(K):
+        views.append(rest.pop((counter_draw(seed, t, 1, V, j) * len(rest)) >> 64))
+    return views
 
 
 @dataclass
@@ -176,14 +190,16 @@ def density_step(tr, t: int, tau_until: int, plan: DensityPlan, extent: float):
 
 
 def run_schedule(tr, steps: int, sch: Schedule, lam_d: float, lam_t: float, seed: int, t0: int = 1,
-                 density: DensityPlan | None = None, on_density=None):
+                 density: DensityPlan | None = None, on_density=None, view_sampling: str = "geometry"):
     """Sparse training driven by the schedule: each step takes K_t and the
     pixel rate from the schedule, picks the anchor and its companions from
     the views' mean errors and runs the step at that rate; afterwards only
     the stepped views' mean errors are reduced again (the other maps are
     unchanged).  With ``density``, every ``every`` steps from ``t_from`` to
     ``t_until`` a density step runs (``density_step``); ``on_density(t, tr)``
-    is called just before it (e.g. to read the statistics).  E_bar_init is
+    is called just before it (e.g. to read the statistics).
+    ``view_sampling`` = "random" replaces the anchor and companion draws by
+    random view sampling (``pick_views_random``).  E_bar_init is
     the mean error when the run starts.  Returns the per-step (views, K_t,
     rate in permille, the views' mean errors before the step, Gaussians
     after it)."""
@@ -199,7 +215,12 @@ def run_schedule(tr, steps: int, sch: Schedule, lam_d: float, lam_t: float, seed
     log = []
     for t in range(t0, t0 + steps):
         K, permille = sch.at(t, sum(means) / len(means), e_init)
-        views, stack = pick_views(stack, means, centres, dirs, K, lam_d, lam_t, seed, t)
+        if view_sampling == "random":
+            views = pick_views_random(len(cams), K, seed, t)
+        elif view_sampling == "geometry":
+            views, stack = pick_views(stack, means, centres, dirs, K, lam_d, lam_t, seed, t)
+        else:
+            raise ValueError(f"unknown view sampling {view_sampling!r}")
         tr.step(views, rate_permille=permille)
         if density is not None and density.t_from <= t <= density.t_until and t % density.every == 0:
             if on_density is not None:

@@ -76,6 +76,30 @@ def test_schedule_driven_training(B):
     assert tr._bufs[0].n_pix == B.tgs_pixels_per_tile(log[-1][2])
 
 
+def test_schedule_driven_training_with_random_view_sampling(B):
+    """The same loop with random view sampling (the ablation baseline): each
+    step trains the oracle's uniform draw of K_t distinct views, K_t and the
+    rate still from the schedule."""
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    from paper_2606_15924_amd.schedule import Schedule, run_schedule
+    from support import scene_c1
+    p, cams = scene_c1()
+    H, W = cams[0].height, cams[0].width
+    gts = [torch.from_numpy(synth.image(H, W, 330 + k)).cuda() for k in range(len(cams))]
+    E = [torch.zeros((H, W), dtype=torch.int16, device="cuda") for _ in cams]
+    A = [torch.zeros((H, W), dtype=torch.int16, device="cuda") for _ in cams]
+    tr = Trainer(torch.from_numpy(p).cuda(), cams, gts, StepConfig(rate_permille=250), E=E, A=A)
+    tr.init_error_maps(list(range(len(cams))))
+    p0 = tr.params.clone()
+    sch = Schedule(tau_until=10, K_min=1, K_max=3, lam=0.75, alpha=3.0)
+    log = run_schedule(tr, 12, sch, lam_d=0.5, lam_t=1.0, seed=8, view_sampling="random")
+    e_init = float(np.mean(log[0][3]))
+    for t, (views, K, permille, means, _) in enumerate(log, start=1):
+        assert views == S.random_views(len(cams), K, 8, t), t
+        assert (K, permille) == sch.at(t, float(np.mean(means)), e_init), t
+    assert torch.isfinite(tr.params).all() and not torch.equal(tr.params, p0)
+
+
 def test_schedule_driven_training_with_density_control(B):
     """The loop with density control every four steps from step 4 to 10 and
     final pruning at step 8 only: the Gaussian count changes only there, and

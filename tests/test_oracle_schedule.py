@@ -72,3 +72,27 @@ def test_stack_refills_and_draws_without_replacement():
     # step draws from the four left; third finds one view left and refills
     assert seen[0][0] == 6 and set(seen[0]).isdisjoint(seen[1])
     assert seen[2][0] == 6
+
+
+def test_random_view_sampling_is_uniform_without_replacement():
+    """Random view sampling: K distinct views per step; over many steps each
+    view is drawn with frequency K/V, and on V = 4, K = 2 each of the six
+    unordered pairs with frequency 1/6 (chi-squared, seeded)."""
+    from scipy.stats import chi2
+    V, K, T = 30, 7, 3000
+    counts = np.zeros(V)
+    for t in range(T):
+        v = S.random_views(V, K, seed=9, t=t)
+        assert len(v) == K == len(set(v)) and all(0 <= x < V for x in v)
+        counts[v] += 1
+    exp = T * K / V
+    stat = ((counts - exp) ** 2 / exp).sum()
+    assert stat < chi2.ppf(0.999, V - 1)
+    pairs = {}
+    for t in range(6000):
+        a, b = sorted(S.random_views(4, 2, seed=10, t=t))
+        pairs[(a, b)] = pairs.get((a, b), 0) + 1
+    assert len(pairs) == 6
+    c = np.array(list(pairs.values()), dtype=float)
+    assert ((c - 1000) ** 2 / 1000).sum() < chi2.ppf(0.999, 5)
+    assert sorted(S.random_views(5, 9, seed=1, t=0)) == list(range(5))

@@ -59,3 +59,9 @@ def test_view_sets_at_the_edges():
         vh, sh = H.pick_views([], means, c, d, K, 1.0, 1.0, seed=2, t=1)
         assert vo == vh and so == sh and vh[0] == 0 and len(vh) == min(K, 3)
     assert H.pick_views([0], [0.5], [[0, 0, 0]], [[0, 0, 1]], 1, 1.0, 1.0, 0, 0) == ([0], [])
+
+
+def test_random_view_sampling_equals_the_oracle():
+    for t in range(300):
+        for V, K in ((150, 3), (150, 10), (7, 7), (4, 9)):
+            assert H.pick_views_random(V, K, 5, t) == S.random_views(V, K, 5, t)
