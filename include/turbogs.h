@@ -173,6 +173,21 @@ int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t
                    int32_t* tile_off, uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
                    size_t ws_bytes, void* stream);
 
+/* tgs_sample for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same sampling, outputs and errors, with the workspace taken from a
+ * static device array of the library (9 bytes per tile for at most
+ * TGS_SAMPLE_NOALLOC_MAX_TILES tiles, 576 KiB, held on each GPU the library
+ * runs on until the process ends) instead of a caller buffer.  Calls no
+ * allocating routine.  Images of more tiles are rejected with
+ * TGS_ERR_INVALID before anything is queued.  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (several streams or host
+ * threads) race and must be ordered by the caller. */
+#define TGS_SAMPLE_NOALLOC_MAX_TILES 65536 /* e.g. 4096 x 4096 pixels */
+int32_t tgs_sample_noalloc(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
+                           const tgs_sample_params* sp, const float* tile_pred, int32_t* valid_tiles,
+                           int32_t* tile_off, uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* stream);
+
 /* Tile x depth binning, sort and per-tile ranges (the depth-ordered
  * per-tile Gaussian lists of Eq. alpha_comp, in the tile order of Sec. 3.6).
  * A (Gaussian, tile) pair is listed when the tile lies in the Gaussian's

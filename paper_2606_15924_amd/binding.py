@@ -78,6 +78,8 @@ PROTOTYPES = {
     "tgs_last_error": (ctypes.c_char_p, []),
     "tgs_pixels_per_tile": (_I32, [_I32]),
     "tgs_check_finite": (_I32, [_P, _I64, _P, _P]),
+    "tgs_sample_noalloc": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(tgs_sample_params), _P, _P, _P, _P, _P, _P,
+                                  _P]),
     "tgs_render_bwd_det_workspace_size": (_SZ, [_I64, _I32, _I32]),
     "tgs_render_bwd_deterministic": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
                                             ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P, _P,
@@ -298,6 +300,14 @@ def tgs_sample(E, A, height, width, sp: tgs_sample_params, valid_tiles, tile_off
     _check(lib().tgs_sample(_ptr(E), _ptr(A), height, width, ctypes.byref(sp), _ptr(tile_pred), _ptr(valid_tiles),
                             _ptr(tile_off), _ptr(pix), _ptr(tile_slot), _ptr(totals), _ptr(ws),
                             ws.numel() * ws.element_size(), _stream()), "tgs_sample")
+
+
+def tgs_sample_noalloc(E, A, height, width, sp: tgs_sample_params, valid_tiles, tile_off, pix, tile_slot, totals,
+                       tile_pred=None):
+    """tgs_sample without a workspace (the library's static per-GPU scratch)."""
+    _check(lib().tgs_sample_noalloc(_ptr(E), _ptr(A), height, width, ctypes.byref(sp), _ptr(tile_pred),
+                                    _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), _ptr(tile_slot), _ptr(totals),
+                                    _stream()), "tgs_sample_noalloc")
 
 
 def tgs_bin_sort_workspace_size(n: int, capacity: int, n_tiles: int) -> int:

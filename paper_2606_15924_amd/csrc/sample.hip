@@ -13,6 +13,8 @@
 // (ascending local index) whose running weight exceeds r.  Each lane owns four
 // consecutive local indices, so lane order is index order and a wave prefix
 // sum locates a draw.
+#include <mutex>
+
 #include "scan.h"
 
 namespace tgs {
@@ -421,10 +423,10 @@ extern "C" size_t tgs_sample_workspace_size(int32_t height, int32_t width) {
   return align_up(n_t * sizeof(uint64_t), 256) + align_up(n_t, 256);
 }
 
-extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
-                              const tgs_sample_params* sp, const float* tile_pred, int32_t* valid_tiles,
-                              int32_t* tile_off, uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
-                              size_t ws_bytes, void* stream) {
+static int32_t sample_impl(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
+                           const tgs_sample_params* sp, const float* tile_pred, int32_t* valid_tiles,
+                           int32_t* tile_off, uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
+                           size_t ws_bytes, void* stream) {
   TGS_REQUIRE(height > 0 && width > 0, "tgs_sample: bad image size %d x %d", width, height);
   TGS_REQUIRE(sp != nullptr, "tgs_sample: null params");
   TGS_REQUIRE(sp->n_pix >= 1 && sp->n_pix <= kTilePixels, "tgs_sample: n_pix %d not in 1..256",
@@ -460,6 +462,65 @@ extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t heig
                        n_st, sp->n_pix, sp->hard_permille, sp->stable_permille, sp->seed, sp->step,
                        (uint64_t)sp->view, valid_tiles, tile_off, pix);
   return hip_status("tgs_sample");
+}
+
+extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
+                              const tgs_sample_params* sp, const float* tile_pred, int32_t* valid_tiles,
+                              int32_t* tile_off, uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
+                              size_t ws_bytes, void* stream) {
+  return sample_impl(E, A, height, width, sp, tile_pred, valid_tiles, tile_off, pix, tile_slot, totals, ws,
+                     ws_bytes, stream);
+}
+
+// ------------------------------------------------------------------ sampling without a workspace
+// The sampler's scratch (tile weights and chosen flags, 9 bytes per tile)
+// in a file-scope device array, for callers that cannot allocate.  Each
+// GPU holds its own copy until the process ends; host code uses only the
+// device address that hipGetSymbolAddress returns for the current device,
+// never the array's name.  Every kernel of a call writes the scratch it
+// reads, so nothing needs clearing between calls; calls that overlap on
+// one GPU share it and race.
+constexpr int kNoAllocMaxTiles = TGS_SAMPLE_NOALLOC_MAX_TILES;
+constexpr size_t kNoAllocScratchBytes =
+    ((size_t)kNoAllocMaxTiles * sizeof(uint64_t) + 255) / 256 * 256 + ((size_t)kNoAllocMaxTiles + 255) / 256 * 256;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of the scratch array, looked up on the
+// first call on that device.
+static void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+extern "C" int32_t tgs_sample_noalloc(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
+                                      const tgs_sample_params* sp, const float* tile_pred, int32_t* valid_tiles,
+                                      int32_t* tile_off, uint8_t* pix, int32_t* tile_slot, int64_t* totals,
+                                      void* stream) {
+  TGS_REQUIRE(height > 0 && width > 0, "tgs_sample_noalloc: bad image size %d x %d", width, height);
+  const int64_t n_t = ceil_div(width, kTile) * ceil_div(height, kTile);
+  TGS_REQUIRE(n_t <= kNoAllocMaxTiles, "tgs_sample_noalloc: %lld tiles exceed the static scratch of %d tiles",
+              (long long)n_t, kNoAllocMaxTiles);
+  void* ws = scratch_address();
+  if (ws == nullptr) {
+    set_error("tgs_sample_noalloc: no device address for the static scratch");
+    return TGS_ERR_HIP;
+  }
+  return sample_impl(E, A, height, width, sp, tile_pred, valid_tiles, tile_off, pix, tile_slot, totals, ws,
+                     kNoAllocScratchBytes, stream);
 }
 
 // ------------------------------------------------------------------ per-view mean error
