@@ -404,10 +404,10 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K* __res
 // One workgroup per digit: exclusive prefix of the digit's per-block counts
 // (a contiguous row of the digit-major table) and the digit's total.
 __global__ void __launch_bounds__(1024) digit_scan_kernel(const uint32_t* __restrict__ hist, int nblocks,
-                                                          uint32_t* __restrict__ hoffs,
+                                                          int stride, uint32_t* __restrict__ hoffs,
                                                           uint32_t* __restrict__ dtot) {
   __shared__ uint32_t lds[1024 / kWave];
-  const int64_t row = (int64_t)blockIdx.x * nblocks;
+  const int64_t row = (int64_t)blockIdx.x * stride;
   uint32_t carry = 0;
   for (int b0 = 0; b0 < nblocks; b0 += 1024) {
     const int b = b0 + (int)threadIdx.x;
@@ -511,7 +511,8 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
       if (dst >= n) continue;  // never taken for a consistent table; keeps every write in bounds
       ((K*)o.keys)[dst] = kk;
       if (kFinal) {
-        const uint32_t g = (uint32_t)(kk & (((K)1 << o.id_bits) - 1));
+        // the Gaussian id: the payload, or the low key bits when it rides in the key
+        const uint32_t g = kVals ? s_vals[lp] : (uint32_t)(kk & (((K)1 << o.id_bits) - 1));
         o.vals[dst] = g;
         if (o.keys64 != nullptr)
           o.keys64[dst] = ((uint64_t)(kk >> o.id_bits) << 32) | (uint64_t)__float_as_uint(o.depth[g]);
@@ -523,13 +524,15 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
 }
 
 // ------------------------------------------------------------------ depth sort
-// The depth sort (four 8-bit passes over n keys with ids) takes two kernels
-// per pass: the per-block digit counts (the table hist[digit][block], row
-// stride hstride), then the scatter, in which each block derives its output
-// offsets from the table itself: for its digit d, a thread adds up the
-// counts of the earlier blocks and of all blocks (no separate scan of the
-// table).  The last pass writes the ids and gathers each Gaussian's
-// rectangle and pair count into depth order instead of writing keys.
+// The depth sort (four 8-bit passes over n keys with ids) takes three
+// kernels per pass: the per-block digit counts (the table hist[digit][block],
+// row stride hstride), one workgroup per digit scanning its row (each
+// block's exclusive offset within the digit, and the digit's total), then
+// the scatter.  (Letting every scatter block add up its offsets from the
+// raw table instead reads the whole table once per block, which grows with
+// the square of the block count: 70-100 us per pass at 1.5M Gaussians.)
+// The last pass writes the ids and gathers each Gaussian's rectangle and
+// pair count into depth order instead of writing keys.
 static_assert(kDepthBlockKeys == kSortThreads * kDepthItems && kDepthDigits == kSortThreads,
               "a depth pass block: one thread per digit");
 
@@ -551,7 +554,8 @@ template <bool kLast>
 __global__ void __launch_bounds__(kSortThreads) depth_pass_kernel(const uint32_t* __restrict__ keys_in,
                                                                   const uint32_t* __restrict__ vals_in, uint32_t n,
                                                                   int shift, int hstride,
-                                                                  const uint32_t* __restrict__ hist, DepthPassOut o) {
+                                                                  const uint32_t* __restrict__ hoffs,
+                                                                  const uint32_t* __restrict__ dtot, DepthPassOut o) {
   constexpr int kItems = kDepthItems, kBlockKeys = kDepthBlockKeys, kDigits = kDepthDigits;
   __shared__ uint32_t s_cnt[kSortWaves][kDigits];  // per-wave digit counts, then block-local offsets
   __shared__ uint32_t s_gbase[kDigits];            // global position of block-local position 0 of the digit
@@ -561,26 +565,8 @@ __global__ void __launch_bounds__(kSortThreads) depth_pass_kernel(const uint32_t
   __shared__ uint64_t s_mask[kSortWaves][kDigits];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   for (int i = tid; i < kSortWaves * kDigits; i += kSortThreads) (&s_cnt[0][0])[i] = 0;
-  // counts of digit tid in the earlier blocks and in all blocks (rows padded to 4 with zeros)
-  uint32_t before = 0, all_d = 0;
-  {
-    const uint4* row = (const uint4*)(hist + (int64_t)tid * hstride);
-    const int b_me = (int)blockIdx.x, nq = hstride / 4;
-    auto add = [&](uint4 c, int b) {
-      all_d += c.x + c.y + c.z + c.w;
-      before += (b < b_me ? c.x : 0u) + (b + 1 < b_me ? c.y : 0u) + (b + 2 < b_me ? c.z : 0u) +
-                (b + 3 < b_me ? c.w : 0u);
-    };
-    int q = 0;
-    for (; q + 8 <= nq; q += 8) {  // eight independent loads in flight
-      uint4 c[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) c[j] = row[q + j];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) add(c[j], 4 * (q + j));
-    }
-    for (; q < nq; ++q) add(row[q], 4 * q);
-  }
+  // keys of digit tid in the earlier blocks, and in all blocks
+  const uint32_t before = hoffs[(int64_t)tid * hstride + blockIdx.x], all_d = dtot[tid];
   const int64_t blk0 = (int64_t)blockIdx.x * kBlockKeys;
   const int64_t wbase = blk0 + (int64_t)wave * kWave * kItems;
   uint32_t key[kItems], val[kItems];
@@ -657,7 +643,7 @@ static void radix_pass(const K* keys, const uint32_t* vals, uint32_t n, int shif
   if (!hist_ready)
     hipLaunchKernelGGL((radix_hist_kernel<K, kBits, kItems>), dim3(nblocks), dim3(kSortThreads), 0, s, keys, n,
                        shift, nblocks, hist);
-  hipLaunchKernelGGL(digit_scan_kernel, dim3(1 << kBits), dim3(1024), 0, s, hist, nblocks, hoffs, dtot);
+  hipLaunchKernelGGL(digit_scan_kernel, dim3(1 << kBits), dim3(1024), 0, s, hist, nblocks, nblocks, hoffs, dtot);
   hipLaunchKernelGGL((radix_scatter_kernel<K, kVals, kFinal, kBits, kItems>), dim3(nblocks), dim3(kSortThreads),
                      0, s, keys, vals, n, shift, nblocks, hoffs, dtot, o);
 }
@@ -708,7 +694,7 @@ template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ off, const uint32_t* __restrict__ ids_sorted,
     int64_t n, const float4* __restrict__ splat, const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t,
-    int id_bits, double tau, uint32_t total, K* __restrict__ keys) {
+    int id_bits, double tau, uint32_t total, K* __restrict__ keys, uint32_t* __restrict__ pay) {
   __shared__ RowBatch rb;
   const int lane = lane_id();
   const int64_t b0 = (int64_t)blockIdx.x * kEmitBatch;
@@ -759,7 +745,12 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
       if (pos < total) {  // always (same spans as the count kernel); the bound is a safeguard
         uint32_t tile = (uint32_t)(trow + lo + (int)k);
         if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
-        keys[pos] = ((K)tile << id_bits) | (K)gid;
+        if (pay != nullptr) {  // the id as a separate payload, the key is the tile alone
+          keys[pos] = (K)tile;
+          pay[pos] = gid;
+        } else {
+          keys[pos] = ((K)tile << id_bits) | (K)gid;
+        }
       }
     }
     __syncthreads();  // the round's mark reads before the next round's writes
@@ -770,6 +761,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
 struct SortWs {
   unsigned long long* scalars;  // [2][TGS_COUNTER_SLOTS] partial totals: valid pairs, pairs
   uint32_t* dhist[4];           // [256][hstride] per-block digit counts of each depth pass
+  uint32_t* dhoffs;             // [256][hstride] their exclusive prefix per digit (the pass being run)
+  uint32_t* ddtot;              // [256] digit totals of the pass being run
   uint32_t* zeroed;             // scalars and dhist: one region, cleared at the start
   int64_t zeroed_words;         // its size in 32-bit words
   int hstride;                  // row stride of the depth tables
@@ -783,7 +776,8 @@ struct SortWs {
   uint32_t* partials;           // scan block sums, digit totals
   uint32_t* hist;               // [256 * max_blocks]
   uint32_t* hoffs;              // [256 * max_blocks]
-  void* pkeys[2];               // [capacity] pair keys (u32 or u64), ping-pong
+  void* pkeys[2];               // [capacity] x 8 bytes each: pair keys (u32), or u16/u32 tile keys then u32 ids
+  int64_t cap;                  // pairs each ping-pong buffer holds
   size_t bytes;
 };
 
@@ -809,6 +803,8 @@ static SortWs layout(void* ws, int64_t n, int64_t capacity) {
   w.zeroed = (uint32_t*)take(sizeof(uint32_t) * w.zeroed_words);
   w.scalars = (unsigned long long*)w.zeroed;
   for (int k = 0; k < 4; ++k) w.dhist[k] = w.zeroed ? w.zeroed + scalar_words + k * table_words : nullptr;
+  w.dhoffs = (uint32_t*)take(sizeof(uint32_t) * table_words);
+  w.ddtot = (uint32_t*)take(sizeof(uint32_t) * kDepthDigits);
   w.emit_cnt = (uint32_t*)take(sizeof(uint32_t) * nn);
   w.rect_sorted = (int4*)take(sizeof(int4) * nn);
   w.cnt_sorted = (uint32_t*)take(sizeof(uint32_t) * nn);
@@ -821,7 +817,9 @@ static SortWs layout(void* ws, int64_t n, int64_t capacity) {
   w.partials = (uint32_t*)take(sizeof(uint32_t) * part_n);
   w.hist = (uint32_t*)take(sizeof(uint32_t) * hist_n);
   w.hoffs = (uint32_t*)take(sizeof(uint32_t) * hist_n);
-  for (int k = 0; k < 2; ++k) w.pkeys[k] = take(sizeof(uint64_t) * cap);
+  w.cap = cap;
+  // 8 bytes per pair: a u32 key, or (16-byte aligned halves) a u16/u32 tile key and a u32 id
+  for (int k = 0; k < 2; ++k) w.pkeys[k] = take(align_up(sizeof(uint32_t) * cap, 256) + sizeof(uint32_t) * cap);
   w.bytes = o;
   return w;
 }
@@ -842,12 +840,14 @@ static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_
     // rows of hstride entries (the padding stays zero from the start-of-call fill)
     hipLaunchKernelGGL((radix_hist_kernel<uint32_t, 8, kDepthItems>), dim3(nb), dim3(kSortThreads), 0, s,
                        w.dkeys[cur], n, 8 * p, w.hstride, w.dhist[p]);
+    hipLaunchKernelGGL(digit_scan_kernel, dim3(kDepthDigits), dim3(1024), 0, s, w.dhist[p], (int)nb, w.hstride,
+                       w.dhoffs, w.ddtot);
     DepthPassOut o{};
     if (p < 3) {
       o.keys = w.dkeys[cur ^ 1];
       o.vals = w.dvals[cur ^ 1];
       hipLaunchKernelGGL(depth_pass_kernel<false>, dim3(nb), dim3(kSortThreads), 0, s, w.dkeys[cur], w.dvals[cur],
-                         n, 8 * p, w.hstride, w.dhist[p], o);
+                         n, 8 * p, w.hstride, w.dhoffs, w.ddtot, o);
     } else {
       o.ids_sorted = w.ids_sorted;
       o.rect = rect;
@@ -857,35 +857,46 @@ static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_
       o.tiles_x = tiles_x;
       o.tiles_y = tiles_y;
       hipLaunchKernelGGL(depth_pass_kernel<true>, dim3(nb), dim3(kSortThreads), 0, s, w.dkeys[cur], w.dvals[cur],
-                         n, 8 * p, w.hstride, w.dhist[p], o);
+                         n, 8 * p, w.hstride, w.dhoffs, w.ddtot, o);
     }
     cur ^= 1;
   }
 }
 
-template <typename K>
+// kPay false: the key is (tile << id_bits) | id (32 bits when they fit).
+// kPay true: the key is the tile alone (16 bits) and the id travels as a
+// 32-bit payload; used when tile and id bits together exceed 32, where a
+// 64-bit key would move 16 bytes per pair and pass instead of 12.
+template <typename K, bool kPay>
 static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t total, const float4* splat,
                        const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits, int tbits, double tau,
                        const float* depth, uint32_t* vals, uint64_t* keys64, uint32_t* ranges, hipStream_t s) {
+  // each ping-pong buffer (8 bytes per pair of capacity) holds the keys and, after them, the payload
   K* kb[2] = {(K*)w.pkeys[0], (K*)w.pkeys[1]};
+  uint32_t* pb[2] = {nullptr, nullptr};
+  if (kPay)
+    for (int k = 0; k < 2; ++k) pb[k] = (uint32_t*)((char*)w.pkeys[k] + align_up(sizeof(K) * (size_t)w.cap, 256));
+  const int key_id_bits = kPay ? 0 : id_bits;
   hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(n, kEmitBatch)), dim3(kEmitThreads), 0, s,
-                     w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, id_bits, tau, total, kb[0]);
+                     w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, key_id_bits, tau, total, kb[0],
+                     pb[0]);
   const int passes = pass_count(tbits);
-  int cur = 0, shift = id_bits;
+  int cur = 0, shift = key_id_bits;
   for (int p = 0; p < passes; ++p) {
     const int b = pass_bits(tbits, p);
-    const ScatterOut o = {kb[cur ^ 1], vals, id_bits, depth, keys64};
+    // non-final passes carry the payload to the other buffer; the last writes the ids
+    const ScatterOut o = {kb[cur ^ 1], p == passes - 1 ? vals : pb[cur ^ 1], key_id_bits, depth, keys64};
     if (p == passes - 1)
-      radix_pass_bits<K, false, true, kPairItems>(b, kb[cur], nullptr, total, shift, false, w.hist, w.hoffs,
-                                                  w.partials, o, s);
+      radix_pass_bits<K, kPay, true, kPairItems>(b, kb[cur], pb[cur], total, shift, false, w.hist, w.hoffs,
+                                                 w.partials, o, s);
     else
-      radix_pass_bits<K, false, false, kPairItems>(b, kb[cur], nullptr, total, shift, false, w.hist, w.hoffs,
-                                                   w.partials, o, s);
+      radix_pass_bits<K, kPay, false, kPairItems>(b, kb[cur], pb[cur], total, shift, false, w.hist, w.hoffs,
+                                                  w.partials, o, s);
     cur ^= 1;
     shift += b;
   }
   hipLaunchKernelGGL((ranges_kernel<K>), dim3((unsigned)ceil_div(total, kRangeBlock)), dim3(256), 0, s,
-                     kb[cur], total, id_bits, n_t, (uint2*)ranges);
+                     kb[cur], total, key_id_bits, n_t, (uint2*)ranges);
 }
 
 }  // namespace tgs
@@ -1000,10 +1011,13 @@ extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const f
   const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
   const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
   if (id_bits + tbits <= 32)
-    sort_pairs<uint32_t>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits, tbits, tau,
-                         depth, vals, keys, ranges, s);
+    sort_pairs<uint32_t, false>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+                                tbits, tau, depth, vals, keys, ranges, s);
+  else if (tbits <= 16)
+    sort_pairs<uint16_t, true>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+                               tbits, tau, depth, vals, keys, ranges, s);
   else
-    sort_pairs<uint64_t>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits, tbits, tau,
-                         depth, vals, keys, ranges, s);
+    sort_pairs<uint32_t, true>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+                               tbits, tau, depth, vals, keys, ranges, s);
   return hip_status("tgs_bin_sort");
 }

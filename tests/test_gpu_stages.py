@@ -86,6 +86,33 @@ def test_project_parity(B, case):
 
 
 # ------------------------------------------------------------------ binning + sort
+def test_bin_sort_wide_tile_ids_with_id_payload(B):
+    """A 4100x4100 view (66,049 tiles: 17 tile bits) of 50k Gaussians (16 id
+    bits): tile and id no longer fit one 32-bit key, so the pair sort keys on
+    the tile and carries the id as a payload.  Keys, ids and ranges against
+    the oracle's rectangle lists as in the other binning tests."""
+    p = synth.gaussians(50000, 41, logscale_mean=-5.0)
+    W = H = 4100
+    cam = synth.look_at((1.9, -1.6, 1.5), fx=300.0 * W / 256, fy=300.0 * W / 256, width=W, height=H)
+    pr = project.project(p, cam, RP)
+    TX, TY = pr["TX"], pr["TY"]
+    assert TX * TY == 66049
+    rec = splat_record(pr)
+    q = splat_as_oracle(pr, rec)
+    rect_area = (pr["rect"][2] - pr["rect"][0]) * (pr["rect"][3] - pr["rect"][1])
+    cap = int(rect_area[pr["visible"]].sum()) + 17
+    n = p.shape[1]
+    K = torch.empty(cap, dtype=torch.int64, device="cuda")
+    V = torch.empty(cap, dtype=torch.int32, device="cuda")
+    R = torch.empty((TX * TY, 2), dtype=torch.int32, device="cuda")
+    ws = torch.empty(B.tgs_bin_sort_workspace_size(n, cap, TX * TY), dtype=torch.uint8, device="cuda")
+    npairs = B.tgs_bin_sort(dev(pr["rect"].T.astype(np.int32)), dev(rec), dev(pr["depth32"]), n, None, TX, TY,
+                            1.0 / 255.0, K, V, cap, R, None, ws)
+    info = check_pair_lists(host(V)[:npairs].view(np.uint32), host(R), npairs, q, keys=host(K),
+                            max_dropped_checked=100000)
+    assert npairs > 100000 and info["dropped"] > 0
+
+
 @pytest.mark.parametrize("case", ["c1_all", "c1_sampled", "ragged"])
 def test_bin_sort_lists_against_rectangle_lists(B, case):
     """The GPU's per-tile lists against the oracle's rectangle lists: an
