@@ -43,6 +43,15 @@ FULL_RATE = 200              # per-mille of each tile's pixels (51 of 256)
 FULL_K = (3, 10)             # views per step (the schedule's K_min and K_max)
 HEADLINE_K = 3
 
+# large scene: 5M Gaussians in a 50-unit corridor, 400 cameras 1920x1080 along it
+LARGE_N = 5_000_000
+LARGE_VIEWS = 400
+LARGE_W, LARGE_H = 1920, 1080
+LARGE_RATE = 200             # per-mille of each selected tile's pixels (51 of 256)
+LARGE_TILE_FRAC = 0.75       # tiles drawn per view by the learned tile priority: 0.75 x 20% = 15% of the pixels
+LARGE_K = 3
+LARGE_STEPS = 3000
+
 # rasterizer scaling
 N_GAUSS = 300_000
 WIDTH, HEIGHT = 1296, 840
@@ -466,6 +475,102 @@ def tile_init_params():
     return p
 
 
+# ------------------------------------------------------------------ large scene
+def large_scene(dev, steps):
+    """Sparse training on the large scene: 5M Gaussians in a corridor, 400
+    cameras 1920x1080 along a 50-unit trajectory, targets rendered densely
+    from a seed-perturbed copy plus N(0, 0.01) noise.  Each step trains K = 3
+    views picked by the anchor and geometry-aware companion draws from the
+    views' mean errors (refreshed after every step); each view samples three
+    quarters of its tiles by the learned tile priority at 20% of their
+    pixels (15% of the image) and the priority network trains online; the
+    backward accumulates the density statistics, and density control runs
+    every 100 steps from step 200 to 2500 (densify the top 2% of the scores
+    that pass the gradient gates, prune the bottom 5% every 500 steps).
+    Reports step time p50/p99 over the training steps (density steps
+    timed apart), the Gaussian count and the peak device memory."""
+    import math
+
+    import torch
+
+    import synth
+    from paper_2606_15924_amd import binding as B
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer, ViewBuffers
+    from paper_2606_15924_amd.schedule import DensityPlan, camera_pose, density_step, pick_views, scene_extent, \
+        view_errors
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    p = synth.corridor_gaussians(LARGE_N, synth.SEED_SCENE)
+    cams = synth.trajectory_cameras(LARGE_VIEWS, width=LARGE_W, height=LARGE_H)
+    P_true = torch.from_numpy(synth.perturb(p, synth.SEED_PERTURB)).to(dev)
+    rp = B.raster_params()
+    vb = ViewBuffers(LARGE_N, LARGE_W, LARGE_H, None, -1, dev)
+    gen = torch.Generator(device=dev)
+    gts = []
+    for k, cam in enumerate(cams):
+        vb.project(P_true, B.camera(cam), rp)
+        vb.bin_sort(alpha_min=rp.alpha_min)
+        vb.render_fwd(rp)
+        gen.manual_seed(synth.SEED_NOISE * 1000 + k)
+        img = vb.out[: LARGE_W * LARGE_H, :3].T.reshape(3, LARGE_H, LARGE_W)
+        gts.append((img + 0.01 * torch.randn(img.shape, generator=gen, device=dev)).contiguous())
+    del P_true, vb
+    n_t = ((LARGE_W + 15) // 16) * ((LARGE_H + 15) // 16)
+    cfg = StepConfig(rate_permille=LARGE_RATE, n_tiles_sel=int(LARGE_TILE_FRAC * n_t), learned_tiles=True,
+                     density_stats=True)
+    E = [torch.zeros((LARGE_H, LARGE_W), dtype=torch.int16, device=dev) for _ in cams]
+    A = [torch.zeros((LARGE_H, LARGE_W), dtype=torch.int16, device=dev) for _ in cams]
+    tr = Trainer(torch.from_numpy(p).to(dev), cams, gts, cfg, E=E, A=A)
+    tr.init_error_maps(range(len(cams)))
+    plan = DensityPlan(t_from=200, t_until=2500, every=100, prune_every=500, eta_topk=0.98, eta_final=0.95)
+    poses = [camera_pose(c) for c in tr.cams]
+    centres, dirs = [q[0] for q in poses], [q[1] for q in poses]
+    pixels = LARGE_W * LARGE_H
+    means = view_errors(tr.E, pixels, dev)
+    extent = scene_extent(tr.cams)
+    stack = list(range(len(cams)))
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    dens = []
+    n_start = tr.n
+    t0 = time.perf_counter()
+    ev[0].record()
+    for t in range(1, steps + 1):
+        views, stack = pick_views(stack, means, centres, dirs, LARGE_K, 0.05, 1.0, synth.SEED_VIEWS, t)
+        tr.step(views)
+        ev[t].record()
+        if plan.t_from <= t <= plan.t_until and t % plan.every == 0:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            density_step(tr, t, plan.t_until, plan, extent)
+            b.record()
+            dens.append((a, b))
+        means = view_errors(tr.E, pixels, dev, views, means)
+        if t % 500 == 0:
+            log(f"  large scene step {t}: {tr.n} Gaussians")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dens_ms = [a.elapsed_time(b) for a, b in dens]
+    # a step's span ends at its own event; a density step in between is timed apart
+    per = np.array([ev[t - 1].elapsed_time(ev[t]) for t in range(1, steps + 1)])
+    dens_steps = [t for t in range(1, steps + 1) if plan.t_from <= t - 1 <= plan.t_until and (t - 1) % plan.every == 0]
+    train = np.delete(per, [t - 1 for t in dens_steps])
+    peak = torch.cuda.max_memory_allocated()
+    res = {"workload": f"{LARGE_N} Gaussians in a 50-unit corridor, {LARGE_VIEWS} cameras {LARGE_W}x{LARGE_H} "
+                       f"along it, K={LARGE_K} views per step, {int(LARGE_TILE_FRAC * 100)}% of tiles by the "
+                       f"learned priority at {LARGE_RATE / 10:g}% of their pixels, density control",
+           "steps": steps, "wall_s": round(wall, 2),
+           "step_ms": {"p50": round(float(np.percentile(train, 50)), 4),
+                       "p99": round(float(np.percentile(train, 99)), 4),
+                       "mean": round(float(train.mean()), 4)},
+           "density_steps": len(dens_ms), "density_ms_mean": round(float(np.mean(dens_ms)), 4) if dens_ms else None,
+           "gaussians_start": n_start, "gaussians_end": tr.n,
+           "peak_hbm_gb": round(peak / 2 ** 30, 2)}
+    del tr, gts, E, A
+    torch.cuda.empty_cache()
+    return res
+
+
 # ------------------------------------------------------------------ oracle on the host
 _CPU = {}   # the oracle baseline's shared inputs (inherited by forked workers)
 
@@ -701,6 +806,9 @@ def main():
     ap.add_argument("--no-tile", action="store_true", help="skip the learned tile-priority measurement")
     ap.add_argument("--no-density", action="store_true", help="skip the density-control measurement")
     ap.add_argument("--only-headline", action="store_true", help="the K=3 sparse full step alone (profiling)")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-scene run")
+    ap.add_argument("--only-large", action="store_true", help="the large-scene run alone (prints its record)")
+    ap.add_argument("--large-steps", type=int, default=LARGE_STEPS, help="timed steps of the large-scene run")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -724,6 +832,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.only_large:
+        print(json.dumps({"large_scene": large_scene(dev, args.large_steps)}), flush=True)
+        return
     if args.only_headline:
         global FULL_K
         FULL_K = (HEADLINE_K,)
@@ -740,7 +851,7 @@ def main():
             d["sparse_vs_dense_speedup"] = round(d["dense"]["ms_per_step"] / d["sparse"]["ms_per_step"], 3)
 
     scaling = None
-    dens = tile = psnr = None
+    dens = tile = psnr = large = None
     if not args.only_headline:
         p, cam, gt = make_workload(dev)
         if not args.no_sweep:
@@ -771,6 +882,9 @@ def main():
             tile = tile_priority(dev)
         if not args.no_psnr:
             psnr = matched_psnr(dev)
+        if not args.no_large:
+            log(f"large scene: {args.large_steps} steps")
+            large = large_scene(dev, args.large_steps)
 
     cpu = None
     if not args.no_cpu:
@@ -807,6 +921,7 @@ def main():
         "matched_psnr": psnr,
         "tile_priority": tile,
         "density_control": dens,
+        "large_scene": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -16,7 +16,9 @@
  *     matching *_workspace_size function.  Struct arguments (camera and
  *     parameter records) are host pointers read during the call.
  *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
- *     null stream).  Only tgs_bin_sort synchronises (it reads the pair count).
+ *     null stream).  Only tgs_bin_sort synchronises (it returns the pair
+ *     count; tgs_bin_sort_async writes it to device memory instead), and the
+ *     density-control count call that returns sizes.
  *   - Return value: TGS_OK, or a negative error (TGS_ERR_INVALID for a null
  *     pointer or a bad size, TGS_ERR_HIP for a failed launch/runtime call) or
  *     TGS_ERR_CAPACITY (an output is too small; the required count is written
@@ -135,7 +137,10 @@ int32_t tgs_sample_tile_count(int32_t height, int32_t width, const tgs_sample_pa
  * splat whose footprint and opacity give alpha; colour from SH coefficients).
  *   params   [59][n] float, read
  *   splat    [n][12] float, written: floor(px), floor(py), px - floor(px),
- *            py - floor(py), conic a, b, c (Q = [[a, b], [b, c]]), opacity,
+ *            py - floor(py), conic Q = [[a, b], [b, c]] in its LDL^T form
+ *            a, beta = b / a, delta = det Q / a (so d^T Q d =
+ *            a (dx + beta dy)^2 + delta dy^2, two non-negative terms, which
+ *            an FP32 evaluation takes without cancellation), opacity,
  *            r, g, b, depth.  The centre is in pixel-index space (pixel
  *            (i, j) sits at offset (i, j) - centre).
  *   depth    [n] float (camera-space z, FP32)
@@ -213,20 +218,34 @@ int32_t tgs_sample_noalloc(const uint16_t* E, const uint16_t* A, int32_t height,
  *                composited at a sample)
  *   n_pairs      host out: number of pairs in valid tiles
  * capacity must hold every listed tile (valid or not) of every Gaussian
- * that has a pair in a valid tile; when it does not, the call returns
- * TGS_ERR_CAPACITY with that count in *n_pairs and the outputs are
- * unspecified.  The host waits once, for the count totals (a kernel writes
- * them into mapped pinned host memory right after the count and an event
- * follows; the depth sort is already queued behind it), to size the pair
- * sort; the call returns with the rest queued on the stream.  Uses a small
- * pinned host buffer per host thread and device, kept until the process
- * ends. */
+ * that has a pair in a valid tile; when it does not, the lists come out
+ * empty (every range [0, 0); vals and keys untouched) and the call returns
+ * TGS_ERR_CAPACITY with that count in *n_pairs.  Every kernel's grid is
+ * sized by the capacity and reads the pair count on the device, so the
+ * work is queued without waiting; this call then waits for the stream once
+ * (a copy of the two counts into host memory) to return them.  The library
+ * keeps no host or device memory of its own for it. */
 size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32_t n_tiles);
 int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const float* depth, int64_t n,
                      const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
                      uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges,
                      uint8_t* touched, int64_t* n_pairs, void* ws, size_t ws_bytes,
                      void* stream);
+
+/* tgs_bin_sort without any host synchronisation: the same lists, with the
+ * counts written to device memory instead of returned.
+ *   counts  [2] int64, device, 8-byte aligned: counts[0] = pairs in valid
+ *           tiles (the lists' length), counts[1] = every listed tile of the
+ *           Gaussians that have a pair, the capacity the call needs.  When
+ *           counts[1] > capacity the lists are empty, as above; the caller
+ *           finds out when it next reads counts (after its own
+ *           synchronisation), and a step rendered from such lists must be
+ *           redone with a larger capacity.
+ * Argument errors are still reported before anything is queued. */
+int32_t tgs_bin_sort_async(const int32_t* rect, const float* splat, const float* depth, int64_t n,
+                           const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
+                           uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges,
+                           uint8_t* touched, int64_t* counts, void* ws, size_t ws_bytes, void* stream);
 
 /* Front-to-back compositing of the sampled pixels of the sampled tiles
  * (Eq. alpha_comp; Sec. 3.6 tile-parallel forward with prefix-sum pixel
@@ -326,7 +345,9 @@ int32_t tgs_loss(const float* out, const float* gt, int32_t height, int32_t widt
 /* Error-map EMA at sampled pixels (Eq. ema_err) and age update (Eq.
  * age_update) of one selected view.  E is half bits, blended in FP32 as
  * fl(fl(fl(1 - beta) E) + fl(beta e)) and rounded to nearest even; A is
- * reset to 0 at samples and incremented (saturating) elsewhere. */
+ * reset to 0 at samples and incremented (saturating) elsewhere.  When the
+ * width is a multiple of 8, A must be 16-byte aligned (it moves in 16-byte
+ * accesses). */
 int32_t tgs_ema_age_update(uint16_t* E, uint16_t* A, int32_t height, int32_t width,
                            const int32_t* tile_slot, const int32_t* tile_off,
                            const uint8_t* pix, const float* err, float beta, void* stream);
@@ -483,9 +504,10 @@ int32_t tgs_grad_screen_mean(const float* acc, int64_t n, float* out, void* stre
 int32_t tgs_view_error_sums(const uint16_t* E, int32_t n_views, int64_t pixels, uint64_t* sums, void* stream);
 
 /* Chain rule from g2d to the Gaussian parameters (backward of tgs_project).
- *   accumulate  1: grad[59][n] += gradient; culled Gaussians (radius 0) are
+ *   accumulate  1: grad[59][n] += gradient; Gaussians whose gradient is
+ *               zero (culled, radius 0, or all nine g2d entries zero) are
  *               left untouched.  0: grad = gradient, every entry written
- *               (zeros for culled Gaussians), so grad needs no clearing.
+ *               (zeros for them), so grad needs no clearing.
  *   clamp       the tgs_project output. */
 int32_t tgs_project_bwd(const float* params, int64_t n, const tgs_camera* cam,
                         const tgs_raster_params* rp, const int32_t* radius,

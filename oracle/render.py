@@ -24,16 +24,27 @@ sequence of multiplications as the scalar loop.
 Guard band: a pixel is flagged when one of its discrete decisions (alpha vs
 alpha_min or alpha_max, T (1 - alpha) vs T_min) lies within ``guard`` times
 an error bound of an FP32 evaluation of that same quantity.  The bound
-follows from the arithmetic, per (pixel, Gaussian): with u = 2^-24 and
-S = |a| dx^2 / 2 + |c| dy^2 / 2 + |b dx dy| the magnitude of the exponent's
-terms, an FP32 exponent (the conic rounded to FP32 and scaled, the centre
-offset, the products and the sums each rounded once) carries an absolute
-error of a small multiple of u S; 32 u S is taken, about twice the largest
-error an FP32 emulation of that evaluation shows on the tiny and the
-rasterizer-scaling workloads.  So alpha carries a relative error of at most
-eps_a = 32 u S + 8 u (exponential, opacity and product included).  The
-transmittance after position k carries a relative error of at most the sum
-over the positions composited up to k of 2 u + eps_a alpha / (1 - alpha).
+follows from the arithmetic of an FP32 evaluation that takes the exponent in
+the conic's LDL^T form, d^T Q d = a w^2 + delta dy^2 with w = dx + beta dy,
+beta = b / a, delta = c - b beta (two non-negative terms, so no
+cancellation).  Per (pixel, Gaussian), with u = 2^-24:
+
+* the terms' size S = (|a| w^2 + |delta| dy^2) / 2: the conic values, the
+  scale by log2(e) and the products and sums each rounded once give an
+  error of a few u S; 8 u S is taken;
+* the offsets dx, dy (tile-local centre = exact integer difference plus the
+  fraction, then the pixel minus it) carry absolute errors of at most
+  u (2 |dx| + 18) and u (2 |dy| + 18), w in addition u (|w| + |beta dy|)
+  from its own rounding and that of beta; times the exponent's slopes
+  |a w| and |a beta w + delta dy| this gives the term ``slope``;
+
+twice their sum bounds the exponent's error (about twice the largest an
+FP32 emulation of that evaluation shows, on the tiny, the
+rasterizer-scaling and a near-camera needle workload), so alpha carries a
+relative error of at most eps_a = 2 u (8 S + slope) + 8 u (exponential,
+opacity and product included).  The transmittance after position k carries
+a relative error of at most the sum over the positions composited up to k
+of 2 u + eps_a alpha / (1 - alpha).
 FP32 and FP64 evaluations can take a decision inside its band differently;
 tests exclude flagged pixels from element-wise comparison and bound how many
 there are.
@@ -59,8 +70,18 @@ def _tile_eval(proj, gids, xs, ys, rp):
     araw = o[None, :] * G
     alpha = np.minimum(rp.alpha_max, araw)
     ok = (power <= 0.0) & (alpha >= rp.alpha_min)
-    S = 0.5 * np.abs(a)[None, :] * dx * dx + 0.5 * np.abs(c)[None, :] * dy * dy + np.abs(b[None, :] * dx * dy)
-    eps_a = 32.0 * U32 * S + 8.0 * U32
+    # error bound of an FP32 exponent taken as a w^2 + delta dy^2 (the LDL^T
+    # form of the conic, w = dx + beta dy): the terms' size S, and the
+    # exponent's slope times the FP32 offset error of the pixel from the centre
+    beta = np.where(a > 0, b / np.where(a > 0, a, 1.0), 0.0)[None, :]
+    delta = np.where(a > 0, c - b * beta[0], 0.0)[None, :]
+    aa = np.abs(a)[None, :]
+    w = dx + beta * dy
+    adx, ady = np.abs(dx), np.abs(dy)
+    S = 0.5 * (aa * w * w + np.abs(delta) * dy * dy)
+    slope = (aa * np.abs(w) * (np.abs(w) + np.abs(beta) * (3.0 * ady + 18.0) + 2.0 * adx + 18.0)
+             + np.abs(aa * beta * w + delta * dy) * (2.0 * ady + 18.0))
+    eps_a = 2.0 * U32 * (8.0 * S + slope) + 8.0 * U32
     av = np.where(ok, alpha, 0.0)
     one_m = 1.0 - av
     K = gids.size

@@ -78,6 +78,8 @@ PROTOTYPES = {
     "tgs_last_error": (ctypes.c_char_p, []),
     "tgs_pixels_per_tile": (_I32, [_I32]),
     "tgs_check_finite": (_I32, [_P, _I64, _P, _P]),
+    "tgs_bin_sort_async": (_I32, [_P, _P, _P, _I64, _P, _I32, _I32, ctypes.c_float, _P, _P, _I64, _P, _P, _P, _P,
+                                  _SZ, _P]),
     "tgs_sample_noalloc": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(tgs_sample_params), _P, _P, _P, _P, _P, _P,
                                   _P]),
     "tgs_render_bwd_det_workspace_size": (_SZ, [_I64, _I32, _I32]),
@@ -323,6 +325,16 @@ def tgs_bin_sort(rect, splat, depth, n, tile_slot, tiles_x, tiles_y, alpha_min, 
                             ctypes.byref(n_pairs), _ptr(ws), ws.numel() * ws.element_size(), _stream())
     _check(st, "tgs_bin_sort", n_pairs.value)
     return int(n_pairs.value)
+
+
+def tgs_bin_sort_async(rect, splat, depth, n, tile_slot, tiles_x, tiles_y, alpha_min, keys, vals, capacity, ranges,
+                       touched, counts, ws):
+    """tgs_bin_sort without a host wait: counts (device int64[2]) receives the
+    list length and the capacity needed."""
+    _check(lib().tgs_bin_sort_async(_ptr(rect), _ptr(splat), _ptr(depth), n, _ptr(tile_slot), tiles_x, tiles_y,
+                                    float(alpha_min), _ptr(keys), _ptr(vals), capacity, _ptr(ranges), _ptr(touched),
+                                    _ptr(counts), _ptr(ws), ws.numel() * ws.element_size(), _stream()),
+           "tgs_bin_sort_async")
 
 
 def tgs_render_state_size(n_slots: int, max_per_tile: int) -> int:

@@ -52,12 +52,32 @@ __global__ void __launch_bounds__(256) zero2_u32_kernel(uint32_t* __restrict__ p
   else if (i - n0 < n1) p1[i - n0] = 0u;
 }
 
-// Copies the count kernel's partial totals into pinned host memory (mapped
-// into the device's address space), in place of a runtime copy.
-__global__ void __launch_bounds__(256) totals_to_host_kernel(const unsigned long long* __restrict__ slots,
-                                                             unsigned long long* host) {
+__global__ void __launch_bounds__(64) copy_counts_kernel(const unsigned long long* __restrict__ src,
+                                                         unsigned long long* __restrict__ dst) {
+  if (threadIdx.x < 2) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+// Sums the count kernel's partial totals (one wave): counts[0] = pairs in
+// valid tiles, counts[1] = all pairs, and the number of pairs the pair sort
+// takes: all of them when they fit the capacity, else none.
+__global__ void __launch_bounds__(64) totals_kernel(const unsigned long long* __restrict__ slots, int64_t capacity,
+                                                    unsigned long long* __restrict__ counts,
+                                                    uint32_t* __restrict__ eff_total) {
   const int i = threadIdx.x;
-  if (i < 2 * TGS_COUNTER_SLOTS) host[i] = slots[i];
+  unsigned long long v = 0, a = 0;
+  for (int q = i; q < TGS_COUNTER_SLOTS; q += 64) {
+    v += slots[q];
+    a += slots[TGS_COUNTER_SLOTS + q];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    v += __shfl_down(v, o, 64);
+    a += __shfl_down(a, o, 64);
+  }
+  if (i == 0) {
+    counts[0] = v;
+    counts[1] = a;
+    *eff_total = a <= (unsigned long long)capacity ? (uint32_t)a : 0u;
+  }
 }
 
 // ------------------------------------------------------------------ scans
@@ -161,10 +181,12 @@ __device__ __forceinline__ RowEllipse load_row_ellipse(const float4* __restrict_
   e.yi = p0.y;
   e.xf = p0.z;
   e.yf = p0.w;
+  // the record's conic is (a, beta, delta) with b = beta a, c = delta + beta b,
+  // det = a c - b^2 = a delta
   e.A = p1.x;
-  e.B = p1.y;
-  const double C = p1.z;
-  e.det = e.A * C - e.B * e.B;
+  e.B = (double)p1.y * e.A;
+  const double C = (double)p1.z + (double)p1.y * e.B;
+  e.det = e.A * (double)p1.z;
   e.pd = e.A > 0.0 && e.det > 0.0;
   e.ym = e.pd ? sqrt((tau * e.A) / e.det) : 0.0;
   e.ys = e.pd ? e.B * sqrt(tau / (C * e.det)) : 0.0;
@@ -322,8 +344,10 @@ constexpr int kRangeItems = 8;
 constexpr int kRangeBlock = 256 * kRangeItems;
 
 template <typename K>
-__global__ void __launch_bounds__(256) ranges_kernel(const K* __restrict__ keys, uint32_t total, int id_bits,
+__global__ void __launch_bounds__(256) ranges_kernel(const K* __restrict__ keys, uint32_t total_arg,
+                                                     const uint32_t* __restrict__ total_dev, int id_bits,
                                                      uint32_t n_t, uint2* __restrict__ ranges) {
+  const uint32_t total = total_dev != nullptr ? *total_dev : total_arg;  // the device count when given
   __shared__ uint32_t s_t[kRangeBlock + 1];  // s_t[0]: the pair before the block
   const uint32_t b0 = blockIdx.x * (uint32_t)kRangeBlock;
   const int tid = threadIdx.x;
@@ -378,9 +402,13 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, uint64_t
 // Per-block histogram: block b covers keys [b * 256 * kItems, ...), wave w
 // the contiguous quarter w of it, 64 keys per round.
 template <typename K, int kBits, int kItems>
-__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K* __restrict__ keys, uint32_t n,
-                                                                 int shift, int nblocks,
-                                                                 uint32_t* __restrict__ hist) {
+__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K* __restrict__ keys, uint32_t n_arg,
+                                                                 const uint32_t* __restrict__ n_dev, int shift,
+                                                                 int nblocks, uint32_t* __restrict__ hist) {
+  const uint32_t n = n_dev != nullptr ? *n_dev : n_arg;  // the device count when given
+  // blocks past the count (a grid sized by the capacity) leave their entries
+  // unwritten: the scan and the scatter stop at the last block that holds keys
+  if (n_dev != nullptr && (int64_t)blockIdx.x * kSortThreads * kItems >= (int64_t)n) return;
   constexpr int kDigits = 1 << kBits;
   __shared__ uint32_t h[kDigits];
   for (int i = threadIdx.x; i < kDigits; i += kSortThreads) h[i] = 0;
@@ -405,8 +433,11 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const K* __res
 // (a contiguous row of the digit-major table) and the digit's total.
 __global__ void __launch_bounds__(1024) digit_scan_kernel(const uint32_t* __restrict__ hist, int nblocks,
                                                           int stride, uint32_t* __restrict__ hoffs,
-                                                          uint32_t* __restrict__ dtot) {
+                                                          uint32_t* __restrict__ dtot,
+                                                          const uint32_t* __restrict__ n_dev, int block_keys) {
   __shared__ uint32_t lds[1024 / kWave];
+  // with a device count, only the blocks that hold keys have table entries
+  if (n_dev != nullptr) nblocks = (int)min<int64_t>(nblocks, ceil_div((int64_t)*n_dev, (int64_t)block_keys));
   const int64_t row = (int64_t)blockIdx.x * stride;
   uint32_t carry = 0;
   for (int b0 = 0; b0 < nblocks; b0 += 1024) {
@@ -433,10 +464,13 @@ struct ScatterOut {
 
 template <typename K, bool kVals, bool kFinal, int kBits, int kItems>
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
-    const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t n, int shift, int nblocks,
-    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ dtot, ScatterOut o) {
+    const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t n_arg,
+    const uint32_t* __restrict__ n_dev, int shift, int nblocks, const uint32_t* __restrict__ offs,
+    const uint32_t* __restrict__ dtot, ScatterOut o) {
+  const uint32_t n = n_dev != nullptr ? *n_dev : n_arg;  // the device count when given
   constexpr int kDigits = 1 << kBits;
   constexpr int kBlockKeys = kSortThreads * kItems;
+  if ((int64_t)blockIdx.x * kBlockKeys >= (int64_t)n) return;  // past the keys: nothing to place
   __shared__ uint32_t s_cnt[kSortWaves][kDigits];  // per-wave digit counts, then block-local offsets
   __shared__ uint32_t s_gbase[kDigits];            // global position of block-local position 0 of the digit
   __shared__ K s_keys[kBlockKeys];
@@ -637,26 +671,27 @@ __global__ void __launch_bounds__(kSortThreads) depth_pass_kernel(const uint32_t
 // One radix pass over n keys on bits [shift, shift + kBits); the histogram
 // table is taken here unless the caller already wrote it (hist_ready).
 template <typename K, bool kVals, bool kFinal, int kBits, int kItems>
-static void radix_pass(const K* keys, const uint32_t* vals, uint32_t n, int shift, bool hist_ready,
+static void radix_pass(const K* keys, const uint32_t* vals, uint32_t n, const uint32_t* n_dev, int shift,
                        uint32_t* hist, uint32_t* hoffs, uint32_t* dtot, const ScatterOut& o, hipStream_t s) {
+  // n bounds the keys (the grid); n_dev, when given, holds the actual count on the device
   const int nblocks = (int)sort_blocks(n, kItems);
-  if (!hist_ready)
-    hipLaunchKernelGGL((radix_hist_kernel<K, kBits, kItems>), dim3(nblocks), dim3(kSortThreads), 0, s, keys, n,
-                       shift, nblocks, hist);
-  hipLaunchKernelGGL(digit_scan_kernel, dim3(1 << kBits), dim3(1024), 0, s, hist, nblocks, nblocks, hoffs, dtot);
+  hipLaunchKernelGGL((radix_hist_kernel<K, kBits, kItems>), dim3(nblocks), dim3(kSortThreads), 0, s, keys, n, n_dev,
+                     shift, nblocks, hist);
+  hipLaunchKernelGGL(digit_scan_kernel, dim3(1 << kBits), dim3(1024), 0, s, hist, nblocks, nblocks, hoffs, dtot, n_dev,
+                     kSortThreads * kItems);
   hipLaunchKernelGGL((radix_scatter_kernel<K, kVals, kFinal, kBits, kItems>), dim3(nblocks), dim3(kSortThreads),
-                     0, s, keys, vals, n, shift, nblocks, hoffs, dtot, o);
+                     0, s, keys, vals, n, n_dev, shift, nblocks, hoffs, dtot, o);
 }
 
 template <typename K, bool kVals, bool kFinal, int kItems>
-static void radix_pass_bits(int bits, const K* keys, const uint32_t* vals, uint32_t n, int shift,
-                            bool hist_ready, uint32_t* hist, uint32_t* hoffs, uint32_t* dtot,
-                            const ScatterOut& o, hipStream_t s) {
+static void radix_pass_bits(int bits, const K* keys, const uint32_t* vals, uint32_t n, const uint32_t* n_dev,
+                            int shift, uint32_t* hist, uint32_t* hoffs, uint32_t* dtot, const ScatterOut& o,
+                            hipStream_t s) {
   switch (bits) {
 #define TGS_PASS(B) \
-  case B: radix_pass<K, kVals, kFinal, B, kItems>(keys, vals, n, shift, hist_ready, hist, hoffs, dtot, o, s); break;
+  case B: radix_pass<K, kVals, kFinal, B, kItems>(keys, vals, n, n_dev, shift, hist, hoffs, dtot, o, s); break;
     TGS_PASS(1) TGS_PASS(2) TGS_PASS(3) TGS_PASS(4) TGS_PASS(5) TGS_PASS(6) TGS_PASS(7)
-    default: radix_pass<K, kVals, kFinal, 8, kItems>(keys, vals, n, shift, hist_ready, hist, hoffs, dtot, o, s);
+    default: radix_pass<K, kVals, kFinal, 8, kItems>(keys, vals, n, n_dev, shift, hist, hoffs, dtot, o, s);
 #undef TGS_PASS
   }
 }
@@ -676,6 +711,10 @@ struct RowBatch {
   RowEllipse ell[kWave];
   uint32_t id[kWave];
   int mark[kWave];
+  // a round's row spans: first column, tile id of the row's column 0, id,
+  // first output (exclusive prefix of the span lengths)
+  int lo[kWave];
+  uint32_t trow[kWave], gid[kWave], ex[kWave];
 };
 
 constexpr int kEmitThreads = kWave;  // one wave per workgroup: __syncthreads is a wave barrier
@@ -694,13 +733,16 @@ template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ off, const uint32_t* __restrict__ ids_sorted,
     int64_t n, const float4* __restrict__ splat, const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t,
-    int id_bits, double tau, uint32_t total, K* __restrict__ keys, uint32_t* __restrict__ pay) {
+    int id_bits, double tau, const uint32_t* __restrict__ total_dev, K* __restrict__ keys,
+    uint32_t* __restrict__ pay) {
+  const uint32_t total = *total_dev;  // pairs to emit (0 when they exceed the capacity)
   __shared__ RowBatch rb;
   const int lane = lane_id();
   const int64_t b0 = (int64_t)blockIdx.x * kEmitBatch;
   const int64_t j = b0 + lane;
   int4 r = make_int4(0, 0, 0, 0);
   uint32_t g = 0, rows = 0;
+  if (total == 0) return;  // workgroup-uniform
   if (lane < kEmitBatch && j < n && off[j + 1] > off[j]) {
     r = rect_sorted[j];
     g = ids_sorted[j];
@@ -737,22 +779,39 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     }
     const uint32_t c = (uint32_t)max(hi - lo + 1, 0);
     const uint32_t ci = wave_inclusive_scan_u32(c);
-    const uint32_t pos0 = base + written + ci - c;
-    written += (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
-    const int64_t trow = (int64_t)ty * tiles_x;
-    for (uint32_t k = 0; k < c; ++k) {
-      const uint32_t pos = pos0 + k;
-      if (pos < total) {  // always (same spans as the count kernel); the bound is a safeguard
-        uint32_t tile = (uint32_t)(trow + lo + (int)k);
+    const uint32_t n_out = (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
+    // the round's rows write n_out consecutive pairs from base + written; they
+    // are handed out 64 per sub-round, lane q taking output q, so every store
+    // covers consecutive addresses: the row owning an output is found like
+    // the rows' owners above (its first output marked, a max-scan carries it)
+    rb.lo[lane] = lo;
+    rb.trow[lane] = in ? (uint32_t)ty * (uint32_t)tiles_x : 0u;
+    rb.gid[lane] = gid;
+    rb.ex[lane] = ci - c;
+    int ocarry = -1;
+    for (uint32_t q0 = 0; q0 < n_out; q0 += kWave) {
+      rb.mark[lane] = -1;
+      __syncthreads();
+      if (c > 0 && ci - c >= q0 && ci - c - q0 < (uint32_t)kWave) rb.mark[ci - c - q0] = lane;
+      __syncthreads();
+      const int own = max(wave_max_scan(rb.mark[lane]), ocarry);
+      ocarry = __builtin_amdgcn_readlane(own, kWave - 1);
+      const uint32_t q = q0 + (uint32_t)lane;
+      const uint32_t pos = base + written + q;
+      // own >= 0 whenever q < n_out: output 0 belongs to the first row with pairs
+      if (q < n_out && own >= 0 && pos < total) {  // pos < total always holds; the bound is a safeguard
+        uint32_t tile = rb.trow[own] + (uint32_t)(rb.lo[own] + (int)(q - rb.ex[own]));
         if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
         if (pay != nullptr) {  // the id as a separate payload, the key is the tile alone
           keys[pos] = (K)tile;
-          pay[pos] = gid;
+          pay[pos] = rb.gid[own];
         } else {
-          keys[pos] = ((K)tile << id_bits) | (K)gid;
+          keys[pos] = ((K)tile << id_bits) | (K)rb.gid[own];
         }
       }
+      __syncthreads();  // the sub-round's mark reads before the next one's writes
     }
+    written += n_out;
     __syncthreads();  // the round's mark reads before the next round's writes
   }
 }
@@ -778,6 +837,8 @@ struct SortWs {
   uint32_t* hoffs;              // [256 * max_blocks]
   void* pkeys[2];               // [capacity] x 8 bytes each: pair keys (u32), or u16/u32 tile keys then u32 ids
   int64_t cap;                  // pairs each ping-pong buffer holds
+  unsigned long long* counts;   // [2] pairs in valid tiles, all pairs (the call's device result)
+  uint32_t* eff_total;          // all pairs when they fit the capacity, else 0 (what the pair sort sorts)
   size_t bytes;
 };
 
@@ -803,6 +864,8 @@ static SortWs layout(void* ws, int64_t n, int64_t capacity) {
   w.zeroed = (uint32_t*)take(sizeof(uint32_t) * w.zeroed_words);
   w.scalars = (unsigned long long*)w.zeroed;
   for (int k = 0; k < 4; ++k) w.dhist[k] = w.zeroed ? w.zeroed + scalar_words + k * table_words : nullptr;
+  w.counts = (unsigned long long*)take(4 * sizeof(unsigned long long));
+  w.eff_total = (uint32_t*)(w.counts ? w.counts + 2 : nullptr);
   w.dhoffs = (uint32_t*)take(sizeof(uint32_t) * table_words);
   w.ddtot = (uint32_t*)take(sizeof(uint32_t) * kDepthDigits);
   w.emit_cnt = (uint32_t*)take(sizeof(uint32_t) * nn);
@@ -839,9 +902,9 @@ static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_
   for (int p = 0; p < 4; ++p) {
     // rows of hstride entries (the padding stays zero from the start-of-call fill)
     hipLaunchKernelGGL((radix_hist_kernel<uint32_t, 8, kDepthItems>), dim3(nb), dim3(kSortThreads), 0, s,
-                       w.dkeys[cur], n, 8 * p, w.hstride, w.dhist[p]);
+                       w.dkeys[cur], n, (const uint32_t*)nullptr, 8 * p, w.hstride, w.dhist[p]);
     hipLaunchKernelGGL(digit_scan_kernel, dim3(kDepthDigits), dim3(1024), 0, s, w.dhist[p], (int)nb, w.hstride,
-                       w.dhoffs, w.ddtot);
+                       w.dhoffs, w.ddtot, (const uint32_t*)nullptr, kDepthBlockKeys);
     DepthPassOut o{};
     if (p < 3) {
       o.keys = w.dkeys[cur ^ 1];
@@ -867,8 +930,10 @@ static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_
 // kPay true: the key is the tile alone (16 bits) and the id travels as a
 // 32-bit payload; used when tile and id bits together exceed 32, where a
 // 64-bit key would move 16 bytes per pair and pass instead of 12.
+// bound: the capacity (host), sizing every grid; the pair count itself is
+// read on the device (w.eff_total), so nothing here waits for the host.
 template <typename K, bool kPay>
-static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t total, const float4* splat,
+static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t bound, const float4* splat,
                        const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits, int tbits, double tau,
                        const float* depth, uint32_t* vals, uint64_t* keys64, uint32_t* ranges, hipStream_t s) {
   // each ping-pong buffer (8 bytes per pair of capacity) holds the keys and, after them, the payload
@@ -878,8 +943,8 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
     for (int k = 0; k < 2; ++k) pb[k] = (uint32_t*)((char*)w.pkeys[k] + align_up(sizeof(K) * (size_t)w.cap, 256));
   const int key_id_bits = kPay ? 0 : id_bits;
   hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(n, kEmitBatch)), dim3(kEmitThreads), 0, s,
-                     w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, key_id_bits, tau, total, kb[0],
-                     pb[0]);
+                     w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, key_id_bits, tau, w.eff_total,
+                     kb[0], pb[0]);
   const int passes = pass_count(tbits);
   int cur = 0, shift = key_id_bits;
   for (int p = 0; p < passes; ++p) {
@@ -887,60 +952,21 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
     // non-final passes carry the payload to the other buffer; the last writes the ids
     const ScatterOut o = {kb[cur ^ 1], p == passes - 1 ? vals : pb[cur ^ 1], key_id_bits, depth, keys64};
     if (p == passes - 1)
-      radix_pass_bits<K, kPay, true, kPairItems>(b, kb[cur], pb[cur], total, shift, false, w.hist, w.hoffs,
+      radix_pass_bits<K, kPay, true, kPairItems>(b, kb[cur], pb[cur], bound, w.eff_total, shift, w.hist, w.hoffs,
                                                  w.partials, o, s);
     else
-      radix_pass_bits<K, kPay, false, kPairItems>(b, kb[cur], pb[cur], total, shift, false, w.hist, w.hoffs,
+      radix_pass_bits<K, kPay, false, kPairItems>(b, kb[cur], pb[cur], bound, w.eff_total, shift, w.hist, w.hoffs,
                                                   w.partials, o, s);
     cur ^= 1;
     shift += b;
   }
-  hipLaunchKernelGGL((ranges_kernel<K>), dim3((unsigned)ceil_div(total, kRangeBlock)), dim3(256), 0, s,
-                     kb[cur], total, key_id_bits, n_t, (uint2*)ranges);
+  hipLaunchKernelGGL((ranges_kernel<K>), dim3((unsigned)std::max<int64_t>(ceil_div(bound, kRangeBlock), 1)),
+                     dim3(256), 0, s, kb[cur], bound, w.eff_total, key_id_bits, n_t, (uint2*)ranges);
 }
 
 }  // namespace tgs
 
 using namespace tgs;
-
-// Pinned host buffer and event for the count totals, one per host thread
-// and device (kept until the process ends).  A call waits on its event
-// before it returns, so successive calls on a thread never share them in
-// flight.
-struct Readback {
-  int dev = -1;
-  unsigned long long* host = nullptr;
-  unsigned long long* mapped = nullptr;  // the device's address of host (null: copy instead)
-  hipEvent_t ev = nullptr;
-};
-
-static Readback* readback() {
-  static thread_local Readback rb[8];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  Readback& r = rb[dev & 7];
-  if (r.dev != dev) {
-    if (r.ev != nullptr) (void)hipEventDestroy(r.ev);
-    r.ev = nullptr;
-    if (r.host == nullptr &&
-        hipHostMalloc((void**)&r.host, sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS,
-                      hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
-      r.host = nullptr;
-      return nullptr;
-    }
-    r.mapped = nullptr;
-    if (hipHostGetDevicePointer((void**)&r.mapped, r.host, 0) != hipSuccess) {
-      r.mapped = nullptr;            // fall back to a runtime copy
-      (void)hipGetLastError();       // and leave no error behind
-    }
-    if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) {
-      r.ev = nullptr;
-      return nullptr;
-    }
-    r.dev = dev;
-  }
-  return &r;
-}
 
 extern "C" size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32_t n_tiles) {
   (void)n_tiles;
@@ -948,76 +974,102 @@ extern "C" size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32
   return layout(nullptr, n, capacity).bytes;
 }
 
+// Everything after the argument checks: queued on the stream, no host wait.
+static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const float* depth, int64_t n,
+                              const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
+                              uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges, uint8_t* touched,
+                              const SortWs& w, hipStream_t s, const char* who) {
+  const uint32_t n_t = (uint32_t)tiles_x * (uint32_t)tiles_y;
+  // 2 ln(1/alpha_min) with a 0.1 % margin, rounded up to a multiple of 1/64
+  const double tau = std::ceil(128.0 * std::log(1.0 / (double)alpha_min) * 1.001) / 64.0;
+  // empty ranges and the zeroed workspace region (counters, table padding)
+  hipLaunchKernelGGL(zero2_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t + w.zeroed_words, 256)), dim3(256),
+                     0, s, ranges, 2 * (int64_t)n_t, w.zeroed, w.zeroed_words);
+  // counts and the pair total of the sort (both 0 until the totals land)
+  hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w.scalars, capacity, w.counts, w.eff_total);
+  if (n == 0) return hip_status(who);
+  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kWave), 0, s,
+                     (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau,
+                     w.dkeys[0], w.dvals[0], w.emit_cnt, touched, w.scalars);
+  hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w.scalars, capacity, w.counts, w.eff_total);
+  // (depth, id) order; Gaussians without pairs last
+  sort_depth(w, (uint32_t)n, (const int4*)rect, tiles_x, tiles_y, s);
+  // pair offsets (they wrap only past 2^32 pairs, where the capacity check has already set the total to 0)
+  exclusive_scan<uint32_t>(w.cnt_sorted, w.off, n, w.partials, s);
+  if (capacity == 0) return hip_status(who);
+  const uint32_t bound = (uint32_t)capacity;
+  const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
+  const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
+  if (id_bits + tbits <= 32)
+    sort_pairs<uint32_t, false>(w, w.ids_sorted, n, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+                                tbits, tau, depth, vals, keys, ranges, s);
+  else if (tbits <= 16)
+    sort_pairs<uint16_t, true>(w, w.ids_sorted, n, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+                               tbits, tau, depth, vals, keys, ranges, s);
+  else
+    sort_pairs<uint32_t, true>(w, w.ids_sorted, n, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+                               tbits, tau, depth, vals, keys, ranges, s);
+  return hip_status(who);
+}
+
+static int32_t bin_sort_check(const int32_t* rect, const float* splat, const float* depth, int64_t n,
+                              int32_t tiles_x, int32_t tiles_y, float alpha_min, uint32_t* vals, int64_t capacity,
+                              uint32_t* ranges, void* ws, size_t ws_bytes, const SortWs& w, const char* who) {
+  TGS_REQUIRE(n >= 0 && n < (1ll << 31), "%s: n out of range", who);
+  TGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && (int64_t)tiles_x * tiles_y < (1ll << 30), "%s: bad tile grid", who);
+  TGS_REQUIRE(capacity >= 0 && capacity < (1ll << 32), "%s: capacity out of range", who);
+  TGS_REQUIRE(alpha_min > 0.f && alpha_min < 1.f, "%s: alpha_min %g not in (0, 1)", who, (double)alpha_min);
+  TGS_REQUIRE(vals && ranges && ws, "%s: null pointer", who);  // keys may be null
+  TGS_REQUIRE(n == 0 || (rect && splat && depth), "%s: null rect/splat/depth", who);
+  TGS_REQUIRE(((uintptr_t)rect & 15) == 0 && ((uintptr_t)splat & 15) == 0 && ((uintptr_t)ws & 15) == 0,
+              "%s: rect, splat and ws must be 16-byte aligned", who);
+  TGS_REQUIRE(ws_bytes >= w.bytes, "%s: workspace %zu bytes < %zu", who, ws_bytes, w.bytes);
+  return TGS_OK;
+}
+
+extern "C" int32_t tgs_bin_sort_async(const int32_t* rect, const float* splat, const float* depth, int64_t n,
+                                      const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
+                                      uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges,
+                                      uint8_t* touched, int64_t* counts, void* ws, size_t ws_bytes, void* stream) {
+  const SortWs w = layout(ws, n, capacity);
+  if (int32_t e = bin_sort_check(rect, splat, depth, n, tiles_x, tiles_y, alpha_min, vals, capacity, ranges, ws,
+                                 ws_bytes, w, "tgs_bin_sort_async"))
+    return e;
+  TGS_REQUIRE(counts != nullptr && ((uintptr_t)counts & 7) == 0,
+              "tgs_bin_sort_async: counts must be an 8-byte aligned device pointer");
+  hipStream_t s = as_stream(stream);
+  if (int32_t e = bin_sort_queue(rect, splat, depth, n, tile_slot, tiles_x, tiles_y, alpha_min, keys, vals, capacity,
+                                 ranges, touched, w, s, "tgs_bin_sort_async"))
+    return e;
+  hipLaunchKernelGGL(copy_counts_kernel, dim3(1), dim3(64), 0, s, (const unsigned long long*)w.counts,
+                     (unsigned long long*)counts);
+  return hip_status("tgs_bin_sort_async");
+}
+
 extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const float* depth, int64_t n,
                                 const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
                                 uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges,
                                 uint8_t* touched, int64_t* n_pairs, void* ws, size_t ws_bytes,
                                 void* stream) {
-  TGS_REQUIRE(n >= 0 && n < (1ll << 31), "tgs_bin_sort: n out of range");
-  TGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && (int64_t)tiles_x * tiles_y < (1ll << 30),
-              "tgs_bin_sort: bad tile grid");
-  TGS_REQUIRE(capacity >= 0 && capacity < (1ll << 32), "tgs_bin_sort: capacity out of range");
-  TGS_REQUIRE(alpha_min > 0.f && alpha_min < 1.f, "tgs_bin_sort: alpha_min %g not in (0, 1)", (double)alpha_min);
-  TGS_REQUIRE(vals && ranges && n_pairs && ws, "tgs_bin_sort: null pointer");  // keys may be null
-  TGS_REQUIRE(n == 0 || (rect && splat && depth), "tgs_bin_sort: null rect/splat/depth");
-  TGS_REQUIRE(((uintptr_t)rect & 15) == 0 && ((uintptr_t)splat & 15) == 0,
-              "tgs_bin_sort: rect and splat must be 16-byte aligned");
-  const uint32_t n_t = (uint32_t)tiles_x * (uint32_t)tiles_y;
   const SortWs w = layout(ws, n, capacity);
-  TGS_REQUIRE(ws_bytes >= w.bytes, "tgs_bin_sort: workspace %zu bytes < %zu", ws_bytes, w.bytes);
+  if (int32_t e = bin_sort_check(rect, splat, depth, n, tiles_x, tiles_y, alpha_min, vals, capacity, ranges, ws,
+                                 ws_bytes, w, "tgs_bin_sort"))
+    return e;
+  TGS_REQUIRE(n_pairs != nullptr, "tgs_bin_sort: null n_pairs");
   hipStream_t s = as_stream(stream);
-  // 2 ln(1/alpha_min) with a 0.1 % margin, rounded up to a multiple of 1/64
-  const double tau = std::ceil(128.0 * std::log(1.0 / (double)alpha_min) * 1.001) / 64.0;
-
-  // empty ranges and the zeroed workspace region (counters, table padding)
-  hipLaunchKernelGGL(zero2_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t + w.zeroed_words, 256)), dim3(256),
-                     0, s, ranges, 2 * (int64_t)n_t, w.zeroed, w.zeroed_words);
-  if (n == 0) {
-    *n_pairs = 0;
-    return hip_status("tgs_bin_sort");
-  }
-  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kWave), 0, s,
-                     (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau,
-                     w.dkeys[0], w.dvals[0], w.emit_cnt, touched, w.scalars);
-  // The totals go to pinned host memory right after the count; the host
-  // queues the depth sort, gather and scan before it waits for them, so the
-  // device keeps working while the host reads the totals and sizes the rest.
-  Readback* rb = readback();
-  if (rb == nullptr) return hip_status("tgs_bin_sort: pinned readback buffer");
-  if (rb->mapped != nullptr)
-    hipLaunchKernelGGL(totals_to_host_kernel, dim3(1), dim3(256), 0, s, w.scalars, rb->mapped);
-  else if (hipMemcpyAsync(rb->host, w.scalars, sizeof(unsigned long long) * 2 * TGS_COUNTER_SLOTS,
-                          hipMemcpyDeviceToHost, s) != hipSuccess)
+  if (int32_t e = bin_sort_queue(rect, splat, depth, n, tile_slot, tiles_x, tiles_y, alpha_min, keys, vals, capacity,
+                                 ranges, touched, w, s, "tgs_bin_sort"))
+    return e;
+  // the one synchronisation: the two counts, read back when the stream has run the call
+  unsigned long long host[2] = {0, 0};
+  if (hipMemcpyAsync(host, w.counts, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
     return hip_status("tgs_bin_sort: count readback");
-  if (hipEventRecord(rb->ev, s) != hipSuccess) return hip_status("tgs_bin_sort: count readback");
-  // (depth, id) order; Gaussians without pairs last
-  sort_depth(w, (uint32_t)n, (const int4*)rect, tiles_x, tiles_y, s);
-  exclusive_scan<uint32_t>(w.cnt_sorted, w.off, n, w.partials, s);  // wraps only past capacity (checked below)
-  if (hipEventSynchronize(rb->ev) != hipSuccess) return hip_status("tgs_bin_sort: count readback");
-  const unsigned long long* slots = rb->host;
-  unsigned long long sum[2] = {0, 0};
-  for (int k = 0; k < 2; ++k)
-    for (int q = 0; q < TGS_COUNTER_SLOTS; ++q) sum[k] += slots[k * TGS_COUNTER_SLOTS + q];
-  const unsigned long long valid_total = sum[0], total64 = sum[1];
-  if ((int64_t)total64 > capacity) {
-    *n_pairs = (int64_t)total64;
-    set_error("tgs_bin_sort: %llu pairs exceed capacity %lld", total64, (long long)capacity);
+  if ((int64_t)host[1] > capacity) {
+    *n_pairs = (int64_t)host[1];
+    set_error("tgs_bin_sort: %llu pairs exceed capacity %lld", host[1], (long long)capacity);
     return TGS_ERR_CAPACITY;
   }
-  const uint32_t total = (uint32_t)total64;  // capacity < 2^32
-  *n_pairs = (int64_t)valid_total;
-  if (total == 0) return hip_status("tgs_bin_sort");
-
-  const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
-  const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
-  if (id_bits + tbits <= 32)
-    sort_pairs<uint32_t, false>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                                tbits, tau, depth, vals, keys, ranges, s);
-  else if (tbits <= 16)
-    sort_pairs<uint16_t, true>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                               tbits, tau, depth, vals, keys, ranges, s);
-  else
-    sort_pairs<uint32_t, true>(w, w.ids_sorted, n, total, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                               tbits, tau, depth, vals, keys, ranges, s);
+  *n_pairs = (int64_t)host[0];
   return hip_status("tgs_bin_sort");
 }

@@ -96,6 +96,36 @@ __device__ __forceinline__ uint64_t wave_inclusive_scan_u64(uint64_t v) {
   return v;
 }
 
+// The same scan on DPP alone: rows of 16 by shifts of 1, 2, 4 and 8 lanes,
+// then the row totals chained by the row broadcasts of lanes 15 and 31.  A
+// lane whose DPP source lies before its row (or in a masked row) reads 0.
+template <int Ctrl, int RowMask = 0xf>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)dpp_i<Ctrl, RowMask>(0, (int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)dpp_i<Ctrl, RowMask>(0, (int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_inclusive_scan_u64_dpp(uint64_t v) {
+  v += dpp_u64<kDppRowShr1>(v);
+  v += dpp_u64<kDppRowShr1 + 1>(v);  // row_shr:2
+  v += dpp_u64<kDppRowShr1 + 3>(v);  // row_shr:4
+  v += dpp_u64<kDppRowShr1 + 7>(v);  // row_shr:8
+  v += dpp_u64<kDppRowBcast15, 0xa>(v);
+  v += dpp_u64<kDppRowBcast31, 0xc>(v);
+  return v;
+}
+
+__device__ __forceinline__ int wave_inclusive_scan_i_dpp(int v) {
+  v += dpp_i<kDppRowShr1>(0, v);
+  v += dpp_i<kDppRowShr1 + 1>(0, v);
+  v += dpp_i<kDppRowShr1 + 3>(0, v);
+  v += dpp_i<kDppRowShr1 + 7>(0, v);
+  v += dpp_i<kDppRowBcast15, 0xa>(0, v);
+  v += dpp_i<kDppRowBcast31, 0xc>(0, v);
+  return v;
+}
+
 __device__ __forceinline__ uint32_t wave_inclusive_scan_u32(uint32_t v) {
   const int lane = lane_id();
 #pragma unroll

@@ -5,8 +5,9 @@
 // samples (strided, so loads coalesce).  The tile statistics (means, centred
 // second moments, NCC per channel, the two mean gradient norms) are wave
 // sums through DPP; everything stays in registers between the passes.
-// ema_age: one workgroup per tile of the view; the tile's sample list is
-// scattered into an LDS slot table so each thread updates one pixel.
+// ema_age: one workgroup per band of eight tiles of a tile row; the sample
+// lists are scattered into an LDS slot table and each thread updates eight
+// consecutive pixels of a row (16-byte age-map accesses).
 #include <hip/hip_fp16.h>
 
 #include "common.h"
@@ -150,6 +151,13 @@ __device__ __forceinline__ uint16_t ema_half(uint16_t e_bits, float e, float bet
   return __half_as_ushort(__float2half_rn(t1 + t2));
 }
 
+// One workgroup per band of kEmaTiles tiles of a tile row (16 rows x 128
+// pixels); a thread takes 8 consecutive pixels of one row, so the age map
+// moves in 16-byte accesses.  The band's sample lists are first scattered
+// into LDS (for each pixel: its sample index or -1); a sampled pixel gets
+// age 0 and its error blended, every other pixel age + 1 (saturating).
+constexpr int kEmaTiles = 8;
+
 __global__ void __launch_bounds__(256) ema_age_kernel(uint16_t* __restrict__ E, uint16_t* __restrict__ A,
                                                       int H, int W, int tiles_x,
                                                       const int32_t* __restrict__ tile_slot,
@@ -157,27 +165,56 @@ __global__ void __launch_bounds__(256) ema_age_kernel(uint16_t* __restrict__ E, 
                                                       const uint8_t* __restrict__ pix,
                                                       const float* __restrict__ err, float beta,
                                                       float omb) {
-  __shared__ int pos[kTilePixels];
-  const int tile = blockIdx.x, tid = threadIdx.x;
-  const int slot = tile_slot[tile];
-  pos[tid] = -1;
+  __shared__ int pos[kEmaTiles][kTilePixels];
+  const int tid = threadIdx.x, ty = blockIdx.y, tx0 = blockIdx.x * kEmaTiles;
+  for (int k = 0; k < kEmaTiles; ++k) pos[k][tid] = -1;
   __syncthreads();
-  if (slot >= 0) {
-    const int p0 = tile_off[slot], np = tile_off[slot + 1] - p0;
-    if (tid < np) pos[pix[p0 + tid]] = p0 + tid;
+  for (int k = 0; k < kEmaTiles; ++k) {
+    const int tx = tx0 + k;
+    if (tx >= tiles_x) break;
+    const int slot = tile_slot[ty * tiles_x + tx];
+    if (slot >= 0) {
+      const int p0 = tile_off[slot], np = tile_off[slot + 1] - p0;
+      if (tid < np) pos[k][pix[p0 + tid]] = p0 + tid;
+    }
   }
   __syncthreads();
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int x = tx * kTile + (tid & 15), y = ty * kTile + (tid >> 4);
-  if (x >= W || y >= H) return;
-  const int64_t i = (int64_t)y * W + x;
-  const int p = pos[tid];
-  if (p >= 0) {
-    A[i] = 0;
-    E[i] = ema_half(E[i], err[p], beta, omb);
+  const int row = tid >> 4, seg = tid & 15;  // 16 rows x 16 segments of 8 pixels
+  const int y = ty * kTile + row, x0 = tx0 * kTile + seg * 8;
+  if (y >= H || x0 >= W) return;
+  const int k = seg >> 1, lx0 = (seg & 1) * 8;  // tile of the band, first local column
+  const int64_t i0 = (int64_t)y * W + x0;
+  uint16_t a[8];
+  const bool vec = (W & 7) == 0 && x0 + 8 <= W;  // 16-byte aligned and inside the row
+  if (vec) {
+    const uint4 v = *reinterpret_cast<const uint4*>(A + i0);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    for (int j = 0; j < 4; ++j) {
+      a[2 * j] = (uint16_t)(w[j] & 0xffffu);
+      a[2 * j + 1] = (uint16_t)(w[j] >> 16);
+    }
   } else {
-    const uint16_t a = A[i];
-    A[i] = a == 0xffffu ? a : (uint16_t)(a + 1u);
+    for (int j = 0; j < 8; ++j) a[j] = x0 + j < W ? A[i0 + j] : 0;
+  }
+  for (int j = 0; j < 8; ++j) {
+    const int p = pos[k][row * kTile + lx0 + j];
+    if (p >= 0) {
+      a[j] = 0;
+      E[i0 + j] = ema_half(E[i0 + j], err[p], beta, omb);
+    } else {
+      a[j] = a[j] == 0xffffu ? a[j] : (uint16_t)(a[j] + 1u);
+    }
+  }
+  if (vec) {
+    uint4 v;
+    v.x = (uint32_t)a[0] | ((uint32_t)a[1] << 16);
+    v.y = (uint32_t)a[2] | ((uint32_t)a[3] << 16);
+    v.z = (uint32_t)a[4] | ((uint32_t)a[5] << 16);
+    v.w = (uint32_t)a[6] | ((uint32_t)a[7] << 16);
+    *reinterpret_cast<uint4*>(A + i0) = v;
+  } else {
+    for (int j = 0; j < 8; ++j)
+      if (x0 + j < W) A[i0 + j] = a[j];
   }
 }
 
@@ -242,8 +279,10 @@ extern "C" int32_t tgs_ema_age_update(uint16_t* E, uint16_t* A, int32_t height, 
   TGS_REQUIRE(E && A && tile_slot && tile_off && pix && err, "tgs_ema_age_update: null pointer");
   const int tiles_x = (int)ceil_div(width, kTile), tiles_y = (int)ceil_div(height, kTile);
   const float omb = 1.0f - beta;
-  hipLaunchKernelGGL(ema_age_kernel, dim3(tiles_x * tiles_y), dim3(256), 0, as_stream(stream), E, A,
-                     height, width, tiles_x, tile_slot, tile_off, pix, err, beta, omb);
+  TGS_REQUIRE((width & 7) != 0 || ((uintptr_t)A & 15) == 0,
+              "tgs_ema_age_update: A must be 16-byte aligned when the width is a multiple of 8");
+  hipLaunchKernelGGL(ema_age_kernel, dim3((unsigned)ceil_div(tiles_x, kEmaTiles), (unsigned)tiles_y), dim3(256), 0,
+                     as_stream(stream), E, A, height, width, tiles_x, tile_slot, tile_off, pix, err, beta, omb);
   return hip_status("tgs_ema_age_update");
 }
 

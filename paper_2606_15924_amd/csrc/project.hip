@@ -69,8 +69,9 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
   const double opac = 1.0 / (1.0 + exp(-(double)params[10 * n + i]));
   const double fxp = floor(g.px), fyp = floor(g.py);
   splat[3 * i + 0] = make_float4((float)fxp, (float)fyp, (float)(g.px - fxp), (float)(g.py - fyp));
-  splat[3 * i + 1] = make_float4((float)(g.c / g.det), (float)(-g.b / g.det), (float)(g.a / g.det),
-                                 (float)opac);
+  // the conic Q = Sigma'^-1 = [[c, -b], [-b, a]] / det in its LDL^T form:
+  // Q_00 = c / det, beta = Q_01 / Q_00 = -b / c, delta = det Q / Q_00 = 1 / c
+  splat[3 * i + 1] = make_float4((float)(g.c / g.det), (float)(-g.b / g.c), (float)(1.0 / g.c), (float)opac);
   splat[3 * i + 2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], (float)g.t[2]);
   radius[i] = (int)g.radius;
   rect[i] = make_int4(g.rect[0], g.rect[1], g.rect[2], g.rect[3]);
@@ -91,15 +92,22 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     const PT* __restrict__ g2d, PT* __restrict__ grad, bool accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (radius[i] == 0) {
+  double gg[9];
+  bool any = false;
+  for (int k = 0; k < 9; ++k) {
+    gg[k] = (double)g2d[i * 9 + k];
+    any = any || gg[k] != 0.0;
+  }
+  // culled, or no screen-space gradient in this view (at sparse rates most
+  // Gaussians): the gradient is zero, so nothing is added, or zeros are
+  // written, without reading the parameters
+  if (radius[i] == 0 || !any) {
     if (!accumulate)
       for (int r = 0; r < TGS_PARAM_ROWS; ++r) grad[(int64_t)r * n + i] = (PT)0;
     return;
   }
   Geom g;
   geometry(params, n, i, cam, z_near, dil, g);
-  double gg[9];
-  for (int k = 0; k < 9; ++k) gg[k] = (double)g2d[i * 9 + k];
   chain_rule(params, n, i, cam, sh_degree, g, gg, clampm[i], [&](int row, double v) {
     const int64_t idx = (int64_t)row * n + i;
     grad[idx] = accumulate ? grad[idx] + (PT)v : (PT)v;

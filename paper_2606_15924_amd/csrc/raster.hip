@@ -47,27 +47,36 @@ struct RasterArgs {
 // replay, so both evaluate alpha through these functions, written with
 // explicit fused operations and no contraction left to the compiler.
 //
-// Staged conic: (A, B, C) = (-a/2, -b, -c/2) * log2(e), so that
-// p2 = A dx^2 + B dx dy + C dy^2 = log2(e) * power and G = exp(power) = 2^p2.
+// The splat record holds the conic Q = [[a, b], [b, c]] in its LDL^T form
+// (a, beta = b/a, delta = det Q / a), so that
+// d^T Q d = a (dx + beta dy)^2 + delta dy^2: a sum of two non-negative
+// terms.  (Summing a dx^2 + 2 b dx dy + c dy^2 cancels far along a thin
+// splat, where the terms are many thousand times the result; the FP32
+// alpha there would carry percent-level errors.)  Staged: A = -a/2 log2(e),
+// beta, D = -delta/2 log2(e), so p2 = A w^2 + D dy^2 with w = dx + beta dy is
+// log2(e) * power and G = exp(power) = 2^p2.
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kUnroll = 8;   // forward: alphas evaluated per group
 constexpr int kUnrollB = 2;  // backward
 
-__device__ __forceinline__ float splat_exponent(float dx, float dy, float A, float Bq, float C) {
+__device__ __forceinline__ float splat_exponent(float dx, float dy, float A, float beta, float D) {
 #pragma clang fp contract(off)
-  const float xx = dx * dx, yy = dy * dy, xy = dx * dy;
-  return __builtin_fmaf(A, xx, __builtin_fmaf(C, yy, Bq * xy));
+  const float w = __builtin_fmaf(beta, dy, dx);
+  const float ww = w * w, yy = dy * dy;
+  return __builtin_fmaf(A, ww, D * yy);
 }
 
 // The same exponent (same operations, bit-identical), also returning the
 // products dx^2, dx dy, dy^2 for the conic gradient.
-__device__ __forceinline__ float splat_exponent_p(float dx, float dy, float A, float Bq, float C, float& xx,
+__device__ __forceinline__ float splat_exponent_p(float dx, float dy, float A, float beta, float D, float& xx,
                                                   float& xy, float& yy) {
 #pragma clang fp contract(off)
   xx = dx * dx;
   yy = dy * dy;
   xy = dx * dy;
-  return __builtin_fmaf(A, xx, __builtin_fmaf(C, yy, Bq * xy));
+  const float w = __builtin_fmaf(beta, dy, dx);
+  const float ww = w * w;
+  return __builtin_fmaf(A, ww, D * yy);
 }
 
 // alpha = min(alpha_max, o G); ok = exponent <= 0 and alpha >= alpha_min.
@@ -109,21 +118,23 @@ __device__ __forceinline__ PixelSlot pixel_of(const RasterArgs& a, int slot, int
 // registers; the next batch's loads are issued before the current batch is
 // evaluated, so their latency overlaps the compute.
 struct Staged {
-  float4 geo;  // tile-local centre x, y; staged conic A, B
-  float4 app;  // staged conic C, opacity, r, g
+  float4 geo;  // tile-local centre x, y; staged A, beta
+  float4 app;  // staged D, opacity, r, g
   float4 con;  // conic a, b, c in natural units, blue (backward only)
   float blue;
   uint32_t gid;
 };
 
 __device__ __forceinline__ Staged stage_load(const RasterArgs& a, uint32_t gid, float x0, float y0) {
+#pragma clang fp contract(off)
   const float4 p0 = a.splat[3 * gid], p1 = a.splat[3 * gid + 1], p2 = a.splat[3 * gid + 2];
   Staged st;
   // exact integer difference first, then the fraction: the tile-local centre
   // keeps full FP32 precision relative to the pixel offsets
-  st.geo = make_float4((p0.x - x0) + p0.z, (p0.y - y0) + p0.w, p1.x * (-0.5f * kLog2e), p1.y * -kLog2e);
+  st.geo = make_float4((p0.x - x0) + p0.z, (p0.y - y0) + p0.w, p1.x * (-0.5f * kLog2e), p1.y);
   st.app = make_float4(p1.z * (-0.5f * kLog2e), p1.w, p2.x, p2.y);
-  st.con = make_float4(p1.x, p1.y, p1.z, p2.z);
+  const float b = p1.y * p1.x;  // b = beta a, c = delta + beta b
+  st.con = make_float4(p1.x, b, __builtin_fmaf(p1.y, b, p1.z), p2.z);
   st.blue = p2.z;
   st.gid = gid;
   return st;

@@ -93,101 +93,160 @@ __global__ void __launch_bounds__(256) tile_pred_weights_kernel(const float* __r
 
 // ------------------------------------------------------------------ tile select
 // One workgroup.  The sequential tile draws (only when a subset of tiles is
-// drawn) run on the first wave, whose lane l owns tiles [l * chunk,
-// (l + 1) * chunk); then the whole workgroup lists the chosen tiles in
-// ascending order with their sample counts and prefix offsets.
+// drawn) run on the first wave; then the whole workgroup lists the chosen
+// tiles in ascending order with their sample counts and prefix offsets.
 constexpr int kSelectThreads = 1024;
-constexpr int kSelectLdsTiles = 7168;  // up to this many tiles the draws run on LDS copies (9 B per tile)
+constexpr uint64_t kChosenBit = 1ull << 63;  // tile weights stay below 2^57 (256 pixels x 2^24 x 65504)
+constexpr int kSelectMaxE = 5;               // tiles per lane in a chunk pass: n_t up to 20480 in LDS
 
-// The draws with the weights and chosen flags in LDS (first wave only).  The
-// lanes' inclusive prefix of their chunk sums is kept up to date instead of
-// being rescanned: a draw r falls in the first lane whose inclusive sum
-// exceeds r; the whole wave then scans that lane's chunk (64 tiles per round)
-// for the first tile whose running sum exceeds r.  The tile found is the one
-// of the sequential definition (ascending tile order), so the draws equal the
-// plain loop's.
-__device__ void select_tiles_lds(uint64_t* s_w, uint8_t* s_c, const uint64_t* __restrict__ tw, int n_t,
-                                 int n_sel, uint64_t key, uint8_t* __restrict__ chosen) {
+// The draws on LDS (first wave only).  s_p[t] holds, for tile t in chunk
+// [l C, (l + 1) C), the remaining weight of the chunk's tiles up to and
+// including t (a chunk-local inclusive prefix), with bit 63 set once t is
+// chosen; s_lsum[l] the chunk's total.  Lane l keeps its chunk's remaining
+// weight and the inclusive prefix of those over the lanes up to date.  A
+// draw r falls in the first lane o whose inclusive sum exceeds r; in o's
+// chunk the tile is the first whose prefix exceeds r minus the chunks
+// before, found by one ballot over the lanes (lane k holds the prefixes of
+// tiles k E .. k E + E - 1, E = ceil(C / 64)) and a walk over E registers.
+// Removing the tile lowers the prefixes from it to the chunk's end, written
+// back from the registers that were read.  That is the first tile in
+// ascending order whose running weight exceeds r, as the sequential
+// definition has it, so the draws equal the plain loop's.  When every
+// remaining weight is zero (all prefixes are then zero) the draw is uniform
+// over the remaining tiles and is found on counts of the unchosen tiles.
+// The draws' 64-bit counter values are hashed 64 at a time, one per lane.
+template <int kE>
+__device__ void select_tiles_lds(uint64_t* s_p, const uint64_t* s_lsum, int n_t, int n_sel, uint64_t key) {
   const int lane = lane_id();
-  const int chunk = (n_t + kWave - 1) / kWave;
-  const int c0 = min(n_t, lane * chunk), c1 = min(n_t, c0 + chunk);
-  uint64_t lsum = 0;
-  for (int t = c0; t < c1; ++t) {
-    const uint64_t x = tw[t];
-    s_w[t] = x;
-    s_c[t] = 0;
-    lsum += x;
-  }
+  const int C = (n_t + kWave - 1) / kWave;
+  const int c0 = min(n_t, lane * C), c1 = min(n_t, c0 + C);
+  uint64_t lsum = s_lsum[lane];
   int lrem = c1 - c0;
-  uint64_t incl = wave_inclusive_scan_u64(lsum);
-  int icnt = wave_inclusive_scan_i(lrem);
+  uint64_t incl = wave_inclusive_scan_u64_dpp(lsum);
+  int icnt = wave_inclusive_scan_i_dpp(lrem);
+  uint64_t ub = 0;
   for (int j = 0; j < n_sel; ++j) {
-    const uint64_t u = absorb(key, (uint64_t)j);
-    const uint64_t total = __shfl(incl, 63, kWave);
-    int pick = -1;
+    if ((j & (kWave - 1)) == 0) ub = absorb(key, (uint64_t)(j + lane));
+    const uint64_t u = readlane_u64(ub, j & (kWave - 1));
+    const uint64_t total = readlane_u64(incl, kWave - 1);
     if (total > 0) {
       const uint64_t r = mulhi64(u, total);
-      const int o = __ffsll((unsigned long long)__ballot(incl > r)) - 1;  // owner lane (incl[63] > r)
-      const int oc0 = min(n_t, max(o, 0) * chunk), olen = o < 0 ? 0 : min(n_t, oc0 + chunk) - oc0;
-      uint64_t base = __shfl(incl, max(o, 0), kWave) - __shfl(lsum, max(o, 0), kWave);
-      for (int s0 = 0; s0 < olen; s0 += kWave) {
-        const int k = s0 + lane;
-        const uint64_t run = base + wave_inclusive_scan_u64(k < olen ? s_w[oc0 + k] : 0ull);
-        const uint64_t hit = __ballot(k < olen && run > r);
-        if (hit != 0ull) {
-          pick = oc0 + s0 + __ffsll((unsigned long long)hit) - 1;
-          break;
-        }
-        base = __shfl(run, 63, kWave);
+      const uint64_t above = __ballot(incl > r);
+      if (above == 0ull) break;  // never taken: the running sums are exact
+      const int o = __ffsll((unsigned long long)above) - 1;
+      const uint64_t rp = r - readlane_u64(incl - lsum, o);
+      const int oc0 = o * C, olen = min(n_t, oc0 + C) - oc0;
+      // this lane's prefixes (positions past the chunk read its last one,
+      // which exceeds rp, so they never come before the true crossing)
+      uint64_t raw[kE], P[kE];
+#pragma unroll
+      for (int e = 0; e < kE; ++e) {
+        raw[e] = s_p[oc0 + min(lane * kE + e, olen - 1)];
+        P[e] = raw[e] & ~kChosenBit;
       }
-    } else {  // every remaining weight is zero: uniform over the remaining tiles
-      const int nrem = __shfl(icnt, 63, kWave);
-      const int r = (int)mulhi64(u, (uint64_t)nrem);
-      const int o = __ffsll((unsigned long long)__ballot(icnt > r)) - 1;  // icnt[63] = nrem > r
-      const int oc0 = min(n_t, max(o, 0) * chunk), olen = o < 0 ? 0 : min(n_t, oc0 + chunk) - oc0;
-      int base = __shfl(icnt, max(o, 0), kWave) - __shfl(lrem, max(o, 0), kWave);
-      for (int s0 = 0; s0 < olen; s0 += kWave) {
-        const int k = s0 + lane;
-        const int run = base + wave_inclusive_scan_i(k < olen && s_c[oc0 + k] == 0 ? 1 : 0);
-        const uint64_t hit = __ballot(k < olen && s_c[oc0 + k] == 0 && run > r);
-        if (hit != 0ull) {
-          pick = oc0 + s0 + __ffsll((unsigned long long)hit) - 1;
-          break;
+      // lane of the crossing (the chunk's last prefix exceeds rp, so some
+      // lane's does; no branch here, so the loads above issue together)
+      const int h = max(0, __ffsll((unsigned long long)__ballot(P[kE - 1] > rp)) - 1);
+      const uint64_t prev_last = dpp_u64<kDppWaveShr1>(P[kE - 1]);  // lane 0 reads 0: the chunk starts at 0
+      int pe = kE - 1;
+      uint64_t wv = P[kE - 1] - (kE > 1 ? P[kE > 1 ? kE - 2 : 0] : prev_last);
+#pragma unroll
+      for (int e = kE - 2; e >= 0; --e) {
+        if (P[e] > rp) {
+          pe = e;
+          wv = P[e] - (e > 0 ? P[e > 0 ? e - 1 : 0] : prev_last);
         }
-        base = __shfl(run, 63, kWave);
       }
-    }
-    if (pick < 0 || pick >= n_t) continue;  // never taken (the sums are consistent); keeps accesses in bounds
-    const uint64_t wp = s_w[pick];          // wave-uniform; read before lane 0 clears it
-    const int owner = pick / chunk;
-    if (lane >= owner) {
-      incl -= wp;
-      icnt -= 1;
-    }
-    if (lane == owner) {
-      lsum -= wp;
-      lrem -= 1;
-    }
-    if (lane == 0) {
-      s_w[pick] = 0;
-      s_c[pick] = 1;
+      const int pl = h * kE + __builtin_amdgcn_readlane(pe, h);  // chunk-local position of the pick
+      const uint64_t w = readlane_u64(wv, h);
+#pragma unroll
+      for (int e = 0; e < kE; ++e) {
+        const int idx = lane * kE + e;
+        if (idx >= pl && idx < olen) s_p[oc0 + idx] = (raw[e] - w) | (idx == pl ? kChosenBit : 0ull);
+      }
+      if (lane >= o) incl -= w;
+      if (lane == o) lsum -= w;
+      if (lane >= o) icnt -= 1;
+      if (lane == o) lrem -= 1;
+    } else {
+      // every remaining weight is zero: the r-th remaining tile, on counts
+      const uint64_t nrem = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(icnt, kWave - 1);
+      if (nrem == 0) break;
+      const int r = (int)mulhi64(u, nrem);
+      const uint64_t above = __ballot(icnt > r);
+      const int o = __ffsll((unsigned long long)above) - 1;
+      const int base = __builtin_amdgcn_readlane(icnt - lrem, o);
+      const int oc0 = o * C, olen = min(n_t, oc0 + C) - oc0;
+      int fl[kE], part = 0;
+#pragma unroll
+      for (int e = 0; e < kE; ++e) {
+        const int idx = lane * kE + e;
+        fl[e] = idx < olen && (s_p[oc0 + min(idx, olen - 1)] & kChosenBit) == 0 ? 1 : 0;
+        part += fl[e];
+      }
+      const int run = base + wave_inclusive_scan_i_dpp(part);
+      const uint64_t hit = __ballot(run > r);
+      if (hit == 0ull) break;  // never taken
+      const int h = __ffsll((unsigned long long)hit) - 1;
+      int acc = run - part, pe = -1;
+#pragma unroll
+      for (int e = 0; e < kE; ++e) {
+        acc += fl[e];
+        if (pe < 0 && acc > r) pe = e;
+      }
+      const int pl = h * kE + __builtin_amdgcn_readlane(pe, h);
+      if (lane == h && pl < olen) s_p[oc0 + pl] |= kChosenBit;
+      if (lane >= o) icnt -= 1;
+      if (lane == o) lrem -= 1;
     }
   }
-  for (int t = c0; t < c1; ++t) chosen[t] = s_c[t];
+}
+
+// The chunk-local prefixes of the tile weights into s_p and the chunk
+// totals into s_lsum: wave w takes chunks w, w + 16, ..., 64 tiles at a
+// time (coalesced reads), the chunk boundaries being the first wave's lane
+// chunks.
+__device__ void chunk_prefixes(const uint64_t* __restrict__ tw, uint64_t* s_p, uint64_t* s_lsum, int n_t) {
+  const int C = (n_t + kWave - 1) / kWave;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  for (int l = w; l < kWave; l += kSelectThreads / kWave) {
+    const int c0 = min(n_t, l * C), c1 = min(n_t, c0 + C);
+    uint64_t carry = 0;
+    for (int t0 = c0; t0 < c1; t0 += kWave) {
+      const int t = t0 + lane;
+      const uint64_t x = wave_inclusive_scan_u64_dpp(t < c1 ? tw[t] : 0ull);
+      if (t < c1) s_p[t] = carry + x;
+      carry += readlane_u64(x, kWave - 1);
+    }
+    if (lane == 0) s_lsum[l] = carry;
+  }
 }
 
 __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
     uint64_t* __restrict__ tw, int H, int W, int tiles_x, int n_t, int n_sel, int n_pix,
     uint64_t seed, uint64_t step, uint64_t view, int32_t* __restrict__ valid_tiles,
     int32_t* __restrict__ tile_off, int32_t* __restrict__ tile_slot, int64_t* __restrict__ totals,
-    uint8_t* __restrict__ chosen) {
-  extern __shared__ uint64_t s_sel[];  // [n_t] weights, then [n_t] flags, when n_t <= kSelectLdsTiles
+    uint8_t* __restrict__ chosen, int lds_tiles) {
+  extern __shared__ uint64_t s_sel[];  // [n_t] chunk prefixes and chosen bits, when n_t <= lds_tiles
+  __shared__ uint64_t s_lsum[kWave];
   const int tid = threadIdx.x;
   const bool all_tiles = n_sel < 0 || n_sel >= n_t;
-  if (!all_tiles && tid < kWave && n_t <= kSelectLdsTiles) {
-    select_tiles_lds(s_sel, (uint8_t*)(s_sel + n_t), tw, n_t, n_sel, stream_key(seed, step, view, (uint64_t)n_t),
-                     chosen);
+  const bool in_lds = !all_tiles && n_t <= lds_tiles;
+  if (in_lds) {
+    chunk_prefixes(tw, s_sel, s_lsum, n_t);
+    __syncthreads();
+    if (tid < kWave) {
+      const uint64_t key = stream_key(seed, step, view, (uint64_t)n_t);
+      switch ((n_t + kWave * kWave - 1) / (kWave * kWave)) {  // tiles per lane in a chunk pass
+        case 1: select_tiles_lds<1>(s_sel, s_lsum, n_t, n_sel, key); break;
+        case 2: select_tiles_lds<2>(s_sel, s_lsum, n_t, n_sel, key); break;
+        case 3: select_tiles_lds<3>(s_sel, s_lsum, n_t, n_sel, key); break;
+        case 4: select_tiles_lds<4>(s_sel, s_lsum, n_t, n_sel, key); break;
+        default: select_tiles_lds<5>(s_sel, s_lsum, n_t, n_sel, key); break;
+      }
+    }
   } else if (!all_tiles && tid < kWave) {
+    // more tiles than LDS holds: each lane walks its own chunk in global memory
     const int lane = tid;
     const int chunk = (n_t + kWave - 1) / kWave;
     const int c0 = min(n_t, lane * chunk), c1 = min(n_t, c0 + chunk);
@@ -244,7 +303,7 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
   const int c0 = min(n_t, tid * chunk), c1 = min(n_t, c0 + chunk);
   uint32_t lcount = 0, lpix = 0;
   for (int t = c0; t < c1; ++t)
-    if (all_tiles || chosen[t]) {
+    if (all_tiles || (in_lds ? (s_sel[t] & kChosenBit) != 0 : chosen[t] != 0)) {
       ++lcount;
       lpix += (uint32_t)min(n_pix, tile_valid_w(t % tiles_x, W) * tile_valid_h(t / tiles_x, H));
     }
@@ -252,7 +311,7 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
   int slot = (int)block_exclusive_scan<kSelectThreads, uint32_t>(lcount, lds, &n_chosen);
   int off = (int)block_exclusive_scan<kSelectThreads, uint32_t>(lpix, lds, &P);
   for (int t = c0; t < c1; ++t) {
-    if (all_tiles || chosen[t]) {
+    if (all_tiles || (in_lds ? (s_sel[t] & kChosenBit) != 0 : chosen[t] != 0)) {
       valid_tiles[slot] = t;
       tile_off[slot] = off;
       tile_slot[t] = slot;
@@ -423,6 +482,33 @@ extern "C" size_t tgs_sample_workspace_size(int32_t height, int32_t width) {
   return align_up(n_t * sizeof(uint64_t), 256) + align_up(n_t, 256);
 }
 
+// Tiles whose weights the draws can hold in LDS on the current device: the
+// workgroup's LDS limit (160 KiB on gfx950) less the kernel's static arrays,
+// 8 bytes per tile, at most what a chunk pass covers (64 x 64 x kSelectMaxE).
+// Queried, and the kernel's dynamic LDS limit raised, once per device.
+static int select_lds_tiles() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static int cache[kMaxDevices];
+  static bool known[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!known[dev]) {
+    int bytes = 0;
+    if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) bytes = 0;
+    int dyn = bytes - 2048;  // static LDS of the kernel (chunk sums, scan partials) with margin
+    if (dyn > 65536 && hipFuncSetAttribute((const void*)tile_select_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) {
+      (void)hipGetLastError();
+      dyn = 65536 - 2048;
+    }
+    cache[dev] = max(0, min(dyn / (int)sizeof(uint64_t), kWave * kWave * kSelectMaxE));
+    known[dev] = true;
+  }
+  return cache[dev];
+}
+
 static int32_t sample_impl(const uint16_t* E, const uint16_t* A, int32_t height, int32_t width,
                            const tgs_sample_params* sp, const float* tile_pred, int32_t* valid_tiles,
                            int32_t* tile_off, uint8_t* pix, int32_t* tile_slot, int64_t* totals, void* ws,
@@ -453,10 +539,11 @@ static int32_t sample_impl(const uint16_t* E, const uint16_t* A, int32_t height,
   else if (!all_tiles)
     hipLaunchKernelGGL(tile_weights_kernel, dim3(n_t), dim3(64), 0, s, E, height, width, tiles_x,
                        n_t, tw);
-  const size_t sel_lds = !all_tiles && n_t <= kSelectLdsTiles ? (size_t)n_t * 9 : 0;
+  const int lds_tiles = select_lds_tiles();
+  const size_t sel_lds = !all_tiles && n_t <= lds_tiles ? (size_t)n_t * sizeof(uint64_t) : 0;
   hipLaunchKernelGGL(tile_select_kernel, dim3(1), dim3(kSelectThreads), sel_lds, s, tw, height, width,
                      tiles_x, n_t, sp->n_tiles_sel, sp->n_pix, sp->seed, sp->step,
-                     (uint64_t)sp->view, valid_tiles, tile_off, tile_slot, totals, chosen);
+                     (uint64_t)sp->view, valid_tiles, tile_off, tile_slot, totals, chosen, lds_tiles);
   if (n_st > 0)
     hipLaunchKernelGGL(tile_pixels_kernel, dim3(n_st), dim3(64), 0, s, E, A, height, width, tiles_x,
                        n_st, sp->n_pix, sp->hard_permille, sp->stable_permille, sp->seed, sp->step,

@@ -96,7 +96,25 @@ class ViewBuffers:
         # per-pixel (T, colour) at the backward's chunk starts, kept by the forward
         n_state = B.tgs_render_state_size(self.n_st, self.n_pix) // 4
         self.state = torch.empty(max(n_state, 4), dtype=torch.float32, device=dev)
+        self.counts = torch.zeros(2, dtype=torch.int64, device=dev)   # (list length, capacity needed)
+        self._n_pairs = 0
+        self.sized = False   # whether a bin/sort has run to completion here (the capacity then fits a view)
         self._alloc_pairs(capacity if capacity is not None else max(1 << 16, 8 * n))
+
+    @property
+    def n_pairs(self) -> int:
+        """Pairs in the lists of the last bin/sort (reads the device count
+        after an asynchronous one; raises CapacityError if it overflowed)."""
+        if self._n_pairs is None:
+            valid, need = (int(x) for x in self.counts.cpu().tolist())
+            if need > self.capacity:
+                raise B.CapacityError(f"pair lists need {need} entries, capacity {self.capacity}", need)
+            self._n_pairs = valid
+        return self._n_pairs
+
+    @n_pairs.setter
+    def n_pairs(self, v: int):
+        self._n_pairs = v
 
     def _alloc_pairs(self, capacity: int):
         dev = self.splat.device
@@ -123,16 +141,26 @@ class ViewBuffers:
         return self.tile_slot is not None and self.n_st < self.n_t
 
     def bin_sort(self, touched=None, alpha_min: float = 1.0 / 255.0) -> int:
+        """Bin and sort, waiting for the count: grows the pair arrays and
+        repeats when they are too small.  Returns the list length."""
+        while True:
+            self.bin_sort_async(touched, alpha_min)
+            valid, need = (int(x) for x in self.counts.cpu().tolist())
+            if need <= self.capacity:
+                self.n_pairs = valid
+                self.sized = True
+                return valid
+            self._alloc_pairs(int(need * 1.5) + 1024)
+
+    def bin_sort_async(self, touched=None, alpha_min: float = 1.0 / 255.0):
+        """Bin and sort without a host wait (tgs_bin_sort_async); the counts
+        stay on the device until n_pairs is read."""
         # every tile is valid when the sampler keeps all of them: no tile map needed
         tile_slot = self.tile_slot if self.bin_sort_needs_samples() else None
-        while True:
-            try:
-                self.n_pairs = B.tgs_bin_sort(self.rect, self.splat, self.depth, self.n, tile_slot, self.tiles_x,
-                                              self.tiles_y, alpha_min, self.keys, self.vals, self.capacity,
-                                              self.ranges, touched, self.sort_ws)
-                return self.n_pairs
-            except B.CapacityError as e:
-                self._alloc_pairs(int(e.required * 1.25) + 1024)
+        B.tgs_bin_sort_async(self.rect, self.splat, self.depth, self.n, tile_slot, self.tiles_x, self.tiles_y,
+                             alpha_min, self.keys, self.vals, self.capacity, self.ranges, touched, self.counts,
+                             self.sort_ws)
+        self._n_pairs = None
 
     def render_fwd(self, rp, counters=None):
         B.tgs_render_fwd(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
@@ -162,13 +190,14 @@ class ViewBuffers:
         if deterministic:
             if stats is not None:
                 raise ValueError("the deterministic backward has no density-control variant")
-            need = B.tgs_render_bwd_det_workspace_size(self.n_pairs, self.n_pix, self.dense)
+            pairs = self.n_pairs
+            need = B.tgs_render_bwd_det_workspace_size(pairs, self.n_pix, self.dense)
             if getattr(self, "det_ws", None) is None or self.det_ws.numel() < need:
                 self.det_ws = torch.empty(need, dtype=torch.uint8, device=self.splat.device)
             B.tgs_render_bwd_deterministic(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                                            self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st,
                                            self.n_pix, rp, self.out, self.ncontrib, self.dL, self.g2d, self.state,
-                                           touched, self.depth, self.rect, self.n, self.n_pairs, self.det_ws)
+                                           touched, self.depth, self.rect, self.n, pairs, self.det_ws)
             return
         if stats is not None:
             B.tgs_render_bwd_density(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
@@ -244,6 +273,8 @@ class Trainer:
     """Gaussians, optimizer state and per-view buffers for sparse (or dense)
     training steps over a fixed set of cameras."""
 
+    SAMPLE_STREAMS = 4   # streams the views' samplers are spread over
+
     def __init__(self, params: torch.Tensor, cams, gts, cfg: StepConfig, E=None, A=None):
         if cfg.deterministic and cfg.density_stats:
             raise ValueError("the deterministic backward has no density-control variant")
@@ -283,8 +314,10 @@ class Trainer:
             self.tiles = TilePriority(len(self.cams), n_t, cfg, self.dev)
         # cross-stream events, recorded anew each step (a wait binds to the
         # record queued before it)
-        self._sampled = torch.cuda.Event()
+        self._sampled: list = []           # per view slot: its sampler's completion
+        self._sample_streams: list = []
         self._lossed = torch.cuda.Event()
+        self._pending: list = []   # (event, pinned counts, [(view buffers, capacity)]) per step
 
     def _stage(self, name):
         """Brackets a stage with HIP events on the current stream when timing."""
@@ -345,6 +378,7 @@ class Trainer:
     def step(self, views, rate_permille: int | None = None) -> list:
         """One training step over ``views`` (at ``rate_permille`` if given,
         else the configured rate); returns the per-view buffers."""
+        self.check_counts()
         self.step_count += 1
         t = self.step_count
         views = list(views)
@@ -355,40 +389,55 @@ class Trainer:
         used = [self.buffers(slot, self.cams[v], rate_permille) for slot, v in enumerate(views)]
         slot_of = {id(vb): k for k, vb in enumerate(used)}
         self.touched.zero_()
-        # the sample totals are cleared and the samplers run on the side
-        # stream (which sees everything queued on main so far), beside the
-        # first projection
-        side.wait_stream(main)
-        sampled, lossed = self._sampled, self._lossed
-        with torch.cuda.stream(side):
-            self.totals.zero_()
-            for vb, v in zip(used, views):
+        # the sample totals are cleared (dense views' counts added) on main;
+        # then each sparse view's sampler runs on a stream of its own (which
+        # sees everything queued on main so far), so the views' tile passes
+        # run side by side and beside the first projection
+        self.totals.zero_()
+        for vb, v in zip(used, views):
+            if vb.dense:
+                self.totals[0] += self.cams[v].width * self.cams[v].height
+                self.totals[1] += vb.n_t
+        sampled = []
+        for k, (vb, v) in enumerate(zip(used, views)):
+            if vb.dense:
+                sampled.append(None)
+                continue
+            ss = self._sample_stream(k)
+            ss.wait_stream(main)
+            with torch.cuda.stream(ss):
                 cam = self.cams[v]
-                if vb.dense:
-                    self.totals[0] += cam.width * cam.height
-                    self.totals[1] += vb.n_t
-                else:
-                    pred = None
-                    if self.tiles is not None:
-                        pred = self.tiles.predict(slot_of[id(vb)], v, self.E[v], self.A[v], vb, cam)
-                    with st("sample"):
-                        vb.sample(self.E[v], self.A[v], self.cfg, t, v, self.totals, tile_pred=pred)
-        sampled.record(side)
-        waited = False
+                pred = None
+                if self.tiles is not None:
+                    pred = self.tiles.predict(slot_of[id(vb)], v, self.E[v], self.A[v], vb, cam)
+                with st("sample"):
+                    vb.sample(self.E[v], self.A[v], self.cfg, t, v, self.totals, tile_pred=pred)
+                while len(self._sampled) <= k:
+                    self._sampled.append(torch.cuda.Event())
+                ev = self._sampled[k]
+                ev.record(ss)
+            sampled.append(ev)
+        lossed = self._lossed
+        all_waited = False
         for k, (vb, v) in enumerate(zip(used, views)):
             cam = self.cams[v]
             with st("project"):
                 vb.project(self.params, cam, self.rp)
-            if not waited and vb.bin_sort_needs_samples():
-                main.wait_event(sampled)
-                waited = True
+            if sampled[k] is not None:
+                main.wait_event(sampled[k])   # this view's samples (the binning and render need them)
             with st("bin_sort"):
-                vb.bin_sort(None, self.rp.alpha_min)
-            if not waited:
-                main.wait_event(sampled)
-                waited = True
+                if vb.sized:
+                    vb.bin_sort_async(None, self.rp.alpha_min)   # no host wait
+                else:
+                    vb.bin_sort(None, self.rp.alpha_min)         # sizes the pair arrays once per slot
             with st("render_fwd"):
                 vb.render_fwd(self.rp, self.counters)
+            if not all_waited:
+                # the loss normalises by the step's total sample count
+                for ev in sampled:
+                    if ev is not None:
+                        main.wait_event(ev)
+                all_waited = True
             with st("loss"):
                 vb.loss(self.gts[v], self.totals, self.lp)
             if not vb.dense:
@@ -420,7 +469,46 @@ class Trainer:
             with st("optimizer"):
                 B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
         main.wait_stream(side)
+        self._queue_count_check(used)
         return used
+
+    def _sample_stream(self, k: int):
+        """Stream of the k-th view's sampler (default priority; a few reused
+        round-robin)."""
+        while len(self._sample_streams) < min(k + 1, self.SAMPLE_STREAMS):
+            self._sample_streams.append(torch.cuda.Stream(device=self.dev))
+        return self._sample_streams[k % self.SAMPLE_STREAMS]
+
+    # ---- pair-capacity watch: the asynchronous bin/sort reports its counts on
+    # the device; they are copied to pinned host memory after each step and
+    # read two steps later (by then the device has finished that step), so
+    # the step loop never waits for them.  A view whose lists needed more
+    # than 85% of its capacity gets larger pair arrays before its next step;
+    # one that overflowed (its lists came out empty) raises.
+    _COUNT_LAG = 2
+
+    def _queue_count_check(self, used):
+        if not used:
+            return
+        host = torch.empty((len(used), 2), dtype=torch.int64, pin_memory=True)
+        for k, vb in enumerate(used):
+            host[k].copy_(vb.counts, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        self._pending.append((ev, host, [(vb, vb.capacity) for vb in used]))
+
+    def check_counts(self, wait_all: bool = False):
+        """Reads the pending pair counts that are due (all of them with
+        ``wait_all``), growing capacities and raising on an overflow."""
+        while self._pending and (wait_all or len(self._pending) > self._COUNT_LAG or self._pending[0][0].query()):
+            ev, host, entries = self._pending.pop(0)
+            ev.synchronize()
+            for (vb, cap), (valid, need) in zip(entries, host.tolist()):
+                if need > cap:
+                    raise B.CapacityError(f"a step's pair lists needed {need} entries but had {cap}: that step "
+                                          f"rendered empty lists and must be redone with a larger capacity", need)
+                if vb.capacity == cap and need > 0.85 * cap:
+                    vb._alloc_pairs(int(1.5 * need) + 1024)
 
     def reset_density(self):
         """Clears the density-control sums (the start of an accumulation window)."""

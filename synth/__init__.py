@@ -136,6 +136,36 @@ def hemisphere_cameras(n: int, radius: float = 3.0, width: int = 1600, height: i
     return cams
 
 
+def corridor_gaussians(n: int, seed: int = SEED_SCENE, length: float = 50.0, width: float = 8.0,
+                       height: float = 3.0, logscale_mean: float = -4.0) -> np.ndarray:
+    """Random Gaussians filling a corridor along the x axis: means uniform in
+    [-length/2, length/2] x [-width/2, width/2] x [-height/2, height/2], the
+    other distributions as in ``gaussians``.  Float32 [59, n]."""
+    p = gaussians(n, seed, logscale_mean=logscale_mean)
+    rng = np.random.default_rng(seed + 1000)
+    p[0] = rng.uniform(-length / 2, length / 2, n)
+    p[1] = rng.uniform(-width / 2, width / 2, n)
+    p[2] = rng.uniform(-height / 2, height / 2, n)
+    return p
+
+
+def trajectory_cameras(n: int, length: float = 50.0, offset: float = 6.0, elevation: float = 1.5,
+                       width: int = 1920, height: int = 1080, focal: float = 1100.0) -> list[Camera]:
+    """``n`` cameras spread along a 50-unit trajectory beside the corridor:
+    x from -length/2 to length/2, alternately on either side (y = -+offset)
+    at z = elevation with a slow sinusoidal sway, each looking at the
+    corridor's axis a little ahead of itself."""
+    cams = []
+    for i in range(n):
+        x = -length / 2 + length * (i + 0.5) / n
+        side = -1.0 if i % 2 == 0 else 1.0
+        y = side * offset * (1.0 + 0.1 * math.sin(0.7 * i))
+        z = elevation + 0.5 * math.sin(0.31 * i)
+        cams.append(look_at((x, y, z), (x + 1.5 * math.sin(0.13 * i), 0.0, 0.0), fx=focal, fy=focal,
+                            width=width, height=height))
+    return cams
+
+
 def config_camera(name: str) -> Camera:
     """The single view of the rasterizer-scaling workload (1296x840, focal kept
     from the 256x256/f=300 field of view) or a tetrahedron view."""

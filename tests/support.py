@@ -31,6 +31,24 @@ def small_scene(n=400, seed=21, W=150, H=107):
     return p, cam
 
 
+def ldl_conic(conic: np.ndarray) -> np.ndarray:
+    """The record's conic form: Q = [[a, b], [b, c]] as (a, beta = b / a,
+    delta = c - b beta), so that d^T Q d = a (dx + beta dy)^2 + delta dy^2
+    (zero where a is not positive)."""
+    a, b, c = (np.asarray(conic[i], dtype=np.float64) for i in range(3))
+    ok = a > 0
+    beta = np.where(ok, b / np.where(ok, a, 1.0), 0.0)
+    delta = np.where(ok, c - b * beta, 0.0)
+    return np.stack([a, beta, delta])
+
+
+def natural_conic(rec: np.ndarray) -> np.ndarray:
+    """(a, b, c) from the record's FP32 (a, beta, delta), in FP64."""
+    a, beta, delta = (rec[:, 4 + i].astype(np.float64) for i in range(3))
+    b = beta * a
+    return np.stack([a, b, delta + beta * b])
+
+
 def splat_record(pr: dict) -> np.ndarray:
     """The library's [N, 12] splat record built from an oracle projection."""
     N = pr["opacity"].size
@@ -39,7 +57,7 @@ def splat_record(pr: dict) -> np.ndarray:
     fx, fy = np.floor(px), np.floor(py)
     s[:, 0], s[:, 1] = fx, fy
     s[:, 2], s[:, 3] = px - fx, py - fy
-    s[:, 4:7] = pr["conic"].T
+    s[:, 4:7] = ldl_conic(pr["conic"]).T
     s[:, 7] = pr["opacity"]
     s[:, 8:11] = pr["rgb"].T
     s[:, 11] = pr["depth32"]
@@ -53,7 +71,7 @@ def splat_as_oracle(pr: dict, rec: np.ndarray) -> dict:
     widened back to FP64 (so both sides composite identical splats)."""
     q = dict(pr)
     q["mean2d"] = np.stack([rec[:, 0].astype(np.float64) + rec[:, 2], rec[:, 1].astype(np.float64) + rec[:, 3]])
-    q["conic"] = rec[:, 4:7].T.astype(np.float64)
+    q["conic"] = natural_conic(rec)
     q["opacity"] = rec[:, 7].astype(np.float64)
     q["rgb"] = rec[:, 8:11].T.astype(np.float64)
     return q

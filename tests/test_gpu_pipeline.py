@@ -266,6 +266,41 @@ def test_deterministic_backward_repeats_bit_for_bit(B, c1_inputs, dense):
         assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
 
 
+def test_trainer_async_binning_equals_blocking_binning(B, c1_inputs):
+    """Five deterministic two-view steps whose binning waits for its counts
+    every step and five whose binning queues without waiting after the
+    first step of each view slot (with pair capacities cut to 1.05 times the
+    need, which the counts watch must grow) give the same parameters,
+    moments and maps bit for bit; the watch reads every step's counts."""
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    p, cams, gts, E, A = c1_inputs
+    res = []
+    for blocking in (True, False):
+        # every tile sampled: a view's lists change only as the parameters move
+        cfg = StepConfig(rate_permille=250, seed=3, deterministic=True)
+        Eg = [dev(e.view(np.int16)) for e in E]
+        Ag = [dev(a.view(np.int16)) for a in A]
+        tr = Trainer(dev(p), cams, [dev(g) for g in gts], cfg, E=Eg, A=Ag)
+        for t in range(5):
+            if blocking:
+                for vb in tr._bufs.values():
+                    vb.sized = False
+            tr.step([1, 2])
+            if t == 1 and not blocking:
+                for vb in tr._bufs.values():   # tight capacities: the watch has to grow them
+                    vb._alloc_pairs(int(vb.n_pairs * 1.05) + 64)
+                caps = [vb.capacity for vb in tr._bufs.values()]
+        tr.check_counts(wait_all=True)
+        assert not tr._pending
+        res.append([host(x).copy() for x in (tr.params, tr.m, tr.v, *Eg, *Ag)])
+        if not blocking:
+            assert all(vb.sized for vb in tr._bufs.values())
+            assert all(vb.capacity > c for vb, c in zip(tr._bufs.values(), caps))
+        del tr
+    for x, y in zip(*res):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
 def test_c1_step_density_sums_match_oracle(B, c1_inputs):
     """A four-view step with the density sums in the backward: per Gaussian,
     E, W and D summed over the views equal the oracle's back-projection of
@@ -596,3 +631,54 @@ def test_full_size_multi_view_step_properties(B, fullstep, views, lm_mode):
     assert np.array_equal(p1[:, ~t1], p[:, ~t1]) and not m1[:, ~t1].any() and not v1[:, ~t1].any()
     moved = (p1[:, t1] != p[:, t1]).any(axis=0)
     assert moved.mean() > 0.05
+
+
+# ------------------------------------------------------------------ large scene
+def test_large_scene_view_on_sampled_tiles(B):
+    """One view of the large scene (5M Gaussians in a 50-unit corridor,
+    1920x1080, three quarters of the tiles drawn at 20% of their pixels):
+    depth bits and rectangles of every visible Gaussian bit-exact against
+    the oracle, the pair lists against the rectangle lists on 300 random
+    tiles, and the forward on 12 sampled tiles against the oracle."""
+    from paper_2606_15924_amd.pipeline import StepConfig, ViewBuffers
+    N = 5_000_000
+    p = synth.corridor_gaussians(N, synth.SEED_SCENE)
+    cam = synth.trajectory_cameras(400)[123]
+    E = synth.error_map(cam.height, cam.width, 93)
+    A = synth.age_map(cam.height, cam.width, 94)
+    n_t = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+    n_sel = int(0.75 * n_t)
+    vb = ViewBuffers(N, cam.width, cam.height, 51, n_sel, torch.device("cuda"), keep_keys=True)
+    totals = torch.zeros(2, dtype=torch.int64, device="cuda")
+    vb.sample(dev(E.view(np.int16)), dev(A.view(np.int16)), StepConfig(rate_permille=200, n_tiles_sel=n_sel), 1, 0,
+              totals)
+    vb.project(dev(p), B.camera(cam), B.raster_params())
+    vb.bin_sort()
+    vb.render_fwd(B.raster_params())
+    torch.cuda.synchronize()
+    pr = project.project(p, cam, RP)
+    vis = pr["visible"]
+    assert 0.05 < vis.mean() < 0.5
+    assert np.array_equal(host(vb.depth).view(np.uint32)[vis], pr["depth32"].view(np.uint32)[vis])
+    safe = vis & (pr["radius_margin"] > 1e-9)
+    assert np.array_equal(host(vb.rect)[safe], pr["rect"].T[safe])
+    s = sampler.sample_view(E, A, SampleParams(n_pix=51, n_tiles_sel=n_sel), 3, 1, 0)
+    assert np.array_equal(host(vb.valid_tiles), s["valid_tiles"])
+    q = splat_as_oracle(pr, splat_record(pr))
+    sub = np.random.default_rng(16).choice(s["valid_tiles"], 300, replace=False)
+    info = check_pair_lists(host(vb.vals)[: vb.n_pairs].view(np.uint32), host(vb.ranges), vb.n_pairs, q,
+                            valid_tiles=s["valid_tiles"], keys=host(vb.keys), tiles_subset=sub,
+                            max_dropped_checked=50000)
+    assert info["gpu"] > 10000
+    tiles = np.sort(np.random.default_rng(17).choice(s["valid_tiles"], 12, replace=False))
+    slot = {t: k for k, t in enumerate(s["valid_tiles"])}
+    idx = np.concatenate([np.arange(s["tile_off"][slot[t]], s["tile_off"][slot[t] + 1]) for t in tiles])
+    xs_all, ys_all, _ = sampler.sample_coords(s, cam.width, cam.height)
+    xs, ys = xs_all[idx], ys_all[idx]
+    _, sv, rg = binning.bin_and_sort(pr, tiles)
+    ref = render.render_pixels(q, sv, rg, xs, ys, RP)
+    ok = ~ref["flag"]
+    # near-camera Gaussians project to long needles; the conic's LDL^T form
+    # keeps their FP32 alpha as exact as elsewhere, so few pixels are flagged
+    assert ok.mean() >= 0.99, ok.mean()
+    assert_close(host(vb.out)[idx][ok, :3], ref["rgb"][ok], 1e-5, 1e-7, "rgb")

@@ -14,8 +14,8 @@ import synth
 from oracle import binning, loss, maps, optim, project, project_bwd, render, sampler
 from oracle.params import LossParams, OptimParams, RasterParams, SampleParams
 
-from support import (assert_close, check_pair_lists, last_ids, scene_c1, small_scene, splat_as_oracle,
-                     splat_record)
+from support import (assert_close, check_pair_lists, last_ids, ldl_conic, scene_c1, scene_scaling, small_scene,
+                     splat_as_oracle, splat_record)
 
 pytestmark = pytest.mark.gpu
 
@@ -78,7 +78,13 @@ def test_project_parity(B, case):
     py = s[:, 1].astype(np.float64) + s[:, 3]
     assert_close(px[vis], pr["mean2d"][0][vis], 0, 2e-7 * 2 ** 0, "centre x")
     assert_close(py[vis], pr["mean2d"][1][vis], 0, 2e-7, "centre y")
-    assert_close(s[vis][:, 4:7], pr["conic"].T[vis], 2e-7, 0, "conic")
+    # the conic in its LDL^T form (a, beta, delta); beta against the scale
+    # sqrt(c / a) it can reach (|beta| <= sqrt(c / a) for a positive definite Q)
+    ldl = ldl_conic(pr["conic"]).T[vis]
+    assert_close(s[vis][:, 4], ldl[:, 0], 2e-7, 0, "conic a")
+    scale_b = np.sqrt(pr["conic"][2][vis] / pr["conic"][0][vis])
+    assert np.all(np.abs(s[vis][:, 5] - ldl[:, 1]) <= 2e-7 * (np.abs(ldl[:, 1]) + 1e-3 * scale_b)), "conic beta"
+    assert_close(s[vis][:, 6], ldl[:, 2], 2e-7, 0, "conic delta")
     assert_close(s[vis][:, 7], pr["opacity"][vis], 2e-7, 0, "opacity")
     assert_close(s[vis][:, 8:11], pr["rgb"].T[vis], 2e-7, 1e-12, "rgb")
     clamp_bits = (pr["clamp"][0] * 1 + pr["clamp"][1] * 2 + pr["clamp"][2] * 4).astype(np.uint8)
@@ -86,6 +92,54 @@ def test_project_parity(B, case):
 
 
 # ------------------------------------------------------------------ binning + sort
+@pytest.mark.parametrize("case", ["c1_sampled", "scaling"])
+def test_bin_sort_async_equals_the_blocking_call(B, case):
+    """tgs_bin_sort_async queues the same lists without a host wait: keys,
+    ids and ranges bit for bit equal to tgs_bin_sort's, counts = (list
+    length, capacity needed); with a short capacity the lists come out
+    empty and counts[1] still reports the capacity needed."""
+    if case == "c1_sampled":
+        p, cams = scene_c1()
+        cam = cams[2]
+    else:
+        p, cam = scene_scaling()
+    pr = project.project(p, cam, RP)
+    TX, TY = pr["TX"], pr["TY"]
+    n = p.shape[1]
+    ts = None
+    if case == "c1_sampled":
+        valid = np.sort(np.random.default_rng(3).choice(TX * TY, 64, replace=False))
+        t = -np.ones(TX * TY, dtype=np.int32)
+        t[valid] = np.arange(valid.size)
+        ts = dev(t)
+    rec = splat_record(pr)
+    rect, splat, depth = dev(pr["rect"].T.astype(np.int32)), dev(rec), dev(pr["depth32"])
+    rect_area = (pr["rect"][2] - pr["rect"][0]) * (pr["rect"][3] - pr["rect"][1])
+    cap = int(rect_area[pr["visible"]].sum()) + 5
+    ws = torch.empty(B.tgs_bin_sort_workspace_size(n, cap, TX * TY), dtype=torch.uint8, device="cuda")
+    out = []
+    for sync in (True, False):
+        K = torch.full((cap,), -1, dtype=torch.int64, device="cuda")
+        V = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        R = torch.full((TX * TY, 2), -1, dtype=torch.int32, device="cuda")
+        c = torch.full((2,), -1, dtype=torch.int64, device="cuda")
+        if sync:
+            npairs = B.tgs_bin_sort(rect, splat, depth, n, ts, TX, TY, 1.0 / 255.0, K, V, cap, R, None, ws)
+        else:
+            B.tgs_bin_sort_async(rect, splat, depth, n, ts, TX, TY, 1.0 / 255.0, K, V, cap, R, None, c, ws)
+        out.append((host(K), host(V), host(R), host(c)))
+    (k1, v1, r1, _), (k2, v2, r2, c2) = out
+    assert c2[0] == npairs > 0 and npairs <= c2[1] <= cap
+    assert np.array_equal(k1[:npairs], k2[:npairs]) and np.array_equal(v1[:npairs], v2[:npairs])
+    assert np.array_equal(r1, r2)
+    short = int(c2[1]) - 1
+    R = torch.full((TX * TY, 2), -1, dtype=torch.int32, device="cuda")
+    c = torch.zeros(2, dtype=torch.int64, device="cuda")
+    V = torch.full((cap,), -7, dtype=torch.int32, device="cuda")
+    B.tgs_bin_sort_async(rect, splat, depth, n, ts, TX, TY, 1.0 / 255.0, None, V, short, R, None, c, ws)
+    assert np.array_equal(host(c), c2) and not host(R).any() and (host(V) == -7).all()
+
+
 def test_bin_sort_wide_tile_ids_with_id_payload(B):
     """A 4100x4100 view (66,049 tiles: 17 tile bits) of 50k Gaussians (16 id
     bits): tile and id no longer fit one 32-bit key, so the pair sort keys on
@@ -176,10 +230,19 @@ def test_bin_sort_lists_against_rectangle_lists(B, case):
                                                         (150, 107, 256, -1, 0.0, False), (96, 80, 51, 7, 1.0, False),
                                                         (1296, 840, 64, -1, 0.1, False), (256, 256, 64, 64, 0.1, True),
                                                         (150, 107, 25, 20, 0.3, True), (1296, 840, 64, 1073, 0.1, False),
-                                                        (1296, 840, 64, 1073, 0.1, True)])
+                                                        (1296, 840, 64, 1073, 0.1, True),
+                                                        (1296, 840, 16, 3000, 0.1, "sparse"),
+                                                        (2560, 1440, 8, 10800, 0.1, "sparse"),
+                                                        (1920, 1600, 8, 9000, 0.1, False),
+                                                        (2560, 1900, 8, 5000, 0.1, "sparse"),
+                                                        (3840, 2160, 8, 100, 0.1, False)])
 def test_sampler_bit_exact(B, W, H, n_pix, n_sel, zero, pred):
     """pred: the tile pass draws by predicted tile errors (negative, NaN and
-    out-of-range predictions included)."""
+    out-of-range predictions included); "sparse": seven tiles in ten predict
+    no error, so the weighted draws run out and the rest are uniform.  The
+    tile counts span one to five tiles per lane in the LDS chunk pass (up
+    to 4,096 tiles: one; 4,293, 12,000, 14,400 and 19,040 tiles: two to
+    five) and the global-memory walk (32,400 tiles)."""
     E = synth.error_map(H, W, 31, zero_frac=zero)
     A = synth.age_map(H, W, 32)
     seed, step, view = 3, 5, 2
@@ -189,6 +252,8 @@ def test_sampler_bit_exact(B, W, H, n_pix, n_sel, zero, pred):
         nt = ((W + 15) // 16) * ((H + 15) // 16)
         tile_pred = np.random.default_rng(33).normal(0.2, 0.2, nt).astype(np.float32)
         tile_pred[:3] = [np.nan, 1e30, -1.0]
+        if pred == "sparse":
+            tile_pred[np.random.default_rng(34).random(nt) < 0.7] = 0.0
     bsp = B.sample_params(n_pix, n_tiles_sel=n_sel, seed=seed, step=step, view=view)
     n_st = B.tgs_sample_tile_count(H, W, bsp)
     TX, TY = (W + 15) // 16, (H + 15) // 16

@@ -318,66 +318,106 @@ def test_transmittance_stop_fixed_position_matches_finite_differences():
             assert abs(fd - g[row, k]) <= 1e-6 * max(abs(fd), 1e-2), (name, comp, k, fd, g[row, k])
 
 
-def test_guard_band_bounds_an_fp32_evaluation():
-    """The guard band is wide enough: an FP32 evaluation of each alpha (the
-    splat record rounded to FP32, the tile-local centre as the exact integer
-    difference plus the fraction, the exponent from single-rounded products
-    and sums, a rounded exponential) and of the running transmittance stays
-    within the oracle's error bounds eps_a and eps_T (half the band at the
-    default guard of two) at every evaluated position of two tiny-workload
-    views' sampled tiles; and few pixels are flagged."""
+def _fp32_band_ratios(pr, tiles, n_loc, seed, TX):
+    """Worst ratios of an FP32 evaluation's alpha and transmittance errors to
+    eps_a and eps_T over sampled pixels of ``tiles``, and the flag count.
+    The FP32 side: the splat record rounded to FP32 (conic in its LDL^T form
+    a, beta, delta), the tile-local centre as the exact integer difference
+    plus the fraction, w = fma(beta, dy, dx), p2 = fma(A, w^2, D dy^2) with
+    A, D the conic values times -log2(e)/2, each operation rounded once, and
+    a rounded exponential."""
     from support import splat_record
     f32 = np.float32
     l2e = f32(1.4426950408889634)
     rp = RasterParams()
     r64 = rp.f64()
+    rec = splat_record(pr)
+    _, sv, rg = binning.bin_and_sort(pr, tiles)
+    rng = np.random.default_rng(seed)
+    worst_a = worst_T = amp = 0.0
+    flagged = total = 0
+    for t in tiles:
+        lo, hi = rg[t]
+        gids = sv[lo:hi].astype(np.int64)
+        if gids.size == 0:
+            continue
+        loc = rng.choice(256, n_loc, replace=False)
+        xs = (t % TX) * 16 + loc % 16
+        ys = (t // TX) * 16 + loc // 16
+        ev = render._tile_eval(pr, gids, xs.astype(float), ys.astype(float), r64)
+        r = rec[gids]
+        x0, y0 = f32((t % TX) * 16), f32((t // TX) * 16)
+        gx = (r[:, 0] - x0) + r[:, 2]
+        gy = (r[:, 1] - y0) + r[:, 3]
+        A = r[:, 4] * f32(-0.5 * l2e)
+        D = r[:, 6] * f32(-0.5 * l2e)
+        dx = (loc % 16).astype(f32)[:, None] - gx[None]
+        dy = (loc // 16).astype(f32)[:, None] - gy[None]
+        w = (r[None, :, 5].astype(np.float64) * dy + dx).astype(f32)     # fma: one rounding
+        p2 = (A[None].astype(np.float64) * (w * w) + D[None] * (dy * dy)).astype(f32)
+        a32 = r[None, :, 7] * np.exp2(p2.astype(np.float64)).astype(f32)
+        neval = np.where(ev["has_stop"], ev["stop_at"] + 1, gids.size)
+        m = (np.arange(gids.size)[None] < neval[:, None]) & (ev["araw"] > 1e-30)
+        rel = np.abs(a32 - ev["araw"]) / np.where(m, ev["araw"], 1.0)
+        if m.any():
+            worst_a = max(worst_a, float((rel / ev["eps_a"])[m].max()))
+            # size of the terms a dx^2 / 2, b dx dy, c dy^2 / 2 against the exponent
+            terms = (0.5 * np.abs(ev["a"])[None] * ev["dx"] ** 2 + 0.5 * np.abs(ev["c"])[None] * ev["dy"] ** 2
+                     + np.abs(ev["b"][None] * ev["dx"] * ev["dy"]))
+            amp = max(amp, float((terms / np.maximum(np.abs(ev["power"]), 0.5))[m & ev["ok"]].max(initial=0.0)))
+        al = np.minimum(f32(r64.alpha_max), a32)
+        T = np.ones(xs.size, f32)
+        for k in range(gids.size):
+            Tn = T * (f32(1) - al[:, k])
+            mk = ev["contrib"][:, k] | (ev["ok"][:, k] & (ev["stop_at"] == k))
+            if mk.any():
+                relT = np.abs(Tn - ev["T_after"][:, k])[mk] / ev["T_after"][mk, k]
+                worst_T = max(worst_T, float((relT / ev["eps_T"][mk, k]).max()))
+            T = np.where(ev["contrib"][:, k], Tn, T)
+        out = render.render_pixels(pr, sv, rg, xs, ys, rp)
+        flagged += int(out["flag"].sum())
+        total += xs.size
+    return worst_a, worst_T, flagged, total, amp
+
+
+def test_guard_band_bounds_an_fp32_evaluation():
+    """The guard band is wide enough and not too wide: the FP32 evaluation's
+    alpha and running transmittance stay within the oracle's error bounds
+    eps_a and eps_T (half the band at the default guard of two) at every
+    evaluated position of two tiny-workload views' sampled tiles, and the
+    largest ratio is above 1/20 (the bound is not vacuous); few pixels are
+    flagged."""
+    rp = RasterParams()
     p = synth.gaussians(10000, synth.SEED_SCENE)
     cams = synth.tetra_cameras()
     worst_a = worst_T = 0.0
     flagged = total = 0
     for vi in (0, 3):
-        cam = cams[vi]
-        pr = project.project(p, cam, rp)
-        rec = splat_record(pr)
+        pr = project.project(p, cams[vi], rp)
         tiles = np.random.default_rng(vi).choice(256, 24, replace=False)
-        _, sv, rg = binning.bin_and_sort(pr, tiles)
-        rng = np.random.default_rng(10 + vi)
-        for t in tiles:
-            lo, hi = rg[t]
-            gids = sv[lo:hi].astype(np.int64)
-            if gids.size == 0:
-                continue
-            loc = rng.choice(256, 48, replace=False)
-            xs = (t % 16) * 16 + loc % 16
-            ys = (t // 16) * 16 + loc // 16
-            ev = render._tile_eval(pr, gids, xs.astype(float), ys.astype(float), r64)
-            r = rec[gids]
-            x0, y0 = f32((t % 16) * 16), f32((t // 16) * 16)
-            gx = (r[:, 0] - x0) + r[:, 2]
-            gy = (r[:, 1] - y0) + r[:, 3]
-            A = r[:, 4] * f32(-0.5 * l2e)
-            Bq = r[:, 5] * (-l2e)
-            C = r[:, 6] * f32(-0.5 * l2e)
-            dx = (loc % 16).astype(f32)[:, None] - gx[None]
-            dy = (loc // 16).astype(f32)[:, None] - gy[None]
-            inner = (C[None].astype(np.float64) * (dy * dy) + (Bq[None] * (dx * dy))).astype(f32)
-            p2 = (A[None].astype(np.float64) * (dx * dx) + inner).astype(f32)
-            a32 = r[None, :, 7] * np.exp2(p2.astype(np.float64)).astype(f32)
-            neval = np.where(ev["has_stop"], ev["stop_at"] + 1, gids.size)
-            m = (np.arange(gids.size)[None] < neval[:, None]) & (ev["araw"] > 1e-30)
-            rel = np.abs(a32 - ev["araw"]) / np.where(m, ev["araw"], 1.0)
-            worst_a = max(worst_a, float((rel / ev["eps_a"])[m].max()))
-            al = np.minimum(f32(r64.alpha_max), a32)
-            T = np.ones(xs.size, f32)
-            for k in range(gids.size):
-                Tn = T * (f32(1) - al[:, k])
-                mk = ev["contrib"][:, k] | (ev["ok"][:, k] & (ev["stop_at"] == k))
-                if mk.any():
-                    relT = np.abs(Tn - ev["T_after"][:, k])[mk] / ev["T_after"][mk, k]
-                    worst_T = max(worst_T, float((relT / ev["eps_T"][mk, k]).max()))
-                T = np.where(ev["contrib"][:, k], Tn, T)
-            out = render.render_pixels(pr, sv, rg, xs, ys, rp)
-            flagged += int(out["flag"].sum())
-            total += xs.size
+        wa, wt, f, n, _ = _fp32_band_ratios(pr, tiles, 48, 10 + vi, 16)
+        worst_a, worst_T = max(worst_a, wa), max(worst_T, wt)
+        flagged, total = flagged + f, total + n
     assert 0.05 < worst_a < 0.8 and worst_T < 0.8, (worst_a, worst_T)
     assert flagged <= 1e-3 * total, (flagged, total)
+
+
+def test_guard_band_bounds_an_fp32_evaluation_of_needle_splats():
+    """The same on a near-camera corridor view (1920x1080) where one Gaussian
+    in fifty is a needle (scales 150:1): two units from the camera these
+    project to splats hundreds of pixels long, where
+    the exponent's terms a dx^2, 2 b dx dy, c dy^2 reach a thousand times
+    the exponent itself at composited positions; the LDL^T evaluation keeps the band narrow (no
+    pixel flagged more often than on the tiny workload)."""
+    rp = RasterParams()
+    p = synth.corridor_gaussians(150_000, 11, length=6.0)
+    p[3:6, ::50] = np.array([-1.5, -6.5, -6.5], dtype=np.float32)[:, None]   # 2%: one long axis (150:1)
+    cam = synth.trajectory_cameras(4, length=6.0)[1]
+    pr = project.project(p, cam, rp)
+    TX, TY = pr["TX"], pr["TY"]
+    tiles = np.sort(np.random.default_rng(6).choice(TX * TY, 40, replace=False))
+    worst_a, worst_T, flagged, total, amp = _fp32_band_ratios(pr, tiles, 32, 12, TX)
+    assert total > 1000
+    assert amp > 1000, amp          # the view does hold such needles
+    assert 0.05 < worst_a < 0.8 and worst_T < 0.8, (worst_a, worst_T)
+    assert flagged <= 3e-3 * total, (flagged, total)
