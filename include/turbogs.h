@@ -197,11 +197,13 @@ int32_t tgs_sample_noalloc(const uint16_t* E, const uint16_t* A, int32_t height,
  * per-tile Gaussian lists of Eq. alpha_comp, in the tile order of Sec. 3.6).
  * A (Gaussian, tile) pair is listed when the tile lies in the Gaussian's
  * tile rectangle and its pixel-centre rectangle meets the ellipse
- * q(d) <= tau of the splat's centre and conic (d measured from the centre,
- * q = a dx^2 + 2 b dx dy + c dy^2, tau = 2 ln(1/alpha_min) x 1.001 rounded
- * up to a multiple of 1/64): no dropped pair can reach alpha_min at any
- * pixel of its tile, so the lists composite exactly like the rectangle
- * lists.  The kept tiles of a tile row are one interval of columns, found
+ * q(d) <= t of the splat's centre and conic (d measured from the centre,
+ * q = a dx^2 + 2 b dx dy + c dy^2; t = 2 ln(o/alpha_min) + 0.004 for the
+ * splat's opacity o, rounded up to a multiple of 1/64 and at most
+ * tau = 2 ln(1/alpha_min) x 1.001 rounded likewise): alpha = o exp(-q/2)
+ * stays below alpha_min (by 0.2 %) outside it, so no dropped pair can reach
+ * alpha_min at any pixel of its tile and the lists composite exactly like
+ * the rectangle lists.  The kept tiles of a tile row are one interval of columns, found
  * in FP64 from the ellipse's x-extent over the row's pixel-centre strip.
  *   rect, splat, depth  projection outputs of n Gaussians
  *   tile_slot    nullable: only tiles with tile_slot >= 0 receive pairs

@@ -164,19 +164,29 @@ __device__ __forceinline__ int4 clamp_rect(int4 r, int tiles_x, int tiles_y) {
 
 // What the row test needs of one Gaussian: the stored centre (integer part
 // and fraction) and conic widened to FP64 (exact), and per-Gaussian terms of
-// the ellipse q(d) = A dx^2 + 2 B dx dy + C dy^2 <= tau: det = AC - B^2,
-// its half-height ym = sqrt(tau A / det), ys = B sqrt(tau / (C det)) (the
+// the ellipse q(d) = A dx^2 + 2 B dx dy + C dy^2 <= t: det = AC - B^2,
+// its half-height ym = sqrt(t A / det), ys = B sqrt(t / (C det)) (the
 // rightmost point of the ellipse sits at dy = -ys, the leftmost at +ys) and
-// tA = tau A.  pd = 0 for a conic that is not positive definite.
+// tA = t A.  pd = 0 for a conic that is not positive definite.
+//
+// The bound t is the Gaussian's own: alpha = o exp(-q/2) reaches alpha_min
+// only where q <= 2 ln(o / alpha_min), so t = that plus 0.004 (alpha below
+// alpha_min by 0.2 % past it, far above the FP32 error of the renderer's
+// alpha), rounded up to a multiple of 1/64, and at most tau (the bound for
+// o = 1).  A Gaussian with t <= 0 keeps no tile (ym < 0 empties every row).
+// lia = ln(1 / alpha_min).
 struct RowEllipse {
   double xi, xf, yi, yf, A, B, det, ym, ys, tA;
   int pd;
 };
 
-__device__ __forceinline__ RowEllipse load_row_ellipse(const float4* __restrict__ splat, int64_t i, double tau) {
+__device__ __forceinline__ RowEllipse load_row_ellipse(const float4* __restrict__ splat, int64_t i, double tau,
+                                                       double lia) {
 #pragma clang fp contract(off)
   const float4 p0 = splat[3 * i], p1 = splat[3 * i + 1];
   RowEllipse e;
+  const double o = (double)p1.w;
+  const double t = o > 0.0 ? fmin(tau, ceil(64.0 * (2.0 * (log(o) + lia) + 0.004)) * (1.0 / 64.0)) : -1.0;
   e.xi = p0.x;
   e.yi = p0.y;
   e.xf = p0.z;
@@ -188,9 +198,9 @@ __device__ __forceinline__ RowEllipse load_row_ellipse(const float4* __restrict_
   const double C = (double)p1.z + (double)p1.y * e.B;
   e.det = e.A * (double)p1.z;
   e.pd = e.A > 0.0 && e.det > 0.0;
-  e.ym = e.pd ? sqrt((tau * e.A) / e.det) : 0.0;
-  e.ys = e.pd ? e.B * sqrt(tau / (C * e.det)) : 0.0;
-  e.tA = tau * e.A;
+  e.ym = !e.pd ? 0.0 : (t > 0.0 ? sqrt((t * e.A) / e.det) : -1.0);
+  e.ys = e.pd && t > 0.0 ? e.B * sqrt(t / (C * e.det)) : 0.0;
+  e.tA = t * e.A;
   return e;
 }
 
@@ -268,7 +278,7 @@ struct CountBatch {
 
 __global__ void __launch_bounds__(kWave) count_kernel(
     const int4* __restrict__ rect, const float4* __restrict__ splat, const float* __restrict__ depth, int64_t n,
-    const int32_t* __restrict__ tile_slot, int tiles_x, int tiles_y, double tau, uint32_t* __restrict__ dkeys,
+    const int32_t* __restrict__ tile_slot, int tiles_x, int tiles_y, double tau, double lia, uint32_t* __restrict__ dkeys,
     uint32_t* __restrict__ dvals, uint32_t* __restrict__ emit_cnt, uint8_t* __restrict__ touched,
     unsigned long long* __restrict__ totals) {
   __shared__ CountBatch cb;
@@ -286,7 +296,7 @@ __global__ void __launch_bounds__(kWave) count_kernel(
   cb.row0[lane] = my_row0;
   cb.kept[lane] = 0u;
   cb.valid[lane] = 0u;
-  if (rows > 0) cb.ell[lane] = load_row_ellipse(splat, i, tau);
+  if (rows > 0) cb.ell[lane] = load_row_ellipse(splat, i, tau, lia);
   int carry = -1;
   for (uint32_t f0 = 0; f0 < n_rows; f0 += kWave) {
     cb.mark[lane] = -1;
@@ -733,7 +743,7 @@ template <typename K>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ off, const uint32_t* __restrict__ ids_sorted,
     int64_t n, const float4* __restrict__ splat, const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t,
-    int id_bits, double tau, const uint32_t* __restrict__ total_dev, K* __restrict__ keys,
+    int id_bits, double tau, double lia, const uint32_t* __restrict__ total_dev, K* __restrict__ keys,
     uint32_t* __restrict__ pay) {
   const uint32_t total = *total_dev;  // pairs to emit (0 when they exceed the capacity)
   __shared__ RowBatch rb;
@@ -755,7 +765,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
   rb.rect[lane] = r;
   rb.row0[lane] = my_row0;
   rb.id[lane] = g;
-  if (rows > 0) rb.ell[lane] = load_row_ellipse(splat, g, tau);
+  if (rows > 0) rb.ell[lane] = load_row_ellipse(splat, g, tau, lia);
   const uint32_t base = off[b0];  // pair offset of the batch's first Gaussian
   uint32_t written = 0;           // wave-uniform
   int carry = -1;
@@ -934,7 +944,7 @@ static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_
 // read on the device (w.eff_total), so nothing here waits for the host.
 template <typename K, bool kPay>
 static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t bound, const float4* splat,
-                       const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits, int tbits, double tau,
+                       const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits, int tbits, double tau, double lia,
                        const float* depth, uint32_t* vals, uint64_t* keys64, uint32_t* ranges, hipStream_t s) {
   // each ping-pong buffer (8 bytes per pair of capacity) holds the keys and, after them, the payload
   K* kb[2] = {(K*)w.pkeys[0], (K*)w.pkeys[1]};
@@ -943,7 +953,7 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
     for (int k = 0; k < 2; ++k) pb[k] = (uint32_t*)((char*)w.pkeys[k] + align_up(sizeof(K) * (size_t)w.cap, 256));
   const int key_id_bits = kPay ? 0 : id_bits;
   hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(n, kEmitBatch)), dim3(kEmitThreads), 0, s,
-                     w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, key_id_bits, tau, w.eff_total,
+                     w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, key_id_bits, tau, lia, w.eff_total,
                      kb[0], pb[0]);
   const int passes = pass_count(tbits);
   int cur = 0, shift = key_id_bits;
@@ -981,7 +991,8 @@ static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const flo
                               const SortWs& w, hipStream_t s, const char* who) {
   const uint32_t n_t = (uint32_t)tiles_x * (uint32_t)tiles_y;
   // 2 ln(1/alpha_min) with a 0.1 % margin, rounded up to a multiple of 1/64
-  const double tau = std::ceil(128.0 * std::log(1.0 / (double)alpha_min) * 1.001) / 64.0;
+  const double lia = std::log(1.0 / (double)alpha_min);
+  const double tau = std::ceil(128.0 * lia * 1.001) / 64.0;
   // empty ranges and the zeroed workspace region (counters, table padding)
   hipLaunchKernelGGL(zero2_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t + w.zeroed_words, 256)), dim3(256),
                      0, s, ranges, 2 * (int64_t)n_t, w.zeroed, w.zeroed_words);
@@ -989,7 +1000,7 @@ static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const flo
   hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w.scalars, capacity, w.counts, w.eff_total);
   if (n == 0) return hip_status(who);
   hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kWave), 0, s,
-                     (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau,
+                     (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau, lia,
                      w.dkeys[0], w.dvals[0], w.emit_cnt, touched, w.scalars);
   hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w.scalars, capacity, w.counts, w.eff_total);
   // (depth, id) order; Gaussians without pairs last
@@ -1002,13 +1013,13 @@ static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const flo
   const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
   if (id_bits + tbits <= 32)
     sort_pairs<uint32_t, false>(w, w.ids_sorted, n, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                                tbits, tau, depth, vals, keys, ranges, s);
+                                tbits, tau, lia, depth, vals, keys, ranges, s);
   else if (tbits <= 16)
     sort_pairs<uint16_t, true>(w, w.ids_sorted, n, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                               tbits, tau, depth, vals, keys, ranges, s);
+                               tbits, tau, lia, depth, vals, keys, ranges, s);
   else
     sort_pairs<uint32_t, true>(w, w.ids_sorted, n, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                               tbits, tau, depth, vals, keys, ranges, s);
+                               tbits, tau, lia, depth, vals, keys, ranges, s);
   return hip_status(who);
 }
 
