@@ -42,6 +42,7 @@ FULL_W, FULL_H = 1600, 1060
 FULL_RATE = 200              # per-mille of each tile's pixels (51 of 256)
 FULL_K = (3, 10)             # views per step (the schedule's K_min and K_max)
 HEADLINE_K = 3
+FULL_PREFIX = 0.15           # depth-prefix lists: the nearest 15% of the Gaussians, then a continuation
 
 # large scene: 5M Gaussians in a 50-unit corridor, 400 cameras 1920x1080 along it
 LARGE_N = 5_000_000
@@ -225,11 +226,11 @@ def full_workload(dev):
     return p, cams, gts
 
 
-def full_trainer(p, cams, gts, rate, dev):
+def full_trainer(p, cams, gts, rate, dev, prefix=FULL_PREFIX):
     import torch
 
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
-    cfg = StepConfig(rate_permille=rate)
+    cfg = StepConfig(rate_permille=rate, prefix_fraction=prefix)
     E = [torch.zeros((FULL_H, FULL_W), dtype=torch.int16, device=dev) for _ in cams]
     A = [torch.zeros((FULL_H, FULL_W), dtype=torch.int16, device=dev) for _ in cams]
     tr = Trainer(torch.from_numpy(p).to(dev), cams, gts, cfg, E=E, A=A)
@@ -247,7 +248,7 @@ def view_order(K, n_views=FULL_VIEWS):
     return lambda i: seq[i % len(seq)]
 
 
-def full_step(dev, steps, warmup, with_dense=True):
+def full_step(dev, steps, warmup, with_dense=True, prefix=FULL_PREFIX):
     """Sparse (20 %) and dense steps at K = 3 and K = 10."""
     import torch
     log("full step: building the 1.5M-Gaussian scene and 150 targets")
@@ -258,7 +259,7 @@ def full_step(dev, steps, warmup, with_dense=True):
             if name == "dense" and not with_dense:
                 continue
             log(f"full step K={K} {name}: {warmup} warmup + {steps} timed steps")
-            tr = full_trainer(p, cams, gts, rate, dev)
+            tr = full_trainer(p, cams, gts, rate, dev, prefix)
             r = run(tr, steps, warmup, view_order(K))
             log(f"  {r['ms_per_step']:.3f} ms/step, stages {r['stage_ms']}")
             res[(K, name)] = r
@@ -806,6 +807,7 @@ def main():
     ap.add_argument("--no-tile", action="store_true", help="skip the learned tile-priority measurement")
     ap.add_argument("--no-density", action="store_true", help="skip the density-control measurement")
     ap.add_argument("--only-headline", action="store_true", help="the K=3 sparse full step alone (profiling)")
+    ap.add_argument("--no-prefix", action="store_true", help="whole lists instead of depth-prefix lists")
     ap.add_argument("--no-large", action="store_true", help="skip the large-scene run")
     ap.add_argument("--only-large", action="store_true", help="the large-scene run alone (prints its record)")
     ap.add_argument("--large-steps", type=int, default=LARGE_STEPS, help="timed steps of the large-scene run")
@@ -839,7 +841,8 @@ def main():
         global FULL_K
         FULL_K = (HEADLINE_K,)
     p_full, cams, full = full_step(dev, args.steps, args.warmup,
-                                   with_dense=not (args.no_dense or args.only_headline))
+                                   with_dense=not (args.no_dense or args.only_headline),
+                                   prefix=None if args.no_prefix else FULL_PREFIX)
     head = full[(HEADLINE_K, "sparse")]
     roofline = roofline_of(head, args.steps)
     full_out = {}
@@ -913,7 +916,8 @@ def main():
                                f"K={HEADLINE_K} views per step, 20% error-guided pixels per tile, "
                                f"sparse NCC + Charbonnier, hybrid LM/Adam update",
                    "gaussians": FULL_N, "views": FULL_VIEWS, "width": FULL_W, "height": FULL_H,
-                   "views_per_step": HEADLINE_K, "rate": FULL_RATE / 1000, "parallelism": "single GPU"},
+                   "views_per_step": HEADLINE_K, "rate": FULL_RATE / 1000,
+                   "depth_prefix": None if args.no_prefix else FULL_PREFIX, "parallelism": "single GPU"},
         "step_ms_spread": head["step_ms_spread"],
         "full_step": full_out,
         "roofline": roofline,

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 9u
+#define TGS_ABI_VERSION 10u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
@@ -249,6 +249,39 @@ int32_t tgs_bin_sort_async(const int32_t* rect, const float* splat, const float*
                            uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges,
                            uint8_t* touched, int64_t* counts, void* ws, size_t ws_bytes, void* stream);
 
+/* Depth-prefix lists (an exact shortcut for the forward walk's early
+ * stop): the lists of tgs_bin_sort_async restricted to the first `prefix`
+ * Gaussians in (depth, id) order, i.e. the first part of every tile's
+ * list.  A pixel whose walk stops (T_min) within its prefix composites as
+ * with the whole list; tgs_render_fwd_prefix marks the tiles where one does
+ * not, tgs_bin_sort_continue_async lists the rest of those tiles' Gaussians
+ * and tgs_render_fwd_cont redoes them over both parts, so the images,
+ * counts and gradients equal those of the whole lists.  Arguments as
+ * tgs_bin_sort_async except counts: [3] int64 device, counts[0] = the
+ * lists' length, counts[1] = the pairs the prefix emits (the capacity it
+ * needs), counts[2] = the pairs of the whole lists (counts[2] - counts[1]
+ * bounds what a continuation can need).  The workspace keeps the depth
+ * order for the continuation call; prefix >= n gives the whole lists. */
+int32_t tgs_bin_sort_prefix_async(const int32_t* rect, const float* splat, const float* depth, int64_t n,
+                                  const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
+                                  int64_t prefix, uint64_t* keys, uint32_t* vals, int64_t capacity,
+                                  uint32_t* ranges, uint8_t* touched, int64_t* counts, void* ws, size_t ws_bytes,
+                                  void* stream);
+
+/* The continuation of depth-prefix lists: for every tile with
+ * flag_slot[tile] >= 0, the pairs of the Gaussians from depth rank `prefix`
+ * on (same culling), each tile's list in (depth, id) order.
+ *   flag_slot  [tiles_x * tiles_y] int32 (tgs_render_fwd_prefix's cont_slot)
+ *   capacity, ws, ws_bytes  the prefix call's (its depth order is read)
+ *   vals2, capacity2, ranges2  the continuation lists, as vals/ranges
+ *   counts2    [2] int64 device: both = the continuation pairs; above
+ *              capacity2 the lists come out empty, as in tgs_bin_sort_async
+ *   ws2        tgs_bin_sort_workspace_size(n, capacity2, n_tiles) bytes */
+int32_t tgs_bin_sort_continue_async(const float* splat, int64_t n, const int32_t* flag_slot, int32_t tiles_x,
+                                    int32_t tiles_y, float alpha_min, int64_t prefix, int64_t capacity,
+                                    const void* ws, size_t ws_bytes, uint32_t* vals2, int64_t capacity2,
+                                    uint32_t* ranges2, int64_t* counts2, void* ws2, size_t ws2_bytes, void* stream);
+
 /* Front-to-back compositing of the sampled pixels of the sampled tiles
  * (Eq. alpha_comp; Sec. 3.6 tile-parallel forward with prefix-sum pixel
  * offsets).  valid_tiles = NULL: dense mode (n_st ignored).
@@ -273,6 +306,35 @@ int32_t tgs_render_fwd(const float* splat, const uint32_t* vals, const uint32_t*
                        int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
                        float* out, uint32_t* ncontrib, uint64_t* counters, float* state,
                        void* stream);
+
+/* tgs_render_fwd over depth-prefix lists that also marks the tiles with a
+ * pixel whose walk ran off the end of its list without the T_min stop:
+ *   cont_slot   [tiles_x * tiles_y] int32, written: the tile's slot (its
+ *               index in valid_tiles, or the tile in dense mode) when
+ *               marked, else -1
+ *   cont_list   [n_st, or tiles_x * tiles_y in dense mode] uint32: the
+ *               marked slots, in no particular order
+ *   cont_count  [1] uint32 device: their number
+ * counters count only the pixels that stopped (tgs_render_fwd_cont counts
+ * the others). */
+int32_t tgs_render_fwd_prefix(const float* splat, const uint32_t* vals, const uint32_t* ranges, int32_t tiles_x,
+                              int32_t tiles_y, int32_t width, int32_t height, const int32_t* valid_tiles,
+                              const int32_t* tile_off, const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
+                              const tgs_raster_params* rp, float* out, uint32_t* ncontrib, uint64_t* counters,
+                              float* state, int32_t* cont_slot, uint32_t* cont_list, uint32_t* cont_count,
+                              void* stream);
+
+/* tgs_render_fwd for the slots cont_list[0 .. *cont_count) over two-part
+ * lists (each tile's list is vals[ranges[t]] followed by vals2[ranges2[t]];
+ * list positions, ncontrib and the state record count across both parts):
+ * rewrites those slots' outputs and state; counters count the pixels that
+ * had not stopped within the first part. */
+int32_t tgs_render_fwd_cont(const float* splat, const uint32_t* vals, const uint32_t* ranges, const uint32_t* vals2,
+                            const uint32_t* ranges2, int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                            const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix, int32_t n_st,
+                            int32_t max_per_tile, const tgs_raster_params* rp, const uint32_t* cont_list,
+                            const uint32_t* cont_count, float* out, uint32_t* ncontrib, uint64_t* counters,
+                            float* state, void* stream);
 
 /* Exact adjoint of tgs_render_fwd for the same samples (Sec. 3.6 backward
  * over sampled pixels only).  Per-pixel state is recomputed front to back
@@ -299,6 +361,17 @@ int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, const uint32_t*
                        int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
                        const float* out, const uint32_t* ncontrib, const float* dL_dout,
                        float* g2d, const float* state, uint8_t* touched, void* stream);
+
+/* tgs_render_bwd (and, with stats, tgs_render_bwd_density) over two-part
+ * lists as in tgs_render_fwd_cont: the adjoint of the forward those lists
+ * gave.  err, n and stats as tgs_render_bwd_density; stats NULL: no
+ * density sums. */
+int32_t tgs_render_bwd2(const float* splat, const uint32_t* vals, const uint32_t* ranges, const uint32_t* vals2,
+                        const uint32_t* ranges2, int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                        const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix, int32_t n_st,
+                        int32_t max_per_tile, const tgs_raster_params* rp, const float* out,
+                        const uint32_t* ncontrib, const float* dL_dout, float* g2d, const float* state,
+                        uint8_t* touched, const float* err, int64_t n, float* stats, void* stream);
 
 /* tgs_render_bwd with bitwise-reproducible gradients: the same adjoint and
  * the same per-Gaussian wave sums, but each wave stores its nine sums of
@@ -390,6 +463,14 @@ int32_t tgs_density_accumulate(const float* splat, const uint32_t* vals, const u
                                int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
                                const uint32_t* ncontrib, const float* err, const float* state, int64_t n,
                                float* stats, void* stream);
+
+/* tgs_density_accumulate over two-part lists (see tgs_render_fwd_cont). */
+int32_t tgs_density_accumulate2(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                                const uint32_t* vals2, const uint32_t* ranges2, int32_t tiles_x, int32_t tiles_y,
+                                int32_t width, int32_t height, const int32_t* valid_tiles, const int32_t* tile_off,
+                                const uint8_t* pix, int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
+                                const uint32_t* ncontrib, const float* err, const float* state, int64_t n,
+                                float* stats, void* stream);
 
 /* tgs_render_bwd that also adds the density-control sums of
  * tgs_density_accumulate (Sec. 3.8) for the same samples: the backward's

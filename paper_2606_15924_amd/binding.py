@@ -80,6 +80,18 @@ PROTOTYPES = {
     "tgs_check_finite": (_I32, [_P, _I64, _P, _P]),
     "tgs_bin_sort_async": (_I32, [_P, _P, _P, _I64, _P, _I32, _I32, ctypes.c_float, _P, _P, _I64, _P, _P, _P, _P,
                                   _SZ, _P]),
+    "tgs_bin_sort_prefix_async": (_I32, [_P, _P, _P, _I64, _P, _I32, _I32, ctypes.c_float, _I64, _P, _P, _I64, _P,
+                                         _P, _P, _P, _SZ, _P]),
+    "tgs_bin_sort_continue_async": (_I32, [_P, _I64, _P, _I32, _I32, ctypes.c_float, _I64, _I64, _P, _SZ, _P, _I64,
+                                           _P, _P, _P, _SZ, _P]),
+    "tgs_render_fwd_prefix": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                                     ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P, _P]),
+    "tgs_render_fwd_cont": (_I32, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                                   ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P]),
+    "tgs_render_bwd2": (_I32, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                               ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P]),
+    "tgs_density_accumulate2": (_I32, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
+                                       ctypes.POINTER(tgs_raster_params), _P, _P, _P, _I64, _P, _P]),
     "tgs_sample_noalloc": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(tgs_sample_params), _P, _P, _P, _P, _P, _P,
                                   _P]),
     "tgs_render_bwd_det_workspace_size": (_SZ, [_I64, _I32, _I32]),
@@ -335,6 +347,68 @@ def tgs_bin_sort_async(rect, splat, depth, n, tile_slot, tiles_x, tiles_y, alpha
                                     float(alpha_min), _ptr(keys), _ptr(vals), capacity, _ptr(ranges), _ptr(touched),
                                     _ptr(counts), _ptr(ws), ws.numel() * ws.element_size(), _stream()),
            "tgs_bin_sort_async")
+
+
+def tgs_bin_sort_prefix_async(rect, splat, depth, n, tile_slot, tiles_x, tiles_y, alpha_min, prefix, keys, vals,
+                              capacity, ranges, touched, counts, ws):
+    """tgs_bin_sort_async restricted to the first ``prefix`` Gaussians in
+    depth order; the workspace keeps the depth order for a continuation."""
+    _check(lib().tgs_bin_sort_prefix_async(_ptr(rect), _ptr(splat), _ptr(depth), n, _ptr(tile_slot), tiles_x,
+                                           tiles_y, float(alpha_min), int(prefix), _ptr(keys), _ptr(vals), capacity,
+                                           _ptr(ranges), _ptr(touched), _ptr(counts), _ptr(ws),
+                                           ws.numel() * ws.element_size(), _stream()),
+           "tgs_bin_sort_prefix_async")
+
+
+def tgs_bin_sort_continue_async(splat, n, flag_slot, tiles_x, tiles_y, alpha_min, prefix, capacity, ws, vals2,
+                                capacity2, ranges2, counts2, ws2):
+    """The continuation lists of the flagged tiles (Gaussians from depth rank
+    ``prefix`` on) from a prefix call's workspace ``ws``."""
+    _check(lib().tgs_bin_sort_continue_async(_ptr(splat), n, _ptr(flag_slot), tiles_x, tiles_y, float(alpha_min),
+                                             int(prefix), capacity, _ptr(ws), ws.numel() * ws.element_size(),
+                                             _ptr(vals2), capacity2, _ptr(ranges2), _ptr(counts2), _ptr(ws2),
+                                             ws2.numel() * ws2.element_size(), _stream()),
+           "tgs_bin_sort_continue_async")
+
+
+def tgs_render_fwd_prefix(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix,
+                          n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, counters, state, cont_slot,
+                          cont_list, cont_count):
+    _check(lib().tgs_render_fwd_prefix(_ptr(splat), _ptr(vals), _ptr(ranges), tiles_x, tiles_y, width, height,
+                                       _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
+                                       ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(counters), _ptr(state),
+                                       _ptr(cont_slot), _ptr(cont_list), _ptr(cont_count), _stream()),
+           "tgs_render_fwd_prefix")
+
+
+def tgs_render_fwd_cont(splat, vals, ranges, vals2, ranges2, tiles_x, tiles_y, width, height, valid_tiles, tile_off,
+                        pix, n_st, max_per_tile, rp: tgs_raster_params, cont_list, cont_count, out, ncontrib,
+                        counters=None, state=None):
+    _check(lib().tgs_render_fwd_cont(_ptr(splat), _ptr(vals), _ptr(ranges), _ptr(vals2), _ptr(ranges2), tiles_x,
+                                     tiles_y, width, height, _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st,
+                                     max_per_tile, ctypes.byref(rp), _ptr(cont_list), _ptr(cont_count), _ptr(out),
+                                     _ptr(ncontrib), _ptr(counters), _ptr(state), _stream()),
+           "tgs_render_fwd_cont")
+
+
+def tgs_render_bwd2(splat, vals, ranges, vals2, ranges2, tiles_x, tiles_y, width, height, valid_tiles, tile_off,
+                    pix, n_st, max_per_tile, rp: tgs_raster_params, out, ncontrib, dL_dout, g2d, state=None,
+                    touched=None, err=None, n=0, stats=None):
+    """tgs_render_bwd over two-segment lists; with ``stats`` (and err, n) it
+    also adds the density-control sums like tgs_render_bwd_density."""
+    _check(lib().tgs_render_bwd2(_ptr(splat), _ptr(vals), _ptr(ranges), _ptr(vals2), _ptr(ranges2), tiles_x, tiles_y,
+                                 width, height, _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st, max_per_tile,
+                                 ctypes.byref(rp), _ptr(out), _ptr(ncontrib), _ptr(dL_dout), _ptr(g2d), _ptr(state),
+                                 _ptr(touched), _ptr(err), n, _ptr(stats), _stream()), "tgs_render_bwd2")
+
+
+def tgs_density_accumulate2(splat, vals, ranges, vals2, ranges2, tiles_x, tiles_y, width, height, valid_tiles,
+                            tile_off, pix, n_st, max_per_tile, rp: tgs_raster_params, ncontrib, err, n, stats,
+                            state=None):
+    _check(lib().tgs_density_accumulate2(_ptr(splat), _ptr(vals), _ptr(ranges), _ptr(vals2), _ptr(ranges2), tiles_x,
+                                         tiles_y, width, height, _ptr(valid_tiles), _ptr(tile_off), _ptr(pix), n_st,
+                                         max_per_tile, ctypes.byref(rp), _ptr(ncontrib), _ptr(err), _ptr(state), n,
+                                         _ptr(stats), _stream()), "tgs_density_accumulate2")
 
 
 def tgs_render_state_size(n_slots: int, max_per_tile: int) -> int:

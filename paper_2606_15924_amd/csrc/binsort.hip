@@ -37,7 +37,9 @@
 // reorders them by digit in LDS and writes runs of equal digits to
 // consecutive addresses.
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <utility>
 
 #include "scan.h"
@@ -76,7 +78,43 @@ __global__ void __launch_bounds__(64) totals_kernel(const unsigned long long* __
   if (i == 0) {
     counts[0] = v;
     counts[1] = a;
+    counts[3] = a;  // kept when a depth-prefix call replaces counts[1]
     *eff_total = a <= (unsigned long long)capacity ? (uint32_t)a : 0u;
+  }
+}
+
+// Depth-prefix lists: the pairs of the first m Gaussians in depth order
+// are off[m] (the emission's need); the sort takes them when they fit.
+// (counts[3] keeps the whole lists' pair count.)
+__global__ void __launch_bounds__(64) prefix_total_kernel(const uint32_t* __restrict__ off, int64_t m,
+                                                          int64_t capacity, unsigned long long* __restrict__ counts,
+                                                          uint32_t* __restrict__ eff_total) {
+  if (threadIdx.x == 0) {
+    const unsigned long long t = off[m];
+    counts[1] = t;
+    *eff_total = t <= (unsigned long long)capacity ? (uint32_t)t : 0u;
+  }
+}
+
+// The prefix call's three counts: lists' length, pairs emitted, whole-list pairs.
+__global__ void __launch_bounds__(64) copy_counts3_kernel(const unsigned long long* __restrict__ src,
+                                                          unsigned long long* __restrict__ dst) {
+  if (threadIdx.x < 3) dst[threadIdx.x] = src[threadIdx.x == 2 ? 3 : threadIdx.x];
+}
+
+// counts[0] = the lists' length: the end of the last non-empty range (the
+// ranges are contiguous from 0 in tile order; sentinel pairs lie past it).
+__global__ void __launch_bounds__(256) list_len_kernel(const uint2* __restrict__ ranges, uint32_t n_t,
+                                                       unsigned long long* __restrict__ counts) {
+  __shared__ uint32_t lds[256 / kWave];
+  uint32_t m = 0;
+  for (uint32_t t = threadIdx.x; t < n_t; t += 256) m = max(m, ranges[t].y);
+  m = (uint32_t)wave_max_u32(m);
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 256 / kWave; ++k) m = max(m, lds[k]);
+    counts[0] = m;
   }
 }
 
@@ -340,6 +378,101 @@ __global__ void __launch_bounds__(kWave) count_kernel(
     if (lane == 0 && tot > 0)
       atomicAdd(&totals[k * TGS_COUNTER_SLOTS + (blockIdx.x & (TGS_COUNTER_SLOTS - 1))], (unsigned long long)tot);
   }
+}
+
+// Summed-area table of the flagged tiles (one workgroup): sat[(y + 1) *
+// (tiles_x + 1) + x + 1] = flagged tiles in rows < y + 1, columns < x + 1;
+// row 0 and column 0 are zero.  Row prefix sums first (a thread per tile
+// row), then column sums (a thread per column).
+__global__ void __launch_bounds__(1024) flag_sat_kernel(const int32_t* __restrict__ flag_slot, int tiles_x,
+                                                        int tiles_y, uint32_t* __restrict__ sat) {
+  const int W1 = tiles_x + 1;
+  for (int y = threadIdx.x; y <= tiles_y; y += 1024) {
+    uint32_t run = 0;
+    sat[(int64_t)y * W1] = 0u;
+    for (int x = 0; x < tiles_x; ++x) {
+      if (y > 0) run += flag_slot[(int64_t)(y - 1) * tiles_x + x] >= 0 ? 1u : 0u;
+      sat[(int64_t)y * W1 + x + 1] = run;
+    }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x <= tiles_x; x += 1024) {
+    uint32_t run = 0;
+    for (int y = 0; y <= tiles_y; ++y) {
+      run += sat[(int64_t)y * W1 + x];
+      sat[(int64_t)y * W1 + x] = run;
+    }
+  }
+}
+
+// Continuation counts: one wave per 64 Gaussians of the depth order from a
+// given rank on (their rectangles, ids and first-pass pair counts in that
+// order).  Per Gaussian: its kept pairs in the flagged tiles (tile map
+// entry >= 0), by the same row spans.  Gaussians without pairs in the first
+// pass, or whose rectangle holds no flagged tile (four reads of the
+// summed-area table, when given), are skipped before their splat is read.
+// The sum goes to the 64-bit totals (both slots).
+__global__ void __launch_bounds__(kWave) count_cont_kernel(
+    const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ ids_sorted,
+    const uint32_t* __restrict__ cnt_sorted, int64_t m, const float4* __restrict__ splat,
+    const int32_t* __restrict__ flag_slot, const uint32_t* __restrict__ sat, int tiles_x, int tiles_y, double tau,
+    double lia, uint32_t* __restrict__ cnt, unsigned long long* __restrict__ totals) {
+  __shared__ CountBatch cb;
+  __shared__ uint64_t s_red[1];
+  const int lane = lane_id();
+  const int64_t k = (int64_t)blockIdx.x * kCountBatch + lane;
+  bool mine = k < m && cnt_sorted[k] > 0;
+  int4 r = make_int4(0, 0, 0, 0);
+  uint32_t g = 0;
+  if (mine) {
+    r = clamp_rect(rect_sorted[k], tiles_x, tiles_y);
+    if (sat != nullptr) {
+      const int64_t W1 = tiles_x + 1;
+      const uint32_t f = sat[r.w * W1 + r.z] - sat[r.y * W1 + r.z] - sat[r.w * W1 + r.x] + sat[r.y * W1 + r.x];
+      if (f == 0u) {
+        mine = false;
+        r = make_int4(0, 0, 0, 0);
+      }
+    }
+    if (mine) g = ids_sorted[k];
+  }
+  const uint32_t rows = r.z > r.x ? (uint32_t)(r.w - r.y) : 0u;
+  const uint32_t incl = wave_inclusive_scan_u32(rows);
+  const uint32_t my_row0 = incl - rows;
+  const uint32_t n_rows = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+  cb.rect[lane] = r;
+  cb.row0[lane] = my_row0;
+  cb.valid[lane] = 0u;
+  if (rows > 0) cb.ell[lane] = load_row_ellipse(splat, g, tau, lia);
+  int carry = -1;
+  for (uint32_t f0 = 0; f0 < n_rows; f0 += kWave) {
+    cb.mark[lane] = -1;
+    __syncthreads();
+    if (rows > 0 && my_row0 >= f0 && my_row0 - f0 < (uint32_t)kWave) cb.mark[my_row0 - f0] = lane;
+    __syncthreads();
+    const int jl = max(wave_max_scan(cb.mark[lane]), carry);
+    carry = __builtin_amdgcn_readlane(jl, kWave - 1);
+    const uint32_t f = f0 + (uint32_t)lane;
+    if (f < n_rows && jl >= 0) {
+      const int4 rj = cb.rect[jl];
+      const int ty = rj.y + (int)(f - cb.row0[jl]);
+      int lo, hi;
+      row_span(cb.ell[jl], ty, rj.x, rj.z, lo, hi);
+      uint32_t cv = 0u;
+      const int32_t* trow = flag_slot + (int64_t)ty * tiles_x;
+      for (int tx = lo; tx <= hi; ++tx) cv += trow[tx] >= 0 ? 1u : 0u;
+      if (cv > 0) atomicAdd(&cb.valid[jl], cv);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const uint32_t valid = cb.valid[lane];
+  if (k < m) cnt[k] = valid;
+  uint64_t tot;
+  block_exclusive_scan<kWave, uint64_t>((uint64_t)valid, s_red, &tot);
+  if (lane == 0 && tot > 0)
+    for (int q = 0; q < 2; ++q)
+      atomicAdd(&totals[q * TGS_COUNTER_SLOTS + (blockIdx.x & (TGS_COUNTER_SLOTS - 1))], (unsigned long long)tot);
 }
 
 // ------------------------------------------------------------------ ranges
@@ -723,7 +856,7 @@ struct RowBatch {
   int mark[kWave];
   // a round's row spans: first column, tile id of the row's column 0, id,
   // first output (exclusive prefix of the span lengths)
-  int lo[kWave];
+  int lo[kWave], hi[kWave];
   uint32_t trow[kWave], gid[kWave], ex[kWave];
 };
 
@@ -739,7 +872,11 @@ constexpr int kEmitBatch = 32;       // Gaussians per wave: more waves, fewer ro
 // starting from the batch's first pair offset (pairs are emitted Gaussian by
 // Gaussian, row by row, columns ascending).  Tiles outside the valid set get
 // the sentinel tile id n_t.
-template <typename K>
+//
+// kFilter: only the tiles whose map entry is >= 0 are emitted (the
+// continuation lists); a row's outputs are then its flagged columns in
+// ascending order, each output lane walking the row's span to its column.
+template <typename K, bool kFilter>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ off, const uint32_t* __restrict__ ids_sorted,
     int64_t n, const float4* __restrict__ splat, const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t,
@@ -787,7 +924,13 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
       gid = rb.id[jl];
       row_span(rb.ell[jl], ty, rj.x, rj.z, lo, hi);
     }
-    const uint32_t c = (uint32_t)max(hi - lo + 1, 0);
+    uint32_t c = (uint32_t)max(hi - lo + 1, 0);
+    if (kFilter && c > 0) {
+      const int32_t* tr = tile_slot + (int64_t)ty * tiles_x;
+      uint32_t cf = 0u;
+      for (int tx = lo; tx <= hi; ++tx) cf += tr[tx] >= 0 ? 1u : 0u;
+      c = cf;
+    }
     const uint32_t ci = wave_inclusive_scan_u32(c);
     const uint32_t n_out = (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
     // the round's rows write n_out consecutive pairs from base + written; they
@@ -795,6 +938,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     // covers consecutive addresses: the row owning an output is found like
     // the rows' owners above (its first output marked, a max-scan carries it)
     rb.lo[lane] = lo;
+    rb.hi[lane] = hi;
     rb.trow[lane] = in ? (uint32_t)ty * (uint32_t)tiles_x : 0u;
     rb.gid[lane] = gid;
     rb.ex[lane] = ci - c;
@@ -810,8 +954,21 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
       const uint32_t pos = base + written + q;
       // own >= 0 whenever q < n_out: output 0 belongs to the first row with pairs
       if (q < n_out && own >= 0 && pos < total) {  // pos < total always holds; the bound is a safeguard
-        uint32_t tile = rb.trow[own] + (uint32_t)(rb.lo[own] + (int)(q - rb.ex[own]));
-        if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
+        uint32_t tile;
+        if (kFilter) {  // the (q - ex)-th flagged column of the row (there are c of them)
+          int left = (int)(q - rb.ex[own]), tx = rb.lo[own];
+          const uint32_t tr = rb.trow[own];
+          for (; tx < rb.hi[own]; ++tx) {
+            if (tile_slot[tr + (uint32_t)tx] >= 0) {
+              if (left == 0) break;
+              --left;
+            }
+          }
+          tile = tr + (uint32_t)tx;
+        } else {
+          tile = rb.trow[own] + (uint32_t)(rb.lo[own] + (int)(q - rb.ex[own]));
+          if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
+        }
         if (pay != nullptr) {  // the id as a separate payload, the key is the tile alone
           keys[pos] = (K)tile;
           pay[pos] = rb.gid[own];
@@ -942,7 +1099,7 @@ static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_
 // 64-bit key would move 16 bytes per pair and pass instead of 12.
 // bound: the capacity (host), sizing every grid; the pair count itself is
 // read on the device (w.eff_total), so nothing here waits for the host.
-template <typename K, bool kPay>
+template <typename K, bool kPay, bool kFilter = false>
 static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t bound, const float4* splat,
                        const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits, int tbits, double tau, double lia,
                        const float* depth, uint32_t* vals, uint64_t* keys64, uint32_t* ranges, hipStream_t s) {
@@ -952,7 +1109,8 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
   if (kPay)
     for (int k = 0; k < 2; ++k) pb[k] = (uint32_t*)((char*)w.pkeys[k] + align_up(sizeof(K) * (size_t)w.cap, 256));
   const int key_id_bits = kPay ? 0 : id_bits;
-  hipLaunchKernelGGL((emit_kernel<K>), dim3((unsigned)ceil_div(n, kEmitBatch)), dim3(kEmitThreads), 0, s,
+  hipLaunchKernelGGL((emit_kernel<K, kFilter>), dim3((unsigned)std::max<int64_t>(ceil_div(n, kEmitBatch), 1)),
+                     dim3(kEmitThreads), 0, s,
                      w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, key_id_bits, tau, lia, w.eff_total,
                      kb[0], pb[0]);
   const int passes = pass_count(tbits);
@@ -985,10 +1143,14 @@ extern "C" size_t tgs_bin_sort_workspace_size(int64_t n, int64_t capacity, int32
 }
 
 // Everything after the argument checks: queued on the stream, no host wait.
+// prefix >= 0: the lists hold the pairs of the first `prefix` Gaussians in
+// (depth, id) order only (every Gaussian when prefix >= n), and the counts
+// are the prefix call's (w.counts[3] = the whole lists' pairs); -1: whole
+// lists with the plain counts.
 static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const float* depth, int64_t n,
                               const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
                               uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* ranges, uint8_t* touched,
-                              const SortWs& w, hipStream_t s, const char* who) {
+                              const SortWs& w, hipStream_t s, const char* who, int64_t prefix = -1) {
   const uint32_t n_t = (uint32_t)tiles_x * (uint32_t)tiles_y;
   // 2 ln(1/alpha_min) with a 0.1 % margin, rounded up to a multiple of 1/64
   const double lia = std::log(1.0 / (double)alpha_min);
@@ -1007,19 +1169,68 @@ static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const flo
   sort_depth(w, (uint32_t)n, (const int4*)rect, tiles_x, tiles_y, s);
   // pair offsets (they wrap only past 2^32 pairs, where the capacity check has already set the total to 0)
   exclusive_scan<uint32_t>(w.cnt_sorted, w.off, n, w.partials, s);
+  const bool pre = prefix >= 0;
+  const int64_t m = pre ? std::min(prefix, n) : n;
+  if (pre) hipLaunchKernelGGL(prefix_total_kernel, dim3(1), dim3(64), 0, s, w.off, m, capacity, w.counts, w.eff_total);
   if (capacity == 0) return hip_status(who);
   const uint32_t bound = (uint32_t)capacity;
   const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
   const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
   if (id_bits + tbits <= 32)
-    sort_pairs<uint32_t, false>(w, w.ids_sorted, n, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+    sort_pairs<uint32_t, false>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
                                 tbits, tau, lia, depth, vals, keys, ranges, s);
   else if (tbits <= 16)
-    sort_pairs<uint16_t, true>(w, w.ids_sorted, n, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+    sort_pairs<uint16_t, true>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
                                tbits, tau, lia, depth, vals, keys, ranges, s);
   else
-    sort_pairs<uint32_t, true>(w, w.ids_sorted, n, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
+    sort_pairs<uint32_t, true>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
                                tbits, tau, lia, depth, vals, keys, ranges, s);
+  if (pre) hipLaunchKernelGGL(list_len_kernel, dim3(1), dim3(256), 0, s, (const uint2*)ranges, n_t, w.counts);
+  return hip_status(who);
+}
+
+// The continuation of depth-prefix lists: the pairs of the Gaussians from
+// depth rank `prefix` on in the flagged tiles, from the depth order that
+// the prefix call left in its workspace w1, sorted by tile (each tile's
+// list in depth order) with the scratch and pair buffers of w2.
+static int32_t continue_queue(const float* splat, int64_t n, const int32_t* flag_slot, int32_t tiles_x,
+                              int32_t tiles_y, float alpha_min, int64_t prefix, uint32_t* vals2, int64_t capacity2,
+                              uint32_t* ranges2, const SortWs& w1, const SortWs& w2, hipStream_t s,
+                              const char* who) {
+  const uint32_t n_t = (uint32_t)tiles_x * (uint32_t)tiles_y;
+  const double lia = std::log(1.0 / (double)alpha_min);
+  const double tau = std::ceil(128.0 * lia * 1.001) / 64.0;
+  hipLaunchKernelGGL(zero2_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t + w2.zeroed_words, 256)), dim3(256),
+                     0, s, ranges2, 2 * (int64_t)n_t, w2.zeroed, w2.zeroed_words);
+  const int64_t m = n - std::min(prefix, n);
+  // the flagged tiles' summed-area table in the pair-sort histogram (free
+  // until the sort), when it fits
+  const int64_t sat_words = (int64_t)(tiles_x + 1) * (tiles_y + 1);
+  uint32_t* sat = sat_words <= 256 * 1024 ? w2.hist : nullptr;
+  if (m > 0 && sat != nullptr)
+    hipLaunchKernelGGL(flag_sat_kernel, dim3(1), dim3(1024), 0, s, flag_slot, tiles_x, tiles_y, sat);
+  if (m > 0)
+    hipLaunchKernelGGL(count_cont_kernel, dim3((unsigned)ceil_div(m, kCountBatch)), dim3(kWave), 0, s,
+                       w1.rect_sorted + prefix, w1.ids_sorted + prefix, w1.cnt_sorted + prefix, m,
+                       (const float4*)splat, flag_slot, (const uint32_t*)sat, tiles_x, tiles_y, tau, lia,
+                       w2.emit_cnt, w2.scalars);
+  hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w2.scalars, capacity2, w2.counts, w2.eff_total);
+  if (m == 0 || capacity2 == 0) return hip_status(who);
+  exclusive_scan<uint32_t>(w2.emit_cnt, w2.off, m, w2.partials, s);
+  SortWs wc = w2;
+  wc.rect_sorted = w1.rect_sorted + prefix;
+  const uint32_t bound = (uint32_t)capacity2;
+  const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
+  const int tbits = bits_for(n_t);
+  if (id_bits + tbits <= 32)
+    sort_pairs<uint32_t, false, true>(wc, w1.ids_sorted + prefix, m, bound, (const float4*)splat, flag_slot, tiles_x,
+                                      n_t, id_bits, tbits, tau, lia, nullptr, vals2, nullptr, ranges2, s);
+  else if (tbits <= 16)
+    sort_pairs<uint16_t, true, true>(wc, w1.ids_sorted + prefix, m, bound, (const float4*)splat, flag_slot, tiles_x,
+                                     n_t, id_bits, tbits, tau, lia, nullptr, vals2, nullptr, ranges2, s);
+  else
+    sort_pairs<uint32_t, true, true>(wc, w1.ids_sorted + prefix, m, bound, (const float4*)splat, flag_slot, tiles_x,
+                                     n_t, id_bits, tbits, tau, lia, nullptr, vals2, nullptr, ranges2, s);
   return hip_status(who);
 }
 
@@ -1055,6 +1266,53 @@ extern "C" int32_t tgs_bin_sort_async(const int32_t* rect, const float* splat, c
   hipLaunchKernelGGL(copy_counts_kernel, dim3(1), dim3(64), 0, s, (const unsigned long long*)w.counts,
                      (unsigned long long*)counts);
   return hip_status("tgs_bin_sort_async");
+}
+
+extern "C" int32_t tgs_bin_sort_prefix_async(const int32_t* rect, const float* splat, const float* depth, int64_t n,
+                                             const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y,
+                                             float alpha_min, int64_t prefix, uint64_t* keys, uint32_t* vals,
+                                             int64_t capacity, uint32_t* ranges, uint8_t* touched, int64_t* counts,
+                                             void* ws, size_t ws_bytes, void* stream) {
+  const SortWs w = layout(ws, n, capacity);
+  if (int32_t e = bin_sort_check(rect, splat, depth, n, tiles_x, tiles_y, alpha_min, vals, capacity, ranges, ws,
+                                 ws_bytes, w, "tgs_bin_sort_prefix_async"))
+    return e;
+  TGS_REQUIRE(prefix >= 0, "tgs_bin_sort_prefix_async: negative prefix");
+  TGS_REQUIRE(counts != nullptr && ((uintptr_t)counts & 7) == 0,
+              "tgs_bin_sort_prefix_async: counts must be an 8-byte aligned device pointer");
+  hipStream_t s = as_stream(stream);
+  if (int32_t e = bin_sort_queue(rect, splat, depth, n, tile_slot, tiles_x, tiles_y, alpha_min, keys, vals, capacity,
+                                 ranges, touched, w, s, "tgs_bin_sort_prefix_async", prefix))
+    return e;
+  hipLaunchKernelGGL(copy_counts3_kernel, dim3(1), dim3(64), 0, s, (const unsigned long long*)w.counts,
+                     (unsigned long long*)counts);
+  return hip_status("tgs_bin_sort_prefix_async");
+}
+
+extern "C" int32_t tgs_bin_sort_continue_async(const float* splat, int64_t n, const int32_t* flag_slot,
+                                               int32_t tiles_x, int32_t tiles_y, float alpha_min, int64_t prefix,
+                                               int64_t capacity, const void* ws, size_t ws_bytes, uint32_t* vals2,
+                                               int64_t capacity2, uint32_t* ranges2, int64_t* counts2, void* ws2,
+                                               size_t ws2_bytes, void* stream) {
+  const char* who = "tgs_bin_sort_continue_async";
+  TGS_REQUIRE(n >= 0 && n < (1ll << 31) && prefix >= 0, "%s: n or prefix out of range", who);
+  TGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && (int64_t)tiles_x * tiles_y < (1ll << 30), "%s: bad tile grid", who);
+  TGS_REQUIRE(capacity >= 0 && capacity2 >= 0 && capacity2 < (1ll << 32), "%s: capacity out of range", who);
+  TGS_REQUIRE(alpha_min > 0.f && alpha_min < 1.f, "%s: alpha_min %g not in (0, 1)", who, (double)alpha_min);
+  TGS_REQUIRE(splat && flag_slot && ws && vals2 && ranges2 && counts2 && ws2, "%s: null pointer", who);
+  TGS_REQUIRE(((uintptr_t)splat & 15) == 0 && ((uintptr_t)ws & 15) == 0 && ((uintptr_t)ws2 & 15) == 0 &&
+                  ((uintptr_t)counts2 & 7) == 0,
+              "%s: splat, ws and ws2 must be 16-byte, counts2 8-byte aligned", who);
+  const SortWs w1 = layout((void*)ws, n, capacity);
+  const SortWs w2 = layout(ws2, n, capacity2);
+  TGS_REQUIRE(ws_bytes >= w1.bytes && ws2_bytes >= w2.bytes, "%s: workspace too small", who);
+  hipStream_t s = as_stream(stream);
+  if (int32_t e = continue_queue(splat, n, flag_slot, tiles_x, tiles_y, alpha_min, prefix, vals2, capacity2, ranges2,
+                                 w1, w2, s, who))
+    return e;
+  hipLaunchKernelGGL(copy_counts_kernel, dim3(1), dim3(64), 0, s, (const unsigned long long*)w2.counts,
+                     (unsigned long long*)counts2);
+  return hip_status(who);
 }
 
 extern "C" int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const float* depth, int64_t n,

@@ -126,6 +126,12 @@ __device__ __forceinline__ int wave_inclusive_scan_i_dpp(int v) {
   return v;
 }
 
+// Maximum over the 64 lanes (every lane receives it).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
+  return v;
+}
+
 __device__ __forceinline__ uint32_t wave_inclusive_scan_u32(uint32_t v) {
   const int lane = lane_id();
 #pragma unroll

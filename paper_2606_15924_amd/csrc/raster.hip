@@ -35,13 +35,47 @@ struct RasterArgs {
   const float4* splat;
   const uint32_t* vals;
   const uint2* ranges;
+  // optional second segment of every tile's list (depth-prefix lists and
+  // their continuation): the tile's list is vals[ranges[t]] followed by
+  // vals2[ranges2[t]]
+  const uint32_t* vals2;
+  const uint2* ranges2;
   const int32_t* valid_tiles;
   const int32_t* tile_off;
   const uint8_t* pix;
   int tiles_x, tiles_y, width, height;
   float alpha_min, alpha_max, T_min;
   float bg0, bg1, bg2;
+  // forward only: 0 plain; 1 depth-prefix pass (marks the tiles with a
+  // pixel that ran off its list without the T_min stop, counts the other
+  // pixels); 2 continuation pass over the slots cont_list[0 .. *cont_count)
+  // (counts only the pixels the prefix pass left open)
+  int mode;
+  int32_t* cont_slot;     // [n_tiles] -1, or the slot of a marked tile (mode 1)
+  uint32_t* cont_list;    // marked slots (written in mode 1, read in mode 2)
+  uint32_t* cont_count;   // their number
 };
+
+// One tile's list: n1 entries from vals at b1, then len - n1 from vals2 at
+// b2.  Positions are list-relative (0 .. len).
+struct TileList {
+  uint32_t b1, n1, b2, len;
+};
+
+__device__ __forceinline__ TileList tile_list(const RasterArgs& a, int tile) {
+  const uint2 r = a.ranges[tile];
+  TileList L{r.x, r.y - r.x, 0u, r.y - r.x};
+  if (a.ranges2 != nullptr) {
+    const uint2 q = a.ranges2[tile];
+    L.b2 = q.x;
+    L.len += q.y - q.x;
+  }
+  return L;
+}
+
+__device__ __forceinline__ uint32_t list_id(const RasterArgs& a, const TileList& L, uint32_t pos) {
+  return pos < L.n1 ? a.vals[L.b1 + pos] : a.vals2[L.b2 + (pos - L.n1)];
+}
 
 // The alpha decisions must come out bit-identical in the forward and the
 // replay, so both evaluate alpha through these functions, written with
@@ -148,25 +182,28 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
   __shared__ float4 s_geo[kBlock];
   __shared__ float4 s_app[kBlock];
   __shared__ float s_blue[kBlock];
-  const int slot = blockIdx.x, tid = threadIdx.x;
+  if (a.mode == 2 && blockIdx.x >= *a.cont_count) return;  // workgroup-uniform
+  const int slot = a.mode == 2 ? (int)a.cont_list[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
   const int tile = kDense ? slot : a.valid_tiles[slot];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const PixelSlot px = pixel_of<kBlock, kDense>(a, slot, tile, tid);
   const float lx = (float)(px.loc & 15), ly = (float)(px.loc >> 4);
   const float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
-  const uint2 range = a.ranges[tile];
+  const TileList L = tile_list(a, tile);
+  const uint2 range = make_uint2(0u, L.len);
   const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.T_min;
 
   float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
   uint32_t last = 0;
   uint32_t n_eval = 0, n_blend = 0;  // this lane's evaluations and blends (summed over the wave at the end)
-  bool done = !px.inside;
+  bool done = !px.inside, stopped = false;
+  uint32_t stop_at = 0;  // list position of the T_min stop
 
   // prologue: records of batch 0 and ids of batch 1 in flight
   Staged nxt = {};
   uint32_t g_after = 0;
-  if (range.x + tid < range.y) nxt = stage_load(a, a.vals[range.x + tid], x0, y0);
-  if (range.x + kBlock + tid < range.y) g_after = a.vals[range.x + kBlock + tid];
+  if (range.x + tid < range.y) nxt = stage_load(a, list_id(a, L, range.x + tid), x0, y0);
+  if (range.x + kBlock + tid < range.y) g_after = list_id(a, L, range.x + kBlock + tid);
 
   for (uint32_t start = range.x; start < range.y; start += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
@@ -177,7 +214,7 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
     __syncthreads();
     const uint32_t i1 = start + kBlock + tid, i2 = start + 2 * kBlock + tid;
     if (i1 < range.y) nxt = stage_load(a, g_after, x0, y0);
-    if (i2 < range.y) g_after = a.vals[i2];
+    if (i2 < range.y) g_after = list_id(a, L, i2);
     const int cnt = (int)min((uint32_t)kBlock, range.y - start);
     const uint32_t pos0 = start - range.x;
     // groups of kUnroll Gaussians: their alphas are independent and are
@@ -208,6 +245,8 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
         bool ok = !done && pw[u] <= 0.f && al[u] >= amin;
         n_eval += (j + u < cnt && !done) ? 1u : 0u;
         const bool stop = ok && t_next < tmin;
+        stop_at = stop ? pos0 + (uint32_t)(j + u) : stop_at;
+        stopped = stopped || stop;
         done = done || stop;
         ok = ok && !stop;
         const float w = ok ? al[u] * T : 0.f;
@@ -223,6 +262,17 @@ __global__ void __launch_bounds__(kBlock) render_fwd_kernel(RasterArgs a, float4
   if (px.inside) {
     out[px.out] = make_float4(c0 + T * a.bg0, c1 + T * a.bg1, c2 + T * a.bg2, T);
     ncontrib[px.out] = last;
+  }
+  if (a.mode == 1) {
+    // a pixel that ran off its list without stopping needs the continuation;
+    // its counts come from the continuation pass
+    const bool open = px.inside && !stopped;
+    if (open) n_eval = n_blend = 0u;
+    if (__ballot(open) != 0ull && lane_id() == 0 &&
+        atomicCAS(&a.cont_slot[tile], -1, slot) == -1)  // the tile's first marking wave lists it
+      a.cont_list[atomicAdd(a.cont_count, 1u)] = (uint32_t)slot;
+  } else if (a.mode == 2 && stopped && stop_at < L.n1) {
+    n_eval = n_blend = 0u;  // stopped within the prefix: counted by the prefix pass
   }
   if (counters != nullptr) {
     n_eval = (uint32_t)wave_sum_i((int)n_eval);
@@ -371,7 +421,8 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
   const int slot = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
   const int tile = kDense ? slot : a.valid_tiles[slot];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const uint2 range = a.ranges[tile];
+  const TileList L = tile_list(a, tile);
+  const uint2 range = make_uint2(0u, L.len);
   // list positions [begin, end) of this chunk (one chunk without a state record)
   const uint32_t begin = range.x + (uint32_t)(chunk * TGS_RENDER_CHUNK_LEN);
   if (begin >= range.y && chunk > 0) return;  // workgroup-uniform
@@ -411,8 +462,8 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
 
   Staged nxt = {};
   uint32_t g_after = 0;
-  if (begin + tid < end) nxt = stage_load(a, a.vals[begin + tid], x0, y0);
-  if (begin + kBlock + tid < end) g_after = a.vals[begin + kBlock + tid];
+  if (begin + tid < end) nxt = stage_load(a, list_id(a, L, begin + tid), x0, y0);
+  if (begin + kBlock + tid < end) g_after = list_id(a, L, begin + kBlock + tid);
 
   for (uint32_t start = begin; start < end; start += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
@@ -424,7 +475,7 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
     __syncthreads();
     const uint32_t i1 = start + kBlock + tid, i2 = start + 2 * kBlock + tid;
     if (i1 < end) nxt = stage_load(a, g_after, x0, y0);
-    if (i2 < end) g_after = a.vals[i2];
+    if (i2 < end) g_after = list_id(a, L, i2);
     const int cnt = (int)min((uint32_t)kBlock, end - start);
     const uint32_t pos0 = start - range.x;
     for (int j = 0; j < cnt; j += kUnrollB) {
@@ -476,7 +527,8 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
           const uint32_t gid = __builtin_amdgcn_readfirstlane(s_gid[j + u]);  // uniform
           if (touched != nullptr && lane_id() == 0) touched[gid] = 1u;  // composited at a sample
           if constexpr (kDet) {
-            const size_t rec = (size_t)(start + (uint32_t)(j + u)) * (kBlock / kWave) + (size_t)(tid / kWave);
+            // the pair's index in vals (the deterministic backward takes single-segment lists)
+            const size_t rec = (size_t)(L.b1 + start + (uint32_t)(j + u)) * (kBlock / kWave) + (size_t)(tid / kWave);
             wave_sum9_store(v, g2d + rec * 9, sl);
           } else if constexpr (kDensity) {
             constexpr float kTwoLn2 = 1.3862943611198906f;
@@ -516,7 +568,8 @@ __global__ void __launch_bounds__(kBlock) render_accum_kernel(RasterArgs a, cons
   const int slot = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
   const int tile = kDense ? slot : a.valid_tiles[slot];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const uint2 range = a.ranges[tile];
+  const TileList L = tile_list(a, tile);
+  const uint2 range = make_uint2(0u, L.len);
   const uint32_t begin = range.x + (uint32_t)(chunk * TGS_RENDER_CHUNK_LEN);
   if (begin >= range.y && chunk > 0) return;  // workgroup-uniform
   const uint32_t end =
@@ -542,8 +595,8 @@ __global__ void __launch_bounds__(kBlock) render_accum_kernel(RasterArgs a, cons
 
   Staged nxt = {};
   uint32_t g_after = 0;
-  if (begin + tid < end) nxt = stage_load(a, a.vals[begin + tid], x0, y0);
-  if (begin + kBlock + tid < end) g_after = a.vals[begin + kBlock + tid];
+  if (begin + tid < end) nxt = stage_load(a, list_id(a, L, begin + tid), x0, y0);
+  if (begin + kBlock + tid < end) g_after = list_id(a, L, begin + kBlock + tid);
 
   for (uint32_t start = begin; start < end; start += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
@@ -555,7 +608,7 @@ __global__ void __launch_bounds__(kBlock) render_accum_kernel(RasterArgs a, cons
     __syncthreads();
     const uint32_t i1 = start + kBlock + tid, i2 = start + 2 * kBlock + tid;
     if (i1 < end) nxt = stage_load(a, g_after, x0, y0);
-    if (i2 < end) g_after = a.vals[i2];
+    if (i2 < end) g_after = list_id(a, L, i2);
     const int cnt = (int)min((uint32_t)kBlock, end - start);
     const uint32_t pos0 = start - range.x;
     for (int j = 0; j < cnt; j += kUnrollB) {
@@ -705,7 +758,28 @@ static int32_t make_args(const float* splat, const uint32_t* vals, const uint32_
   a.bg0 = rp->bg[0];
   a.bg1 = rp->bg[1];
   a.bg2 = rp->bg[2];
+  a.vals2 = nullptr;
+  a.ranges2 = nullptr;
+  a.mode = 0;
+  a.cont_slot = nullptr;
+  a.cont_list = nullptr;
+  a.cont_count = nullptr;
   return TGS_OK;
+}
+
+// The second list segment of the two-segment entry points.
+static int32_t set_second(RasterArgs& a, const uint32_t* vals2, const uint32_t* ranges2, const char* who) {
+  TGS_REQUIRE(vals2 && ranges2, "%s: null vals2/ranges2", who);
+  a.vals2 = vals2;
+  a.ranges2 = (const uint2*)ranges2;
+  return TGS_OK;
+}
+
+__global__ void __launch_bounds__(256) fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v,
+                                                       uint32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+  if (i == 0 && count != nullptr) *count = 0u;
 }
 
 }  // namespace tgs
@@ -715,6 +789,22 @@ using namespace tgs;
 extern "C" size_t tgs_render_state_size(int32_t n_slots, int32_t max_per_tile) {
   if (n_slots < 0 || max_per_tile < 0 || max_per_tile > kTilePixels) return 0;
   return (size_t)n_slots * (TGS_RENDER_CHUNKS - 1) * (size_t)raster_block(false, max_per_tile) * sizeof(float4);
+}
+
+static int32_t render_fwd_launch(const RasterArgs& a, bool dense, int32_t n_st, int32_t max_per_tile, float* out,
+                                 uint32_t* ncontrib, uint64_t* counters, float* state, hipStream_t s,
+                                 const char* who) {
+  TGS_REQUIRE(out && ncontrib, "%s: null output", who);
+  TGS_REQUIRE(((uintptr_t)out & 15) == 0 && ((uintptr_t)state & 15) == 0, "%s: out and state must be 16-byte aligned",
+              who);
+  if (dense) {
+    launch_fwd<256, true>(a, a.tiles_x * a.tiles_y, out, ncontrib, counters, state, s);
+  } else if (n_st > 0) {
+    if (max_per_tile <= 64) launch_fwd<64, false>(a, n_st, out, ncontrib, counters, state, s);
+    else if (max_per_tile <= 128) launch_fwd<128, false>(a, n_st, out, ncontrib, counters, state, s);
+    else launch_fwd<256, false>(a, n_st, out, ncontrib, counters, state, s);
+  }
+  return hip_status(who);
 }
 
 extern "C" int32_t tgs_render_fwd(const float* splat, const uint32_t* vals, const uint32_t* ranges,
@@ -727,18 +817,70 @@ extern "C" int32_t tgs_render_fwd(const float* splat, const uint32_t* vals, cons
   if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
                             tile_off, pix, n_st, max_per_tile, rp, "tgs_render_fwd", a))
     return e;
-  TGS_REQUIRE(out && ncontrib, "tgs_render_fwd: null output");
-  TGS_REQUIRE(((uintptr_t)out & 15) == 0 && ((uintptr_t)state & 15) == 0,
-              "tgs_render_fwd: out and state must be 16-byte aligned");
+  return render_fwd_launch(a, valid_tiles == nullptr, n_st, max_per_tile, out, ncontrib, counters, state,
+                           as_stream(stream), "tgs_render_fwd");
+}
+
+extern "C" int32_t tgs_render_fwd_prefix(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                                         int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
+                                         const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                                         int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp, float* out,
+                                         uint32_t* ncontrib, uint64_t* counters, float* state, int32_t* cont_slot,
+                                         uint32_t* cont_list, uint32_t* cont_count, void* stream) {
+  const char* who = "tgs_render_fwd_prefix";
+  RasterArgs a;
+  if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix, n_st,
+                            max_per_tile, rp, who, a))
+    return e;
+  TGS_REQUIRE(cont_slot && cont_list && cont_count, "%s: null continuation outputs", who);
+  a.mode = 1;
+  a.cont_slot = cont_slot;
+  a.cont_list = cont_list;
+  a.cont_count = cont_count;
   hipStream_t s = as_stream(stream);
-  if (valid_tiles == nullptr) {
-    launch_fwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, counters, state, s);
+  const int64_t n_t = (int64_t)tiles_x * tiles_y;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)ceil_div(n_t, 256)), dim3(256), 0, s, cont_slot, n_t, -1,
+                     cont_count);
+  return render_fwd_launch(a, valid_tiles == nullptr, n_st, max_per_tile, out, ncontrib, counters, state, s, who);
+}
+
+extern "C" int32_t tgs_render_fwd_cont(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                                       const uint32_t* vals2, const uint32_t* ranges2, int32_t tiles_x,
+                                       int32_t tiles_y, int32_t width, int32_t height, const int32_t* valid_tiles,
+                                       const int32_t* tile_off, const uint8_t* pix, int32_t n_st,
+                                       int32_t max_per_tile, const tgs_raster_params* rp, const uint32_t* cont_list,
+                                       const uint32_t* cont_count, float* out, uint32_t* ncontrib,
+                                       uint64_t* counters, float* state, void* stream) {
+  const char* who = "tgs_render_fwd_cont";
+  RasterArgs a;
+  if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix, n_st,
+                            max_per_tile, rp, who, a))
+    return e;
+  if (int32_t e = set_second(a, vals2, ranges2, who)) return e;
+  TGS_REQUIRE(cont_list && cont_count, "%s: null continuation list", who);
+  a.mode = 2;
+  a.cont_list = (uint32_t*)cont_list;
+  a.cont_count = (uint32_t*)cont_count;
+  return render_fwd_launch(a, valid_tiles == nullptr, n_st, max_per_tile, out, ncontrib, counters, state,
+                           as_stream(stream), who);
+}
+
+static int32_t render_bwd_launch(const RasterArgs& a, bool dense, int32_t n_st, int32_t max_per_tile,
+                                 const float* out, const uint32_t* ncontrib, const float* dL_dout, float* g2d,
+                                 const float* state, uint8_t* touched, const DensityArgs* dens, hipStream_t s,
+                                 const char* who) {
+  TGS_REQUIRE(out && ncontrib && dL_dout && g2d, "%s: null pointer", who);
+  TGS_REQUIRE(((uintptr_t)out & 15) == 0 && ((uintptr_t)dL_dout & 15) == 0 && ((uintptr_t)state & 15) == 0,
+              "%s: out, dL_dout and state must be 16-byte aligned", who);
+  if (dense) {
+    launch_bwd<256, true>(a, a.tiles_x * a.tiles_y, out, ncontrib, dL_dout, g2d, state, touched, s, dens);
   } else if (n_st > 0) {
-    if (max_per_tile <= 64) launch_fwd<64, false>(a, n_st, out, ncontrib, counters, state, s);
-    else if (max_per_tile <= 128) launch_fwd<128, false>(a, n_st, out, ncontrib, counters, state, s);
-    else launch_fwd<256, false>(a, n_st, out, ncontrib, counters, state, s);
+    if (max_per_tile <= 64) launch_bwd<64, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s, dens);
+    else if (max_per_tile <= 128)
+      launch_bwd<128, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s, dens);
+    else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s, dens);
   }
-  return hip_status("tgs_render_fwd");
+  return hip_status(who);
 }
 
 extern "C" int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, const uint32_t* ranges,
@@ -752,18 +894,30 @@ extern "C" int32_t tgs_render_bwd(const float* splat, const uint32_t* vals, cons
   if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
                             tile_off, pix, n_st, max_per_tile, rp, "tgs_render_bwd", a))
     return e;
-  TGS_REQUIRE(out && ncontrib && dL_dout && g2d, "tgs_render_bwd: null pointer");
-  TGS_REQUIRE(((uintptr_t)out & 15) == 0 && ((uintptr_t)dL_dout & 15) == 0 && ((uintptr_t)state & 15) == 0,
-              "tgs_render_bwd: out, dL_dout and state must be 16-byte aligned");
-  hipStream_t s = as_stream(stream);
-  if (valid_tiles == nullptr) {
-    launch_bwd<256, true>(a, tiles_x * tiles_y, out, ncontrib, dL_dout, g2d, state, touched, s);
-  } else if (n_st > 0) {
-    if (max_per_tile <= 64) launch_bwd<64, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s);
-    else if (max_per_tile <= 128) launch_bwd<128, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s);
-    else launch_bwd<256, false>(a, n_st, out, ncontrib, dL_dout, g2d, state, touched, s);
+  return render_bwd_launch(a, valid_tiles == nullptr, n_st, max_per_tile, out, ncontrib, dL_dout, g2d, state,
+                           touched, nullptr, as_stream(stream), "tgs_render_bwd");
+}
+
+extern "C" int32_t tgs_render_bwd2(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                                   const uint32_t* vals2, const uint32_t* ranges2, int32_t tiles_x, int32_t tiles_y,
+                                   int32_t width, int32_t height, const int32_t* valid_tiles,
+                                   const int32_t* tile_off, const uint8_t* pix, int32_t n_st, int32_t max_per_tile,
+                                   const tgs_raster_params* rp, const float* out, const uint32_t* ncontrib,
+                                   const float* dL_dout, float* g2d, const float* state, uint8_t* touched,
+                                   const float* err, int64_t n, float* stats, void* stream) {
+  const char* who = "tgs_render_bwd2";
+  RasterArgs a;
+  if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles, tile_off, pix, n_st,
+                            max_per_tile, rp, who, a))
+    return e;
+  if (int32_t e = set_second(a, vals2, ranges2, who)) return e;
+  DensityArgs d{err, stats, n};
+  if (stats != nullptr) {
+    TGS_REQUIRE(err != nullptr && n > 0 && n < (1ll << 31), "%s: density sums need err and n", who);
+    TGS_REQUIRE(((uintptr_t)stats & 15) == 0, "%s: stats must be 16-byte aligned", who);
   }
-  return hip_status("tgs_render_bwd");
+  return render_bwd_launch(a, valid_tiles == nullptr, n_st, max_per_tile, out, ncontrib, dL_dout, g2d, state,
+                           touched, stats != nullptr ? &d : nullptr, as_stream(stream), who);
 }
 
 extern "C" size_t tgs_render_bwd_det_workspace_size(int64_t n_pairs, int32_t max_per_tile, int32_t dense) {
@@ -844,6 +998,10 @@ extern "C" int32_t tgs_render_bwd_density(const float* splat, const uint32_t* va
   return hip_status("tgs_render_bwd_density");
 }
 
+static int32_t density_accumulate_launch(const RasterArgs& a, const int32_t* valid_tiles, int32_t n_st,
+                                         int32_t max_per_tile, const uint32_t* ncontrib, const float* err,
+                                         const float* state, int64_t n, float* stats, void* stream);
+
 extern "C" int32_t tgs_density_accumulate(const float* splat, const uint32_t* vals, const uint32_t* ranges,
                                           int32_t tiles_x, int32_t tiles_y, int32_t width, int32_t height,
                                           const int32_t* valid_tiles, const int32_t* tile_off,
@@ -855,6 +1013,28 @@ extern "C" int32_t tgs_density_accumulate(const float* splat, const uint32_t* va
   if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
                             tile_off, pix, n_st, max_per_tile, rp, "tgs_density_accumulate", a))
     return e;
+  return density_accumulate_launch(a, valid_tiles, n_st, max_per_tile, ncontrib, err, state, n, stats, stream);
+}
+
+extern "C" int32_t tgs_density_accumulate2(const float* splat, const uint32_t* vals, const uint32_t* ranges,
+                                           const uint32_t* vals2, const uint32_t* ranges2, int32_t tiles_x,
+                                           int32_t tiles_y, int32_t width, int32_t height,
+                                           const int32_t* valid_tiles, const int32_t* tile_off, const uint8_t* pix,
+                                           int32_t n_st, int32_t max_per_tile, const tgs_raster_params* rp,
+                                           const uint32_t* ncontrib, const float* err, const float* state,
+                                           int64_t n, float* stats, void* stream) {
+  RasterArgs a;
+  if (int32_t e = make_args(splat, vals, ranges, tiles_x, tiles_y, width, height, valid_tiles,
+                            tile_off, pix, n_st, max_per_tile, rp, "tgs_density_accumulate2", a))
+    return e;
+  if (int32_t e = set_second(a, vals2, ranges2, "tgs_density_accumulate2")) return e;
+  return density_accumulate_launch(a, valid_tiles, n_st, max_per_tile, ncontrib, err, state, n, stats, stream);
+}
+
+static int32_t density_accumulate_launch(const RasterArgs& a, const int32_t* valid_tiles, int32_t n_st,
+                                         int32_t max_per_tile, const uint32_t* ncontrib, const float* err,
+                                         const float* state, int64_t n, float* stats, void* stream) {
+  const int tiles_x = a.tiles_x, tiles_y = a.tiles_y;
   TGS_REQUIRE(n >= 0 && n < (1ll << 31), "tgs_density_accumulate: n out of range");
   TGS_REQUIRE(ncontrib && err && stats, "tgs_density_accumulate: null pointer");
   TGS_REQUIRE(((uintptr_t)stats & 15) == 0, "tgs_density_accumulate: stats must be 16-byte aligned");

@@ -49,6 +49,10 @@ class StepConfig:
     tile_seed: int = 23           # its initial weights
     density_stats: bool = False   # back-project (e, w, D) onto the Gaussians each sparse view (Sec. 3.8)
     deterministic: bool = False   # bitwise-reproducible backward (tgs_render_bwd_deterministic)
+    # depth-prefix binning: each view's lists hold the nearest prefix_fraction
+    # of the Gaussians, plus a continuation for the tiles where a pixel ran
+    # past them (the same images and gradients as whole lists; None: off)
+    prefix_fraction: float | None = None
     raster: dict = field(default_factory=dict)
     loss: dict = field(default_factory=dict)
     optim: dict = field(default_factory=dict)
@@ -96,7 +100,15 @@ class ViewBuffers:
         # per-pixel (T, colour) at the backward's chunk starts, kept by the forward
         n_state = B.tgs_render_state_size(self.n_st, self.n_pix) // 4
         self.state = torch.empty(max(n_state, 4), dtype=torch.float32, device=dev)
-        self.counts = torch.zeros(2, dtype=torch.int64, device=dev)   # (list length, capacity needed)
+        # (list length, capacity needed[, whole-list pairs after a depth-prefix call])
+        self.counts = torch.zeros(3, dtype=torch.int64, device=dev)
+        # depth-prefix lists: the continuation's lists and the marked tiles
+        self.two_part = False
+        self.prefix = self.n
+        self.counts2 = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.capacity2 = 0
+        self.vals2 = self.ranges2 = self.sort_ws2 = None
+        self.cont_slot = self.cont_list = self.cont_count = None
         self._n_pairs = 0
         self.sized = False   # whether a bin/sort has run to completion here (the capacity then fits a view)
         self._alloc_pairs(capacity if capacity is not None else max(1 << 16, 8 * n))
@@ -106,9 +118,15 @@ class ViewBuffers:
         """Pairs in the lists of the last bin/sort (reads the device count
         after an asynchronous one; raises CapacityError if it overflowed)."""
         if self._n_pairs is None:
-            valid, need = (int(x) for x in self.counts.cpu().tolist())
+            valid, need = (int(x) for x in self.counts[:2].cpu().tolist())
             if need > self.capacity:
                 raise B.CapacityError(f"pair lists need {need} entries, capacity {self.capacity}", need)
+            if self.two_part:
+                valid2, need2 = (int(x) for x in self.counts2.cpu().tolist())
+                if need2 > self.capacity2:
+                    raise B.CapacityError(f"continuation lists need {need2} entries, capacity {self.capacity2}",
+                                          need2)
+                valid += valid2
             self._n_pairs = valid
         return self._n_pairs
 
@@ -145,7 +163,7 @@ class ViewBuffers:
         repeats when they are too small.  Returns the list length."""
         while True:
             self.bin_sort_async(touched, alpha_min)
-            valid, need = (int(x) for x in self.counts.cpu().tolist())
+            valid, need = (int(x) for x in self.counts[:2].cpu().tolist())
             if need <= self.capacity:
                 self.n_pairs = valid
                 self.sized = True
@@ -160,9 +178,80 @@ class ViewBuffers:
         B.tgs_bin_sort_async(self.rect, self.splat, self.depth, self.n, tile_slot, self.tiles_x, self.tiles_y,
                              alpha_min, self.keys, self.vals, self.capacity, self.ranges, touched, self.counts,
                              self.sort_ws)
+        self.two_part = False
         self._n_pairs = None
 
+    # ---- depth-prefix lists
+    def _alloc_cont(self, capacity2: int):
+        dev = self.splat.device
+        self.capacity2 = int(capacity2)
+        self.vals2 = torch.empty(self.capacity2, dtype=torch.int32, device=dev)
+        self.sort_ws2 = torch.empty(B.tgs_bin_sort_workspace_size(self.n, self.capacity2, self.n_t),
+                                    dtype=torch.uint8, device=dev)
+        if self.ranges2 is None:
+            self.ranges2 = torch.empty((self.n_t, 2), dtype=torch.int32, device=dev)
+            self.cont_slot = torch.empty(self.n_t, dtype=torch.int32, device=dev)
+            self.cont_list = torch.empty(max(self.n_st, 1), dtype=torch.int32, device=dev)
+            self.cont_count = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    # capacity margins of depth-prefix lists: views of one scene differ in
+    # their prefix and continuation needs, and an overflow is only seen two
+    # steps later, so both arrays keep room to spare
+    PREFIX_MARGIN = 2.0       # prefix arrays: twice the need they were sized on
+    CONT_MIN_SHARE = 0.35     # continuation: at least this share of the whole lists' pairs
+
+    def bin_sort_prefix(self, prefix: int, touched=None, alpha_min: float = 1.0 / 255.0, wait: bool = False):
+        """The lists of the nearest ``prefix`` Gaussians (no host wait unless
+        ``wait``: then the pair arrays, and the continuation's, are sized
+        from the counts)."""
+        tile_slot = self.tile_slot if self.bin_sort_needs_samples() else None
+        self.prefix = int(min(prefix, self.n))
+        while True:
+            B.tgs_bin_sort_prefix_async(self.rect, self.splat, self.depth, self.n, tile_slot, self.tiles_x,
+                                        self.tiles_y, alpha_min, self.prefix, self.keys, self.vals, self.capacity,
+                                        self.ranges, touched, self.counts, self.sort_ws)
+            if not wait:
+                break
+            _, need, whole = (int(x) for x in self.counts.cpu().tolist())
+            if need <= self.capacity:
+                if self.capacity < self.PREFIX_MARGIN * need:
+                    self._alloc_pairs(int(self.PREFIX_MARGIN * need) + 1024)
+                    continue   # re-run into the new arrays
+                want2 = max(1 << 16, int(self.CONT_MIN_SHARE * whole))
+                if self.vals2 is None or self.capacity2 < want2:
+                    self._alloc_cont(want2)
+                break
+            self._alloc_pairs(int(self.PREFIX_MARGIN * need) + 1024)
+        self.two_part = True
+        self._n_pairs = None
+
+    def render_fwd_two_part(self, rp, counters=None, alpha_min: float = 1.0 / 255.0, wait: bool = False):
+        """Forward over the prefix lists, the continuation lists of the tiles
+        it marks, and the forward again for those tiles over both parts."""
+        if self.vals2 is None:
+            self._alloc_cont(max(1 << 16, self.capacity // 2))
+        B.tgs_render_fwd_prefix(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
+                                self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix, rp,
+                                self.out, self.ncontrib, counters, self.state, self.cont_slot, self.cont_list,
+                                self.cont_count)
+        while True:
+            B.tgs_bin_sort_continue_async(self.splat, self.n, self.cont_slot, self.tiles_x, self.tiles_y, alpha_min,
+                                          self.prefix, self.capacity, self.sort_ws, self.vals2, self.capacity2,
+                                          self.ranges2, self.counts2, self.sort_ws2)
+            if not wait:
+                break
+            need = int(self.counts2[1].item())
+            if need <= self.capacity2:
+                break
+            self._alloc_cont(int(need * 1.5) + 1024)
+        B.tgs_render_fwd_cont(self.splat, self.vals, self.ranges, self.vals2, self.ranges2, self.tiles_x,
+                              self.tiles_y, self.width, self.height, self.valid_tiles, self.tile_off, self.pix,
+                              self.n_st, self.n_pix, rp, self.cont_list, self.cont_count, self.out, self.ncontrib,
+                              counters, self.state)
+
     def render_fwd(self, rp, counters=None):
+        if self.two_part:
+            raise RuntimeError("two-part lists: render with render_fwd_two_part")
         B.tgs_render_fwd(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                          self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
                          rp, self.out, self.ncontrib, counters, self.state)
@@ -176,6 +265,12 @@ class ViewBuffers:
                              self.err, beta)
 
     def density(self, rp, stats):
+        if self.two_part:
+            B.tgs_density_accumulate2(self.splat, self.vals, self.ranges, self.vals2, self.ranges2, self.tiles_x,
+                                      self.tiles_y, self.width, self.height, self.valid_tiles, self.tile_off,
+                                      self.pix, self.n_st, self.n_pix, rp, self.ncontrib, self.err, self.n, stats,
+                                      self.state)
+            return
         B.tgs_density_accumulate(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                                  self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix,
                                  rp, self.ncontrib, self.err, self.n, stats, self.state)
@@ -187,6 +282,15 @@ class ViewBuffers:
         with ``stats``)."""
         if zero:
             self.g2d.zero_()
+        if self.two_part:
+            if deterministic:
+                raise ValueError("the deterministic backward takes whole lists, not depth-prefix lists")
+            B.tgs_render_bwd2(self.splat, self.vals, self.ranges, self.vals2, self.ranges2, self.tiles_x,
+                              self.tiles_y, self.width, self.height, self.valid_tiles, self.tile_off, self.pix,
+                              self.n_st, self.n_pix, rp, self.out, self.ncontrib, self.dL, self.g2d, self.state,
+                              touched, self.err if stats is not None else None, self.n if stats is not None else 0,
+                              stats)
+            return
         if deterministic:
             if stats is not None:
                 raise ValueError("the deterministic backward has no density-control variant")
@@ -419,6 +523,9 @@ class Trainer:
             sampled.append(ev)
         lossed = self._lossed
         all_waited = False
+        prefix_n = None
+        if self.cfg.prefix_fraction is not None and not self.cfg.deterministic:
+            prefix_n = max(1, int(math.ceil(self.cfg.prefix_fraction * self.n)))
         for k, (vb, v) in enumerate(zip(used, views)):
             cam = self.cams[v]
             with st("project"):
@@ -426,12 +533,19 @@ class Trainer:
             if sampled[k] is not None:
                 main.wait_event(sampled[k])   # this view's samples (the binning and render need them)
             with st("bin_sort"):
-                if vb.sized:
+                if prefix_n is not None:
+                    # the nearest Gaussians only; the first step of a slot waits to size its arrays
+                    vb.bin_sort_prefix(prefix_n, None, self.rp.alpha_min, wait=not vb.sized)
+                elif vb.sized:
                     vb.bin_sort_async(None, self.rp.alpha_min)   # no host wait
                 else:
                     vb.bin_sort(None, self.rp.alpha_min)         # sizes the pair arrays once per slot
             with st("render_fwd"):
-                vb.render_fwd(self.rp, self.counters)
+                if vb.two_part:
+                    vb.render_fwd_two_part(self.rp, self.counters, self.rp.alpha_min, wait=not vb.sized)
+                    vb.sized = True
+                else:
+                    vb.render_fwd(self.rp, self.counters)
             if not all_waited:
                 # the loss normalises by the step's total sample count
                 for ev in sampled:
@@ -490,12 +604,14 @@ class Trainer:
     def _queue_count_check(self, used):
         if not used:
             return
-        host = torch.empty((len(used), 2), dtype=torch.int64, pin_memory=True)
+        host = torch.zeros((len(used), 5), dtype=torch.int64, pin_memory=True)
         for k, vb in enumerate(used):
-            host[k].copy_(vb.counts, non_blocking=True)
+            host[k, :3].copy_(vb.counts, non_blocking=True)
+            if vb.two_part:
+                host[k, 3:].copy_(vb.counts2, non_blocking=True)
         ev = torch.cuda.Event()
         ev.record()
-        self._pending.append((ev, host, [(vb, vb.capacity) for vb in used]))
+        self._pending.append((ev, host, [(vb, vb.capacity, vb.capacity2, vb.two_part) for vb in used]))
 
     def check_counts(self, wait_all: bool = False):
         """Reads the pending pair counts that are due (all of them with
@@ -503,12 +619,20 @@ class Trainer:
         while self._pending and (wait_all or len(self._pending) > self._COUNT_LAG or self._pending[0][0].query()):
             ev, host, entries = self._pending.pop(0)
             ev.synchronize()
-            for (vb, cap), (valid, need) in zip(entries, host.tolist()):
-                if need > cap:
-                    raise B.CapacityError(f"a step's pair lists needed {need} entries but had {cap}: that step "
-                                          f"rendered empty lists and must be redone with a larger capacity", need)
-                if vb.capacity == cap and need > 0.85 * cap:
-                    vb._alloc_pairs(int(1.5 * need) + 1024)
+            for (vb, cap, cap2, two), (valid, need, whole, valid2, need2) in zip(entries, host.tolist()):
+                if need > cap or (two and need2 > cap2):
+                    raise B.CapacityError(f"a step's pair lists needed {need} (continuation {need2}) entries but "
+                                          f"had {cap} ({cap2}): that step rendered empty lists and must be redone "
+                                          f"with a larger capacity", max(need, need2))
+                if not two:
+                    if vb.capacity == cap and need > 0.85 * cap:
+                        vb._alloc_pairs(int(1.5 * need) + 1024)
+                    continue
+                if vb.capacity == cap and need > 0.7 * cap:
+                    vb._alloc_pairs(int(vb.PREFIX_MARGIN * need) + 1024)
+                want2 = max(int(1.5 * need2), int(vb.CONT_MIN_SHARE * whole)) + 1024
+                if vb.capacity2 == cap2 and (need2 > 0.7 * cap2 or cap2 < vb.CONT_MIN_SHARE * whole):
+                    vb._alloc_cont(want2)
 
     def reset_density(self):
         """Clears the density-control sums (the start of an accumulation window)."""
