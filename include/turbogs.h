@@ -272,13 +272,16 @@ int32_t tgs_bin_sort_prefix_async(const int32_t* rect, const float* splat, const
  * flag_slot[tile] >= 0, the pairs of the Gaussians from depth rank `prefix`
  * on (same culling), each tile's list in (depth, id) order.
  *   flag_slot  [tiles_x * tiles_y] int32 (tgs_render_fwd_prefix's cont_slot)
+ *   n_flagged  nullable [1] uint32 device: the number of flagged tiles
+ *              (cont_count); when it is 0 the kernels return at once
  *   capacity, ws, ws_bytes  the prefix call's (its depth order is read)
  *   vals2, capacity2, ranges2  the continuation lists, as vals/ranges
  *   counts2    [2] int64 device: both = the continuation pairs; above
  *              capacity2 the lists come out empty, as in tgs_bin_sort_async
  *   ws2        tgs_bin_sort_workspace_size(n, capacity2, n_tiles) bytes */
-int32_t tgs_bin_sort_continue_async(const float* splat, int64_t n, const int32_t* flag_slot, int32_t tiles_x,
-                                    int32_t tiles_y, float alpha_min, int64_t prefix, int64_t capacity,
+int32_t tgs_bin_sort_continue_async(const float* splat, int64_t n, const int32_t* flag_slot,
+                                    const uint32_t* n_flagged, int32_t tiles_x, int32_t tiles_y, float alpha_min,
+                                    int64_t prefix, int64_t capacity,
                                     const void* ws, size_t ws_bytes, uint32_t* vals2, int64_t capacity2,
                                     uint32_t* ranges2, int64_t* counts2, void* ws2, size_t ws2_bytes, void* stream);
 

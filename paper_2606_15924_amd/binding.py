@@ -82,8 +82,8 @@ PROTOTYPES = {
                                   _SZ, _P]),
     "tgs_bin_sort_prefix_async": (_I32, [_P, _P, _P, _I64, _P, _I32, _I32, ctypes.c_float, _I64, _P, _P, _I64, _P,
                                          _P, _P, _P, _SZ, _P]),
-    "tgs_bin_sort_continue_async": (_I32, [_P, _I64, _P, _I32, _I32, ctypes.c_float, _I64, _I64, _P, _SZ, _P, _I64,
-                                           _P, _P, _P, _SZ, _P]),
+    "tgs_bin_sort_continue_async": (_I32, [_P, _I64, _P, _P, _I32, _I32, ctypes.c_float, _I64, _I64, _P, _SZ, _P,
+                                           _I64, _P, _P, _P, _SZ, _P]),
     "tgs_render_fwd_prefix": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
                                      ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P, _P]),
     "tgs_render_fwd_cont": (_I32, [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _I32,
@@ -361,10 +361,11 @@ def tgs_bin_sort_prefix_async(rect, splat, depth, n, tile_slot, tiles_x, tiles_y
 
 
 def tgs_bin_sort_continue_async(splat, n, flag_slot, tiles_x, tiles_y, alpha_min, prefix, capacity, ws, vals2,
-                                capacity2, ranges2, counts2, ws2):
+                                capacity2, ranges2, counts2, ws2, n_flagged=None):
     """The continuation lists of the flagged tiles (Gaussians from depth rank
     ``prefix`` on) from a prefix call's workspace ``ws``."""
-    _check(lib().tgs_bin_sort_continue_async(_ptr(splat), n, _ptr(flag_slot), tiles_x, tiles_y, float(alpha_min),
+    _check(lib().tgs_bin_sort_continue_async(_ptr(splat), n, _ptr(flag_slot), _ptr(n_flagged), tiles_x, tiles_y,
+                                             float(alpha_min),
                                              int(prefix), capacity, _ptr(ws), ws.numel() * ws.element_size(),
                                              _ptr(vals2), capacity2, _ptr(ranges2), _ptr(counts2), _ptr(ws2),
                                              ws2.numel() * ws2.element_size(), _stream()),

@@ -380,28 +380,23 @@ __global__ void __launch_bounds__(kWave) count_kernel(
   }
 }
 
-// Summed-area table of the flagged tiles (one workgroup): sat[(y + 1) *
-// (tiles_x + 1) + x + 1] = flagged tiles in rows < y + 1, columns < x + 1;
-// row 0 and column 0 are zero.  Row prefix sums first (a thread per tile
-// row), then column sums (a thread per column).
-__global__ void __launch_bounds__(1024) flag_sat_kernel(const int32_t* __restrict__ flag_slot, int tiles_x,
-                                                        int tiles_y, uint32_t* __restrict__ sat) {
-  const int W1 = tiles_x + 1;
-  for (int y = threadIdx.x; y <= tiles_y; y += 1024) {
-    uint32_t run = 0;
-    sat[(int64_t)y * W1] = 0u;
-    for (int x = 0; x < tiles_x; ++x) {
-      if (y > 0) run += flag_slot[(int64_t)(y - 1) * tiles_x + x] >= 0 ? 1u : 0u;
-      sat[(int64_t)y * W1 + x + 1] = run;
-    }
-  }
-  __syncthreads();
-  for (int x = threadIdx.x; x <= tiles_x; x += 1024) {
-    uint32_t run = 0;
-    for (int y = 0; y <= tiles_y; ++y) {
-      run += sat[(int64_t)y * W1 + x];
-      sat[(int64_t)y * W1 + x] = run;
-    }
+// Per tile row, the running count of flagged tiles: rowc[y * (tiles_x + 1)
+// + x] = flagged tiles among columns < x of row y (a wave per row, 64
+// columns per scan).  Nothing to do when no tile is flagged.
+__global__ void __launch_bounds__(kWave) flag_rows_kernel(const int32_t* __restrict__ flag_slot, int tiles_x,
+                                                          const uint32_t* __restrict__ n_flagged,
+                                                          uint32_t* __restrict__ rowc) {
+  if (n_flagged != nullptr && *n_flagged == 0u) return;
+  const int y = blockIdx.x, lane = lane_id();
+  const int64_t W1 = tiles_x + 1;
+  uint32_t carry = 0;
+  if (lane == 0) rowc[y * W1] = 0u;
+  for (int x0 = 0; x0 < tiles_x; x0 += kWave) {
+    const int x = x0 + lane;
+    const uint32_t f = x < tiles_x && flag_slot[(int64_t)y * tiles_x + x] >= 0 ? 1u : 0u;
+    const uint32_t incl = carry + wave_inclusive_scan_u32(f);
+    if (x < tiles_x) rowc[y * W1 + x + 1] = incl;
+    carry = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
   }
 }
 
@@ -409,26 +404,33 @@ __global__ void __launch_bounds__(1024) flag_sat_kernel(const int32_t* __restric
 // given rank on (their rectangles, ids and first-pass pair counts in that
 // order).  Per Gaussian: its kept pairs in the flagged tiles (tile map
 // entry >= 0), by the same row spans.  Gaussians without pairs in the first
-// pass, or whose rectangle holds no flagged tile (four reads of the
-// summed-area table, when given), are skipped before their splat is read.
+// pass, or whose rectangle holds no flagged tile (two reads of the row
+// counts per rectangle row, when given), are skipped before their splat is
+// read; the whole call is skipped when no tile is flagged (every count 0).
 // The sum goes to the 64-bit totals (both slots).
 __global__ void __launch_bounds__(kWave) count_cont_kernel(
     const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ ids_sorted,
     const uint32_t* __restrict__ cnt_sorted, int64_t m, const float4* __restrict__ splat,
-    const int32_t* __restrict__ flag_slot, const uint32_t* __restrict__ sat, int tiles_x, int tiles_y, double tau,
-    double lia, uint32_t* __restrict__ cnt, unsigned long long* __restrict__ totals) {
+    const int32_t* __restrict__ flag_slot, const uint32_t* __restrict__ n_flagged,
+    const uint32_t* __restrict__ rowc, int tiles_x, int tiles_y, double tau, double lia,
+    uint32_t* __restrict__ cnt, unsigned long long* __restrict__ totals) {
   __shared__ CountBatch cb;
   __shared__ uint64_t s_red[1];
   const int lane = lane_id();
   const int64_t k = (int64_t)blockIdx.x * kCountBatch + lane;
+  if (n_flagged != nullptr && *n_flagged == 0u) {  // workgroup-uniform
+    if (k < m) cnt[k] = 0u;
+    return;
+  }
   bool mine = k < m && cnt_sorted[k] > 0;
   int4 r = make_int4(0, 0, 0, 0);
   uint32_t g = 0;
   if (mine) {
     r = clamp_rect(rect_sorted[k], tiles_x, tiles_y);
-    if (sat != nullptr) {
+    if (rowc != nullptr) {
       const int64_t W1 = tiles_x + 1;
-      const uint32_t f = sat[r.w * W1 + r.z] - sat[r.y * W1 + r.z] - sat[r.w * W1 + r.x] + sat[r.y * W1 + r.x];
+      uint32_t f = 0u;
+      for (int y = r.y; y < r.w && f == 0u; ++y) f = rowc[y * W1 + r.z] - rowc[y * W1 + r.x];
       if (f == 0u) {
         mine = false;
         r = make_int4(0, 0, 0, 0);
@@ -1193,26 +1195,27 @@ static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const flo
 // depth rank `prefix` on in the flagged tiles, from the depth order that
 // the prefix call left in its workspace w1, sorted by tile (each tile's
 // list in depth order) with the scratch and pair buffers of w2.
-static int32_t continue_queue(const float* splat, int64_t n, const int32_t* flag_slot, int32_t tiles_x,
-                              int32_t tiles_y, float alpha_min, int64_t prefix, uint32_t* vals2, int64_t capacity2,
-                              uint32_t* ranges2, const SortWs& w1, const SortWs& w2, hipStream_t s,
-                              const char* who) {
+static int32_t continue_queue(const float* splat, int64_t n, const int32_t* flag_slot, const uint32_t* n_flagged,
+                              int32_t tiles_x, int32_t tiles_y, float alpha_min, int64_t prefix, uint32_t* vals2,
+                              int64_t capacity2, uint32_t* ranges2, const SortWs& w1, const SortWs& w2,
+                              hipStream_t s, const char* who) {
   const uint32_t n_t = (uint32_t)tiles_x * (uint32_t)tiles_y;
   const double lia = std::log(1.0 / (double)alpha_min);
   const double tau = std::ceil(128.0 * lia * 1.001) / 64.0;
   hipLaunchKernelGGL(zero2_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t + w2.zeroed_words, 256)), dim3(256),
                      0, s, ranges2, 2 * (int64_t)n_t, w2.zeroed, w2.zeroed_words);
   const int64_t m = n - std::min(prefix, n);
-  // the flagged tiles' summed-area table in the pair-sort histogram (free
-  // until the sort), when it fits
-  const int64_t sat_words = (int64_t)(tiles_x + 1) * (tiles_y + 1);
-  uint32_t* sat = sat_words <= 256 * 1024 ? w2.hist : nullptr;
-  if (m > 0 && sat != nullptr)
-    hipLaunchKernelGGL(flag_sat_kernel, dim3(1), dim3(1024), 0, s, flag_slot, tiles_x, tiles_y, sat);
+  // the flagged tiles' per-row running counts in the pair-sort histogram
+  // (free until the sort), when they fit
+  const int64_t rc_words = (int64_t)(tiles_x + 1) * tiles_y;
+  uint32_t* rowc = rc_words <= 256 * 1024 ? w2.hist : nullptr;
+  if (m > 0 && rowc != nullptr)
+    hipLaunchKernelGGL(flag_rows_kernel, dim3((unsigned)tiles_y), dim3(kWave), 0, s, flag_slot, tiles_x, n_flagged,
+                       rowc);
   if (m > 0)
     hipLaunchKernelGGL(count_cont_kernel, dim3((unsigned)ceil_div(m, kCountBatch)), dim3(kWave), 0, s,
                        w1.rect_sorted + prefix, w1.ids_sorted + prefix, w1.cnt_sorted + prefix, m,
-                       (const float4*)splat, flag_slot, (const uint32_t*)sat, tiles_x, tiles_y, tau, lia,
+                       (const float4*)splat, flag_slot, n_flagged, (const uint32_t*)rowc, tiles_x, tiles_y, tau, lia,
                        w2.emit_cnt, w2.scalars);
   hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w2.scalars, capacity2, w2.counts, w2.eff_total);
   if (m == 0 || capacity2 == 0) return hip_status(who);
@@ -1290,7 +1293,8 @@ extern "C" int32_t tgs_bin_sort_prefix_async(const int32_t* rect, const float* s
 }
 
 extern "C" int32_t tgs_bin_sort_continue_async(const float* splat, int64_t n, const int32_t* flag_slot,
-                                               int32_t tiles_x, int32_t tiles_y, float alpha_min, int64_t prefix,
+                                               const uint32_t* n_flagged, int32_t tiles_x, int32_t tiles_y,
+                                               float alpha_min, int64_t prefix,
                                                int64_t capacity, const void* ws, size_t ws_bytes, uint32_t* vals2,
                                                int64_t capacity2, uint32_t* ranges2, int64_t* counts2, void* ws2,
                                                size_t ws2_bytes, void* stream) {
@@ -1307,8 +1311,8 @@ extern "C" int32_t tgs_bin_sort_continue_async(const float* splat, int64_t n, co
   const SortWs w2 = layout(ws2, n, capacity2);
   TGS_REQUIRE(ws_bytes >= w1.bytes && ws2_bytes >= w2.bytes, "%s: workspace too small", who);
   hipStream_t s = as_stream(stream);
-  if (int32_t e = continue_queue(splat, n, flag_slot, tiles_x, tiles_y, alpha_min, prefix, vals2, capacity2, ranges2,
-                                 w1, w2, s, who))
+  if (int32_t e = continue_queue(splat, n, flag_slot, n_flagged, tiles_x, tiles_y, alpha_min, prefix, vals2, capacity2,
+                                 ranges2, w1, w2, s, who))
     return e;
   hipLaunchKernelGGL(copy_counts_kernel, dim3(1), dim3(64), 0, s, (const unsigned long long*)w2.counts,
                      (unsigned long long*)counts2);

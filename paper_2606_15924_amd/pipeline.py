@@ -237,7 +237,7 @@ class ViewBuffers:
         while True:
             B.tgs_bin_sort_continue_async(self.splat, self.n, self.cont_slot, self.tiles_x, self.tiles_y, alpha_min,
                                           self.prefix, self.capacity, self.sort_ws, self.vals2, self.capacity2,
-                                          self.ranges2, self.counts2, self.sort_ws2)
+                                          self.ranges2, self.counts2, self.sort_ws2, n_flagged=self.cont_count)
             if not wait:
                 break
             need = int(self.counts2[1].item())
