@@ -43,6 +43,7 @@ FULL_RATE = 200              # per-mille of each tile's pixels (51 of 256)
 FULL_K = (3, 10)             # views per step (the schedule's K_min and K_max)
 HEADLINE_K = 3
 FULL_PREFIX = 0.15           # depth-prefix lists: the nearest 15% of the Gaussians, then a continuation
+PREFIX = FULL_PREFIX         # the setting of every trainer below but the large scene (--no-prefix: whole lists)
 
 # large scene: 5M Gaussians in a 50-unit corridor, 400 cameras 1920x1080 along it
 LARGE_N = 5_000_000
@@ -128,7 +129,7 @@ def make_trainer(p, cam, gt, rate, dev, density_stats=False):
     import torch
 
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
-    cfg = StepConfig(rate_permille=rate, density_stats=density_stats)
+    cfg = StepConfig(rate_permille=rate, density_stats=density_stats, prefix_fraction=PREFIX)
     E = torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev)
     A = torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev)
     tr = Trainer(torch.from_numpy(p).to(dev), [cam], [torch.from_numpy(gt).to(dev)], cfg, E=[E], A=[A])
@@ -311,7 +312,7 @@ def matched_psnr(dev, dense_steps=PSNR_DENSE_STEPS, max_steps=PSNR_MAX_STEPS):
     order = np.random.default_rng(synth.SEED_VIEWS).integers(0, len(train), size=max_steps)
 
     def run(rate, target_psnr, n_max, n_tiles_sel=-1, learned=False):
-        cfg = StepConfig(rate_permille=rate, n_tiles_sel=n_tiles_sel, learned_tiles=learned)
+        cfg = StepConfig(rate_permille=rate, n_tiles_sel=n_tiles_sel, learned_tiles=learned, prefix_fraction=PREFIX)
         E = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in train]
         A = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in train]
         tr = Trainer(torch.from_numpy(p0).to(dev), [cams[i] for i in train], [gts[i] for i in train], cfg,
@@ -840,9 +841,10 @@ def main():
     if args.only_headline:
         global FULL_K
         FULL_K = (HEADLINE_K,)
+    global PREFIX
+    PREFIX = None if args.no_prefix else FULL_PREFIX
     p_full, cams, full = full_step(dev, args.steps, args.warmup,
-                                   with_dense=not (args.no_dense or args.only_headline),
-                                   prefix=None if args.no_prefix else FULL_PREFIX)
+                                   with_dense=not (args.no_dense or args.only_headline), prefix=PREFIX)
     head = full[(HEADLINE_K, "sparse")]
     roofline = roofline_of(head, args.steps)
     full_out = {}

@@ -438,15 +438,18 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
   float Cout0 = 0.f, Cout1 = 0.f, Cout2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
   uint32_t last = 0;
   float e_pix = 0.f;
+  if (px.inside) last = ncontrib[px.out];
+  bool done = last <= begin - range.x;  // nothing composited from this chunk on
+  // a chunk past every pixel's last composited position has nothing to do:
+  // it leaves before reading the pixels' outputs, gradients and state
+  if (__syncthreads_count(done) == kBlock) return;
   if (px.inside) {
     const float4 o = out[px.out];
     const float4 d = dL[px.out];
     Cout0 = o.x; Cout1 = o.y; Cout2 = o.z;
     g0 = d.x; g1 = d.y; g2 = d.z;
-    last = ncontrib[px.out];
     if (kDensity) e_pix = dens.err[px.out];
   }
-  bool done = last <= begin - range.x;  // nothing composited from this chunk on
   // T and S = sum_c g_c (C_c - acc_c): the loss-weighted colour behind the
   // current Gaussian (final colour minus what is composited in front of
   // and at it), updated as S -= w * sum_c g_c colour_c

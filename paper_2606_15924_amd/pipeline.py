@@ -228,12 +228,22 @@ class ViewBuffers:
     def render_fwd_two_part(self, rp, counters=None, alpha_min: float = 1.0 / 255.0, wait: bool = False):
         """Forward over the prefix lists, the continuation lists of the tiles
         it marks, and the forward again for those tiles over both parts."""
+        self.render_fwd_prefix(rp, counters)
+        self.continue_lists(alpha_min, wait)
+        self.render_fwd_cont(rp, counters)
+
+    def render_fwd_prefix(self, rp, counters=None):
+        """Forward over the prefix lists, marking the tiles that need more."""
         if self.vals2 is None:
             self._alloc_cont(max(1 << 16, self.capacity // 2))
         B.tgs_render_fwd_prefix(self.splat, self.vals, self.ranges, self.tiles_x, self.tiles_y, self.width,
                                 self.height, self.valid_tiles, self.tile_off, self.pix, self.n_st, self.n_pix, rp,
                                 self.out, self.ncontrib, counters, self.state, self.cont_slot, self.cont_list,
                                 self.cont_count)
+
+    def continue_lists(self, alpha_min: float = 1.0 / 255.0, wait: bool = False):
+        """The continuation lists of the marked tiles (``wait``: grow their
+        arrays until they fit)."""
         while True:
             B.tgs_bin_sort_continue_async(self.splat, self.n, self.cont_slot, self.tiles_x, self.tiles_y, alpha_min,
                                           self.prefix, self.capacity, self.sort_ws, self.vals2, self.capacity2,
@@ -244,6 +254,9 @@ class ViewBuffers:
             if need <= self.capacity2:
                 break
             self._alloc_cont(int(need * 1.5) + 1024)
+
+    def render_fwd_cont(self, rp, counters=None):
+        """The marked tiles' forward over both parts of their lists."""
         B.tgs_render_fwd_cont(self.splat, self.vals, self.ranges, self.vals2, self.ranges2, self.tiles_x,
                               self.tiles_y, self.width, self.height, self.valid_tiles, self.tile_off, self.pix,
                               self.n_st, self.n_pix, rp, self.cont_list, self.cont_count, self.out, self.ncontrib,
@@ -540,11 +553,17 @@ class Trainer:
                     vb.bin_sort_async(None, self.rp.alpha_min)   # no host wait
                 else:
                     vb.bin_sort(None, self.rp.alpha_min)         # sizes the pair arrays once per slot
-            with st("render_fwd"):
-                if vb.two_part:
-                    vb.render_fwd_two_part(self.rp, self.counters, self.rp.alpha_min, wait=not vb.sized)
-                    vb.sized = True
-                else:
+            if vb.two_part:
+                # prefix forward, the marked tiles' continuation lists, their forward
+                with st("render_fwd"):
+                    vb.render_fwd_prefix(self.rp, self.counters)
+                with st("bin_sort"):
+                    vb.continue_lists(self.rp.alpha_min, wait=not vb.sized)
+                with st("render_fwd"):
+                    vb.render_fwd_cont(self.rp, self.counters)
+                vb.sized = True
+            else:
+                with st("render_fwd"):
                     vb.render_fwd(self.rp, self.counters)
             if not all_waited:
                 # the loss normalises by the step's total sample count
