@@ -22,7 +22,8 @@ constexpr int kOffW1 = 0, kOffB1 = 2048, kOffW2 = 2112, kOffB2 = 6208, kOffW3 = 
 constexpr int kParams = TGS_TILE_MLP_PARAMS;
 static_assert(kOffB3 + 1 == kParams, "parameter layout");
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // float32 -> bfloat16 bits, round to nearest, ties to even (finite inputs)
@@ -96,24 +97,34 @@ __device__ void stage_weights(const float* __restrict__ p, MlpLds& s) {
   }
 }
 
-// MFMA operand of W^T (16 outputs x 16 inputs) for input block kb and output
-// block ob: lane l holds W[kb*16 + 4(l/16) + r][ob*16 + l%16], r = 0..3.
-__device__ __forceinline__ bf16x4 weight_frag(const uint16_t* w, int kb, int ob, int lane) {
-  const int k0 = kb * 16 + 4 * (lane >> 4), o = ob * 16 + (lane & 15);
-  bf16x4 a;
-  a.x = (short)w[(k0 + 0) * kHid + o];
-  a.y = (short)w[(k0 + 1) * kHid + o];
-  a.z = (short)w[(k0 + 2) * kHid + o];
-  a.w = (short)w[(k0 + 3) * kHid + o];
-  return a;
-}
-
-// Each wave evaluates 16 rows in the transposed form Z^T = W^T X^T: the
-// 16x16x16 bfloat16 MFMA leaves lane l with rows row0 + l%16 and outputs
-// ob*16 + 4(l/16) + r, which is exactly the operand layout the next layer
-// takes for its input block ob, so activations never leave registers.
+// The forward runs on gfx950's 16x16x32 bfloat16 MFMA in the transposed
+// form Z^T = W^T X^T: A = W^T (16 outputs x 32 inputs), B = X^T (32 inputs x
+// 16 rows); lane l holds row/output l % 16 and eight inputs of quarter
+// q = l / 16, and receives outputs 4q .. 4q + 3 of row l % 16.  The sum
+// over the 32 inputs does not depend on which input each (lane, element)
+// slot carries, as long as A and B agree: layer 1 gives slot (q, e) input
+// 8q + e (eight consecutive features, two 16-byte loads); layer 2 gives it
+// 4q + e (e < 4) or 16 + 4q + e - 4 of its 32-input half, which are
+// exactly the outputs of two consecutive output blocks that the previous
+// layer left in this lane, so activations never leave registers.
 constexpr int kMlpBlock = 256;
 constexpr int kMlpRowsPerWave = 16;
+
+__device__ __forceinline__ bf16x8 pack8(const short8& v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Slot e of quarter q: the input index within a 32-input half.
+__device__ __forceinline__ int slot_in(int layer, int q, int e) {
+  return layer == 1 ? 8 * q + e : (e < 4 ? 4 * q + e : 16 + 4 * q + e - 4);
+}
+
+// A operand of W^T for input half kh (inputs 32 kh ..) and output block ob.
+__device__ __forceinline__ bf16x8 weight_frag8(const uint16_t* w, int layer, int kh, int ob, int lane) {
+  const int q = lane >> 4, o = ob * 16 + (lane & 15);
+  short8 a;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) a[e] = (short)w[(32 * kh + slot_in(layer, q, e)) * kHid + o];
+  return pack8(a);
+}
 
 __global__ void __launch_bounds__(kMlpBlock) tile_mlp_fwd_kernel(const float* __restrict__ p,
                                                                  const float* __restrict__ X, int64_t n,
@@ -126,38 +137,47 @@ __global__ void __launch_bounds__(kMlpBlock) tile_mlp_fwd_kernel(const float* __
   if (row0 >= n) return;  // wave-uniform; no barrier follows
   const int64_t row = row0 + (lane & 15);
   const bool live = row < n;
-  const int kq = 4 * (lane >> 4);  // this lane's 4 consecutive inputs / outputs within a block
-  // layer 1: inputs in two blocks of 16
-  bf16x4 xf[2];
+  const int q = lane >> 4, kq = 4 * q;  // this lane's quarter; its 4 outputs within a block
+  // layer 1: the 32 inputs as one MFMA operand (features 8q .. 8q + 7)
+  short8 xs;
+  {
+    const float4 v0 = live ? *reinterpret_cast<const float4*>(X + row * kFeat + 8 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 v1 =
+        live ? *reinterpret_cast<const float4*>(X + row * kFeat + 8 * q + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
-  for (int kb = 0; kb < 2; ++kb) {
-    const float4 v = live ? *reinterpret_cast<const float4*>(X + row * kFeat + kb * 16 + kq)
-                          : make_float4(0.f, 0.f, 0.f, 0.f);
-    xf[kb] = bf16x4{(short)to_bf16(v.x), (short)to_bf16(v.y), (short)to_bf16(v.z), (short)to_bf16(v.w)};
+    for (int e = 0; e < 8; ++e) xs[e] = (short)to_bf16(v[e]);
   }
-  bf16x4 hf[4];
+  const bf16x8 xf = pack8(xs);
+  uint16_t h[4][4];  // bfloat16 activations: output block ob, outputs kq .. kq + 3
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(weight_frag(s.w1, kb, ob, lane), xf[kb], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(weight_frag8(s.w1, 1, 0, ob, lane), xf, acc, 0, 0, 0);
     float z[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) z[r] = acc[r] + s.b1[ob * 16 + kq + r];
     if (live && act != nullptr)
       *reinterpret_cast<float4*>(act + row * (2 * kHid) + ob * 16 + kq) = make_float4(z[0], z[1], z[2], z[3]);
-    hf[ob] = bf16x4{(short)to_bf16(gelu(z[0])), (short)to_bf16(gelu(z[1])), (short)to_bf16(gelu(z[2])),
-                    (short)to_bf16(gelu(z[3]))};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[ob][r] = to_bf16(gelu(z[r]));
   }
-  // layer 2 and the output unit
+  // layer 2 (two 32-input halves) and the output unit
+  bf16x8 hf[2];
+#pragma unroll
+  for (int kh = 0; kh < 2; ++kh) {
+    short8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (short)h[2 * kh + (e >> 2)][e & 3];
+    hf[kh] = pack8(v);
+  }
   float part = 0.f;
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(weight_frag(s.w2, kb, ob, lane), hf[kb], acc, 0, 0, 0);
+    for (int kh = 0; kh < 2; ++kh)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(weight_frag8(s.w2, 2, kh, ob, lane), hf[kh], acc, 0, 0, 0);
     float z[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
