@@ -129,7 +129,7 @@ def make_trainer(p, cam, gt, rate, dev, density_stats=False):
     import torch
 
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
-    cfg = StepConfig(rate_permille=rate, density_stats=density_stats, prefix_fraction=PREFIX)
+    cfg = StepConfig(rate_permille=rate, density_stats=density_stats, prefix_fraction=PREFIX, fuse_views=True)
     E = torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev)
     A = torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev)
     tr = Trainer(torch.from_numpy(p).to(dev), [cam], [torch.from_numpy(gt).to(dev)], cfg, E=[E], A=[A])
@@ -231,7 +231,7 @@ def full_trainer(p, cams, gts, rate, dev, prefix=FULL_PREFIX):
     import torch
 
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
-    cfg = StepConfig(rate_permille=rate, prefix_fraction=prefix)
+    cfg = StepConfig(rate_permille=rate, prefix_fraction=prefix, fuse_views=True)
     E = [torch.zeros((FULL_H, FULL_W), dtype=torch.int16, device=dev) for _ in cams]
     A = [torch.zeros((FULL_H, FULL_W), dtype=torch.int16, device=dev) for _ in cams]
     tr = Trainer(torch.from_numpy(p).to(dev), cams, gts, cfg, E=E, A=A)
@@ -312,7 +312,8 @@ def matched_psnr(dev, dense_steps=PSNR_DENSE_STEPS, max_steps=PSNR_MAX_STEPS):
     order = np.random.default_rng(synth.SEED_VIEWS).integers(0, len(train), size=max_steps)
 
     def run(rate, target_psnr, n_max, n_tiles_sel=-1, learned=False):
-        cfg = StepConfig(rate_permille=rate, n_tiles_sel=n_tiles_sel, learned_tiles=learned, prefix_fraction=PREFIX)
+        cfg = StepConfig(rate_permille=rate, n_tiles_sel=n_tiles_sel, learned_tiles=learned, prefix_fraction=PREFIX,
+                         fuse_views=True)
         E = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in train]
         A = [torch.zeros((HEIGHT, WIDTH), dtype=torch.int16, device=dev) for _ in train]
         tr = Trainer(torch.from_numpy(p0).to(dev), [cams[i] for i in train], [gts[i] for i in train], cfg,

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 10u
+#define TGS_ABI_VERSION 11u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
@@ -648,6 +648,29 @@ int32_t tgs_project_bwd_optimizer_step(float* params, int64_t n, const tgs_camer
                                        const float* grad_prev, float* m, float* v,
                                        const uint8_t* touched, const tgs_optim_params* op,
                                        int64_t step, void* ws, size_t ws_bytes, void* stream);
+
+/* The projection backward of every view of a training step fused with the
+ * update (Sec. 3.9 update applied to the sum over the step's views of
+ * Sec. 3.6's backward), in place of tgs_project_bwd for each view and
+ * tgs_project_bwd_optimizer_step for the last: each Gaussian's chain rule
+ * is evaluated for every view in registers, summed in FP64, rounded to
+ * float once and the rows are updated in the same pass; no gradient array
+ * is written or read.  The sum over views is taken in another order than
+ * the per-view path's float sums, so results agree with it to rounding,
+ * not bit for bit.
+ *   n_views  1..16
+ *   cams     [n_views] host array of the views' cameras
+ *   radius, clamp, g2d  host arrays of n_views device pointers: each view's
+ *            projection outputs and its backward's screen-space gradient
+ *   ws       tgs_project_bwd_optimizer_views_workspace_size(n, n_views)
+ *            bytes (8-byte aligned): each view's partial dL/du
+ *   other arguments as in tgs_project_bwd_optimizer_step */
+size_t tgs_project_bwd_optimizer_views_workspace_size(int64_t n, int32_t n_views);
+int32_t tgs_project_bwd_optimizer_step_views(float* params, int64_t n, int32_t n_views, const tgs_camera* cams,
+                                             const tgs_raster_params* rp, const int32_t* const* radius,
+                                             const uint8_t* const* clamp, const float* const* g2d, float* m,
+                                             float* v, const uint8_t* touched, const tgs_optim_params* op,
+                                             int64_t step, void* ws, size_t ws_bytes, void* stream);
 
 /* Hybrid moment-damped LM / Adam update (Sec. 3.9, Eq. moment_damped_lm, and
  * the appendix optimizer details): per touched Gaussian, Adam moments for all

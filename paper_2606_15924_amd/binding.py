@@ -148,6 +148,10 @@ PROTOTYPES = {
     "tgs_tile_mlp_workspace_size": (_SZ, [_I64]),
     "tgs_tile_mlp_train_step": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I64, _I64, ctypes.c_float, _P, _P, _SZ, _P]),
     "tgs_project_bwd_optimizer_workspace_size": (_SZ, [_I64]),
+    "tgs_project_bwd_optimizer_views_workspace_size": (_SZ, [_I64, _I32]),
+    "tgs_project_bwd_optimizer_step_views": (_I32, [_P, _I64, _I32, ctypes.POINTER(tgs_camera),
+                                                    ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P,
+                                                    ctypes.POINTER(tgs_optim_params), _I64, _P, _SZ, _P]),
     "tgs_project_bwd_optimizer_step": (_I32, [_P, _I64, ctypes.POINTER(tgs_camera),
                                               ctypes.POINTER(tgs_raster_params), _P, _P, _P, _P, _P, _P, _P,
                                               ctypes.POINTER(tgs_optim_params), _I64, _P, _SZ, _P]),
@@ -562,6 +566,24 @@ def tgs_project_bwd_optimizer_step(params, n, cam: tgs_camera, rp: tgs_raster_pa
                                                 _ptr(m), _ptr(v), _ptr(touched), ctypes.byref(op), step,
                                                 _ptr(ws), ws.numel() * ws.element_size(), _stream()),
            "tgs_project_bwd_optimizer_step")
+
+
+def tgs_project_bwd_optimizer_views_workspace_size(n: int, n_views: int) -> int:
+    return int(lib().tgs_project_bwd_optimizer_views_workspace_size(n, n_views))
+
+
+def tgs_project_bwd_optimizer_step_views(params, n, cams, rp: tgs_raster_params, radius, clamp, g2d, m, v, touched,
+                                         op: tgs_optim_params, step, ws):
+    """Every view's projection backward and the update in one pass; cams,
+    radius, clamp and g2d are per-view lists (tgs_camera records, device
+    tensors)."""
+    k = len(cams)
+    cam_arr = (tgs_camera * k)(*cams)
+    ptrs = [(ctypes.c_void_p * k)(*[_ptr(t) for t in xs]) for xs in (radius, clamp, g2d)]
+    _check(lib().tgs_project_bwd_optimizer_step_views(_ptr(params), n, k, cam_arr, ctypes.byref(rp), ptrs[0], ptrs[1],
+                                                      ptrs[2], _ptr(m), _ptr(v), _ptr(touched), ctypes.byref(op),
+                                                      step, _ptr(ws), ws.numel() * ws.element_size(), _stream()),
+           "tgs_project_bwd_optimizer_step_views")
 
 
 # ------------------------------------------------------------------ learned tile priority

@@ -44,6 +44,9 @@ class StepConfig:
     beta: float = 0.4
     seed: int = 3
     fuse_optimizer: bool = True   # last view's projection backward fused with the update
+    # every view's projection backward fused with the update in one pass
+    # (tgs_project_bwd_optimizer_step_views; no gradient array)
+    fuse_views: bool = False
     learned_tiles: bool = False   # tile pass by the learned tile priority (with n_tiles_sel > 0)
     tile_lr: float = 3e-3         # its online Adam learning rate
     tile_seed: int = 23           # its initial weights
@@ -588,7 +591,9 @@ class Trainer:
                               deterministic=self.cfg.deterministic)
             if self.gstats is not None:
                 B.tgs_grad_screen_accumulate(vb.g2d, vb.radius, self.n, cam.width, cam.height, self.gstats)
-            if k + 1 < len(used) or not self.cfg.fuse_optimizer:
+            if self.cfg.fuse_views:
+                pass   # every view's chain rule joins the update after the loop
+            elif k + 1 < len(used) or not self.cfg.fuse_optimizer:
                 with st("project_bwd"):
                     # the first view overwrites the gradient, later views add to it
                     vb.project_bwd(self.params, cam, self.rp, self.grad, accumulate=k > 0)
@@ -598,7 +603,16 @@ class Trainer:
                     B.tgs_project_bwd_optimizer_step(self.params, self.n, cam, self.rp, vb.radius, vb.clamp,
                                                      vb.g2d, self.grad if k > 0 else None, self.m, self.v,
                                                      self.touched, self.op, t, self.fused_ws)
-        if not used or not self.cfg.fuse_optimizer:
+        if used and self.cfg.fuse_views:
+            need = B.tgs_project_bwd_optimizer_views_workspace_size(self.n, len(used))
+            if getattr(self, "views_ws", None) is None or self.views_ws.numel() < need:
+                self.views_ws = torch.empty(need, dtype=torch.uint8, device=self.dev)
+            with st("project_bwd_optimizer"):
+                B.tgs_project_bwd_optimizer_step_views(self.params, self.n, [self.cams[v] for v in views], self.rp,
+                                                       [vb.radius for vb in used], [vb.clamp for vb in used],
+                                                       [vb.g2d for vb in used], self.m, self.v, self.touched,
+                                                       self.op, t, self.views_ws)
+        elif not used or not self.cfg.fuse_optimizer:
             with st("optimizer"):
                 B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
         main.wait_stream(side)

@@ -167,6 +167,21 @@ def check_pair_lists(vals, ranges, n_pairs, pr: dict, valid_tiles=None, keys=Non
     return dict(gpu=int(code_g.size), oracle=int(sk.size), dropped=int(dropped.size), checked=int(chk.size))
 
 
+def last_ids_two_part(vals, ranges, vals2, ranges2, tiles, ncontrib) -> np.ndarray:
+    """last_ids over two-part lists (a tile's list is vals[ranges[t]]
+    followed by vals2[ranges2[t]])."""
+    vals = np.asarray(vals).astype(np.int64)
+    vals2 = np.asarray(vals2).astype(np.int64)
+    r1 = np.asarray(ranges, dtype=np.int64).reshape(-1, 2)[np.asarray(tiles, dtype=np.int64)]
+    r2 = np.asarray(ranges2, dtype=np.int64).reshape(-1, 2)[np.asarray(tiles, dtype=np.int64)]
+    pos = np.asarray(ncontrib).astype(np.int64) - 1
+    n1 = r1[:, 1] - r1[:, 0]
+    first = np.clip(r1[:, 0] + pos, 0, max(vals.size - 1, 0))
+    second = np.clip(r2[:, 0] + pos - n1, 0, max(vals2.size - 1, 0))
+    ids = np.where(pos < n1, vals[first] if vals.size else -1, vals2[second] if vals2.size else -1)
+    return np.where(pos >= 0, ids, -1)
+
+
 def last_ids(vals, ranges, tiles, ncontrib) -> np.ndarray:
     """The id of the last composited Gaussian of each pixel (-1 when none):
     the ncontrib-th entry of the pixel's tile list.  Unique for a pixel

@@ -10,8 +10,8 @@ import synth
 from oracle import binning, maps, optim, pipeline, project, project_bwd, render, sampler
 from oracle.params import LossParams, OptimParams, RasterParams, SampleParams
 
-from support import (assert_close, check_pair_lists, last_ids, scene_c1, scene_scaling, small_scene,
-                     splat_as_oracle, splat_record)
+from support import (assert_close, check_pair_lists, last_ids, last_ids_two_part, scene_c1, scene_scaling,
+                     small_scene, splat_as_oracle, splat_record)
 
 pytestmark = pytest.mark.gpu
 
@@ -126,7 +126,7 @@ def _dL_perturbations(fv, gt, s, P_step, tiles_step, rng):
     return out
 
 
-@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("fused", [False, True, "views", "views_prefix"])
 def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     """One four-view step against the oracle's step, element by element:
     samples bit for bit; rgb to 1e-5; the last composited Gaussian of every
@@ -142,14 +142,19 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     * the updated parameters per element within the spread of the oracle's
       update over gradients moved inside that error bar (all magnitudes up,
       all down, four random sign patterns; times 1.5), plus 1e-4 relative
-      and two FP32 ulps of the parameter."""
+      and two FP32 ulps of the parameter.
+    fused: False, the per-view projection backward then the update; True,
+    the last view's fused with the update; "views", every view's in the
+    update's pass; "views_prefix", that with depth-prefix lists (10%)."""
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
     p, cams, gts, E, A = c1_inputs
     n = p.shape[1]
     sp = SampleParams(n_pix=64, n_tiles_sel=64)
     ref = pipeline.train_step(p, np.zeros_like(p, np.float64), np.zeros_like(p, np.float64), cams, gts, E, A,
                               1, sp, RP, LossParams(), OptimParams(), seed=3)
-    cfg = StepConfig(rate_permille=250, n_tiles_sel=64, seed=3, fuse_optimizer=fused)
+    cfg = StepConfig(rate_permille=250, n_tiles_sel=64, seed=3, fuse_optimizer=fused is not False,
+                     fuse_views=fused in ("views", "views_prefix"),
+                     prefix_fraction=0.1 if fused == "views_prefix" else None)
     Eg = [dev(e.view(np.int16)) for e in E]
     Ag = [dev(a.view(np.int16)) for a in A]
     tr = Trainer(dev(p), cams, [dev(g) for g in gts], cfg, E=Eg, A=Ag)
@@ -173,7 +178,11 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
         assert ok.mean() > 0.999
         assert_close(o[ok, :3], fv["out"]["rgb"][ok], 1e-5, 1e-6, f"view {v} rgb")
         tiles = (fv["ys"] // 16) * fv["proj"]["TX"] + fv["xs"] // 16
-        got_last = last_ids(host(vb.vals), host(vb.ranges), tiles, host(vb.ncontrib)[:P])
+        if vb.two_part:
+            got_last = last_ids_two_part(host(vb.vals), host(vb.ranges), host(vb.vals2), host(vb.ranges2), tiles,
+                                         host(vb.ncontrib)[:P])
+        else:
+            got_last = last_ids(host(vb.vals), host(vb.ranges), tiles, host(vb.ncontrib)[:P])
         want_last = last_ids(fv["vals"], fv["ranges"], tiles, fv["out"]["n_contrib"])
         assert np.array_equal(got_last[ok], want_last[ok])
         assert np.array_equal(host(Ag[v]).view(np.uint16), ref["A"][v])
@@ -682,3 +691,30 @@ def test_large_scene_view_on_sampled_tiles(B):
     # keeps their FP32 alpha as exact as elsewhere, so few pixels are flagged
     assert ok.mean() >= 0.99, ok.mean()
     assert_close(host(vb.out)[idx][ok, :3], ref["rgb"][ok], 1e-5, 1e-7, "rgb")
+
+
+def test_views_fused_update_matches_per_view_path(B, c1_inputs):
+    """One four-view step with every view's projection backward fused into
+    the update's pass against the per-view path (projection backward per
+    view, the last fused with the update): the same step up to the order of
+    the gradient sums over views.  eps of Adam and of the LM damping at 1
+    keep the update linear in small gradient changes, so moments and
+    parameter changes compare at 1e-4 relative plus 1e-6 of the row's
+    largest change; the touched set is the same."""
+    from paper_2606_15924_amd.pipeline import StepConfig, Trainer
+    p, cams, gts, E, A = c1_inputs
+    res = []
+    for views in (False, True):
+        cfg = StepConfig(rate_permille=250, n_tiles_sel=64, seed=3, fuse_views=views,
+                         optim={"eps_adam": 1.0, "eps_lm": 1.0})
+        tr = Trainer(dev(p), cams, [dev(g) for g in gts], cfg, E=[dev(e.view(np.int16)) for e in E],
+                     A=[dev(a.view(np.int16)) for a in A])
+        tr.step([0, 1, 2, 3])
+        res.append([host(x).astype(np.float64) for x in (tr.params, tr.m, tr.v, tr.touched)])
+        del tr
+    (p0, m0, v0, t0), (p1, m1, v1, t1) = res
+    assert np.array_equal(t0, t1) and t0.sum() > 1000
+    d0, d1 = p0 - p, p1 - p
+    for a, b in ((d1, d0), (m1, m0), (v1, v0)):
+        scale = np.abs(b).max(axis=1, keepdims=True) + 1e-30
+        assert np.all(np.abs(a - b) <= 1e-4 * np.abs(b) + 1e-6 * scale)
