@@ -653,17 +653,20 @@ int32_t tgs_project_bwd_optimizer_step(float* params, int64_t n, const tgs_camer
  * update (Sec. 3.9 update applied to the sum over the step's views of
  * Sec. 3.6's backward), in place of tgs_project_bwd for each view and
  * tgs_project_bwd_optimizer_step for the last: each Gaussian's chain rule
- * is evaluated for every view in registers, summed in FP64, rounded to
- * float once and the rows are updated in the same pass; no gradient array
- * is written or read.  The sum over views is taken in another order than
- * the per-view path's float sums, so results agree with it to rounding,
- * not bit for bit.
+ * is evaluated for every view in registers and the rows are updated in the
+ * same pass; no gradient array is written or read.  SH rows of degree >= 1
+ * sum each view's float-rounded gradient in view order (as the per-view
+ * path's gradient array does); rows 0-13 sum the views in FP64, the
+ * covariance, opacity and colour gradients before the linear maps to the
+ * scale, quaternion, opacity and DC rows, so they agree with the per-view
+ * path to rounding, not bit for bit.
  *   n_views  1..16
  *   cams     [n_views] host array of the views' cameras
  *   radius, clamp, g2d  host arrays of n_views device pointers: each view's
  *            projection outputs and its backward's screen-space gradient
  *   ws       tgs_project_bwd_optimizer_views_workspace_size(n, n_views)
- *            bytes (8-byte aligned): each view's partial dL/du
+ *            bytes (8-byte aligned): per Gaussian the mean's gradient
+ *            through the SH rows' view directions (3 doubles)
  *   other arguments as in tgs_project_bwd_optimizer_step */
 size_t tgs_project_bwd_optimizer_views_workspace_size(int64_t n, int32_t n_views);
 int32_t tgs_project_bwd_optimizer_step_views(float* params, int64_t n, int32_t n_views, const tgs_camera* cams,

@@ -190,10 +190,11 @@ __global__ void __launch_bounds__(kWave) geom_lm_kernel(
 }
 
 // ---- every view of a step in one pass: the chain rule of each view is
-// evaluated in registers and summed (in FP64) before the update, so neither
-// the earlier views' projection backward nor their gradient array is
-// needed.  Same split as above; the SH kernel leaves each view's partial
-// dL/du in the workspace ([view][n][3] doubles) for the geometry kernel.
+// evaluated in registers and summed before the update, so neither the
+// earlier views' projection backward nor their gradient array is needed.
+// The SH kernel leaves, per Gaussian, the mean's gradient through the view
+// directions of the SH terms of degree >= 1 (three doubles in the
+// workspace) for the geometry kernel.
 constexpr int kMaxViews = 16;
 
 struct ViewSet {
@@ -204,101 +205,263 @@ struct ViewSet {
   int nv;
 };
 
-// SH rows in three groups of five terms (15 rows): per group the view loop
-// sums each row's gradient and adds the group's share of each view's
-// dL/du to the workspace (the first group stores it), which keeps the
-// registers of one group live rather than all 45 rows'.
-template <int kDeg>
-__global__ void __launch_bounds__(256) sh_rest_views_kernel(float* params, int64_t n, ViewSet vs, float* __restrict__ m,
-                                                            float* __restrict__ v, const uint8_t* __restrict__ touched,
-                                                            OptArgs o, double* __restrict__ dL_du_out) {
+// SH rows in three groups of five terms (15 rows), one wave per group: a
+// block holds 64 Gaussians in three waves.  Each wave sums its rows'
+// gradients over the views (each view's value rounded to float and added
+// in view order, as the per-view path's gradient array sums them), updates
+// its rows, and forms its share of the mean's gradient through u:
+// (I - u u^T) dL/du / |mu - centre| per view, summed in FP64.  The block
+// adds the three shares in group order and stores the sum.
+constexpr int kShGroups = 3;
+
+template <int kDeg, int kGrp>
+__device__ __forceinline__ void sh_group_views(float* params, int64_t n, const ViewSet& vs, float* __restrict__ m,
+                                               float* __restrict__ v, bool live, int64_t i, const OptArgs& o,
+                                               double (&dmu)[3]) {
 #pragma clang fp contract(off)
   constexpr int nk = (kDeg + 1) * (kDeg + 1);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (touched != nullptr && touched[i] == 0) return;  // untouched: parameters and moments stay
-  double mu[3];
-  for (int k = 0; k < 3; ++k) mu[k] = (double)params[(int64_t)k * n + i];
+  constexpr bool kTerms = 1 + 5 * kGrp < nk;
+  if (!live) return;
+  float cf[15], gs[15];
 #pragma unroll
-  for (int grp = 0; grp < 3; ++grp) {
-    float cf[15];
-#pragma unroll
-    for (int r = 0; r < 15; ++r) cf[r] = params[(int64_t)(14 + 15 * grp + r) * n + i];
-    double gs[15];
-#pragma unroll
-    for (int r = 0; r < 15; ++r) gs[r] = 0.0;
+  for (int r = 0; r < 15; ++r) {
+    cf[r] = params[(int64_t)(14 + 15 * kGrp + r) * n + i];
+    gs[r] = 0.f;
+  }
+  if (kTerms) {
+    double mu[3];
+    for (int k = 0; k < 3; ++k) mu[k] = (double)params[(int64_t)k * n + i];
     for (int j = 0; j < vs.nv; ++j) {
-      double* du_out = dL_du_out + ((int64_t)j * n + i) * 3;
-      const bool vis = vs.radius[j][i] != 0;
+      if (vs.radius[j][i] == 0) continue;
+      double gg[9];
+      for (int k = 0; k < 9; ++k) gg[k] = (double)vs.g2d[j][i * 9 + k];
+      const ViewDir u = view_dir(mu, vs.cam[j]);
+      double drgb[3];
+      color_grad(gg, vs.clampm[j][i], drgb);
       double du[3] = {0.0, 0.0, 0.0};
-      if (vis && 1 + 5 * grp < nk) {
-        double gg[9];
-        for (int k = 0; k < 9; ++k) gg[k] = (double)vs.g2d[j][i * 9 + k];
-        const ViewDir u = view_dir(mu, vs.cam[j]);
-        double drgb[3];
-        color_grad(gg, vs.clampm[j][i], drgb);
 #pragma unroll
-        for (int t = 0; t < 5; ++t) {
-          const int k = 1 + 5 * grp + t;
-          if (k >= nk) break;
-          double Yk, d0, d1, d2;
-          sh_term(k, u.ux, u.uy, u.uz, Yk, d0, d1, d2);
-          double gk = 0.0;
+      for (int t = 0; t < 5; ++t) {
+        const int k = 1 + 5 * kGrp + t;
+        if (k >= nk) break;
+        double Yk, d0, d1, d2;
+        sh_term(k, u.ux, u.uy, u.uz, Yk, d0, d1, d2);
+        double gk = 0.0;
 #pragma unroll
-          for (int ch = 0; ch < 3; ++ch) {
-            gk += (double)cf[3 * t + ch] * drgb[ch];
-            gs[3 * t + ch] += Yk * drgb[ch];
-          }
-          du[0] += d0 * gk;
-          du[1] += d1 * gk;
-          du[2] += d2 * gk;
+        for (int ch = 0; ch < 3; ++ch) {
+          gk += (double)cf[3 * t + ch] * drgb[ch];
+          gs[3 * t + ch] += (float)(Yk * drgb[ch]);
         }
+        du[0] += d0 * gk;
+        du[1] += d1 * gk;
+        du[2] += d2 * gk;
       }
-      if (grp == 0) {
-        for (int k = 0; k < 3; ++k) du_out[k] = du[k];
-      } else if (vis && 1 + 5 * grp < nk) {
-        for (int k = 0; k < 3; ++k) du_out[k] = du_out[k] + du[k];
-      }
+      const double udot = u.ux * du[0] + u.uy * du[1] + u.uz * du[2];
+      const double inv = 1.0 / u.dn;
+      dmu[0] += (du[0] - u.ux * udot) * inv;
+      dmu[1] += (du[1] - u.uy * udot) * inv;
+      dmu[2] += (du[2] - u.uz * udot) * inv;
     }
+  }
 #pragma unroll
-    for (int r = 0; r < 15; ++r) {
-      const int row = 14 + 15 * grp + r;
-      const int64_t idx = (int64_t)row * n + i;
-      float pp = cf[r], mm = m[idx], vv = v[idx];
-      adam_elem(pp, (float)gs[r], mm, vv, row_lr_bc1(o, row), o);
-      params[idx] = pp;
-      m[idx] = mm;
-      v[idx] = vv;
-    }
+  for (int r = 0; r < 15; ++r) {
+    const int row = 14 + 15 * kGrp + r;
+    const int64_t idx = (int64_t)row * n + i;
+    float pp = cf[r], mm = m[idx], vv = v[idx];
+    adam_elem(pp, gs[r], mm, vv, row_lr_bc1(o, row), o);
+    params[idx] = pp;
+    m[idx] = mm;
+    v[idx] = vv;
   }
 }
 
-__global__ void __launch_bounds__(64) geom_lm_views_kernel(float* params, int64_t n, ViewSet vs, int sh_degree,
-                                                           double z_near, double dil, float* __restrict__ m,
-                                                           float* __restrict__ v, const uint8_t* __restrict__ touched,
-                                                           OptArgs o, const double* __restrict__ dL_du_in) {
+template <int kDeg>
+__global__ void __launch_bounds__(kShGroups * kWave) sh_rest_views_kernel(float* params, int64_t n, ViewSet vs,
+                                                                           float* __restrict__ m,
+                                                                           float* __restrict__ v,
+                                                                           const uint8_t* __restrict__ touched,
+                                                                           OptArgs o, double* __restrict__ dmu_out) {
+  __shared__ double share[kShGroups - 1][3][kWave];
+  const int grp = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x % kWave);
+  const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+  // untouched: parameters and moments stay
+  const bool live = i < n && (touched == nullptr || touched[i] != 0);
+  double dmu[3] = {0.0, 0.0, 0.0};
+  if (grp == 0)
+    sh_group_views<kDeg, 0>(params, n, vs, m, v, live, i, o, dmu);
+  else if (grp == 1)
+    sh_group_views<kDeg, 1>(params, n, vs, m, v, live, i, o, dmu);
+  else
+    sh_group_views<kDeg, 2>(params, n, vs, m, v, live, i, o, dmu);
+  if (grp > 0)
+    for (int k = 0; k < 3; ++k) share[grp - 1][k][lane] = dmu[k];
+  __syncthreads();
+  if (grp == 0 && live)
+    for (int k = 0; k < 3; ++k) dmu_out[i * 3 + k] = (dmu[k] + share[0][k][lane]) + share[1][k][lane];
+}
+
+// Rows 0-13 (mean, log-scale, quaternion, opacity, SH DC) of one Gaussian
+// summed over the views.  The shape (scales, rotation, 3D covariance) is
+// formed once; per view only the projection Jacobian, the 2D covariance
+// and the backward through them run.  The maps from the summed covariance
+// gradient to the scale and quaternion rows, from the summed opacity
+// gradient to its logit and from the summed colour gradient to the DC rows
+// are linear, so each is applied once to the sum.  Products by reciprocals
+// stand for the divisions of the per-view chain rule.
+__device__ __forceinline__ void geom_views_grad(const float* params, int64_t n, const ViewSet& vs, int64_t i,
+                                                double dil, const double (&dmu_sh)[3], double (&gr)[kGeoRows]) {
+#pragma clang fp contract(off)
+  // the shape: only the 3D covariance and the scales stay live through the
+  // view loop; rotation and M are formed again for the linear tail
+  const double mu[3] = {params[i], params[n + i], params[2 * n + i]};
+  double s[3];
+  for (int k = 0; k < 3; ++k) s[k] = exp((double)params[(int64_t)(3 + k) * n + i]);
+  auto quat = [&](double (&q)[4]) {
+    const double qw = params[6 * n + i], qx = params[7 * n + i], qy = params[8 * n + i], qz = params[9 * n + i];
+    const double iq = 1.0 / sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+    q[0] = qw * iq;
+    q[1] = qx * iq;
+    q[2] = qy * iq;
+    q[3] = qz * iq;
+    return iq;
+  };
+  auto rot = [](const double (&q)[4], double (&Rq)[3][3]) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    Rq[0][0] = 1.0 - 2.0 * (y * y + z * z);
+    Rq[0][1] = 2.0 * (x * y - w * z);
+    Rq[0][2] = 2.0 * (x * z + w * y);
+    Rq[1][0] = 2.0 * (x * y + w * z);
+    Rq[1][1] = 1.0 - 2.0 * (x * x + z * z);
+    Rq[1][2] = 2.0 * (y * z - w * x);
+    Rq[2][0] = 2.0 * (x * z - w * y);
+    Rq[2][1] = 2.0 * (y * z + w * x);
+    Rq[2][2] = 1.0 - 2.0 * (x * x + y * y);
+  };
+  double S[3][3];
+  {
+    double q[4], Rq[3][3], M[3][3];
+    (void)quat(q);
+    rot(q, Rq);
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) M[r][k] = Rq[r][k] * s[k];
+    for (int r = 0; r < 3; ++r)
+      for (int k = r; k < 3; ++k) S[r][k] = (M[r][0] * M[k][0] + M[r][1] * M[k][1]) + M[r][2] * M[k][2];
+    for (int r = 1; r < 3; ++r)
+      for (int k = 0; k < r; ++k) S[r][k] = S[k][r];
+  }
+
+  double dS[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  double dmu[3] = {dmu_sh[0], dmu_sh[1], dmu_sh[2]};
+  double dop = 0.0, dc[3] = {0.0, 0.0, 0.0};
+#pragma clang loop unroll(disable)
+  for (int j = 0; j < vs.nv; ++j) {
+    if (vs.radius[j][i] == 0) continue;  // listed views only (in front of the camera)
+    const CamArgs& cam = vs.cam[j];
+    double gg[9];
+    for (int k = 0; k < 9; ++k) gg[k] = (double)vs.g2d[j][i * 9 + k];
+    double t[3];
+    for (int r = 0; r < 3; ++r)
+      t[r] = ((cam.R[r * 3 + 0] * mu[0] + cam.R[r * 3 + 1] * mu[1]) + cam.R[r * 3 + 2] * mu[2]) + cam.t[r];
+    const double tx = t[0], ty = t[1];
+    const double itz = 1.0 / t[2], itz2 = itz * itz, itz3 = itz2 * itz;
+    const double J00 = cam.fx * itz, J02 = -(cam.fx * tx) * itz2, J11 = cam.fy * itz, J12 = -(cam.fy * ty) * itz2;
+    double T[2][3];
+    for (int k = 0; k < 3; ++k) {
+      T[0][k] = J00 * cam.R[0 * 3 + k] + J02 * cam.R[2 * 3 + k];
+      T[1][k] = J11 * cam.R[1 * 3 + k] + J12 * cam.R[2 * 3 + k];
+    }
+    double TS[2][3];
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 3; ++k) TS[r][k] = (T[r][0] * S[0][k] + T[r][1] * S[1][k]) + T[r][2] * S[2][k];
+    const double a = ((TS[0][0] * T[0][0] + TS[0][1] * T[0][1]) + TS[0][2] * T[0][2]) + dil;
+    const double b = (TS[0][0] * T[1][0] + TS[0][1] * T[1][1]) + TS[0][2] * T[1][2];
+    const double c = ((TS[1][0] * T[1][0] + TS[1][1] * T[1][1]) + TS[1][2] * T[1][2]) + dil;
+    const double idet = 1.0 / (a * c - b * b), id2 = idet * idet;
+
+    // centre
+    double dt[3];
+    dt[0] = gg[0] * cam.fx * itz;
+    dt[1] = gg[1] * cam.fy * itz;
+    dt[2] = gg[0] * (-cam.fx * tx * itz2) + gg[1] * (-cam.fy * ty * itz2);
+    // conic (c, -b, a) / det -> 2D covariance entries
+    const double gca = gg[2], gcb = gg[3], gcc = gg[4];
+    const double dLa = gca * (-c * c * id2) + gcb * (b * c * id2) + gcc * (idet - a * c * id2);
+    const double dLb = gca * (2.0 * b * c * id2) + gcb * (-idet - 2.0 * b * b * id2) + gcc * (2.0 * a * b * id2);
+    const double dLc = gca * (idet - a * c * id2) + gcb * (a * b * id2) + gcc * (-a * a * id2);
+    const double G[2][2] = {{dLa, 0.5 * dLb}, {0.5 * dLb, dLc}};
+    double GT[2][3];
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 3; ++k) GT[r][k] = G[r][0] * T[0][k] + G[r][1] * T[1][k];
+    // dSigma += T^T G T ; dT = 2 G T Sigma
+    for (int r = 0; r < 3; ++r)
+      for (int k = r; k < 3; ++k) dS[r][k] += T[0][r] * GT[0][k] + T[1][r] * GT[1][k];
+    double dT[2][3];
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 3; ++k) dT[r][k] = 2.0 * (GT[r][0] * S[0][k] + GT[r][1] * S[1][k] + GT[r][2] * S[2][k]);
+    auto dJ = [&](int r, int k) {
+      return dT[r][0] * cam.R[k * 3 + 0] + dT[r][1] * cam.R[k * 3 + 1] + dT[r][2] * cam.R[k * 3 + 2];
+    };
+    const double dJ00 = dJ(0, 0), dJ02 = dJ(0, 2), dJ11 = dJ(1, 1), dJ12 = dJ(1, 2);
+    dt[0] += dJ02 * (-cam.fx * itz2);
+    dt[1] += dJ12 * (-cam.fy * itz2);
+    dt[2] += dJ00 * (-cam.fx * itz2) + dJ02 * (2.0 * cam.fx * tx * itz3) + dJ11 * (-cam.fy * itz2) +
+             dJ12 * (2.0 * cam.fy * ty * itz3);
+    for (int k = 0; k < 3; ++k)
+      dmu[k] += cam.R[0 * 3 + k] * dt[0] + cam.R[1 * 3 + k] * dt[1] + cam.R[2 * 3 + k] * dt[2];
+    dop += gg[5];
+    double drgb[3];
+    color_grad(gg, vs.clampm[j][i], drgb);
+    for (int ch = 0; ch < 3; ++ch) dc[ch] += drgb[ch];
+  }
+
+  // Sigma = M M^T, M = R(q) diag(s): scale and quaternion rows
+  for (int r = 1; r < 3; ++r)
+    for (int k = 0; k < r; ++k) dS[r][k] = dS[k][r];
+  double q[4], Rq[3][3], M[3][3];
+  const double iq = quat(q);
+  rot(q, Rq);
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) M[r][k] = Rq[r][k] * s[k];
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  double dM[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) dM[r][k] = 2.0 * (dS[r][0] * M[0][k] + dS[r][1] * M[1][k] + dS[r][2] * M[2][k]);
+  double dR[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double ds = Rq[0][k] * dM[0][k] + Rq[1][k] * dM[1][k] + Rq[2][k] * dM[2][k];
+    gr[3 + k] = ds * s[k];
+    for (int r = 0; r < 3; ++r) dR[r][k] = dM[r][k] * s[k];
+  }
+  double dq[4];
+  dq[0] = 2.0 * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
+  dq[1] = 2.0 * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.0 * x * dR[1][1] - w * dR[1][2] + z * dR[2][0] +
+                 w * dR[2][1] - 2.0 * x * dR[2][2]);
+  dq[2] = 2.0 * (-2.0 * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] - w * dR[2][0] +
+                 z * dR[2][1] - 2.0 * y * dR[2][2]);
+  dq[3] = 2.0 * (-2.0 * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.0 * z * dR[1][1] +
+                 y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+  const double qdot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+  gr[6] = (dq[0] - w * qdot) * iq;
+  gr[7] = (dq[1] - x * qdot) * iq;
+  gr[8] = (dq[2] - y * qdot) * iq;
+  gr[9] = (dq[3] - z * qdot) * iq;
+  for (int k = 0; k < 3; ++k) gr[k] = dmu[k];
+  const double op = 1.0 / (1.0 + exp(-(double)params[10 * n + i]));
+  gr[10] = dop * op * (1.0 - op);
+  for (int ch = 0; ch < 3; ++ch) gr[11 + ch] = kC0 * dc[ch];
+}
+
+__global__ void __launch_bounds__(64) geom_lm_views_kernel(float* params, int64_t n, ViewSet vs, double dil,
+                                                           float* __restrict__ m, float* __restrict__ v,
+                                                           const uint8_t* __restrict__ touched, OptArgs o,
+                                                           const double* __restrict__ dmu_sh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (touched != nullptr && touched[i] == 0) return;
+  const double dsh[3] = {dmu_sh[i * 3], dmu_sh[i * 3 + 1], dmu_sh[i * 3 + 2]};
   double gsum[kGeoRows];
-#pragma unroll
-  for (int r = 0; r < kGeoRows; ++r) gsum[r] = 0.0;
-  auto sink = [&](int row, double val) { gsum[row] += val; };
-  for (int j = 0; j < vs.nv; ++j) {
-    if (vs.radius[j][i] == 0) continue;
-    Geom g;
-    geometry(params, n, i, vs.cam[j], z_near, dil, g);
-    double gg[9];
-    for (int k = 0; k < 9; ++k) gg[k] = (double)vs.g2d[j][i * 9 + k];
-    const ViewDir u = view_dir(g.mu, vs.cam[j]);
-    double drgb[3];
-    color_grad(gg, vs.clampm[j][i], drgb);
-    double dc_du[3] = {0.0, 0.0, 0.0};  // the DC basis is constant: no dL/du
-    sh_backward(params, n, i, u, drgb, n_sh(sh_degree), 0, 1, dc_du, sink);
-    const int64_t w = ((int64_t)j * n + i) * 3;
-    const double dL_du[3] = {dL_du_in[w], dL_du_in[w + 1], dL_du_in[w + 2]};
-    geom_backward(params, n, i, vs.cam[j], g, gg, u, dL_du, sink);
-  }
+  geom_views_grad(params, n, vs, i, dil, dsh, gsum);
   auto store = [&](int row, float pp, float mm, float vv) {
     const int64_t idx = (int64_t)row * n + i;
     m[idx] = mm;
@@ -347,7 +510,7 @@ using namespace tgs;
 
 extern "C" size_t tgs_project_bwd_optimizer_views_workspace_size(int64_t n, int32_t n_views) {
   if (n < 0 || n_views < 0) return 0;
-  return align_up((size_t)(3 * std::max<int64_t>(n, 1)) * (size_t)std::max(n_views, 1) * sizeof(double), 256);
+  return align_up((size_t)(3 * std::max<int64_t>(n, 1)) * sizeof(double), 256);
 }
 
 extern "C" int32_t tgs_project_bwd_optimizer_step_views(float* params, int64_t n, int32_t n_views,
@@ -385,9 +548,10 @@ extern "C" int32_t tgs_project_bwd_optimizer_step_views(float* params, int64_t n
   TGS_REQUIRE(ws_bytes >= need, "%s: workspace %zu bytes < %zu", who, ws_bytes, need);
   TGS_REQUIRE(((uintptr_t)ws & 7) == 0, "%s: workspace must be 8-byte aligned", who);
   hipStream_t s = as_stream(stream);
-  const dim3 grid((unsigned)ceil_div(n, 256));
-#define TGS_SH_VIEWS(D)                                                                                       \
-  hipLaunchKernelGGL(sh_rest_views_kernel<D>, grid, dim3(256), 0, s, params, n, vs, m, v, touched, o, (double*)ws)
+  const dim3 grid((unsigned)ceil_div(n, kWave));
+#define TGS_SH_VIEWS(D)                                                                                        \
+  hipLaunchKernelGGL(sh_rest_views_kernel<D>, grid, dim3(kShGroups * kWave), 0, s, params, n, vs, m, v, touched, \
+                     o, (double*)ws)
   switch (rp->sh_degree) {
     case 0: TGS_SH_VIEWS(0); break;
     case 1: TGS_SH_VIEWS(1); break;
@@ -396,7 +560,7 @@ extern "C" int32_t tgs_project_bwd_optimizer_step_views(float* params, int64_t n
   }
 #undef TGS_SH_VIEWS
   hipLaunchKernelGGL(geom_lm_views_kernel, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, s, params, n, vs,
-                     rp->sh_degree, (double)rp->z_near, (double)rp->dilation, m, v, touched, o, (const double*)ws);
+                     (double)rp->dilation, m, v, touched, o, (const double*)ws);
   return hip_status(who);
 }
 

@@ -45,7 +45,8 @@ class StepConfig:
     seed: int = 3
     fuse_optimizer: bool = True   # last view's projection backward fused with the update
     # every view's projection backward fused with the update in one pass
-    # (tgs_project_bwd_optimizer_step_views; no gradient array)
+    # (tgs_project_bwd_optimizer_step_views; no gradient array) in steps of
+    # two or more views; a one-view step takes the single-view fused kernel
     fuse_views: bool = False
     learned_tiles: bool = False   # tile pass by the learned tile priority (with n_tiles_sel > 0)
     tile_lr: float = 3e-3         # its online Adam learning rate
@@ -508,6 +509,7 @@ class Trainer:
         st = self._stage
         used = [self.buffers(slot, self.cams[v], rate_permille) for slot, v in enumerate(views)]
         slot_of = {id(vb): k for k, vb in enumerate(used)}
+        views_fused = self.cfg.fuse_views and len(used) > 1
         self.touched.zero_()
         # the sample totals are cleared (dense views' counts added) on main;
         # then each sparse view's sampler runs on a stream of its own (which
@@ -591,7 +593,7 @@ class Trainer:
                               deterministic=self.cfg.deterministic)
             if self.gstats is not None:
                 B.tgs_grad_screen_accumulate(vb.g2d, vb.radius, self.n, cam.width, cam.height, self.gstats)
-            if self.cfg.fuse_views:
+            if views_fused:
                 pass   # every view's chain rule joins the update after the loop
             elif k + 1 < len(used) or not self.cfg.fuse_optimizer:
                 with st("project_bwd"):
@@ -603,7 +605,7 @@ class Trainer:
                     B.tgs_project_bwd_optimizer_step(self.params, self.n, cam, self.rp, vb.radius, vb.clamp,
                                                      vb.g2d, self.grad if k > 0 else None, self.m, self.v,
                                                      self.touched, self.op, t, self.fused_ws)
-        if used and self.cfg.fuse_views:
+        if views_fused:
             need = B.tgs_project_bwd_optimizer_views_workspace_size(self.n, len(used))
             if getattr(self, "views_ws", None) is None or self.views_ws.numel() < need:
                 self.views_ws = torch.empty(need, dtype=torch.uint8, device=self.dev)
