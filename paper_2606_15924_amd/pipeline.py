@@ -48,6 +48,10 @@ class StepConfig:
     # (tgs_project_bwd_optimizer_step_views; no gradient array) in steps of
     # two or more views; a one-view step takes the single-view fused kernel
     fuse_views: bool = False
+    # views side by side: each view's sampler and chain (projection to
+    # backward) on a stream of its own, reused round-robin (1: all on the
+    # current stream, in view order)
+    view_streams: int = 1
     learned_tiles: bool = False   # tile pass by the learned tile priority (with n_tiles_sel > 0)
     tile_lr: float = 3e-3         # its online Adam learning rate
     tile_seed: int = 23           # its initial weights
@@ -140,6 +144,11 @@ class ViewBuffers:
 
     def _alloc_pairs(self, capacity: int):
         dev = self.splat.device
+        if getattr(self, "vals", None) is not None:
+            # the old arrays may still be in use on another stream (views
+            # side by side): the allocator must not hand them out before
+            # that work ends
+            torch.cuda.synchronize(dev)
         self.capacity = int(capacity)
         self.keys = torch.empty(self.capacity, dtype=torch.int64, device=dev) if self.keep_keys else None
         self.vals = torch.empty(self.capacity, dtype=torch.int32, device=dev)
@@ -188,6 +197,8 @@ class ViewBuffers:
     # ---- depth-prefix lists
     def _alloc_cont(self, capacity2: int):
         dev = self.splat.device
+        if self.vals2 is not None:
+            torch.cuda.synchronize(dev)   # as in _alloc_pairs
         self.capacity2 = int(capacity2)
         self.vals2 = torch.empty(self.capacity2, dtype=torch.int32, device=dev)
         self.sort_ws2 = torch.empty(B.tgs_bin_sort_workspace_size(self.n, self.capacity2, self.n_t),
@@ -437,7 +448,9 @@ class Trainer:
         # record queued before it)
         self._sampled: list = []           # per view slot: its sampler's completion
         self._sample_streams: list = []
-        self._lossed = torch.cuda.Event()
+        self._view_streams: list = []
+        self._lossed: list = []            # per view slot: its loss (the error maps' update waits)
+        self._done: list = []              # per view slot: its backward (with view streams)
         self._pending: list = []   # (event, pinned counts, [(view buffers, capacity)]) per step
 
     def _stage(self, name):
@@ -478,6 +491,7 @@ class Trainer:
             return old
         cap = old.capacity if old is not None and old.n == self.n else None
         if old is not None:
+            torch.cuda.synchronize(self.dev)   # its arrays may be in use on a view stream
             del self._bufs[key]
         self._bufs[key] = ViewBuffers(self.n, cam.width, cam.height, n_pix, self.cfg.n_tiles_sel, self.dev,
                                       capacity=cap)
@@ -520,12 +534,13 @@ class Trainer:
             if vb.dense:
                 self.totals[0] += self.cams[v].width * self.cams[v].height
                 self.totals[1] += vb.n_t
+        par = self.cfg.view_streams > 1
         sampled = []
         for k, (vb, v) in enumerate(zip(used, views)):
             if vb.dense:
                 sampled.append(None)
                 continue
-            ss = self._sample_stream(k)
+            ss = self._view_stream(k) if par else self._sample_stream(k)
             ss.wait_stream(main)
             with torch.cuda.stream(ss):
                 cam = self.cams[v]
@@ -539,53 +554,30 @@ class Trainer:
                 ev = self._sampled[k]
                 ev.record(ss)
             sampled.append(ev)
-        lossed = self._lossed
-        all_waited = False
         prefix_n = None
         if self.cfg.prefix_fraction is not None and not self.cfg.deterministic:
             prefix_n = max(1, int(math.ceil(self.cfg.prefix_fraction * self.n)))
+        # each view's chain, projection to loss: on main, or (view_streams >
+        # 1) on a stream per view, the views side by side; the backward and
+        # what sums over views in place (screen-gradient statistics, the
+        # per-view projection backward into the gradient array) run on main
+        # in view order, the backward of a view once its loss is queued
+        if par:
+            for k, (vb, v) in enumerate(zip(used, views)):
+                vs = self._view_stream(k)
+                if vb.dense:
+                    vs.wait_stream(main)
+                with torch.cuda.stream(vs):
+                    self._view_chain(k, vb, v, self.cams[v], sampled, prefix_n, vs)
+                while len(self._done) <= k:
+                    self._done.append(torch.cuda.Event())
+                self._done[k].record(vs)
         for k, (vb, v) in enumerate(zip(used, views)):
             cam = self.cams[v]
-            with st("project"):
-                vb.project(self.params, cam, self.rp)
-            if sampled[k] is not None:
-                main.wait_event(sampled[k])   # this view's samples (the binning and render need them)
-            with st("bin_sort"):
-                if prefix_n is not None:
-                    # the nearest Gaussians only; the first step of a slot waits to size its arrays
-                    vb.bin_sort_prefix(prefix_n, None, self.rp.alpha_min, wait=not vb.sized)
-                elif vb.sized:
-                    vb.bin_sort_async(None, self.rp.alpha_min)   # no host wait
-                else:
-                    vb.bin_sort(None, self.rp.alpha_min)         # sizes the pair arrays once per slot
-            if vb.two_part:
-                # prefix forward, the marked tiles' continuation lists, their forward
-                with st("render_fwd"):
-                    vb.render_fwd_prefix(self.rp, self.counters)
-                with st("bin_sort"):
-                    vb.continue_lists(self.rp.alpha_min, wait=not vb.sized)
-                with st("render_fwd"):
-                    vb.render_fwd_cont(self.rp, self.counters)
-                vb.sized = True
+            if par:
+                main.wait_event(self._done[k])
             else:
-                with st("render_fwd"):
-                    vb.render_fwd(self.rp, self.counters)
-            if not all_waited:
-                # the loss normalises by the step's total sample count
-                for ev in sampled:
-                    if ev is not None:
-                        main.wait_event(ev)
-                all_waited = True
-            with st("loss"):
-                vb.loss(self.gts[v], self.totals, self.lp)
-            if not vb.dense:
-                lossed.record(main)
-                side.wait_event(lossed)
-                with torch.cuda.stream(side):
-                    with st("ema_age"):
-                        vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
-                    if self.tiles is not None:
-                        self.tiles.learn(k, v, self.E[v], self.A[v], vb, cam)
+                self._view_chain(k, vb, v, cam, sampled, prefix_n, main)
             with st("render_bwd"):
                 # g2d was cleared by the projection; the density sums of sparse
                 # views join the backward's reduction
@@ -620,6 +612,58 @@ class Trainer:
         main.wait_stream(side)
         self._queue_count_check(used)
         return used
+
+    def _view_chain(self, k, vb, v, cam, sampled, prefix_n, vs):
+        """Projection, binning, forward and loss of the step's k-th view on
+        stream ``vs`` (the current stream)."""
+        st = self._stage
+        with st("project"):
+            vb.project(self.params, cam, self.rp)
+        if sampled[k] is not None:
+            vs.wait_event(sampled[k])   # this view's samples (the binning and render need them)
+        with st("bin_sort"):
+            if prefix_n is not None:
+                # the nearest Gaussians only; the first step of a slot waits to size its arrays
+                vb.bin_sort_prefix(prefix_n, None, self.rp.alpha_min, wait=not vb.sized)
+            elif vb.sized:
+                vb.bin_sort_async(None, self.rp.alpha_min)   # no host wait
+            else:
+                vb.bin_sort(None, self.rp.alpha_min)         # sizes the pair arrays once per slot
+        if vb.two_part:
+            # prefix forward, the marked tiles' continuation lists, their forward
+            with st("render_fwd"):
+                vb.render_fwd_prefix(self.rp, self.counters)
+            with st("bin_sort"):
+                vb.continue_lists(self.rp.alpha_min, wait=not vb.sized)
+            with st("render_fwd"):
+                vb.render_fwd_cont(self.rp, self.counters)
+            vb.sized = True
+        else:
+            with st("render_fwd"):
+                vb.render_fwd(self.rp, self.counters)
+        # the loss normalises by the step's total sample count
+        for ev in sampled:
+            if ev is not None:
+                vs.wait_event(ev)
+        with st("loss"):
+            vb.loss(self.gts[v], self.totals, self.lp)
+        if not vb.dense:
+            while len(self._lossed) <= k:
+                self._lossed.append(torch.cuda.Event())
+            self._lossed[k].record(vs)
+            self.side.wait_event(self._lossed[k])
+            with torch.cuda.stream(self.side):
+                with st("ema_age"):
+                    vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
+                if self.tiles is not None:
+                    self.tiles.learn(k, v, self.E[v], self.A[v], vb, cam)
+
+    def _view_stream(self, k: int):
+        """Stream of the k-th view's sampler and chain when views run side
+        by side (default priority; view_streams of them, reused round-robin)."""
+        while len(self._view_streams) < min(k + 1, self.cfg.view_streams):
+            self._view_streams.append(torch.cuda.Stream(device=self.dev))
+        return self._view_streams[k % self.cfg.view_streams]
 
     def _sample_stream(self, k: int):
         """Stream of the k-th view's sampler (default priority; a few reused

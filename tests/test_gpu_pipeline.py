@@ -126,7 +126,7 @@ def _dL_perturbations(fv, gt, s, P_step, tiles_step, rng):
     return out
 
 
-@pytest.mark.parametrize("fused", [False, True, "views", "views_prefix"])
+@pytest.mark.parametrize("fused", [False, True, "views", "views_prefix", "streams", "views_prefix_streams"])
 def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     """One four-view step against the oracle's step, element by element:
     samples bit for bit; rgb to 1e-5; the last composited Gaussian of every
@@ -145,16 +145,20 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
       and two FP32 ulps of the parameter.
     fused: False, the per-view projection backward then the update; True,
     the last view's fused with the update; "views", every view's in the
-    update's pass; "views_prefix", that with depth-prefix lists (10%)."""
+    update's pass; "views_prefix", that with depth-prefix lists (10%);
+    "streams", the per-view path with the views' chains on two streams
+    (four views, so each stream takes two in turn); "views_prefix_streams",
+    "views_prefix" with three view streams."""
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer
     p, cams, gts, E, A = c1_inputs
     n = p.shape[1]
     sp = SampleParams(n_pix=64, n_tiles_sel=64)
     ref = pipeline.train_step(p, np.zeros_like(p, np.float64), np.zeros_like(p, np.float64), cams, gts, E, A,
                               1, sp, RP, LossParams(), OptimParams(), seed=3)
-    cfg = StepConfig(rate_permille=250, n_tiles_sel=64, seed=3, fuse_optimizer=fused is not False,
-                     fuse_views=fused in ("views", "views_prefix"),
-                     prefix_fraction=0.1 if fused == "views_prefix" else None)
+    cfg = StepConfig(rate_permille=250, n_tiles_sel=64, seed=3, fuse_optimizer=fused not in (False, "streams"),
+                     fuse_views=fused in ("views", "views_prefix", "views_prefix_streams"),
+                     prefix_fraction=0.1 if fused in ("views_prefix", "views_prefix_streams") else None,
+                     view_streams={"streams": 2, "views_prefix_streams": 3}.get(fused, 1))
     Eg = [dev(e.view(np.int16)) for e in E]
     Ag = [dev(a.view(np.int16)) for a in A]
     tr = Trainer(dev(p), cams, [dev(g) for g in gts], cfg, E=Eg, A=Ag)
@@ -206,7 +210,7 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     assert np.array_equal(t_gpu[~ex], ref["touched"][~ex]) and ref["touched"].sum() > 2000
     keep = ~ex
     tol_g = 1e-4 * np.abs(ref["grad"]) + scale + 1e-30
-    if not fused:
+    if fused in (False, "streams"):
         g = host(tr.grad).astype(np.float64)
         for name, sl in GROUPS.items():
             assert_close(g[sl][:, keep], ref["grad"][sl][:, keep], 1e-4, (scale[sl] + 1e-30)[:, keep],

@@ -136,12 +136,13 @@ def test_prefix_lists_render_like_whole_lists(B, case, frac):
         assert n1 < 0.5 * np_w          # the prefix is the smaller part of the pairs
 
 
-def test_trainer_prefix_binning_matches_whole_lists(B):
+@pytest.mark.parametrize("streams", [1, 2])
+def test_trainer_prefix_binning_matches_whole_lists(B, streams):
     """Two sparse steps of the rasterizer-scaling scene over two views (the
     first sizing the arrays with host waits, the second queued without),
     the parameters reset to the same values before each: outputs and
     counters bit for bit and the second step's gradient as with whole
-    lists."""
+    lists; streams: the views' chains on that many streams."""
     from paper_2606_15924_amd.pipeline import StepConfig, Trainer, ViewBuffers
     p, cam = scene_scaling()
     cams = [cam, synth.look_at((2.0, -1.6, 1.4), fx=cam.fx, fy=cam.fy, width=cam.width, height=cam.height)]
@@ -157,7 +158,7 @@ def test_trainer_prefix_binning_matches_whole_lists(B):
     del vb
     res = []
     for frac in (None, 0.1):
-        cfg = StepConfig(rate_permille=200, fuse_optimizer=False, prefix_fraction=frac)
+        cfg = StepConfig(rate_permille=200, fuse_optimizer=False, prefix_fraction=frac, view_streams=streams)
         E = [torch.zeros((c.height, c.width), dtype=torch.int16, device="cuda") for c in cams]
         A = [torch.zeros((c.height, c.width), dtype=torch.int16, device="cuda") for c in cams]
         tr = Trainer(dev(p), cams, gts, cfg, E=E, A=A)
