@@ -251,17 +251,22 @@ int32_t tgs_bin_sort_async(const int32_t* rect, const float* splat, const float*
 
 /* Depth-prefix lists (an exact shortcut for the forward walk's early
  * stop): the lists of tgs_bin_sort_async restricted to the first `prefix`
- * Gaussians in (depth, id) order, i.e. the first part of every tile's
- * list.  A pixel whose walk stops (T_min) within its prefix composites as
+ * Gaussians in (depth, id) order (Gaussians with a non-empty rectangle,
+ * the others after them), i.e. the first part of every tile's list; only
+ * those are counted.  A pixel whose walk stops (T_min) within its prefix composites as
  * with the whole list; tgs_render_fwd_prefix marks the tiles where one does
  * not, tgs_bin_sort_continue_async lists the rest of those tiles' Gaussians
  * and tgs_render_fwd_cont redoes them over both parts, so the images,
  * counts and gradients equal those of the whole lists.  Arguments as
- * tgs_bin_sort_async except counts: [3] int64 device, counts[0] = the
- * lists' length, counts[1] = the pairs the prefix emits (the capacity it
- * needs), counts[2] = the pairs of the whole lists (counts[2] - counts[1]
- * bounds what a continuation can need).  The workspace keeps the depth
- * order for the continuation call; prefix >= n gives the whole lists. */
+ * tgs_bin_sort_async except touched (only the prefix's Gaussians with a
+ * pair are flagged) and counts: [3] int64 device, counts[0] = the lists'
+ * length, counts[1] = the pairs the prefix emits (the capacity it needs),
+ * counts[2] = an estimate of the whole lists' pairs for sizing a
+ * continuation: the prefix's pairs per Gaussian times the Gaussians with a
+ * rectangle (exact when the prefix holds them all; the nearest Gaussians
+ * cover the most tiles, so it tends to exceed the true count).  The
+ * workspace keeps the depth order for the continuation call; prefix >= n
+ * gives the whole lists. */
 int32_t tgs_bin_sort_prefix_async(const int32_t* rect, const float* splat, const float* depth, int64_t n,
                                   const int32_t* tile_slot, int32_t tiles_x, int32_t tiles_y, float alpha_min,
                                   int64_t prefix, uint64_t* keys, uint32_t* vals, int64_t capacity,

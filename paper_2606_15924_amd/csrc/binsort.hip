@@ -83,19 +83,6 @@ __global__ void __launch_bounds__(64) totals_kernel(const unsigned long long* __
   }
 }
 
-// Depth-prefix lists: the pairs of the first m Gaussians in depth order
-// are off[m] (the emission's need); the sort takes them when they fit.
-// (counts[3] keeps the whole lists' pair count.)
-__global__ void __launch_bounds__(64) prefix_total_kernel(const uint32_t* __restrict__ off, int64_t m,
-                                                          int64_t capacity, unsigned long long* __restrict__ counts,
-                                                          uint32_t* __restrict__ eff_total) {
-  if (threadIdx.x == 0) {
-    const unsigned long long t = off[m];
-    counts[1] = t;
-    *eff_total = t <= (unsigned long long)capacity ? (uint32_t)t : 0u;
-  }
-}
-
 // The prefix call's three counts: lists' length, pairs emitted, whole-list pairs.
 __global__ void __launch_bounds__(64) copy_counts3_kernel(const unsigned long long* __restrict__ src,
                                                           unsigned long long* __restrict__ dst) {
@@ -314,18 +301,26 @@ struct CountBatch {
   uint32_t kept[kWave], valid[kWave];
 };
 
+// ids == nullptr: Gaussian i of the index order (rect, depth by index),
+// writing the depth keys.  ids != nullptr: position i of the depth order
+// (rect is then the sorted rectangles, ids the Gaussians), writing only the
+// counts by position (emit_cnt) and the touched flags.
 __global__ void __launch_bounds__(kWave) count_kernel(
-    const int4* __restrict__ rect, const float4* __restrict__ splat, const float* __restrict__ depth, int64_t n,
-    const int32_t* __restrict__ tile_slot, int tiles_x, int tiles_y, double tau, double lia, uint32_t* __restrict__ dkeys,
-    uint32_t* __restrict__ dvals, uint32_t* __restrict__ emit_cnt, uint8_t* __restrict__ touched,
-    unsigned long long* __restrict__ totals) {
+    const int4* __restrict__ rect, const uint32_t* __restrict__ ids, const float4* __restrict__ splat,
+    const float* __restrict__ depth, int64_t n, const int32_t* __restrict__ tile_slot, int tiles_x, int tiles_y,
+    double tau, double lia, uint32_t* __restrict__ dkeys, uint32_t* __restrict__ dvals,
+    uint32_t* __restrict__ emit_cnt, uint8_t* __restrict__ touched, unsigned long long* __restrict__ totals) {
   __shared__ CountBatch cb;
   __shared__ uint64_t s_red[1];
   const int lane = lane_id();
   const int64_t i = (int64_t)blockIdx.x * kCountBatch + lane;
   const bool mine = lane < kCountBatch && i < n;
   int4 r = make_int4(0, 0, 0, 0);
-  if (mine) r = clamp_rect(rect[i], tiles_x, tiles_y);
+  uint32_t g = (uint32_t)i;
+  if (mine) {
+    r = clamp_rect(rect[i], tiles_x, tiles_y);
+    if (ids != nullptr) g = ids[i];
+  }
   const uint32_t rows = r.z > r.x ? (uint32_t)(r.w - r.y) : 0u;
   const uint32_t incl = wave_inclusive_scan_u32(rows);
   const uint32_t my_row0 = incl - rows;
@@ -334,7 +329,7 @@ __global__ void __launch_bounds__(kWave) count_kernel(
   cb.row0[lane] = my_row0;
   cb.kept[lane] = 0u;
   cb.valid[lane] = 0u;
-  if (rows > 0) cb.ell[lane] = load_row_ellipse(splat, i, tau, lia);
+  if (rows > 0) cb.ell[lane] = load_row_ellipse(splat, g, tau, lia);
   int carry = -1;
   for (uint32_t f0 = 0; f0 < n_rows; f0 += kWave) {
     cb.mark[lane] = -1;
@@ -365,10 +360,12 @@ __global__ void __launch_bounds__(kWave) count_kernel(
   __syncthreads();
   const uint32_t kept = cb.kept[lane], valid = cb.valid[lane];
   if (mine) {
-    dkeys[i] = valid > 0 ? __float_as_uint(depth[i]) : kCulledKey;
-    dvals[i] = (uint32_t)i;
+    if (ids == nullptr) {
+      dkeys[i] = valid > 0 ? __float_as_uint(depth[i]) : kCulledKey;
+      dvals[i] = (uint32_t)i;
+    }
     emit_cnt[i] = valid > 0 ? kept : 0u;  // every kept tile, valid or not, once the Gaussian has a pair
-    if (touched != nullptr && valid > 0) touched[i] = 1;
+    if (touched != nullptr && valid > 0) touched[g] = 1;
   }
   // 64-bit totals, spread over slots: [0] pairs in valid tiles, [1] all pairs
   const uint64_t v2[2] = {valid, valid > 0 ? kept : 0u};
@@ -377,6 +374,58 @@ __global__ void __launch_bounds__(kWave) count_kernel(
     block_exclusive_scan<kWave, uint64_t>(v2[k], s_red, &tot);
     if (lane == 0 && tot > 0)
       atomicAdd(&totals[k * TGS_COUNTER_SLOTS + (blockIdx.x & (TGS_COUNTER_SLOTS - 1))], (unsigned long long)tot);
+  }
+}
+
+// Depth keys of the depth-prefix call, before any count: a Gaussian with a
+// non-empty rectangle is keyed by its depth, the others sort last; the
+// number of keyed Gaussians goes to the 64-bit slots of row 2.
+__global__ void __launch_bounds__(256) key_kernel(const int4* __restrict__ rect, const float* __restrict__ depth,
+                                                  int64_t n, int tiles_x, int tiles_y, uint32_t* __restrict__ dkeys,
+                                                  uint32_t* __restrict__ dvals,
+                                                  unsigned long long* __restrict__ totals) {
+  __shared__ uint64_t s_red[1];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool keyed = false;
+  if (i < n) {
+    const int4 r = clamp_rect(rect[i], tiles_x, tiles_y);
+    keyed = r.z > r.x && r.w > r.y;
+    dkeys[i] = keyed ? __float_as_uint(depth[i]) : kCulledKey;
+    dvals[i] = (uint32_t)i;
+  }
+  uint64_t tot;
+  block_exclusive_scan<256, uint64_t>(keyed ? 1ull : 0ull, s_red, &tot);
+  if (threadIdx.x == 0 && tot > 0)
+    atomicAdd(&totals[2 * TGS_COUNTER_SLOTS + (blockIdx.x & (TGS_COUNTER_SLOTS - 1))], (unsigned long long)tot);
+}
+
+// The depth-prefix call's counts from the slots: counts[0] = pairs of the
+// prefix in valid tiles, counts[1] = its pairs (the capacity it needs; the
+// sort takes them when they fit), counts[3] = an estimate of the whole
+// lists' pairs for sizing a continuation: the prefix's pairs per Gaussian
+// times the keyed Gaussians (exact when the prefix holds them all; the
+// nearest Gaussians cover the most tiles, so it tends to exceed the count).
+__global__ void __launch_bounds__(64) prefix_totals_kernel(const unsigned long long* __restrict__ slots, int64_t m,
+                                                           int64_t capacity, unsigned long long* __restrict__ counts,
+                                                           uint32_t* __restrict__ eff_total) {
+  const int i = threadIdx.x;
+  unsigned long long v = 0, a = 0, k = 0;
+  for (int q = i; q < TGS_COUNTER_SLOTS; q += 64) {
+    v += slots[q];
+    a += slots[TGS_COUNTER_SLOTS + q];
+    k += slots[2 * TGS_COUNTER_SLOTS + q];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    v += __shfl_down(v, o, 64);
+    a += __shfl_down(a, o, 64);
+    k += __shfl_down(k, o, 64);
+  }
+  if (i == 0) {
+    counts[0] = v;
+    counts[1] = a;
+    const unsigned long long mk = (unsigned long long)(m < (int64_t)k ? m : (int64_t)k);
+    counts[3] = mk >= k || mk == 0 ? a : (unsigned long long)ceil((double)a * (double)k / (double)mk);
+    *eff_total = a <= (unsigned long long)capacity ? (uint32_t)a : 0u;
   }
 }
 
@@ -401,8 +450,8 @@ __global__ void __launch_bounds__(kWave) flag_rows_kernel(const int32_t* __restr
 }
 
 // Continuation counts: one wave per 64 Gaussians of the depth order from a
-// given rank on (their rectangles, ids and first-pass pair counts in that
-// order).  Per Gaussian: its kept pairs in the flagged tiles (tile map
+// given rank on (their rectangles, ids and, when known, first-pass pair
+// counts in that order).  Per Gaussian: its kept pairs in the flagged tiles (tile map
 // entry >= 0), by the same row spans.  Gaussians without pairs in the first
 // pass, or whose rectangle holds no flagged tile (two reads of the row
 // counts per rectangle row, when given), are skipped before their splat is
@@ -422,7 +471,7 @@ __global__ void __launch_bounds__(kWave) count_cont_kernel(
     if (k < m) cnt[k] = 0u;
     return;
   }
-  bool mine = k < m && cnt_sorted[k] > 0;
+  bool mine = k < m && (cnt_sorted == nullptr || cnt_sorted[k] > 0);
   int4 r = make_int4(0, 0, 0, 0);
   uint32_t g = 0;
   if (mine) {
@@ -804,7 +853,7 @@ __global__ void __launch_bounds__(kSortThreads) depth_pass_kernel(const uint32_t
       if (kLast) {
         o.ids_sorted[dst] = g;
         o.rect_sorted[dst] = clamp_rect(o.rect[g], o.tiles_x, o.tiles_y);
-        o.cnt_sorted[dst] = o.emit_cnt[g];
+        if (o.emit_cnt != nullptr) o.cnt_sorted[dst] = o.emit_cnt[g];
       } else {
         o.keys[dst] = kk;
         o.vals[dst] = g;
@@ -1028,7 +1077,7 @@ static SortWs layout(void* ws, int64_t n, int64_t capacity) {
   SortWs w;
   w.hstride = (int)depth_hstride(nn);
   const int64_t table_words = (int64_t)kDepthDigits * w.hstride;
-  const int64_t scalar_words = 2 * 2 * TGS_COUNTER_SLOTS;
+  const int64_t scalar_words = 3 * 2 * TGS_COUNTER_SLOTS;  // three rows of 64-bit slots
   w.zeroed_words = scalar_words + 4 * table_words;
   w.zeroed = (uint32_t*)take(sizeof(uint32_t) * w.zeroed_words);
   w.scalars = (unsigned long long*)w.zeroed;
@@ -1065,7 +1114,8 @@ static int bits_for(uint64_t max_value) {  // bits needed to represent 0..max_va
 // Stable LSD sort of the n depth keys with their ids (the count kernel has
 // filled the first pass's table); the last pass writes ids, rectangles and
 // pair counts in depth order.
-static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_x, int tiles_y, hipStream_t s) {
+static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_x, int tiles_y, hipStream_t s,
+                       bool gather_counts = true) {
   const unsigned nb = (unsigned)depth_blocks(n);
   int cur = 0;
   for (int p = 0; p < 4; ++p) {
@@ -1083,7 +1133,7 @@ static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_
     } else {
       o.ids_sorted = w.ids_sorted;
       o.rect = rect;
-      o.emit_cnt = w.emit_cnt;
+      o.emit_cnt = gather_counts ? w.emit_cnt : nullptr;
       o.rect_sorted = w.rect_sorted;
       o.cnt_sorted = w.cnt_sorted;
       o.tiles_x = tiles_x;
@@ -1160,20 +1210,36 @@ static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const flo
   // empty ranges and the zeroed workspace region (counters, table padding)
   hipLaunchKernelGGL(zero2_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t + w.zeroed_words, 256)), dim3(256),
                      0, s, ranges, 2 * (int64_t)n_t, w.zeroed, w.zeroed_words);
-  // counts and the pair total of the sort (both 0 until the totals land)
-  hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w.scalars, capacity, w.counts, w.eff_total);
-  if (n == 0) return hip_status(who);
-  hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kWave), 0, s,
-                     (const int4*)rect, (const float4*)splat, depth, n, tile_slot, tiles_x, tiles_y, tau, lia,
-                     w.dkeys[0], w.dvals[0], w.emit_cnt, touched, w.scalars);
-  hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w.scalars, capacity, w.counts, w.eff_total);
-  // (depth, id) order; Gaussians without pairs last
-  sort_depth(w, (uint32_t)n, (const int4*)rect, tiles_x, tiles_y, s);
-  // pair offsets (they wrap only past 2^32 pairs, where the capacity check has already set the total to 0)
-  exclusive_scan<uint32_t>(w.cnt_sorted, w.off, n, w.partials, s);
+  if (n == 0) {  // zero counts and pair total
+    hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w.scalars, capacity, w.counts, w.eff_total);
+    return hip_status(who);
+  }
   const bool pre = prefix >= 0;
   const int64_t m = pre ? std::min(prefix, n) : n;
-  if (pre) hipLaunchKernelGGL(prefix_total_kernel, dim3(1), dim3(64), 0, s, w.off, m, capacity, w.counts, w.eff_total);
+  if (!pre) {
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(n, kCountBatch)), dim3(kWave), 0, s,
+                       (const int4*)rect, (const uint32_t*)nullptr, (const float4*)splat, depth, n, tile_slot,
+                       tiles_x, tiles_y, tau, lia, w.dkeys[0], w.dvals[0], w.emit_cnt, touched, w.scalars);
+    hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w.scalars, capacity, w.counts, w.eff_total);
+    // (depth, id) order; Gaussians without pairs last
+    sort_depth(w, (uint32_t)n, (const int4*)rect, tiles_x, tiles_y, s);
+    // pair offsets (they wrap only past 2^32 pairs, where the capacity check has already set the total to 0)
+    exclusive_scan<uint32_t>(w.cnt_sorted, w.off, n, w.partials, s);
+  } else {
+    // depth-prefix lists: (depth, id) order of the Gaussians with a
+    // rectangle (the others last), then the counts of the first m only
+    hipLaunchKernelGGL(key_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, (const int4*)rect, depth, n,
+                       tiles_x, tiles_y, w.dkeys[0], w.dvals[0], w.scalars);
+    sort_depth(w, (uint32_t)n, (const int4*)rect, tiles_x, tiles_y, s, false);
+    if (m > 0)
+      hipLaunchKernelGGL(count_kernel, dim3((unsigned)ceil_div(m, kCountBatch)), dim3(kWave), 0, s,
+                         (const int4*)w.rect_sorted, (const uint32_t*)w.ids_sorted, (const float4*)splat, depth, m,
+                         tile_slot, tiles_x, tiles_y, tau, lia, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                         w.cnt_sorted, touched, w.scalars);
+    hipLaunchKernelGGL(prefix_totals_kernel, dim3(1), dim3(64), 0, s, w.scalars, m, capacity, w.counts,
+                       w.eff_total);
+    exclusive_scan<uint32_t>(w.cnt_sorted, w.off, m, w.partials, s);
+  }
   if (capacity == 0) return hip_status(who);
   const uint32_t bound = (uint32_t)capacity;
   const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
@@ -1214,7 +1280,7 @@ static int32_t continue_queue(const float* splat, int64_t n, const int32_t* flag
                        rowc);
   if (m > 0)
     hipLaunchKernelGGL(count_cont_kernel, dim3((unsigned)ceil_div(m, kCountBatch)), dim3(kWave), 0, s,
-                       w1.rect_sorted + prefix, w1.ids_sorted + prefix, w1.cnt_sorted + prefix, m,
+                       w1.rect_sorted + prefix, w1.ids_sorted + prefix, (const uint32_t*)nullptr, m,
                        (const float4*)splat, flag_slot, n_flagged, (const uint32_t*)rowc, tiles_x, tiles_y, tau, lia,
                        w2.emit_cnt, w2.scalars);
   hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w2.scalars, capacity2, w2.counts, w2.eff_total);

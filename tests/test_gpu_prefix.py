@@ -32,10 +32,11 @@ def host(t):
     return t.cpu().numpy()
 
 
-def _depth_rank(vals, depth):
-    """Rank of every listed Gaussian in (depth bits, id) order among the
-    Gaussians that have pairs (the binning puts the others last)."""
-    ids = np.unique(vals)
+def _depth_rank(rect, depth):
+    """Rank of every Gaussian with a non-empty rectangle in (depth bits, id)
+    order among those Gaussians (the binning puts the others last)."""
+    r = rect.astype(np.int64)
+    ids = np.nonzero((r[:, 2] > r[:, 0]) & (r[:, 3] > r[:, 1]))[0]
     bits = depth.view(np.uint32)[ids].astype(np.int64)
     order = ids[np.lexsort((ids, bits))]
     rank = np.full(depth.size, -1, dtype=np.int64)
@@ -110,7 +111,7 @@ def test_prefix_lists_render_like_whole_lists(B, case, frac):
     # the lists: the first part is the depth prefix of every whole list,
     # the continuation the rest of every marked tile's list
     depth = host(vb.depth)
-    rank = _depth_rank(vals_w[:np_w].astype(np.int64), depth)
+    rank = _depth_rank(host(vb.rect), depth)
     t_w, _ = _tiles_of(rng_w, np_w)
     vw = vals_w[:np_w].astype(np.int64)
     keep = rank[vw] < m
