@@ -25,6 +25,13 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
     double* __restrict__ rec64) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  // the SH coefficients are loaded with the geometry rows, before anything
+  // depends on them (one round trip to memory; culled Gaussians read them
+  // for nothing, a small share of the traffic)
+  constexpr int nk = (kDeg + 1) * (kDeg + 1);
+  PT cf[3 * nk];
+#pragma unroll
+  for (int q = 0; q < 3 * nk; ++q) cf[q] = params[(int64_t)(11 + q) * n + i];
   if (g2d_clear != nullptr)
     for (int k = 0; k < 9; ++k) g2d_clear[i * 9 + k] = 0.f;
   Geom g;
@@ -46,13 +53,6 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
                dz = g.mu[2] - cam.center[2];
   const double dn = sqrt(dx * dx + dy * dy + dz * dz);
   const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
-  // the degree is a template argument, so all coefficient loads are
-  // independent and issued together
-  constexpr int nk = (kDeg + 1) * (kDeg + 1);
-  PT cf[3 * nk];
-#pragma unroll
-  for (int q = 0; q < 3 * nk; ++q) cf[q] = params[(int64_t)(11 + q) * n + i];
-  __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the SH arithmetic
   double rgb[3] = {0.5, 0.5, 0.5};
 #pragma unroll
   for (int k = 0; k < nk; ++k) {

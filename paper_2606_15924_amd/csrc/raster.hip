@@ -418,7 +418,9 @@ __global__ void __launch_bounds__(kBlock) render_bwd_kernel(RasterArgs a,
   __shared__ float4 s_app[kBlock];
   __shared__ float4 s_con[kBlock];  // conic a, b, c (natural units), blue
   __shared__ uint32_t s_gid[kBlock];
-  const int slot = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
+  // the last chunk (the rest of the list, the longest walks) is dispatched
+  // first, so its workgroups run beside the fixed-length chunks
+  const int slot = blockIdx.x, chunk = (int)gridDim.y - 1 - (int)blockIdx.y, tid = threadIdx.x;
   const int tile = kDense ? slot : a.valid_tiles[slot];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const TileList L = tile_list(a, tile);
@@ -568,7 +570,9 @@ __global__ void __launch_bounds__(kBlock) render_accum_kernel(RasterArgs a, cons
   __shared__ float s_opa[kBlock];
   __shared__ float s_cc[kBlock];
   __shared__ uint32_t s_gid[kBlock];
-  const int slot = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
+  // the last chunk (the rest of the list, the longest walks) is dispatched
+  // first, so its workgroups run beside the fixed-length chunks
+  const int slot = blockIdx.x, chunk = (int)gridDim.y - 1 - (int)blockIdx.y, tid = threadIdx.x;
   const int tile = kDense ? slot : a.valid_tiles[slot];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const TileList L = tile_list(a, tile);
