@@ -343,10 +343,11 @@ __device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float* __r
   const float r0 = row_sum16(swap_sum16(p01, p23));
   const float r1 = row_sum16(swap_sum16(p45, p67));
   const float r2 = row_sum16(swap_sum16(p8, 0.f));
-  if (sl.field >= 0) {
-    const float val = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : r2);
-    if (val != 0.f) unsafeAtomicAdd(&dst[sl.field], val);
-  }
+  float val = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : r2);
+  // every lane takes its sum here, with the whole wave active, so the last
+  // DPP step stays one fused add instead of a move out of the branch below
+  asm volatile("" : "+v"(val));
+  if (sl.field >= 0 && val != 0.f) unsafeAtomicAdd(&dst[sl.field], val);
 }
 
 // The same nine wave sums, stored (not added) to dst[0..8]: the
@@ -361,7 +362,9 @@ __device__ __forceinline__ void wave_sum9_store(const float (&v)[9], float* __re
   const float r0 = row_sum16(swap_sum16(p01, p23));
   const float r1 = row_sum16(swap_sum16(p45, p67));
   const float r2 = row_sum16(swap_sum16(p8, 0.f));
-  if (sl.field >= 0) dst[sl.field] = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : r2);
+  float val = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : r2);
+  asm volatile("" : "+v"(val));  // as in wave_sum9_atomic
+  if (sl.field >= 0) dst[sl.field] = val;
 }
 
 // The nine gradient sums plus the four density-control sums (e w, w, D w
@@ -383,12 +386,11 @@ __device__ __forceinline__ void wave_sum13_atomic(const float (&v)[13], float* _
   const float r1 = row_sum16(swap_sum16(p45, p67));
   const float r2 = row_sum16(swap_sum16(p89, pab));
   const float r3 = row_sum16(swap_sum16(pc, 0.f));
-  if (sl.field >= 0) {
-    const float val = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : (sl.which == 2 ? r2 : r3));
-    if (val != 0.f) {
-      if (sl.field < 9) unsafeAtomicAdd(&dst[sl.field], val);
-      else if (gid < (uint32_t)n) unsafeAtomicAdd(&stats[(int64_t)gid * 4 + (sl.field - 9)], val);
-    }
+  float val = sl.which == 0 ? r0 : (sl.which == 1 ? r1 : (sl.which == 2 ? r2 : r3));
+  asm volatile("" : "+v"(val));  // as in wave_sum9_atomic
+  if (sl.field >= 0 && val != 0.f) {
+    if (sl.field < 9) unsafeAtomicAdd(&dst[sl.field], val);
+    else if (gid < (uint32_t)n) unsafeAtomicAdd(&stats[(int64_t)gid * 4 + (sl.field - 9)], val);
   }
 }
 
@@ -639,7 +641,8 @@ __global__ void __launch_bounds__(kBlock) render_accum_kernel(RasterArgs a, cons
           const float dist = __builtin_sqrtf(fmaxf(-kTwoLn2 * pw[u], 0.f));
           const float p01 = swap_sum32(e * w, w);
           const float p2 = swap_sum32(dist * w, 0.f);
-          const float r = row_sum16(swap_sum16(p01, p2));
+          float r = row_sum16(swap_sum16(p01, p2));
+          asm volatile("" : "+v"(r));  // the whole row sum with the whole wave active
           const uint32_t gid = __builtin_amdgcn_readfirstlane(s_gid[j + u]);  // uniform
           if (field >= 0 && r != 0.f && gid < (uint32_t)n) unsafeAtomicAdd(&stats[(int64_t)gid * 4 + field], r);
         }

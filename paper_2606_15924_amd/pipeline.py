@@ -450,7 +450,8 @@ class Trainer:
         self._sample_streams: list = []
         self._view_streams: list = []
         self._lossed: list = []            # per view slot: its loss (the error maps' update waits)
-        self._done: list = []              # per view slot: its backward (with view streams)
+        self._done: list = []              # per view slot: its loss (with view streams)
+        self._cleared = None               # main after a step's clears (with view streams)
         self._pending: list = []   # (event, pinned counts, [(view buffers, capacity)]) per step
 
     def _stage(self, name):
@@ -535,12 +536,49 @@ class Trainer:
                 self.totals[0] += self.cams[v].width * self.cams[v].height
                 self.totals[1] += vb.n_t
         par = self.cfg.view_streams > 1
-        sampled = []
+        prefix_n = None
+        if self.cfg.prefix_fraction is not None and not self.cfg.deterministic:
+            prefix_n = max(1, int(math.ceil(self.cfg.prefix_fraction * self.n)))
+        sampled: list = []   # filled below, read by the chains' later stages
+        S = self.cfg.view_streams
+
+        def chains_of(g0):
+            # the view streams wait for the previous step and this step's
+            # clears (the _cleared event), not for the samplers queued on main
+            out = []
+            for k in range(g0, min(g0 + S, len(used))):
+                vs = self._view_stream(k)
+                vs.wait_event(self._cleared)
+                while len(self._done) <= k:
+                    self._done.append(torch.cuda.Event())
+                out.append((vs, self._view_chain(k, used[k], views[k], self.cams[views[k]], sampled, prefix_n, vs,
+                                                 self._done[k])))
+            return out
+
+        def advance(chains, once=False):
+            while chains:
+                for c in list(chains):
+                    with torch.cuda.stream(c[0]):
+                        if next(c[1], StopIteration) is StopIteration:
+                            chains.remove(c)
+                if once:
+                    return
+
+        first = []
+        if par:
+            if self._cleared is None:
+                self._cleared = torch.cuda.Event()
+            self._cleared.record(main)
+            # the first views' projections are queued before the samplers
+            first = chains_of(0)
+            advance(first, once=True)
         for k, (vb, v) in enumerate(zip(used, views)):
             if vb.dense:
                 sampled.append(None)
                 continue
-            ss = self._view_stream(k) if par else self._sample_stream(k)
+            # views side by side: the samplers run on main (idle until the
+            # first backward) beside the projections
+            ss = main if par else self._sample_stream(k)
             ss.wait_stream(main)
             with torch.cuda.stream(ss):
                 cam = self.cams[v]
@@ -554,30 +592,25 @@ class Trainer:
                 ev = self._sampled[k]
                 ev.record(ss)
             sampled.append(ev)
-        prefix_n = None
-        if self.cfg.prefix_fraction is not None and not self.cfg.deterministic:
-            prefix_n = max(1, int(math.ceil(self.cfg.prefix_fraction * self.n)))
         # each view's chain, projection to loss: on main, or (view_streams >
         # 1) on a stream per view, the views side by side; the backward and
         # what sums over views in place (screen-gradient statistics, the
         # per-view projection backward into the gradient array) run on main
         # in view order, the backward of a view once its loss is queued
         if par:
-            for k, (vb, v) in enumerate(zip(used, views)):
-                vs = self._view_stream(k)
-                if vb.dense:
-                    vs.wait_stream(main)
-                with torch.cuda.stream(vs):
-                    self._view_chain(k, vb, v, self.cams[v], sampled, prefix_n, vs)
-                while len(self._done) <= k:
-                    self._done.append(torch.cuda.Event())
-                self._done[k].record(vs)
+            # enqueued breadth first, a stage of every view in turn, so each
+            # stream has work queued soon after the step starts (views that
+            # share a stream go in consecutive rounds)
+            advance(first)
+            for g0 in range(S, len(used), S):
+                advance(chains_of(g0))
         for k, (vb, v) in enumerate(zip(used, views)):
             cam = self.cams[v]
             if par:
                 main.wait_event(self._done[k])
             else:
-                self._view_chain(k, vb, v, cam, sampled, prefix_n, main)
+                for _ in self._view_chain(k, vb, v, cam, sampled, prefix_n, main):
+                    pass
             with st("render_bwd"):
                 # g2d was cleared by the projection; the density sums of sparse
                 # views join the backward's reduction
@@ -610,17 +643,26 @@ class Trainer:
             with st("optimizer"):
                 B.tgs_optimizer_step(self.params, self.grad, self.m, self.v, self.n, self.touched, self.op, t)
         main.wait_stream(side)
+        if par:
+            for vs in self._view_streams:
+                main.wait_stream(vs)   # their error-map updates, before the next step samples
         self._queue_count_check(used)
         return used
 
-    def _view_chain(self, k, vb, v, cam, sampled, prefix_n, vs):
+    def _view_chain(self, k, vb, v, cam, sampled, prefix_n, vs, done=None):
         """Projection, binning, forward and loss of the step's k-th view on
-        stream ``vs`` (the current stream)."""
+        stream ``vs`` (the current stream).  With ``done`` (views side by
+        side) the event is recorded after the loss and the error maps'
+        update follows on ``vs`` itself: a wait queued on the side stream
+        would hold up whatever view stream shares its hardware queue.  A
+        generator: it yields after each stage, with the stream set by the
+        caller around every resumption."""
         st = self._stage
         with st("project"):
             vb.project(self.params, cam, self.rp)
-        if sampled[k] is not None:
-            vs.wait_event(sampled[k])   # this view's samples (the binning and render need them)
+        yield
+        if sampled[k] is not None and vb.bin_sort_needs_samples():
+            vs.wait_event(sampled[k])   # binning keeps the sampled tiles only
         with st("bin_sort"):
             if prefix_n is not None:
                 # the nearest Gaussians only; the first step of a slot waits to size its arrays
@@ -629,25 +671,36 @@ class Trainer:
                 vb.bin_sort_async(None, self.rp.alpha_min)   # no host wait
             else:
                 vb.bin_sort(None, self.rp.alpha_min)         # sizes the pair arrays once per slot
+        yield
+        if sampled[k] is not None:
+            vs.wait_event(sampled[k])   # the forward renders this view's samples
         if vb.two_part:
             # prefix forward, the marked tiles' continuation lists, their forward
             with st("render_fwd"):
                 vb.render_fwd_prefix(self.rp, self.counters)
+            yield
             with st("bin_sort"):
                 vb.continue_lists(self.rp.alpha_min, wait=not vb.sized)
+            yield
             with st("render_fwd"):
                 vb.render_fwd_cont(self.rp, self.counters)
             vb.sized = True
         else:
             with st("render_fwd"):
                 vb.render_fwd(self.rp, self.counters)
+        yield
         # the loss normalises by the step's total sample count
         for ev in sampled:
             if ev is not None:
                 vs.wait_event(ev)
         with st("loss"):
             vb.loss(self.gts[v], self.totals, self.lp)
-        if not vb.dense:
+        if done is not None:
+            done.record(vs)
+        if not vb.dense and done is not None and self.tiles is None:
+            with st("ema_age"):
+                vb.ema_age(self.E[v], self.A[v], self.cfg.beta)
+        elif not vb.dense:
             while len(self._lossed) <= k:
                 self._lossed.append(torch.cuda.Event())
             self._lossed[k].record(vs)
