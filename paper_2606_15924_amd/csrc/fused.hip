@@ -212,6 +212,35 @@ struct ViewSet {
 // its rows, and forms its share of the mean's gradient through u:
 // (I - u u^T) dL/du / |mu - centre| per view, summed in FP64.  The block
 // adds the three shares in group order and stores the sum.
+// The update touches few Gaussians (those composited at a sample: ~6% of
+// 1.5M in the full step, spread at random), so a wave over 64 consecutive
+// Gaussians would run its FP64 work for a handful of live lanes.  A
+// workgroup therefore takes a window of kWindow consecutive Gaussians,
+// lists the touched ones in LDS (ballots over the window's flags, in
+// order) and gives each wave lane one listed Gaussian, 64 at a time.  The
+// window's rows span 16 cache lines each, so its loads touch the lines a
+// streaming pass would, with a fraction of the waves.
+constexpr int kWindow = 512;
+
+// The touched Gaussians of [w0, w0 + kWindow) as offsets from w0, in
+// order, into lds[0..c); returns c (wave-uniform).  Every Gaussian when
+// touched is null.  Called by one whole wave.
+__device__ __forceinline__ int window_list(const uint8_t* __restrict__ touched, int64_t n, int64_t w0,
+                                           uint16_t* __restrict__ lds) {
+  const int lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < kWindow / kWave; ++r) {
+    const int64_t i = w0 + r * kWave + lane;
+    const bool t = i < n && (touched == nullptr || touched[i] != 0);
+    const uint64_t mask = __ballot(t);
+    if (t) lds[c + __popcll(mask & below)] = (uint16_t)(r * kWave + lane);
+    c += __popcll(mask);
+  }
+  return c;
+}
+
 constexpr int kShGroups = 3;
 
 template <int kDeg, int kGrp>
@@ -281,23 +310,29 @@ __global__ void __launch_bounds__(kShGroups * kWave) sh_rest_views_kernel(float*
                                                                            const uint8_t* __restrict__ touched,
                                                                            OptArgs o, double* __restrict__ dmu_out) {
   __shared__ double share[kShGroups - 1][3][kWave];
+  __shared__ uint16_t wl[kShGroups][kWindow];  // each wave lists the window itself (no barrier)
   const int grp = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
-  const int64_t i = (int64_t)blockIdx.x * kWave + lane;
-  // untouched: parameters and moments stay
-  const bool live = i < n && (touched == nullptr || touched[i] != 0);
-  double dmu[3] = {0.0, 0.0, 0.0};
-  if (grp == 0)
-    sh_group_views<kDeg, 0>(params, n, vs, m, v, live, i, o, dmu);
-  else if (grp == 1)
-    sh_group_views<kDeg, 1>(params, n, vs, m, v, live, i, o, dmu);
-  else
-    sh_group_views<kDeg, 2>(params, n, vs, m, v, live, i, o, dmu);
-  if (grp > 0)
-    for (int k = 0; k < 3; ++k) share[grp - 1][k][lane] = dmu[k];
-  __syncthreads();
-  if (grp == 0 && live)
-    for (int k = 0; k < 3; ++k) dmu_out[i * 3 + k] = (dmu[k] + share[0][k][lane]) + share[1][k][lane];
+  const int64_t w0 = (int64_t)blockIdx.x * kWindow;
+  const int c = window_list(touched, n, w0, wl[grp]);  // the same count in every wave
+  for (int g = 0; g < c; g += kWave) {
+    // untouched Gaussians are not listed: their parameters and moments stay
+    const bool live = g + lane < c;
+    const int64_t i = live ? w0 + wl[grp][g + lane] : 0;
+    double dmu[3] = {0.0, 0.0, 0.0};
+    if (grp == 0)
+      sh_group_views<kDeg, 0>(params, n, vs, m, v, live, i, o, dmu);
+    else if (grp == 1)
+      sh_group_views<kDeg, 1>(params, n, vs, m, v, live, i, o, dmu);
+    else
+      sh_group_views<kDeg, 2>(params, n, vs, m, v, live, i, o, dmu);
+    if (grp > 0)
+      for (int k = 0; k < 3; ++k) share[grp - 1][k][lane] = dmu[k];
+    __syncthreads();
+    if (grp == 0 && live)
+      for (int k = 0; k < 3; ++k) dmu_out[i * 3 + k] = (dmu[k] + share[0][k][lane]) + share[1][k][lane];
+    __syncthreads();  // the shares are read before the next group writes them
+  }
 }
 
 // Rows 0-13 (mean, log-scale, quaternion, opacity, SH DC) of one Gaussian
@@ -452,13 +487,24 @@ __device__ __forceinline__ void geom_views_grad(const float* params, int64_t n, 
   for (int ch = 0; ch < 3; ++ch) gr[11 + ch] = kC0 * dc[ch];
 }
 
+__device__ __forceinline__ void geom_lm_views_one(float* params, int64_t n, const ViewSet& vs, double dil,
+                                                  float* __restrict__ m, float* __restrict__ v, const OptArgs& o,
+                                                  const double* __restrict__ dmu_sh, int64_t i);
+
 __global__ void __launch_bounds__(64) geom_lm_views_kernel(float* params, int64_t n, ViewSet vs, double dil,
                                                            float* __restrict__ m, float* __restrict__ v,
                                                            const uint8_t* __restrict__ touched, OptArgs o,
                                                            const double* __restrict__ dmu_sh) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (touched != nullptr && touched[i] == 0) return;
+  __shared__ uint16_t wl[kWindow];
+  const int64_t w0 = (int64_t)blockIdx.x * kWindow;
+  const int c = window_list(touched, n, w0, wl);
+  for (int g = 0; g < c; g += kWave)
+    if (g + (int)threadIdx.x < c) geom_lm_views_one(params, n, vs, dil, m, v, o, dmu_sh, w0 + wl[g + threadIdx.x]);
+}
+
+__device__ __forceinline__ void geom_lm_views_one(float* params, int64_t n, const ViewSet& vs, double dil,
+                                                  float* __restrict__ m, float* __restrict__ v, const OptArgs& o,
+                                                  const double* __restrict__ dmu_sh, int64_t i) {
   const double dsh[3] = {dmu_sh[i * 3], dmu_sh[i * 3 + 1], dmu_sh[i * 3 + 2]};
   double gsum[kGeoRows];
   geom_views_grad(params, n, vs, i, dil, dsh, gsum);
@@ -548,7 +594,7 @@ extern "C" int32_t tgs_project_bwd_optimizer_step_views(float* params, int64_t n
   TGS_REQUIRE(ws_bytes >= need, "%s: workspace %zu bytes < %zu", who, ws_bytes, need);
   TGS_REQUIRE(((uintptr_t)ws & 7) == 0, "%s: workspace must be 8-byte aligned", who);
   hipStream_t s = as_stream(stream);
-  const dim3 grid((unsigned)ceil_div(n, kWave));
+  const dim3 grid((unsigned)ceil_div(n, kWindow));
 #define TGS_SH_VIEWS(D)                                                                                        \
   hipLaunchKernelGGL(sh_rest_views_kernel<D>, grid, dim3(kShGroups * kWave), 0, s, params, n, vs, m, v, touched, \
                      o, (double*)ws)
@@ -559,8 +605,8 @@ extern "C" int32_t tgs_project_bwd_optimizer_step_views(float* params, int64_t n
     default: TGS_SH_VIEWS(3); break;
   }
 #undef TGS_SH_VIEWS
-  hipLaunchKernelGGL(geom_lm_views_kernel, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, s, params, n, vs,
-                     (double)rp->dilation, m, v, touched, o, (const double*)ws);
+  hipLaunchKernelGGL(geom_lm_views_kernel, grid, dim3(kWave), 0, s, params, n, vs, (double)rp->dilation, m, v,
+                     touched, o, (const double*)ws);
   return hip_status(who);
 }
 
