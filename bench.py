@@ -818,6 +818,8 @@ def main():
     ap.add_argument("--no-density", action="store_true", help="skip the density-control measurement")
     ap.add_argument("--only-headline", action="store_true", help="the K=3 sparse full step alone (profiling)")
     ap.add_argument("--no-prefix", action="store_true", help="whole lists instead of depth-prefix lists")
+    ap.add_argument("--view-streams", type=int, default=None,
+                    help="streams the full step's view chains run on (default 3; 1: all on one stream)")
     ap.add_argument("--no-large", action="store_true", help="skip the large-scene run")
     ap.add_argument("--only-large", action="store_true", help="the large-scene run alone (prints its record)")
     ap.add_argument("--large-steps", type=int, default=LARGE_STEPS, help="timed steps of the large-scene run")
@@ -850,8 +852,10 @@ def main():
     if args.only_headline:
         global FULL_K
         FULL_K = (HEADLINE_K,)
-    global PREFIX
+    global PREFIX, FULL_VIEW_STREAMS
     PREFIX = None if args.no_prefix else FULL_PREFIX
+    if args.view_streams is not None:
+        FULL_VIEW_STREAMS = max(1, args.view_streams)
     p_full, cams, full = full_step(dev, args.steps, args.warmup,
                                    with_dense=not (args.no_dense or args.only_headline), prefix=PREFIX)
     head = full[(HEADLINE_K, "sparse")]

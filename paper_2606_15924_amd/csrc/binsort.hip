@@ -449,20 +449,53 @@ __global__ void __launch_bounds__(kWave) flag_rows_kernel(const int32_t* __restr
   }
 }
 
+// The summed-area table of the flagged tiles: sat[y * (tiles_x + 1) + x] =
+// flagged tiles in rows < y and columns < x, (tiles_y + 1) x (tiles_x + 1)
+// entries built in LDS by one workgroup (row scans by the waves, then a
+// column pass per thread).  Nothing to do when no tile is flagged.
+constexpr int kSatWords = 12288;  // LDS words: grids up to this many (tiles_x + 1) (tiles_y + 1)
+
+__global__ void __launch_bounds__(1024) flag_sat_kernel(const int32_t* __restrict__ flag_slot, int tiles_x,
+                                                        int tiles_y, const uint32_t* __restrict__ n_flagged,
+                                                        uint32_t* __restrict__ sat) {
+  __shared__ uint32_t t[kSatWords];
+  if (n_flagged != nullptr && *n_flagged == 0u) return;  // workgroup-uniform
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+  const int W1 = tiles_x + 1, words = (tiles_y + 1) * W1;
+  for (int x = tid; x < W1; x += 1024) t[x] = 0u;
+  for (int y = wave; y < tiles_y; y += 1024 / kWave) {
+    uint32_t carry = 0;
+    if (lane == 0) t[(y + 1) * W1] = 0u;
+    for (int x0 = 0; x0 < tiles_x; x0 += kWave) {
+      const int x = x0 + lane;
+      const uint32_t f = x < tiles_x && flag_slot[(int64_t)y * tiles_x + x] >= 0 ? 1u : 0u;
+      const uint32_t incl = carry + wave_inclusive_scan_u32(f);
+      if (x < tiles_x) t[(y + 1) * W1 + x + 1] = incl;
+      carry = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    }
+  }
+  __syncthreads();
+  for (int x = tid; x < W1; x += 1024)
+    for (int y = 1; y <= tiles_y; ++y) t[y * W1 + x] += t[(y - 1) * W1 + x];
+  __syncthreads();
+  for (int i = tid; i < words; i += 1024) sat[i] = t[i];
+}
+
 // Continuation counts: one wave per 64 Gaussians of the depth order from a
 // given rank on (their rectangles, ids and, when known, first-pass pair
 // counts in that order).  Per Gaussian: its kept pairs in the flagged tiles (tile map
 // entry >= 0), by the same row spans.  Gaussians without pairs in the first
-// pass, or whose rectangle holds no flagged tile (two reads of the row
-// counts per rectangle row, when given), are skipped before their splat is
-// read; the whole call is skipped when no tile is flagged (every count 0).
+// pass, or whose rectangle holds no flagged tile (four reads of the
+// summed-area table, or two reads of the row counts per rectangle row, when
+// given), are skipped before their splat is read; the whole call is skipped
+// when no tile is flagged (every count 0).
 // The sum goes to the 64-bit totals (both slots).
 __global__ void __launch_bounds__(kWave) count_cont_kernel(
     const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ ids_sorted,
     const uint32_t* __restrict__ cnt_sorted, int64_t m, const float4* __restrict__ splat,
     const int32_t* __restrict__ flag_slot, const uint32_t* __restrict__ n_flagged,
-    const uint32_t* __restrict__ rowc, int tiles_x, int tiles_y, double tau, double lia,
-    uint32_t* __restrict__ cnt, unsigned long long* __restrict__ totals) {
+    const uint32_t* __restrict__ rowc, const uint32_t* __restrict__ sat, int tiles_x, int tiles_y, double tau,
+    double lia, uint32_t* __restrict__ cnt, unsigned long long* __restrict__ totals) {
   __shared__ CountBatch cb;
   __shared__ uint64_t s_red[1];
   const int lane = lane_id();
@@ -476,10 +509,13 @@ __global__ void __launch_bounds__(kWave) count_cont_kernel(
   uint32_t g = 0;
   if (mine) {
     r = clamp_rect(rect_sorted[k], tiles_x, tiles_y);
-    if (rowc != nullptr) {
+    if (sat != nullptr || rowc != nullptr) {
       const int64_t W1 = tiles_x + 1;
       uint32_t f = 0u;
-      for (int y = r.y; y < r.w && f == 0u; ++y) f = rowc[y * W1 + r.z] - rowc[y * W1 + r.x];
+      if (sat != nullptr)
+        f = (sat[r.w * W1 + r.z] - sat[r.y * W1 + r.z]) - (sat[r.w * W1 + r.x] - sat[r.y * W1 + r.x]);
+      else
+        for (int y = r.y; y < r.w && f == 0u; ++y) f = rowc[y * W1 + r.z] - rowc[y * W1 + r.x];
       if (f == 0u) {
         mine = false;
         r = make_int4(0, 0, 0, 0);
@@ -1271,18 +1307,22 @@ static int32_t continue_queue(const float* splat, int64_t n, const int32_t* flag
   hipLaunchKernelGGL(zero2_u32_kernel, dim3((unsigned)ceil_div(2 * (int64_t)n_t + w2.zeroed_words, 256)), dim3(256),
                      0, s, ranges2, 2 * (int64_t)n_t, w2.zeroed, w2.zeroed_words);
   const int64_t m = n - std::min(prefix, n);
-  // the flagged tiles' per-row running counts in the pair-sort histogram
-  // (free until the sort), when they fit
+  // the flagged tiles' summed-area table (or, for larger grids, per-row
+  // running counts) in the pair-sort histogram (free until the sort)
+  const int64_t sat_words = (int64_t)(tiles_x + 1) * (tiles_y + 1);
   const int64_t rc_words = (int64_t)(tiles_x + 1) * tiles_y;
-  uint32_t* rowc = rc_words <= 256 * 1024 ? w2.hist : nullptr;
+  uint32_t* sat = sat_words <= kSatWords ? w2.hist : nullptr;
+  uint32_t* rowc = sat == nullptr && rc_words <= 256 * 1024 ? w2.hist : nullptr;
+  if (m > 0 && sat != nullptr)
+    hipLaunchKernelGGL(flag_sat_kernel, dim3(1), dim3(1024), 0, s, flag_slot, tiles_x, tiles_y, n_flagged, sat);
   if (m > 0 && rowc != nullptr)
     hipLaunchKernelGGL(flag_rows_kernel, dim3((unsigned)tiles_y), dim3(kWave), 0, s, flag_slot, tiles_x, n_flagged,
                        rowc);
   if (m > 0)
     hipLaunchKernelGGL(count_cont_kernel, dim3((unsigned)ceil_div(m, kCountBatch)), dim3(kWave), 0, s,
                        w1.rect_sorted + prefix, w1.ids_sorted + prefix, (const uint32_t*)nullptr, m,
-                       (const float4*)splat, flag_slot, n_flagged, (const uint32_t*)rowc, tiles_x, tiles_y, tau, lia,
-                       w2.emit_cnt, w2.scalars);
+                       (const float4*)splat, flag_slot, n_flagged, (const uint32_t*)rowc, (const uint32_t*)sat,
+                       tiles_x, tiles_y, tau, lia, w2.emit_cnt, w2.scalars);
   hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, s, w2.scalars, capacity2, w2.counts, w2.eff_total);
   if (m == 0 || capacity2 == 0) return hip_status(who);
   exclusive_scan<uint32_t>(w2.emit_cnt, w2.off, m, w2.partials, s);
