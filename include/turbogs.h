@@ -29,7 +29,11 @@
  *       rows 0-2 mean xyz; 3-5 log-scale; 6-9 quaternion (w, x, y, z),
  *       unnormalised; 10 opacity logit; 11 + 3k + c SH coefficient k
  *       (k = 0..15, order l then m = -l..l) of colour channel c.
- *     Gradients, and the Adam moments m, v, use the same layout.
+ *     Gradients use the same layout.  The optimizer's moments m, v are
+ *     Gaussian-major, m[n][TGS_MOMENT_STRIDE] (the moment of row r of
+ *     Gaussian i at m[i * TGS_MOMENT_STRIDE + r]; entries 59-63 are padding,
+ *     never read or written): an update touches a few percent of the
+ *     Gaussians, and each one's moments then sit in two cache lines.
  *   - Images are tiled in 16 x 16 tiles; tiles_x = ceil(W/16),
  *     tiles_y = ceil(H/16); tile id = ty * tiles_x + tx; a pixel's local
  *     index inside its tile is ly * 16 + lx.
@@ -49,11 +53,12 @@
 extern "C" {
 #endif
 
-#define TGS_ABI_VERSION 11u
+#define TGS_ABI_VERSION 12u
 #define TGS_TILE 16
 #define TGS_SPLAT_FLOATS 12  /* floats per projected splat record */
 #define TGS_G2D_FLOATS 9     /* floats per screen-space gradient record */
 #define TGS_PARAM_ROWS 59
+#define TGS_MOMENT_STRIDE 64 /* floats per Gaussian in the moment arrays m, v */
 #define TGS_COUNTER_SLOTS 64 /* slots per counter of tgs_render_fwd */
 #define TGS_RENDER_CHUNKS 8     /* backward workgroups per tile when the forward keeps state */
 #define TGS_RENDER_CHUNK_LEN 32 /* list positions per backward chunk (the last takes the rest) */
@@ -538,8 +543,9 @@ int32_t tgs_threshold_mask(const float* values, int64_t n, const float* thr, uin
  *     new one at mean - o, both with log-scales lowered by ln 1.6;
  *     otherwise the new Gaussian is a copy;
  *   - m and v are copied, except for split and new Gaussians (zeros).
- *   params, m, v        [59][n] float, read
- *   params_out, m_out, v_out  [59][n_out] float, written
+ *   params [59][n], m, v [n][TGS_MOMENT_STRIDE] float, read
+ *   params_out [59][n_out], m_out, v_out [n_out][TGS_MOMENT_STRIDE] float,
+ *   written
  * Errors: n outside [1, 2^31), n_out outside [0, 2n], a short workspace. */
 size_t tgs_density_topology_workspace_size(int64_t n);
 int32_t tgs_density_topology_count(const uint8_t* keep, const uint8_t* densify, int64_t n, int64_t* n_keep,
@@ -688,7 +694,7 @@ int32_t tgs_project_bwd_optimizer_step_views(float* params, int64_t n, int32_t n
  * solved in closed form by the Sherman-Morrison identity, with
  * J^T J = diag(g^2) (lm_mode 1) elementwise (lm_mode 2: Adam for every
  * row); the other SH rows take a bias-corrected Adam step.  touched
- * nullable (all).
+ * nullable (all).  params, grad [59][n]; m, v [n][TGS_MOMENT_STRIDE].
  * step >= 1.  Internally FP64. */
 int32_t tgs_optimizer_step(float* params, const float* grad, float* m, float* v, int64_t n,
                            const uint8_t* touched, const tgs_optim_params* op, int64_t step,

@@ -21,6 +21,7 @@ TGS_ERR_HIP = -2
 SPLAT_FLOATS = 12
 G2D_FLOATS = 9
 PARAM_ROWS = 59
+MOMENT_STRIDE = 64   # floats per Gaussian in the optimizer moments m, v ([n][64], Gaussian-major)
 TILE = 16
 COUNTER_SLOTS = 64
 RENDER_CHUNKS = 8

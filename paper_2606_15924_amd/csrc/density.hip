@@ -207,12 +207,13 @@ __global__ void __launch_bounds__(256) topo_apply_kernel(const float* __restrict
       kv = nv = val - kLnSplit;
     }
     po[(int64_t)r * n_out + dst] = kv;
-    mo[(int64_t)r * n_out + dst] = split ? 0.f : m[(int64_t)r * n + i];
-    vo[(int64_t)r * n_out + dst] = split ? 0.f : v[(int64_t)r * n + i];
+    // the moments are Gaussian-major (TGS_MOMENT_STRIDE floats per Gaussian)
+    mo[dst * TGS_MOMENT_STRIDE + r] = split ? 0.f : m[i * TGS_MOMENT_STRIDE + r];
+    vo[dst * TGS_MOMENT_STRIDE + r] = split ? 0.f : v[i * TGS_MOMENT_STRIDE + r];
     if (dn) {
       po[(int64_t)r * n_out + dst2] = nv;
-      mo[(int64_t)r * n_out + dst2] = 0.f;
-      vo[(int64_t)r * n_out + dst2] = 0.f;
+      mo[dst2 * TGS_MOMENT_STRIDE + r] = 0.f;
+      vo[dst2 * TGS_MOMENT_STRIDE + r] = 0.f;
     }
   }
 }

@@ -54,8 +54,8 @@ __global__ void __launch_bounds__(256) sh_rest_kernel(
     for (int ch = 0; ch < 3; ++ch) {
       const int64_t idx = (int64_t)(11 + 3 * k + ch) * n + i;
       r.p[ch] = params[idx];
-      r.m[ch] = m[idx];
-      r.v[ch] = v[idx];
+      r.m[ch] = m[mom(i, 11 + 3 * k + ch)];
+      r.v[ch] = v[mom(i, 11 + 3 * k + ch)];
       r.g[ch] = grad_prev != nullptr ? grad_prev[idx] : 0.f;
     }
   };
@@ -87,8 +87,8 @@ __global__ void __launch_bounds__(256) sh_rest_kernel(
       const float gf = grad_prev != nullptr ? cur.g[ch] + (float)grad[ch] : (float)grad[ch];
       adam_elem(pp, gf, mm, vv, row_lr_bc1(o, row), o);
       params[idx] = pp;
-      m[idx] = mm;
-      v[idx] = vv;
+      m[mom(i, row)] = mm;
+      v[mom(i, row)] = vv;
     }
     if (k + 1 < 16) cur = nxt;
   }
@@ -114,12 +114,15 @@ __global__ void __launch_bounds__(kWave) geom_lm_kernel(
   const int64_t i = (int64_t)blockIdx.x * kWave + lane;
   const int64_t ic = i < n ? i : n - 1;  // lanes past the end load a valid element
   // asynchronous row copies global -> LDS: lane l's value lands at [row][l]
+  // (params and the gradient row-major [59][n], the moments Gaussian-major)
   const float* srcs[4] = {params, m, v, grad_prev};
   const int n_src = grad_prev != nullptr ? 4 : 3;
   for (int q = 0; q < n_src; ++q)
 #pragma unroll
-    for (int r = 0; r < kGeoRows; ++r)
-      __builtin_amdgcn_global_load_lds(srcs[q] + (int64_t)r * n + ic, s_rows + (q * kGeoRows + r) * kWave, 4, 0, 0);
+    for (int r = 0; r < kGeoRows; ++r) {
+      const int64_t at_q = q == 1 || q == 2 ? mom(ic, r) : (int64_t)r * n + ic;
+      __builtin_amdgcn_global_load_lds(srcs[q] + at_q, s_rows + (q * kGeoRows + r) * kWave, 4, 0, 0);
+    }
 
   const bool live = i < n && (touched == nullptr || touched[i] != 0);  // untouched: nothing changes
   float gl[kGeoRows];  // this view's gradient of rows 0-13, rounded to float
@@ -151,10 +154,9 @@ __global__ void __launch_bounds__(kWave) geom_lm_kernel(
 #pragma unroll
     for (int r = 0; r < kGeoRows; ++r) gl[r] = at(3, r) + gl[r];
   auto store = [&](int row, float pp, float mm, float vv) {
-    const int64_t idx = (int64_t)row * n + i;
-    m[idx] = mm;
-    v[idx] = vv;
-    params[idx] = pp;
+    m[mom(i, row)] = mm;
+    v[mom(i, row)] = vv;
+    params[(int64_t)row * n + i] = pp;
   };
   if (o.lm_mode == 2) {
 #pragma unroll
@@ -294,12 +296,11 @@ __device__ __forceinline__ void sh_group_views(float* params, int64_t n, const V
 #pragma unroll
   for (int r = 0; r < 15; ++r) {
     const int row = 14 + 15 * kGrp + r;
-    const int64_t idx = (int64_t)row * n + i;
-    float pp = cf[r], mm = m[idx], vv = v[idx];
+    float pp = cf[r], mm = m[mom(i, row)], vv = v[mom(i, row)];
     adam_elem(pp, gs[r], mm, vv, row_lr_bc1(o, row), o);
-    params[idx] = pp;
-    m[idx] = mm;
-    v[idx] = vv;
+    params[(int64_t)row * n + i] = pp;
+    m[mom(i, row)] = mm;
+    v[mom(i, row)] = vv;
   }
 }
 
@@ -509,16 +510,14 @@ __device__ __forceinline__ void geom_lm_views_one(float* params, int64_t n, cons
   double gsum[kGeoRows];
   geom_views_grad(params, n, vs, i, dil, dsh, gsum);
   auto store = [&](int row, float pp, float mm, float vv) {
-    const int64_t idx = (int64_t)row * n + i;
-    m[idx] = mm;
-    v[idx] = vv;
-    params[idx] = pp;
+    m[mom(i, row)] = mm;
+    v[mom(i, row)] = vv;
+    params[(int64_t)row * n + i] = pp;
   };
   auto load = [&](int row, float& pp, float& mm, float& vv) {
-    const int64_t idx = (int64_t)row * n + i;
-    pp = params[idx];
-    mm = m[idx];
-    vv = v[idx];
+    pp = params[(int64_t)row * n + i];
+    mm = m[mom(i, row)];
+    vv = v[mom(i, row)];
   };
   if (o.lm_mode == 2) {
 #pragma unroll

@@ -11,6 +11,11 @@
 
 namespace tgs {
 
+// The moments m, v are Gaussian-major: row r of Gaussian i at
+// i * kMom + r (TGS_MOMENT_STRIDE floats per Gaussian).
+constexpr int kMom = TGS_MOMENT_STRIDE;
+__host__ __device__ inline int64_t mom(int64_t i, int row) { return i * kMom + row; }
+
 struct OptArgs {
   double lr[6];  // mean, scale, quat, opacity, sh dc, sh rest
   double beta1, beta2, eps_adam, eps_lm;
@@ -94,7 +99,7 @@ __device__ __forceinline__ void lm_block(float (&p)[K], float (&m)[K], float (&v
   for (int k = 0; k < K; ++k) p[k] = (float)((double)p[k] + row_lr(o, rows[k]) * x[k]);
 }
 
-// The same on the [59][n] stores: loads the block's rows of Gaussian i,
+// The same on the stores (params [59][n], moments Gaussian-major): loads the block's rows of Gaussian i,
 // updates them and stores them back.
 template <int K>
 __device__ __forceinline__ void lm_update(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
@@ -103,18 +108,16 @@ __device__ __forceinline__ void lm_update(float* __restrict__ p, float* __restri
   float pk[K], mk[K], vk[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int64_t idx = (int64_t)rows[k] * n + i;
-    pk[k] = p[idx];
-    mk[k] = m[idx];
-    vk[k] = v[idx];
+    pk[k] = p[(int64_t)rows[k] * n + i];
+    mk[k] = m[mom(i, rows[k])];
+    vk[k] = v[mom(i, rows[k])];
   }
   lm_block<K>(pk, mk, vk, rows, gf, o);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int64_t idx = (int64_t)rows[k] * n + i;
-    m[idx] = mk[k];
-    v[idx] = vk[k];
-    p[idx] = pk[k];
+    m[mom(i, rows[k])] = mk[k];
+    v[mom(i, rows[k])] = vk[k];
+    p[(int64_t)rows[k] * n + i] = pk[k];
   }
 }
 

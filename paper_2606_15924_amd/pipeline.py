@@ -413,8 +413,9 @@ class Trainer:
         self.dev = params.device
         self.params = params.contiguous()
         self.n = params.shape[1]
-        self.m = torch.zeros_like(self.params)
-        self.v = torch.zeros_like(self.params)
+        # the moments are Gaussian-major, [n][MOMENT_STRIDE] (see moments())
+        self.m = torch.zeros((self.n, B.MOMENT_STRIDE), dtype=torch.float32, device=self.dev)
+        self.v = torch.zeros_like(self.m)
         self.grad = torch.zeros_like(self.params)
         self.touched = torch.zeros(self.n, dtype=torch.uint8, device=self.dev)
         self.cams = [B.camera(c) for c in cams]
@@ -823,8 +824,9 @@ class Trainer:
         ws = torch.empty(B.tgs_density_topology_workspace_size(self.n), dtype=torch.uint8, device=self.dev)
         n_keep, n_new = B.tgs_density_topology_count(keep, densify, self.n, ws)
         n_out = n_keep + n_new
-        p_out, m_out, v_out = (torch.empty((self.params.shape[0], n_out), dtype=torch.float32, device=self.dev)
-                               for _ in range(3))
+        p_out = torch.empty((self.params.shape[0], n_out), dtype=torch.float32, device=self.dev)
+        m_out, v_out = (torch.empty((n_out, B.MOMENT_STRIDE), dtype=torch.float32, device=self.dev)
+                        for _ in range(2))
         B.tgs_density_topology_apply(self.params, self.m, self.v, self.n, z.contiguous(), log_split, ws,
                                      p_out, m_out, v_out, n_out)
         self.params, self.m, self.v, self.n = p_out, m_out, v_out, n_out
@@ -837,6 +839,11 @@ class Trainer:
             self.gstats = torch.zeros((self.n, 4), dtype=torch.float32, device=self.dev)
         self._bufs = {}   # per-view buffers are sized by the Gaussian count
         return n_out
+
+    def moments(self):
+        """The Adam moments m, v in the parameter layout, [59][n] views of
+        the Gaussian-major arrays."""
+        return self.m[:, :B.PARAM_ROWS].T, self.v[:, :B.PARAM_ROWS].T
 
     def loss_value(self, used) -> float:
         return float(sum(vb.tile_loss[: vb.n_st].sum() for vb in used))

@@ -81,6 +81,22 @@ def samples_dict(s: dict):
     return s["valid_tiles"], s["tile_off"], s["pix"]
 
 
+MOMENT_STRIDE = 64  # the library's Gaussian-major moment layout, [n][64]
+
+
+def moments_gaussian_major(m: np.ndarray) -> np.ndarray:
+    """[59][n] moments (the oracle's layout) as the library's [n][64] array
+    (padding zero)."""
+    out = np.zeros((m.shape[1], MOMENT_STRIDE), dtype=np.float32)
+    out[:, : m.shape[0]] = m.T
+    return out
+
+
+def moments_rows(m: np.ndarray, rows: int = 59) -> np.ndarray:
+    """The library's [n][64] moments as [59][n] (the oracle's layout)."""
+    return np.ascontiguousarray(np.asarray(m)[:, :rows].T)
+
+
 def close(a, b, rtol, atol=0.0):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)

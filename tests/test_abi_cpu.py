@@ -36,7 +36,7 @@ def test_header_symbols_exported(B):
 
 
 def test_version_and_counts(B):
-    assert B.tgs_version() == 11
+    assert B.tgs_version() == 12
     for r in (1, 100, 150, 200, 250, 500, 1000):
         assert B.tgs_pixels_per_tile(r) == pixels_per_tile(r)
     sp = B.sample_params(64, n_tiles_sel=64)

@@ -19,7 +19,7 @@ import synth
 from oracle import binning, density, project, render, sampler
 from oracle.params import RasterParams, SampleParams
 
-from support import assert_close, scene_c1, small_scene, splat_as_oracle, splat_record
+from support import moments_gaussian_major, moments_rows, assert_close, scene_c1, small_scene, splat_as_oracle, splat_record
 
 pytestmark = pytest.mark.gpu
 
@@ -361,9 +361,11 @@ def test_densify_and_prune_parity(B, n):
     nk, nn = B.tgs_density_topology_count(dev(keep), dev(dens), n, ws)
     assert (nk, nn) == (want["n_keep"], want["n_new"])
     n_out = nk + nn
-    po, mo, vo = (torch.full((59, n_out), np.nan, dtype=torch.float32, device="cuda") for _ in range(3))
-    B.tgs_density_topology_apply(dev(p), dev(m), dev(v), n, dev(z), log_split, ws, po, mo, vo, n_out)
-    got, gm, gv = host(po), host(mo), host(vo)
+    po = torch.full((59, n_out), np.nan, dtype=torch.float32, device="cuda")
+    mo, vo = (torch.full((n_out, B.MOMENT_STRIDE), np.nan, dtype=torch.float32, device="cuda") for _ in range(2))
+    B.tgs_density_topology_apply(dev(p), dev(moments_gaussian_major(m)), dev(moments_gaussian_major(v)), n, dev(z),
+                                 log_split, ws, po, mo, vo, n_out)
+    got, gm, gv = host(po), moments_rows(host(mo)), moments_rows(host(vo))
     ref = want["params"]
     # rows copied as they are, and the moments: bit for bit
     assert np.array_equal(got[6:], ref[6:].astype(np.float32))

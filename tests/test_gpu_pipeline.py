@@ -10,7 +10,7 @@ import synth
 from oracle import binning, maps, optim, pipeline, project, project_bwd, render, sampler
 from oracle.params import LossParams, OptimParams, RasterParams, SampleParams
 
-from support import (assert_close, check_pair_lists, last_ids, last_ids_two_part, scene_c1, scene_scaling,
+from support import (moments_gaussian_major, moments_rows, assert_close, check_pair_lists, last_ids, last_ids_two_part, scene_c1, scene_scaling,
                      small_scene, splat_as_oracle, splat_record)
 
 pytestmark = pytest.mark.gpu
@@ -273,7 +273,7 @@ def test_deterministic_backward_repeats_bit_for_bit(B, c1_inputs, dense):
         tr = Trainer(dev(p), cams, [dev(x) for x in gts], cfg, E=[dev(e.view(np.int16)) for e in E],
                      A=[dev(x.view(np.int16)) for x in A])
         tr.step([0, 1, 2, 3])
-        res.append([host(t).copy() for t in (tr.params, tr.m, tr.v, tr.touched)])
+        res.append([host(t).copy() for t in (tr.params, *tr.moments(), tr.touched)])
         del tr
     for x, y in zip(*res):
         assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
@@ -305,7 +305,7 @@ def test_trainer_async_binning_equals_blocking_binning(B, c1_inputs):
                 caps = [vb.capacity for vb in tr._bufs.values()]
         tr.check_counts(wait_all=True)
         assert not tr._pending
-        res.append([host(x).copy() for x in (tr.params, tr.m, tr.v, *Eg, *Ag)])
+        res.append([host(x).copy() for x in (tr.params, *tr.moments(), *Eg, *Ag)])
         if not blocking:
             assert all(vb.sized for vb in tr._bufs.values())
             assert all(vb.capacity > c for vb, c in zip(tr._bufs.values(), caps))
@@ -520,7 +520,8 @@ def test_scaling_optimizer_on_sampled_gaussians(B, scaling):
     rng = np.random.default_rng(6)
     g = (rng.normal(size=p.shape) * 1e-3).astype(np.float32)
     touched = (rng.uniform(size=n) < 0.5).astype(np.uint8)
-    P, M, V = dev(p.copy()), torch.zeros((59, n), device="cuda"), torch.zeros((59, n), device="cuda")
+    P, M, V = dev(p.copy()), torch.zeros((n, B.MOMENT_STRIDE), device="cuda"), torch.zeros((n, B.MOMENT_STRIDE),
+                                                                                          device="cuda")
     B.tgs_optimizer_step(P, dev(g), M, V, n, dev(touched), B.optim_params(), 1)
     pick = rng.choice(n, 2000, replace=False)
     rp_, rm, rv = optim.optimizer_step(p[:, pick], g[:, pick], np.zeros((59, 2000)), np.zeros((59, 2000)),
@@ -627,7 +628,7 @@ def test_full_size_multi_view_step_properties(B, fullstep, views, lm_mode):
         used = tr.step(list(range(len(views))))
         torch.cuda.synchronize()
         assert np.isfinite(tr.loss_value(used))
-        res.append((host(tr.params), host(tr.m), host(tr.v), host(tr.touched).astype(bool)))
+        res.append((host(tr.params), *(host(x) for x in tr.moments()), host(tr.touched).astype(bool)))
         del tr
     (p1, m1, v1, t1), (p2, m2, v2, t2) = res
     assert np.array_equal(t1, t2)
@@ -714,7 +715,7 @@ def test_views_fused_update_matches_per_view_path(B, c1_inputs):
         tr = Trainer(dev(p), cams, [dev(g) for g in gts], cfg, E=[dev(e.view(np.int16)) for e in E],
                      A=[dev(a.view(np.int16)) for a in A])
         tr.step([0, 1, 2, 3])
-        res.append([host(x).astype(np.float64) for x in (tr.params, tr.m, tr.v, tr.touched)])
+        res.append([host(x).astype(np.float64) for x in (tr.params, *tr.moments(), tr.touched)])
         del tr
     (p0, m0, v0, t0), (p1, m1, v1, t1) = res
     assert np.array_equal(t0, t1) and t0.sum() > 1000

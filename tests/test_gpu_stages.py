@@ -14,7 +14,7 @@ import synth
 from oracle import binning, loss, maps, optim, project, project_bwd, render, sampler
 from oracle.params import LossParams, OptimParams, RasterParams, SampleParams
 
-from support import (assert_close, check_pair_lists, last_ids, ldl_conic, scene_c1, scene_scaling, small_scene,
+from support import (moments_gaussian_major, moments_rows, assert_close, check_pair_lists, last_ids, ldl_conic, scene_c1, scene_scaling, small_scene,
                      splat_as_oracle, splat_record)
 
 pytestmark = pytest.mark.gpu
@@ -671,12 +671,12 @@ def test_project_bwd_optimizer_fused(B, mode, prev, deg, n):
     op = B.optim_params(lm_mode=mode)
     step = 5
     # unfused: gradient (accumulated onto the earlier views' one), then the update
-    Pa, Ma, Va = dev(p), dev(m0), dev(v0)
+    Pa, Ma, Va = dev(p), dev(moments_gaussian_major(m0)), dev(moments_gaussian_major(v0))
     G = dev(grad_prev) if prev else torch.empty((59, n), dtype=torch.float32, device="cuda")
     B.tgs_project_bwd(Pa, n, c, brp, radius, clamp, dev(g2d), G, accumulate=prev)
     B.tgs_optimizer_step(Pa, G, Ma, Va, n, dev(touched), op, step)
     # fused
-    Pb, Mb, Vb = dev(p), dev(m0), dev(v0)
+    Pb, Mb, Vb = dev(p), dev(moments_gaussian_major(m0)), dev(moments_gaussian_major(v0))
     B.tgs_project_bwd_optimizer_step(Pb, n, c, brp, radius, clamp, dev(g2d), dev(grad_prev) if prev else None,
                                      Mb, Vb, dev(touched), op, step,
                                      torch.empty(B.tgs_project_bwd_optimizer_workspace_size(n), dtype=torch.uint8,
@@ -700,9 +700,9 @@ def test_optimizer_parity(B, mode):
     op = OptimParams(lm_mode=mode)
     step = 7
     rp_, rm, rv = optim.optimizer_step(p, g, m, v, touched, op, step)
-    P, M, V = dev(p), dev(m), dev(v)
+    P, M, V = dev(p), dev(moments_gaussian_major(m)), dev(moments_gaussian_major(v))
     B.tgs_optimizer_step(P, dev(g), M, V, N, dev(touched), B.optim_params(lm_mode=mode), step)
-    gp, gm, gv = host(P), host(M), host(V)
+    gp, gm, gv = host(P), moments_rows(host(M)), moments_rows(host(V))
     # FP64 inside: results equal the FP32 rounding of the FP64 oracle to 1 ulp
     for name, a, b in (("params", gp, rp_), ("m", gm, rm), ("v", gv, rv)):
         b32 = b.astype(np.float32)
