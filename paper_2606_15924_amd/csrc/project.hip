@@ -17,69 +17,99 @@ namespace tgs {
 // PT = float: the training path.  PT = double: the FP64 instantiation for
 // gradient checks, which also writes the splat record in doubles (rec64:
 // centre x, y; conic a, b, c; opacity; r, g, b; depth; two zeros).
+// The splat records (48 bytes per Gaussian) and the cleared gradient
+// records (36 bytes) of a wave's 64 Gaussians are contiguous, so they are
+// written as whole runs: the splat floats staged in LDS, then every lane
+// storing consecutive 16-byte pieces (and 4-byte zeros for the gradient),
+// instead of each lane writing its own records at a 48- or 36-byte stride.
 template <typename PT, int kDeg>
 __global__ void __launch_bounds__(256) project_fwd_kernel(
     const PT* __restrict__ params, int64_t n, CamArgs cam, double z_near,
     double dil, float4* __restrict__ splat, float* __restrict__ depth, int* __restrict__ radius,
     int4* __restrict__ rect, uint8_t* __restrict__ clampm, float* __restrict__ g2d_clear,
     double* __restrict__ rec64) {
+  __shared__ float4 s_rec[256 / kWave][3 * kWave];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
+  if (b0 >= n) return;  // workgroup-uniform
+  const bool valid = i < n;
+  const int64_t ic = valid ? i : n - 1;  // lanes past the end compute on a valid Gaussian and store nothing
+  const int lane = lane_id(), wave = (int)threadIdx.x / kWave;
+  const int64_t w0 = i - lane;  // the wave's first Gaussian
   // the SH coefficients are loaded with the geometry rows, before anything
   // depends on them (one round trip to memory; culled Gaussians read them
   // for nothing, a small share of the traffic)
   constexpr int nk = (kDeg + 1) * (kDeg + 1);
   PT cf[3 * nk];
 #pragma unroll
-  for (int q = 0; q < 3 * nk; ++q) cf[q] = params[(int64_t)(11 + q) * n + i];
-  if (g2d_clear != nullptr)
-    for (int k = 0; k < 9; ++k) g2d_clear[i * 9 + k] = 0.f;
-  Geom g;
-  geometry(params, n, i, cam, z_near, dil, g);
-  depth[i] = (float)g.t[2];
-  if (!g.visible) {
-    radius[i] = 0;
-    rect[i] = make_int4(0, 0, 0, 0);
-    clampm[i] = 0;
-    splat[3 * i + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
-    splat[3 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-    splat[3 * i + 2] = make_float4(0.f, 0.f, 0.f, (float)g.t[2]);
-    if (rec64 != nullptr)
-      for (int k = 0; k < 12; ++k) rec64[12 * i + k] = k == 9 ? g.t[2] : 0.0;
-    return;
-  }
-  // view-dependent colour
-  const double dx = g.mu[0] - cam.center[0], dy = g.mu[1] - cam.center[1],
-               dz = g.mu[2] - cam.center[2];
-  const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-  const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
-  double rgb[3] = {0.5, 0.5, 0.5};
+  for (int q = 0; q < 3 * nk; ++q) cf[q] = params[(int64_t)(11 + q) * n + ic];
+  if (g2d_clear != nullptr && w0 < n) {
+    const int64_t end = n * TGS_G2D_FLOATS;
 #pragma unroll
-  for (int k = 0; k < nk; ++k) {
-    double Yk, g0, g1, g2;
-    sh_term(k, ux, uy, uz, Yk, g0, g1, g2);
-    for (int ch = 0; ch < 3; ++ch) rgb[ch] += Yk * (double)cf[3 * k + ch];
-  }
-  uint8_t cm = 0;
-  for (int ch = 0; ch < 3; ++ch)
-    if (rgb[ch] < 0.0) {
-      rgb[ch] = 0.0;
-      cm |= (uint8_t)(1u << ch);
+    for (int q = 0; q < TGS_G2D_FLOATS; ++q) {
+      const int64_t e = w0 * TGS_G2D_FLOATS + q * kWave + lane;
+      if (e < end) g2d_clear[e] = 0.f;
     }
-  const double opac = 1.0 / (1.0 + exp(-(double)params[10 * n + i]));
-  const double fxp = floor(g.px), fyp = floor(g.py);
-  splat[3 * i + 0] = make_float4((float)fxp, (float)fyp, (float)(g.px - fxp), (float)(g.py - fyp));
-  // the conic Q = Sigma'^-1 = [[c, -b], [-b, a]] / det in its LDL^T form:
-  // Q_00 = c / det, beta = Q_01 / Q_00 = -b / c, delta = det Q / Q_00 = 1 / c
-  splat[3 * i + 1] = make_float4((float)(g.c / g.det), (float)(-g.b / g.c), (float)(1.0 / g.c), (float)opac);
-  splat[3 * i + 2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], (float)g.t[2]);
-  radius[i] = (int)g.radius;
-  rect[i] = make_int4(g.rect[0], g.rect[1], g.rect[2], g.rect[3]);
-  clampm[i] = cm;
-  if (rec64 != nullptr) {
-    const double r64[12] = {g.px, g.py, g.c / g.det, -g.b / g.det, g.a / g.det, opac,
-                            rgb[0], rgb[1], rgb[2], g.t[2], 0.0, 0.0};
-    for (int k = 0; k < 12; ++k) rec64[12 * i + k] = r64[k];
+  }
+  Geom g;
+  geometry(params, n, ic, cam, z_near, dil, g);
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = make_float4(0.f, 0.f, 0.f, (float)g.t[2]);
+  int rad = 0;
+  int4 rc = make_int4(0, 0, 0, 0);
+  uint8_t cm = 0;
+  if (g.visible) {
+    // view-dependent colour
+    const double dx = g.mu[0] - cam.center[0], dy = g.mu[1] - cam.center[1],
+                 dz = g.mu[2] - cam.center[2];
+    const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+    const double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+    double rgb[3] = {0.5, 0.5, 0.5};
+#pragma unroll
+    for (int k = 0; k < nk; ++k) {
+      double Yk, g0, g1, g2;
+      sh_term(k, ux, uy, uz, Yk, g0, g1, g2);
+      for (int ch = 0; ch < 3; ++ch) rgb[ch] += Yk * (double)cf[3 * k + ch];
+    }
+    for (int ch = 0; ch < 3; ++ch)
+      if (rgb[ch] < 0.0) {
+        rgb[ch] = 0.0;
+        cm |= (uint8_t)(1u << ch);
+      }
+    const double opac = 1.0 / (1.0 + exp(-(double)params[10 * n + ic]));
+    const double fxp = floor(g.px), fyp = floor(g.py);
+    r0 = make_float4((float)fxp, (float)fyp, (float)(g.px - fxp), (float)(g.py - fyp));
+    // the conic Q = Sigma'^-1 = [[c, -b], [-b, a]] / det in its LDL^T form:
+    // Q_00 = c / det, beta = Q_01 / Q_00 = -b / c, delta = det Q / Q_00 = 1 / c
+    r1 = make_float4((float)(g.c / g.det), (float)(-g.b / g.c), (float)(1.0 / g.c), (float)opac);
+    r2 = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], (float)g.t[2]);
+    rad = (int)g.radius;
+    rc = make_int4(g.rect[0], g.rect[1], g.rect[2], g.rect[3]);
+    if (rec64 != nullptr && valid) {
+      const double r64[12] = {g.px, g.py, g.c / g.det, -g.b / g.det, g.a / g.det, opac,
+                              rgb[0], rgb[1], rgb[2], g.t[2], 0.0, 0.0};
+      for (int k = 0; k < 12; ++k) rec64[12 * i + k] = r64[k];
+    }
+  } else if (rec64 != nullptr && valid) {
+    for (int k = 0; k < 12; ++k) rec64[12 * i + k] = k == 9 ? g.t[2] : 0.0;
+  }
+  if (valid) {
+    depth[i] = (float)g.t[2];
+    radius[i] = rad;
+    rect[i] = rc;
+    clampm[i] = cm;
+  }
+  float4* sr = s_rec[wave];
+  sr[3 * lane] = r0;
+  sr[3 * lane + 1] = r1;
+  sr[3 * lane + 2] = r2;
+  __syncthreads();
+  if (w0 < n) {
+    const int64_t end = n * 3;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int64_t e = w0 * 3 + q * kWave + lane;
+      if (e < end) splat[e] = sr[q * kWave + lane];
+    }
   }
 }
 
