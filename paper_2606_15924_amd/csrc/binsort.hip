@@ -89,22 +89,6 @@ __global__ void __launch_bounds__(64) copy_counts3_kernel(const unsigned long lo
   if (threadIdx.x < 3) dst[threadIdx.x] = src[threadIdx.x == 2 ? 3 : threadIdx.x];
 }
 
-// counts[0] = the lists' length: the end of the last non-empty range (the
-// ranges are contiguous from 0 in tile order; sentinel pairs lie past it).
-__global__ void __launch_bounds__(256) list_len_kernel(const uint2* __restrict__ ranges, uint32_t n_t,
-                                                       unsigned long long* __restrict__ counts) {
-  __shared__ uint32_t lds[256 / kWave];
-  uint32_t m = 0;
-  for (uint32_t t = threadIdx.x; t < n_t; t += 256) m = max(m, ranges[t].y);
-  m = (uint32_t)wave_max_u32(m);
-  if (lane_id() == 0) lds[threadIdx.x / kWave] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < 256 / kWave; ++k) m = max(m, lds[k]);
-    counts[0] = m;
-  }
-}
-
 // ------------------------------------------------------------------ scans
 template <typename T>
 __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const T* __restrict__ in, int64_t n,
@@ -475,8 +459,16 @@ __global__ void __launch_bounds__(1024) flag_sat_kernel(const int32_t* __restric
     }
   }
   __syncthreads();
-  for (int x = tid; x < W1; x += 1024)
-    for (int y = 1; y <= tiles_y; ++y) t[y * W1 + x] += t[(y - 1) * W1 + x];
+  // column prefix: a wave scans each of its columns, 64 rows at a time
+  for (int x = wave; x < W1; x += 1024 / kWave) {
+    uint32_t carry = 0;
+    for (int y0 = 0; y0 <= tiles_y; y0 += kWave) {
+      const int y = y0 + lane;
+      const uint32_t incl = carry + wave_inclusive_scan_u32(y <= tiles_y ? t[y * W1 + x] : 0u);
+      if (y <= tiles_y) t[y * W1 + x] = incl;
+      carry = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    }
+  }
   __syncthreads();
   for (int i = tid; i < words; i += 1024) sat[i] = t[i];
 }
@@ -949,6 +941,11 @@ struct RowBatch {
 
 constexpr int kEmitThreads = kWave;  // one wave per workgroup: __syncthreads is a wave barrier
 constexpr int kEmitBatch = 32;       // Gaussians per wave: more waves, fewer rounds each (64 measured slower)
+// The continuation's emission runs over every Gaussian past the prefix, few
+// of which have pairs in the marked tiles: 64 per wave halves the waves
+// that only find an empty batch.
+template <bool kFilter>
+constexpr int emit_batch() { return kFilter ? kWave : kEmitBatch; }
 
 // A wave per kEmitBatch depth-ordered Gaussians.  Their rectangle rows are
 // flattened Gaussian by Gaussian and handed out 64 per round; a Gaussian
@@ -972,12 +969,13 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
   const uint32_t total = *total_dev;  // pairs to emit (0 when they exceed the capacity)
   __shared__ RowBatch rb;
   const int lane = lane_id();
-  const int64_t b0 = (int64_t)blockIdx.x * kEmitBatch;
+  constexpr int kBatch = emit_batch<kFilter>();
+  const int64_t b0 = (int64_t)blockIdx.x * kBatch;
   const int64_t j = b0 + lane;
   int4 r = make_int4(0, 0, 0, 0);
   uint32_t g = 0, rows = 0;
   if (total == 0) return;  // workgroup-uniform
-  if (lane < kEmitBatch && j < n && off[j + 1] > off[j]) {
+  if (lane < kBatch && j < n && off[j + 1] > off[j]) {
     r = rect_sorted[j];
     g = ids_sorted[j];
     rows = (uint32_t)(r.w - r.y);
@@ -1197,7 +1195,7 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
   if (kPay)
     for (int k = 0; k < 2; ++k) pb[k] = (uint32_t*)((char*)w.pkeys[k] + align_up(sizeof(K) * (size_t)w.cap, 256));
   const int key_id_bits = kPay ? 0 : id_bits;
-  hipLaunchKernelGGL((emit_kernel<K, kFilter>), dim3((unsigned)std::max<int64_t>(ceil_div(n, kEmitBatch), 1)),
+  hipLaunchKernelGGL((emit_kernel<K, kFilter>), dim3((unsigned)std::max<int64_t>(ceil_div(n, emit_batch<kFilter>()), 1)),
                      dim3(kEmitThreads), 0, s,
                      w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, key_id_bits, tau, lia, w.eff_total,
                      kb[0], pb[0]);
@@ -1289,7 +1287,6 @@ static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const flo
   else
     sort_pairs<uint32_t, true>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
                                tbits, tau, lia, depth, vals, keys, ranges, s);
-  if (pre) hipLaunchKernelGGL(list_len_kernel, dim3(1), dim3(256), 0, s, (const uint2*)ranges, n_t, w.counts);
   return hip_status(who);
 }
 
