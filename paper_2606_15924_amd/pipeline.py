@@ -45,8 +45,8 @@ class StepConfig:
     seed: int = 3
     fuse_optimizer: bool = True   # last view's projection backward fused with the update
     # every view's projection backward fused with the update in one pass
-    # (tgs_project_bwd_optimizer_step_views; no gradient array) in steps of
-    # two or more views; a one-view step takes the single-view fused kernel
+    # (tgs_project_bwd_optimizer_step_views; no gradient array), one-view
+    # steps included (it visits touched Gaussians only)
     fuse_views: bool = False
     # views side by side: each view's sampler and chain (projection to
     # backward) on a stream of its own, reused round-robin (1: all on the
@@ -525,7 +525,7 @@ class Trainer:
         st = self._stage
         used = [self.buffers(slot, self.cams[v], rate_permille) for slot, v in enumerate(views)]
         slot_of = {id(vb): k for k, vb in enumerate(used)}
-        views_fused = self.cfg.fuse_views and len(used) > 1
+        views_fused = self.cfg.fuse_views
         self.touched.zero_()
         # the sample totals are cleared (dense views' counts added) on main;
         # then each sparse view's sampler runs on a stream of its own (which
