@@ -31,8 +31,8 @@
  *       (k = 0..15, order l then m = -l..l) of colour channel c.
  *     Gradients use the same layout.  The optimizer's moments m, v are
  *     Gaussian-major, m[n][TGS_MOMENT_STRIDE] (the moment of row r of
- *     Gaussian i at m[i * TGS_MOMENT_STRIDE + r]; entries 59-63 are padding,
- *     never read or written): an update touches a few percent of the
+ *     Gaussian i at m[i * TGS_MOMENT_STRIDE + r]; entries 59-63 are padding
+ *     that no update reads or writes): an update touches a few percent of the
  *     Gaussians, and each one's moments then sit in two cache lines.
  *   - Images are tiled in 16 x 16 tiles; tiles_x = ceil(W/16),
  *     tiles_y = ceil(H/16); tile id = ty * tiles_x + tx; a pixel's local
@@ -545,7 +545,8 @@ int32_t tgs_threshold_mask(const float* values, int64_t n, const float* thr, uin
  *   - m and v are copied, except for split and new Gaussians (zeros).
  *   params [59][n], m, v [n][TGS_MOMENT_STRIDE] float, read
  *   params_out [59][n_out], m_out, v_out [n_out][TGS_MOMENT_STRIDE] float,
- *   written
+ *   written (moment records move whole, padding included; the four moment
+ *   arrays 16-byte aligned)
  * Errors: n outside [1, 2^31), n_out outside [0, 2n], a short workspace. */
 size_t tgs_density_topology_workspace_size(int64_t n);
 int32_t tgs_density_topology_count(const uint8_t* keep, const uint8_t* densify, int64_t n, int64_t* n_keep,

@@ -207,13 +207,37 @@ __global__ void __launch_bounds__(256) topo_apply_kernel(const float* __restrict
       kv = nv = val - kLnSplit;
     }
     po[(int64_t)r * n_out + dst] = kv;
-    // the moments are Gaussian-major (TGS_MOMENT_STRIDE floats per Gaussian)
-    mo[dst * TGS_MOMENT_STRIDE + r] = split ? 0.f : m[i * TGS_MOMENT_STRIDE + r];
-    vo[dst * TGS_MOMENT_STRIDE + r] = split ? 0.f : v[i * TGS_MOMENT_STRIDE + r];
-    if (dn) {
-      po[(int64_t)r * n_out + dst2] = nv;
-      mo[dst2 * TGS_MOMENT_STRIDE + r] = 0.f;
-      vo[dst2 * TGS_MOMENT_STRIDE + r] = 0.f;
+    if (dn) po[(int64_t)r * n_out + dst2] = nv;
+  }
+  // the moments are Gaussian-major: each record (TGS_MOMENT_STRIDE floats)
+  // moves whole, 16 bytes per access, all loads before the stores (a row at
+  // a time would touch every record's lines once per row)
+  constexpr int kQ = TGS_MOMENT_STRIDE / 4;
+  const float4* ms = reinterpret_cast<const float4*>(m) + i * kQ;
+  const float4* vs = reinterpret_cast<const float4*>(v) + i * kQ;
+  float4* md = reinterpret_cast<float4*>(mo) + dst * kQ;
+  float4* vd = reinterpret_cast<float4*>(vo) + dst * kQ;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int h = 0; h < 2; ++h) {  // two halves, eight 16-byte pieces each
+    float4 a[kQ / 2], b[kQ / 2];
+#pragma unroll
+    for (int q = 0; q < kQ / 2; ++q) {
+      a[q] = split ? z4 : ms[h * (kQ / 2) + q];
+      b[q] = split ? z4 : vs[h * (kQ / 2) + q];
+    }
+#pragma unroll
+    for (int q = 0; q < kQ / 2; ++q) {
+      md[h * (kQ / 2) + q] = a[q];
+      vd[h * (kQ / 2) + q] = b[q];
+    }
+  }
+  if (dn) {
+    float4* md2 = reinterpret_cast<float4*>(mo) + dst2 * kQ;
+    float4* vd2 = reinterpret_cast<float4*>(vo) + dst2 * kQ;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      md2[q] = z4;
+      vd2[q] = z4;
     }
   }
 }
@@ -356,6 +380,8 @@ extern "C" int32_t tgs_density_topology_apply(const float* params, const float* 
   TGS_REQUIRE(ws_bytes >= w.bytes, "tgs_density_topology_apply: workspace %zu bytes < %zu", ws_bytes, w.bytes);
   if (n_out == 0) return TGS_OK;
   TGS_REQUIRE(params_out && m_out && v_out, "tgs_density_topology_apply: null output");
+  TGS_REQUIRE((((uintptr_t)m | (uintptr_t)v | (uintptr_t)m_out | (uintptr_t)v_out) & 15) == 0,
+              "tgs_density_topology_apply: moment arrays must be 16-byte aligned");
   hipStream_t s = as_stream(stream);
   hipLaunchKernelGGL(topo_apply_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0, s, params, m, v,
                      n, w.kflag, w.dflag, w.koff, w.doff, z, log_split, params_out, m_out, v_out, n_out);

@@ -577,10 +577,15 @@ class Trainer:
             if vb.dense:
                 sampled.append(None)
                 continue
-            # views side by side: the samplers run on main (idle until the
-            # first backward) beside the projections
-            ss = main if par else self._sample_stream(k)
-            ss.wait_stream(main)
+            # views side by side: a sampler over every tile is short and runs
+            # on main (idle until the first backward) beside the projections;
+            # drawing a tile subset is one long workgroup per view, so those
+            # run on the view streams (after the view's projection), side by side
+            if par:
+                ss = self._view_stream(k) if self.cfg.n_tiles_sel > 0 else main
+            else:
+                ss = self._sample_stream(k)
+                ss.wait_stream(main)
             with torch.cuda.stream(ss):
                 cam = self.cams[v]
                 pred = None
