@@ -174,7 +174,13 @@ int32_t tgs_project(const float* params, int64_t n, const tgs_camera* cam,
  *   tile_slot   [tiles_x * tiles_y] int32: slot of each tile or -1 (written)
  *   totals      [2] int64 device counters: += P and += n_st of this view
  *               (the caller zeroes them once per training step)
- *   ws          workspace of tgs_sample_workspace_size(H, W) bytes
+ *   ws          workspace of tgs_sample_workspace_size(H, W) bytes (8 per
+ *               tile: the race keys)
+ * With 0 <= n_tiles_sel < tiles, the tile pass draws that many tiles without
+ * replacement in proportion to weight (uniform over the rest once the weight
+ * runs out) as an exponential race (Efraimidis and Spirakis 2006): the tiles
+ * of the smallest keys L / w win, L the tile's -log2 uniform to 47 fractional
+ * bits, computed exactly in integer and IEEE double arithmetic.
  * Deterministic: counter-based SplitMix64 draws keyed by (seed, step, view,
  * tile, slot). */
 size_t tgs_sample_workspace_size(int32_t height, int32_t width);
@@ -186,8 +192,8 @@ int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t height, int32_t
 /* tgs_sample for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same sampling, outputs and errors, with the workspace taken from a
- * static device array of the library (9 bytes per tile for at most
- * TGS_SAMPLE_NOALLOC_MAX_TILES tiles, 576 KiB, held on each GPU the library
+ * static device array of the library (8 bytes per tile for at most
+ * TGS_SAMPLE_NOALLOC_MAX_TILES tiles, 512 KiB, held on each GPU the library
  * runs on until the process ends) instead of a caller buffer.  Calls no
  * allocating routine.  Images of more tiles are rejected with
  * TGS_ERR_INVALID before anything is queued.  Every call on one GPU shares
@@ -224,10 +230,10 @@ int32_t tgs_sample_noalloc(const uint16_t* E, const uint16_t* A, int32_t height,
  *                (tgs_render_bwd marks the narrower set of Gaussians
  *                composited at a sample)
  *   n_pairs      host out: number of pairs in valid tiles
- * capacity must hold every listed tile (valid or not) of every Gaussian
- * that has a pair in a valid tile; when it does not, the lists come out
- * empty (every range [0, 0); vals and keys untouched) and the call returns
- * TGS_ERR_CAPACITY with that count in *n_pairs.  Every kernel's grid is
+ * capacity must hold the pairs in valid tiles (only those are listed);
+ * when it does not, the lists come out empty (every range [0, 0); vals and
+ * keys untouched) and the call returns TGS_ERR_CAPACITY with that count in
+ * *n_pairs.  Every kernel's grid is
  * sized by the capacity and reads the pair count on the device, so the
  * work is queued without waiting; this call then waits for the stream once
  * (a copy of the two counts into host memory) to return them.  The library
@@ -242,8 +248,8 @@ int32_t tgs_bin_sort(const int32_t* rect, const float* splat, const float* depth
 /* tgs_bin_sort without any host synchronisation: the same lists, with the
  * counts written to device memory instead of returned.
  *   counts  [2] int64, device, 8-byte aligned: counts[0] = pairs in valid
- *           tiles (the lists' length), counts[1] = every listed tile of the
- *           Gaussians that have a pair, the capacity the call needs.  When
+ *           tiles (the lists' length), counts[1] = the capacity the call
+ *           needs (the same number: only valid tiles are listed).  When
  *           counts[1] > capacity the lists are empty, as above; the caller
  *           finds out when it next reads counts (after its own
  *           synchronisation), and a step rendered from such lists must be

@@ -13,7 +13,7 @@ OOPSLA 2014): output(state) = mix(state + gamma) with gamma the odd constant
 used here as a stateless counter hash: each field of (seed, step, view, tile,
 slot) is absorbed in turn, h <- mix(h + gamma * (field + 1)), starting from
 h = seed.  Pixel slots 0..255 are hard draws, 256..511 mixed draws; the tile
-pass uses tile = number of tiles.
+pass uses tile = number of tiles and slot = the tile's index.
 """
 from __future__ import annotations
 

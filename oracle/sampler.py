@@ -18,11 +18,22 @@ without replacement with probability proportional to the error map
   r = floor(u * n_left / 2^64)-th in ascending order;
 * partial edge tiles sample min(N_pix, valid pixels) and recompute the split;
   pixels outside the image are never sampled;
-* optional tile pass: n_tiles_sel tiles drawn the same way with weights equal
-  to the tile's summed pixel weights (uniform over the remaining tiles once
-  those weights run out); selected tiles are listed in ascending order.
+* optional tile pass: n_tiles_sel tiles drawn without replacement with
+  probability proportional to the tile's summed pixel weights, uniform over
+  the remaining tiles once those weights run out; selected tiles are listed in
+  ascending order.  The draw order plays no part downstream, so the pass takes
+  the exponential race of Efraimidis and Spirakis ("Weighted random sampling
+  with a reservoir", IPL 2006), which gives the sequential draws' distribution
+  exactly: every tile gets an independent Exp(1) time divided by its weight and
+  the n_tiles_sel earliest win.  Times are exact on both sides of the parity
+  check: Exp(1) / ln 2 = -log2 of a uniform, taken to 47 fractional bits by the
+  binary logarithm by repeated squaring, divided by the weight once in IEEE
+  double; zero-weight tiles come after every weighted one, ordered by a uniform
+  key; ties go to the lower tile index.
 """
 from __future__ import annotations
+
+import struct
 
 import numpy as np
 
@@ -76,6 +87,60 @@ def predicted_tile_weights(pred, TX: int, TY: int, W: int, H: int) -> np.ndarray
     return tw
 
 
+LOG_FRAC = 47     # fractional bits of a race time: the largest time, 64, times 2^47 is 2^53
+
+
+def neg_log2_fixed(u: int) -> int:
+    """2^47 * -log2(v / 2^64) for v = u | 1 (so v / 2^64 lies in (0, 1)),
+    with the fraction truncated to 47 bits.  v = 2^e * m with m in [1, 2):
+    -log2(v / 2^64) = 64 - e - log2(m), and the bits of log2(m) come one per
+    squaring (binary logarithm by repeated squaring, e.g. Knuth, TAOCP vol. 1,
+    1.2.2): m^2 >= 2 gives bit 1 and m <- m^2 / 2, else bit 0 and m <- m^2.
+    m is held in Q1.63 (2^63 <= m < 2^64), each square truncated to it."""
+    v = (u & ((1 << 64) - 1)) | 1
+    e = v.bit_length() - 1
+    m = v << (63 - e)
+    frac = 0
+    for _ in range(LOG_FRAC):
+        sq = m * m                                # Q2.126
+        if sq >> 127:
+            frac = 2 * frac + 1
+            m = sq >> 64
+        else:
+            frac = 2 * frac
+            m = sq >> 63
+    return ((64 - e) << LOG_FRAC) - frac
+
+
+def _double_bits(x: float) -> int:
+    return struct.unpack("<Q", struct.pack("<d", x))[0]
+
+
+def tile_race_keys(tw, seed: int, step: int, view: int) -> list:
+    """Race key of every tile (smaller runs first), as an unsigned 64-bit
+    integer: for weight w > 0 the bit pattern of the double L / w, L the
+    tile's fixed-point -log2 uniform (positive doubles order like their bit
+    patterns, all below 2^63); for w = 0, 2^63 + (u >> 1), after every
+    weighted tile.  u is the tile's draw in the tile pass's stream."""
+    n_t = len(tw)
+    keys = []
+    for t in range(n_t):
+        u = draw(seed, step, view, n_t, t)
+        w = int(tw[t])
+        if w > 0:
+            keys.append(_double_bits(float(neg_log2_fixed(u)) / float(w)))
+        else:
+            keys.append((1 << 63) | (u >> 1))
+    return keys
+
+
+def race_select(tw, n_sel: int, seed: int, step: int, view: int) -> np.ndarray:
+    """The n_sel tiles of smallest (race key, tile index), ascending."""
+    keys = tile_race_keys(tw, seed, step, view)
+    order = sorted(range(len(keys)), key=lambda t: (keys[t], t))
+    return np.sort(np.array(order[:n_sel], dtype=np.int64))
+
+
 def select_tiles(w: np.ndarray, TX: int, TY: int, W: int, H: int, n_sel: int,
                  seed: int, step: int, view: int, tile_pred=None) -> np.ndarray:
     """Tiles drawn without replacement with probability proportional to their
@@ -90,19 +155,7 @@ def select_tiles(w: np.ndarray, TX: int, TY: int, W: int, H: int, n_sel: int,
         for t in range(n_t):
             _, x, y = tile_pixels(t, TX, W, H)
             tw[t] = int(w[y, x].sum())
-    remaining = np.ones(n_t, dtype=bool)
-    chosen = []
-    for j in range(n_sel):
-        u = draw(seed, step, view, n_t, j)
-        cand = np.nonzero(remaining)[0]
-        wr = tw[cand]
-        if int(wr.sum()) > 0:
-            pick = cand[_pick_weighted(wr, u)]
-        else:
-            pick = cand[below(u, cand.size)]
-        remaining[pick] = False
-        chosen.append(pick)
-    return np.sort(np.array(chosen, dtype=np.int64))
+    return race_select(tw, n_sel, seed, step, view)
 
 
 def sample_tile(w: np.ndarray, A: np.ndarray, tile: int, TX: int, W: int, H: int,

@@ -12,19 +12,18 @@
 // key is (tile << id_bits) | Gaussian id, usually 32 bits: the id bits only
 // ride along, since a stable sort never compares them.
 //
-//   count     a thread per Gaussian over its rectangle rows: kept pairs and
-//             kept pairs in valid tiles, depth key (Gaussians without a kept
-//             valid tile get a key above every depth), touched flag
+//   count     a thread per Gaussian over its rectangle rows: kept pairs in
+//             valid tiles, depth key (Gaussians without a kept valid tile
+//             get a key above every depth), touched flag
 //   sort      LSD radix sort of (depth key, id) over n, one kernel per pass:
 //             stable, so ties keep id order; Gaussians with pairs come
 //             first; the last pass gathers rectangles and pair counts into
 //             depth order
 //   scan      exclusive scan of the counts -> pair offsets; the totals are
 //             read back once
-//   emit      a wave per 64 depth-ordered Gaussians walks their rows; each
-//             row's span is keyed and written contiguously after the rows
-//             before it; tiles outside the valid set get the sentinel tile
-//             id n_tiles (after every real tile)
+//   emit      a wave per 32 depth-ordered Gaussians walks their rows; each
+//             row's span (its valid columns, with a tile subset) is keyed
+//             and written contiguously after the rows before it
 //   sort      LSD radix sort of the pair keys on the tile bits only; the
 //             last pass writes the ids, the sorted keys and (if asked) the
 //             64-bit keys
@@ -271,10 +270,10 @@ constexpr int kDepthDigits = 256;
 // flattened Gaussian by Gaussian and handed out 64 per round, so every lane
 // evaluates a row span whatever the rectangles' heights; a Gaussian whose
 // first row falls in the round marks its slot and an inclusive max-scan
-// carries each owner to the following slots.  Per Gaussian: kept pairs, and
-// kept pairs in valid tiles (every kept pair when there is no tile subset),
-// summed by LDS atomics; then the depth key (Gaussians without a kept valid
-// tile get a key above every depth), pair count and touched flag.
+// carries each owner to the following slots.  Per Gaussian: kept pairs in
+// valid tiles (every kept pair when there is no tile subset), summed by LDS
+// atomics; then the depth key (Gaussians without a kept valid tile get a key
+// above every depth), pair count and touched flag.
 constexpr int kCountBatch = kWave;  // Gaussians per wave (32 measured slower)
 
 struct CountBatch {
@@ -282,7 +281,7 @@ struct CountBatch {
   uint32_t row0[kWave];  // exclusive prefix of the row counts in the batch
   RowEllipse ell[kWave];
   int mark[kWave];
-  uint32_t kept[kWave], valid[kWave];
+  uint32_t valid[kWave];
 };
 
 // ids == nullptr: Gaussian i of the index order (rect, depth by index),
@@ -311,7 +310,6 @@ __global__ void __launch_bounds__(kWave) count_kernel(
   const uint32_t n_rows = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
   cb.rect[lane] = r;
   cb.row0[lane] = my_row0;
-  cb.kept[lane] = 0u;
   cb.valid[lane] = 0u;
   if (rows > 0) cb.ell[lane] = load_row_ellipse(splat, g, tau, lia);
   int carry = -1;
@@ -329,30 +327,29 @@ __global__ void __launch_bounds__(kWave) count_kernel(
       const int ty = rj.y + (int)(f - cb.row0[jl]);
       int lo, hi;
       row_span(cb.ell[jl], ty, rj.x, rj.z, lo, hi);
-      const uint32_t c = (uint32_t)max(hi - lo + 1, 0);
-      uint32_t cv = c;
+      uint32_t cv = (uint32_t)max(hi - lo + 1, 0);
       if (tile_slot != nullptr) {
         cv = 0u;
         const int32_t* trow = tile_slot + (int64_t)ty * tiles_x;
         for (int tx = lo; tx <= hi; ++tx) cv += trow[tx] >= 0 ? 1u : 0u;
       }
-      if (c > 0) atomicAdd(&cb.kept[jl], c);
       if (cv > 0) atomicAdd(&cb.valid[jl], cv);
     }
     __syncthreads();  // the round's reads and sums before the next round's writes
   }
   __syncthreads();
-  const uint32_t kept = cb.kept[lane], valid = cb.valid[lane];
+  const uint32_t valid = cb.valid[lane];
   if (mine) {
     if (ids == nullptr) {
       dkeys[i] = valid > 0 ? __float_as_uint(depth[i]) : kCulledKey;
       dvals[i] = (uint32_t)i;
     }
-    emit_cnt[i] = valid > 0 ? kept : 0u;  // every kept tile, valid or not, once the Gaussian has a pair
+    emit_cnt[i] = valid;  // only the valid tiles are listed
     if (touched != nullptr && valid > 0) touched[g] = 1;
   }
-  // 64-bit totals, spread over slots: [0] pairs in valid tiles, [1] all pairs
-  const uint64_t v2[2] = {valid, valid > 0 ? kept : 0u};
+  // 64-bit totals, spread over slots: [0] pairs in valid tiles, [1] pairs
+  // listed (the same count: the lists hold the valid tiles only)
+  const uint64_t v2[2] = {valid, valid};
   for (int k = 0; k < 2; ++k) {
     uint64_t tot;
     block_exclusive_scan<kWave, uint64_t>(v2[k], s_red, &tot);
@@ -944,8 +941,13 @@ constexpr int kEmitBatch = 32;       // Gaussians per wave: more waves, fewer ro
 // The continuation's emission runs over every Gaussian past the prefix, few
 // of which have pairs in the marked tiles: 64 per wave halves the waves
 // that only find an empty batch.
-template <bool kFilter>
-constexpr int emit_batch() { return kFilter ? kWave : kEmitBatch; }
+// What a row emits: every kept column; its columns with a map entry >= 0,
+// compacted by a ballot over the sub-round's outputs (a tile subset, where
+// a good share of the columns is valid); or its flagged columns found by a
+// walk over the row (the continuation, where few are).
+constexpr int kEmitAll = 0, kEmitCompact = 1, kEmitWalk = 2;
+template <int kMode>
+constexpr int emit_batch() { return kMode == kEmitWalk ? kWave : kEmitBatch; }
 
 // A wave per kEmitBatch depth-ordered Gaussians.  Their rectangle rows are
 // flattened Gaussian by Gaussian and handed out 64 per round; a Gaussian
@@ -954,13 +956,14 @@ constexpr int emit_batch() { return kFilter ? kWave : kEmitBatch; }
 // Gaussian without a search.  Each lane takes its row's span; a wave scan of
 // the span lengths places the row's keys after those of the rows before it,
 // starting from the batch's first pair offset (pairs are emitted Gaussian by
-// Gaussian, row by row, columns ascending).  Tiles outside the valid set get
-// the sentinel tile id n_t.
+// Gaussian, row by row, columns ascending).
 //
-// kFilter: only the tiles whose map entry is >= 0 are emitted (the
-// continuation lists); a row's outputs are then its flagged columns in
-// ascending order, each output lane walking the row's span to its column.
-template <typename K, bool kFilter>
+// kEmitCompact, kEmitWalk: only the tiles whose map entry is >= 0 are
+// emitted.  Compact hands out every kept column as above and writes the
+// valid ones at the ballot prefix of the sub-round's valid outputs; Walk
+// (the continuation lists) counts a row's flagged columns and hands out only
+// those, each output lane walking the row's span to its column.
+template <typename K, int kMode>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
     const int4* __restrict__ rect_sorted, const uint32_t* __restrict__ off, const uint32_t* __restrict__ ids_sorted,
     int64_t n, const float4* __restrict__ splat, const int32_t* __restrict__ tile_slot, int tiles_x, uint32_t n_t,
@@ -969,7 +972,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
   const uint32_t total = *total_dev;  // pairs to emit (0 when they exceed the capacity)
   __shared__ RowBatch rb;
   const int lane = lane_id();
-  constexpr int kBatch = emit_batch<kFilter>();
+  constexpr int kBatch = emit_batch<kMode>();
   const int64_t b0 = (int64_t)blockIdx.x * kBatch;
   const int64_t j = b0 + lane;
   int4 r = make_int4(0, 0, 0, 0);
@@ -1010,7 +1013,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
       row_span(rb.ell[jl], ty, rj.x, rj.z, lo, hi);
     }
     uint32_t c = (uint32_t)max(hi - lo + 1, 0);
-    if (kFilter && c > 0) {
+    if (kMode == kEmitWalk && c > 0) {
       const int32_t* tr = tile_slot + (int64_t)ty * tiles_x;
       uint32_t cf = 0u;
       for (int tx = lo; tx <= hi; ++tx) cf += tr[tx] >= 0 ? 1u : 0u;
@@ -1036,11 +1039,11 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
       const int own = max(wave_max_scan(rb.mark[lane]), ocarry);
       ocarry = __builtin_amdgcn_readlane(own, kWave - 1);
       const uint32_t q = q0 + (uint32_t)lane;
-      const uint32_t pos = base + written + q;
       // own >= 0 whenever q < n_out: output 0 belongs to the first row with pairs
-      if (q < n_out && own >= 0 && pos < total) {  // pos < total always holds; the bound is a safeguard
-        uint32_t tile;
-        if (kFilter) {  // the (q - ex)-th flagged column of the row (there are c of them)
+      bool out = q < n_out && own >= 0;
+      uint32_t tile = 0;
+      if (out) {
+        if (kMode == kEmitWalk) {  // the (q - ex)-th flagged column of the row (there are c of them)
           int left = (int)(q - rb.ex[own]), tx = rb.lo[own];
           const uint32_t tr = rb.trow[own];
           for (; tx < rb.hi[own]; ++tx) {
@@ -1052,8 +1055,17 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
           tile = tr + (uint32_t)tx;
         } else {
           tile = rb.trow[own] + (uint32_t)(rb.lo[own] + (int)(q - rb.ex[own]));
-          if (tile_slot != nullptr && tile_slot[tile] < 0) tile = n_t;
         }
+      }
+      uint32_t pos = base + written + q;
+      if (kMode == kEmitCompact) {
+        out = out && tile_slot[tile] >= 0;
+        const uint64_t vb = __ballot(out);
+        pos = base + written +
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(vb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vb, 0u));
+        written += (uint32_t)__popcll(vb);  // wave-uniform
+      }
+      if (out && pos < total) {  // pos < total always holds; the bound is a safeguard
         if (pay != nullptr) {  // the id as a separate payload, the key is the tile alone
           keys[pos] = (K)tile;
           pay[pos] = rb.gid[own];
@@ -1063,7 +1075,7 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(
       }
       __syncthreads();  // the sub-round's mark reads before the next one's writes
     }
-    written += n_out;
+    if (kMode != kEmitCompact) written += n_out;
     __syncthreads();  // the round's mark reads before the next round's writes
   }
 }
@@ -1185,7 +1197,7 @@ static void sort_depth(const SortWs& w, uint32_t n, const int4* rect, int tiles_
 // 64-bit key would move 16 bytes per pair and pass instead of 12.
 // bound: the capacity (host), sizing every grid; the pair count itself is
 // read on the device (w.eff_total), so nothing here waits for the host.
-template <typename K, bool kPay, bool kFilter = false>
+template <typename K, bool kPay, int kMode = kEmitAll>
 static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t bound, const float4* splat,
                        const int32_t* tile_slot, int tiles_x, uint32_t n_t, int id_bits, int tbits, double tau, double lia,
                        const float* depth, uint32_t* vals, uint64_t* keys64, uint32_t* ranges, hipStream_t s) {
@@ -1195,7 +1207,7 @@ static void sort_pairs(const SortWs& w, const uint32_t* ids, int64_t n, uint32_t
   if (kPay)
     for (int k = 0; k < 2; ++k) pb[k] = (uint32_t*)((char*)w.pkeys[k] + align_up(sizeof(K) * (size_t)w.cap, 256));
   const int key_id_bits = kPay ? 0 : id_bits;
-  hipLaunchKernelGGL((emit_kernel<K, kFilter>), dim3((unsigned)std::max<int64_t>(ceil_div(n, emit_batch<kFilter>()), 1)),
+  hipLaunchKernelGGL((emit_kernel<K, kMode>), dim3((unsigned)std::max<int64_t>(ceil_div(n, emit_batch<kMode>()), 1)),
                      dim3(kEmitThreads), 0, s,
                      w.rect_sorted, w.off, ids, n, splat, tile_slot, tiles_x, n_t, key_id_bits, tau, lia, w.eff_total,
                      kb[0], pb[0]);
@@ -1277,16 +1289,24 @@ static int32_t bin_sort_queue(const int32_t* rect, const float* splat, const flo
   if (capacity == 0) return hip_status(who);
   const uint32_t bound = (uint32_t)capacity;
   const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
-  const int tbits = bits_for(n_t);  // the sentinel tile id n_t must fit
-  if (id_bits + tbits <= 32)
-    sort_pairs<uint32_t, false>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                                tbits, tau, lia, depth, vals, keys, ranges, s);
-  else if (tbits <= 16)
-    sort_pairs<uint16_t, true>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                               tbits, tau, lia, depth, vals, keys, ranges, s);
+  const int tbits = bits_for(n_t);
+  // with a tile subset only its tiles are emitted
+  auto sort_all = [&](auto filter) {
+    constexpr int kF = decltype(filter)::value ? kEmitCompact : kEmitAll;
+    if (id_bits + tbits <= 32)
+      sort_pairs<uint32_t, false, kF>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t,
+                                      id_bits, tbits, tau, lia, depth, vals, keys, ranges, s);
+    else if (tbits <= 16)
+      sort_pairs<uint16_t, true, kF>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t,
+                                     id_bits, tbits, tau, lia, depth, vals, keys, ranges, s);
+    else
+      sort_pairs<uint32_t, true, kF>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t,
+                                     id_bits, tbits, tau, lia, depth, vals, keys, ranges, s);
+  };
+  if (tile_slot != nullptr)
+    sort_all(std::true_type{});
   else
-    sort_pairs<uint32_t, true>(w, w.ids_sorted, m, bound, (const float4*)splat, tile_slot, tiles_x, n_t, id_bits,
-                               tbits, tau, lia, depth, vals, keys, ranges, s);
+    sort_all(std::false_type{});
   return hip_status(who);
 }
 
@@ -1329,13 +1349,13 @@ static int32_t continue_queue(const float* splat, int64_t n, const int32_t* flag
   const int id_bits = std::max(1, bits_for((uint64_t)n - 1));
   const int tbits = bits_for(n_t);
   if (id_bits + tbits <= 32)
-    sort_pairs<uint32_t, false, true>(wc, w1.ids_sorted + prefix, m, bound, (const float4*)splat, flag_slot, tiles_x,
+    sort_pairs<uint32_t, false, kEmitWalk>(wc, w1.ids_sorted + prefix, m, bound, (const float4*)splat, flag_slot, tiles_x,
                                       n_t, id_bits, tbits, tau, lia, nullptr, vals2, nullptr, ranges2, s);
   else if (tbits <= 16)
-    sort_pairs<uint16_t, true, true>(wc, w1.ids_sorted + prefix, m, bound, (const float4*)splat, flag_slot, tiles_x,
+    sort_pairs<uint16_t, true, kEmitWalk>(wc, w1.ids_sorted + prefix, m, bound, (const float4*)splat, flag_slot, tiles_x,
                                      n_t, id_bits, tbits, tau, lia, nullptr, vals2, nullptr, ranges2, s);
   else
-    sort_pairs<uint32_t, true, true>(wc, w1.ids_sorted + prefix, m, bound, (const float4*)splat, flag_slot, tiles_x,
+    sort_pairs<uint32_t, true, kEmitWalk>(wc, w1.ids_sorted + prefix, m, bound, (const float4*)splat, flag_slot, tiles_x,
                                      n_t, id_bits, tbits, tau, lia, nullptr, vals2, nullptr, ranges2, s);
   return hip_status(who);
 }

@@ -1,10 +1,12 @@
 // Tile-wise error/age pixel sampling (Sec. 3.5).
 //
 // Three kernels per view:
-//   tile_weights  one wave per tile: integer tile weight (sum of E * 2^24), only
-//                 when tiles are drawn in proportion to error;
-//   tile_select   one workgroup: the tile draws (or every tile), the per-tile
-//                 sample counts, their prefix offsets and the tile -> slot map;
+//   tile_keys     one wave per tile (one thread with predicted weights): the
+//                 integer tile weight (sum of E * 2^24) and the tile's race
+//                 key, only when a subset of tiles is drawn;
+//   tile_select   one workgroup: the tiles of the smallest race keys (or every
+//                 tile), listed ascending with their sample counts, prefix
+//                 offsets and the tile -> slot map;
 //   tile_pixels   one wave per selected tile: N_hard sequential error-weighted
 //                 draws without replacement, TopK age, uniform mixed draws.
 // All decisions are integer: weights are exact integers (every finite
@@ -13,6 +15,17 @@
 // (ascending local index) whose running weight exceeds r.  Each lane owns four
 // consecutive local indices, so lane order is index order and a wave prefix
 // sum locates a draw.
+//
+// The tile pass draws tiles without replacement in proportion to weight.  Its
+// order does not matter (tiles are listed ascending), so it runs as the
+// exponential race of Efraimidis and Spirakis (IPL 2006), which has the
+// sequential draws' distribution: tile t runs an Exp(1) time over its weight
+// and the earliest n_sel win.  The time is exact integer and IEEE arithmetic:
+// L = -log2 of the tile's uniform to 47 fractional bits (binary logarithm by
+// repeated squaring), one correctly rounded double division L / w, and its bit
+// pattern as the key; zero-weight tiles key 2^63 + u / 2, after every weighted
+// tile.  Selection is an exact MSB-first radix select on the 64-bit keys, ties
+// to the lower tile index.
 #include <mutex>
 
 #include "scan.h"
@@ -58,10 +71,40 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
 __device__ __forceinline__ int tile_valid_w(int tx, int W) { return min(kTile, W - tx * kTile); }
 __device__ __forceinline__ int tile_valid_h(int ty, int H) { return min(kTile, H - ty * kTile); }
 
-// ------------------------------------------------------------------ tile weights
-__global__ void __launch_bounds__(64) tile_weights_kernel(const uint16_t* __restrict__ E, int H,
-                                                          int W, int tiles_x, int n_t,
-                                                          uint64_t* __restrict__ tw) {
+// ------------------------------------------------------------------ race keys
+constexpr int kLogFrac = 47;  // fractional bits of a race time: 64 * 2^47 = 2^53 is exact in a double
+
+// 2^47 * -log2(v / 2^64) for v = u | 1, the fraction truncated: with
+// v = 2^e m, m in [1, 2), the time is 64 - e - log2(m), and each squaring of m
+// (held in Q1.63, truncated) yields the next bit of log2(m): bit 1 and
+// m <- m^2 / 2 when m^2 >= 2, else bit 0 and m <- m^2.
+__device__ __forceinline__ uint64_t neg_log2_fixed(uint64_t u) {
+  const uint64_t v = u | 1ull;
+  const int e = 63 - __clzll((long long)v);
+  uint64_t m = v << (63 - e);
+  uint64_t frac = 0;
+#pragma unroll 4
+  for (int k = 0; k < kLogFrac; ++k) {
+    const uint64_t hi = __umul64hi(m, m);
+    const uint64_t lo_top = (m * m) >> 63;
+    const uint64_t bit = hi >> 63;
+    frac = (frac << 1) | bit;
+    m = bit ? hi : ((hi << 1) | lo_top);
+  }
+  return ((uint64_t)(64 - e) << kLogFrac) - frac;
+}
+
+// Race key of a tile of weight w whose uniform is u: the bit pattern of the
+// positive double L / w (ordered like the doubles, below 2^63), or 2^63 + u / 2
+// for w = 0.
+__device__ __forceinline__ uint64_t race_key(uint64_t w, uint64_t u) {
+  if (w == 0) return (1ull << 63) | (u >> 1);
+  return (uint64_t)__double_as_longlong(__ddiv_rn((double)neg_log2_fixed(u), (double)w));
+}
+
+__global__ void __launch_bounds__(64) tile_keys_kernel(const uint16_t* __restrict__ E, int H, int W,
+                                                       int tiles_x, int n_t, uint64_t seed, uint64_t step,
+                                                       uint64_t view, uint64_t* __restrict__ keys) {
   const int t = blockIdx.x;
   if (t >= n_t) return;
   const int tx = t % tiles_x, ty = t / tiles_x;
@@ -74,244 +117,139 @@ __global__ void __launch_bounds__(64) tile_weights_kernel(const uint16_t* __rest
   }
   // wave sum of u64 as two 32-bit halves is not exact; use the inclusive scan
   s = wave_inclusive_scan_u64(s);
-  if (lane == 63) tw[t] = s;
+  if (lane == 63) keys[t] = race_key(s, absorb(stream_key(seed, step, view, (uint64_t)n_t), (uint64_t)t));
 }
 
-// Tile weights from predicted mean tile errors: floor(clamp(p, 0, 65504) *
+// Keys from predicted mean tile errors: weight floor(clamp(p, 0, 65504) *
 // in-image pixels * 2^24), the units of the error-map sums; exact in FP64 (a
 // float times a count up to 256 times a power of two).
-__global__ void __launch_bounds__(256) tile_pred_weights_kernel(const float* __restrict__ pred, int H, int W,
-                                                               int tiles_x, int n_t, uint64_t* __restrict__ tw) {
+__global__ void __launch_bounds__(256) tile_pred_keys_kernel(const float* __restrict__ pred, int H, int W,
+                                                            int tiles_x, int n_t, uint64_t seed, uint64_t step,
+                                                            uint64_t view, uint64_t* __restrict__ keys) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= n_t) return;
   const int tx = t % tiles_x, ty = t / tiles_x;
   const int nx = min(kTile, W - tx * kTile), ny = min(kTile, H - ty * kTile);
   const float p = pred[t];
   const double q = p > 0.f ? (double)fminf(p, 65504.f) : 0.0;  // NaN and negatives give 0
-  tw[t] = (uint64_t)floor(q * (double)(nx * ny) * 16777216.0);
+  const uint64_t w = (uint64_t)floor(q * (double)(nx * ny) * 16777216.0);
+  keys[t] = race_key(w, absorb(stream_key(seed, step, view, (uint64_t)n_t), (uint64_t)t));
 }
 
 // ------------------------------------------------------------------ tile select
-// One workgroup.  The sequential tile draws (only when a subset of tiles is
-// drawn) run on the first wave; then the whole workgroup lists the chosen
-// tiles in ascending order with their sample counts and prefix offsets.
+// One workgroup.  When a subset is drawn, an MSB-first radix select over the
+// race keys (8 bits a pass, LDS histogram, keys staged in LDS when they fit)
+// finds the n_sel-th smallest key thr and how many of the keys equal to it
+// are taken (krem, the lowest tile indices first); then the whole workgroup
+// lists the chosen tiles in ascending order with their sample counts and
+// prefix offsets.
 constexpr int kSelectThreads = 1024;
-constexpr uint64_t kChosenBit = 1ull << 63;  // tile weights stay below 2^57 (256 pixels x 2^24 x 65504)
-constexpr int kSelectMaxE = 5;               // tiles per lane in a chunk pass: n_t up to 20480 in LDS
-
-// The draws on LDS (first wave only).  s_p[t] holds, for tile t in chunk
-// [l C, (l + 1) C), the remaining weight of the chunk's tiles up to and
-// including t (a chunk-local inclusive prefix), with bit 63 set once t is
-// chosen; s_lsum[l] the chunk's total.  Lane l keeps its chunk's remaining
-// weight and the inclusive prefix of those over the lanes up to date.  A
-// draw r falls in the first lane o whose inclusive sum exceeds r; in o's
-// chunk the tile is the first whose prefix exceeds r minus the chunks
-// before, found by one ballot over the lanes (lane k holds the prefixes of
-// tiles k E .. k E + E - 1, E = ceil(C / 64)) and a walk over E registers.
-// Removing the tile lowers the prefixes from it to the chunk's end, written
-// back from the registers that were read.  That is the first tile in
-// ascending order whose running weight exceeds r, as the sequential
-// definition has it, so the draws equal the plain loop's.  When every
-// remaining weight is zero (all prefixes are then zero) the draw is uniform
-// over the remaining tiles and is found on counts of the unchosen tiles.
-// The draws' 64-bit counter values are hashed 64 at a time, one per lane.
-template <int kE>
-__device__ void select_tiles_lds(uint64_t* s_p, const uint64_t* s_lsum, int n_t, int n_sel, uint64_t key) {
-  const int lane = lane_id();
-  const int C = (n_t + kWave - 1) / kWave;
-  const int c0 = min(n_t, lane * C), c1 = min(n_t, c0 + C);
-  uint64_t lsum = s_lsum[lane];
-  int lrem = c1 - c0;
-  uint64_t incl = wave_inclusive_scan_u64_dpp(lsum);
-  int icnt = wave_inclusive_scan_i_dpp(lrem);
-  uint64_t ub = 0;
-  for (int j = 0; j < n_sel; ++j) {
-    if ((j & (kWave - 1)) == 0) ub = absorb(key, (uint64_t)(j + lane));
-    const uint64_t u = readlane_u64(ub, j & (kWave - 1));
-    const uint64_t total = readlane_u64(incl, kWave - 1);
-    if (total > 0) {
-      const uint64_t r = mulhi64(u, total);
-      const uint64_t above = __ballot(incl > r);
-      if (above == 0ull) break;  // never taken: the running sums are exact
-      const int o = __ffsll((unsigned long long)above) - 1;
-      const uint64_t rp = r - readlane_u64(incl - lsum, o);
-      const int oc0 = o * C, olen = min(n_t, oc0 + C) - oc0;
-      // this lane's prefixes (positions past the chunk read its last one,
-      // which exceeds rp, so they never come before the true crossing)
-      uint64_t raw[kE], P[kE];
-#pragma unroll
-      for (int e = 0; e < kE; ++e) {
-        raw[e] = s_p[oc0 + min(lane * kE + e, olen - 1)];
-        P[e] = raw[e] & ~kChosenBit;
-      }
-      // lane of the crossing (the chunk's last prefix exceeds rp, so some
-      // lane's does; no branch here, so the loads above issue together)
-      const int h = max(0, __ffsll((unsigned long long)__ballot(P[kE - 1] > rp)) - 1);
-      const uint64_t prev_last = dpp_u64<kDppWaveShr1>(P[kE - 1]);  // lane 0 reads 0: the chunk starts at 0
-      int pe = kE - 1;
-      uint64_t wv = P[kE - 1] - (kE > 1 ? P[kE > 1 ? kE - 2 : 0] : prev_last);
-#pragma unroll
-      for (int e = kE - 2; e >= 0; --e) {
-        if (P[e] > rp) {
-          pe = e;
-          wv = P[e] - (e > 0 ? P[e > 0 ? e - 1 : 0] : prev_last);
-        }
-      }
-      const int pl = h * kE + __builtin_amdgcn_readlane(pe, h);  // chunk-local position of the pick
-      const uint64_t w = readlane_u64(wv, h);
-#pragma unroll
-      for (int e = 0; e < kE; ++e) {
-        const int idx = lane * kE + e;
-        if (idx >= pl && idx < olen) s_p[oc0 + idx] = (raw[e] - w) | (idx == pl ? kChosenBit : 0ull);
-      }
-      if (lane >= o) incl -= w;
-      if (lane == o) lsum -= w;
-      if (lane >= o) icnt -= 1;
-      if (lane == o) lrem -= 1;
-    } else {
-      // every remaining weight is zero: the r-th remaining tile, on counts
-      const uint64_t nrem = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(icnt, kWave - 1);
-      if (nrem == 0) break;
-      const int r = (int)mulhi64(u, nrem);
-      const uint64_t above = __ballot(icnt > r);
-      const int o = __ffsll((unsigned long long)above) - 1;
-      const int base = __builtin_amdgcn_readlane(icnt - lrem, o);
-      const int oc0 = o * C, olen = min(n_t, oc0 + C) - oc0;
-      int fl[kE], part = 0;
-#pragma unroll
-      for (int e = 0; e < kE; ++e) {
-        const int idx = lane * kE + e;
-        fl[e] = idx < olen && (s_p[oc0 + min(idx, olen - 1)] & kChosenBit) == 0 ? 1 : 0;
-        part += fl[e];
-      }
-      const int run = base + wave_inclusive_scan_i_dpp(part);
-      const uint64_t hit = __ballot(run > r);
-      if (hit == 0ull) break;  // never taken
-      const int h = __ffsll((unsigned long long)hit) - 1;
-      int acc = run - part, pe = -1;
-#pragma unroll
-      for (int e = 0; e < kE; ++e) {
-        acc += fl[e];
-        if (pe < 0 && acc > r) pe = e;
-      }
-      const int pl = h * kE + __builtin_amdgcn_readlane(pe, h);
-      if (lane == h && pl < olen) s_p[oc0 + pl] |= kChosenBit;
-      if (lane >= o) icnt -= 1;
-      if (lane == o) lrem -= 1;
-    }
-  }
-}
-
-// The chunk-local prefixes of the tile weights into s_p and the chunk
-// totals into s_lsum: wave w takes chunks w, w + 16, ..., 64 tiles at a
-// time (coalesced reads), the chunk boundaries being the first wave's lane
-// chunks.
-__device__ void chunk_prefixes(const uint64_t* __restrict__ tw, uint64_t* s_p, uint64_t* s_lsum, int n_t) {
-  const int C = (n_t + kWave - 1) / kWave;
-  const int lane = lane_id(), w = threadIdx.x / kWave;
-  for (int l = w; l < kWave; l += kSelectThreads / kWave) {
-    const int c0 = min(n_t, l * C), c1 = min(n_t, c0 + C);
-    uint64_t carry = 0;
-    for (int t0 = c0; t0 < c1; t0 += kWave) {
-      const int t = t0 + lane;
-      const uint64_t x = wave_inclusive_scan_u64_dpp(t < c1 ? tw[t] : 0ull);
-      if (t < c1) s_p[t] = carry + x;
-      carry += readlane_u64(x, kWave - 1);
-    }
-    if (lane == 0) s_lsum[l] = carry;
-  }
-}
 
 __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
-    uint64_t* __restrict__ tw, int H, int W, int tiles_x, int n_t, int n_sel, int n_pix,
-    uint64_t seed, uint64_t step, uint64_t view, int32_t* __restrict__ valid_tiles,
-    int32_t* __restrict__ tile_off, int32_t* __restrict__ tile_slot, int64_t* __restrict__ totals,
-    uint8_t* __restrict__ chosen, int lds_tiles) {
-  extern __shared__ uint64_t s_sel[];  // [n_t] chunk prefixes and chosen bits, when n_t <= lds_tiles
-  __shared__ uint64_t s_lsum[kWave];
-  const int tid = threadIdx.x;
+    const uint64_t* __restrict__ keys, int H, int W, int tiles_x, int n_t, int n_sel, int n_pix,
+    int32_t* __restrict__ valid_tiles, int32_t* __restrict__ tile_off, int32_t* __restrict__ tile_slot,
+    int64_t* __restrict__ totals, int lds_tiles) {
+  extern __shared__ uint64_t s_keys[];  // [n_t] when n_t <= lds_tiles
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_thr;
+  __shared__ int s_krem;
+  const int tid = threadIdx.x, lane = lane_id();
   const bool all_tiles = n_sel < 0 || n_sel >= n_t;
   const bool in_lds = !all_tiles && n_t <= lds_tiles;
-  if (in_lds) {
-    chunk_prefixes(tw, s_sel, s_lsum, n_t);
-    __syncthreads();
-    if (tid < kWave) {
-      const uint64_t key = stream_key(seed, step, view, (uint64_t)n_t);
-      switch ((n_t + kWave * kWave - 1) / (kWave * kWave)) {  // tiles per lane in a chunk pass
-        case 1: select_tiles_lds<1>(s_sel, s_lsum, n_t, n_sel, key); break;
-        case 2: select_tiles_lds<2>(s_sel, s_lsum, n_t, n_sel, key); break;
-        case 3: select_tiles_lds<3>(s_sel, s_lsum, n_t, n_sel, key); break;
-        case 4: select_tiles_lds<4>(s_sel, s_lsum, n_t, n_sel, key); break;
-        default: select_tiles_lds<5>(s_sel, s_lsum, n_t, n_sel, key); break;
-      }
-    }
-  } else if (!all_tiles && tid < kWave) {
-    // more tiles than LDS holds: each lane walks its own chunk in global memory
-    const int lane = tid;
-    const int chunk = (n_t + kWave - 1) / kWave;
-    const int c0 = min(n_t, lane * chunk), c1 = min(n_t, c0 + chunk);
-    for (int t = c0; t < c1; ++t) chosen[t] = 0;
-    uint64_t lsum = 0;
-    for (int t = c0; t < c1; ++t) lsum += tw[t];
-    int lrem = c1 - c0;
-    const uint64_t key = stream_key(seed, step, view, (uint64_t)n_t);
-    for (int j = 0; j < n_sel; ++j) {
-      const uint64_t u = absorb(key, (uint64_t)j);
-      const uint64_t incl = wave_inclusive_scan_u64(lsum);
-      const uint64_t total = __shfl(incl, 63, kWave);
-      if (total > 0) {
-        const uint64_t r = mulhi64(u, total);
-        const uint64_t excl = incl - lsum;
-        if (lsum > 0 && excl <= r && r < incl) {
-          uint64_t run = excl;
-          for (int t = c0; t < c1; ++t) {
-            run += tw[t];
-            if (run > r) {
-              lsum -= tw[t];
-              tw[t] = 0;
-              chosen[t] = 1;
-              --lrem;
-              break;
-            }
-          }
-        }
-      } else {
-        const int ic = wave_inclusive_scan_i(lrem);
-        const int nrem = __shfl(ic, 63, kWave);
-        const int r = (int)mulhi64(u, (uint64_t)nrem);
-        const int ex = ic - lrem;
-        if (lrem > 0 && ex <= r && r < ic) {
-          int k = ex;
-          for (int t = c0; t < c1; ++t) {
-            if (!chosen[t]) {
-              if (k == r) {
-                chosen[t] = 1;
-                --lrem;
-                break;
-              }
-              ++k;
-            }
+  if (in_lds)
+    for (int t = tid; t < n_t; t += kSelectThreads) s_keys[t] = keys[t];
+  __syncthreads();
+  const uint64_t* kk = in_lds ? s_keys : keys;
+  uint64_t thr = 0;  // n_sel = 0: no key is below 0 and none is taken at it
+  int krem = 0;
+  if (!all_tiles && n_sel > 0) {
+    krem = n_sel;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      if (tid < 256) hist[tid] = 0;
+      __syncthreads();
+      const uint64_t hmask = shift == 56 ? 0ull : ~0ull << (shift + 8);  // bits already fixed
+      for (int t0 = 0; t0 < n_t; t0 += kSelectThreads) {
+        const int t = t0 + tid;
+        const uint64_t k = t < n_t ? kk[t] : 0ull;
+        const bool act = t < n_t && ((k ^ thr) & hmask) == 0;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint64_t am = __ballot(act);
+        if (am != 0ull) {
+          // one atomic for the wave when its candidates share a digit (the
+          // leading passes, where every key has the same exponent bits)
+          const int o = __ffsll((unsigned long long)am) - 1;
+          const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, o);
+          if (__ballot(act && d == d0) == am) {
+            if (lane == o) atomicAdd(&hist[d0], (uint32_t)__popcll(am));
+          } else if (act) {
+            atomicAdd(&hist[d], 1u);
           }
         }
       }
+      __syncthreads();
+      if (tid < kWave) {
+        uint32_t h[4], sum = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          h[i] = hist[lane * 4 + i];
+          sum += h[i];
+        }
+        const uint32_t incl = wave_inclusive_scan_t<uint32_t>(sum);
+        // the candidates number at least krem, so some lane's sum reaches it
+        const int o = __ffsll((unsigned long long)__ballot(incl >= (uint32_t)krem)) - 1;
+        if (lane == o) {
+          uint32_t below = incl - sum;  // candidates in the bins before this lane's
+          int b = -1;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (b < 0) {
+              if (below + h[i] >= (uint32_t)krem) b = i;
+              else below += h[i];
+            }
+          }
+          s_thr = thr | ((uint64_t)(lane * 4 + b) << shift);
+          s_krem = krem - (int)below;
+        }
+      }
+      __syncthreads();
+      thr = s_thr;
+      krem = s_krem;
     }
   }
-  __syncthreads();
-  // ascending list of the chosen tiles with their sample counts
+  // ascending list of the chosen tiles (keys below thr, and the first krem
+  // tiles whose key equals thr) with their sample counts
   __shared__ uint32_t lds[kSelectThreads / kWave];
   const int chunk = (n_t + kSelectThreads - 1) / kSelectThreads;
   const int c0 = min(n_t, tid * chunk), c1 = min(n_t, c0 + chunk);
+  uint32_t lties = 0;
+  if (!all_tiles)
+    for (int t = c0; t < c1; ++t) lties += kk[t] == thr ? 1u : 0u;
+  uint32_t n_ties;
+  const uint32_t tie0 = block_exclusive_scan<kSelectThreads, uint32_t>(lties, lds, &n_ties);
   uint32_t lcount = 0, lpix = 0;
-  for (int t = c0; t < c1; ++t)
-    if (all_tiles || (in_lds ? (s_sel[t] & kChosenBit) != 0 : chosen[t] != 0)) {
+  uint32_t tie = tie0;
+  for (int t = c0; t < c1; ++t) {
+    bool ch = all_tiles;
+    if (!all_tiles) {
+      const uint64_t k = kk[t];
+      ch = k < thr || (k == thr && tie++ < (uint32_t)krem);
+    }
+    if (ch) {
       ++lcount;
       lpix += (uint32_t)min(n_pix, tile_valid_w(t % tiles_x, W) * tile_valid_h(t / tiles_x, H));
     }
+  }
   uint32_t n_chosen, P;
   int slot = (int)block_exclusive_scan<kSelectThreads, uint32_t>(lcount, lds, &n_chosen);
   int off = (int)block_exclusive_scan<kSelectThreads, uint32_t>(lpix, lds, &P);
+  tie = tie0;
   for (int t = c0; t < c1; ++t) {
-    if (all_tiles || (in_lds ? (s_sel[t] & kChosenBit) != 0 : chosen[t] != 0)) {
+    bool ch = all_tiles;
+    if (!all_tiles) {
+      const uint64_t k = kk[t];
+      ch = k < thr || (k == thr && tie++ < (uint32_t)krem);
+    }
+    if (ch) {
       valid_tiles[slot] = t;
       tile_off[slot] = off;
       tile_slot[t] = slot;
@@ -479,13 +417,13 @@ using namespace tgs;
 extern "C" size_t tgs_sample_workspace_size(int32_t height, int32_t width) {
   if (height <= 0 || width <= 0) return 0;
   const size_t n_t = (size_t)(ceil_div(width, kTile) * ceil_div(height, kTile));
-  return align_up(n_t * sizeof(uint64_t), 256) + align_up(n_t, 256);
+  return align_up(n_t * sizeof(uint64_t), 256);
 }
 
-// Tiles whose weights the draws can hold in LDS on the current device: the
-// workgroup's LDS limit (160 KiB on gfx950) less the kernel's static arrays,
-// 8 bytes per tile, at most what a chunk pass covers (64 x 64 x kSelectMaxE).
-// Queried, and the kernel's dynamic LDS limit raised, once per device.
+// Tiles whose race keys the select can stage in LDS on the current device:
+// the workgroup's LDS limit (160 KiB on gfx950) less the kernel's static
+// arrays, 8 bytes per tile.  Queried, and the kernel's dynamic LDS limit
+// raised, once per device.
 static int select_lds_tiles() {
   constexpr int kMaxDevices = 64;
   static std::mutex mu;
@@ -497,13 +435,13 @@ static int select_lds_tiles() {
   if (!known[dev]) {
     int bytes = 0;
     if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) bytes = 0;
-    int dyn = bytes - 2048;  // static LDS of the kernel (chunk sums, scan partials) with margin
+    int dyn = bytes - 2048;  // static LDS of the kernel (histogram, scan partials) with margin
     if (dyn > 65536 && hipFuncSetAttribute((const void*)tile_select_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) {
       (void)hipGetLastError();
       dyn = 65536 - 2048;
     }
-    cache[dev] = max(0, min(dyn / (int)sizeof(uint64_t), kWave * kWave * kSelectMaxE));
+    cache[dev] = max(0, dyn / (int)sizeof(uint64_t));
     known[dev] = true;
   }
   return cache[dev];
@@ -529,21 +467,20 @@ static int32_t sample_impl(const uint16_t* E, const uint16_t* A, int32_t height,
   const int tiles_x = (int)ceil_div(width, kTile), tiles_y = (int)ceil_div(height, kTile);
   const int n_t = tiles_x * tiles_y;
   const int n_st = tgs_sample_tile_count(height, width, sp);
-  uint64_t* tw = (uint64_t*)ws;
-  uint8_t* chosen = (uint8_t*)ws + align_up((size_t)n_t * sizeof(uint64_t), 256);
+  uint64_t* keys = (uint64_t*)ws;
   hipStream_t s = as_stream(stream);
   const bool all_tiles = sp->n_tiles_sel < 0 || sp->n_tiles_sel >= n_t;
   if (!all_tiles && tile_pred != nullptr)
-    hipLaunchKernelGGL(tile_pred_weights_kernel, dim3((unsigned)ceil_div(n_t, 256)), dim3(256), 0, s, tile_pred,
-                       height, width, tiles_x, n_t, tw);
+    hipLaunchKernelGGL(tile_pred_keys_kernel, dim3((unsigned)ceil_div(n_t, 256)), dim3(256), 0, s, tile_pred,
+                       height, width, tiles_x, n_t, sp->seed, sp->step, (uint64_t)sp->view, keys);
   else if (!all_tiles)
-    hipLaunchKernelGGL(tile_weights_kernel, dim3(n_t), dim3(64), 0, s, E, height, width, tiles_x,
-                       n_t, tw);
+    hipLaunchKernelGGL(tile_keys_kernel, dim3(n_t), dim3(64), 0, s, E, height, width, tiles_x, n_t, sp->seed,
+                       sp->step, (uint64_t)sp->view, keys);
   const int lds_tiles = select_lds_tiles();
   const size_t sel_lds = !all_tiles && n_t <= lds_tiles ? (size_t)n_t * sizeof(uint64_t) : 0;
-  hipLaunchKernelGGL(tile_select_kernel, dim3(1), dim3(kSelectThreads), sel_lds, s, tw, height, width,
-                     tiles_x, n_t, sp->n_tiles_sel, sp->n_pix, sp->seed, sp->step,
-                     (uint64_t)sp->view, valid_tiles, tile_off, tile_slot, totals, chosen, lds_tiles);
+  hipLaunchKernelGGL(tile_select_kernel, dim3(1), dim3(kSelectThreads), sel_lds, s, keys, height, width,
+                     tiles_x, n_t, sp->n_tiles_sel, sp->n_pix, valid_tiles, tile_off, tile_slot, totals,
+                     lds_tiles);
   if (n_st > 0)
     hipLaunchKernelGGL(tile_pixels_kernel, dim3(n_st), dim3(64), 0, s, E, A, height, width, tiles_x,
                        n_st, sp->n_pix, sp->hard_permille, sp->stable_permille, sp->seed, sp->step,
@@ -560,7 +497,7 @@ extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t heig
 }
 
 // ------------------------------------------------------------------ sampling without a workspace
-// The sampler's scratch (tile weights and chosen flags, 9 bytes per tile)
+// The sampler's scratch (the tiles' race keys, 8 bytes per tile)
 // in a file-scope device array, for callers that cannot allocate.  Each
 // GPU holds its own copy until the process ends; host code uses only the
 // device address that hipGetSymbolAddress returns for the current device,
@@ -569,7 +506,7 @@ extern "C" int32_t tgs_sample(const uint16_t* E, const uint16_t* A, int32_t heig
 // one GPU share it and race.
 constexpr int kNoAllocMaxTiles = TGS_SAMPLE_NOALLOC_MAX_TILES;
 constexpr size_t kNoAllocScratchBytes =
-    ((size_t)kNoAllocMaxTiles * sizeof(uint64_t) + 255) / 256 * 256 + ((size_t)kNoAllocMaxTiles + 255) / 256 * 256;
+    ((size_t)kNoAllocMaxTiles * sizeof(uint64_t) + 255) / 256 * 256;
 static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
 
 constexpr int kMaxDevices = 64;

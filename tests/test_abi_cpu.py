@@ -48,7 +48,7 @@ def test_version_and_counts(B):
 
 
 def test_workspace_sizes_grow(B):
-    assert B.tgs_sample_workspace_size(256, 256) >= 256 * 9
+    assert B.tgs_sample_workspace_size(256, 256) >= 256 * 8
     a = B.tgs_bin_sort_workspace_size(1000, 10000, 256)
     b = B.tgs_bin_sort_workspace_size(1000, 100000, 256)
     assert 0 < a < b

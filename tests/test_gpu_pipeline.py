@@ -204,10 +204,13 @@ def test_c1_training_step_matches_oracle(B, c1_inputs, fused):
     scale += 4.0 * np.abs(resp).max(axis=0)
     loss_gpu = tr.loss_value(used)
     assert abs(loss_gpu - ref["loss"]) <= 1e-4 * abs(ref["loss"])
+    # this draw flags 7 of 16,384 samples in 7 tiles, each listing ~300 of the
+    # 10k Gaussians: 19% are excluded, 7,519 touched ones remain compared
     ex = _excluded_gaussians(ref, range(4), n)
-    assert ex.mean() < 0.15, ex.mean()
+    assert ex.mean() < 0.25, ex.mean()
+    assert sum(int(ref["views"][v]["fwd"]["out"]["flag"].sum()) for v in range(4)) <= 8
     t_gpu = host(tr.touched).astype(bool)
-    assert np.array_equal(t_gpu[~ex], ref["touched"][~ex]) and ref["touched"].sum() > 2000
+    assert np.array_equal(t_gpu[~ex], ref["touched"][~ex]) and (ref["touched"] & ~ex).sum() > 7000
     keep = ~ex
     tol_g = 1e-4 * np.abs(ref["grad"]) + scale + 1e-30
     if fused in (False, "streams"):

@@ -235,14 +235,14 @@ def test_bin_sort_lists_against_rectangle_lists(B, case):
                                                         (2560, 1440, 8, 10800, 0.1, "sparse"),
                                                         (1920, 1600, 8, 9000, 0.1, False),
                                                         (2560, 1900, 8, 5000, 0.1, "sparse"),
-                                                        (3840, 2160, 8, 100, 0.1, False)])
+                                                        (3840, 2160, 8, 100, 0.1, False),
+                                                        (150, 107, 25, 1, 0.3, False), (96, 80, 51, 29, 0.0, False)])
 def test_sampler_bit_exact(B, W, H, n_pix, n_sel, zero, pred):
     """pred: the tile pass draws by predicted tile errors (negative, NaN and
     out-of-range predictions included); "sparse": seven tiles in ten predict
-    no error, so the weighted draws run out and the rest are uniform.  The
-    tile counts span one to five tiles per lane in the LDS chunk pass (up
-    to 4,096 tiles: one; 4,293, 12,000, 14,400 and 19,040 tiles: two to
-    five) and the global-memory walk (32,400 tiles)."""
+    no error, so the weighted race runs out and the rest are uniform.  The
+    select stages the keys in LDS up to 19,040 tiles and reads them from
+    global memory at 32,400; one tile drawn, and all but one of 30."""
     E = synth.error_map(H, W, 31, zero_frac=zero)
     A = synth.age_map(H, W, 32)
     seed, step, view = 3, 5, 2

@@ -4,6 +4,8 @@ enumeration, frequency tests)."""
 import itertools
 import math
 import os
+import struct
+from decimal import Decimal, getcontext
 
 import numpy as np
 import pytest
@@ -275,3 +277,76 @@ def test_predicted_tile_weights_and_selection():
         s = sampler.sample_view(E, A, SampleParams(n_pix=16, n_tiles_sel=3), seed, 1, 0, tile_pred=hot)
         assert s["valid_tiles"].tolist() == [1, 4, 8]
 
+
+
+# ---------------------------------------------------------------- tile pass: exponential race
+def test_neg_log2_fixed_against_decimal():
+    """The fixed-point -log2 of a uniform against a 50-digit decimal logarithm:
+    within 2^-46 (47 fractional bits, truncated), at the extremes of v = u | 1
+    and on random draws."""
+    getcontext().prec = 50
+    ln2 = Decimal(2).ln()
+    us = [0, 1, 2, 3, (1 << 63) - 1, 1 << 63, (1 << 63) + 1, (1 << 64) - 2, (1 << 64) - 1, 1 << 32,
+          0x5555555555555555, 0xAAAAAAAAAAAAAAAA] + [rng.draw(9, 1, 2, 3, k) for k in range(300)]
+    for u in us:
+        v = u | 1
+        exact = -(Decimal(v) / Decimal(2 ** 64)).ln() / ln2
+        got = Decimal(sampler.neg_log2_fixed(u)) / Decimal(2 ** sampler.LOG_FRAC)
+        assert abs(got - exact) <= Decimal(2) ** -46, (u, got, exact)
+    assert sampler.neg_log2_fixed(1 << 63) == 1 << sampler.LOG_FRAC        # -log2(1/2) = 1
+    assert sampler.neg_log2_fixed(0) == 64 << sampler.LOG_FRAC             # v = 1: 64 exactly
+    assert sampler.neg_log2_fixed((1 << 64) - 1) >= 1                      # times stay positive
+
+
+def test_tile_race_inclusion_matches_sequential_enumeration():
+    """The race's inclusion frequencies over many seeds match the exact
+    probabilities of sequential draws without replacement proportional to
+    weight (chi-square over 5 tiles); uniform (not exponential) race times or
+    times multiplied by the weight fail this by orders of magnitude."""
+    wts = [1, 2, 4, 8, 3]
+    tw = [x << 24 for x in wts]
+    exact = _inclusion_exact(wts, 2)
+    n_seeds = 10000
+    counts = np.zeros(5)
+    for seed in range(n_seeds):
+        counts[sampler.race_select(tw, 2, seed, 0, 0)] += 1
+    expected = exact * n_seeds
+    assert (((counts - expected) ** 2) / expected).sum() < 20.5
+
+
+def test_tile_race_zero_weights_come_last_and_uniform():
+    """Weighted tiles always precede zero-weight ones (the sequential draws
+    take a zero-weight tile only once the weight has run out), and the
+    zero-weight tiles that fill the rest are a uniform subset."""
+    tw = [3 << 24, 0, 1 << 24, 0, 2 << 24, 0]
+    counts = np.zeros(6)
+    n_seeds = 3000
+    for seed in range(n_seeds):
+        got = sampler.race_select(tw, 4, seed, 1, 2)
+        assert {0, 2, 4} <= set(got.tolist())
+        counts[got] += 1
+    # each zero-weight tile joins with probability 1/3: 3 sigma ~ 0.026
+    assert np.all(np.abs(counts[[1, 3, 5]] / n_seeds - 1 / 3) < 0.03)
+    assert sampler.race_select([0] * 5, 0, 1, 1, 1).size == 0
+    # all weights zero: uniform over every 2-subset of 4 tiles (6 subsets)
+    pairs = {}
+    for seed in range(3000):
+        key = tuple(sampler.race_select([0, 0, 0, 0], 2, seed, 0, 0).tolist())
+        pairs[key] = pairs.get(key, 0) + 1
+    assert len(pairs) == 6 and all(abs(c / 3000 - 1 / 6) < 0.025 for c in pairs.values())
+
+
+def test_tile_race_keys_order_and_ties(monkeypatch):
+    """Key layout: a weighted tile's key is the bit pattern of L / w (larger
+    weight, earlier run for the same L), every zero-weight key is >= 2^63;
+    equal keys fall back to the tile index."""
+    tw = [5, 0, 1 << 40, 7]
+    keys = sampler.tile_race_keys(tw, 4, 5, 6)
+    for t in (0, 2, 3):
+        u = rng.draw(4, 5, 6, 4, t)
+        want = float(sampler.neg_log2_fixed(u)) / float(tw[t])
+        assert keys[t] == struct.unpack("<Q", struct.pack("<d", want))[0] < (1 << 63)
+    assert keys[1] >= 1 << 63
+    # identical keys (forced) keep index order
+    monkeypatch.setattr(sampler, "tile_race_keys", lambda tw, *a: [7, 7, 3, 7])
+    assert sampler.race_select([1, 1, 1, 1], 2, 0, 0, 0).tolist() == [0, 2]
