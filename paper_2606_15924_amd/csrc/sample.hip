@@ -4,9 +4,10 @@
 //   tile_keys     one wave per tile (one thread with predicted weights): the
 //                 integer tile weight (sum of E * 2^24) and the tile's race
 //                 key, only when a subset of tiles is drawn;
-//   tile_select   one workgroup: the tiles of the smallest race keys (or every
-//                 tile), listed ascending with their sample counts, prefix
-//                 offsets and the tile -> slot map;
+//   tile_select   one workgroup: the tiles of the smallest race keys, listed
+//                 ascending with their sample counts, prefix offsets and the
+//                 tile -> slot map (every tile: a thread per tile, closed
+//                 form);
 //   tile_pixels   one wave per selected tile: N_hard sequential error-weighted
 //                 draws without replacement, TopK age, uniform mixed draws.
 // All decisions are integer: weights are exact integers (every finite
@@ -137,12 +138,40 @@ __global__ void __launch_bounds__(256) tile_pred_keys_kernel(const float* __rest
 }
 
 // ------------------------------------------------------------------ tile select
-// One workgroup.  When a subset is drawn, an MSB-first radix select over the
-// race keys (8 bits a pass, LDS histogram, keys staged in LDS when they fit)
-// finds the n_sel-th smallest key thr and how many of the keys equal to it
-// are taken (krem, the lowest tile indices first); then the whole workgroup
-// lists the chosen tiles in ascending order with their sample counts and
-// prefix offsets.
+// Every tile: a thread per tile writes its slot and its sample offset in
+// closed form (every tile column but the last is 16 pixels wide, every row
+// but the last 16 high), so no single-workgroup pass has to wait for a free
+// compute unit while other streams' kernels fill the device.
+__global__ void __launch_bounds__(256) tile_list_all_kernel(int H, int W, int tiles_x, int tiles_y, int n_pix,
+                                                            int32_t* __restrict__ valid_tiles,
+                                                            int32_t* __restrict__ tile_off,
+                                                            int32_t* __restrict__ tile_slot,
+                                                            int64_t* __restrict__ totals) {
+  const int n_t = tiles_x * tiles_y;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t > n_t) return;
+  const int wl = W - (tiles_x - 1) * kTile, hl = H - (tiles_y - 1) * kTile;  // last column's width, last row's height
+  const int64_t row16 = (int64_t)(tiles_x - 1) * min(n_pix, kTile * kTile) + min(n_pix, wl * kTile);
+  const int ty = t / tiles_x, tx = t % tiles_x;  // t = n_t: ty = tiles_y, tx = 0
+  int64_t off = (int64_t)min(ty, tiles_y - 1) * row16;
+  if (ty == tiles_y) off += (int64_t)(tiles_x - 1) * min(n_pix, kTile * hl) + min(n_pix, wl * hl);
+  else off += (int64_t)tx * min(n_pix, kTile * (ty == tiles_y - 1 ? hl : kTile));
+  tile_off[t] = (int32_t)off;
+  if (t < n_t) {
+    valid_tiles[t] = t;
+    tile_slot[t] = t;
+  } else {
+    atomicAdd((unsigned long long*)&totals[0], (unsigned long long)off);
+    atomicAdd((unsigned long long*)&totals[1], (unsigned long long)n_t);
+  }
+}
+
+// A subset: one workgroup.  An MSB-first radix select over the race keys (8
+// bits a pass, LDS histogram, keys staged in LDS when they fit) finds the
+// n_sel-th smallest key thr and how many of the keys equal to it are taken
+// (krem, the lowest tile indices first); then the whole workgroup lists the
+// chosen tiles in ascending order with their sample counts and prefix
+// offsets.
 constexpr int kSelectThreads = 1024;
 
 __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
@@ -154,15 +183,14 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
   __shared__ uint64_t s_thr;
   __shared__ int s_krem;
   const int tid = threadIdx.x, lane = lane_id();
-  const bool all_tiles = n_sel < 0 || n_sel >= n_t;
-  const bool in_lds = !all_tiles && n_t <= lds_tiles;
+  const bool in_lds = n_t <= lds_tiles;  // 0 <= n_sel < n_t here
   if (in_lds)
     for (int t = tid; t < n_t; t += kSelectThreads) s_keys[t] = keys[t];
   __syncthreads();
   const uint64_t* kk = in_lds ? s_keys : keys;
   uint64_t thr = 0;  // n_sel = 0: no key is below 0 and none is taken at it
   int krem = 0;
-  if (!all_tiles && n_sel > 0) {
+  if (n_sel > 0) {
     krem = n_sel;
     for (int shift = 56; shift >= 0; shift -= 8) {
       if (tid < 256) hist[tid] = 0;
@@ -222,18 +250,14 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
   const int chunk = (n_t + kSelectThreads - 1) / kSelectThreads;
   const int c0 = min(n_t, tid * chunk), c1 = min(n_t, c0 + chunk);
   uint32_t lties = 0;
-  if (!all_tiles)
-    for (int t = c0; t < c1; ++t) lties += kk[t] == thr ? 1u : 0u;
+  for (int t = c0; t < c1; ++t) lties += kk[t] == thr ? 1u : 0u;
   uint32_t n_ties;
   const uint32_t tie0 = block_exclusive_scan<kSelectThreads, uint32_t>(lties, lds, &n_ties);
   uint32_t lcount = 0, lpix = 0;
   uint32_t tie = tie0;
   for (int t = c0; t < c1; ++t) {
-    bool ch = all_tiles;
-    if (!all_tiles) {
-      const uint64_t k = kk[t];
-      ch = k < thr || (k == thr && tie++ < (uint32_t)krem);
-    }
+    const uint64_t k = kk[t];
+    const bool ch = k < thr || (k == thr && tie++ < (uint32_t)krem);
     if (ch) {
       ++lcount;
       lpix += (uint32_t)min(n_pix, tile_valid_w(t % tiles_x, W) * tile_valid_h(t / tiles_x, H));
@@ -244,11 +268,8 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
   int off = (int)block_exclusive_scan<kSelectThreads, uint32_t>(lpix, lds, &P);
   tie = tie0;
   for (int t = c0; t < c1; ++t) {
-    bool ch = all_tiles;
-    if (!all_tiles) {
-      const uint64_t k = kk[t];
-      ch = k < thr || (k == thr && tie++ < (uint32_t)krem);
-    }
+    const uint64_t k = kk[t];
+    const bool ch = k < thr || (k == thr && tie++ < (uint32_t)krem);
     if (ch) {
       valid_tiles[slot] = t;
       tile_off[slot] = off;
@@ -476,11 +497,16 @@ static int32_t sample_impl(const uint16_t* E, const uint16_t* A, int32_t height,
   else if (!all_tiles)
     hipLaunchKernelGGL(tile_keys_kernel, dim3(n_t), dim3(64), 0, s, E, height, width, tiles_x, n_t, sp->seed,
                        sp->step, (uint64_t)sp->view, keys);
-  const int lds_tiles = select_lds_tiles();
-  const size_t sel_lds = !all_tiles && n_t <= lds_tiles ? (size_t)n_t * sizeof(uint64_t) : 0;
-  hipLaunchKernelGGL(tile_select_kernel, dim3(1), dim3(kSelectThreads), sel_lds, s, keys, height, width,
-                     tiles_x, n_t, sp->n_tiles_sel, sp->n_pix, valid_tiles, tile_off, tile_slot, totals,
-                     lds_tiles);
+  if (all_tiles) {
+    hipLaunchKernelGGL(tile_list_all_kernel, dim3((unsigned)ceil_div(n_t + 1, 256)), dim3(256), 0, s, height, width,
+                       tiles_x, tiles_y, sp->n_pix, valid_tiles, tile_off, tile_slot, totals);
+  } else {
+    const int lds_tiles = select_lds_tiles();
+    const size_t sel_lds = n_t <= lds_tiles ? (size_t)n_t * sizeof(uint64_t) : 0;
+    hipLaunchKernelGGL(tile_select_kernel, dim3(1), dim3(kSelectThreads), sel_lds, s, keys, height, width,
+                       tiles_x, n_t, sp->n_tiles_sel, sp->n_pix, valid_tiles, tile_off, tile_slot, totals,
+                       lds_tiles);
+  }
   if (n_st > 0)
     hipLaunchKernelGGL(tile_pixels_kernel, dim3(n_st), dim3(64), 0, s, E, A, height, width, tiles_x,
                        n_st, sp->n_pix, sp->hard_permille, sp->stable_permille, sp->seed, sp->step,
