@@ -1,7 +1,7 @@
 // Tile-wise error/age pixel sampling (Sec. 3.5).
 //
 // Three kernels per view:
-//   tile_keys     one wave per tile (one thread with predicted weights): the
+//   tile_keys     eight lanes per tile (one thread with predicted weights): the
 //                 integer tile weight (sum of E * 2^24) and the tile's race
 //                 key, only when a subset of tiles is drawn;
 //   tile_select   one workgroup: the tiles of the smallest race keys, listed
@@ -103,22 +103,37 @@ __device__ __forceinline__ uint64_t race_key(uint64_t w, uint64_t u) {
   return (uint64_t)__double_as_longlong(__ddiv_rn((double)neg_log2_fixed(u), (double)w));
 }
 
+// Eight tiles per wave, eight lanes per tile: lane k of a tile's group sums
+// its pixels k, k + 8, ... (32 of them, a half row per load across the
+// group), a butterfly over the group adds the eight 64-bit partial sums
+// exactly, and the group's first lane computes the key, eight keys in
+// parallel per wave.
+constexpr int kKeyTiles = 8;
+
 __global__ void __launch_bounds__(64) tile_keys_kernel(const uint16_t* __restrict__ E, int H, int W,
                                                        int tiles_x, int n_t, uint64_t seed, uint64_t step,
                                                        uint64_t view, uint64_t* __restrict__ keys) {
-  const int t = blockIdx.x;
-  if (t >= n_t) return;
-  const int tx = t % tiles_x, ty = t / tiles_x;
   const int lane = threadIdx.x;
+  const int sub = lane & (kKeyTiles - 1);
+  const int t = blockIdx.x * kKeyTiles + lane / kKeyTiles;
   uint64_t s = 0;
-  for (int k = 0; k < 4; ++k) {
-    const int loc = lane * 4 + k;
-    const int x = tx * kTile + (loc & 15), y = ty * kTile + (loc >> 4);
-    if (x < W && y < H) s += half_weight(E[(int64_t)y * W + x]);
+  if (t < n_t) {
+    const int tx = t % tiles_x, ty = t / tiles_x;
+#pragma unroll 8
+    for (int k = 0; k < kTilePixels / kKeyTiles; ++k) {
+      const int loc = sub + kKeyTiles * k;
+      const int x = tx * kTile + (loc & 15), y = ty * kTile + (loc >> 4);
+      if (x < W && y < H) s += half_weight(E[(int64_t)y * W + x]);
+    }
   }
-  // wave sum of u64 as two 32-bit halves is not exact; use the inclusive scan
-  s = wave_inclusive_scan_u64(s);
-  if (lane == 63) keys[t] = race_key(s, absorb(stream_key(seed, step, view, (uint64_t)n_t), (uint64_t)t));
+#pragma unroll
+  for (int o = 1; o < kKeyTiles; o <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)s, o, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(s >> 32), o, kWave);
+    s += ((uint64_t)hi << 32) | lo;
+  }
+  if (t < n_t && sub == 0)
+    keys[t] = race_key(s, absorb(stream_key(seed, step, view, (uint64_t)n_t), (uint64_t)t));
 }
 
 // Keys from predicted mean tile errors: weight floor(clamp(p, 0, 65504) *
@@ -495,8 +510,8 @@ static int32_t sample_impl(const uint16_t* E, const uint16_t* A, int32_t height,
     hipLaunchKernelGGL(tile_pred_keys_kernel, dim3((unsigned)ceil_div(n_t, 256)), dim3(256), 0, s, tile_pred,
                        height, width, tiles_x, n_t, sp->seed, sp->step, (uint64_t)sp->view, keys);
   else if (!all_tiles)
-    hipLaunchKernelGGL(tile_keys_kernel, dim3(n_t), dim3(64), 0, s, E, height, width, tiles_x, n_t, sp->seed,
-                       sp->step, (uint64_t)sp->view, keys);
+    hipLaunchKernelGGL(tile_keys_kernel, dim3((unsigned)ceil_div(n_t, kKeyTiles)), dim3(64), 0, s, E, height, width,
+                       tiles_x, n_t, sp->seed, sp->step, (uint64_t)sp->view, keys);
   if (all_tiles) {
     hipLaunchKernelGGL(tile_list_all_kernel, dim3((unsigned)ceil_div(n_t + 1, 256)), dim3(256), 0, s, height, width,
                        tiles_x, tiles_y, sp->n_pix, valid_tiles, tile_off, tile_slot, totals);
