@@ -556,9 +556,8 @@ __global__ void __launch_bounds__(kWave) count_cont_kernel(
 // ids are loaded coalesced into LDS (with the one before the block), then
 // each position is compared with its predecessor.  A tile boundary writes
 // the start of the new tile and the end of the previous one, the last pair
-// the end of its tile.  Sentinel keys (tiles outside the valid set) sit
-// after every real tile and write nothing; empty tiles keep the [0, 0) of
-// the fill.
+// the end of its tile (a tile id >= n_t, which no list emits, would write
+// nothing); empty tiles keep the [0, 0) of the fill.
 constexpr int kRangeItems = 8;
 constexpr int kRangeBlock = 256 * kRangeItems;
 
