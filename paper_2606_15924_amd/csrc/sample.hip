@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
   extern __shared__ uint64_t s_keys[];  // [n_t] when n_t <= lds_tiles
   __shared__ uint32_t hist[256];
   __shared__ uint64_t s_thr;
-  __shared__ int s_krem;
+  __shared__ int s_krem, s_done;
   const int tid = threadIdx.x, lane = lane_id();
   const bool in_lds = n_t <= lds_tiles;  // 0 <= n_sel < n_t here
   if (in_lds)
@@ -205,6 +205,7 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
   const uint64_t* kk = in_lds ? s_keys : keys;
   uint64_t thr = 0;  // n_sel = 0: no key is below 0 and none is taken at it
   int krem = 0;
+  int fs = 0;  // keys are compared on their bits from fs up
   if (n_sel > 0) {
     krem = n_sel;
     for (int shift = 56; shift >= 0; shift -= 8) {
@@ -252,27 +253,36 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
           }
           s_thr = thr | ((uint64_t)(lane * 4 + b) << shift);
           s_krem = krem - (int)below;
+          // the bin holds exactly the keys still to take: every key with
+          // this prefix is chosen and the lower bits decide nothing
+          s_done = (int)h[b] == krem - (int)below;
         }
       }
       __syncthreads();
       thr = s_thr;
       krem = s_krem;
+      if (s_done) {  // workgroup-uniform
+        fs = shift;
+        break;
+      }
     }
   }
   // ascending list of the chosen tiles (keys below thr, and the first krem
-  // tiles whose key equals thr) with their sample counts
+  // tiles whose key equals thr, both on the bits from fs up) with their
+  // sample counts
   __shared__ uint32_t lds[kSelectThreads / kWave];
   const int chunk = (n_t + kSelectThreads - 1) / kSelectThreads;
   const int c0 = min(n_t, tid * chunk), c1 = min(n_t, c0 + chunk);
   uint32_t lties = 0;
-  for (int t = c0; t < c1; ++t) lties += kk[t] == thr ? 1u : 0u;
+  const uint64_t thr_s = thr >> fs;
+  for (int t = c0; t < c1; ++t) lties += kk[t] >> fs == thr_s ? 1u : 0u;
   uint32_t n_ties;
   const uint32_t tie0 = block_exclusive_scan<kSelectThreads, uint32_t>(lties, lds, &n_ties);
   uint32_t lcount = 0, lpix = 0;
   uint32_t tie = tie0;
   for (int t = c0; t < c1; ++t) {
-    const uint64_t k = kk[t];
-    const bool ch = k < thr || (k == thr && tie++ < (uint32_t)krem);
+    const uint64_t k = kk[t] >> fs;
+    const bool ch = k < thr_s || (k == thr_s && tie++ < (uint32_t)krem);
     if (ch) {
       ++lcount;
       lpix += (uint32_t)min(n_pix, tile_valid_w(t % tiles_x, W) * tile_valid_h(t / tiles_x, H));
@@ -283,8 +293,8 @@ __global__ void __launch_bounds__(kSelectThreads) tile_select_kernel(
   int off = (int)block_exclusive_scan<kSelectThreads, uint32_t>(lpix, lds, &P);
   tie = tie0;
   for (int t = c0; t < c1; ++t) {
-    const uint64_t k = kk[t];
-    const bool ch = k < thr || (k == thr && tie++ < (uint32_t)krem);
+    const uint64_t k = kk[t] >> fs;
+    const bool ch = k < thr_s || (k == thr_s && tie++ < (uint32_t)krem);
     if (ch) {
       valid_tiles[slot] = t;
       tile_off[slot] = off;
